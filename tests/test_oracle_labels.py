@@ -1,0 +1,77 @@
+"""Pins of the exact any-hit labels (visible = no triangle hit with 0 < t < t_max):
+hand cases of the watertight test and BVH == brute force."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2306_07191_amd import synth as S
+
+TRI = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+
+
+def test_centroid_hit_and_misses():
+    c = TRI.mean(axis=0).astype(np.float64)
+    o = c + [0, 0, 2]
+    assert O.ray_tri(o, [0, 0, -1], np.inf, TRI)          # through the centroid
+    assert O.ray_tri(c - [0, 0, 2], [0, 0, 1], np.inf, TRI)  # from behind: double-sided
+    assert not O.ray_tri(o, [0, 0, 1], np.inf, TRI)       # triangle behind the origin
+    assert not O.ray_tri([2, 2, 2], [0, 0, -1], np.inf, TRI)  # outside the triangle
+    assert not O.ray_tri(o, [1, 0, 0], np.inf, TRI)       # parallel to the plane
+
+
+def test_tmax_is_strict():
+    o = np.array([0.25, 0.25, 2.0])
+    assert not O.ray_tri(o, [0, 0, -1], 2.0, TRI)  # hit exactly at t = t_max is not an occluder
+    assert O.ray_tri(o, [0, 0, -1], 2.0 + 1e-12, TRI)
+    assert not O.ray_tri(o, [0, 0, -1], 1.999, TRI)
+    # a hit at t = 0 (origin on the surface) does not occlude
+    assert not O.ray_tri([0.25, 0.25, 0.0], [0, 0, 1], np.inf, TRI)
+
+
+def test_shared_edge_is_watertight():
+    """Two triangles sharing the diagonal of a square: rays through the shared edge
+    must hit at least one of them (no leak)."""
+    a = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0]], np.float32)
+    b = np.array([[0, 0, 0], [1, 1, 0], [0, 1, 0]], np.float32)
+    g = np.random.default_rng(0)
+    for s in g.uniform(0, 1, 200):
+        p = np.array([s, s, 0.0])
+        o = p + [0.3, -0.2, 1.5]
+        d = p - o
+        assert O.ray_tri(o, d, np.inf, a) or O.ray_tri(o, d, np.inf, b)
+    # a shared vertex as well
+    o = np.array([0.2, 0.7, -3.0])
+    d = -o
+    assert O.ray_tri(o, d, np.inf, a) or O.ray_tri(o, d, np.inf, b)
+
+
+def test_bvh_equals_brute_force_random_meshes():
+    g = np.random.default_rng(1)
+    for trial in range(200):
+        T = int(g.integers(1, 65))
+        tris = S.random_triangles(T, g)
+        if trial % 4 == 0:  # shared edges and vertices: a fan
+            c = g.uniform(-1, 1, 3)
+            ring = g.uniform(-1, 1, (T + 1, 3))
+            tris = np.stack([np.broadcast_to(c, (T, 3)), ring[:-1], ring[1:]], axis=1).astype(np.float32)
+        box = S.mesh_aabb(tris)
+        rays, tmax = S.rays_sphere_to_box(300, box, g)
+        tmax = np.where(g.uniform(size=300) < 0.3, g.uniform(0.5, 4.0, 300), tmax).astype(np.float32)
+        vb = O.anyhit_brute(tris, rays, tmax, nthreads=1)
+        vv = O.BVH(tris).anyhit(rays, tmax, nthreads=1)
+        np.testing.assert_array_equal(vb, vv)
+
+
+def test_bvh_equals_brute_force_tiny_workload():
+    w = S.tiny_workload()
+    vb = O.anyhit_brute(w["tris"], w["rays"], w["tmax"])
+    vv = O.BVH(w["tris"]).anyhit(w["rays"], w["tmax"])
+    np.testing.assert_array_equal(vb, vv)
+    assert 0.0 < vb.mean() < 0.2  # the tiny mesh occludes most rays aimed into its box
+
+
+def test_visible_when_no_triangles():
+    w = S.tiny_workload(n_rays=50)
+    empty = np.zeros((0, 3, 3), np.float32)
+    assert (O.anyhit_brute(empty, w["rays"], w["tmax"]) == 1).all()
+    assert (O.BVH(empty).anyhit(w["rays"], w["tmax"]) == 1).all()
