@@ -323,8 +323,9 @@ static int valid_query(const float* r, float tmax, int32_t id, int32_t K) {
     return 1;
 }
 
-static float clamp01f(float x) { return x < 0.0f ? 0.0f : (x > 1.0f ? 1.0f : x); }
-static double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
+/* clamp to [0, 1]; NaN (from an infinite segment end) maps to 0 */
+static float clamp01f(float x) { return x > 0.0f ? (x < 1.0f ? x : 1.0f) : 0.0f; }
+static double clamp01(double x) { return x > 0.0 ? (x < 1.0 ? x : 1.0) : 0.0; }
 
 /* Normalised coordinates of the three encoded quantities:
  *   u[0] entry point, u[1] exit point: (p - lo) / (hi - lo), clamped to [0,1]^3
@@ -347,7 +348,7 @@ static int query_coords(const orc_model* m, const float* r, float tmax, int32_t 
             float pout = o[a] + tb * d[a];
             u[0][a] = clamp01f((pin - lo[a]) / ext);
             u[1][a] = clamp01f((pout - lo[a]) / ext);
-            u[2][a] = (d[a] / len + 1.0f) * 0.5f;
+            u[2][a] = clamp01f((d[a] / len + 1.0f) * 0.5f);
         }
         return 1;
     }
@@ -359,7 +360,7 @@ static int query_coords(const orc_model* m, const float* r, float tmax, int32_t 
     for (int a = 0; a < 3; ++a) {
         u[0][a] = clamp01((o[a] + ta * d[a] - lo[a]) / (hi[a] - lo[a]));
         u[1][a] = clamp01((o[a] + tb * d[a] - lo[a]) / (hi[a] - lo[a]));
-        u[2][a] = (d[a] / len + 1.0) * 0.5;
+        u[2][a] = clamp01((d[a] / len + 1.0) * 0.5);
     }
     return 1;
 }
@@ -379,7 +380,7 @@ typedef struct {
 } orc_corners;
 
 static void encode(const orc_model* m, int32_t obj, double u[3][3], const int64_t* off, const int32_t* res,
-                   double* x, double* xmag, orc_corners* cs) {
+                   double* x, double* gmax, orc_corners* cs) {
     const int L = m->levels, F = m->feats;
     for (int e = 0; e < ORC_E; ++e)
         for (int l = 0; l < L; ++l) {
@@ -405,7 +406,7 @@ static void encode(const orc_model* m, int32_t obj, double u[3][3], const int64_
             const int64_t N1 = N + 1;
             for (int f = 0; f < F; ++f) {
                 x[(e * L + l) * F + f] = 0.0;
-                if (xmag) xmag[(e * L + l) * F + f] = 0.0;
+                if (gmax) gmax[(e * L + l) * F + f] = 0.0;
             }
             for (int b = 0; b < 8; ++b) {
                 int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
@@ -415,7 +416,7 @@ static void encode(const orc_model* m, int32_t obj, double u[3][3], const int64_
                 for (int f = 0; f < F; ++f) {
                     double g = grid_value(m, obj, el + f);
                     x[(e * L + l) * F + f] += wt * g;
-                    if (xmag) xmag[(e * L + l) * F + f] += fabs(wt * g);
+                    if (gmax && fabs(g) > gmax[(e * L + l) * F + f]) gmax[(e * L + l) * F + f] = fabs(g);
                 }
                 if (cs) { cs->elem[e * L + l][b] = el; cs->w[e * L + l][b] = wt; }
             }
@@ -484,19 +485,47 @@ static double gamma32(int K) {
 
 #define U32 (0x1p-24)
 
-/* xmag[i] = sum over corners of |weight * latent|: the device evaluates the
- * interpolation in binary32, which moves x[i] by a few rounding units of that
- * magnitude (three weight factors, one product, an eight-term sum).
+/* Sum of the 8 largest values of a[0..K). */
+static double top8_sum(const double* a, int K) {
+    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < K; ++i) {
+        double v = a[i];
+        if (v <= t[7]) continue;
+        int j = 7;
+        while (j > 0 && t[j - 1] < v) { t[j] = t[j - 1]; --j; }
+        t[j] = v;
+    }
+    return t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6] + t[7];
+}
+
+/* Accumulation drift of one K-term dot product on the device.
+ *  - binary32 partial sums in any order: gamma_K sum|p| (Higham, Sec. 3.1).
+ *  - FP8 matrix-core products are summed in blocks of 8; inside a block every
+ *    product is truncated to 13 fraction bits below the block's largest
+ *    product (measured on the target device), and the block sums are combined
+ *    in binary32.  For any assignment of the K products to blocks the error is
+ *    below 7 * 2^-13 * (sum of the 8 largest |p|) + gamma_8 sum|p|. */
+static double acc_drift(int quant, int K, const double* absprod, double mag) {
+    if (quant != 3) return gamma32(K) * mag;
+    return 7.0 * ldexp(1.0, -13) * top8_sum(absprod, K) + gamma32(8) * mag;
+}
+
+/* gmax[i] = largest |latent| among the corners of feature i: the device
+ * interpolates in binary32 with three nested linear interpolations, each at
+ * most three roundings of values bounded by gmax, so its x[i] is within
+ * 9 u gmax of the exact interpolant.
  *
  * Three quantities are propagated per element:
  *   eps  worst-case bound on |device value - exact value| (Higham-style,
  *        rounding of every operand by up to half a quantum, |W| propagation)
- *   dr   realistic binary32 drift of the device value from this emulation
- *        with the same rounding decisions (local rounding + RMS propagation)
- *   flip one quantum if the element's rounding decision lies within 4 dr of
- *        a midpoint (it may round the other way on the device), else 0
- * ztol = 4 dr_z + sum over flagged elements of quantum x |dz/dh|. */
-static void mlp_forward(const orc_model* m, const double* W, const double* sc, const double* x, const double* xmag,
+ *   dr   drift of the device value from this emulation taking the same
+ *        rounding decisions: gamma_K |terms| for the K-term binary32 sum
+ *        (any summation order) plus the inputs' drift propagated in
+ *        root-sum-square
+ *   flip one quantum if the element's rounding decision lies within 2 dr of
+ *        a midpoint (the device may round it the other way), else 0
+ * ztol = 2 dr_z + sum over flagged elements of quantum x |dz/dh|. */
+static void mlp_forward(const orc_model* m, const double* W, const double* sc, const double* x, const double* gmax,
                         double* acts, orc_fwd* out) {
     const int H = m->hidden, Wd = m->width, Din = orc_din(m), q = m->quant;
     double hq[ORC_MAXDIN], eps[ORC_MAXDIN], dr[ORC_MAXDIN];
@@ -509,11 +538,11 @@ static void mlp_forward(const orc_model* m, const double* W, const double* sc, c
     int K = Din;
     const double s0 = (q == 3) ? sc[H] : 1.0;
     for (int i = 0; i < Din; ++i) {
-        dr[i] = xmag ? 4.0 * U32 * xmag[i] : 0.0;
+        dr[i] = gmax ? 9.0 * U32 * gmax[i] : 0.0;
         hq[i] = q ? qact(x[i], q, s0) : x[i];
-        eps[i] = (q ? half_q(x[i], q, s0) : 0.0) + (xmag ? 32.0 * U32 * xmag[i] : 0.0);
+        eps[i] = (q ? half_q(x[i], q, s0) : 0.0) + dr[i];
         flip[0][i] = 0.0;
-        if (q && orc_midpoint_distance(q == 3 ? x[i] / s0 : x[i], qfmt(q)) * (q == 3 ? s0 : 1.0) <= 4.0 * dr[i]) {
+        if (q && orc_midpoint_distance(q == 3 ? x[i] / s0 : x[i], qfmt(q)) * (q == 3 ? s0 : 1.0) <= 2.0 * dr[i]) {
             flip[0][i] = 2.0 * half_q(x[i], q, s0);
             ++flags;
         }
@@ -525,17 +554,20 @@ static void mlp_forward(const orc_model* m, const double* W, const double* sc, c
         Kl[j] = K;
         for (int o = 0; o < Wd; ++o) {
             double acc = 0.0, err = 0.0, mag = 0.0, prop2 = 0.0;
+            double absprod[ORC_MAXDIN];
             for (int i = 0; i < K; ++i) {
                 double w = Wj[(int64_t)o * K + i];
                 double wq = qweight(w, q, sw);
                 acc += wq * hq[i];
                 err += fabs(wq - w) * (fabs(hq[i]) + eps[i]) + fabs(w) * eps[i];
-                mag += fabs(wq * hq[i]);
+                absprod[i] = fabs(wq * hq[i]);
+                mag += absprod[i];
                 prop2 += (wq * dr[i]) * (wq * dr[i]);
             }
             a[o] = acc;
-            enew[o] = err + gamma32(K) * (mag + 1e-300);
-            dnew[o] = 4.0 * U32 * mag + sqrt(prop2);
+            const double local = acc_drift(q, K, absprod, mag) + 1e-300;
+            enew[o] = err + local;
+            dnew[o] = local + sqrt(prop2);
         }
         if (acts) memcpy(acts + (int64_t)(j - 1) * Wd, a, sizeof(double) * Wd);
         memcpy(aall[j], a, sizeof(double) * Wd);
@@ -547,7 +579,7 @@ static void mlp_forward(const orc_model* m, const double* W, const double* sc, c
                 hq[o] = qact(h, q, sx);
                 eps[o] = enew[o] + half_q(h + enew[o], q, sx);
                 if (h > 0.0 && orc_midpoint_distance(q == 3 ? h / sx : h, qfmt(q)) * (q == 3 ? sx : 1.0) <=
-                                   4.0 * dnew[o]) {
+                                   2.0 * dnew[o]) {
                     flip[j][o] = 2.0 * half_q(h, q, sx);
                     ++flags;
                 }
@@ -590,7 +622,7 @@ static void mlp_forward(const orc_model* m, const double* W, const double* sc, c
     out->z = z;
     out->y = 1.0 / (1.0 + exp(-z));
     out->flags = flags;
-    out->ztol = 4.0 * (4.0 * U32 * mag + sqrt(prop2)) + tol_flip;
+    out->ztol = 2.0 * (gamma32(Wd) * mag + sqrt(prop2)) + tol_flip;
     out->ybound = 0.25 * (ez + gamma32(Wd) * mag);
 }
 
@@ -648,7 +680,7 @@ static void fwd_range(void* p, int64_t b, int64_t e) {
     orc_grid_offsets(m, off);
     orc_level_res(m->levels, m->res_min, m->res_max, res);
     const int Din = orc_din(m);
-    double x[ORC_MAXDIN], xmag[ORC_MAXDIN];
+    double x[ORC_MAXDIN], gmax[ORC_MAXDIN];
     for (int64_t i = b; i < e; ++i) {
         double u[3][3];
         const float* r = J->rays + 6 * i;
@@ -656,9 +688,9 @@ static void fwd_range(void* p, int64_t b, int64_t e) {
         orc_fwd o = {0};
         if (st == 1) {
             int32_t obj = J->ids[i];
-            encode(m, obj, u, off, res, x, xmag, NULL);
+            encode(m, obj, u, off, res, x, gmax, NULL);
             int32_t mi = m->mlp_index[obj];
-            mlp_forward(m, m->mlps[mi], m->fp8_scales ? m->fp8_scales[mi] : NULL, x, xmag, NULL, &o);
+            mlp_forward(m, m->mlps[mi], m->fp8_scales ? m->fp8_scales[mi] : NULL, x, gmax, NULL, &o);
             if (J->x) memcpy(J->x + i * Din, x, sizeof(double) * Din);
         } else if (st == 0) {
             o.z = INFINITY; o.y = 1.0;
