@@ -1,0 +1,187 @@
+/*
+ * nif.h - C ABI of the MI355X neural visibility library (libnif.so).
+ *
+ * The library answers shadow-ray visibility queries with a Neural
+ * Intersection Function (Fujieda, Kao, Harada, HPG 2023): for each
+ * (ray, object) pair it clips the ray against the object's AABB (Sec. 2 end,
+ * Sec. 3.1), encodes the entry point, exit point and direction with learned
+ * multi-resolution grids (Sec. 3.1, Fig. 2), and evaluates a small MLP with a
+ * sigmoid output giving the probability that the ray is NOT occluded by that
+ * object (Sec. 3, Eq. (1); Sec. 5 "Architecture").  It also provides the
+ * training step (Sec. 4.2, Sec. 5 "Training": joint optimisation of latents
+ * and weights with Adam) and a plain BVH any-hit kernel for labels and for
+ * the comparison the paper makes (Sec. 6 "Performance Evaluation").
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers marked (dev) are device memory owned by the caller; (host) are
+ *    host memory read during the call only.  `stream` is a hipStream_t (NULL =
+ *    the default stream).  Work is enqueued asynchronously on `stream`; the
+ *    call returns before it completes.
+ *  - Every call returns nif_status.  Argument errors (NULL pointer, n < 0,
+ *    unsupported shape, workspace too small, unprepared context) are detected
+ *    on the host before anything is enqueued; nif_last_error() then holds a
+ *    thread-local message.  n == 0 is a successful no-op.
+ *  - Per-query domain errors never fail a call: a non-finite origin or
+ *    direction, a zero direction, t_max NaN or negative, or an object id
+ *    outside [0, num_objects) give visibility = NaN.
+ *  - The context owns host metadata and two small device tables (objects,
+ *    packed weights), allocated by nif_prepare and freed by nif_destroy.
+ *    Grids, master weights, gradients, optimiser state, inputs, outputs and
+ *    workspaces are the caller's.  No C++ exception crosses this interface.
+ */
+#ifndef NIF_H
+#define NIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NIF_OK = 0,
+    NIF_ERR_INVALID_ARG = -1, /* NULL pointer, negative size, id out of range */
+    NIF_ERR_UNSUPPORTED = -2, /* model shape or dtype the kernels do not cover */
+    NIF_ERR_WORKSPACE = -3,   /* workspace smaller than nif_workspace_bytes */
+    NIF_ERR_HIP = -4,         /* a HIP runtime call failed */
+    NIF_ERR_STATE = -5        /* context not prepared for the requested dtype */
+} nif_status;
+
+typedef enum { NIF_F32 = 0, NIF_F16 = 1, NIF_BF16 = 2, NIF_FP8_E4M3 = 3 } nif_dtype;
+
+/* Model shape.  Grids: for each of the 3 encoded quantities (entry point,
+ * exit point, direction) `levels` dense 3D tables; level l has
+ * N_l = round(res_min * (res_max/res_min)^(l/(levels-1))) cells per axis and
+ * (N_l+1)^3 vertices of `feats` latents, stored as grid_dtype (NIF_F32 or
+ * NIF_F16; the paper keeps latents in half, Sec. 5 "Memory Footprint").
+ * MLP: input 3*levels*feats, `hidden_layers` ReLU layers of `width`, one
+ * sigmoid output, no biases (Sec. 5 "Architecture").
+ * Supported by the kernels: feats = 2, width = 64, levels in {4, 8},
+ * 1 <= hidden_layers <= 8, res_max <= 1024. */
+typedef struct {
+    int32_t levels, res_min, res_max, feats;
+    int32_t grid_dtype;
+    int32_t hidden_layers, width;
+} nif_model_desc;
+
+typedef struct nif_ctx nif_ctx;
+
+/* Create a context for `num_objects` objects sharing `num_mlps` MLPs
+ * (num_mlps = 1 is the paper's single shared network, Sec. 4.1; one MLP per
+ * object is the per-object variant).  *out receives the context. */
+nif_status nif_create(const nif_model_desc* desc, int32_t num_objects, int32_t num_mlps, nif_ctx** out);
+void nif_destroy(nif_ctx* ctx);
+
+/* Parameter layout.  grid_elems: latents per object (one buffer per object,
+ * tables in order entry/exit/direction x level, each vertex-major
+ * ((z (N+1) + y) (N+1) + x) * feats + f).  table_offsets (host, 3*levels+1
+ * entries, nullable): element offset of each table.  level_res (host, levels
+ * entries, nullable).  mlp_params: weights per MLP, flat row-major
+ * [W1 (width x din)][W2..WH (width x width)][w_out (width)]. */
+nif_status nif_param_layout(const nif_ctx* ctx, int64_t* grid_elems, int64_t* table_offsets, int32_t* level_res,
+                            int64_t* mlp_params);
+
+/* Register object `obj`: its AABB (host, lo xyz then hi xyz; hi > lo on every
+ * axis), its grid buffer (dev, grid_elems latents of grid_dtype) and the MLP
+ * it uses.  Takes effect at the next nif_prepare. */
+nif_status nif_set_object(nif_ctx* ctx, int32_t obj, const float* aabb, void* grid, int32_t mlp_index);
+
+/* Register MLP `mlp`: binary32 master weights (dev, mlp_params floats).  The
+ * binary32 path and the training step read them in place; reduced-precision
+ * paths read the copy made by nif_prepare. */
+nif_status nif_set_mlp(nif_ctx* ctx, int32_t mlp, float* weights);
+
+/* FP8 E4M3 scales of MLP `mlp` (host, 2*hidden_layers floats): s_W for layers
+ * 1..H, then s_x for the inputs of layers 1..H.  Layer j computes
+ * s_W s_x (Q(W_j / s_W) . Q(h_{j-1} / s_x)) with Q = round to E4M3,
+ * saturating at 448, accumulated in binary32. */
+nif_status nif_set_fp8_scales(nif_ctx* ctx, int32_t mlp, const float* scales);
+
+/* Fill object obj's grid with the initial latents U[-amp, amp) (Sec. 5
+ * "Initialization": amp = 1e-4): element i gets the top 24 bits m of word
+ * (i mod 4) of Philox4x64-10 (Salmon et al., SC 2011) at counter
+ * (i div 4, 0, 0, 0), key (seed, obj), as (m - 2^23) * (amp * 2^-23) in
+ * binary32, rounded to nearest-even into grid_dtype. */
+nif_status nif_init_grid(nif_ctx* ctx, int32_t obj, uint64_t seed, float amp, void* stream);
+
+/* Upload the object table and pack the weights of every MLP for `dtype`
+ * (NIF_F32, NIF_BF16, NIF_F16 or NIF_FP8_E4M3; FP8 needs scales).  Must be
+ * called after changing objects, weights or scales and before nif_query with
+ * that dtype.  Enqueued on stream. */
+nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
+
+/* Workspace bytes needed by nif_query / nif_train_step for n queries. */
+size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode /* 0 query, 1 train */);
+
+/* Visibility of n (ray, object) queries (Sec. 4.1: one query per object AABB
+ * the ray meets; Sec. 3 Eq. (1): 1 = visible).
+ *   rays (dev, n x 6 floats: ox oy oz dx dy dz; d need not be unit, t is in
+ *   units of d), object_ids (dev, n), t_max (dev, n; +inf allowed)
+ *   visibility (dev, n): sigmoid(z) in [0,1]; a ray that misses the AABB or
+ *   whose segment [max(t_near,0), min(t_far,t_max)] is empty is visible (1).
+ *   The paper's decision is occluded iff visibility < 0.5 (Sec. 5).
+ *   logits (dev, n, nullable): z, +inf for a miss.
+ *   dtype: arithmetic of the MLP (binary32, BF16, FP16 or FP8 E4M3 operands,
+ *   binary32 accumulation); clip and grid coordinates are always binary32.
+ *   ws: workspace of at least nif_workspace_bytes(ctx, n, 0) bytes (dev). */
+nif_status nif_query(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids, const float* t_max,
+                     int64_t n, float* visibility, float* logits, void* ws, size_t ws_bytes, void* stream);
+
+/* The two stages of a query as separate launches, as the paper's pipeline runs
+ * them (Sec. 4.1: a grid-lookup kernel, then an inference kernel).
+ * nif_encode: clip, normalise and interpolate the latents of n queries into
+ *   features (dev, n x din floats, din = 3*levels*feats, order encoding-major
+ *   (entry, exit, direction), then level, then latent); status (dev, n,
+ *   nullable): 1 = the segment meets the AABB, 0 = miss (features 0),
+ *   -1 = invalid query.  Needs nif_prepare (any dtype) for the object table.
+ * nif_mlp: logits z (dev, n) of MLP `mlp` on given features (dev, n x din),
+ *   in `dtype` arithmetic as nif_query. */
+nif_status nif_encode(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max, int64_t n,
+                      float* features, int32_t* status, void* stream);
+nif_status nif_mlp(nif_ctx* ctx, int32_t dtype, int32_t mlp, const float* features, int64_t n, float* logits,
+                   void* stream);
+
+/* Adam hyper-parameters (Sec. 5 "Training"). */
+typedef struct {
+    float lr, beta1, beta2, eps;
+} nif_adam;
+
+/* One training step on n labelled queries (Sec. 4.2; Sec. 5 "Training").
+ * labels (dev, n bytes): 1 = visible, 0 = occluded.  Loss: binary
+ * cross-entropy on the logit, averaged over the B queries that meet their
+ * AABB.  Backward through the MLP and into the grids (every interpolation
+ * corner receives weight x feature gradient), then Adam with bias correction
+ * for global step `step` (1-based) on every MLP weight and on every latent
+ * whose gradient is non-zero this step (others keep latent and moments).
+ * Latents are updated in binary32 and rounded to grid_dtype; MLP masters stay
+ * binary32.
+ *   grid_grad, grid_m, grid_v (dev, per object: pointer arrays (host) of
+ *   num_objects buffers of grid_elems floats): gradient accumulator, first and
+ *   second moments.  grid_grad must be all zero before the first step; the
+ *   step leaves it zero again.  touched (host array of num_objects dev
+ *   pointers, each nif_touched_bytes): zero before the first step, left zero.
+ *   mlp_m, mlp_v (dev, num_mlps x mlp_params floats).
+ *   loss (dev, 1 float, nullable): mean loss of this batch.
+ *   mlp_grad_out (dev, num_mlps x mlp_params floats, nullable): the MLP
+ *   gradient of this batch. */
+nif_status nif_train_step(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max,
+                          const uint8_t* labels, int64_t n, int32_t step, const nif_adam* adam,
+                          float* const* grid_grad, float* const* grid_m, float* const* grid_v,
+                          uint32_t* const* touched, float* mlp_m, float* mlp_v, float* loss, float* mlp_grad_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of the per-object touched-vertex bitmap used by nif_train_step. */
+size_t nif_touched_bytes(const nif_ctx* ctx);
+
+/* Thread-local text of the last error (empty after success). */
+const char* nif_last_error(void);
+
+/* Library version string. */
+const char* nif_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NIF_H */

@@ -1,0 +1,614 @@
+// Fused neural visibility query for gfx950: AABB clip, multi-resolution
+// trilinear grid encoding and the MLP on MFMA, in one kernel.
+//
+// Method (Fujieda, Kao, Harada, "Neural Intersection Function", HPG 2023):
+//  - the ray is re-parameterised by the object's AABB: its entry point replaces
+//    the origin so that rays on one line encode identically (Sec. 2 end, Sec. 3.1);
+//  - latents stored on grids are interpolated at the encoded coordinates and
+//    concatenated as the MLP input (Sec. 3.1, Fig. 2);
+//  - the MLP has ReLU hidden layers and a sigmoid output, the probability that
+//    the ray is not occluded by this object (Sec. 3 Eq. (1), Sec. 5 "Architecture").
+//
+// Work mapping.  A wave handles 32 queries at a time, two lanes per query.
+// Both lanes clip and normalise (binary32, no contraction, same operation
+// order everywhere so that the grid cell a point falls in is reproducible);
+// lane half h then encodes lookups h*3L/2 .. (h+1)*3L/2-1 of the 3L
+// (encoding, level) tables.  Those are exactly the K-positions half h feeds to
+// the first MFMA, so features never leave registers.  Each hidden layer is a
+// chain of 32x32xK MFMAs (N = queries); the accumulator rows a half holds are
+// fed back as its next B operand, the weight columns having been permuted to
+// match at pack time.  Weights are read from LDS as one 16-byte packet per
+// lane and MFMA.
+#include <hip/hip_fp16.h>
+
+#include "nif_internal.h"
+
+namespace nif {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int FLAV> struct FT;
+template <> struct FT<kF32> { static constexpr int ebytes = 4, kstep = 1; };
+template <> struct FT<kBF16> { static constexpr int ebytes = 2, kstep = 8; };
+template <> struct FT<kF16> { static constexpr int ebytes = 2, kstep = 8; };
+template <> struct FT<kFP8> { static constexpr int ebytes = 1, kstep = 32; };
+
+constexpr int roundup(int a, int b) { return (a + b - 1) / b * b; }
+
+// 16-byte packets per M-tile of a layer whose halves hold kh local inputs.
+constexpr int packets_for(int flav, int kh) {
+    return flav == kF32   ? roundup(kh, 1) * 4 / 16
+           : flav == kFP8 ? roundup(kh, 32) / 16
+                          : roundup(kh, 8) * 2 / 16;
+}
+
+PackInfo pack_info(int flavor, int din, int hidden) {
+    PackInfo p{};
+    p.din = din;
+    p.hidden = hidden;
+    int64_t off = 0;
+    for (int j = 0; j < hidden; ++j) {
+        int kh = j == 0 ? din / 2 : kWidth / 2;
+        int pk = flavor == kF32 ? (kh * 4 + 15) / 16 : flavor == kFP8 ? roundup(kh, 32) / 16 : roundup(kh, 8) * 2 / 16;
+        p.layer_off[j] = off;
+        off += (int64_t)2 * pk * 64 * 16;
+    }
+    p.layer_off[hidden] = off;  // w_out: [half][32] floats
+    off += 2 * 32 * 4;
+    p.bytes = off;
+    return p;
+}
+
+size_t lds_bytes(const PackInfo& p) { return (size_t)p.bytes; }
+
+// ----------------------------------------------------------------------------
+// Clip and normalisation, binary32, no contraction.
+// Returns 1 if the segment [max(t_near,0), min(t_far,t_max)] is non-empty.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int clip_normalise(const float o[3], const float d[3], float tmax, const ObjDev& b,
+                                              float u[3][3]) {
+#pragma clang fp contract(off)
+    float tn = -INFINITY, tf = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < b.lo[a] || o[a] > b.hi[a]) return 0;
+            continue;
+        }
+        float t0 = (b.lo[a] - o[a]) / d[a];
+        float t1 = (b.hi[a] - o[a]) / d[a];
+        float l = t0 < t1 ? t0 : t1, h = t0 < t1 ? t1 : t0;
+        if (l > tn) tn = l;
+        if (h < tf) tf = h;
+    }
+    float ta = tn > 0.0f ? tn : 0.0f;
+    float tb = tf < tmax ? tf : tmax;
+    if (!(ta <= tb)) return 0;
+    float len2 = d[0] * d[0];
+    len2 = len2 + d[1] * d[1];
+    len2 = len2 + d[2] * d[2];
+    float len = sqrtf(len2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float pin = o[a] + ta * d[a];
+        float pout = o[a] + tb * d[a];
+        float ui = (pin - b.lo[a]) / b.ext[a];
+        float uo = (pout - b.lo[a]) / b.ext[a];
+        float ud = (d[a] / len + 1.0f) * 0.5f;
+        // clamp to [0, 1]; NaN (an infinite segment end) maps to 0
+        u[0][a] = ui > 0.0f ? (ui < 1.0f ? ui : 1.0f) : 0.0f;
+        u[1][a] = uo > 0.0f ? (uo < 1.0f ? uo : 1.0f) : 0.0f;
+        u[2][a] = ud > 0.0f ? (ud < 1.0f ? ud : 1.0f) : 0.0f;
+    }
+    return 1;
+}
+
+__device__ __forceinline__ bool valid_query(const float o[3], const float d[3], float tmax, int32_t id, int32_t K) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = ok && isfinite(o[a]) && isfinite(d[a]);
+    ok = ok && !(d[0] == 0.0f && d[1] == 0.0f && d[2] == 0.0f);
+    ok = ok && !(tmax != tmax) && tmax >= 0.0f;
+    ok = ok && id >= 0 && id < K;
+    return ok;
+}
+
+#define GLOBAL __attribute__((address_space(1)))
+
+// Two adjacent vertices (x and x+1) of one grid row, two latents each.
+template <typename GT> struct Row;
+template <> struct Row<_Float16> {
+    float v[4];  // v[0], v[1]: vertex x; v[2], v[3]: vertex x+1
+    __device__ __forceinline__ void load(const GLOBAL _Float16* p) {
+        // two dword reads of adjacent vertices; the backend merges them into one
+        // dword-aligned 8-byte load
+        const GLOBAL unsigned* q = reinterpret_cast<const GLOBAL unsigned*>(p);
+        const unsigned wx = q[0], wy = q[1];
+        __half2 a = __builtin_bit_cast(__half2, wx), b = __builtin_bit_cast(__half2, wy);
+        float2 fa = __half22float2(a), fb = __half22float2(b);
+        v[0] = fa.x; v[1] = fa.y; v[2] = fb.x; v[3] = fb.y;
+    }
+};
+template <> struct Row<float> {
+    float v[4];
+    __device__ __forceinline__ void load(const GLOBAL float* p) {
+        v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; v[3] = p[3];  // one 16-byte load
+    }
+};
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return a + t * (b - a); }
+
+// Cell and in-cell weight of coordinate u at resolution N: s = u N (one
+// binary32 product), cell = min(floor(s), N - 1), w = s - cell (exact).  No
+// contraction: fusing u N - cell into one FMA would use the unrounded product
+// for w while the cell came from the rounded one.
+__device__ __forceinline__ int cell_coord(float u, float fN, int N, float& w) {
+#pragma clang fp contract(off)
+    float s = u * fN;
+    float cf = floorf(s);
+    cf = cf > (float)(N - 1) ? (float)(N - 1) : cf;
+    w = s - cf;
+    int ci = (int)cf;
+    return ci < 0 ? 0 : (ci > N - 1 ? N - 1 : ci);  // u is in [0, 1]; kept for safety
+}
+
+// Encode the lookups of lane half `half`: NL = 3L/2 lookups, 2 features each,
+// local feature c = 2 t + f.
+template <int L, typename GT>
+__device__ __forceinline__ void encode_half(const float u[3][3], int half, const GLOBAL GT* grid, const FwdArgs& A,
+                                            float* x) {
+    constexpr int NL = 3 * L / 2;
+    int64_t base[NL];
+    float w[NL][3];
+    int32_t stride[NL];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+        const int k0 = t, k1 = NL + t;  // lookup index for half 0 / half 1
+        const int e = half ? k1 / L : k0 / L;
+        const int l = half ? k1 % L : k0 % L;
+        const int N = A.res[l];
+        const float fN = (float)N;
+        int c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float ue = e == 0 ? u[0][a] : (e == 1 ? u[1][a] : u[2][a]);
+            c[a] = cell_coord(ue, fN, N, w[t][a]);
+        }
+        const int32_t N1 = N + 1;
+        const int32_t v = (c[2] * N1 + c[1]) * N1 + c[0];
+        base[t] = (half ? A.toff[k1] : A.toff[k0]) + (int64_t)v * kFeats;
+        stride[t] = N1 * kFeats;
+    }
+    Row<GT> r[NL][4];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+        const GLOBAL GT* p = grid + base[t];
+        const int32_t sy = stride[t];
+        const int64_t sz = (int64_t)sy * (sy / kFeats);
+        r[t][0].load(p);
+        r[t][1].load(p + sy);
+        r[t][2].load(p + sz);
+        r[t][3].load(p + sz + sy);
+    }
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+#pragma unroll
+        for (int f = 0; f < kFeats; ++f) {
+            float y0 = lerp(lerp(r[t][0].v[f], r[t][0].v[2 + f], w[t][0]), lerp(r[t][1].v[f], r[t][1].v[2 + f], w[t][0]),
+                            w[t][1]);
+            float y1 = lerp(lerp(r[t][2].v[f], r[t][2].v[2 + f], w[t][0]), lerp(r[t][3].v[f], r[t][3].v[2 + f], w[t][0]),
+                            w[t][1]);
+            x[2 * t + f] = lerp(y0, y1, w[t][2]);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// MLP on MFMA.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ i32x4 load_packet(const uint8_t* img, int idx) {
+    return *reinterpret_cast<const i32x4*>(img + (int64_t)idx * 16);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+// two floats -> packed pair, round to nearest even
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+__device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
+}
+// four floats -> four OCP E4M3 bytes, round to nearest even, saturated to +-448
+__device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d) {
+    a = fminf(fmaxf(a, -448.0f), 448.0f);
+    b = fminf(fmaxf(b, -448.0f), 448.0f);
+    c = fminf(fmaxf(c, -448.0f), 448.0f);
+    d = fminf(fmaxf(d, -448.0f), 448.0f);
+    int r = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, r, true);
+    return r;
+}
+
+// Output of one MLP evaluation for the wave's 32 queries: z for this lane's query.
+// xin: this half's layer-1 local inputs (din/2 floats, zero for inactive queries).
+template <int FLAV, int KH1>
+__device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, int hidden, const float* xin,
+                                         const float* scales, int lane) {
+    const int half = lane >> 5;
+    f32x16 acc[2];
+    // ------------------------------------------------------------------ layer 1
+    {
+        constexpr int PK = packets_for(FLAV, KH1);
+        const uint8_t* L1 = img + P.layer_off[0];
+        acc[0] = f32x16{};
+        acc[1] = f32x16{};
+        if constexpr (FLAV == kF32) {
+#pragma unroll
+            for (int p = 0; p < PK; ++p) {
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    // bit-cast the whole packet: this compiler mis-reads a bit_cast
+                    // of a single vector element (it takes element 0)
+                    const f32x4 af = __builtin_bit_cast(f32x4, load_packet(L1, (mt * PK + p) * 64 + lane));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int c = 4 * p + q;
+                        float b = c < KH1 ? xin[c] : 0.0f;
+                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], b, acc[mt], 0, 0, 0);
+                    }
+                }
+            }
+        } else if constexpr (FLAV == kBF16 || FLAV == kF16) {
+#pragma unroll
+            for (int p = 0; p < PK; ++p) {
+                i32x4 b4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = 8 * p + 2 * q;
+                    float v0 = c < KH1 ? xin[c] : 0.0f, v1 = c + 1 < KH1 ? xin[c + 1] : 0.0f;
+                    b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(v0, v1) : pack_f16x2(v0, v1));
+                }
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    i32x4 a4 = load_packet(L1, (mt * PK + p) * 64 + lane);
+                    if constexpr (FLAV == kBF16)
+                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a4),
+                                                                          __builtin_bit_cast(bf16x8, b4), acc[mt], 0, 0, 0);
+                    else
+                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a4),
+                                                                         __builtin_bit_cast(f16x8, b4), acc[mt], 0, 0, 0);
+                }
+            }
+        } else {  // FP8: one K-step of 32 local positions
+            const float inv = 1.0f / scales[hidden + 0];
+            i32x8 b8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                float v[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int c = 4 * q + t;
+                    v[t] = c < KH1 ? xin[c] * inv : 0.0f;
+                }
+                b8[q] = pack_fp8x4(v[0], v[1], v[2], v[3]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                i32x4 lo = load_packet(L1, (mt * 2 + 0) * 64 + lane);
+                i32x4 hi = load_packet(L1, (mt * 2 + 1) * 64 + lane);
+                i32x8 a8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                acc[mt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[mt], 0, 0, 0, 0, 0, 0);
+            }
+        }
+    }
+    // ------------------------------------------------------------------ hidden layers 2..H
+    for (int j = 1; j < hidden; ++j) {
+        const uint8_t* Lj = img + P.layer_off[j];
+        float deq = 1.0f, inv_next = 1.0f;
+        if constexpr (FLAV == kFP8) {
+            deq = scales[j - 1] * scales[hidden + j - 1];
+            inv_next = 1.0f / scales[hidden + j];
+        }
+        // activations of the previous layer: local c = 16 mt + r
+        float h[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+            float v = acc[c / 16][c % 16];
+            if constexpr (FLAV == kFP8) v *= deq;
+            h[c] = v > 0.0f ? v : 0.0f;
+        }
+        acc[0] = f32x16{};
+        acc[1] = f32x16{};
+        if constexpr (FLAV == kF32) {
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    const f32x4 af = __builtin_bit_cast(f32x4, load_packet(Lj, (mt * 8 + p) * 64 + lane));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], h[4 * p + q], acc[mt], 0, 0, 0);
+                }
+            }
+        } else if constexpr (FLAV == kBF16 || FLAV == kF16) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                i32x4 b4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(h[8 * p + 2 * q], h[8 * p + 2 * q + 1])
+                                                : pack_f16x2(h[8 * p + 2 * q], h[8 * p + 2 * q + 1]));
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    i32x4 a4 = load_packet(Lj, (mt * 4 + p) * 64 + lane);
+                    if constexpr (FLAV == kBF16)
+                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a4),
+                                                                          __builtin_bit_cast(bf16x8, b4), acc[mt], 0, 0, 0);
+                    else
+                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a4),
+                                                                         __builtin_bit_cast(f16x8, b4), acc[mt], 0, 0, 0);
+                }
+            }
+        } else {
+            i32x8 b8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                b8[q] = pack_fp8x4(h[4 * q] * inv_next, h[4 * q + 1] * inv_next, h[4 * q + 2] * inv_next,
+                                   h[4 * q + 3] * inv_next);
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                i32x4 lo = load_packet(Lj, (mt * 2 + 0) * 64 + lane);
+                i32x4 hi = load_packet(Lj, (mt * 2 + 1) * 64 + lane);
+                i32x8 a8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                acc[mt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[mt], 0, 0, 0, 0, 0, 0);
+            }
+        }
+    }
+    // ------------------------------------------------------------------ output layer (binary32)
+    const float* wo = reinterpret_cast<const float*>(img + P.layer_off[hidden]) + half * 32;
+    float deq = 1.0f;
+    if constexpr (FLAV == kFP8) deq = scales[hidden - 1] * scales[2 * hidden - 1];
+    float zp = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        float v = acc[c / 16][c % 16];
+        if constexpr (FLAV == kFP8) v *= deq;
+        v = v > 0.0f ? v : 0.0f;
+        zp = fmaf(wo[c], v, zp);
+    }
+    return zp + __shfl_xor(zp, 32);
+}
+
+// ----------------------------------------------------------------------------
+// The fused kernel.
+// ----------------------------------------------------------------------------
+// MODE 0: fused query.  MODE 1: grid stage only (writes the MLP inputs and the
+// clip status).  MODE 2: inference stage only (reads MLP inputs, one MLP).
+template <int FLAV, int L, typename GT, int MODE>
+__global__ __launch_bounds__(kBlock) void nif_query_kernel(FwdArgs A) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr int KH1 = 3 * L;  // layer-1 local inputs per half: 3L/2 lookups x 2 latents
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int qlane = lane & 31;
+
+    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous share of the tiles so that neighbouring queries share its L2
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * A.xcd_stride + (b >> 3);
+    const int64_t t_begin = (int64_t)lb * A.num_tiles / A.tiles_per_block_num;
+    const int64_t t_end = (int64_t)(lb + 1) * A.num_tiles / A.tiles_per_block_num;
+    if (t_begin >= t_end) return;
+
+    // MLP of the block: that of the first query of its first tile
+    int32_t blk_mlp = A.fixed_mlp;
+    if (MODE == 0) {
+        int64_t q0 = t_begin * kQueriesPerBlock;
+        int32_t id0 = A.ids[q0];
+        if (id0 >= 0 && id0 < A.num_objects) blk_mlp = A.objs[id0].mlp;
+    }
+    if (MODE != 1) {
+        const uint8_t* src = A.packed + (int64_t)blk_mlp * A.pack.bytes;
+        const int nvec = (int)(A.pack.bytes / 16);
+        for (int i = threadIdx.x; i < nvec; i += kBlock)
+            reinterpret_cast<i32x4*>(smem)[i] = reinterpret_cast<const i32x4*>(src)[i];
+    }
+    __syncthreads();
+
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        const int64_t q = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
+        const bool inb = q < A.n;
+        float o[3] = {0, 0, 0}, d[3] = {1, 0, 0};
+        float tm = 0.0f;
+        int32_t id = -1;
+        if (inb && MODE != 2) {
+            const float* r = A.rays + q * 6;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
+            tm = A.tmax[q];
+            id = A.ids[q];
+        }
+        // status: 1 query, 0 miss (visible), -1 invalid, -2 out of range
+        int status = -2;
+        float xin[KH1];
+#pragma unroll
+        for (int c = 0; c < KH1; ++c) xin[c] = 0.0f;
+        int32_t mlp = -1;
+        if (MODE == 2) {
+            if (inb) {
+                status = 1;
+                mlp = A.fixed_mlp;
+                const float* src = A.features + q * (2 * KH1) + half * KH1;
+#pragma unroll
+                for (int c = 0; c < KH1; ++c) xin[c] = src[c];
+            }
+        } else if (inb) {
+            if (!valid_query(o, d, tm, id, A.num_objects)) {
+                status = -1;
+            } else {
+                const ObjDev ob = A.objs[id];
+                float u[3][3];
+                status = clip_normalise(o, d, tm, ob, u);
+                if (status == 1) {
+                    mlp = ob.mlp;
+                    encode_half<L, GT>(u, half, (const GLOBAL GT*)(ob.grid), A, xin);
+                }
+            }
+        }
+        if (MODE == 1) {
+            if (inb) {
+                float* dst = A.features + q * (2 * KH1) + half * KH1;
+#pragma unroll
+                for (int c = 0; c < KH1; ++c) dst[c] = xin[c];
+                if (half == 0 && A.status_out) A.status_out[q] = status;
+            }
+            continue;
+        }
+        // waterfall over the distinct MLPs of the wave's queries
+        float z = 0.0f;
+        uint64_t pend = __ballot(status == 1);
+        while (pend) {
+            const int first = __builtin_ctzll(pend);
+            const int m0 = __shfl(mlp, first);
+            const bool mine = status == 1 && mlp == m0;
+            float xb[KH1];
+#pragma unroll
+            for (int c = 0; c < KH1; ++c) xb[c] = mine ? xin[c] : 0.0f;
+            const float* sc = A.fp8_scales ? A.fp8_scales + (int64_t)m0 * 2 * A.hidden : nullptr;
+            float zz;
+            if (m0 == blk_mlp)
+                zz = run_mlp<FLAV, KH1>(smem, A.pack, A.hidden, xb, sc, lane);
+            else
+                zz = run_mlp<FLAV, KH1>(A.packed + (int64_t)m0 * A.pack.bytes, A.pack, A.hidden, xb, sc, lane);
+            if (mine) z = zz;
+            pend &= ~__ballot(mine);
+        }
+        if (inb && half == 0) {
+            float y, zo;
+            if (status == 1) {
+                zo = z;
+                y = 1.0f / (1.0f + expf(-z));
+            } else if (status == 0) {
+                zo = INFINITY;
+                y = 1.0f;
+            } else {
+                zo = NAN;
+                y = NAN;
+            }
+            if (A.vis) A.vis[q] = y;
+            if (A.logit) A.logit[q] = zo;
+        }
+    }
+}
+
+template <int FLAV, int L, typename GT, int MODE>
+static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
+    FwdArgs a = a0;
+    const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    // persistent-style grid: a few blocks per CU, a multiple of the 8 XCDs
+    int64_t blocks = (int64_t)num_cus * 8;
+    if (blocks > tiles) blocks = tiles;
+    blocks = (blocks + 7) / 8 * 8;
+    a.num_tiles = (int32_t)tiles;
+    a.tiles_per_block_num = (int32_t)blocks;
+    a.xcd_stride = (int32_t)(blocks / 8);
+    const size_t lds = MODE == 1 ? 0 : lds_bytes(a.pack);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((nif_query_kernel<FLAV, L, GT, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int FLAV, int MODE>
+static hipError_t launch_f(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
+    if (levels == 8) {
+        if (grid_dtype == 1) return launch_t<FLAV, 8, _Float16, MODE>(a, num_cus, s);
+        return launch_t<FLAV, 8, float, MODE>(a, num_cus, s);
+    }
+    if (grid_dtype == 1) return launch_t<FLAV, 4, _Float16, MODE>(a, num_cus, s);
+    return launch_t<FLAV, 4, float, MODE>(a, num_cus, s);
+}
+
+hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
+    switch (flavor) {
+    case kF32: return launch_f<kF32, 0>(levels, grid_dtype, a, num_cus, s);
+    case kBF16: return launch_f<kBF16, 0>(levels, grid_dtype, a, num_cus, s);
+    case kF16: return launch_f<kF16, 0>(levels, grid_dtype, a, num_cus, s);
+    case kFP8: return launch_f<kFP8, 0>(levels, grid_dtype, a, num_cus, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_encode(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
+    return launch_f<kF32, 1>(levels, grid_dtype, a, num_cus, s);
+}
+
+hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hipStream_t s) {
+    // the grid type is irrelevant when the features are given
+    switch (flavor) {
+    case kF32: return launch_f<kF32, 2>(levels, 1, a, num_cus, s);
+    case kBF16: return launch_f<kBF16, 2>(levels, 1, a, num_cus, s);
+    case kF16: return launch_f<kF16, 2>(levels, 1, a, num_cus, s);
+    case kFP8: return launch_f<kFP8, 2>(levels, 1, a, num_cus, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ----------------------------------------------------------------------------
+// Latent initialisation: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += W0; k1 += W1; }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+__global__ void init_grid_kernel(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp) {
+    const int64_t nblk = (count + 3) / 4;
+    const float scale = amp * 0x1p-23f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nblk; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t c[4] = {(uint64_t)i, 0, 0, 0};
+        philox4x64_10(c, seed, obj);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int64_t e = 4 * i + w;
+            if (e >= count) break;
+            const int32_t m = (int32_t)(c[w] >> 40);
+            const float v = (float)(m - (1 << 23)) * scale;
+            if (grid_dtype == 1)
+                reinterpret_cast<__half*>(grid)[e] = __float2half_rn(v);
+            else
+                reinterpret_cast<float*>(grid)[e] = v;
+        }
+    }
+}
+
+hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
+                            hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = ((count + 3) / 4 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(init_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, s, grid, grid_dtype, count, seed, obj,
+                       amp);
+    return hipGetLastError();
+}
+
+}  // namespace nif

@@ -1,0 +1,79 @@
+// Internal definitions shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nif {
+
+constexpr int kMaxLevels = 8;
+constexpr int kWidth = 64;      // hidden width covered by the MFMA tiling
+constexpr int kFeats = 2;       // latents per grid vertex
+constexpr int kMaxHidden = 8;
+constexpr int kBlock = 256;     // threads per block: 4 waves
+constexpr int kQueriesPerWave = 32;  // two lanes per query
+constexpr int kQueriesPerBlock = kBlock / 64 * kQueriesPerWave;
+
+// Per-object device record.  ext = hi - lo evaluated in binary32 once.
+struct ObjDev {
+    float lo[3];
+    float hi[3];
+    float ext[3];
+    int32_t mlp;
+    const void* grid;
+};
+
+enum Flavor { kF32 = 0, kF16 = 1, kBF16 = 2, kFP8 = 3 };
+
+// Packed weight image of one MLP for one arithmetic flavour.
+//
+// The MLP runs as 32x32 MFMA tiles with the 32 queries of a wave on the N
+// dimension; the two 32-lane halves of the wave split the K dimension.  Half h
+// owns "local" input features c = 0..Kh-1 of every layer:
+//  - layer 1: global feature h*(din/2) + c (the half encodes those lookups);
+//  - layer j > 1: the accumulator rows it holds, f(c) = 32*(c/16) + 8*((c%16)/4)
+//    + 4h + (c%4) (output row of accumulator register c%16 of M-tile c/16).
+// A K-step consumes the same local positions from both halves, so the packed
+// A operand of lane l (row 32*mt + l%32, half l/32) stores W[row][global(half, c)]
+// in local order.  Layout: per layer, per M-tile (2), per K-group, 64 lanes x
+// 16 bytes; w_out follows in binary32 permuted per half: wout[h][c] = w_out[f_h(c)].
+struct PackInfo {
+    int32_t din;        // MLP input width (3 * levels * feats)
+    int32_t hidden;
+    int64_t layer_off[kMaxHidden + 1];  // byte offsets of each layer's A image, [H] = w_out
+    int64_t bytes;      // total bytes per MLP
+};
+
+struct FwdArgs {
+    const float* rays;
+    const int32_t* ids;
+    const float* tmax;
+    int64_t n;
+    float* vis;
+    float* logit;
+    const ObjDev* objs;
+    int32_t num_objects;
+    int32_t hidden;
+    const uint8_t* packed;  // num_mlps x pack.bytes
+    PackInfo pack;
+    const float* fp8_scales;  // num_mlps x 2H (s_W then s_x) or null
+    int64_t toff[3 * kMaxLevels];
+    int32_t res[kMaxLevels];
+    float* features;         // grid stage output / inference stage input: n x din, or null
+    int32_t* status_out;     // grid stage: 1 query, 0 miss, -1 invalid (nullable)
+    int32_t fixed_mlp;       // inference stage: the MLP used by every query
+    int32_t tiles_per_block_num;  // tiles are split evenly: block b gets [b*T/G, (b+1)*T/G)
+    int32_t num_tiles;
+    int32_t xcd_stride;           // logical block = (b % 8) * xcd_stride + b / 8
+};
+
+PackInfo pack_info(int flavor, int din, int hidden);
+size_t lds_bytes(const PackInfo& p);
+
+hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s);
+hipError_t launch_encode(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s);
+hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hipStream_t s);
+hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
+                            hipStream_t s);
+
+}  // namespace nif

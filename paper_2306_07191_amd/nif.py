@@ -1,0 +1,196 @@
+"""Python binding of libnif.so (ctypes).
+
+Argument marshalling only: every step of a query or training step runs in the
+library's HIP kernels.  PyTorch supplies device memory (tensors) and the
+stream (torch.cuda.current_stream()).  If the library is missing, loading it
+raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnif.so")
+
+NIF_F32, NIF_F16, NIF_BF16, NIF_FP8_E4M3 = 0, 1, 2, 3
+DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
+STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3: "NIF_ERR_WORKSPACE",
+          -4: "NIF_ERR_HIP", -5: "NIF_ERR_STATE"}
+
+# every symbol include/nif.h declares
+EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
+           "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_train_step", "nif_touched_bytes",
+           "nif_last_error", "nif_version"]
+
+
+class NifError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("res_min", C.c_int32), ("res_max", C.c_int32), ("feats", C.c_int32),
+                ("grid_dtype", C.c_int32), ("hidden_layers", C.c_int32), ("width", C.c_int32)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Open libnif.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2306_07191_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "nif_create": (i32, [vp, i32, i32, vp]),
+            "nif_destroy": (None, [vp]),
+            "nif_param_layout": (i32, [vp, vp, vp, vp, vp]),
+            "nif_set_object": (i32, [vp, i32, vp, vp, i32]),
+            "nif_set_mlp": (i32, [vp, i32, vp]),
+            "nif_set_fp8_scales": (i32, [vp, i32, vp]),
+            "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
+            "nif_prepare": (i32, [vp, i32, vp]),
+            "nif_workspace_bytes": (sz, [vp, i64, i32]),
+            "nif_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+            "nif_encode": (i32, [vp, vp, vp, vp, i64, vp, vp, vp]),
+            "nif_mlp": (i32, [vp, i32, i32, vp, i64, vp, vp]),
+            "nif_train_step": (i32, [vp, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "nif_touched_bytes": (sz, [vp]),
+            "nif_last_error": (C.c_char_p, []),
+            "nif_version": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise NifError(status, where, lib().nif_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """A nif_ctx plus the device buffers the caller owns (torch tensors).
+
+    shape: synth.ModelShape-like object (levels, res_min, res_max, feats,
+    hidden, width, grid_dtype "f32"/"f16")."""
+
+    def __init__(self, shape, num_objects: int = 1, num_mlps: int = 1, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.shape = shape
+        self.K, self.M = num_objects, num_mlps
+        self.device = device
+        d = ModelDesc(shape.levels, shape.res_min, shape.res_max, shape.feats,
+                      NIF_F16 if shape.grid_dtype == "f16" else NIF_F32, shape.hidden, shape.width)
+        h = C.c_void_p()
+        _check(lib().nif_create(C.byref(d), num_objects, num_mlps, C.byref(h)), "nif_create")
+        self.h = h
+        ge = C.c_int64()
+        mp = C.c_int64()
+        off = np.zeros(3 * shape.levels + 1, np.int64)
+        res = np.zeros(shape.levels, np.int32)
+        _check(lib().nif_param_layout(self.h, C.byref(ge), off.ctypes.data, res.ctypes.data, C.byref(mp)),
+               "nif_param_layout")
+        self.grid_elems, self.mlp_params = ge.value, mp.value
+        self.table_offsets, self.level_res = off, res
+        self.grids = [None] * num_objects
+        self.mlps = [None] * num_mlps
+        self.aabb = np.zeros((num_objects, 6), np.float32)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nif_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- parameters ----------------------------------------------------
+    def alloc_grid(self):
+        t = self.torch
+        dt = t.float16 if self.shape.grid_dtype == "f16" else t.float32
+        return t.empty(self.grid_elems, dtype=dt, device=self.device)
+
+    def set_object(self, k: int, aabb, grid, mlp: int = 0):
+        a = np.ascontiguousarray(aabb, np.float32).reshape(6)
+        self.aabb[k] = a
+        self.grids[k] = grid
+        _check(lib().nif_set_object(self.h, k, a.ctypes.data, _ptr(grid), mlp), "nif_set_object")
+
+    def set_mlp(self, m: int, weights):
+        self.mlps[m] = weights
+        _check(lib().nif_set_mlp(self.h, m, _ptr(weights)), "nif_set_mlp")
+
+    def set_fp8_scales(self, m: int, scales):
+        s = np.ascontiguousarray(scales, np.float32)
+        _check(lib().nif_set_fp8_scales(self.h, m, s.ctypes.data), "nif_set_fp8_scales")
+
+    def init_grid(self, k: int, seed: int, amp: float = 1e-4):
+        _check(lib().nif_init_grid(self.h, k, seed, amp, _stream()), "nif_init_grid")
+
+    def prepare(self, dtype: str):
+        _check(lib().nif_prepare(self.h, DTYPES[dtype], _stream()), "nif_prepare")
+
+    def workspace_bytes(self, n: int, mode: int = 0) -> int:
+        return int(lib().nif_workspace_bytes(self.h, n, mode))
+
+    # ---- queries -------------------------------------------------------
+    def query(self, rays, ids, tmax, dtype: str = "f32", out=None, logits=None, ws=None):
+        t = self.torch
+        n = ids.shape[0]
+        if out is None:
+            out = t.empty(n, dtype=t.float32, device=self.device)
+        wsb = self.workspace_bytes(n, 0)
+        if ws is None and wsb > 0:
+            ws = t.empty(wsb, dtype=t.uint8, device=self.device)
+        _check(lib().nif_query(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(out),
+                               _ptr(logits), _ptr(ws), 0 if ws is None else ws.numel(), _stream()), "nif_query")
+        return out
+
+    def encode(self, rays, ids, tmax):
+        """Grid stage alone: (features [n, din], status [n])."""
+        t = self.torch
+        n = ids.shape[0]
+        f = t.empty((n, self.shape.din), dtype=t.float32, device=self.device)
+        st = t.empty(n, dtype=t.int32, device=self.device)
+        _check(lib().nif_encode(self.h, _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(f), _ptr(st), _stream()),
+               "nif_encode")
+        return f, st
+
+    def mlp(self, features, dtype: str = "f32", mlp: int = 0):
+        """Inference stage alone: logits of MLP `mlp` on features [n, din]."""
+        t = self.torch
+        n = features.shape[0]
+        z = t.empty(n, dtype=t.float32, device=self.device)
+        _check(lib().nif_mlp(self.h, DTYPES[dtype], mlp, _ptr(features), n, _ptr(z), _stream()), "nif_mlp")
+        return z

@@ -1,0 +1,80 @@
+"""The C-ABI library loads, exports every symbol include/nif.h declares, and
+validates arguments on the host (no GPU needed: these calls return before any
+device work)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_07191_amd import nif
+from paper_2306_07191_amd import synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nif.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nif_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_exports_agree():
+    assert _declared() == sorted(nif.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = nif.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.nif_version()
+
+
+def _desc(**kw):
+    d = dict(levels=4, res_min=4, res_max=32, feats=2, grid_dtype=0, hidden_layers=3, width=64)
+    d.update(kw)
+    return nif.ModelDesc(**d)
+
+
+@pytest.mark.parametrize("bad,code", [(dict(feats=3), -2), (dict(width=48), -2), (dict(levels=5), -2),
+                                      (dict(hidden_layers=0), -2), (dict(res_max=2), -2), (dict(grid_dtype=2), -2),
+                                      (dict(res_max=2048), -2)])
+def test_create_rejects_unsupported(bad, code):
+    h = C.c_void_p()
+    assert nif.lib().nif_create(C.byref(_desc(**bad)), 1, 1, C.byref(h)) == code
+    assert len(nif.lib().nif_last_error()) > 0
+
+
+def test_validation_before_device_work():
+    L = nif.lib()
+    h = C.c_void_p()
+    assert L.nif_create(None, 1, 1, C.byref(h)) == -1
+    assert L.nif_create(C.byref(_desc()), 0, 1, C.byref(h)) == -1
+    assert L.nif_create(C.byref(_desc()), 2, 1, C.byref(h)) == 0
+    try:
+        ge, mp = C.c_int64(), C.c_int64()
+        off = np.zeros(13, np.int64)
+        res = np.zeros(4, np.int32)
+        assert L.nif_param_layout(h, C.byref(ge), off.ctypes.data, res.ctypes.data, C.byref(mp)) == 0
+        assert list(res) == [4, 8, 16, 32] and mp.value == S.TINY.mlp_params
+        assert ge.value == off[-1] == 3 * 2 * sum((r + 1) ** 3 for r in res)
+        box = np.array([0, 0, 0, 1, 1, 1], np.float32)
+        flat = np.array([0, 0, 0, 1, 0, 1], np.float32)  # zero extent on y
+        fake = C.c_void_p(4096)
+        assert L.nif_set_object(h, 2, box.ctypes.data, fake, 0) == -1  # object out of range
+        assert L.nif_set_object(h, 0, box.ctypes.data, fake, 1) == -1  # MLP out of range
+        assert L.nif_set_object(h, 0, flat.ctypes.data, fake, 0) == -1  # degenerate box
+        assert L.nif_set_object(h, 0, box.ctypes.data, None, 0) == -1
+        assert L.nif_set_object(h, 0, box.ctypes.data, fake, 0) == 0
+        assert L.nif_query(h, 0, fake, fake, fake, -1, fake, None, None, 0, None) == -1  # n < 0
+        assert L.nif_query(h, 0, fake, fake, fake, 0, fake, None, None, 0, None) == 0   # n = 0: no-op
+        assert L.nif_query(h, 0, None, fake, fake, 10, fake, None, None, 0, None) == -1  # NULL rays
+        assert L.nif_query(h, 7, fake, fake, fake, 10, fake, None, None, 0, None) == -2  # unknown dtype
+        assert L.nif_query(h, 0, fake, fake, fake, 10, fake, None, None, 0, None) == -5  # not prepared
+        assert L.nif_prepare(h, 0, None) == -5  # object 1 and the MLP are not registered
+        sc = np.array([1, 1, 1, 0, 1, 1], np.float32)
+        assert L.nif_set_fp8_scales(h, 0, sc.ctypes.data) == -1  # zero scale
+        assert L.nif_last_error() != b""
+    finally:
+        L.nif_destroy(h)

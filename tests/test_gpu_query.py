@@ -1,0 +1,171 @@
+"""Parity of the HIP query path (nif_query through the C ABI) with the oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2306_07191_amd import synth as S
+
+from gpu_util import GRID_SEED, check_outputs, fp8_scales_from_oracle, make_pair, run_query
+
+pytestmark = pytest.mark.gpu
+
+
+def _lowp_vs_exact(y, ref_q, ref_exact):
+    """Reduced precision vs the unquantised binary64 result: within the per-query bound."""
+    hit = ref_exact["status"] == 1
+    dy = np.abs(y[hit] - ref_exact["y"][hit])
+    assert (dy <= ref_q["ybound"][hit]).all()
+    return float(dy.max(initial=0)), float(np.percentile(dy, 99.9))
+
+
+def test_init_grid_bit_exact():
+    import torch
+    for sh in (S.TINY, S.FRAME):
+        w = dict(shape=sh, aabb=np.array([[0, 0, 0, 1, 1, 1]], np.float32), mlps=np.zeros((1, sh.mlp_params), np.float32),
+                 mlp_index=np.zeros(1, np.int32))
+        ctx, _ = make_pair(w, grid_amp=1e-4)
+        g = ctx.grids[0]
+        torch.cuda.synchronize()
+        for begin in (0, 1, 12345, ctx.grid_elems - 999):
+            cnt = min(999, ctx.grid_elems - begin)
+            ref = O.init_grid(GRID_SEED, 0, 1e-4, sh.grid_dtype, cnt, begin)
+            got = g[begin:begin + cnt].cpu().numpy()
+            got = got.view(np.uint16) if sh.grid_dtype == "f16" else got
+            np.testing.assert_array_equal(got, ref)
+        del ctx, g
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("amp,gain", [(1e-4, 1.0), (1.0, 1.0), (0.5, 2.0)])
+def test_query_f32_tiny(amp, gain):
+    w = S.tiny_workload()
+    w["mlps"] = (w["mlps"].astype(np.float64) * gain).astype(np.float32)
+    ctx, model = make_pair(w, grid_amp=amp)
+    ref = model.forward(w["rays"], w["ids"], w["tmax"])
+    y, z = run_query(ctx, w, "f32")
+    st = check_outputs(y, z, ref, "f32", f"tiny amp={amp}")
+    print("f32 tiny", amp, gain, st)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("amp", [1e-4, 1.0])
+def test_query_lowp_tiny(dtype, amp):
+    w = S.tiny_workload()
+    ctx, model = make_pair(w, grid_amp=amp)
+    ref_x = model.forward(w["rays"], w["ids"], w["tmax"])
+    ref_q = model.with_(quant=dtype).forward(w["rays"], w["ids"], w["tmax"])
+    y, z = run_query(ctx, w, dtype)
+    st = check_outputs(y, z, ref_q, dtype, f"tiny {dtype} amp={amp}")
+    st["vs_exact_max_dy"], st["vs_exact_p999_dy"] = _lowp_vs_exact(y, ref_q, ref_x)
+    print(dtype, "tiny", amp, st)
+
+
+@pytest.mark.parametrize("amp", [1e-4, 1.0])
+def test_query_fp8_tiny(amp):
+    w = S.tiny_workload()
+    model = O.Model(w["shape"], w["aabb"], w["mlps"], grid_seed=GRID_SEED, grid_amp=amp)
+    scales = fp8_scales_from_oracle(model, w)
+    ctx, model_q = make_pair(w, grid_amp=amp, quant="fp8", fp8_scales=scales)
+    ref_q = model_q.forward(w["rays"], w["ids"], w["tmax"])
+    ref_x = model.forward(w["rays"], w["ids"], w["tmax"])
+    y, z = run_query(ctx, w, "fp8")
+    st = check_outputs(y, z, ref_q, "fp8", f"tiny fp8 amp={amp}")
+    st["vs_exact_max_dy"], st["vs_exact_p999_dy"] = _lowp_vs_exact(y, ref_q, ref_x)
+    print("fp8 tiny", amp, st)
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 129, 1000, 4097])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_query_ragged_sizes(n, dtype):
+    w = S.tiny_workload(n_rays=n)
+    ctx, model = make_pair(w, grid_amp=1.0)
+    ref = model.with_(quant="exact" if dtype == "f32" else dtype).forward(w["rays"], w["ids"], w["tmax"])
+    y, z = run_query(ctx, w, dtype)
+    check_outputs(y, z, ref, dtype, f"n={n}")
+
+
+def test_query_empty_and_errors():
+    import torch
+    from paper_2306_07191_amd import nif
+    w = S.tiny_workload(n_rays=64)
+    ctx, _ = make_pair(w, grid_amp=1.0)
+    ctx.prepare("f32")
+    e = torch.empty(0, device="cuda")
+    ctx.query(e.reshape(0, 6), torch.empty(0, dtype=torch.int32, device="cuda"), e, "f32")  # n = 0: no-op
+    with pytest.raises(nif.NifError) as ei:
+        ctx.query(torch.zeros(64, 6, device="cuda"), torch.zeros(64, dtype=torch.int32, device="cuda"),
+                  torch.zeros(64, device="cuda"), "bf16")  # not prepared for bf16
+    assert ei.value.status == -5
+
+
+def test_query_invalid_inputs():
+    w = S.tiny_workload(n_rays=300)
+    rays, tmax, ids = w["rays"], w["tmax"], w["ids"]
+    rays[0, 0] = np.nan
+    rays[1, 3:] = 0
+    tmax[2] = -1.0
+    ids[3] = 7
+    ids[4] = -1
+    rays[5, :3] = [10, 10, 10]
+    rays[5, 3:] = [0, 1, 0]
+    tmax[6] = 1e-3  # segment ends before the box
+    rays[7, 3:] = [0, 0, np.inf]
+    ctx, model = make_pair(w, grid_amp=1.0)
+    for dtype in ("f32", "bf16"):
+        ref = model.with_(quant="exact" if dtype == "f32" else dtype).forward(rays, ids, tmax)
+        assert list(ref["status"][:8]) == [-1, -1, -1, -1, -1, 0, 0, -1]
+        y, z = run_query(ctx, w, dtype)
+        check_outputs(y, z, ref, dtype, "invalid")
+
+
+def test_query_multi_object_multi_mlp():
+    """Several objects sharing three MLPs, ids shuffled: every wave mixes MLPs."""
+    g = np.random.default_rng(5)
+    K, M = 6, 3
+    boxes = []
+    for k in range(K):
+        c = g.uniform(-5, 5, 3)
+        h = g.uniform(0.3, 1.5, 3)
+        boxes.append(np.concatenate([c - h, c + h]))
+    boxes = np.array(boxes, np.float32)
+    n = 5000
+    ids = g.integers(0, K, n).astype(np.int32)
+    rays = np.empty((n, 6), np.float32)
+    tmax = np.empty(n, np.float32)
+    for k in range(K):
+        s = np.nonzero(ids == k)[0]
+        ctr = 0.5 * (boxes[k, :3] + boxes[k, 3:])
+        r, t = S.rays_sphere_to_box(s.size, boxes[k], g, radius=4.0, center=ctr)
+        rays[s], tmax[s] = r, t
+    mlps = np.stack([S.xavier_mlp(S.TINY, S.rng(99, 3, m)) for m in range(M)])
+    w = dict(shape=S.TINY, aabb=boxes, mlps=mlps, mlp_index=np.array([0, 1, 2, 0, 1, 2], np.int32),
+             rays=rays, tmax=tmax, ids=ids)
+    ctx, model = make_pair(w, grid_amp=1.0)
+    for dtype in ("f32", "bf16"):
+        ref = model.with_(quant="exact" if dtype == "f32" else dtype).forward(rays, ids, tmax)
+        y, z = run_query(ctx, w, dtype)
+        check_outputs(y, z, ref, dtype, f"multi {dtype}")
+
+
+@pytest.mark.parametrize("amp", [1e-4, 0.5])
+def test_query_frame_full_size_sampled(amp):
+    """Frame workload at full size (1920 x 1080 rays, 8 levels 16..512, binary16
+    latents, 2.1 GB grid) in the bench's launch configuration; sampled outputs
+    checked against the oracle (which regenerates latents lazily)."""
+    import torch
+    w = S.frame_workload(with_mesh=False)
+    ctx, model = make_pair(w, grid_amp=amp)
+    sel = np.sort(np.random.default_rng(0).choice(w["ids"].shape[0], 3000, replace=False))
+    sel = np.concatenate([sel, np.arange(w["ids"].shape[0] - 40, w["ids"].shape[0])])  # ragged tail
+    rays, ids, tmax = w["rays"][sel], w["ids"][sel], w["tmax"][sel]
+    scales = fp8_scales_from_oracle(model, dict(w, rays=rays, ids=ids, tmax=tmax))
+    for m in range(1):
+        ctx.set_fp8_scales(m, scales[m])
+    for dtype in ("f32", "bf16", "f16", "fp8"):
+        mq = model.with_(quant="exact" if dtype == "f32" else dtype, fp8_scales=scales if dtype == "fp8" else None)
+        ref = mq.forward(rays, ids, tmax)
+        y, z = run_query(ctx, w, dtype, sel=sel)
+        st = check_outputs(y, z, ref, dtype, f"frame {dtype} amp={amp}")
+        print("frame", dtype, amp, st)
+    del ctx
+    torch.cuda.empty_cache()

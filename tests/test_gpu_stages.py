@@ -1,0 +1,97 @@
+"""The two stages of a query run separately (grid stage, inference stage), each
+checked against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2306_07191_amd import synth as S
+
+from gpu_util import make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape_name", ["tiny", "frame_small"])
+def test_encode_matches_oracle(shape_name):
+    import torch
+    if shape_name == "tiny":
+        w = S.tiny_workload(n_rays=3000)
+    else:
+        w = S.frame_workload(n_rays=3000, with_mesh=False)
+    amp = 0.5
+    ctx, model = make_pair(w, grid_amp=amp)
+    ctx.prepare("f32")
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    f, st = ctx.encode(rays, ids, tmax)
+    torch.cuda.synchronize()
+    f, st = f.cpu().numpy().astype(np.float64), st.cpu().numpy()
+    ref = model.forward(w["rays"], w["ids"], w["tmax"], want_x=True)
+    np.testing.assert_array_equal(st, ref["status"])
+    hit = st == 1
+    err = np.abs(f[hit] - ref["x"][hit])
+    # binary32 interpolation of latents bounded by amp: a few rounding units of amp
+    assert err.max() <= 1e-6 * amp, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    assert (f[~hit] == 0).all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_mlp_matches_oracle(dtype):
+    import torch
+    w = S.tiny_workload(n_rays=2000)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    g = np.random.default_rng(3)
+    x = g.uniform(-1, 1, (2000, w["shape"].din)).astype(np.float32)
+    ctx.prepare(dtype)
+    z = ctx.mlp(torch.from_numpy(x).cuda(), dtype=dtype)
+    torch.cuda.synchronize()
+    z = z.cpu().numpy().astype(np.float64)
+    mq = model.with_(quant="exact" if dtype == "f32" else dtype)
+    zr = mq.mlp_only(x.astype(np.float64))
+    err = np.abs(z - zr)
+    tol = 1e-5 * np.maximum(np.abs(zr), 1e-2) if dtype == "f32" else 2e-2 * np.maximum(np.abs(zr), 1e-1)
+    print(dtype, "max err", err.max(), "median", np.median(err))
+    assert (err <= tol).mean() >= 0.999, (err.max(), np.median(err))
+
+
+@pytest.mark.parametrize("hidden", [1, 2])
+def test_fp8_exact_when_representable(hidden):
+    """FP8 with unit scales on operands that are E4M3 values whose products stay
+    within a factor 2^3 of each other: no quantisation and no truncation inside
+    the matrix core, so the result equals the exact one up to binary32 sums."""
+    import torch
+    from oracle import oracle as O
+    from paper_2306_07191_amd import nif
+    sh = S.ModelShape(levels=4, res_min=4, res_max=32, feats=2, hidden=hidden, width=64, grid_dtype="f32")
+    g = np.random.default_rng(11)
+    mant = np.array([1.0, 1.125, 1.25, 1.375, 1.5, 1.625, 1.75, 1.875])
+    def e4m3_values(n, lo_exp, hi_exp):
+        return g.choice(mant, n) * 2.0 ** g.integers(lo_exp, hi_exp + 1, n) * g.choice([-1.0, 1.0], n)
+    P = sh.mlp_params
+    W = np.zeros(P)
+    n1 = sh.width * sh.din
+    W[:n1] = e4m3_values(n1, -1, -1)  # [0.5, 1)
+    off = n1
+    for j in range(1, hidden):
+        # second layer: powers of two only, so every product is exact and within range
+        W[off: off + sh.width * sh.width] = 2.0 ** -7 * g.choice([-1.0, 1.0], sh.width * sh.width)
+        off += sh.width * sh.width
+    W[off:] = g.standard_normal(sh.width)
+    x = e4m3_values(500 * sh.din, 0, 0).reshape(500, sh.din)  # [1, 2)
+    w = dict(shape=sh, aabb=np.array([[0, 0, 0, 1, 1, 1]], np.float32), mlps=W[None].astype(np.float32),
+             mlp_index=np.zeros(1, np.int32))
+    ctx = nif.Context(sh)
+    ctx.set_mlp(0, torch.from_numpy(W.astype(np.float32)).cuda())
+    ctx.set_object(0, w["aabb"][0], ctx.alloc_grid(), 0)
+    # unit scales except the input of layer 2 (s_x2 = 16): layer-1 outputs are exact
+    # (multiples of 2^-7 below 96), a / 16 rounds identically on both sides, and the
+    # layer-2 products (codes x 2^-7) stay within 2^11.6 of each other
+    sc = np.array([1.0] * hidden + [1.0, 16.0][:hidden], np.float32)
+    ctx.set_fp8_scales(0, sc)
+    ctx.prepare("fp8")
+    z = ctx.mlp(torch.from_numpy(x.astype(np.float32)).cuda(), dtype="fp8").cpu().numpy().astype(np.float64)
+    m = O.Model(sh, w["aabb"], w["mlps"], quant="fp8", fp8_scales=sc.astype(np.float64)[None])
+    zr = m.mlp_only(x)
+    if hidden == 1:
+        h = np.maximum(x @ W[:n1].reshape(sh.width, sh.din).T, 0)
+        np.testing.assert_allclose(zr, h @ W[-sh.width:], rtol=1e-12, atol=1e-12)  # the oracle's emulation is exact here
+    mag = np.abs(W[-sh.width:]).sum() * 200.0
+    assert np.abs(z - zr).max() <= 64 * 2.0 ** -24 * mag, np.abs(z - zr).max()
