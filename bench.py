@@ -109,37 +109,54 @@ def main():
     torch.cuda.synchronize()
 
     flops = 2 * (sh.din * sh.width + (sh.hidden - 1) * sh.width * sh.width + sh.width)  # 30,848 per query
+    ws = torch.empty(max(1, ctx.workspace_bytes(n)), dtype=torch.uint8, device="cuda")
     per_dtype = {}
     gpu_y = {}
-    for dtype in ("f32", "f16", "bf16"):
-        ctx.prepare(dtype)
-        sec = time_launches(lambda: ctx.query(rays, ids, tmax, dtype=dtype, out=y), max(5, args.steps // 5), 2)
-        per_dtype[dtype] = {"queries_per_s": n / sec, "us_per_launch": sec * 1e6,
-                            "mfma_frac": flops * n / sec / (PEAK_TFLOPS[dtype] * 1e12)}
-        gpu_y[dtype] = y.cpu().numpy().copy()
-        log(f"{dtype}: {sec * 1e6:.1f} us/launch, {n / sec / 1e9:.3f} G queries/s")
+    for order in (0, 2):
+        ctx.set_option(nif.NIF_OPT_ORDER, order)
+        for dtype in ("f32", "f16", "bf16"):
+            ctx.prepare(dtype)
+            sec = time_launches(lambda: ctx.query(rays, ids, tmax, dtype=dtype, out=y, ws=ws), max(5, args.steps // 5), 2)
+            key = dtype if order else dtype + "_unordered"
+            per_dtype[key] = {"queries_per_s": n / sec, "us_per_call": sec * 1e6}
+            if order:
+                gpu_y[dtype] = y.cpu().numpy().copy()
+            log(f"{key}: {sec * 1e6:.1f} us/call, {n / sec / 1e9:.3f} G queries/s")
 
-    # the contract timing for the headline dtype
+    # the contract timing for the headline dtype: a step is the ordering pass plus
+    # the fused query kernel; events around the kernel give its own duration
     ctx.prepare(HEADLINE_DTYPE)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    ows = torch.empty(max(1, nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
+
+    def step():
+        ctx.order(rays, ids, tmax, perm=perm, ws=ows)
+        ctx.query_ordered(rays, ids, tmax, perm, dtype=HEADLINE_DTYPE, out=y)
+
     for _ in range(args.warmup):
-        ctx.query(rays, ids, tmax, dtype=HEADLINE_DTYPE, out=y)
+        step()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
     w0 = time.perf_counter()
-    e0.record(s)
-    for _ in range(args.steps):
-        ctx.query(rays, ids, tmax, dtype=HEADLINE_DTYPE, out=y)
-    e1.record(s)
+    ev[0].record(s)
+    for k in range(args.steps):
+        ctx.order(rays, ids, tmax, perm=perm, ws=ows)
+        ev[2 * k + 1].record(s)
+        ctx.query_ordered(rays, ids, tmax, perm, dtype=HEADLINE_DTYPE, out=y)
+        ev[2 * k + 2].record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    sec = e0.elapsed_time(e1) / 1e3 / args.steps
+    sec = ev[0].elapsed_time(ev[-1]) / 1e3 / args.steps
+    kern = sum(ev[2 * k + 1].elapsed_time(ev[2 * k + 2]) for k in range(args.steps)) / 1e3 / args.steps
     value = n / sec
-    achieved_tflops = flops * n / sec / 1e12
+    achieved_tflops = flops * n / kern / 1e12
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_TFLOPS[HEADLINE_DTYPE],
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": None,
-                "kernel": "nif_query_kernel<bf16, L=8, f16 grid>", "algorithmic_flop_per_launch": flops * n,
-                "us_per_launch": sec * 1e6}
+                "kernel": "nif_query_kernel<bf16, L=8, f16 grid> (fused clip+encode+MLP)",
+                "algorithmic_flop_per_launch": flops * n, "kernel_us": kern * 1e6,
+                "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6}
+    log(f"step {sec * 1e6:.1f} us (order {(sec - kern) * 1e6:.1f} us, fused kernel {kern * 1e6:.1f} us)")
 
     cpu = None
     errs = None

@@ -111,6 +111,13 @@ nif_status nif_init_grid(nif_ctx* ctx, int32_t obj, uint64_t seed, float amp, vo
  * that dtype.  Enqueued on stream. */
 nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
 
+/* Options.  NIF_OPT_ORDER: before a query, bucket-sort the queries by
+ * (object, Morton code of the AABB entry point) so that a wave's gathers share
+ * cache lines and waves use one MLP: 0 never, 1 always, 2 (default) when
+ * n >= 65536.  Changes nif_workspace_bytes. */
+enum { NIF_OPT_ORDER = 1 };
+nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
+
 /* Workspace bytes needed by nif_query / nif_train_step for n queries. */
 size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode /* 0 query, 1 train */);
 
@@ -127,6 +134,21 @@ size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode /* 0 quer
  *   ws: workspace of at least nif_workspace_bytes(ctx, n, 0) bytes (dev). */
 nif_status nif_query(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids, const float* t_max,
                      int64_t n, float* visibility, float* logits, void* ws, size_t ws_bytes, void* stream);
+
+/* The ordering step and the query on a given order, as two calls (nif_query
+ * runs both when NIF_OPT_ORDER selects ordering).
+ * nif_order: perm (dev, n uint32) receives a permutation of [0, n): queries
+ *   grouped by object, then by Morton code of their AABB entry point; misses
+ *   and invalid queries last.  ws: nif_order_workspace_bytes(ctx, n) bytes.
+ *   Needs nif_prepare (any dtype) for the object table.
+ * nif_query_ordered: as nif_query, processing query perm[i] in slot i; perm
+ *   must be a permutation of [0, n) (any order gives the same outputs). */
+size_t nif_order_workspace_bytes(const nif_ctx* ctx, int64_t n);
+nif_status nif_order(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max, int64_t n,
+                     uint32_t* perm, void* ws, size_t ws_bytes, void* stream);
+nif_status nif_query_ordered(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids,
+                             const float* t_max, const uint32_t* perm, int64_t n, float* visibility, float* logits,
+                             void* stream);
 
 /* The two stages of a query as separate launches, as the paper's pipeline runs
  * them (Sec. 4.1: a grid-lookup kernel, then an inference kernel).

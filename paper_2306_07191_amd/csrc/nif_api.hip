@@ -57,7 +57,14 @@ struct nif_ctx {
     bool prepared[4] = {false, false, false, false};
     int num_cus = 256;
     int device = 0;
+    int32_t order_mode = 2;  // NIF_ORDER_AUTO
 };
+
+static bool uses_order(const nif_ctx* c, int64_t n) {
+    if (c->order_mode == 0) return false;
+    if (c->order_mode == 1) return true;
+    return n >= 65536;
+}
 
 extern "C" const char* nif_last_error(void) { return g_err.c_str(); }
 extern "C" const char* nif_version(void) { return "nif-mi355x 0.1 (gfx950)"; }
@@ -320,24 +327,37 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
 }
 
 extern "C" size_t nif_workspace_bytes(const nif_ctx* c, int64_t n, int32_t mode) {
-    (void)c;
-    (void)n;
+    if (!c || n <= 0) return 0;
     (void)mode;
-    return 0;
+    return uses_order(c, n) ? order_workspace_bytes(n, c->K) : 0;
 }
 
-extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
-                                int64_t n, float* vis, float* logits, void* ws, size_t ws_bytes, void* stream) {
-    (void)ws;
-    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_query: NULL context");
-    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_query: n < 0");
+extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_set_option: NULL context");
+    switch (option) {
+    case NIF_OPT_ORDER:
+        if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_ORDER takes 0, 1 or 2");
+        c->order_mode = (int32_t)value;
+        return ok();
+    }
+    return fail(NIF_ERR_INVALID_ARG, "unknown option %d", option);
+}
+
+static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, const void* ids, const void* tmax,
+                                   int64_t n, const void* vis, const char* where) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "%s: NULL context", where);
+    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "%s: n < 0", where);
     if (dtype < 0 || dtype > 3) return fail(NIF_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
-    if (n == 0) return ok();
-    if (!rays || !ids || !tmax || !vis) return fail(NIF_ERR_INVALID_ARG, "nif_query: NULL input or output");
-    if (n > (int64_t)1 << 36) return fail(NIF_ERR_UNSUPPORTED, "nif_query: n too large");
-    if (ws_bytes < nif_workspace_bytes(c, n, 0)) return fail(NIF_ERR_WORKSPACE, "workspace too small");
-    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    if (n == 0) return NIF_OK;
+    if (!rays || !ids || !tmax || !vis) return fail(NIF_ERR_INVALID_ARG, "%s: NULL input or output", where);
+    if (n > ((int64_t)1 << 32) - 1) return fail(NIF_ERR_UNSUPPORTED, "%s: n must be below 2^32", where);
+    return NIF_OK;
+}
+
+static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
+                            const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s) {
     FwdArgs a{};
+    a.perm = perm;
     a.rays = rays;
     a.ids = ids;
     a.tmax = tmax;
@@ -352,8 +372,63 @@ extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, co
     a.fp8_scales = dtype == kFP8 ? c->d_scales : nullptr;
     for (int k = 0; k < 3 * c->d.levels; ++k) a.toff[k] = c->toff[k];
     for (int l = 0; l < c->d.levels; ++l) a.res[l] = c->res[l];
-    HIP_TRY(launch_forward(dtype, c->d.levels, c->d.grid_dtype, a, c->num_cus, (hipStream_t)stream));
+    HIP_TRY(launch_forward(dtype, c->d.levels, c->d.grid_dtype, a, c->num_cus, s));
     return ok();
+}
+
+static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
+                            uint32_t* perm_dst, void* ws, const uint32_t** perm, hipStream_t s) {
+    OrderArgs o{};
+    o.rays = rays;
+    o.ids = ids;
+    o.tmax = tmax;
+    o.n = n;
+    o.objs = c->d_objs;
+    o.num_objects = c->K;
+    o.perm = perm_dst;
+    HIP_TRY(launch_order(o, ws, s, perm));
+    return ok();
+}
+
+extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
+                                int64_t n, float* vis, float* logits, void* ws, size_t ws_bytes, void* stream) {
+    nif_status st = check_query_args(c, dtype, rays, ids, tmax, n, vis, "nif_query");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    const size_t need = nif_workspace_bytes(c, n, 0);
+    if (ws_bytes < need || (need > 0 && !ws)) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    const uint32_t* perm = nullptr;
+    if (need > 0) {
+        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream);
+        if (st != NIF_OK) return st;
+    }
+    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream);
+}
+
+extern "C" size_t nif_order_workspace_bytes(const nif_ctx* c, int64_t n) {
+    if (!c || n <= 0) return 0;
+    return order_workspace_bytes(n, c->K);
+}
+
+extern "C" nif_status nif_order(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
+                                uint32_t* perm, void* ws, size_t ws_bytes, void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, perm, "nif_order");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    const size_t need = order_workspace_bytes(n, c->K);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    const uint32_t* p = nullptr;
+    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream);
+}
+
+extern "C" nif_status nif_query_ordered(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids,
+                                        const float* tmax, const uint32_t* perm, int64_t n, float* vis, float* logits,
+                                        void* stream) {
+    nif_status st = check_query_args(c, dtype, rays, ids, tmax, n, vis, "nif_query_ordered");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    if (!perm) return fail(NIF_ERR_INVALID_ARG, "nif_query_ordered: NULL perm");
+    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream);
 }
 
 static void fill_common(const nif_ctx* c, FwdArgs& a) {

@@ -1,0 +1,62 @@
+// Device helpers shared by the library's kernels (query, ordering, training).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nif_internal.h"
+
+namespace nif {
+
+// ----------------------------------------------------------------------------
+// Clip and normalisation, binary32, no contraction.
+// Returns 1 if the segment [max(t_near,0), min(t_far,t_max)] is non-empty.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int clip_normalise(const float o[3], const float d[3], float tmax, const ObjDev& b,
+                                              float u[3][3]) {
+#pragma clang fp contract(off)
+    float tn = -INFINITY, tf = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < b.lo[a] || o[a] > b.hi[a]) return 0;
+            continue;
+        }
+        float t0 = (b.lo[a] - o[a]) / d[a];
+        float t1 = (b.hi[a] - o[a]) / d[a];
+        float l = t0 < t1 ? t0 : t1, h = t0 < t1 ? t1 : t0;
+        if (l > tn) tn = l;
+        if (h < tf) tf = h;
+    }
+    float ta = tn > 0.0f ? tn : 0.0f;
+    float tb = tf < tmax ? tf : tmax;
+    if (!(ta <= tb)) return 0;
+    float len2 = d[0] * d[0];
+    len2 = len2 + d[1] * d[1];
+    len2 = len2 + d[2] * d[2];
+    float len = sqrtf(len2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float pin = o[a] + ta * d[a];
+        float pout = o[a] + tb * d[a];
+        float ui = (pin - b.lo[a]) / b.ext[a];
+        float uo = (pout - b.lo[a]) / b.ext[a];
+        float ud = (d[a] / len + 1.0f) * 0.5f;
+        // clamp to [0, 1]; NaN (an infinite segment end) maps to 0
+        u[0][a] = ui > 0.0f ? (ui < 1.0f ? ui : 1.0f) : 0.0f;
+        u[1][a] = uo > 0.0f ? (uo < 1.0f ? uo : 1.0f) : 0.0f;
+        u[2][a] = ud > 0.0f ? (ud < 1.0f ? ud : 1.0f) : 0.0f;
+    }
+    return 1;
+}
+
+__device__ __forceinline__ bool valid_query(const float o[3], const float d[3], float tmax, int32_t id, int32_t K) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = ok && isfinite(o[a]) && isfinite(d[a]);
+    ok = ok && !(d[0] == 0.0f && d[1] == 0.0f && d[2] == 0.0f);
+    ok = ok && !(tmax != tmax) && tmax >= 0.0f;
+    ok = ok && id >= 0 && id < K;
+    return ok;
+}
+
+}  // namespace nif

@@ -59,6 +59,7 @@ struct FwdArgs {
     const float* fp8_scales;  // num_mlps x 2H (s_W then s_x) or null
     int64_t toff[3 * kMaxLevels];
     int32_t res[kMaxLevels];
+    const uint32_t* perm;    // processing order: query perm[q] is handled in slot q (null = identity)
     float* features;         // grid stage output / inference stage input: n x din, or null
     int32_t* status_out;     // grid stage: 1 query, 0 miss, -1 invalid (nullable)
     int32_t fixed_mlp;       // inference stage: the MLP used by every query
@@ -66,6 +67,26 @@ struct FwdArgs {
     int32_t num_tiles;
     int32_t xcd_stride;           // logical block = (b % 8) * xcd_stride + b / 8
 };
+
+struct OrderArgs {
+    const float* rays;
+    const int32_t* ids;
+    const float* tmax;
+    int64_t n;
+    const ObjDev* objs;
+    int32_t num_objects;
+    int32_t bits;          // Morton bits per axis
+    uint32_t num_buckets;  // (num_objects << 3 bits) + 1; the last holds misses and invalid queries
+    uint32_t* hist;
+    uint32_t* block_sums;
+    uint32_t* bucket;
+    uint32_t* rank;
+    uint32_t* perm;
+};
+
+int order_bits(int32_t num_objects);
+size_t order_workspace_bytes(int64_t n, int32_t num_objects);
+hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out);
 
 PackInfo pack_info(int flavor, int din, int hidden);
 size_t lds_bytes(const PackInfo& p);

@@ -16,6 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libnif.so")
 
 NIF_F32, NIF_F16, NIF_BF16, NIF_FP8_E4M3 = 0, 1, 2, 3
+NIF_OPT_ORDER = 1
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
 STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3: "NIF_ERR_WORKSPACE",
           -4: "NIF_ERR_HIP", -5: "NIF_ERR_STATE"}
@@ -23,6 +24,7 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_train_step", "nif_touched_bytes",
            "nif_last_error", "nif_version"]
 
@@ -63,6 +65,10 @@ def lib():
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
             "nif_prepare": (i32, [vp, i32, vp]),
             "nif_workspace_bytes": (sz, [vp, i64, i32]),
+            "nif_set_option": (i32, [vp, i32, i64]),
+            "nif_order_workspace_bytes": (sz, [vp, i64]),
+            "nif_order": (i32, [vp, vp, vp, vp, i64, vp, vp, sz, vp]),
+            "nif_query_ordered": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp]),
             "nif_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
             "nif_encode": (i32, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "nif_mlp": (i32, [vp, i32, i32, vp, i64, vp, vp]),
@@ -161,6 +167,9 @@ class Context:
     def prepare(self, dtype: str):
         _check(lib().nif_prepare(self.h, DTYPES[dtype], _stream()), "nif_prepare")
 
+    def set_option(self, option: int, value: int):
+        _check(lib().nif_set_option(self.h, option, value), "nif_set_option")
+
     def workspace_bytes(self, n: int, mode: int = 0) -> int:
         return int(lib().nif_workspace_bytes(self.h, n, mode))
 
@@ -175,6 +184,27 @@ class Context:
             ws = t.empty(wsb, dtype=t.uint8, device=self.device)
         _check(lib().nif_query(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(out),
                                _ptr(logits), _ptr(ws), 0 if ws is None else ws.numel(), _stream()), "nif_query")
+        return out
+
+    def order(self, rays, ids, tmax, perm=None, ws=None):
+        """Ordering step alone: a permutation of [0, n) (int32 tensor, uint32 values)."""
+        t = self.torch
+        n = ids.shape[0]
+        if perm is None:
+            perm = t.empty(n, dtype=t.int32, device=self.device)
+        if ws is None:
+            ws = t.empty(max(1, int(lib().nif_order_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
+        _check(lib().nif_order(self.h, _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(perm), _ptr(ws), ws.numel(),
+                               _stream()), "nif_order")
+        return perm
+
+    def query_ordered(self, rays, ids, tmax, perm, dtype: str = "f32", out=None, logits=None):
+        t = self.torch
+        n = ids.shape[0]
+        if out is None:
+            out = t.empty(n, dtype=t.float32, device=self.device)
+        _check(lib().nif_query_ordered(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(perm), n,
+                                       _ptr(out), _ptr(logits), _stream()), "nif_query_ordered")
         return out
 
     def encode(self, rays, ids, tmax):

@@ -169,3 +169,65 @@ def test_query_frame_full_size_sampled(amp):
         print("frame", dtype, amp, st)
     del ctx
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_ordering_is_transparent(dtype):
+    """Queries bucket-sorted by (object, entry-point Morton code) before the kernel give
+    bit-identical outputs to the unordered launch: each query is computed on its own."""
+    import torch
+    from paper_2306_07191_amd import nif
+    g = np.random.default_rng(9)
+    K = 3
+    boxes = np.array([[-1, -1, -1, 1, 1, 1], [2, 0, 0, 3, 1, 2], [-4, -3, 0, -2, -1, 1]], np.float32)
+    n = 70000
+    ids = g.integers(0, K, n).astype(np.int32)
+    rays = np.empty((n, 6), np.float32)
+    tmax = np.empty(n, np.float32)
+    for k in range(K):
+        s = np.nonzero(ids == k)[0]
+        ctr = 0.5 * (boxes[k, :3] + boxes[k, 3:])
+        r, tt = S.rays_sphere_to_box(s.size, boxes[k], g, radius=4.0, center=ctr)
+        rays[s], tmax[s] = r, tt
+    rays[::97, 3:] = -rays[::97, 3:]  # some misses
+    ids[::1001] = 9                   # some invalid ids
+    mlps = np.stack([S.xavier_mlp(S.TINY, S.rng(98, 3, m)) for m in range(2)])
+    w = dict(shape=S.TINY, aabb=boxes, mlps=mlps, mlp_index=np.array([0, 1, 0], np.int32), rays=rays, tmax=tmax, ids=ids)
+    scales = np.ones((2, 2 * S.TINY.hidden)) * 0.01 if dtype == "fp8" else None
+    ctx, model = make_pair(w, grid_amp=1.0, quant="exact" if dtype == "f32" else dtype, fp8_scales=scales)
+    outs = []
+    for mode in (0, 1):
+        ctx.set_option(nif.NIF_OPT_ORDER, mode)
+        outs.append(run_query(ctx, w, dtype))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    ref = model.forward(rays, ids, tmax)
+    check_outputs(outs[1][0], outs[1][1], ref, dtype, f"ordered {dtype}")
+
+
+def test_order_is_a_grouped_permutation():
+    import torch
+    from paper_2306_07191_amd import nif
+    g = np.random.default_rng(13)
+    K, n = 5, 50000
+    boxes = np.array([[k * 3.0, 0, 0, k * 3.0 + 2, 1, 1] for k in range(K)], np.float32)
+    ids = g.integers(0, K, n).astype(np.int32)
+    rays = np.empty((n, 6), np.float32)
+    tmax = np.empty(n, np.float32)
+    for k in range(K):
+        s = np.nonzero(ids == k)[0]
+        r, tt = S.rays_sphere_to_box(s.size, boxes[k], g, radius=3.0, center=0.5 * (boxes[k, :3] + boxes[k, 3:]))
+        rays[s], tmax[s] = r, tt
+    rays[::50, 3:] = -rays[::50, 3:]
+    ids[::777] = -3
+    w = dict(shape=S.TINY, aabb=boxes, mlps=S.xavier_mlp(S.TINY, S.rng(1, 3))[None], mlp_index=np.zeros(K, np.int32),
+             rays=rays, tmax=tmax, ids=ids)
+    ctx, model = make_pair(w, grid_amp=1.0)
+    ctx.prepare("f32")
+    perm = ctx.order(*(torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))).cpu().numpy()
+    assert np.array_equal(np.sort(perm), np.arange(n))  # a permutation
+    st = model.forward(rays, ids, tmax)["status"]
+    hit = st[perm] == 1
+    nh = hit.sum()
+    assert hit[:nh].all() and not hit[nh:].any()       # misses and invalid queries last
+    assert (np.diff(ids[perm[:nh]]) >= 0).all()          # grouped by object

@@ -91,7 +91,8 @@ def test_fp8_exact_when_representable(hidden):
     m = O.Model(sh, w["aabb"], w["mlps"], quant="fp8", fp8_scales=sc.astype(np.float64)[None])
     zr = m.mlp_only(x)
     if hidden == 1:
-        h = np.maximum(x @ W[:n1].reshape(sh.width, sh.din).T, 0)
-        np.testing.assert_allclose(zr, h @ W[-sh.width:], rtol=1e-12, atol=1e-12)  # the oracle's emulation is exact here
+        W32 = W.astype(np.float32).astype(np.float64)
+        h = np.maximum(x @ W32[:n1].reshape(sh.width, sh.din).T, 0)
+        np.testing.assert_allclose(zr, h @ W32[-sh.width:], rtol=1e-12, atol=1e-12)  # the oracle's emulation is exact here
     mag = np.abs(W[-sh.width:]).sum() * 200.0
     assert np.abs(z - zr).max() <= 64 * 2.0 ** -24 * mag, np.abs(z - zr).max()
