@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true",
+                    help="time the headline step only (no per-dtype sweep, no CPU baseline): for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -112,7 +114,7 @@ def main():
     ws = torch.empty(max(1, ctx.workspace_bytes(n)), dtype=torch.uint8, device="cuda")
     per_dtype = {}
     gpu_y = {}
-    for order in (0, 2):
+    for order in (() if args.quick else (0, 2)):
         ctx.set_option(nif.NIF_OPT_ORDER, order)
         for dtype in ("f32", "f16", "bf16"):
             ctx.prepare(dtype)
@@ -160,7 +162,7 @@ def main():
 
     cpu = None
     errs = None
-    if not args.no_cpu:
+    if not (args.no_cpu or args.quick):
         cpu, errs = cpu_baseline(w, gpu_y)
         log(f"cpu oracle: {cpu['value']:.0f} queries/s on {cpu['cores']} cores")
 

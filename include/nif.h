@@ -169,32 +169,58 @@ typedef struct {
     float lr, beta1, beta2, eps;
 } nif_adam;
 
-/* One training step on n labelled queries (Sec. 4.2; Sec. 5 "Training").
- * labels (dev, n bytes): 1 = visible, 0 = occluded.  Loss: binary
- * cross-entropy on the logit, averaged over the B queries that meet their
- * AABB.  Backward through the MLP and into the grids (every interpolation
- * corner receives weight x feature gradient), then Adam with bias correction
- * for global step `step` (1-based) on every MLP weight and on every latent
- * whose gradient is non-zero this step (others keep latent and moments).
- * Latents are updated in binary32 and rounded to grid_dtype; MLP masters stay
- * binary32.
- *   grid_grad, grid_m, grid_v (dev, per object: pointer arrays (host) of
- *   num_objects buffers of grid_elems floats): gradient accumulator, first and
- *   second moments.  grid_grad must be all zero before the first step; the
- *   step leaves it zero again.  touched (host array of num_objects dev
- *   pointers, each nif_touched_bytes): zero before the first step, left zero.
- *   mlp_m, mlp_v (dev, num_mlps x mlp_params floats).
- *   loss (dev, 1 float, nullable): mean loss of this batch.
- *   mlp_grad_out (dev, num_mlps x mlp_params floats, nullable): the MLP
- *   gradient of this batch. */
-nif_status nif_train_step(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max,
-                          const uint8_t* labels, int64_t n, int32_t step, const nif_adam* adam,
-                          float* const* grid_grad, float* const* grid_m, float* const* grid_v,
-                          uint32_t* const* touched, float* mlp_m, float* mlp_v, float* loss, float* mlp_grad_out,
-                          void* ws, size_t ws_bytes, void* stream);
-
-/* Bytes of the per-object touched-vertex bitmap used by nif_train_step. */
+/* Training buffers.
+ * nif_set_object_train: latent gradient, Adam moments m and v (dev,
+ *   grid_elems floats each) and the touched-vertex bitmap (dev,
+ *   nif_touched_bytes) of object obj.  grad and touched must be all zero
+ *   before the first step; steps with Adam leave them zero again; m and v
+ *   start at zero.
+ * nif_set_mlp_train: Adam moments of MLP mlp (dev, mlp_params floats each,
+ *   zero at the start). */
+nif_status nif_set_object_train(nif_ctx* ctx, int32_t obj, float* grad, float* m, float* v, uint32_t* touched);
+nif_status nif_set_mlp_train(nif_ctx* ctx, int32_t mlp, float* m, float* v);
 size_t nif_touched_bytes(const nif_ctx* ctx);
+
+/* One training step of MLP `mlp` and of the grids of the objects that use it
+ * (Sec. 4.2 and Sec. 5 "Training": latents and weights are optimised jointly
+ * with Adam by back-propagation through the MLP and the interpolation).
+ *   rays, object_ids, t_max as nif_query; labels (dev, n bytes): 1 = visible
+ *   (no occluder in the segment), 0 = occluded.  Queries that miss their AABB,
+ *   are invalid, or whose object uses another MLP take no part.
+ *   Loss: binary cross-entropy on the logit, mean over the B queries that take
+ *   part; gradients dL/dz = (sigmoid(z) - label) / B, back-propagated through
+ *   the ReLU MLP (binary32 MFMA) and into the grids: every interpolation corner
+ *   of every lookup receives corner weight x feature gradient (binary32 atomics).
+ *   adam != NULL: bias-corrected Adam step number `step` (1-based) on every MLP
+ *   weight and on every latent whose gradient is non-zero this step (the others
+ *   keep latent and moments); latents are updated in binary32 and rounded to
+ *   nearest-even into grid_dtype; the MLP master stays binary32.  Packed query
+ *   weights become stale: call nif_prepare before the next nif_query.
+ *   adam == NULL: gradients only: mlp_grad receives dL/dW, each object's grid
+ *   gradient buffer receives dL/dlatent (the caller zeroes it before the next
+ *   step), weights and moments are not touched.
+ *   loss (dev, 1 float, nullable): batch loss.  mlp_grad (dev, mlp_params
+ *   floats, nullable): batch gradient of the MLP.
+ *   ws: nif_workspace_bytes(ctx, n, 1) bytes. */
+nif_status nif_train_step(nif_ctx* ctx, int32_t mlp, const float* rays, const int32_t* object_ids, const float* t_max,
+                          const uint8_t* labels, int64_t n, int32_t step, const nif_adam* adam, float* loss,
+                          float* mlp_grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Plain BVH any-hit ray casting: exact shadow-ray labels for training and the
+ * baseline the paper compares against (Sec. 6 "Performance Evaluation").
+ * nif_bvh_create: builds a binned-SAH BVH on the host from num_tris
+ *   triangles (host, num_tris x 9 floats: three vertices) and copies it to the
+ *   current device (the handle owns that memory).
+ * nif_bvh_anyhit: visible[i] (dev, n bytes) = 1 iff no triangle is hit at a
+ *   distance t with 0 < t < t_max[i] along rays[i] (dev, n x 6 floats);
+ *   binary32 watertight triangle test (Woop, Benthin, Wald, JCGT 2013),
+ *   double-sided. */
+typedef struct nif_bvh nif_bvh;
+nif_status nif_bvh_create(const float* tris, int64_t num_tris, nif_bvh** out);
+void nif_bvh_destroy(nif_bvh* bvh);
+int64_t nif_bvh_num_nodes(const nif_bvh* bvh);
+nif_status nif_bvh_anyhit(const nif_bvh* bvh, const float* rays, const float* t_max, int64_t n, uint8_t* visible,
+                          void* stream);
 
 /* Thread-local text of the last error (empty after success). */
 const char* nif_last_error(void);

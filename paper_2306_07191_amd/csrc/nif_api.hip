@@ -38,6 +38,10 @@ struct ObjHost {
     void* grid = nullptr;
     int32_t mlp = -1;
     bool set = false;
+    float* grad = nullptr;  // training buffers
+    float* m = nullptr;
+    float* v = nullptr;
+    uint32_t* touched = nullptr;
 };
 
 struct nif_ctx {
@@ -58,6 +62,12 @@ struct nif_ctx {
     int num_cus = 256;
     int device = 0;
     int32_t order_mode = 2;  // NIF_ORDER_AUTO
+    std::vector<float*> mlp_m, mlp_v;  // Adam moments per MLP
+    // device tables of per-object training pointers: grad, m, v, touched, grid
+    void** d_train_tab = nullptr;
+    bool train_tab_dirty = true;
+    uint8_t* d_train_fwd = nullptr;  // binary32 forward image of the MLP being trained
+    float* d_train_bwd = nullptr;    // backward image
 };
 
 static bool uses_order(const nif_ctx* c, int64_t n) {
@@ -87,6 +97,7 @@ extern "C" nif_status nif_create(const nif_model_desc* desc, int32_t num_objects
     if (!desc || !out) return fail(NIF_ERR_INVALID_ARG, "nif_create: NULL argument");
     const nif_model_desc& d = *desc;
     if (num_objects < 1 || num_mlps < 1) return fail(NIF_ERR_INVALID_ARG, "nif_create: need >= 1 object and MLP");
+    if (num_objects > 4096) return fail(NIF_ERR_UNSUPPORTED, "nif_create: at most 4096 objects");
     if (d.feats != kFeats) return fail(NIF_ERR_UNSUPPORTED, "feats must be %d", kFeats);
     if (d.width != kWidth) return fail(NIF_ERR_UNSUPPORTED, "width must be %d", kWidth);
     if (d.levels != 4 && d.levels != 8) return fail(NIF_ERR_UNSUPPORTED, "levels must be 4 or 8");
@@ -116,6 +127,8 @@ extern "C" nif_status nif_create(const nif_model_desc* desc, int32_t num_objects
     c->objs.resize(num_objects);
     c->masters.assign(num_mlps, nullptr);
     c->fp8.resize(num_mlps);
+    c->mlp_m.assign(num_mlps, nullptr);
+    c->mlp_v.assign(num_mlps, nullptr);
     if (hipGetDevice(&c->device) == hipSuccess) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
@@ -132,6 +145,9 @@ extern "C" void nif_destroy(nif_ctx* c) {
     for (auto& p : c->d_packed)
         if (p) (void)hipFree(p);
     if (c->d_scales) (void)hipFree(c->d_scales);
+    if (c->d_train_tab) (void)hipFree(c->d_train_tab);
+    if (c->d_train_fwd) (void)hipFree(c->d_train_fwd);
+    if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
     delete c;
 }
 
@@ -195,90 +211,6 @@ extern "C" nif_status nif_init_grid(nif_ctx* c, int32_t obj, uint64_t seed, floa
     return ok();
 }
 
-// ---------------------------------------------------------------------------
-// weight packing (see PackInfo)
-// ---------------------------------------------------------------------------
-static uint16_t bf16_rne(float f) {
-    uint32_t b;
-    memcpy(&b, &f, 4);
-    if ((b & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
-static uint16_t f16_rne(float f) {
-    _Float16 h = (_Float16)f;
-    uint16_t b;
-    memcpy(&b, &h, 2);
-    return b;
-}
-// OCP E4M3: bias 7, largest finite 448, no infinity; round to nearest even, saturate
-static uint8_t e4m3_rne_sat(float f) {
-    uint8_t s = signbit(f) ? 0x80 : 0;
-    double a = fabs((double)f);
-    if (a != a) return 0x7f;
-    if (a >= 448.0) return s | 0x7e;
-    if (a < ldexp(1.0, -6)) {
-        double m = nearbyint(a / ldexp(1.0, -9));  // subnormal step 2^-9; m == 8 encodes 2^-6
-        return s | (uint8_t)m;
-    }
-    int e;
-    frexp(a, &e);
-    e -= 1;  // 2^e <= a < 2^(e+1)
-    double m = nearbyint(a / ldexp(1.0, e - 3));  // 8..16
-    if (m >= 16.0) {
-        m = 8.0;
-        e += 1;
-    }
-    if (e > 8 || (e == 8 && m > 14.0)) return s | 0x7e;
-    return s | (uint8_t)(((e + 7) << 3) | ((int)m - 8));
-}
-
-static int hidden_feature(int half, int c) { return 32 * (c / 16) + 8 * ((c % 16) / 4) + 4 * half + (c % 4); }
-
-static void pack_mlp(const nif_ctx* c, int flav, const float* W, const float* scales, uint8_t* out) {
-    const PackInfo& P = c->pack[flav];
-    const int H = c->d.hidden_layers, Wd = c->d.width, din = c->din;
-    const int eb = flav == kF32 ? 4 : flav == kFP8 ? 1 : 2;
-    const int epp = 16 / eb;
-    memset(out, 0, P.bytes);
-    for (int j = 0; j < H; ++j) {
-        const int kin = j == 0 ? din : Wd;
-        const int kh = kin / 2;
-        const float* Wj = W + (j == 0 ? 0 : (int64_t)Wd * din + (int64_t)(j - 1) * Wd * Wd);
-        const int64_t layer_bytes = P.layer_off[j + 1] - P.layer_off[j];
-        const int PK = (int)(layer_bytes / (2 * 64 * 16));
-        for (int mt = 0; mt < 2; ++mt)
-            for (int p = 0; p < PK; ++p)
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int half = lane / 32, row = 32 * mt + lane % 32;
-                    uint8_t* dst = out + P.layer_off[j] + ((int64_t)(mt * PK + p) * 64 + lane) * 16;
-                    for (int t = 0; t < epp; ++t) {
-                        const int cc = p * epp + t;
-                        float w = 0.0f;
-                        if (cc < kh) {
-                            const int col = j == 0 ? half * kh + cc : hidden_feature(half, cc);
-                            w = Wj[(int64_t)row * kin + col];
-                        }
-                        if (flav == kF32) {
-                            memcpy(dst + 4 * t, &w, 4);
-                        } else if (flav == kBF16) {
-                            uint16_t b = bf16_rne(w);
-                            memcpy(dst + 2 * t, &b, 2);
-                        } else if (flav == kF16) {
-                            uint16_t b = f16_rne(w);
-                            memcpy(dst + 2 * t, &b, 2);
-                        } else {
-                            dst[t] = e4m3_rne_sat(w / scales[j]);
-                        }
-                    }
-                }
-    }
-    const float* wout = W + (int64_t)Wd * din + (int64_t)(H - 1) * Wd * Wd;
-    float* wo = reinterpret_cast<float*>(out + P.layer_off[H]);
-    for (int half = 0; half < 2; ++half)
-        for (int cc = 0; cc < 32; ++cc) wo[half * 32 + cc] = wout[hidden_feature(half, cc)];
-}
-
 extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_prepare: NULL context");
     if (dtype < 0 || dtype > 3) return fail(NIF_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
@@ -304,17 +236,10 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     }
     if (!c->d_objs) HIP_TRY(hipMalloc(&c->d_objs, sizeof(ObjDev) * c->K));
     HIP_TRY(hipMemcpy(c->d_objs, od.data(), sizeof(ObjDev) * c->K, hipMemcpyHostToDevice));
-    // weights
+    // weights, packed on the device from the binary32 masters
     const int flav = dtype;
     const PackInfo& P = c->pack[flav];
     if (!c->d_packed[flav]) HIP_TRY(hipMalloc(&c->d_packed[flav], (size_t)P.bytes * c->M));
-    std::vector<float> W(c->P);
-    std::vector<uint8_t> img(P.bytes);
-    for (int m = 0; m < c->M; ++m) {
-        HIP_TRY(hipMemcpy(W.data(), c->masters[m], sizeof(float) * c->P, hipMemcpyDeviceToHost));
-        pack_mlp(c, flav, W.data(), flav == kFP8 ? c->fp8[m].data() : nullptr, img.data());
-        HIP_TRY(hipMemcpy(c->d_packed[flav] + (int64_t)m * P.bytes, img.data(), P.bytes, hipMemcpyHostToDevice));
-    }
     if (flav == kFP8) {
         const int H = c->d.hidden_layers;
         std::vector<float> sc((size_t)2 * H * c->M);
@@ -322,13 +247,19 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         if (!c->d_scales) HIP_TRY(hipMalloc(&c->d_scales, sizeof(float) * sc.size()));
         HIP_TRY(hipMemcpy(c->d_scales, sc.data(), sizeof(float) * sc.size(), hipMemcpyHostToDevice));
     }
+    for (int m = 0; m < c->M; ++m)
+        HIP_TRY(launch_pack_forward(c->masters[m], c->d_packed[flav] + (int64_t)m * P.bytes, P, flav, c->din,
+                                    c->d.width, flav == kFP8 ? c->d_scales + (int64_t)2 * c->d.hidden_layers * m : nullptr,
+                                    s));
     c->prepared[flav] = true;
     return ok();
 }
 
+static size_t train_bytes(const nif_ctx* c, int64_t n);
+
 extern "C" size_t nif_workspace_bytes(const nif_ctx* c, int64_t n, int32_t mode) {
     if (!c || n <= 0) return 0;
-    (void)mode;
+    if (mode == 1) return train_bytes(c, n);
     return uses_order(c, n) ? order_workspace_bytes(n, c->K) : 0;
 }
 
@@ -490,13 +421,124 @@ extern "C" size_t nif_touched_bytes(const nif_ctx* c) {
     return (size_t)((vertices + 31) / 32) * 4;
 }
 
-extern "C" nif_status nif_train_step(nif_ctx* c, const float* rays, const int32_t* object_ids, const float* t_max,
-                                     const uint8_t* labels, int64_t n, int32_t step, const nif_adam* adam,
-                                     float* const* grid_grad, float* const* grid_m, float* const* grid_v,
-                                     uint32_t* const* touched, float* mlp_m, float* mlp_v, float* loss,
-                                     float* mlp_grad_out, void* ws, size_t ws_bytes, void* stream) {
-    (void)c; (void)rays; (void)object_ids; (void)t_max; (void)labels; (void)n; (void)step; (void)adam;
-    (void)grid_grad; (void)grid_m; (void)grid_v; (void)touched; (void)mlp_m; (void)mlp_v; (void)loss;
-    (void)mlp_grad_out; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(NIF_ERR_UNSUPPORTED, "nif_train_step: not built yet");
+extern "C" nif_status nif_set_object_train(nif_ctx* c, int32_t obj, float* grad, float* m, float* v,
+                                           uint32_t* touched) {
+    if (!c || !grad || !m || !v || !touched) return fail(NIF_ERR_INVALID_ARG, "nif_set_object_train: NULL argument");
+    if (obj < 0 || obj >= c->K) return fail(NIF_ERR_INVALID_ARG, "object %d out of range", obj);
+    ObjHost& o = c->objs[obj];
+    o.grad = grad;
+    o.m = m;
+    o.v = v;
+    o.touched = touched;
+    c->train_tab_dirty = true;
+    return ok();
+}
+
+extern "C" nif_status nif_set_mlp_train(nif_ctx* c, int32_t mlp, float* m, float* v) {
+    if (!c || !m || !v) return fail(NIF_ERR_INVALID_ARG, "nif_set_mlp_train: NULL argument");
+    if (mlp < 0 || mlp >= c->M) return fail(NIF_ERR_INVALID_ARG, "mlp %d out of range", mlp);
+    c->mlp_m[mlp] = m;
+    c->mlp_v[mlp] = v;
+    return ok();
+}
+
+static size_t train_bytes(const nif_ctx* c, int64_t n) {
+    return train_workspace_bytes(n, c->din, c->d.hidden_layers, c->P, nullptr) +
+           (uses_order(c, n) ? order_workspace_bytes(n, c->K) : 0);
+}
+
+extern "C" nif_status nif_train_step(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,
+                                     const float* tmax, const uint8_t* labels, int64_t n, int32_t step,
+                                     const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
+                                     void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, labels, "nif_train_step");
+    if (st != NIF_OK) return st;
+    if (mlp < 0 || mlp >= c->M) return fail(NIF_ERR_INVALID_ARG, "mlp %d out of range", mlp);
+    if (adam && step < 1) return fail(NIF_ERR_INVALID_ARG, "step must be >= 1");
+    if (adam && !(adam->lr > 0.0f && adam->beta1 >= 0.0f && adam->beta1 < 1.0f && adam->beta2 >= 0.0f &&
+                  adam->beta2 < 1.0f && adam->eps >= 0.0f))
+        return fail(NIF_ERR_INVALID_ARG, "invalid Adam hyper-parameters");
+    if (n == 0) return ok();
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    if (!c->masters[mlp]) return fail(NIF_ERR_STATE, "MLP %d not registered", mlp);
+    if (adam && (!c->mlp_m[mlp] || !c->mlp_v[mlp])) return fail(NIF_ERR_STATE, "MLP %d has no Adam moments", mlp);
+    std::vector<int32_t> objs;
+    for (int k = 0; k < c->K; ++k)
+        if (c->objs[k].mlp == mlp) {
+            const ObjHost& o = c->objs[k];
+            if (!o.grad || !o.touched || (adam && (!o.m || !o.v)))
+                return fail(NIF_ERR_STATE, "object %d has no training buffers", k);
+            objs.push_back(k);
+        }
+    const size_t need = train_bytes(c, n);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    const int K = c->K;
+    if (!c->d_train_tab) HIP_TRY(hipMalloc(&c->d_train_tab, sizeof(void*) * 5 * K));
+    if (c->train_tab_dirty) {
+        std::vector<void*> tab((size_t)5 * K, nullptr);
+        for (int k = 0; k < K; ++k) {
+            tab[0 * K + k] = c->objs[k].grad;
+            tab[1 * K + k] = c->objs[k].m;
+            tab[2 * K + k] = c->objs[k].v;
+            tab[3 * K + k] = c->objs[k].touched;
+            tab[4 * K + k] = c->objs[k].grid;
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpy(c->d_train_tab, tab.data(), sizeof(void*) * tab.size(), hipMemcpyHostToDevice));
+        c->train_tab_dirty = false;
+    }
+    const PackInfo& P32 = c->pack[kF32];
+    if (!c->d_train_fwd) HIP_TRY(hipMalloc(&c->d_train_fwd, P32.bytes));
+    if (!c->d_train_bwd) HIP_TRY(hipMalloc(&c->d_train_bwd, backward_image_bytes(c->d.hidden_layers)));
+    HIP_TRY(launch_pack_forward(c->masters[mlp], c->d_train_fwd, P32, kF32, c->din, c->d.width, nullptr, s));
+    HIP_TRY(launch_pack_backward(c->masters[mlp], c->d_train_bwd, c->d.hidden_layers, c->din, c->d.width, s));
+    TrainArgs A{};
+    uint8_t* wsp = reinterpret_cast<uint8_t*>(ws);
+    const size_t tb = train_workspace_bytes(n, c->din, c->d.hidden_layers, c->P, nullptr);
+    if (uses_order(c, n)) {
+        st = run_order(c, rays, ids, tmax, n, nullptr, wsp + tb, &A.perm, s);
+        if (st != NIF_OK) return st;
+    }
+    A.rays = rays;
+    A.ids = ids;
+    A.tmax = tmax;
+    A.labels = labels;
+    A.n = n;
+    A.objs = c->d_objs;
+    A.num_objects = K;
+    A.mlp = mlp;
+    A.hidden = c->d.hidden_layers;
+    A.din = c->din;
+    A.P = c->P;
+    for (int k = 0; k < 3 * c->d.levels; ++k) A.toff[k] = c->toff[k];
+    for (int l = 0; l < c->d.levels; ++l) A.res[l] = c->res[l];
+    A.fwd = reinterpret_cast<const float*>(c->d_train_fwd);
+    A.pack = P32;
+    A.bwd = c->d_train_bwd;
+    A.grid_grad = reinterpret_cast<float* const*>(c->d_train_tab + 0 * K);
+    A.grid_m = reinterpret_cast<float* const*>(c->d_train_tab + 1 * K);
+    A.grid_v = reinterpret_cast<float* const*>(c->d_train_tab + 2 * K);
+    A.touched = reinterpret_cast<uint32_t* const*>(c->d_train_tab + 3 * K);
+    A.grids = c->d_train_tab + 4 * K;
+    A.master = c->masters[mlp];
+    A.mlp_m = c->mlp_m[mlp];
+    A.mlp_v = c->mlp_v[mlp];
+    A.loss_out = loss;
+    A.grad_out = mlp_grad;
+    A.apply_adam = adam ? 1 : 0;
+    if (adam) {
+        A.adam.lr = adam->lr;
+        A.adam.beta1 = adam->beta1;
+        A.adam.beta2 = adam->beta2;
+        A.adam.eps = adam->eps;
+        A.adam.bc1 = (float)(1.0 - pow((double)adam->beta1, step));
+        A.adam.bc2 = (float)(1.0 - pow((double)adam->beta2, step));
+    }
+    const int64_t vertices = c->grid_elems / c->d.feats;
+    std::vector<int64_t> words(K, (vertices + 31) / 32);
+    HIP_TRY(launch_train(A, wsp, objs.data(), (int32_t)objs.size(), words.data(), c->d.grid_dtype, c->d.levels,
+                         c->num_cus, s));
+    if (adam) invalidate(c);  // the masters changed: packed copies are stale
+    return ok();
 }

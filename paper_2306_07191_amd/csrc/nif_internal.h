@@ -77,16 +77,79 @@ struct OrderArgs {
     int32_t num_objects;
     int32_t bits;          // Morton bits per axis
     uint32_t num_buckets;  // (num_objects << 3 bits) + 1; the last holds misses and invalid queries
-    uint32_t* hist;
+    int64_t tile;          // queries per block
+    int64_t num_tiles;
+    uint32_t* table;       // num_buckets x num_tiles counts, then offsets
     uint32_t* block_sums;
-    uint32_t* bucket;
-    uint32_t* rank;
+    uint16_t* key;         // bucket of every query
     uint32_t* perm;
 };
 
 int order_bits(int32_t num_objects);
 size_t order_workspace_bytes(int64_t n, int32_t num_objects);
 hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out);
+
+struct AdamDev {
+    float lr, beta1, beta2, eps;
+    float bc1, bc2;  // 1 - beta^step
+};
+
+struct TrainArgs {
+    const float* rays;
+    const int32_t* ids;
+    const float* tmax;
+    const uint8_t* labels;
+    int64_t n;
+    const uint32_t* perm;
+    const ObjDev* objs;
+    int32_t num_objects;
+    int32_t mlp;
+    int32_t hidden;
+    int32_t din;
+    int64_t P;
+    int64_t toff[3 * kMaxLevels];
+    int32_t res[kMaxLevels];
+    const float* fwd;  // binary32 forward image of the trained MLP
+    PackInfo pack;
+    const float* bwd;  // backward (transposed) image
+    float* const* grid_grad;
+    float* const* grid_m;
+    float* const* grid_v;
+    uint32_t* const* touched;
+    void* const* grids;
+    float* master;
+    float* mlp_m;
+    float* mlp_v;
+    float* act;
+    int64_t act_off[kMaxHidden + 1];
+    float* delta;
+    int64_t delta_off[kMaxHidden];
+    float* dz;
+    float* dw_part;
+    float* dw;
+    int64_t dw_chunk;
+    int64_t w_off[kMaxHidden + 1];
+    unsigned* count;
+    float* loss_sum;
+    float* loss_out;
+    float* grad_out;
+    int32_t apply_adam;  // 0: gradients only (scaled by 1/B, left in grid_grad)
+    AdamDev adam;
+};
+
+size_t train_workspace_bytes(int64_t n, int din, int hidden, int64_t P, int64_t* chunk_out);
+hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_t num_obj_of_mlp,
+                        const int64_t* words_per_obj, int grid_dtype, int levels, int num_cus, hipStream_t s);
+
+size_t backward_image_bytes(int hidden);
+hipError_t launch_pack_forward(const float* W, uint8_t* out, const PackInfo& P, int flav, int din, int width,
+                               const float* scales_w, hipStream_t s);
+hipError_t launch_pack_backward(const float* W, float* out, int hidden, int din, int width, hipStream_t s);
+// Output feature of an MLP layer held in accumulator register (c % 16) of
+// M-tile c / 16 by lane half h of a 32x32 MFMA: row 8 (r / 4) + 4 h + r % 4.
+__host__ __device__ __forceinline__ int acc_feature(int half, int c) {
+    return 32 * (c / 16) + 8 * ((c % 16) / 4) + 4 * half + (c % 4);
+}
 
 PackInfo pack_info(int flavor, int din, int hidden);
 size_t lds_bytes(const PackInfo& p);

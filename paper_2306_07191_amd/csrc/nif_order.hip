@@ -7,11 +7,13 @@
 // cells, so their trilinear gathers share cache lines.  Queries that miss their
 // AABB or are invalid go to a last bucket.
 //
-// Passes: (1) key + rank: each query computes its bucket and takes a rank in it
-// with one atomic increment; (2) exclusive scan of the bucket counts (reduce,
-// top-level scan, down-sweep); (3) scatter: perm[offset[bucket] + rank] = query.
-// The order inside a bucket depends on atomic arrival; the outputs do not,
-// because every query is computed independently of its neighbours.
+// Passes (no global atomics): (1) each block counts the buckets of its tile of
+// queries in LDS and writes the non-zero counts into a (bucket x tile) table;
+// (2) exclusive scan of that table in bucket-major order; (3) each block ranks
+// its queries inside (bucket, tile) with LDS counters and scatters
+// perm[offset + rank] = query.  The order inside a (bucket, tile) cell depends
+// on LDS atomic arrival; the outputs do not, because every query is computed
+// independently of its neighbours.
 #include "nif_device.h"
 #include "nif_internal.h"
 
@@ -35,29 +37,56 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
-__global__ void order_keys_kernel(OrderArgs A) {
+__device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i) {
     const uint32_t cells = 1u << A.bits;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float* r = A.rays + i * 6;
-        float o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
-        const float tm = A.tmax[i];
-        const int32_t id = A.ids[i];
-        uint32_t b = A.num_buckets - 1;
-        if (valid_query(o, d, tm, id, A.num_objects)) {
-            float u[3][3];
-            const ObjDev ob = A.objs[id];
-            if (clip_normalise(o, d, tm, ob, u)) {
-                uint32_t c[3];
+    const float* r = A.rays + i * 6;
+    float o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
+    const float tm = A.tmax[i];
+    const int32_t id = A.ids[i];
+    uint32_t b = A.num_buckets - 1;
+    if (valid_query(o, d, tm, id, A.num_objects)) {
+        float u[3][3];
+        const ObjDev ob = A.objs[id];
+        if (clip_normalise(o, d, tm, ob, u)) {
+            uint32_t c[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    uint32_t v = (uint32_t)(u[0][a] * (float)cells);  // u in [0, 1]
-                    c[a] = v < cells ? v : cells - 1;
-                }
-                b = ((uint32_t)id << (3 * A.bits)) | spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+            for (int a = 0; a < 3; ++a) {
+                uint32_t v = (uint32_t)(u[0][a] * (float)cells);  // u in [0, 1]
+                c[a] = v < cells ? v : cells - 1;
             }
+            b = ((uint32_t)id << (3 * A.bits)) | spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
         }
-        A.bucket[i] = b;
-        A.rank[i] = atomicAdd(&A.hist[b], 1u);
+    }
+    return b;
+}
+
+// Pass 1: bucket of every query of the block's tile, counted in LDS; the
+// non-zero counts go to table[bucket * num_tiles + tile] (the table is zeroed).
+__global__ __launch_bounds__(256) void order_count_kernel(OrderArgs A) {
+    extern __shared__ uint32_t cnt[];
+    for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
+    for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        const uint32_t b = order_key(A, i);
+        A.key[i] = (uint16_t)b;
+        atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x)
+        if (cnt[k]) A.table[(int64_t)k * A.num_tiles + blockIdx.x] = cnt[k];
+}
+
+// Pass 3: rank inside (bucket, tile) with an LDS counter; scatter.
+__global__ __launch_bounds__(256) void order_rank_kernel(OrderArgs A) {
+    extern __shared__ uint32_t cur[];
+    for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cur[k] = 0;
+    __syncthreads();
+    const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
+    for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        const uint32_t b = A.key[i];
+        const uint32_t r = atomicAdd(&cur[b], 1u);
+        A.perm[A.table[(int64_t)b * A.num_tiles + blockIdx.x] + r] = (uint32_t)i;
     }
 }
 
@@ -141,52 +170,66 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* hist,
     }
 }
 
-__global__ void order_scatter_kernel(OrderArgs A) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * blockDim.x)
-        A.perm[A.hist[A.bucket[i]] + A.rank[i]] = (uint32_t)i;
-}
-
+// Buckets: (object, Morton code with `bits` per axis), at most 4096 plus one
+// for misses and invalid queries, so that a block's counters fit in LDS.
 int order_bits(int32_t num_objects) {
-    // at most 2^22 buckets in all, at most 2^18 per object
-    int bits = 6;
-    while (bits > 0 && ((int64_t)num_objects << (3 * bits)) > ((int64_t)1 << 22)) --bits;
+    int bits = 4;
+    while (bits > 0 && ((int64_t)num_objects << (3 * bits)) > 4096) --bits;
     return bits;
 }
 
-size_t order_workspace_bytes(int64_t n, int32_t num_objects) {
-    const int bits = order_bits(num_objects);
-    const int64_t nb = ((int64_t)num_objects << (3 * bits)) + 1;
+static constexpr int64_t kOrderTile = 8192;  // queries per block
+
+struct OrderLayout {
+    int64_t nb, tiles, table, scan_tiles;
+    size_t off_table, off_sums, off_key, off_perm, total;
+};
+
+static OrderLayout order_layout(int64_t n, int32_t num_objects) {
+    OrderLayout L{};
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const int64_t tiles = (nb + kScanTile - 1) / kScanTile;
-    return al(nb * 4) + al(tiles * 4) + 3 * al(n * 4);
+    const int bits = order_bits(num_objects);
+    L.nb = ((int64_t)num_objects << (3 * bits)) + 1;
+    L.tiles = (n + kOrderTile - 1) / kOrderTile;
+    L.table = L.nb * L.tiles;
+    L.scan_tiles = (L.table + kScanTile - 1) / kScanTile;
+    L.off_table = 0;
+    L.off_sums = al(L.table * 4);
+    L.off_key = L.off_sums + al(L.scan_tiles * 4);
+    L.off_perm = L.off_key + al(n * 2);
+    L.total = L.off_perm + al(n * 4);
+    return L;
+}
+
+size_t order_workspace_bytes(int64_t n, int32_t num_objects) {
+    if (num_objects > 4096) return 0;  // rejected by launch_order
+    return order_layout(n, num_objects).total;
 }
 
 hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out) {
+    if (A.num_objects > 4096) return hipErrorInvalidValue;
+    const OrderLayout L = order_layout(A.n, A.num_objects);
+    if (L.scan_tiles > kScanTile) return hipErrorInvalidValue;  // > 16M table entries
     A.bits = order_bits(A.num_objects);
-    const int64_t nb = ((int64_t)A.num_objects << (3 * A.bits)) + 1;
-    A.num_buckets = (uint32_t)nb;
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const int64_t tiles = (nb + kScanTile - 1) / kScanTile;
+    A.num_buckets = (uint32_t)L.nb;
+    A.tile = kOrderTile;
+    A.num_tiles = L.tiles;
     uint8_t* p = reinterpret_cast<uint8_t*>(ws);
-    A.hist = reinterpret_cast<uint32_t*>(p);
-    p += al(nb * 4);
-    A.block_sums = reinterpret_cast<uint32_t*>(p);
-    p += al(tiles * 4);
-    A.bucket = reinterpret_cast<uint32_t*>(p);
-    p += al(A.n * 4);
-    A.rank = reinterpret_cast<uint32_t*>(p);
-    p += al(A.n * 4);
-    if (!A.perm) A.perm = reinterpret_cast<uint32_t*>(p);  // else the caller's buffer
+    A.table = reinterpret_cast<uint32_t*>(p + L.off_table);
+    A.block_sums = reinterpret_cast<uint32_t*>(p + L.off_sums);
+    A.key = reinterpret_cast<uint16_t*>(p + L.off_key);
+    if (!A.perm) A.perm = reinterpret_cast<uint32_t*>(p + L.off_perm);  // else the caller's buffer
     *perm_out = A.perm;
-    if (tiles > kScanTile) return hipErrorInvalidValue;
-    const unsigned fb = (unsigned)((nb + 255) / 256 < 4096 ? (nb + 255) / 256 : 4096);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(fb), dim3(256), 0, s, A.hist, nb, 0u);
-    const unsigned qb = (unsigned)((A.n + 255) / 256 < 8192 ? (A.n + 255) / 256 : 8192);
-    hipLaunchKernelGGL(order_keys_kernel, dim3(qb), dim3(256), 0, s, A);
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, A.hist, nb, A.block_sums);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, A.block_sums, tiles);
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, A.hist, nb, A.block_sums);
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(qb), dim3(256), 0, s, A);
+    const size_t lds = (size_t)L.nb * 4;
+    const unsigned fb = (unsigned)((L.table + 255) / 256 < 4096 ? (L.table + 255) / 256 : 4096);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fb), dim3(256), 0, s, A.table, L.table, 0u);
+    hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)L.scan_tiles), dim3(kScanThreads), 0, s, A.table, L.table,
+                       A.block_sums);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, A.block_sums, L.scan_tiles);
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)L.scan_tiles), dim3(kScanThreads), 0, s, A.table, L.table,
+                       A.block_sums);
+    hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
     return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
            "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
-           "nif_train_step", "nif_touched_bytes",
+           "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_touched_bytes",
+           "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit",
            "nif_last_error", "nif_version"]
 
 
@@ -72,8 +73,14 @@ def lib():
             "nif_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
             "nif_encode": (i32, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "nif_mlp": (i32, [vp, i32, i32, vp, i64, vp, vp]),
-            "nif_train_step": (i32, [vp, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "nif_set_object_train": (i32, [vp, i32, vp, vp, vp, vp]),
+            "nif_set_mlp_train": (i32, [vp, i32, vp, vp]),
+            "nif_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
             "nif_touched_bytes": (sz, [vp]),
+            "nif_bvh_create": (i32, [vp, i64, vp]),
+            "nif_bvh_destroy": (None, [vp]),
+            "nif_bvh_num_nodes": (i64, [vp]),
+            "nif_bvh_anyhit": (i32, [vp, vp, vp, i64, vp, vp]),
             "nif_last_error": (C.c_char_p, []),
             "nif_version": (C.c_char_p, []),
         }
@@ -99,6 +106,36 @@ def _ptr(t) -> int | None:
 def _stream():
     import torch
     return torch.cuda.current_stream().cuda_stream
+
+
+class BVH:
+    """GPU BVH for any-hit shadow-ray casting (built on the host, traversed on the device)."""
+
+    def __init__(self, tris):
+        t = np.ascontiguousarray(tris, np.float32).reshape(-1, 9)
+        h = C.c_void_p()
+        _check(lib().nif_bvh_create(t.ctypes.data, t.shape[0], C.byref(h)), "nif_bvh_create")
+        self.h = h
+        self.num_nodes = int(lib().nif_bvh_num_nodes(self.h))
+
+    def anyhit(self, rays, tmax, out=None):
+        import torch
+        n = tmax.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=rays.device)
+        _check(lib().nif_bvh_anyhit(self.h, _ptr(rays), _ptr(tmax), n, _ptr(out), _stream()), "nif_bvh_anyhit")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nif_bvh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -224,3 +261,36 @@ class Context:
         z = t.empty(n, dtype=t.float32, device=self.device)
         _check(lib().nif_mlp(self.h, DTYPES[dtype], mlp, _ptr(features), n, _ptr(z), _stream()), "nif_mlp")
         return z
+
+    # ---- training --------------------------------------------------------
+    def setup_training(self):
+        """Allocate and register zeroed training buffers for every object and MLP."""
+        t = self.torch
+        tb = int(lib().nif_touched_bytes(self.h))
+        self.train_bufs = []
+        for k in range(self.K):
+            g = t.zeros(self.grid_elems, dtype=t.float32, device=self.device)
+            m = t.zeros_like(g)
+            v = t.zeros_like(g)
+            tch = t.zeros((tb + 3) // 4, dtype=t.int32, device=self.device)
+            self.train_bufs.append((g, m, v, tch))
+            _check(lib().nif_set_object_train(self.h, k, _ptr(g), _ptr(m), _ptr(v), _ptr(tch)),
+                   "nif_set_object_train")
+        self.mlp_moments = []
+        for mi in range(self.M):
+            m = t.zeros(self.mlp_params, dtype=t.float32, device=self.device)
+            v = t.zeros_like(m)
+            self.mlp_moments.append((m, v))
+            _check(lib().nif_set_mlp_train(self.h, mi, _ptr(m), _ptr(v)), "nif_set_mlp_train")
+
+    def train_step(self, rays, ids, tmax, labels, step: int, mlp: int = 0, adam=(1e-2, 0.9, 0.99, 1e-15),
+                   loss=None, mlp_grad=None, ws=None):
+        """One training step; adam=None computes gradients only."""
+        t = self.torch
+        n = ids.shape[0]
+        if ws is None:
+            ws = t.empty(max(1, self.workspace_bytes(n, 1)), dtype=t.uint8, device=self.device)
+        a = None if adam is None else Adam(*adam)
+        _check(lib().nif_train_step(self.h, mlp, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(labels), n, step,
+                                    None if a is None else C.byref(a), _ptr(loss), _ptr(mlp_grad), _ptr(ws),
+                                    ws.numel(), _stream()), "nif_train_step")

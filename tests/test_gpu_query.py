@@ -231,3 +231,29 @@ def test_order_is_a_grouped_permutation():
     nh = hit.sum()
     assert hit[:nh].all() and not hit[nh:].any()       # misses and invalid queries last
     assert (np.diff(ids[perm[:nh]]) >= 0).all()          # grouped by object
+
+
+def test_gpu_bvh_labels_match_oracle():
+    """GPU BVH any-hit (binary32 watertight test) vs the oracle's exact binary64 labels."""
+    import torch
+    from oracle import oracle as O
+    from paper_2306_07191_amd import nif
+    w = S.tiny_workload()
+    w["tmax"] = np.where(np.arange(w["tmax"].size) % 3 == 0, 3.0, w["tmax"]).astype(np.float32)
+    ref = O.anyhit_brute(w["tris"], w["rays"], w["tmax"])
+    bvh = nif.BVH(w["tris"])
+    got = bvh.anyhit(torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()).cpu().numpy()
+    agree = (got == ref).mean()
+    print("tiny labels agreement", agree, "visible", ref.mean())
+    assert agree >= 0.9999
+    # frame mesh, a sample of frame rays against the oracle BVH
+    tris = S.frame_mesh()
+    rays, tmax = S.rays_ground_to_light(20000, S.rng(2, 1))
+    ref = O.BVH(tris).anyhit(rays, tmax)
+    bvh2 = nif.BVH(tris)
+    got = bvh2.anyhit(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy()
+    agree = (got == ref).mean()
+    print("frame labels agreement", agree, "visible", ref.mean(), "nodes", bvh2.num_nodes)
+    assert agree >= 0.9999
+    empty = nif.BVH(np.zeros((0, 9), np.float32))
+    assert (empty.anyhit(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy() == 1).all()
