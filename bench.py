@@ -51,6 +51,21 @@ def time_launches(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter run,
+    or None when the kernel source has changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "query_frame_bf16_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = b"".join(open(os.path.join(ROOT, "paper_2306_07191_amd", "csrc", f), "rb").read()
+                   for f in ("nif_forward.hip", "nif_device.h"))
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(w, gpu_y, budget_s: float = 12.0):
     """The binary64 oracle on the host cores over a bounded sample of the same
     queries; also the error of the GPU outputs on that sample."""
@@ -82,6 +97,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--quick", action="store_true",
                     help="time the headline step only (no per-dtype sweep, no CPU baseline): for profilers")
     args = ap.parse_args()
@@ -93,6 +110,14 @@ def main():
     from paper_2306_07191_amd import nif, synth as S
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 1 GiB three times")
+        return
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     w = S.frame_workload(with_mesh=False)
@@ -154,7 +179,7 @@ def main():
     value = n / sec
     achieved_tflops = flops * n / kern / 1e12
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_TFLOPS[HEADLINE_DTYPE],
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic(),
                 "kernel": "nif_query_kernel<bf16, L=8, f16 grid> (fused clip+encode+MLP)",
                 "algorithmic_flop_per_launch": flops * n, "kernel_us": kern * 1e6,
                 "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6}
