@@ -764,6 +764,7 @@ typedef struct {
     const float *rays, *tmax;
     const int32_t* ids;
     const uint8_t* labels;
+    const double* grad_y; /* upstream dL/dy per query, or NULL for the BCE loss */
     double inv_b;
     int32_t num_mlps;
     double* gmlp_part; /* [nthreads][num_mlps][P] */
@@ -772,8 +773,11 @@ typedef struct {
     int64_t chunk;
 } bwd_job;
 
-static void bwd_one(const orc_model* m, const double* W, const double* x, double t, double inv_b, double* gW,
-                    double* gx, double* loss) {
+/* One query's gradients.  gy == NULL: binary cross-entropy against label t,
+ * scaled by inv_b.  Otherwise the upstream gradient *gy = dL/dy of the
+ * visibility y = sigmoid(z): dL/dz = gy sigmoid(z) (1 - sigmoid(z)). */
+static void bwd_one(const orc_model* m, const double* W, const double* x, double t, double inv_b, const double* gy,
+                    double* gW, double* gx, double* loss) {
     const int H = m->hidden, Wd = m->width, Din = orc_din(m);
     double h[16][ORC_MAXW > ORC_MAXDIN ? ORC_MAXW : ORC_MAXDIN];
     double a[16][ORC_MAXW];
@@ -796,9 +800,15 @@ static void bwd_one(const orc_model* m, const double* W, const double* x, double
     const double* wout = Wj;
     double z = 0.0;
     for (int i = 0; i < Wd; ++i) z += wout[i] * h[H][i];
-    double sp = (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z)));
-    *loss += (sp - t * z) * inv_b;
-    double dz = (1.0 / (1.0 + exp(-z)) - t) * inv_b;
+    double dz;
+    if (gy) {
+        const double y = 1.0 / (1.0 + exp(-z));
+        dz = *gy * y * (1.0 - y);
+    } else {
+        double sp = (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z)));
+        *loss += (sp - t * z) * inv_b;
+        dz = (1.0 / (1.0 + exp(-z)) - t) * inv_b;
+    }
     /* output layer */
     int64_t offw[16];
     {
@@ -851,16 +861,16 @@ static void bwd_range(void* p, int64_t b, int64_t e) {
         int32_t obj = J->ids[i];
         encode(m, obj, u, off, res, x, NULL, NULL);
         int32_t mi = m->mlp_index[obj];
-        bwd_one(m, m->mlps[mi], x, J->labels[i] ? 1.0 : 0.0, J->inv_b, gpart + (int64_t)mi * P, gx, &loss);
+        bwd_one(m, m->mlps[mi], x, J->labels ? (J->labels[i] ? 1.0 : 0.0) : 0.0, J->inv_b,
+                J->grad_y ? J->grad_y + i : NULL, gpart + (int64_t)mi * P, gx, &loss);
         if (J->gx) memcpy(J->gx + i * Din, gx, sizeof(double) * Din);
     }
     J->loss_part[tid] = loss;
 }
 
-/* Returns B (queries that meet their AABB).  mlp_grads: [num_mlps][P], overwritten. */
-int64_t orc_backward(const orc_model* m, int32_t num_mlps, int64_t n, const float* rays, const int32_t* ids,
-                     const float* tmax, const uint8_t* labels, double* loss, double* mlp_grads, double* gx,
-                     int nthreads) {
+static int64_t backward_impl(const orc_model* m, int32_t num_mlps, int64_t n, const float* rays,
+                             const int32_t* ids, const float* tmax, const uint8_t* labels, const double* grad_y,
+                             double* loss, double* mlp_grads, double* gx, int nthreads) {
     const int64_t P = orc_mlp_params(m);
     int32_t* st = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
     int64_t B = 0;
@@ -877,7 +887,7 @@ int64_t orc_backward(const orc_model* m, int32_t num_mlps, int64_t n, const floa
     int nt = (int)((n + chunk - 1) / chunk);
     if (nt < 1) nt = 1;
     bwd_job J;
-    J.m = m; J.n = n; J.rays = rays; J.tmax = tmax; J.ids = ids; J.labels = labels;
+    J.m = m; J.n = n; J.rays = rays; J.tmax = tmax; J.ids = ids; J.labels = labels; J.grad_y = grad_y;
     J.inv_b = B > 0 ? 1.0 / (double)B : 0.0;
     J.num_mlps = num_mlps;
     J.gmlp_part = (double*)calloc((size_t)nt * num_mlps * P, sizeof(double));
@@ -907,6 +917,23 @@ int64_t orc_backward(const orc_model* m, int32_t num_mlps, int64_t n, const floa
     free(J.gmlp_part);
     free(J.loss_part);
     return B;
+}
+
+/* Training gradients (Sec. 4.2): binary cross-entropy on the logits, mean over
+ * the B queries that meet their AABB.  Returns B.  mlp_grads: [num_mlps][P],
+ * overwritten; gx: [n][din] feature gradients or NULL. */
+int64_t orc_backward(const orc_model* m, int32_t num_mlps, int64_t n, const float* rays, const int32_t* ids,
+                     const float* tmax, const uint8_t* labels, double* loss, double* mlp_grads, double* gx,
+                     int nthreads) {
+    return backward_impl(m, num_mlps, n, rays, ids, tmax, labels, NULL, loss, mlp_grads, gx, nthreads);
+}
+
+/* Gradients of sum_i grad_y[i] * y_i (chain rule through the sigmoid, the MLP
+ * and the interpolation), no 1/B factor.  Returns B. */
+int64_t orc_backward_given(const orc_model* m, int32_t num_mlps, int64_t n, const float* rays, const int32_t* ids,
+                           const float* tmax, const double* grad_y, double* mlp_grads, double* gx, int nthreads) {
+    double loss = 0.0;
+    return backward_impl(m, num_mlps, n, rays, ids, tmax, NULL, grad_y, &loss, mlp_grads, gx, nthreads);
 }
 
 /* Scatter per-query feature gradients gx [n][din] into a dense binary64 grid

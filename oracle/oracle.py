@@ -71,6 +71,7 @@ def lib():
             "orc_query_detail": (C.c_int, [vp, vp, i32, C.c_float, vp, vp, vp, vp]),
             "orc_mlp_only": (None, [vp, i32, i64, vp, vp, vp]),
             "orc_backward": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
+            "orc_backward_given": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_grid_grad_dense": (None, [vp, i32, i64, vp, vp, vp, vp, vp]),
             "orc_grid_grad_at": (None, [vp, i32, i64, vp, vp, vp, vp, i64, vp, vp]),
             "orc_ray_tri": (C.c_int, [vp, vp, d, vp]),
@@ -220,12 +221,42 @@ class Model:
         return st, u.reshape(3, 3), x, ce.reshape(3 * L, 8), cw.reshape(3 * L, 8)
 
     def mlp_only(self, x, mlp: int = 0, want_acts: bool = False):
+        """Logits of MLP `mlp` on features x [n, din]; with want_acts also the
+        pre-activation outputs a_j = W_j h_{j-1} of the hidden layers [n, H, width]."""
         x = np.ascontiguousarray(x, np.float64).reshape(-1, self.shape.din)
         n = x.shape[0]
         z = np.empty(n)
         acts = np.empty((n, self.shape.hidden, self.shape.width)) if want_acts else None
         lib().orc_mlp_only(self.ref, mlp, n, _p(x), _p(z), _p(acts))
         return (z, acts) if want_acts else z
+
+    def fp8_calibrate(self, rays, ids, tmax, mlp: int = 0):
+        """Per-layer E4M3 scales of MLP `mlp` (the paper's networks run in reduced
+        precision, Sec. 4.2; per-layer scaling is the reading for E4M3): s_W[j] =
+        max|W_j| / 448 and s_x[j] = max |input of layer j| / 448 over the queries
+        that meet their AABB and whose object uses `mlp`, the inputs taken from
+        the binary64 forward pass (x for layer 1, h_{j-1} after ReLU for layer
+        j); 1 where the maximum is 0.  Returns [s_W..., s_x...]."""
+        exact = self.with_(quant="exact")
+        f = exact.forward(rays, ids, tmax, want_x=True)
+        ids = np.asarray(ids)
+        sel = f["status"] == 1
+        sel[sel] &= self.mlp_index[ids[sel]] == mlp
+        H, W, din = self.shape.hidden, self.shape.width, self.shape.din
+        w = self.mlps64[mlp]
+        amax_w, amax_x = [], []
+        off = 0
+        for j in range(H):
+            kin = din if j == 0 else W
+            amax_w.append(np.abs(w[off:off + W * kin]).max(initial=0.0))
+            off += W * kin
+        x = f["x"][sel]
+        amax_x.append(np.abs(x).max(initial=0.0))
+        if H > 1:
+            _, acts = exact.mlp_only(x, mlp, want_acts=True)
+            for j in range(1, H):
+                amax_x.append(np.maximum(acts[:, j - 1, :], 0.0).max(initial=0.0))  # acts: pre-ReLU
+        return np.array([a / 448.0 if a > 0 else 1.0 for a in amax_w + amax_x])
 
     # ---- training ------------------------------------------------------
     def backward(self, rays, ids, tmax, labels, nthreads: int = 0, want_gx: bool = True):
@@ -241,6 +272,19 @@ class Model:
         B = lib().orc_backward(self.ref, self.M, n, _p(rays), _p(ids), _p(tmax), _p(labels), C.byref(loss),
                                _p(g), _p(gx), nthreads)
         return loss.value, int(B), g, gx
+
+    def backward_given(self, rays, ids, tmax, grad_y, nthreads: int = 0):
+        """Gradients of sum_i grad_y[i] * y_i: returns (B, mlp_grads [M, P], gx [n, din])."""
+        rays = np.ascontiguousarray(rays, np.float32)
+        ids = np.ascontiguousarray(ids, np.int32)
+        tmax = np.ascontiguousarray(tmax, np.float32)
+        gy = np.ascontiguousarray(grad_y, np.float64)
+        n = ids.shape[0]
+        g = np.zeros((self.M, self.shape.mlp_params))
+        gx = np.zeros((n, self.shape.din))
+        B = lib().orc_backward_given(self.ref, self.M, n, _p(rays), _p(ids), _p(tmax), _p(gy), _p(g), _p(gx),
+                                     nthreads)
+        return int(B), g, gx
 
     def grid_grad_dense(self, obj, rays, ids, tmax, gx):
         out = np.zeros(self.grid_elems)

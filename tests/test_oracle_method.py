@@ -301,6 +301,57 @@ def test_fp8_identity_when_exact():
     np.testing.assert_array_equal(m.mlp_only(x), mq.mlp_only(x))
 
 
+def _two_object_calibration_case(mlp0):
+    g = np.random.default_rng(31)
+    boxes = np.array([[-1, -1, -1, 1, 1, 1], [3, 0, 0, 4, 2, 1]], np.float32)
+    n = 3000
+    ids = (np.arange(n) % 2).astype(np.int32)
+    rays = np.empty((n, 6), np.float32)
+    tmax = np.empty(n, np.float32)
+    for k in range(2):
+        s = np.nonzero(ids == k)[0]
+        r, t = S.rays_sphere_to_box(s.size, boxes[k], g, radius=4.0, center=0.5 * (boxes[k, :3] + boxes[k, 3:]))
+        rays[s], tmax[s] = r, t
+    rays[::7, 3:] = -rays[::7, 3:]  # misses
+    mlps = np.stack([mlp0, S.xavier_mlp(S.TINY, S.rng(5, 3))])
+    # object 1 (MLP 1) has latents 1e4 times larger: it must not enter MLP 0's scales
+    m = O.Model(S.TINY, boxes, mlps, mlp_index=np.array([0, 1], np.int32), grid_seed=3, grid_amp=[1.0, 1e4])
+    return m, rays, ids, tmax
+
+
+def test_fp8_calibration_closed_form():
+    """Identity-like layers make every layer input a closed form of the features:
+    W_1 = -[I; 0] gives h_1 = ReLU(-x) (zero-padded), W_2 = 2I gives h_2 = 2 ReLU(-x).
+    So s_W = [1, 2, 3] / 448 and s_x = [max|x|, max ReLU(-x), 2 max ReLU(-x)] / 448 over
+    the MLP's own hitting queries."""
+    sh = S.TINY
+    din, W = sh.din, sh.width
+    w = np.concatenate([-np.eye(W, din).ravel(), 2 * np.eye(W).ravel(), 3 * np.eye(W).ravel(), np.ones(W)])
+    m, rays, ids, tmax = _two_object_calibration_case(w.astype(np.float32))
+    f = m.forward(rays, ids, tmax, want_x=True)
+    sel = (f["status"] == 1) & (ids == 0)
+    assert 0 < sel.sum() < (f["status"] == 1).sum()
+    x = f["x"][sel]
+    r = np.maximum(-x, 0).max()
+    assert np.abs(x).max() > r > 0  # the max of |x| and of ReLU(-x) differ here
+    s = m.fp8_calibrate(rays, ids, tmax, mlp=0)
+    np.testing.assert_array_equal(s[:3], np.array([1.0, 2.0, 3.0]) / 448.0)
+    np.testing.assert_array_equal(s[3:], np.array([np.abs(x).max(), r, 2 * r]) / 448.0)
+    # the other MLP sees the large latents
+    s1 = m.fp8_calibrate(rays, ids, tmax, mlp=1)
+    assert s1[3] > 1e3 * s[3]
+
+
+def test_fp8_calibration_zero_weights_and_no_queries():
+    """All-zero weights give unit weight scales and unit scales for the all-zero hidden
+    inputs; with no query of the MLP every activation scale is 1."""
+    m, rays, ids, tmax = _two_object_calibration_case(np.zeros(S.TINY.mlp_params, np.float32))
+    s = m.fp8_calibrate(rays, ids, tmax, mlp=0)
+    assert (s[:3] == 1.0).all() and s[3] < 1.0 and (s[4:] == 1.0).all()
+    s = m.fp8_calibrate(rays[ids == 1], ids[ids == 1], tmax[ids == 1], mlp=0)
+    assert (s == 1.0).all()
+
+
 @pytest.mark.parametrize("q", ["bf16", "f16"])
 def test_quantised_within_bound(q):
     w = S.tiny_workload(n_rays=3000)
@@ -369,6 +420,40 @@ def test_backward_matches_finite_differences():
         gm[k] -= h
         # grid values are binary32 in the model: divide by the step actually taken
         fd = (loss_of(W, gp.astype(np.float32)) - loss_of(W, gm.astype(np.float32))) / (
+            gp.astype(np.float32)[k] - gm.astype(np.float32)[k])
+        assert abs(fd - gg[k]) <= 1e-5 * abs(gg[k]) + 1e-10, (k, fd, gg[k])
+
+
+def test_backward_given_matches_finite_differences():
+    """Upstream-gradient backward: d/dtheta of sum_i c_i y_i by central differences."""
+    sh = S.TINY
+    wl = S.tiny_workload(n_rays=256)
+    g0 = O.init_grid(seed=8, obj=0, amp=0.5, grid_dtype="f32", count=O.Model(sh, UNIT_BOX, zero_mlp(sh)).grid_elems)
+    W = S.xavier_mlp(sh, S.rng(78, 3)).astype(np.float64) * 2.0
+    c = np.random.default_rng(9).normal(size=256)
+
+    def obj_of(Wv, g):
+        y = O.Model(sh, wl["aabb"], Wv[None, :], grids=[g], coord_mode=1).forward(wl["rays"], wl["ids"], wl["tmax"])["y"]
+        return float(np.sum(c * y))
+
+    m = O.Model(sh, wl["aabb"], W[None, :], grids=[g0], coord_mode=1)
+    B, gW, gx = m.backward_given(wl["rays"], wl["ids"], wl["tmax"], c)
+    assert B == 256
+    rng = np.random.default_rng(10)
+    for k in rng.choice(sh.mlp_params, 30, replace=False):
+        h = 1e-6 * max(1.0, abs(W[k]))
+        Wp, Wm = W.copy(), W.copy()
+        Wp[k] += h
+        Wm[k] -= h
+        fd = (obj_of(Wp, g0) - obj_of(Wm, g0)) / (2 * h)
+        assert abs(fd - gW[0, k]) <= 1e-6 * max(1e-3, abs(gW[0, k])) + 1e-9, (k, fd, gW[0, k])
+    gg = m.grid_grad_dense(0, wl["rays"], wl["ids"], wl["tmax"], gx)
+    g64 = g0.astype(np.float64)
+    for k in rng.choice(np.nonzero(gg)[0], 20, replace=False):
+        gp, gm = g64.copy(), g64.copy()
+        gp[k] += 2.0 ** -14
+        gm[k] -= 2.0 ** -14
+        fd = (obj_of(W, gp.astype(np.float32)) - obj_of(W, gm.astype(np.float32))) / (
             gp.astype(np.float32)[k] - gm.astype(np.float32)[k])
         assert abs(fd - gg[k]) <= 1e-5 * abs(gg[k]) + 1e-10, (k, fd, gg[k])
 
