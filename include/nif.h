@@ -98,6 +98,18 @@ nif_status nif_set_mlp(nif_ctx* ctx, int32_t mlp, float* weights);
  * saturating at 448, accumulated in binary32. */
 nif_status nif_set_fp8_scales(nif_ctx* ctx, int32_t mlp, const float* scales);
 
+/* FP8 calibration of MLP `mlp` (per-layer scaling for the E4M3 path; the
+ * paper runs its networks in reduced precision, Sec. 4.2 and Sec. 5): runs the
+ * binary32 encoding and layers 1..H-1 over the n queries (dev arrays as
+ * nif_query) whose object uses `mlp` and whose segment meets the AABB, and
+ * sets s_W[j] = max|W_j| / 448 and s_x[j] = max |input of layer j| / 448
+ * (1 when the maximum is 0), as nif_set_fp8_scales would.  scales (host,
+ * 2*hidden_layers floats, nullable) receives them.  Needs nif_prepare (any
+ * dtype) for the object table; ws: nif_workspace_bytes(ctx, n, 2) bytes.
+ * Synchronises `stream`.  n = 0 gives s_x = 1. */
+nif_status nif_calibrate_fp8(nif_ctx* ctx, int32_t mlp, const float* rays, const int32_t* object_ids,
+                             const float* t_max, int64_t n, float* scales, void* ws, size_t ws_bytes, void* stream);
+
 /* Fill object obj's grid with the initial latents U[-amp, amp) (Sec. 5
  * "Initialization": amp = 1e-4): element i gets the top 24 bits m of word
  * (i mod 4) of Philox4x64-10 (Salmon et al., SC 2011) at counter
@@ -114,12 +126,19 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
 /* Options.  NIF_OPT_ORDER: before a query, bucket-sort the queries by
  * (object, Morton code of the AABB entry point) so that a wave's gathers share
  * cache lines and waves use one MLP: 0 never, 1 always, 2 (default) when
- * n >= 65536.  Changes nif_workspace_bytes. */
-enum { NIF_OPT_ORDER = 1 };
+ * n >= 65536.  Changes nif_workspace_bytes.
+ * NIF_OPT_GRID_IMAGE (binary16 grids only): 1 = nif_prepare also builds, for
+ * every object, a context-owned query image of its grid in which the four
+ * latent pairs of a cell face (x..x+1, y..y+1) are one 16-byte span, halving
+ * the gathers of a lookup; it costs twice the grid's memory per object and is
+ * rebuilt by every nif_prepare.  Outputs are bit-identical.  0 (default) =
+ * gather from the grids. */
+enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2 };
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 
-/* Workspace bytes needed by nif_query / nif_train_step for n queries. */
-size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode /* 0 query, 1 train */);
+/* Workspace bytes needed by nif_query (mode 0), nif_train_step (mode 1) or
+ * nif_calibrate_fp8 (mode 2) for n queries. */
+size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode);
 
 /* Visibility of n (ray, object) queries (Sec. 4.1: one query per object AABB
  * the ray meets; Sec. 3 Eq. (1): 1 = visible).
@@ -149,6 +168,32 @@ nif_status nif_order(nif_ctx* ctx, const float* rays, const int32_t* object_ids,
 nif_status nif_query_ordered(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids,
                              const float* t_max, const uint32_t* perm, int64_t n, float* visibility, float* logits,
                              void* stream);
+
+/* Query plans for repeated batches on fixed buffers (the batched form: rays
+ * of many objects of uneven size in one persistent launch, Sec. 4.1 issues one
+ * query per (ray, object) pair).  A plan fixes ctx, dtype, the input, output
+ * and workspace pointers and n; their contents may change between launches.
+ * nif_plan_create: with tuning == NULL, times every candidate schedule
+ *   (ordering off / bucket order / bucket order + window sort, times the
+ *   persistent grid's blocks per compute unit) on these buffers and keeps the
+ *   fastest; otherwise uses the schedule of the JSON string `tuning` (as
+ *   written by nif_plan_tuning: keys "order" 0..2 and "blocks_per_cu" 1..32).
+ *   Then captures the ordering and query kernels into a HIP graph.  Writes the
+ *   outputs while tuning; synchronises `stream`.  ws: at least
+ *   nif_plan_workspace_bytes(ctx, n) bytes (dev), kept by the plan.  Needs
+ *   nif_prepare(ctx, dtype); later nif_prepare calls (new weights) are seen by
+ *   the plan, nif_set_object calls are not.
+ * nif_plan_launch: replays the graph on `stream` (same outputs as nif_query).
+ * nif_plan_tuning: the chosen schedule as JSON (host buffer buf of buf_bytes).
+ * nif_plan_destroy: frees the plan (not the caller's buffers). */
+typedef struct nif_plan nif_plan;
+size_t nif_plan_workspace_bytes(const nif_ctx* ctx, int64_t n);
+nif_status nif_plan_create(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids,
+                           const float* t_max, int64_t n, float* visibility, float* logits, void* ws, size_t ws_bytes,
+                           const char* tuning, void* stream, nif_plan** out);
+nif_status nif_plan_launch(nif_plan* plan, void* stream);
+nif_status nif_plan_tuning(const nif_plan* plan, char* buf, size_t buf_bytes);
+void nif_plan_destroy(nif_plan* plan);
 
 /* The two stages of a query as separate launches, as the paper's pipeline runs
  * them (Sec. 4.1: a grid-lookup kernel, then an inference kernel).
@@ -205,6 +250,21 @@ size_t nif_touched_bytes(const nif_ctx* ctx);
 nif_status nif_train_step(nif_ctx* ctx, int32_t mlp, const float* rays, const int32_t* object_ids, const float* t_max,
                           const uint8_t* labels, int64_t n, int32_t step, const nif_adam* adam, float* loss,
                           float* mlp_grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward pass of a binary32 query for a given upstream gradient, so that the
+ * query can sit inside a larger differentiable program (the gradients the
+ * paper's training back-propagates through the MLP and the interpolation,
+ * Sec. 4.2, for an arbitrary loss of the visibilities).
+ *   grad_visibility (dev, n floats): dL/dy_i of the visibility y_i.
+ *   Recomputes the forward pass of the queries whose object uses MLP `mlp` and
+ *   whose segment meets the AABB, then dL/dz_i = g_i y_i (1 - y_i) (no 1/B
+ *   factor); mlp_grad (dev, mlp_params floats, nullable) receives dL/dW;
+ *   each such object's registered grid gradient buffer (nif_set_object_train)
+ *   is incremented by dL/dlatent.  Touched bitmaps are left zero; weights,
+ *   latents and moments are not touched.  ws: nif_workspace_bytes(ctx, n, 1). */
+nif_status nif_backward(nif_ctx* ctx, int32_t mlp, const float* rays, const int32_t* object_ids, const float* t_max,
+                        const float* grad_visibility, int64_t n, float* mlp_grad, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* Plain BVH any-hit ray casting: exact shadow-ray labels for training and the
  * baseline the paper compares against (Sec. 6 "Performance Evaluation").

@@ -4,6 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stdlib.h>
+
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -68,7 +71,19 @@ struct nif_ctx {
     bool train_tab_dirty = true;
     uint8_t* d_train_fwd = nullptr;  // binary32 forward image of the MLP being trained
     float* d_train_bwd = nullptr;    // backward image
+    // y-pair query images of binary16 grids (NIF_OPT_GRID_IMAGE)
+    int32_t image_mode = 0;
+    int64_t ioff[3 * kMaxLevels + 1];
+    std::vector<void*> images;  // per object, built by nif_prepare
+    bool images_ready = false;
 };
+
+static void free_images(nif_ctx* c) {
+    for (auto& p : c->images)
+        if (p) (void)hipFree(p);
+    c->images.clear();
+    c->images_ready = false;
+}
 
 static bool uses_order(const nif_ctx* c, int64_t n) {
     if (c->order_mode == 0) return false;
@@ -123,6 +138,12 @@ extern "C" nif_status nif_create(const nif_model_desc* desc, int32_t num_objects
         }
     c->toff[3 * d.levels] = o;
     c->grid_elems = o;
+    o = 0;
+    for (int k = 0; k < 3 * d.levels; ++k) {
+        c->ioff[k] = o;
+        o += image_table_elems(c->res[k % d.levels]);
+    }
+    c->ioff[3 * d.levels] = o;
     c->P = (int64_t)d.width * c->din + (int64_t)(d.hidden_layers - 1) * d.width * d.width + d.width;
     c->objs.resize(num_objects);
     c->masters.assign(num_mlps, nullptr);
@@ -148,6 +169,7 @@ extern "C" void nif_destroy(nif_ctx* c) {
     if (c->d_train_tab) (void)hipFree(c->d_train_tab);
     if (c->d_train_fwd) (void)hipFree(c->d_train_fwd);
     if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
+    free_images(c);
     delete c;
 }
 
@@ -222,6 +244,15 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     }
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
+    // query images of the grids (rebuilt on every call: the grids may have changed)
+    if (c->image_mode) {
+        if (c->images.size() != (size_t)c->K) c->images.assign(c->K, nullptr);
+        for (int k = 0; k < c->K; ++k) {
+            if (!c->images[k]) HIP_TRY(hipMalloc(&c->images[k], (size_t)c->ioff[3 * c->d.levels] * 2));
+            HIP_TRY(launch_build_image(c->objs[k].grid, c->images[k], c->toff, c->ioff, c->res, c->d.levels, s));
+        }
+        c->images_ready = true;
+    }
     // object table
     std::vector<ObjDev> od(c->K);
     for (int k = 0; k < c->K; ++k) {
@@ -233,6 +264,7 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         }
         od[k].mlp = o.mlp;
         od[k].grid = o.grid;
+        od[k].image = c->image_mode ? c->images[k] : nullptr;
     }
     if (!c->d_objs) HIP_TRY(hipMalloc(&c->d_objs, sizeof(ObjDev) * c->K));
     HIP_TRY(hipMemcpy(c->d_objs, od.data(), sizeof(ObjDev) * c->K, hipMemcpyHostToDevice));
@@ -258,7 +290,9 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
 static size_t train_bytes(const nif_ctx* c, int64_t n);
 
 extern "C" size_t nif_workspace_bytes(const nif_ctx* c, int64_t n, int32_t mode) {
-    if (!c || n <= 0) return 0;
+    if (!c || n < 0) return 0;
+    if (mode == 2) return calib_workspace_bytes(n, c->din);  // also n = 0: the maxima words
+    if (n == 0) return 0;
     if (mode == 1) return train_bytes(c, n);
     return uses_order(c, n) ? order_workspace_bytes(n, c->K) : 0;
 }
@@ -269,6 +303,16 @@ extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) 
     case NIF_OPT_ORDER:
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_ORDER takes 0, 1 or 2");
         c->order_mode = (int32_t)value;
+        return ok();
+    case NIF_OPT_GRID_IMAGE:
+        if (value < 0 || value > 1) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_GRID_IMAGE takes 0 or 1");
+        if (value == 1 && c->d.grid_dtype != NIF_F16)
+            return fail(NIF_ERR_UNSUPPORTED, "NIF_OPT_GRID_IMAGE needs binary16 grids");
+        if (value == 0) free_images(c);
+        if ((int32_t)value != c->image_mode) {
+            c->image_mode = (int32_t)value;
+            for (bool& p : c->prepared) p = false;
+        }
         return ok();
     }
     return fail(NIF_ERR_INVALID_ARG, "unknown option %d", option);
@@ -286,8 +330,12 @@ static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, 
 }
 
 static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
-                            const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s) {
+                            const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s,
+                            int32_t blocks_per_cu = 0) {
     FwdArgs a{};
+    a.blocks_per_cu = blocks_per_cu;
+    a.use_image = c->image_mode && c->images_ready;
+    for (int k = 0; k < 3 * c->d.levels; ++k) a.ioff[k] = c->ioff[k];
     a.perm = perm;
     a.rays = rays;
     a.ids = ids;
@@ -308,8 +356,10 @@ static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const 
 }
 
 static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
-                            uint32_t* perm_dst, void* ws, const uint32_t** perm, hipStream_t s) {
+                            uint32_t* perm_dst, void* ws, const uint32_t** perm, hipStream_t s,
+                            bool refine = true) {
     OrderArgs o{};
+    o.no_refine = refine ? 0 : 1;
     o.rays = rays;
     o.ids = ids;
     o.tmax = tmax;
@@ -363,6 +413,8 @@ extern "C" nif_status nif_query_ordered(nif_ctx* c, int32_t dtype, const float* 
 }
 
 static void fill_common(const nif_ctx* c, FwdArgs& a) {
+    a.use_image = c->image_mode && c->images_ready;
+    for (int k = 0; k < 3 * c->d.levels; ++k) a.ioff[k] = c->ioff[k];
     a.objs = c->d_objs;
     a.num_objects = c->K;
     a.hidden = c->d.hidden_layers;
@@ -388,6 +440,44 @@ extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* i
     a.status_out = status;
     a.pack = c->pack[kF32];
     HIP_TRY(launch_encode(c->d.levels, c->d.grid_dtype, a, c->num_cus, (hipStream_t)stream));
+    return ok();
+}
+
+extern "C" nif_status nif_calibrate_fp8(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,
+                                        const float* tmax, int64_t n, float* scales, void* ws, size_t ws_bytes,
+                                        void* stream) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_calibrate_fp8: NULL context");
+    if (mlp < 0 || mlp >= c->M) return fail(NIF_ERR_INVALID_ARG, "mlp %d out of range", mlp);
+    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_calibrate_fp8: n < 0");
+    if (n > 0 && (!rays || !ids || !tmax)) return fail(NIF_ERR_INVALID_ARG, "nif_calibrate_fp8: NULL input");
+    if (n > (int64_t)1 << 31) return fail(NIF_ERR_UNSUPPORTED, "nif_calibrate_fp8: n too large");
+    if (!c->masters[mlp]) return fail(NIF_ERR_STATE, "MLP %d not registered", mlp);
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    const size_t need = calib_workspace_bytes(n, c->din);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    FwdArgs a{};
+    fill_common(c, a);
+    a.rays = rays;
+    a.ids = ids;
+    a.tmax = tmax;
+    a.n = n;
+    a.pack = c->pack[kF32];
+    const int H = c->d.hidden_layers;
+    unsigned amax[2 * kMaxHidden];
+    HIP_TRY(launch_calibrate(a, c->d.levels, c->d.grid_dtype, c->num_cus, mlp, c->masters[mlp], c->din, H, ws, amax,
+                             (hipStream_t)stream));
+    std::vector<float> sc(2 * H);
+    for (int j = 0; j < H; ++j) {
+        float w, x;
+        memcpy(&w, &amax[kMaxHidden + j], 4);
+        memcpy(&x, &amax[j], 4);
+        if (!isfinite(w) || !isfinite(x)) return fail(NIF_ERR_STATE, "non-finite weight or activation in layer %d", j + 1);
+        sc[j] = w > 0.0f ? w / 448.0f : 1.0f;
+        sc[H + j] = x > 0.0f ? x / 448.0f : 1.0f;
+    }
+    c->fp8[mlp] = sc;
+    c->prepared[kFP8] = false;
+    if (scales) memcpy(scales, sc.data(), sizeof(float) * 2 * H);
     return ok();
 }
 
@@ -447,12 +537,13 @@ static size_t train_bytes(const nif_ctx* c, int64_t n) {
            (uses_order(c, n) ? order_workspace_bytes(n, c->K) : 0);
 }
 
-extern "C" nif_status nif_train_step(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,
-                                     const float* tmax, const uint8_t* labels, int64_t n, int32_t step,
-                                     const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
-                                     void* stream) {
-    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, labels, "nif_train_step");
-    if (st != NIF_OK) return st;
+// Training step (labels, optional Adam) or backward pass of a given upstream
+// gradient (grad_y; gradients only).
+static nif_status train_common(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids, const float* tmax,
+                               const uint8_t* labels, const float* grad_y, int64_t n, int32_t step,
+                               const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
+                               void* stream) {
+    nif_status st = NIF_OK;
     if (mlp < 0 || mlp >= c->M) return fail(NIF_ERR_INVALID_ARG, "mlp %d out of range", mlp);
     if (adam && step < 1) return fail(NIF_ERR_INVALID_ARG, "step must be >= 1");
     if (adam && !(adam->lr > 0.0f && adam->beta1 >= 0.0f && adam->beta1 < 1.0f && adam->beta2 >= 0.0f &&
@@ -504,6 +595,7 @@ extern "C" nif_status nif_train_step(nif_ctx* c, int32_t mlp, const float* rays,
     A.ids = ids;
     A.tmax = tmax;
     A.labels = labels;
+    A.grad_y = grad_y;
     A.n = n;
     A.objs = c->d_objs;
     A.num_objects = K;
@@ -541,4 +633,182 @@ extern "C" nif_status nif_train_step(nif_ctx* c, int32_t mlp, const float* rays,
                          c->num_cus, s));
     if (adam) invalidate(c);  // the masters changed: packed copies are stale
     return ok();
+}
+
+extern "C" nif_status nif_train_step(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,
+                                     const float* tmax, const uint8_t* labels, int64_t n, int32_t step,
+                                     const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
+                                     void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, labels, "nif_train_step");
+    if (st != NIF_OK) return st;
+    return train_common(c, mlp, rays, ids, tmax, labels, nullptr, n, step, adam, loss, mlp_grad, ws, ws_bytes,
+                        stream);
+}
+
+extern "C" nif_status nif_backward(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,
+                                   const float* tmax, const float* grad_visibility, int64_t n, float* mlp_grad,
+                                   void* ws, size_t ws_bytes, void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, grad_visibility, "nif_backward");
+    if (st != NIF_OK) return st;
+    return train_common(c, mlp, rays, ids, tmax, nullptr, grad_visibility, n, 1, nullptr, nullptr, mlp_grad, ws,
+                        ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Query plans: one schedule (ordering variant + persistent grid size) chosen by
+// timing the candidates on the caller's buffers, then captured into a HIP
+// graph that replays the ordering kernels and the fused query kernel.
+// ---------------------------------------------------------------------------
+struct Sched {
+    int32_t order;          // 0 none, 1 bucket order, 2 bucket order + window sort
+    int32_t blocks_per_cu;  // persistent grid: blocks per compute unit
+};
+
+struct nif_plan {
+    nif_ctx* c = nullptr;
+    int32_t dtype = 0;
+    const float* rays = nullptr;
+    const int32_t* ids = nullptr;
+    const float* tmax = nullptr;
+    int64_t n = 0;
+    float* vis = nullptr;
+    float* logits = nullptr;
+    void* ws = nullptr;
+    Sched sched{2, 8};
+    float tuned_us = -1.0f;  // time of the chosen schedule (-1: given, not tuned)
+    int32_t candidates = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static nif_status plan_run(nif_plan* p, const Sched& sc, hipStream_t s) {
+    const uint32_t* perm = nullptr;
+    if (sc.order > 0) {
+        nif_status st = run_order(p->c, p->rays, p->ids, p->tmax, p->n, nullptr, p->ws, &perm, s, sc.order == 2);
+        if (st != NIF_OK) return st;
+    }
+    return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu);
+}
+
+static bool parse_int_key(const char* js, const char* key, int32_t* v) {
+    const char* q = strstr(js, key);
+    if (!q) return false;
+    q = strchr(q + strlen(key), ':');
+    if (!q) return false;
+    char* end = nullptr;
+    const long x = strtol(q + 1, &end, 10);
+    if (end == q + 1) return false;
+    *v = (int32_t)x;
+    return true;
+}
+
+extern "C" size_t nif_plan_workspace_bytes(const nif_ctx* c, int64_t n) {
+    if (!c || n <= 0) return 0;
+    return order_workspace_bytes(n, c->K);
+}
+
+extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids,
+                                      const float* tmax, int64_t n, float* vis, float* logits, void* ws,
+                                      size_t ws_bytes, const char* tuning, void* stream, nif_plan** out) {
+    if (!out) return fail(NIF_ERR_INVALID_ARG, "nif_plan_create: NULL out");
+    *out = nullptr;
+    nif_status st = check_query_args(c, dtype, rays, ids, tmax, n, vis, "nif_plan_create");
+    if (st != NIF_OK) return st;
+    if (n == 0) return fail(NIF_ERR_INVALID_ARG, "nif_plan_create: n must be > 0");
+    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    const size_t need = order_workspace_bytes(n, c->K);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    std::unique_ptr<nif_plan> p(new nif_plan);
+    p->c = c;
+    p->dtype = dtype;
+    p->rays = rays;
+    p->ids = ids;
+    p->tmax = tmax;
+    p->n = n;
+    p->vis = vis;
+    p->logits = logits;
+    p->ws = ws;
+    hipStream_t s = (hipStream_t)stream;
+    if (tuning) {
+        Sched sc{2, 8};
+        if (!parse_int_key(tuning, "\"order\"", &sc.order) || !parse_int_key(tuning, "\"blocks_per_cu\"", &sc.blocks_per_cu))
+            return fail(NIF_ERR_INVALID_ARG, "tuning string lacks \"order\" or \"blocks_per_cu\"");
+        if (sc.order < 0 || sc.order > 2 || sc.blocks_per_cu < 1 || sc.blocks_per_cu > 32)
+            return fail(NIF_ERR_INVALID_ARG, "tuning out of range (order 0..2, blocks_per_cu 1..32)");
+        p->sched = sc;
+    } else {
+        // autotune: every candidate once untimed, then the best of three timed runs
+        const Sched cand[] = {{0, 4}, {0, 8}, {0, 16}, {1, 4}, {1, 8}, {1, 16}, {2, 2}, {2, 4}, {2, 8}, {2, 16}};
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best = -1.0f;
+        for (const Sched& sc : cand) {
+            st = plan_run(p.get(), sc, s);
+            float tmin = 1e30f;
+            for (int r = 0; r < 3 && st == NIF_OK; ++r) {
+                (void)hipEventRecord(e0, s);
+                st = plan_run(p.get(), sc, s);
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) st = fail(NIF_ERR_HIP, "event synchronisation failed");
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tmin = ms < tmin ? ms : tmin;
+            }
+            if (st != NIF_OK) break;
+            ++p->candidates;
+            if (best < 0.0f || tmin < best) {
+                best = tmin;
+                p->sched = sc;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != NIF_OK) return st;
+        p->tuned_us = best * 1e3f;
+    }
+    // capture on a private stream (the caller's may be the legacy default stream)
+    hipStream_t cs;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        st = plan_run(p.get(), p->sched, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        p->graph = g;
+        if (e == hipSuccess && st == NIF_OK) e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != NIF_OK) {
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        return st;
+    }
+    if (e != hipSuccess) {
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        return fail(NIF_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = p.release();
+    return ok();
+}
+
+extern "C" nif_status nif_plan_launch(nif_plan* p, void* stream) {
+    if (!p || !p->exec) return fail(NIF_ERR_INVALID_ARG, "nif_plan_launch: NULL plan");
+    HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return ok();
+}
+
+extern "C" nif_status nif_plan_tuning(const nif_plan* p, char* buf, size_t buf_bytes) {
+    if (!p || !buf) return fail(NIF_ERR_INVALID_ARG, "nif_plan_tuning: NULL argument");
+    const int k = snprintf(buf, buf_bytes, "{\"order\": %d, \"blocks_per_cu\": %d, \"tuned_us\": %.3f, \"candidates\": %d}",
+                           p->sched.order, p->sched.blocks_per_cu, (double)p->tuned_us, p->candidates);
+    if (k < 0 || (size_t)k >= buf_bytes) return fail(NIF_ERR_INVALID_ARG, "nif_plan_tuning: buffer too small");
+    return ok();
+}
+
+extern "C" void nif_plan_destroy(nif_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
 }

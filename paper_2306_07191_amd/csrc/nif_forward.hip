@@ -157,6 +157,67 @@ __device__ __forceinline__ void encode_half(const float u[3][3], int half, const
     }
 }
 
+// The same lookups from the y-pair image of a binary16 grid: two 16-byte loads
+// per lookup (z and z+1 faces) instead of four 8-byte row loads, with the same
+// interpolation order, so the features are bit-identical to encode_half.
+template <int L>
+__device__ __forceinline__ void encode_half_image(const float u[3][3], int half, const GLOBAL _Float16* img,
+                                                  const FwdArgs& A, float* x) {
+    constexpr int NL = 3 * L / 2;
+    int64_t base[NL];
+    float w[NL][3];
+    int64_t sz[NL];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+        const int k0 = t, k1 = NL + t;
+        const int e = half ? k1 / L : k0 / L;
+        const int l = half ? k1 % L : k0 % L;
+        const int N = A.res[l];
+        const float fN = (float)N;
+        int c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float ue = e == 0 ? u[0][a] : (e == 1 ? u[1][a] : u[2][a]);
+            c[a] = cell_coord(ue, fN, N, w[t][a]);
+        }
+        const int32_t N1 = N + 1;
+        const int64_t ent = ((int64_t)c[2] * N + c[1]) * N1 + c[0];
+        base[t] = (half ? A.ioff[k1] : A.ioff[k0]) + ent * 4;
+        sz[t] = (int64_t)N * N1 * 4;
+    }
+    uint32_t q[NL][2][4];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+#pragma unroll
+        for (int zz = 0; zz < 2; ++zz) {
+            // four dword reads of one dword-aligned 16-byte span: one global_load_dwordx4
+            const GLOBAL unsigned* p = reinterpret_cast<const GLOBAL unsigned*>(img + base[t] + zz * sz[t]);
+            q[t][zz][0] = p[0];
+            q[t][zz][1] = p[1];
+            q[t][zz][2] = p[2];
+            q[t][zz][3] = p[3];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+        float r[2][8];  // per face: (x,y) f0 f1, (x,y+1) f0 f1, (x+1,y) f0 f1, (x+1,y+1) f0 f1
+#pragma unroll
+        for (int zz = 0; zz < 2; ++zz)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 f = __half22float2(__builtin_bit_cast(__half2, q[t][zz][j]));
+                r[zz][2 * j] = f.x;
+                r[zz][2 * j + 1] = f.y;
+            }
+#pragma unroll
+        for (int f = 0; f < kFeats; ++f) {
+            float y0 = lerp(lerp(r[0][f], r[0][4 + f], w[t][0]), lerp(r[0][2 + f], r[0][6 + f], w[t][0]), w[t][1]);
+            float y1 = lerp(lerp(r[1][f], r[1][4 + f], w[t][0]), lerp(r[1][2 + f], r[1][6 + f], w[t][0]), w[t][1]);
+            x[2 * t + f] = lerp(y0, y1, w[t][2]);
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // MLP on MFMA.
 // ----------------------------------------------------------------------------
@@ -340,8 +401,8 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
 // ----------------------------------------------------------------------------
 // MODE 0: fused query.  MODE 1: grid stage only (writes the MLP inputs and the
 // clip status).  MODE 2: inference stage only (reads MLP inputs, one MLP).
-template <int FLAV, int L, typename GT, int MODE>
-__global__ __launch_bounds__(kBlock) void nif_query_kernel(FwdArgs A) {
+template <int FLAV, int L, typename GT, int MODE, bool IMG>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void nif_query_kernel(FwdArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int KH1 = 3 * L;  // layer-1 local inputs per half: 3L/2 lookups x 2 latents
     const int lane = threadIdx.x & 63;
@@ -373,6 +434,22 @@ __global__ __launch_bounds__(kBlock) void nif_query_kernel(FwdArgs A) {
     __syncthreads();
 
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        if (MODE == 0 && tile > t_begin) {
+            // ordered queries change MLP at object boundaries: follow the MLP of
+            // the tile's first query (a block-uniform decision)
+            const int64_t q0 = tile * kQueriesPerBlock;
+            const int32_t id0 = A.ids[A.perm ? (int64_t)A.perm[q0] : q0];
+            const int32_t m = id0 >= 0 && id0 < A.num_objects ? A.objs[id0].mlp : blk_mlp;
+            if (m != blk_mlp) {
+                __syncthreads();
+                const uint8_t* src = A.packed + (int64_t)m * A.pack.bytes;
+                const int nvec = (int)(A.pack.bytes / 16);
+                for (int i = threadIdx.x; i < nvec; i += kBlock)
+                    reinterpret_cast<i32x4*>(smem)[i] = reinterpret_cast<const i32x4*>(src)[i];
+                __syncthreads();
+                blk_mlp = m;
+            }
+        }
         const int64_t slot = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
         const bool inb = slot < A.n;
         const int64_t q = inb && A.perm ? (int64_t)A.perm[slot] : slot;  // the query handled here
@@ -409,7 +486,10 @@ __global__ __launch_bounds__(kBlock) void nif_query_kernel(FwdArgs A) {
                 status = clip_normalise(o, d, tm, ob, u);
                 if (status == 1) {
                     mlp = ob.mlp;
-                    encode_half<L, GT>(u, half, (const GLOBAL GT*)(ob.grid), A, xin);
+                    if constexpr (IMG)
+                        encode_half_image<L>(u, half, (const GLOBAL _Float16*)(ob.image), A, xin);
+                    else
+                        encode_half<L, GT>(u, half, (const GLOBAL GT*)(ob.grid), A, xin);
                 }
             }
         }
@@ -459,12 +539,12 @@ __global__ __launch_bounds__(kBlock) void nif_query_kernel(FwdArgs A) {
     }
 }
 
-template <int FLAV, int L, typename GT, int MODE>
+template <int FLAV, int L, typename GT, int MODE, bool IMG>
 static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     FwdArgs a = a0;
     const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
     // persistent-style grid: a few blocks per CU, a multiple of the 8 XCDs
-    int64_t blocks = (int64_t)num_cus * 8;
+    int64_t blocks = (int64_t)num_cus * (a.blocks_per_cu > 0 ? a.blocks_per_cu : 8);
     if (blocks > tiles) blocks = tiles;
     blocks = (blocks + 7) / 8 * 8;
     a.num_tiles = (int32_t)tiles;
@@ -472,22 +552,27 @@ static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     a.xcd_stride = (int32_t)(blocks / 8);
     const size_t lds = MODE == 1 ? 0 : lds_bytes(a.pack);
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE>,
+        hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE, IMG>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((nif_query_kernel<FLAV, L, GT, MODE>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((nif_query_kernel<FLAV, L, GT, MODE, IMG>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
 template <int FLAV, int MODE>
 static hipError_t launch_f(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
+    const bool img = MODE != 2 && grid_dtype == 1 && a.use_image;
     if (levels == 8) {
-        if (grid_dtype == 1) return launch_t<FLAV, 8, _Float16, MODE>(a, num_cus, s);
-        return launch_t<FLAV, 8, float, MODE>(a, num_cus, s);
+        if (grid_dtype == 1)
+            return img ? launch_t<FLAV, 8, _Float16, MODE, true>(a, num_cus, s)
+                       : launch_t<FLAV, 8, _Float16, MODE, false>(a, num_cus, s);
+        return launch_t<FLAV, 8, float, MODE, false>(a, num_cus, s);
     }
-    if (grid_dtype == 1) return launch_t<FLAV, 4, _Float16, MODE>(a, num_cus, s);
-    return launch_t<FLAV, 4, float, MODE>(a, num_cus, s);
+    if (grid_dtype == 1)
+        return img ? launch_t<FLAV, 4, _Float16, MODE, true>(a, num_cus, s)
+                   : launch_t<FLAV, 4, _Float16, MODE, false>(a, num_cus, s);
+    return launch_t<FLAV, 4, float, MODE, false>(a, num_cus, s);
 }
 
 hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
@@ -558,6 +643,38 @@ hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t 
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(init_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, s, grid, grid_dtype, count, seed, obj,
                        amp);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// y-pair query image of a binary16 grid.
+// ----------------------------------------------------------------------------
+int64_t image_table_elems(int32_t N) { return (int64_t)(N + 1) * N * (N + 1) * 4; }
+
+__global__ void build_image_kernel(const uint32_t* __restrict__ grid, uint2* __restrict__ img, int64_t toff_pairs,
+                                   int64_t ioff_entries, int32_t N) {
+    const int64_t N1 = N + 1;
+    const int64_t entries = N1 * N * N1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % N1, r = i / N1;
+        const int64_t y = r % N, z = r / N;
+        const int64_t v = (z * N1 + y) * N1 + x;  // vertex (x, y, z); its two latents are one dword
+        img[ioff_entries + i] = make_uint2(grid[toff_pairs + v], grid[toff_pairs + v + N1]);
+    }
+}
+
+hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
+                              const int32_t* res, int levels, hipStream_t s) {
+    for (int k = 0; k < 3 * levels; ++k) {
+        const int32_t N = res[k % levels];
+        const int64_t entries = (int64_t)(N + 1) * N * (N + 1);
+        const int64_t blocks = (entries + 255) / 256 < 65536 ? (entries + 255) / 256 : 65536;
+        // offsets in latents: the grid's 2 latents per vertex are one dword, an
+        // image entry (4 latents) is 8 bytes
+        hipLaunchKernelGGL(build_image_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const uint32_t*>(grid), reinterpret_cast<uint2*>(image), toff[k] / 2,
+                           ioff[k] / 4, N);
+    }
     return hipGetLastError();
 }
 

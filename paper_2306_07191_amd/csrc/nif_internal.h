@@ -21,6 +21,7 @@ struct ObjDev {
     float ext[3];
     int32_t mlp;
     const void* grid;
+    const void* image;  // y-pair query image of a binary16 grid, or null
 };
 
 enum Flavor { kF32 = 0, kF16 = 1, kBF16 = 2, kFP8 = 3 };
@@ -66,6 +67,9 @@ struct FwdArgs {
     int32_t tiles_per_block_num;  // tiles are split evenly: block b gets [b*T/G, (b+1)*T/G)
     int32_t num_tiles;
     int32_t xcd_stride;           // logical block = (b % 8) * xcd_stride + b / 8
+    int32_t blocks_per_cu;        // persistent grid size per compute unit (0: 8)
+    int32_t use_image;            // gather from the objects' y-pair images
+    int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
 };
 
 struct OrderArgs {
@@ -82,6 +86,10 @@ struct OrderArgs {
     uint32_t* table;       // num_buckets x num_tiles counts, then offsets
     uint32_t* block_sums;
     uint16_t* key;         // bucket of every query
+    uint32_t* fine;        // finer key of every query
+    uint32_t* coarse;      // bucket order (before the window refinement)
+    int32_t fine_bits;
+    int32_t no_refine;     // 1: bucket order only (skip the window sort)
     uint32_t* perm;
 };
 
@@ -99,6 +107,7 @@ struct TrainArgs {
     const int32_t* ids;
     const float* tmax;
     const uint8_t* labels;
+    const float* grad_y;  // upstream dL/dy per query (backward mode) or null
     int64_t n;
     const uint32_t* perm;
     const ObjDev* objs;
@@ -138,6 +147,9 @@ struct TrainArgs {
 };
 
 size_t train_workspace_bytes(int64_t n, int din, int hidden, int64_t P, int64_t* chunk_out);
+size_t calib_workspace_bytes(int64_t n, int din);
+hipError_t launch_calibrate(const FwdArgs& enc, int levels, int grid_dtype, int num_cus, int32_t mlp, const float* W,
+                            int din, int hidden, void* ws, unsigned* amax_host, hipStream_t s);
 hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_t num_obj_of_mlp,
                         const int64_t* words_per_obj, int grid_dtype, int levels, int num_cus, hipStream_t s);
 
@@ -157,6 +169,14 @@ size_t lds_bytes(const PackInfo& p);
 hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s);
 hipError_t launch_encode(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s);
 hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hipStream_t s);
+// y-pair query image of a binary16 grid: for every table (N cells per axis),
+// entry (x, y, z), x, z in [0, N], y in [0, N-1], holds the two latents of
+// vertex (x, y, z) then those of (x, y+1, z); entries are x-fastest, so one
+// 16-byte load at entry (x, y, z) returns the four corners (x..x+1, y..y+1) of
+// a cell face.
+int64_t image_table_elems(int32_t N);
+hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
+                              const int32_t* res, int levels, hipStream_t s);
 hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
                             hipStream_t s);
 

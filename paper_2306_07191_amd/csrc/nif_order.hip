@@ -12,8 +12,10 @@
 // (2) exclusive scan of that table in bucket-major order; (3) each block ranks
 // its queries inside (bucket, tile) with LDS counters and scatters
 // perm[offset + rank] = query.  The order inside a (bucket, tile) cell depends
-// on LDS atomic arrival; the outputs do not, because every query is computed
-// independently of its neighbours.
+// on LDS atomic arrival; (4) every window of 4096 consecutive entries is then
+// sorted by a finer key (8 Morton bits per axis) in LDS, so that a wave's 32
+// queries cover a few finest-level cells.  The outputs do not depend on the
+// order, because every query is computed independently of its neighbours.
 #include "nif_device.h"
 #include "nif_internal.h"
 
@@ -37,13 +39,18 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
-__device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i) {
-    const uint32_t cells = 1u << A.bits;
+// Bucket (object, coarse Morton code) of query i; *fine receives the finer key
+// (object, Morton code with fine_bits per axis), 0xffffffff for a miss.  The
+// coarse code is a prefix of the fine one, so ordering by the fine key refines
+// the bucket order.
+__device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i, uint32_t* fine) {
+    const uint32_t cells = 1u << A.fine_bits;
     const float* r = A.rays + i * 6;
     float o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
     const float tm = A.tmax[i];
     const int32_t id = A.ids[i];
     uint32_t b = A.num_buckets - 1;
+    *fine = 0xffffffffu;
     if (valid_query(o, d, tm, id, A.num_objects)) {
         float u[3][3];
         const ObjDev ob = A.objs[id];
@@ -54,7 +61,9 @@ __device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i) {
                 uint32_t v = (uint32_t)(u[0][a] * (float)cells);  // u in [0, 1]
                 c[a] = v < cells ? v : cells - 1;
             }
-            b = ((uint32_t)id << (3 * A.bits)) | spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+            const uint32_t m = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+            *fine = ((uint32_t)id << (3 * A.fine_bits)) | m;
+            b = ((uint32_t)id << (3 * A.bits)) | (m >> (3 * (A.fine_bits - A.bits)));
         }
     }
     return b;
@@ -68,8 +77,10 @@ __global__ __launch_bounds__(256) void order_count_kernel(OrderArgs A) {
     __syncthreads();
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
     for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
-        const uint32_t b = order_key(A, i);
+        uint32_t fine;
+        const uint32_t b = order_key(A, i, &fine);
         A.key[i] = (uint16_t)b;
+        A.fine[i] = fine;
         atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
@@ -86,8 +97,40 @@ __global__ __launch_bounds__(256) void order_rank_kernel(OrderArgs A) {
     for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
         const uint32_t b = A.key[i];
         const uint32_t r = atomicAdd(&cur[b], 1u);
-        A.perm[A.table[(int64_t)b * A.num_tiles + blockIdx.x] + r] = (uint32_t)i;
+        A.coarse[A.table[(int64_t)b * A.num_tiles + blockIdx.x] + r] = (uint32_t)i;
     }
+}
+
+// Pass 4: sort each window of kRefine consecutive entries of the coarse order
+// by (fine key, query) with a bitonic network in LDS.
+constexpr int kRefine = 4096;
+__global__ __launch_bounds__(256) void order_refine_kernel(OrderArgs A) {
+    __shared__ uint64_t kv[kRefine];
+    const int64_t w0 = (int64_t)blockIdx.x * kRefine;
+    const int cnt = (int)(A.n - w0 < kRefine ? A.n - w0 : kRefine);
+    for (int i = threadIdx.x; i < kRefine; i += blockDim.x) {
+        uint64_t v = ~0ull;  // padding sorts last
+        if (i < cnt) {
+            const uint32_t q = A.coarse[w0 + i];
+            v = ((uint64_t)A.fine[q] << 32) | q;
+        }
+        kv[i] = v;
+    }
+    __syncthreads();
+    for (int k = 2; k <= kRefine; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < kRefine; i += blockDim.x) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const uint64_t a = kv[i], b = kv[p];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) { kv[i] = b; kv[p] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) A.perm[w0 + i] = (uint32_t)(kv[i] & 0xffffffffu);
 }
 
 // Sum of the counts of one scan tile.
@@ -178,11 +221,20 @@ int order_bits(int32_t num_objects) {
     return bits;
 }
 
+// Fine key: object id and up to 8 Morton bits per axis in 31 bits, so that no
+// hit's key equals the miss key 0xffffffff.
+static int fine_bits(int32_t num_objects) {
+    int ob = 0;
+    while (((int64_t)1 << ob) < num_objects) ++ob;
+    int fb = (31 - ob) / 3;
+    return fb > 8 ? 8 : fb;
+}
+
 static constexpr int64_t kOrderTile = 8192;  // queries per block
 
 struct OrderLayout {
     int64_t nb, tiles, table, scan_tiles;
-    size_t off_table, off_sums, off_key, off_perm, total;
+    size_t off_table, off_sums, off_key, off_fine, off_coarse, off_perm, total;
 };
 
 static OrderLayout order_layout(int64_t n, int32_t num_objects) {
@@ -196,7 +248,9 @@ static OrderLayout order_layout(int64_t n, int32_t num_objects) {
     L.off_table = 0;
     L.off_sums = al(L.table * 4);
     L.off_key = L.off_sums + al(L.scan_tiles * 4);
-    L.off_perm = L.off_key + al(n * 2);
+    L.off_fine = L.off_key + al(n * 2);
+    L.off_coarse = L.off_fine + al(n * 4);
+    L.off_perm = L.off_coarse + al(n * 4);
     L.total = L.off_perm + al(n * 4);
     return L;
 }
@@ -211,6 +265,8 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     const OrderLayout L = order_layout(A.n, A.num_objects);
     if (L.scan_tiles > kScanTile) return hipErrorInvalidValue;  // > 16M table entries
     A.bits = order_bits(A.num_objects);
+    A.fine_bits = fine_bits(A.num_objects);
+    if (A.fine_bits < A.bits) A.fine_bits = A.bits;
     A.num_buckets = (uint32_t)L.nb;
     A.tile = kOrderTile;
     A.num_tiles = L.tiles;
@@ -218,6 +274,8 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     A.table = reinterpret_cast<uint32_t*>(p + L.off_table);
     A.block_sums = reinterpret_cast<uint32_t*>(p + L.off_sums);
     A.key = reinterpret_cast<uint16_t*>(p + L.off_key);
+    A.fine = reinterpret_cast<uint32_t*>(p + L.off_fine);
+    A.coarse = reinterpret_cast<uint32_t*>(p + L.off_coarse);
     if (!A.perm) A.perm = reinterpret_cast<uint32_t*>(p + L.off_perm);  // else the caller's buffer
     *perm_out = A.perm;
     const size_t lds = (size_t)L.nb * 4;
@@ -229,7 +287,13 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, A.block_sums, L.scan_tiles);
     hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)L.scan_tiles), dim3(kScanThreads), 0, s, A.table, L.table,
                        A.block_sums);
+    if (A.no_refine) {
+        A.coarse = A.perm;  // the bucket order is the result
+        hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
+    hipLaunchKernelGGL(order_refine_kernel, dim3((unsigned)((A.n + kRefine - 1) / kRefine)), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@
 //   L = (1/B) sum [softplus(z) - t z],   dL/dz = (sigmoid(z) - t) / B.
 // Everything below accumulates the unscaled (sigmoid(z) - t); the 1/B factor
 // is applied when the gradients are consumed (B is only known on the device).
+// Upstream-gradient mode (grad_y set, no labels, no Adam): dL/dz = g_y
+// sigmoid(z) (1 - sigmoid(z)) for a given dL/dy per query, and no 1/B factor.
 //
 // Kernels:
 //  T1 train_fb_kernel: per wave 32 queries, two lanes per query (the query
@@ -212,10 +214,14 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
         const float z = zp + __shfl_xor(zp, 32);
         float dz = 0.0f, lterm = 0.0f;
         if (active) {
-            const float t = A.labels[q] ? 1.0f : 0.0f;
             const float sg = 1.0f / (1.0f + expf(-z));
-            dz = sg - t;
-            lterm = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))) - t * z;
+            if (A.grad_y) {
+                dz = A.grad_y[q] * (sg * (1.0f - sg));
+            } else {
+                const float t = A.labels[q] ? 1.0f : 0.0f;
+                dz = sg - t;
+                lterm = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))) - t * z;
+            }
         }
         if (inb && half == 0) A.dz[slot] = dz;
         {
@@ -399,7 +405,7 @@ __global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t words) {
 // touched vertices and clear the bitmap (the caller owns and clears the gradient).
 __global__ void scale_grid_grad_kernel(TrainArgs A, int32_t obj, int64_t words) {
     const unsigned B = *A.count;
-    const float inv = B ? 1.0f / (float)B : 0.0f;
+    const float inv = A.grad_y ? 1.0f : B ? 1.0f / (float)B : 0.0f;
     float* gg = A.grid_grad[obj];
     uint32_t* tb = A.touched[obj];
     for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words; wi += (int64_t)gridDim.x * blockDim.x) {
@@ -418,7 +424,7 @@ __global__ void scale_grid_grad_kernel(TrainArgs A, int32_t obj, int64_t words) 
 
 __global__ void mlp_grad_only_kernel(TrainArgs A) {
     const unsigned B = *A.count;
-    const float inv = B ? 1.0f / (float)B : 0.0f;
+    const float inv = A.grad_y ? 1.0f : B ? 1.0f / (float)B : 0.0f;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.P; k += (int64_t)gridDim.x * blockDim.x)
         if (A.grad_out) A.grad_out[k] = A.dw[k] * inv;
     if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) *A.loss_out = B ? *A.loss_sum * inv : 0.0f;

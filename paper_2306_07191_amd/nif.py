@@ -17,15 +17,17 @@ LIB_PATH = os.path.join(_PKG, "libnif.so")
 
 NIF_F32, NIF_F16, NIF_BF16, NIF_FP8_E4M3 = 0, 1, 2, 3
 NIF_OPT_ORDER = 1
+NIF_OPT_GRID_IMAGE = 2
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
 STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3: "NIF_ERR_WORKSPACE",
           -4: "NIF_ERR_HIP", -5: "NIF_ERR_STATE"}
 
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
-           "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_calibrate_fp8", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
            "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
-           "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_touched_bytes",
+           "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
+           "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
            "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit",
            "nif_last_error", "nif_version"]
 
@@ -63,6 +65,7 @@ def lib():
             "nif_set_object": (i32, [vp, i32, vp, vp, i32]),
             "nif_set_mlp": (i32, [vp, i32, vp]),
             "nif_set_fp8_scales": (i32, [vp, i32, vp]),
+            "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
             "nif_prepare": (i32, [vp, i32, vp]),
             "nif_workspace_bytes": (sz, [vp, i64, i32]),
@@ -71,11 +74,17 @@ def lib():
             "nif_order": (i32, [vp, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_query_ordered": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp]),
             "nif_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+            "nif_plan_workspace_bytes": (sz, [vp, i64]),
+            "nif_plan_create": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, C.c_char_p, vp, vp]),
+            "nif_plan_launch": (i32, [vp, vp]),
+            "nif_plan_tuning": (i32, [vp, vp, sz]),
+            "nif_plan_destroy": (None, [vp]),
             "nif_encode": (i32, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "nif_mlp": (i32, [vp, i32, i32, vp, i64, vp, vp]),
             "nif_set_object_train": (i32, [vp, i32, vp, vp, vp, vp]),
             "nif_set_mlp_train": (i32, [vp, i32, vp, vp]),
             "nif_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
+            "nif_backward": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_touched_bytes": (sz, [vp]),
             "nif_bvh_create": (i32, [vp, i64, vp]),
             "nif_bvh_destroy": (None, [vp]),
@@ -138,6 +147,46 @@ class BVH:
             pass
 
 
+class Plan:
+    """A tuned, graph-captured query over fixed buffers (see nif_plan_create)."""
+
+    def __init__(self, ctx, rays, ids, tmax, dtype: str = "bf16", out=None, logits=None, tuning: str | None = None):
+        import torch
+        n = ids.shape[0]
+        self.ctx = ctx
+        self.out = torch.empty(n, dtype=torch.float32, device=rays.device) if out is None else out
+        self.logits = logits
+        self.bufs = (rays, ids, tmax)
+        self.ws = torch.empty(max(1, int(lib().nif_plan_workspace_bytes(ctx.h, n))), dtype=torch.uint8,
+                              device=rays.device)
+        h = C.c_void_p()
+        _check(lib().nif_plan_create(ctx.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(self.out),
+                                     _ptr(logits), _ptr(self.ws), self.ws.numel(),
+                                     None if tuning is None else tuning.encode(), _stream(), C.byref(h)),
+               "nif_plan_create")
+        self.h = h
+
+    def launch(self):
+        _check(lib().nif_plan_launch(self.h, _stream()), "nif_plan_launch")
+        return self.out
+
+    def tuning(self) -> str:
+        buf = C.create_string_buffer(256)
+        _check(lib().nif_plan_tuning(self.h, buf, 256), "nif_plan_tuning")
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nif_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A nif_ctx plus the device buffers the caller owns (torch tensors).
 
@@ -165,6 +214,7 @@ class Context:
         self.table_offsets, self.level_res = off, res
         self.grids = [None] * num_objects
         self.mlps = [None] * num_mlps
+        self.mlp_index = np.zeros(num_objects, np.int32)
         self.aabb = np.zeros((num_objects, 6), np.float32)
 
     def close(self):
@@ -188,6 +238,7 @@ class Context:
         a = np.ascontiguousarray(aabb, np.float32).reshape(6)
         self.aabb[k] = a
         self.grids[k] = grid
+        self.mlp_index[k] = mlp
         _check(lib().nif_set_object(self.h, k, a.ctypes.data, _ptr(grid), mlp), "nif_set_object")
 
     def set_mlp(self, m: int, weights):
@@ -197,6 +248,17 @@ class Context:
     def set_fp8_scales(self, m: int, scales):
         s = np.ascontiguousarray(scales, np.float32)
         _check(lib().nif_set_fp8_scales(self.h, m, s.ctypes.data), "nif_set_fp8_scales")
+
+    def calibrate_fp8(self, rays, ids, tmax, mlp: int = 0, ws=None):
+        """Per-layer FP8 scales of MLP `mlp` from the given queries; returns them (s_W then s_x)."""
+        t = self.torch
+        n = ids.shape[0]
+        if ws is None:
+            ws = t.empty(max(1, self.workspace_bytes(n, 2)), dtype=t.uint8, device=self.device)
+        out = np.zeros(2 * self.shape.hidden, np.float32)
+        _check(lib().nif_calibrate_fp8(self.h, mlp, _ptr(rays), _ptr(ids), _ptr(tmax), n, out.ctypes.data, _ptr(ws),
+                                       ws.numel(), _stream()), "nif_calibrate_fp8")
+        return out
 
     def init_grid(self, k: int, seed: int, amp: float = 1e-4):
         _check(lib().nif_init_grid(self.h, k, seed, amp, _stream()), "nif_init_grid")
@@ -263,16 +325,21 @@ class Context:
         return z
 
     # ---- training --------------------------------------------------------
-    def setup_training(self):
-        """Allocate and register zeroed training buffers for every object and MLP."""
+    def setup_training(self, shared: bool = False):
+        """Allocate and register zeroed training buffers for every object and MLP.
+        shared=True registers one set of latent buffers for every object (objects
+        trained one MLP at a time; zero the moments before moving to the next)."""
         t = self.torch
         tb = int(lib().nif_touched_bytes(self.h))
         self.train_bufs = []
         for k in range(self.K):
-            g = t.zeros(self.grid_elems, dtype=t.float32, device=self.device)
-            m = t.zeros_like(g)
-            v = t.zeros_like(g)
-            tch = t.zeros((tb + 3) // 4, dtype=t.int32, device=self.device)
+            if shared and k > 0:
+                g, m, v, tch = self.train_bufs[0]
+            else:
+                g = t.zeros(self.grid_elems, dtype=t.float32, device=self.device)
+                m = t.zeros_like(g)
+                v = t.zeros_like(g)
+                tch = t.zeros((tb + 3) // 4, dtype=t.int32, device=self.device)
             self.train_bufs.append((g, m, v, tch))
             _check(lib().nif_set_object_train(self.h, k, _ptr(g), _ptr(m), _ptr(v), _ptr(tch)),
                    "nif_set_object_train")
@@ -294,3 +361,13 @@ class Context:
         _check(lib().nif_train_step(self.h, mlp, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(labels), n, step,
                                     None if a is None else C.byref(a), _ptr(loss), _ptr(mlp_grad), _ptr(ws),
                                     ws.numel(), _stream()), "nif_train_step")
+
+    def backward(self, rays, ids, tmax, grad_y, mlp: int = 0, mlp_grad=None, ws=None):
+        """dL/dW (into mlp_grad) and dL/dlatent (added to the registered grid gradient
+        buffers) for an upstream gradient grad_y = dL/dvisibility."""
+        t = self.torch
+        n = ids.shape[0]
+        if ws is None:
+            ws = t.empty(max(1, self.workspace_bytes(n, 1)), dtype=t.uint8, device=self.device)
+        _check(lib().nif_backward(self.h, mlp, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(grad_y), n, _ptr(mlp_grad),
+                                  _ptr(ws), ws.numel(), _stream()), "nif_backward")

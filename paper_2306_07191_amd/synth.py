@@ -318,3 +318,12 @@ def multi_workload(n_objects: int = 32, n_rays: int = 4194304, zipf_s: float = 1
     mlps = np.stack([xavier_mlp(FRAME, rng(CFG_MULTI, 3, k)) for k in range(n_objects)])
     return dict(shape=FRAME, tris=meshes if with_mesh else None, tri_counts=tri_counts, aabb=boxes,
                 rays=rays, tmax=tmax, ids=ids, mlps=mlps, mlp_index=np.arange(n_objects, dtype=np.int32))
+
+
+def multi_train_batch(box, obj: int, step: int, n: int = 262144):
+    """Fresh training rays of one object of the multi-object workload: the same
+    radius-3 sphere recipe relative to its box."""
+    box = np.asarray(box, np.float32)
+    ctr = 0.5 * (box[:3].astype(np.float64) + box[3:])
+    half = 0.5 * float((box[3:].astype(np.float64) - box[:3]).max())
+    return rays_sphere_to_box(n, box, rng(CFG_MULTI, 5, obj, step), radius=3.0 * half, center=ctr)

@@ -75,6 +75,9 @@ def test_validation_before_device_work():
         assert L.nif_prepare(h, 0, None) == -5  # object 1 and the MLP are not registered
         sc = np.array([1, 1, 1, 0, 1, 1], np.float32)
         assert L.nif_set_fp8_scales(h, 0, sc.ctypes.data) == -1  # zero scale
+        assert L.nif_calibrate_fp8(h, 1, fake, fake, fake, 10, None, fake, 1 << 30, None) == -1  # MLP out of range
+        assert L.nif_calibrate_fp8(h, 0, None, fake, fake, 10, None, fake, 1 << 30, None) == -1  # NULL rays
+        assert L.nif_calibrate_fp8(h, 0, fake, fake, fake, 10, None, fake, 1 << 30, None) == -5  # MLP not set
         assert L.nif_last_error() != b""
     finally:
         L.nif_destroy(h)

@@ -1,0 +1,73 @@
+"""Batched multi-object form: a tuned, graph-captured query plan over many
+objects of uneven size (Zipf-distributed rays), against the eager query and
+the oracle."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2306_07191_amd import synth as S
+
+from gpu_util import check_outputs, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _multi_tiny(n_objects=8, n_rays=150000):
+    w = S.multi_workload(n_objects=n_objects, n_rays=n_rays)
+    w["shape"] = S.TINY
+    w["mlps"] = np.stack([S.xavier_mlp(S.TINY, S.rng(60, 3, k)) for k in range(n_objects)])
+    return w
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_plan_matches_eager_and_oracle_over_replays(dtype):
+    import torch
+    from paper_2306_07191_amd import nif
+    w = _multi_tiny()
+    ctx, model = make_pair(w, grid_amp=0.5, quant="exact" if dtype == "f32" else dtype)
+    ctx.prepare(dtype)
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    z = torch.empty(ids.shape[0], device="cuda")
+    plan = nif.Plan(ctx, rays, ids, tmax, dtype=dtype, logits=z)
+    tun = json.loads(plan.tuning())
+    assert tun["candidates"] == 10 and tun["order"] in (0, 1, 2) and tun["tuned_us"] > 0
+    torch.cuda.synchronize()
+    check_outputs(plan.out.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64),
+                  model.forward(w["rays"], w["ids"], w["tmax"]), dtype, f"plan {dtype}")
+    g = np.random.default_rng(3)
+    for rep in range(3):
+        # new contents in the same buffers, eager work and a synchronisation between replays
+        p = torch.from_numpy(g.permutation(ids.shape[0])).cuda()
+        r2, i2, t2 = rays[p].clone(), ids[p].clone(), tmax[p].clone()
+        rays.copy_(r2)
+        ids.copy_(i2)
+        tmax.copy_(t2)
+        y_eager = ctx.query(rays, ids, tmax, dtype=dtype)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(plan.out.cpu().numpy(), y_eager.cpu().numpy())
+    # a given schedule skips the tuning and gives the same outputs
+    plan2 = nif.Plan(ctx, rays, ids, tmax, dtype=dtype, tuning='{"order": 0, "blocks_per_cu": 4}')
+    assert json.loads(plan2.tuning())["candidates"] == 0
+    plan2.launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(plan2.out.cpu().numpy(), plan.out.cpu().numpy())
+    plan.close()
+    plan2.close()
+
+
+def test_plan_rejects_bad_arguments():
+    import torch
+    from paper_2306_07191_amd import nif
+    w = _multi_tiny(n_objects=2, n_rays=1000)
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    with pytest.raises(nif.NifError):  # not prepared
+        nif.Plan(ctx, rays, ids, tmax, dtype="bf16")
+    ctx.prepare("bf16")
+    with pytest.raises(nif.NifError):
+        nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning='{"order": 5, "blocks_per_cu": 4}')
+    with pytest.raises(nif.NifError):
+        nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning='{"blocks_per_cu": 4}')

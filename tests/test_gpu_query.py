@@ -257,3 +257,33 @@ def test_gpu_bvh_labels_match_oracle():
     assert agree >= 0.9999
     empty = nif.BVH(np.zeros((0, 9), np.float32))
     assert (empty.anyhit(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy() == 1).all()
+
+
+def test_grid_image_is_bit_identical():
+    """NIF_OPT_GRID_IMAGE gathers from the y-pair image: same lookups, same
+    interpolation order, so features and outputs are bit-identical; it is rebuilt
+    by nif_prepare after the grid changes."""
+    import torch
+    from paper_2306_07191_amd import nif
+    w = S.frame_workload(n_rays=30000, with_mesh=False)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    outs = {}
+    for img in (0, 1):
+        ctx.set_option(nif.NIF_OPT_GRID_IMAGE, img)
+        for dtype in ("f32", "bf16"):
+            outs[img, dtype] = run_query(ctx, w, dtype)
+        ctx.prepare("f32")
+        outs[img, "x"] = ctx.encode(rays, ids, tmax)[0].cpu().numpy()
+    for key in ("f32", "bf16", "x"):
+        np.testing.assert_array_equal(outs[0, key][0] if key != "x" else outs[0, key],
+                                      outs[1, key][0] if key != "x" else outs[1, key])
+    check_outputs(*outs[1, "f32"], model.forward(w["rays"], w["ids"], w["tmax"]), "f32", "image f32")
+    # a changed grid is seen after nif_prepare
+    ctx.init_grid(0, GRID_SEED + 1, 0.5)
+    y_img = run_query(ctx, w, "f32")
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    np.testing.assert_array_equal(y_img[0], run_query(ctx, w, "f32")[0])
+    with pytest.raises(nif.NifError):  # binary32 grids have no image form
+        c2, _ = make_pair(S.tiny_workload(n_rays=10), grid_amp=0.5)
+        c2.set_option(nif.NIF_OPT_GRID_IMAGE, 1)

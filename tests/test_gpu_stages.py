@@ -96,3 +96,27 @@ def test_fp8_exact_when_representable(hidden):
         np.testing.assert_allclose(zr, h @ W32[-sh.width:], rtol=1e-12, atol=1e-12)  # the oracle's emulation is exact here
     mag = np.abs(W[-sh.width:]).sum() * 200.0
     assert np.abs(z - zr).max() <= 64 * 2.0 ** -24 * mag, np.abs(z - zr).max()
+
+
+@pytest.mark.parametrize("shape_name", ["tiny", "frame"])
+def test_fp8_calibration_matches_oracle(shape_name):
+    """nif_calibrate_fp8 (binary32 encode and layers) vs the oracle's binary64 maxima,
+    on the calibration set of the frame scene (its first 65,536 queries)."""
+    import torch
+    if shape_name == "tiny":
+        w = S.tiny_workload(n_rays=4096)
+    else:
+        w = S.frame_workload(n_rays=65536, with_mesh=False)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    got = ctx.calibrate_fp8(rays, ids, tmax, mlp=0).astype(np.float64)
+    ref = model.fp8_calibrate(w["rays"], w["ids"], w["tmax"], mlp=0)
+    H = w["shape"].hidden
+    # weight maxima are exact; activation maxima carry binary32 accumulation error
+    np.testing.assert_array_equal(got[:H], ref[:H].astype(np.float32))
+    np.testing.assert_allclose(got[H:], ref[H:], rtol=1e-5)
+    # n = 0: unit activation scales
+    e = torch.empty(0, device="cuda")
+    got0 = ctx.calibrate_fp8(e.view(0, 6), e.int(), e, mlp=0)
+    assert (got0[H:] == 1.0).all()

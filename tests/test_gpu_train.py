@@ -144,3 +144,45 @@ def test_frame_batch_gradients_sampled():
     assert np.linalg.norm(err) <= 1e-4 * np.linalg.norm(ref) and err.max() <= 1e-3 * np.abs(ref).max()
     del ctx
     torch.cuda.empty_cache()
+
+
+def test_backward_upstream_gradient_matches_oracle():
+    """nif_backward: gradients of sum_i c_i y_i vs the oracle's binary64 chain rule."""
+    import torch
+    w = _tiny_labelled()
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    ctx.setup_training()
+    c = np.random.default_rng(12).normal(size=w["ids"].shape[0]).astype(np.float32)
+    rays, ids, tmax = _cuda(w, "rays", "ids", "tmax")
+    g = torch.zeros(ctx.mlp_params, device="cuda")
+    ctx.backward(rays, ids, tmax, torch.from_numpy(c).cuda(), mlp_grad=g)
+    torch.cuda.synchronize()
+    B, gW, gx = model.backward_given(w["rays"], w["ids"], w["tmax"], c.astype(np.float64))
+    _grad_close(g.cpu().numpy().astype(np.float64), gW[0])
+    gg64 = model.grid_grad_dense(0, w["rays"], w["ids"], w["tmax"], gx)
+    _grad_close(ctx.train_bufs[0][0].cpu().numpy().astype(np.float64), gg64)
+    assert (ctx.train_bufs[0][3].cpu().numpy() == 0).all()
+
+
+def test_autograd_function():
+    """torch.autograd through the query: weight and latent gradients of sum_i c_i y_i."""
+    import torch
+    from paper_2306_07191_amd.autograd import visibility
+    w = _tiny_labelled()
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.setup_training()
+    ctx.mlps[0].requires_grad_(True)
+    ctx.grids[0].requires_grad_(True)
+    rays, ids, tmax = _cuda(w, "rays", "ids", "tmax")
+    c = np.random.default_rng(13).normal(size=w["ids"].shape[0]).astype(np.float32)
+    y = visibility(ctx, rays, ids, tmax)
+    ref = model.forward(w["rays"], w["ids"], w["tmax"])
+    hit = ref["status"] == 1
+    yc = y.detach().cpu().numpy().astype(np.float64)
+    assert (np.abs(yc[hit] - ref["y"][hit]) <= 1e-5 * ref["y"][hit]).all()
+    (y * torch.from_numpy(c).cuda()).sum().backward()
+    B, gW, gx = model.backward_given(w["rays"], w["ids"], w["tmax"], c.astype(np.float64))
+    _grad_close(ctx.mlps[0].grad.cpu().numpy().astype(np.float64), gW[0])
+    gg64 = model.grid_grad_dense(0, w["rays"], w["ids"], w["tmax"], gx)
+    _grad_close(ctx.grids[0].grad.cpu().numpy().astype(np.float64), gg64)
