@@ -127,12 +127,14 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * (object, Morton code of the AABB entry point) so that a wave's gathers share
  * cache lines and waves use one MLP: 0 never, 1 always, 2 (default) when
  * n >= 65536.  Changes nif_workspace_bytes.
- * NIF_OPT_GRID_IMAGE (binary16 grids only): 1 = nif_prepare also builds, for
- * every object, a context-owned query image of its grid in which the four
- * latent pairs of a cell face (x..x+1, y..y+1) are one 16-byte span, halving
- * the gathers of a lookup; it costs twice the grid's memory per object and is
- * rebuilt by every nif_prepare.  Outputs are bit-identical.  0 (default) =
- * gather from the grids. */
+ * NIF_OPT_GRID_IMAGE (binary16 grids only): 1 (default for binary16 grids) =
+ * nif_prepare also builds, for every object, a context-owned query image of
+ * its grid in which the four latent pairs of a cell face (x..x+1, y..y+1) are
+ * one 16-byte span, halving the gathers of a lookup; it costs twice the grid's
+ * memory per object and is rebuilt by every nif_prepare.  Outputs are
+ * bit-identical.  0 = gather from the grids (and, when ordering, also sort
+ * each 4,096-query window by an 8-bit-per-axis Morton key, which pays off
+ * only without the image). */
 enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2 };
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 

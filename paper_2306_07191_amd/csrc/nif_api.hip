@@ -145,6 +145,7 @@ extern "C" nif_status nif_create(const nif_model_desc* desc, int32_t num_objects
     }
     c->ioff[3 * d.levels] = o;
     c->P = (int64_t)d.width * c->din + (int64_t)(d.hidden_layers - 1) * d.width * d.width + d.width;
+    c->image_mode = d.grid_dtype == NIF_F16 ? 1 : 0;
     c->objs.resize(num_objects);
     c->masters.assign(num_mlps, nullptr);
     c->fp8.resize(num_mlps);
@@ -380,7 +381,7 @@ extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, co
     if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
     const uint32_t* perm = nullptr;
     if (need > 0) {
-        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream);
+        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, !c->image_mode);
         if (st != NIF_OK) return st;
     }
     return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream);
@@ -399,7 +400,7 @@ extern "C" nif_status nif_order(nif_ctx* c, const float* rays, const int32_t* id
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
     const uint32_t* p = nullptr;
-    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream);
+    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, !c->image_mode);
 }
 
 extern "C" nif_status nif_query_ordered(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids,

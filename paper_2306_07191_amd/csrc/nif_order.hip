@@ -14,8 +14,10 @@
 // perm[offset + rank] = query.  The order inside a (bucket, tile) cell depends
 // on LDS atomic arrival; (4) every window of 4096 consecutive entries is then
 // sorted by a finer key (8 Morton bits per axis) in LDS, so that a wave's 32
-// queries cover a few finest-level cells.  The outputs do not depend on the
+// queries cover a few finest-level cells (ties keep the bucket order).  The outputs do not depend on the
 // order, because every query is computed independently of its neighbours.
+#include <rocprim/block/block_radix_sort.hpp>
+
 #include "nif_device.h"
 #include "nif_internal.h"
 
@@ -71,7 +73,8 @@ __device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i, uin
 
 // Pass 1: bucket of every query of the block's tile, counted in LDS; the
 // non-zero counts go to table[bucket * num_tiles + tile] (the table is zeroed).
-__global__ __launch_bounds__(256) void order_count_kernel(OrderArgs A) {
+constexpr int kOrderThreads = 1024;
+__global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A) {
     extern __shared__ uint32_t cnt[];
     for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cnt[k] = 0;
     __syncthreads();
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(256) void order_count_kernel(OrderArgs A) {
         uint32_t fine;
         const uint32_t b = order_key(A, i, &fine);
         A.key[i] = (uint16_t)b;
-        A.fine[i] = fine;
+        if (!A.no_refine) A.fine[i] = fine;
         atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void order_count_kernel(OrderArgs A) {
 }
 
 // Pass 3: rank inside (bucket, tile) with an LDS counter; scatter.
-__global__ __launch_bounds__(256) void order_rank_kernel(OrderArgs A) {
+__global__ __launch_bounds__(kOrderThreads) void order_rank_kernel(OrderArgs A) {
     extern __shared__ uint32_t cur[];
     for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cur[k] = 0;
     __syncthreads();
@@ -101,36 +104,67 @@ __global__ __launch_bounds__(256) void order_rank_kernel(OrderArgs A) {
     }
 }
 
-// Pass 4: sort each window of kRefine consecutive entries of the coarse order
-// by (fine key, query) with a bitonic network in LDS.
-constexpr int kRefine = 4096;
-__global__ __launch_bounds__(256) void order_refine_kernel(OrderArgs A) {
-    __shared__ uint64_t kv[kRefine];
+// Pass 4: sort each window of kRefine consecutive entries of the bucket order
+// by the finer key (object, 8 Morton bits per axis).  The window holds one or a
+// few bucket runs, so its keys span a small range: keys are taken relative to
+// the window's minimum and radix-sorted (rocPRIM block radix sort, stable) over
+// only the bits that range needs.
+constexpr int kRefineThreads = 256;
+constexpr int kRefineItems = 16;
+constexpr int kRefine = kRefineThreads * kRefineItems;
+using RefineSort = rocprim::block_radix_sort<uint32_t, kRefineThreads, kRefineItems, uint32_t>;
+
+__global__ __launch_bounds__(kRefineThreads) void order_refine_kernel(OrderArgs A) {
+    __shared__ typename RefineSort::storage_type storage;
+    __shared__ uint32_t red_min[kRefineThreads / 64], red_max[kRefineThreads / 64];
     const int64_t w0 = (int64_t)blockIdx.x * kRefine;
     const int cnt = (int)(A.n - w0 < kRefine ? A.n - w0 : kRefine);
-    for (int i = threadIdx.x; i < kRefine; i += blockDim.x) {
-        uint64_t v = ~0ull;  // padding sorts last
+    uint32_t key[kRefineItems], val[kRefineItems];
+    uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+    for (int j = 0; j < kRefineItems; ++j) {
+        const int i = threadIdx.x * kRefineItems + j;  // blocked arrangement
+        key[j] = 0xffffffffu;
+        val[j] = 0xffffffffu;
         if (i < cnt) {
-            const uint32_t q = A.coarse[w0 + i];
-            v = ((uint64_t)A.fine[q] << 32) | q;
+            val[j] = A.coarse[w0 + i];
+            key[j] = A.fine[val[j]];
+            mn = key[j] < mn ? key[j] : mn;
+            mx = key[j] > mx ? key[j] : mx;
         }
-        kv[i] = v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t a = __shfl_xor(mn, off), b = __shfl_xor(mx, off);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red_min[threadIdx.x >> 6] = mn;
+        red_max[threadIdx.x >> 6] = mx;
     }
     __syncthreads();
-    for (int k = 2; k <= kRefine; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < kRefine; i += blockDim.x) {
-                const int p = i ^ j;
-                if (p > i) {
-                    const uint64_t a = kv[i], b = kv[p];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) { kv[i] = b; kv[p] = a; }
-                }
-            }
-            __syncthreads();
-        }
+    mn = red_min[0];
+    mx = red_max[0];
+#pragma unroll
+    for (int wv = 1; wv < kRefineThreads / 64; ++wv) {
+        mn = red_min[wv] < mn ? red_min[wv] : mn;
+        mx = red_max[wv] > mx ? red_max[wv] : mx;
     }
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) A.perm[w0 + i] = (uint32_t)(kv[i] & 0xffffffffu);
+    const uint32_t range = mx - mn;  // valid keys map to [0, range]; padding stays 0xffffffff
+    const int bits = range == 0u ? 0 : 32 - __builtin_clz(range);
+    if (bits > 0) {
+#pragma unroll
+        for (int j = 0; j < kRefineItems; ++j)
+            if (threadIdx.x * kRefineItems + j < cnt) key[j] -= mn;
+        // padding keys (all ones) are >= every valid key in the low `bits` bits;
+        // on a tie the stable sort keeps the padding, which comes last, last
+        RefineSort().sort(key, val, storage, 0, (unsigned)bits);
+    }
+#pragma unroll
+    for (int j = 0; j < kRefineItems; ++j) {
+        const int i = threadIdx.x * kRefineItems + j;
+        if (i < cnt) A.perm[w0 + i] = val[j];
+    }
 }
 
 // Sum of the counts of one scan tile.
@@ -213,8 +247,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* hist,
     }
 }
 
-// Buckets: (object, Morton code with `bits` per axis), at most 4096 plus one
-// for misses and invalid queries, so that a block's counters fit in LDS.
+
 int order_bits(int32_t num_objects) {
     int bits = 4;
     while (bits > 0 && ((int64_t)num_objects << (3 * bits)) > 4096) --bits;
@@ -281,7 +314,7 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     const size_t lds = (size_t)L.nb * 4;
     const unsigned fb = (unsigned)((L.table + 255) / 256 < 4096 ? (L.table + 255) / 256 : 4096);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(fb), dim3(256), 0, s, A.table, L.table, 0u);
-    hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
+    hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)L.scan_tiles), dim3(kScanThreads), 0, s, A.table, L.table,
                        A.block_sums);
     hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, A.block_sums, L.scan_tiles);
@@ -289,10 +322,10 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
                        A.block_sums);
     if (A.no_refine) {
         A.coarse = A.perm;  // the bucket order is the result
-        hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
+        hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(256), lds, s, A);
+    hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
     hipLaunchKernelGGL(order_refine_kernel, dim3((unsigned)((A.n + kRefine - 1) / kRefine)), dim3(256), 0, s, A);
     return hipGetLastError();
 }

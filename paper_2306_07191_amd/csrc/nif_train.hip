@@ -86,6 +86,47 @@ __global__ void fill_zero_kernel(uint32_t* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
+// Gradient scatter of one interpolation corner: adds (v0, v1) to the two
+// latents at gg + el and marks the vertex in the touched bitmap.  Lanes with
+// gg == nullptr take no part.  Queries are ordered, so at the coarse levels
+// many lanes of a wave hit the same vertex, and same-address atomics serialise
+// in the L2: lanes are first grouped by (table, element) address, leader first,
+// for up to kPeel groups, each group summed across the wave and added by its
+// leader; lanes left after that add their own values.
+constexpr int kPeel = 6;
+
+__device__ __forceinline__ void add_and_mark(float* p, uint32_t* tb, int64_t vtx, float s0, float s1) {
+    if (s0 != 0.0f) unsafeAtomicAdd(p, s0);
+    if (s1 != 0.0f) unsafeAtomicAdd(p + 1, s1);
+    const uint32_t bit = 1u << (vtx & 31);
+    uint32_t* word = tb + (vtx >> 5);
+    if (!(__atomic_load_n(word, __ATOMIC_RELAXED) & bit)) atomicOr(word, bit);
+}
+
+__device__ __forceinline__ void scatter_corner(float* gg, uint32_t* tb, int64_t el, float v0, float v1, int lane) {
+    const uintptr_t addr = gg ? (uintptr_t)(gg + el) : 0;
+    uint64_t pend = __ballot(gg != nullptr);
+    for (int it = 0; it < kPeel && pend; ++it) {
+        const int leader = __builtin_ctzll(pend);
+        const uintptr_t la = (uintptr_t)__shfl((long long)addr, leader);
+        const bool mine = ((pend >> lane) & 1) && addr == la;
+        const uint64_t grp = __ballot(mine);
+        float s0 = v0, s1 = v1;
+        if (__popcll(grp) > 1) {  // wave-uniform
+            s0 = mine ? v0 : 0.0f;
+            s1 = mine ? v1 : 0.0f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                s0 += __shfl_xor(s0, off);
+                s1 += __shfl_xor(s1, off);
+            }
+        }
+        if (lane == leader) add_and_mark(gg + el, tb, el / kFeats, s0, s1);
+        pend &= ~grp;
+    }
+    if ((pend >> lane) & 1) add_and_mark(gg + el, tb, el / kFeats, v0, v1);
+}
+
 // ---------------------------------------------------------------------------
 // T1
 // ---------------------------------------------------------------------------
@@ -259,10 +300,10 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
             }
         }
         // acc now holds g_x for this half's local features c = 16 mt + r < KH1
-        if (!active) continue;
         // ---- scatter into the grid gradient; mark touched vertices
-        float* gg = A.grid_grad[id];
-        uint32_t* tb = A.touched[id];
+        if (!__ballot(active)) continue;  // wave-uniform
+        float* gg = active ? A.grid_grad[id] : nullptr;
+        uint32_t* tb = active ? A.touched[id] : nullptr;
 #pragma unroll
         for (int t = 0; t < NL; ++t) {
             int64_t base;
@@ -276,14 +317,7 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
                 const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
                 const float wt = (bx ? w[0] : 1.0f - w[0]) * (by ? w[1] : 1.0f - w[1]) * (bz ? w[2] : 1.0f - w[2]);
                 const int64_t el = base + (bz ? sz : 0) + (by ? sy : 0) + bx * kFeats;
-                if (wt != 0.0f) {
-                    unsafeAtomicAdd(gg + el, wt * g0);
-                    unsafeAtomicAdd(gg + el + 1, wt * g1);
-                }
-                const int64_t vtx = el / kFeats;
-                const uint32_t bit = 1u << (vtx & 31);
-                uint32_t* word = tb + (vtx >> 5);
-                if (!(__atomic_load_n(word, __ATOMIC_RELAXED) & bit)) atomicOr(word, bit);
+                scatter_corner(gg, tb, el, wt * g0, wt * g1, lane);
             }
         }
     }
