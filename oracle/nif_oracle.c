@@ -510,10 +510,12 @@ static double acc_drift(int quant, int K, const double* absprod, double mag) {
     return 7.0 * ldexp(1.0, -13) * top8_sum(absprod, K) + gamma32(8) * mag;
 }
 
-/* gmax[i] = largest |latent| among the corners of feature i: the device
- * interpolates in binary32 with three nested linear interpolations, each at
- * most three roundings of values bounded by gmax, so its x[i] is within
- * 9 u gmax of the exact interpolant.
+/* gmax[i] = largest |latent| among the corners of feature i.  A binary32
+ * evaluation of the trilinear interpolant is within 16 u gmax of the exact
+ * value whether it nests linear interpolations (three levels of at most three
+ * roundings of values bounded by gmax: 9 u) or sums the eight corner terms
+ * (weights products of three factors 1 - w or w, each within u, formed with
+ * two roundings: 5 u; an eight-term sum in any order: 8 u; 13 u in all).
  *
  * Three quantities are propagated per element:
  *   eps  worst-case bound on |device value - exact value| (Higham-style,
@@ -538,7 +540,7 @@ static void mlp_forward(const orc_model* m, const double* W, const double* sc, c
     int K = Din;
     const double s0 = (q == 3) ? sc[H] : 1.0;
     for (int i = 0; i < Din; ++i) {
-        dr[i] = gmax ? 9.0 * U32 * gmax[i] : 0.0;
+        dr[i] = gmax ? 16.0 * U32 * gmax[i] : 0.0;
         hq[i] = q ? qact(x[i], q, s0) : x[i];
         eps[i] = (q ? half_q(x[i], q, s0) : 0.0) + dr[i];
         flip[0][i] = 0.0;

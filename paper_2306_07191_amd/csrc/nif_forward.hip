@@ -69,151 +69,167 @@ size_t lds_bytes(const PackInfo& p) { return (size_t)p.bytes; }
 
 #define GLOBAL __attribute__((address_space(1)))
 
-// Two adjacent vertices (x and x+1) of one grid row, two latents each.
-template <typename GT> struct Row;
-template <> struct Row<_Float16> {
-    float v[4];  // v[0], v[1]: vertex x; v[2], v[3]: vertex x+1
-    __device__ __forceinline__ void load(const GLOBAL _Float16* p) {
-        // two dword reads of adjacent vertices; the backend merges them into one
-        // dword-aligned 8-byte load
-        const GLOBAL unsigned* q = reinterpret_cast<const GLOBAL unsigned*>(p);
-        const unsigned wx = q[0], wy = q[1];
-        __half2 a = __builtin_bit_cast(__half2, wx), b = __builtin_bit_cast(__half2, wy);
-        float2 fa = __half22float2(a), fb = __half22float2(b);
-        v[0] = fa.x; v[1] = fa.y; v[2] = fb.x; v[3] = fb.y;
-    }
-};
-template <> struct Row<float> {
-    float v[4];
-    __device__ __forceinline__ void load(const GLOBAL float* p) {
-        v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; v[3] = p[3];  // one 16-byte load
-    }
-};
+typedef _Float16 f16x2v __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ float lerp(float a, float b, float t) { return a + t * (b - a); }
-
-// Cell and in-cell weight of coordinate u at resolution N: s = u N (one
-// binary32 product), cell = min(floor(s), N - 1), w = s - cell (exact).  No
-// contraction: fusing u N - cell into one FMA would use the unrounded product
-// for w while the cell came from the rounded one.
-__device__ __forceinline__ int cell_coord(float u, float fN, int N, float& w) {
+// Cell and in-cell weight of coordinate u in [0, 1] at resolution N: s = u N
+// (one binary32 product), cell = min(floor(s), N - 1), w = s - cell (exact).
+// No contraction: fusing u N - cell into one FMA would use the unrounded
+// product for w while the cell came from the rounded one.
+__device__ __forceinline__ uint32_t cell_coord(float u, float fN, uint32_t N, float& w) {
 #pragma clang fp contract(off)
     float s = u * fN;
-    float cf = floorf(s);
-    cf = cf > (float)(N - 1) ? (float)(N - 1) : cf;
+    float cf = fminf(floorf(s), (float)(N - 1));
     w = s - cf;
-    int ci = (int)cf;
-    return ci < 0 ? 0 : (ci > N - 1 ? N - 1 : ci);  // u is in [0, 1]; kept for safety
+    const uint32_t ci = (uint32_t)(int)cf;
+    return ci < N - 1 ? ci : N - 1;  // u is in [0, 1]; kept for safety
 }
 
-// Encode the lookups of lane half `half`: NL = 3L/2 lookups, 2 features each,
-// local feature c = 2 t + f.
+// Trilinear weights of the eight cell corners, corner b = bx + 2 by + 4 bz:
+// prod over axes of (b_a ? w_a : 1 - w_a), formed as ((x y) z).
+__device__ __forceinline__ void corner_weights(const float w[3], float cw[8]) {
+    const float x0 = 1.0f - w[0], y0 = 1.0f - w[1], z0 = 1.0f - w[2];
+    const float a00 = x0 * y0, a10 = w[0] * y0, a01 = x0 * w[1], a11 = w[0] * w[1];
+    cw[0] = a00 * z0;
+    cw[1] = a10 * z0;
+    cw[2] = a01 * z0;
+    cw[3] = a11 * z0;
+    cw[4] = a00 * w[2];
+    cw[5] = a10 * w[2];
+    cw[6] = a01 * w[2];
+    cw[7] = a11 * w[2];
+}
+
+// Latent pair (f0, f1) of one vertex from a dword of two binary16 values.
+__device__ __forceinline__ f16x2v half_pair(uint32_t d) { return __builtin_bit_cast(f16x2v, d); }
+
+// The interpolated feature pair: sum of corner weight x latent over the
+// corners in order 0..7 (binary32 FMAs; binary16 latents convert exactly).
+__device__ __forceinline__ void interp_pairs(const float cw[8], const f16x2v g[8], float& x0, float& x1) {
+    float s0 = cw[0] * (float)g[0][0], s1 = cw[0] * (float)g[0][1];
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+        s0 = fmaf(cw[c], (float)g[c][0], s0);
+        s1 = fmaf(cw[c], (float)g[c][1], s1);
+    }
+    x0 = s0;
+    x1 = s1;
+}
+
+// Geometry of lookup t of lane half `half`: table k, cell, weights.
+template <int L>
+__device__ __forceinline__ int lookup_cell(const float u[3][3], int half, int t, const FwdArgs& A, uint32_t c[3],
+                                           float w[3]) {
+    constexpr int NL = 3 * L / 2;
+    const int k = half ? NL + t : t;
+    const int e = k / L, l = k % L;
+    const uint32_t N = (uint32_t)A.res[l];
+    const float fN = (float)N;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float ue = e == 0 ? u[0][a] : (e == 1 ? u[1][a] : u[2][a]);
+        c[a] = cell_coord(ue, fN, N, w[a]);
+    }
+    return k;
+}
+
+// Encode the lookups of lane half `half` from the grids: NL = 3L/2 lookups, 2
+// features each, local feature c = 2 t + f.  Rows (x, x+1) of the cell at
+// (y, z), (y+1, z), (y, z+1), (y+1, z+1) are one load each.
 template <int L, typename GT>
 __device__ __forceinline__ void encode_half(const float u[3][3], int half, const GLOBAL GT* grid, const FwdArgs& A,
                                             float* x) {
     constexpr int NL = 3 * L / 2;
-    int64_t base[NL];
+    constexpr int EW = sizeof(GT) == 2 ? 1 : 2;  // dwords per vertex
     float w[NL][3];
-    int32_t stride[NL];
+    uint32_t q[NL][4][2 * EW];
 #pragma unroll
     for (int t = 0; t < NL; ++t) {
-        const int k0 = t, k1 = NL + t;  // lookup index for half 0 / half 1
-        const int e = half ? k1 / L : k0 / L;
-        const int l = half ? k1 % L : k0 % L;
-        const int N = A.res[l];
-        const float fN = (float)N;
-        int c[3];
+        uint32_t c[3];
+        const int k = lookup_cell<L>(u, half, t, A, c, w[t]);
+        const uint32_t N1 = (uint32_t)A.res[k % L] + 1;
+        const uint32_t v = (c[2] * N1 + c[1]) * N1 + c[0];  // < 2^31 for N <= 1024
+        const GLOBAL uint32_t* p = reinterpret_cast<const GLOBAL uint32_t*>(grid + A.toff[k]) + (uint64_t)v * EW;
+        const uint32_t sy = N1 * EW, sz = N1 * N1 * EW;  // in dwords
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float ue = e == 0 ? u[0][a] : (e == 1 ? u[1][a] : u[2][a]);
-            c[a] = cell_coord(ue, fN, N, w[t][a]);
+        for (int r = 0; r < 4; ++r) {
+            const GLOBAL uint32_t* pr = p;
+            if (r & 1) pr += sy;
+            if (r >> 1) pr += sz;
+#pragma unroll
+            for (int j = 0; j < 2 * EW; ++j) q[t][r][j] = pr[j];  // one 8- or 16-byte load
         }
-        const int32_t N1 = N + 1;
-        const int32_t v = (c[2] * N1 + c[1]) * N1 + c[0];
-        base[t] = (half ? A.toff[k1] : A.toff[k0]) + (int64_t)v * kFeats;
-        stride[t] = N1 * kFeats;
-    }
-    Row<GT> r[NL][4];
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-        const GLOBAL GT* p = grid + base[t];
-        const int32_t sy = stride[t];
-        const int64_t sz = (int64_t)sy * (sy / kFeats);
-        r[t][0].load(p);
-        r[t][1].load(p + sy);
-        r[t][2].load(p + sz);
-        r[t][3].load(p + sz + sy);
     }
 #pragma unroll
     for (int t = 0; t < NL; ++t) {
+        float cw[8];
+        corner_weights(w[t], cw);
+        if constexpr (sizeof(GT) == 2) {
+            f16x2v g[8];
 #pragma unroll
-        for (int f = 0; f < kFeats; ++f) {
-            float y0 = lerp(lerp(r[t][0].v[f], r[t][0].v[2 + f], w[t][0]), lerp(r[t][1].v[f], r[t][1].v[2 + f], w[t][0]),
-                            w[t][1]);
-            float y1 = lerp(lerp(r[t][2].v[f], r[t][2].v[2 + f], w[t][0]), lerp(r[t][3].v[f], r[t][3].v[2 + f], w[t][0]),
-                            w[t][1]);
-            x[2 * t + f] = lerp(y0, y1, w[t][2]);
+            for (int r = 0; r < 4; ++r) {
+                g[2 * r] = half_pair(q[t][r][0]);      // (x, .)
+                g[2 * r + 1] = half_pair(q[t][r][1]);  // (x+1, .)
+            }
+            interp_pairs(cw, g, x[2 * t], x[2 * t + 1]);
+        } else {
+            float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+            for (int cidx = 0; cidx < 8; ++cidx) {
+                const int r = cidx >> 1, bx = cidx & 1;
+                const float g0 = __builtin_bit_cast(float, q[t][r][2 * bx]);
+                const float g1 = __builtin_bit_cast(float, q[t][r][2 * bx + 1]);
+                s0 = cidx ? fmaf(cw[cidx], g0, s0) : cw[0] * g0;
+                s1 = cidx ? fmaf(cw[cidx], g1, s1) : cw[0] * g1;
+            }
+            x[2 * t] = s0;
+            x[2 * t + 1] = s1;
         }
     }
 }
 
 // The same lookups from the y-pair image of a binary16 grid: two 16-byte loads
-// per lookup (z and z+1 faces) instead of four 8-byte row loads, with the same
-// interpolation order, so the features are bit-identical to encode_half.
+// per lookup (the z and z+1 faces) instead of four row loads, same corner
+// order, so the features are bit-identical to encode_half.
+constexpr int kImageBatch = 6;  // lookups whose loads are issued together
 template <int L>
 __device__ __forceinline__ void encode_half_image(const float u[3][3], int half, const GLOBAL _Float16* img,
                                                   const FwdArgs& A, float* x) {
     constexpr int NL = 3 * L / 2;
-    int64_t base[NL];
-    float w[NL][3];
-    int64_t sz[NL];
+    constexpr int G = NL < kImageBatch ? NL : kImageBatch;
+    static_assert(NL % G == 0, "batch must divide the lookups");
 #pragma unroll
-    for (int t = 0; t < NL; ++t) {
-        const int k0 = t, k1 = NL + t;
-        const int e = half ? k1 / L : k0 / L;
-        const int l = half ? k1 % L : k0 % L;
-        const int N = A.res[l];
-        const float fN = (float)N;
-        int c[3];
+    for (int t0 = 0; t0 < NL; t0 += G) {
+        float w[G][3];
+        uint32_t q[G][2][4];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float ue = e == 0 ? u[0][a] : (e == 1 ? u[1][a] : u[2][a]);
-            c[a] = cell_coord(ue, fN, N, w[t][a]);
-        }
-        const int32_t N1 = N + 1;
-        const int64_t ent = ((int64_t)c[2] * N + c[1]) * N1 + c[0];
-        base[t] = (half ? A.ioff[k1] : A.ioff[k0]) + ent * 4;
-        sz[t] = (int64_t)N * N1 * 4;
-    }
-    uint32_t q[NL][2][4];
+        for (int i = 0; i < G; ++i) {
+            uint32_t c[3];
+            const int k = lookup_cell<L>(u, half, t0 + i, A, c, w[i]);
+            const uint32_t N = (uint32_t)A.res[k % L], N1 = N + 1;
+            const uint32_t ent = (c[2] * N + c[1]) * N1 + c[0];  // entries of 4 latents (8 bytes)
+            const GLOBAL uint32_t* p = reinterpret_cast<const GLOBAL uint32_t*>(img + A.ioff[k]) + (uint64_t)ent * 2;
+            const uint32_t sz = N * N1 * 2;  // one z step, in dwords
 #pragma unroll
-    for (int t = 0; t < NL; ++t) {
+            for (int zz = 0; zz < 2; ++zz) {
+                const GLOBAL uint32_t* pf = zz ? p + sz : p;
 #pragma unroll
-        for (int zz = 0; zz < 2; ++zz) {
-            // four dword reads of one dword-aligned 16-byte span: one global_load_dwordx4
-            const GLOBAL unsigned* p = reinterpret_cast<const GLOBAL unsigned*>(img + base[t] + zz * sz[t]);
-            q[t][zz][0] = p[0];
-            q[t][zz][1] = p[1];
-            q[t][zz][2] = p[2];
-            q[t][zz][3] = p[3];
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-        float r[2][8];  // per face: (x,y) f0 f1, (x,y+1) f0 f1, (x+1,y) f0 f1, (x+1,y+1) f0 f1
-#pragma unroll
-        for (int zz = 0; zz < 2; ++zz)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float2 f = __half22float2(__builtin_bit_cast(__half2, q[t][zz][j]));
-                r[zz][2 * j] = f.x;
-                r[zz][2 * j + 1] = f.y;
+                for (int j = 0; j < 4; ++j) q[i][zz][j] = pf[j];  // one 16-byte load per face
             }
+        }
 #pragma unroll
-        for (int f = 0; f < kFeats; ++f) {
-            float y0 = lerp(lerp(r[0][f], r[0][4 + f], w[t][0]), lerp(r[0][2 + f], r[0][6 + f], w[t][0]), w[t][1]);
-            float y1 = lerp(lerp(r[1][f], r[1][4 + f], w[t][0]), lerp(r[1][2 + f], r[1][6 + f], w[t][0]), w[t][1]);
-            x[2 * t + f] = lerp(y0, y1, w[t][2]);
+        for (int i = 0; i < G; ++i) {
+            float cw[8];
+            corner_weights(w[i], cw);
+            // face dwords: (x, y), (x, y+1), (x+1, y), (x+1, y+1) -> corners bx + 2 by + 4 bz
+            f16x2v g[8];
+#pragma unroll
+            for (int zz = 0; zz < 2; ++zz) {
+                g[4 * zz + 0] = half_pair(q[i][zz][0]);
+                g[4 * zz + 2] = half_pair(q[i][zz][1]);
+                g[4 * zz + 1] = half_pair(q[i][zz][2]);
+                g[4 * zz + 3] = half_pair(q[i][zz][3]);
+            }
+            interp_pairs(cw, g, x[2 * (t0 + i)], x[2 * (t0 + i) + 1]);
         }
     }
 }
@@ -402,7 +418,7 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
 // MODE 0: fused query.  MODE 1: grid stage only (writes the MLP inputs and the
 // clip status).  MODE 2: inference stage only (reads MLP inputs, one MLP).
 template <int FLAV, int L, typename GT, int MODE, bool IMG>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void nif_query_kernel(FwdArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == kF32 ? 2 : 3))) void nif_query_kernel(FwdArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int KH1 = 3 * L;  // layer-1 local inputs per half: 3L/2 lookups x 2 latents
     const int lane = threadIdx.x & 63;

@@ -49,7 +49,6 @@ __device__ __forceinline__ int cell_coord_t(float u, float fN, int N, float& w) 
     return ci < 0 ? 0 : (ci > N - 1 ? N - 1 : ci);
 }
 
-__device__ __forceinline__ float lerp_t(float a, float b, float t) { return a + t * (b - a); }
 
 template <typename GT> __device__ __forceinline__ void load_row(const GLOBAL GT* p, float v[4]);
 template <> __device__ __forceinline__ void load_row<_Float16>(const GLOBAL _Float16* p, float v[4]) {
@@ -95,12 +94,16 @@ __global__ void fill_zero_kernel(uint32_t* p, int n) {
 // leader; lanes left after that add their own values.
 constexpr int kPeel = 6;
 
+// Global-address-space atomics: generic (flat) atomics would also wait on the
+// LDS counter.
 __device__ __forceinline__ void add_and_mark(float* p, uint32_t* tb, int64_t vtx, float s0, float s1) {
-    if (s0 != 0.0f) unsafeAtomicAdd(p, s0);
-    if (s1 != 0.0f) unsafeAtomicAdd(p + 1, s1);
+    GLOBAL float* gp = (GLOBAL float*)p;
+    if (s0 != 0.0f) __builtin_amdgcn_global_atomic_fadd_f32(gp, s0);
+    if (s1 != 0.0f) __builtin_amdgcn_global_atomic_fadd_f32(gp + 1, s1);
     const uint32_t bit = 1u << (vtx & 31);
-    uint32_t* word = tb + (vtx >> 5);
-    if (!(__atomic_load_n(word, __ATOMIC_RELAXED) & bit)) atomicOr(word, bit);
+    GLOBAL uint32_t* word = (GLOBAL uint32_t*)tb + (vtx >> 5);
+    if (!(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+        __hip_atomic_fetch_or(word, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void scatter_corner(float* gg, uint32_t* tb, int64_t el, float v0, float v1, int lane) {
@@ -181,11 +184,18 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
                 load_row<GT>(grid + base + sy, r1);
                 load_row<GT>(grid + base + sz, r2);
                 load_row<GT>(grid + base + sz + sy, r3);
+                // corner weights prod (b_a ? w_a : 1 - w_a), formed as ((x y) z), and the
+                // sum over corners b = bx + 2 by + 4 bz in that order
+                const float x0 = 1.0f - w[0], y0 = 1.0f - w[1], z0 = 1.0f - w[2];
+                const float a00 = x0 * y0, a10 = w[0] * y0, a01 = x0 * w[1], a11 = w[0] * w[1];
+                const float cw[8] = {a00 * z0, a10 * z0, a01 * z0, a11 * z0, a00 * w[2], a10 * w[2], a01 * w[2], a11 * w[2]};
+                const float* rows[4] = {r0, r1, r2, r3};
 #pragma unroll
                 for (int f = 0; f < kFeats; ++f) {
-                    float y0 = lerp_t(lerp_t(r0[f], r0[2 + f], w[0]), lerp_t(r1[f], r1[2 + f], w[0]), w[1]);
-                    float y1 = lerp_t(lerp_t(r2[f], r2[2 + f], w[0]), lerp_t(r3[f], r3[2 + f], w[0]), w[1]);
-                    x[2 * t + f] = lerp_t(y0, y1, w[2]);
+                    float acc = cw[0] * r0[f];
+#pragma unroll
+                    for (int cidx = 1; cidx < 8; ++cidx) acc = fmaf(cw[cidx], rows[cidx >> 1][2 * (cidx & 1) + f], acc);
+                    x[2 * t + f] = acc;
                 }
             }
         }
@@ -406,11 +416,11 @@ template <typename GT>
 __global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t words) {
     const unsigned B = *A.count;
     const float inv = B ? 1.0f / (float)B : 0.0f;
-    float* gg = A.grid_grad[obj];
-    float* gm = A.grid_m[obj];
-    float* gv = A.grid_v[obj];
-    uint32_t* tb = A.touched[obj];
-    GT* theta = reinterpret_cast<GT*>(A.grids[obj]);
+    GLOBAL float* gg = (GLOBAL float*)A.grid_grad[obj];
+    GLOBAL float* gm = (GLOBAL float*)A.grid_m[obj];
+    GLOBAL float* gv = (GLOBAL float*)A.grid_v[obj];
+    GLOBAL uint32_t* tb = (GLOBAL uint32_t*)A.touched[obj];
+    GLOBAL GT* theta = (GLOBAL GT*)A.grids[obj];
     for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words; wi += (int64_t)gridDim.x * blockDim.x) {
         uint32_t bits = tb[wi];
         if (!bits) continue;
