@@ -230,7 +230,10 @@ def run_batched(args):
     tl = torch.empty(nb, dtype=torch.uint8, device="cuda")
     train_ms, bvh_build = 0.0, 0.0
     final_loss = []
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=8)
     for k in range(K):
+        batches = list(pool.map(lambda s: S.multi_train_batch(w["aabb"][k], k, s, nb), range(TRAIN_STEPS)))
         tb = time.perf_counter()
         bvh = nif.BVH(w["tris"][k])
         bvh_build += time.perf_counter() - tb
@@ -243,7 +246,7 @@ def run_batched(args):
         tid.fill_(k)
         loss = torch.zeros(1, device="cuda")
         for s in range(TRAIN_STEPS):
-            r, t = S.multi_train_batch(w["aabb"][k], k, s, nb)
+            r, t = batches[s]
             r, t = torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda()
             bvh.anyhit(r, t, out=tl)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -260,8 +263,11 @@ def run_batched(args):
     for dt in ("f32", "bf16"):
         ctx.prepare(dt)
 
-    # baseline: plain binary32 path, one launch per object on pre-split rays
+    # baseline: plain binary32 path (no ordering, gathers from the grids), one
+    # launch per object on pre-split rays
     ctx.set_option(nif.NIF_OPT_ORDER, 0)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    ctx.prepare("f32")
     split = [(rays[torch.from_numpy(order[bounds[k]:bounds[k + 1]]).cuda()].contiguous(),
               torch.full((int(bounds[k + 1] - bounds[k]),), k, dtype=torch.int32, device="cuda"),
               tmax[torch.from_numpy(order[bounds[k]:bounds[k + 1]]).cuda()].contiguous()) for k in range(K)]
@@ -276,6 +282,9 @@ def run_batched(args):
     y_base = np.empty(n, np.float32)
     y_base[order] = torch.cat(outs).cpu().numpy()
     ctx.set_option(nif.NIF_OPT_ORDER, 2)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 1)
+    for dt in ("f32", "bf16"):
+        ctx.prepare(dt)
     log(f"plain f32, {K} per-object launches: {base_sec * 1e3:.3f} ms = {n / base_sec / 1e9:.3f} G queries/s")
 
     res = {}
