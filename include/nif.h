@@ -98,6 +98,15 @@ nif_status nif_set_mlp(nif_ctx* ctx, int32_t mlp, float* weights);
  * saturating at 448, accumulated in binary32. */
 nif_status nif_set_fp8_scales(nif_ctx* ctx, int32_t mlp, const float* scales);
 
+/* Domain-error bits OR-ed together by every nif_query, nif_query_ordered,
+ * nif_encode and plan launch of this context since the last clear: queries
+ * whose output is NaN.  NIF_FLAG_INVALID_RAY: non-finite origin or direction,
+ * zero direction, or t_max NaN or negative; NIF_FLAG_BAD_OBJECT: object id
+ * outside [0, num_objects).  flags (host) receives the word; clear != 0 resets
+ * it.  Synchronises `stream`. */
+enum { NIF_FLAG_INVALID_RAY = 1, NIF_FLAG_BAD_OBJECT = 2 };
+nif_status nif_get_error_flags(nif_ctx* ctx, uint32_t* flags, int32_t clear, void* stream);
+
 /* FP8 calibration of MLP `mlp` (per-layer scaling for the E4M3 path; the
  * paper runs its networks in reduced precision, Sec. 4.2 and Sec. 5): runs the
  * binary32 encoding and layers 1..H-1 over the n queries (dev arrays as

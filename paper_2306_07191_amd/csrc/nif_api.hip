@@ -76,6 +76,7 @@ struct nif_ctx {
     int64_t ioff[3 * kMaxLevels + 1];
     std::vector<void*> images;  // per object, built by nif_prepare
     bool images_ready = false;
+    uint32_t* d_flags = nullptr;  // domain-error bits of queries (nif_get_error_flags)
 };
 
 static void free_images(nif_ctx* c) {
@@ -171,6 +172,7 @@ extern "C" void nif_destroy(nif_ctx* c) {
     if (c->d_train_fwd) (void)hipFree(c->d_train_fwd);
     if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
     free_images(c);
+    if (c->d_flags) (void)hipFree(c->d_flags);
     delete c;
 }
 
@@ -245,6 +247,10 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     }
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
+    if (!c->d_flags) {
+        HIP_TRY(hipMalloc(&c->d_flags, 256));
+        HIP_TRY(launch_fill_u32(c->d_flags, 1, 0u, s));
+    }
     // query images of the grids (rebuilt on every call: the grids may have changed)
     if (c->image_mode) {
         if (c->images.size() != (size_t)c->K) c->images.assign(c->K, nullptr);
@@ -334,6 +340,7 @@ static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const 
                             const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s,
                             int32_t blocks_per_cu = 0) {
     FwdArgs a{};
+    a.flags = c->d_flags;
     a.blocks_per_cu = blocks_per_cu;
     a.use_image = c->image_mode && c->images_ready;
     for (int k = 0; k < 3 * c->d.levels; ++k) a.ioff[k] = c->ioff[k];
@@ -414,6 +421,7 @@ extern "C" nif_status nif_query_ordered(nif_ctx* c, int32_t dtype, const float* 
 }
 
 static void fill_common(const nif_ctx* c, FwdArgs& a) {
+    a.flags = c->d_flags;
     a.use_image = c->image_mode && c->images_ready;
     for (int k = 0; k < 3 * c->d.levels; ++k) a.ioff[k] = c->ioff[k];
     a.objs = c->d_objs;
@@ -441,6 +449,17 @@ extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* i
     a.status_out = status;
     a.pack = c->pack[kF32];
     HIP_TRY(launch_encode(c->d.levels, c->d.grid_dtype, a, c->num_cus, (hipStream_t)stream));
+    return ok();
+}
+
+extern "C" nif_status nif_get_error_flags(nif_ctx* c, uint32_t* flags, int32_t clear, void* stream) {
+    if (!c || !flags) return fail(NIF_ERR_INVALID_ARG, "nif_get_error_flags: NULL argument");
+    *flags = 0;
+    if (!c->d_flags) return ok();  // nothing has run yet
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(flags, c->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (clear) HIP_TRY(launch_fill_u32(c->d_flags, 1, 0u, s));
     return ok();
 }
 

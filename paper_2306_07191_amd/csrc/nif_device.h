@@ -59,4 +59,17 @@ __device__ __forceinline__ bool valid_query(const float o[3], const float d[3], 
     return ok;
 }
 
+// Domain-error bits of a query (0 for a valid one): 1 = non-finite origin or
+// direction, zero direction, or t_max NaN or negative; 2 = object id out of
+// range.
+__device__ __forceinline__ uint32_t query_error_bits(const float o[3], const float d[3], float tmax, int32_t id,
+                                                     int32_t K) {
+    bool ray_ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ray_ok = ray_ok && isfinite(o[a]) && isfinite(d[a]);
+    ray_ok = ray_ok && !(d[0] == 0.0f && d[1] == 0.0f && d[2] == 0.0f);
+    ray_ok = ray_ok && !(tmax != tmax) && tmax >= 0.0f;
+    return (ray_ok ? 0u : 1u) | (id >= 0 && id < K ? 0u : 2u);
+}
+
 }  // namespace nif

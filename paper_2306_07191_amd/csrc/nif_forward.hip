@@ -494,8 +494,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
                 for (int c = 0; c < KH1; ++c) xin[c] = src[c];
             }
         } else if (inb) {
-            if (!valid_query(o, d, tm, id, A.num_objects)) {
+            const uint32_t err = query_error_bits(o, d, tm, id, A.num_objects);
+            if (err) {
                 status = -1;
+                if (A.flags) __hip_atomic_fetch_or(A.flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 const ObjDev ob = A.objs[id];
                 float u[3][3];

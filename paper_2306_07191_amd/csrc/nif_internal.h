@@ -69,6 +69,7 @@ struct FwdArgs {
     int32_t xcd_stride;           // logical block = (b % 8) * xcd_stride + b / 8
     int32_t blocks_per_cu;        // persistent grid size per compute unit (0: 8)
     int32_t use_image;            // gather from the objects' y-pair images
+    uint32_t* flags;              // domain-error bits of the launch are OR-ed in here (nullable)
     int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
 };
 
@@ -177,6 +178,7 @@ hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hip
 int64_t image_table_elems(int32_t N);
 hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
                               const int32_t* res, int levels, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
                             hipStream_t s);
 

@@ -41,6 +41,13 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t b = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)b), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 // Bucket (object, coarse Morton code) of query i; *fine receives the finer key
 // (object, Morton code with fine_bits per axis), 0xffffffff for a miss.  The
 // coarse code is a prefix of the fine one, so ordering by the fine key refines

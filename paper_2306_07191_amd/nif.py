@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(_PKG, "libnif.so")
 NIF_F32, NIF_F16, NIF_BF16, NIF_FP8_E4M3 = 0, 1, 2, 3
 NIF_OPT_ORDER = 1
 NIF_OPT_GRID_IMAGE = 2
+NIF_FLAG_INVALID_RAY = 1
+NIF_FLAG_BAD_OBJECT = 2
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
 STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3: "NIF_ERR_WORKSPACE",
           -4: "NIF_ERR_HIP", -5: "NIF_ERR_STATE"}
 
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
-           "nif_calibrate_fp8", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_calibrate_fp8", "nif_get_error_flags", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
            "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
            "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
@@ -65,6 +67,7 @@ def lib():
             "nif_set_object": (i32, [vp, i32, vp, vp, i32]),
             "nif_set_mlp": (i32, [vp, i32, vp]),
             "nif_set_fp8_scales": (i32, [vp, i32, vp]),
+            "nif_get_error_flags": (i32, [vp, vp, i32, vp]),
             "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
             "nif_prepare": (i32, [vp, i32, vp]),
@@ -248,6 +251,12 @@ class Context:
     def set_fp8_scales(self, m: int, scales):
         s = np.ascontiguousarray(scales, np.float32)
         _check(lib().nif_set_fp8_scales(self.h, m, s.ctypes.data), "nif_set_fp8_scales")
+
+    def error_flags(self, clear: bool = True) -> int:
+        """Domain-error bits of the queries since the last clear (1 invalid ray, 2 bad object id)."""
+        f = C.c_uint32(0)
+        _check(lib().nif_get_error_flags(self.h, C.byref(f), 1 if clear else 0, _stream()), "nif_get_error_flags")
+        return int(f.value)
 
     def calibrate_fp8(self, rays, ids, tmax, mlp: int = 0, ws=None):
         """Per-layer FP8 scales of MLP `mlp` from the given queries; returns them (s_W then s_x)."""

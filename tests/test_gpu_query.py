@@ -99,6 +99,7 @@ def test_query_empty_and_errors():
 
 
 def test_query_invalid_inputs():
+    from paper_2306_07191_amd import nif
     w = S.tiny_workload(n_rays=300)
     rays, tmax, ids = w["rays"], w["tmax"], w["ids"]
     rays[0, 0] = np.nan
@@ -116,6 +117,13 @@ def test_query_invalid_inputs():
         assert list(ref["status"][:8]) == [-1, -1, -1, -1, -1, 0, 0, -1]
         y, z = run_query(ctx, w, dtype)
         check_outputs(y, z, ref, dtype, "invalid")
+        # the context's error word has both kinds of domain error, then clears
+        assert ctx.error_flags() == nif.NIF_FLAG_INVALID_RAY | nif.NIF_FLAG_BAD_OBJECT
+        assert ctx.error_flags() == 0
+    w2 = S.tiny_workload(n_rays=300)
+    w2["ids"][9] = 3
+    run_query(ctx, w2, "f32")
+    assert ctx.error_flags() == nif.NIF_FLAG_BAD_OBJECT
 
 
 def test_query_multi_object_multi_mlp():
