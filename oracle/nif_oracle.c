@@ -708,6 +708,16 @@ static void fwd_range(void* p, int64_t b, int64_t e) {
     }
 }
 
+/* Clip status of n queries only (1: the segment meets the AABB, 0: miss,
+ * -1: invalid query), the first step of orc_forward (Sec. 4.1). */
+void orc_status(const orc_model* m, int64_t n, const float* rays, const int32_t* ids, const float* tmax,
+                int32_t* status) {
+    for (int64_t i = 0; i < n; ++i) {
+        double u[3][3];
+        status[i] = query_coords(m, rays + 6 * i, tmax[i], ids[i], u);
+    }
+}
+
 void orc_forward(const orc_model* m, int64_t n, const float* rays, const int32_t* ids, const float* tmax,
                  double* z, double* y, int32_t* status, double* ztol, double* ybound, int32_t* flags,
                  double* x_out, int nthreads) {

@@ -70,6 +70,7 @@ def lib():
             "orc_forward": (None, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_query_detail": (C.c_int, [vp, vp, i32, C.c_float, vp, vp, vp, vp]),
             "orc_mlp_only": (None, [vp, i32, i64, vp, vp, vp]),
+            "orc_status": (None, [vp, i64, vp, vp, vp, vp]),
             "orc_backward": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_backward_given": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_grid_grad_dense": (None, [vp, i32, i64, vp, vp, vp, vp, vp]),
@@ -210,6 +211,25 @@ class Model:
             out["x"] = x
         return out
 
+    def status(self, rays, ids, tmax):
+        """Clip status only: 1 the segment meets the AABB, 0 miss, -1 invalid."""
+        rays = np.ascontiguousarray(rays, np.float32)
+        ids = np.ascontiguousarray(ids, np.int32)
+        tmax = np.ascontiguousarray(tmax, np.float32)
+        st = np.empty(ids.shape[0], np.int32)
+        lib().orc_status(self.ref, ids.shape[0], _p(rays), _p(ids), _p(tmax), _p(st))
+        return st
+
+    def expand_pairs(self, rays, tmax):
+        """(Sec. 4.1) The (ray, object) pairs whose segment meets the object's AABB,
+        in ray order and objects ascending: (pair_ray, pair_obj)."""
+        n, K = tmax.shape[0], self.K
+        rr = np.repeat(np.arange(n, dtype=np.int64), K)
+        kk = np.tile(np.arange(K, dtype=np.int32), n)
+        st = self.status(np.asarray(rays)[rr], kk, np.asarray(tmax)[rr])
+        hit = st == 1
+        return rr[hit], kk[hit]
+
     def detail(self, ray, obj, tmax):
         L = self.shape.levels
         u = np.zeros(9)
@@ -307,6 +327,16 @@ class Model:
 # --------------------------------------------------------------------------
 # elementwise steps
 # --------------------------------------------------------------------------
+
+def combine_pairs(pair_ray, visibility, n_rays):
+    """(Sec. 4.1) A ray is visible iff every one of its pairs is visible
+    (visibility >= 0.5); a ray without pairs is visible.  Returns uint8 [n_rays]."""
+    out = np.ones(n_rays, np.uint8)
+    for r, v in zip(np.asarray(pair_ray).tolist(), np.asarray(visibility).tolist()):
+        if v < 0.5:
+            out[r] = 0
+    return out
+
 
 def bce_with_logits(z, t):
     """mean(softplus(z) - t z) and its derivative (sigmoid(z) - t) / B."""
