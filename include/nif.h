@@ -98,6 +98,27 @@ nif_status nif_set_mlp(nif_ctx* ctx, int32_t mlp, float* weights);
  * saturating at 448, accumulated in binary32. */
 nif_status nif_set_fp8_scales(nif_ctx* ctx, int32_t mlp, const float* scales);
 
+/* Scenes of several objects (Sec. 4.1: a top-level pass finds the objects
+ * whose AABB a shadow ray meets; each such (ray, object) pair is one query; a
+ * ray is visible iff all its pairs are, and a ray with no pair is visible).
+ * nif_expand_pairs: for n_rays rays (dev, n x 6 floats) with t_max (dev),
+ *   tests every registered object's AABB with the query's binary32 segment
+ *   rule and writes the pairs in ray order, objects ascending: pair_rays (dev,
+ *   max_pairs x 6 floats, a copy of the ray), pair_tmax, pair_ids (object),
+ *   pair_ray (source ray index).  *pair_count (dev, int64) receives the number
+ *   of pairs, also when it exceeds max_pairs (then only the first max_pairs
+ *   are written: call again with more room).  Invalid rays (non-finite,
+ *   zero direction, t_max NaN or negative) have no pairs.  n_rays <= 2^24.  Needs
+ *   nif_prepare; ws: nif_pairs_workspace_bytes(ctx, n_rays) bytes (dev).
+ * nif_combine_pairs: ray_visible (dev, n_rays bytes) = 0 iff some pair p of
+ *   the ray (pair_ray[p], dev) has visibility[p] < 0.5 (dev), else 1. */
+size_t nif_pairs_workspace_bytes(const nif_ctx* ctx, int64_t n_rays);
+nif_status nif_expand_pairs(nif_ctx* ctx, const float* rays, const float* t_max, int64_t n_rays, int64_t max_pairs,
+                            float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
+                            int64_t* pair_count, void* ws, size_t ws_bytes, void* stream);
+nif_status nif_combine_pairs(nif_ctx* ctx, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
+                             int64_t n_rays, uint8_t* ray_visible, void* stream);
+
 /* Domain-error bits OR-ed together by every nif_query, nif_query_ordered,
  * nif_encode and plan launch of this context since the last clear: queries
  * whose output is NaN.  NIF_FLAG_INVALID_RAY: non-finite origin or direction,

@@ -452,6 +452,40 @@ extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* i
     return ok();
 }
 
+extern "C" size_t nif_pairs_workspace_bytes(const nif_ctx* c, int64_t n_rays) {
+    if (!c || n_rays < 0) return 0;
+    return pairs_workspace_bytes(n_rays);
+}
+
+extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,
+                                       int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
+                                       uint32_t* pair_ray, int64_t* pair_count, void* ws, size_t ws_bytes,
+                                       void* stream) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL context");
+    if (n_rays < 0 || max_pairs < 0) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: negative size");
+    if (!pair_count) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL pair_count");
+    if (n_rays > 0 && (!rays || !tmax)) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL rays");
+    if (max_pairs > 0 && (!pair_rays || !pair_tmax || !pair_ids || !pair_ray))
+        return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL pair output");
+    if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: at most 2^24 rays per call");
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    const size_t need = pairs_workspace_bytes(n_rays);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->d_objs, c->K, max_pairs, pair_rays, pair_tmax, pair_ids,
+                                pair_ray, pair_count, ws, (hipStream_t)stream));
+    return ok();
+}
+
+extern "C" nif_status nif_combine_pairs(nif_ctx* c, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
+                                        int64_t n_rays, uint8_t* ray_visible, void* stream) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_combine_pairs: NULL context");
+    if (n_pairs < 0 || n_rays < 0) return fail(NIF_ERR_INVALID_ARG, "nif_combine_pairs: negative size");
+    if ((n_pairs > 0 && (!pair_ray || !visibility)) || (n_rays > 0 && !ray_visible))
+        return fail(NIF_ERR_INVALID_ARG, "nif_combine_pairs: NULL argument");
+    HIP_TRY(launch_combine_pairs(pair_ray, visibility, n_pairs, n_rays, ray_visible, (hipStream_t)stream));
+    return ok();
+}
+
 extern "C" nif_status nif_get_error_flags(nif_ctx* c, uint32_t* flags, int32_t clear, void* stream) {
     if (!c || !flags) return fail(NIF_ERR_INVALID_ARG, "nif_get_error_flags: NULL argument");
     *flags = 0;

@@ -11,25 +11,34 @@ namespace nif {
 // Clip and normalisation, binary32, no contraction.
 // Returns 1 if the segment [max(t_near,0), min(t_far,t_max)] is non-empty.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ int clip_normalise(const float o[3], const float d[3], float tmax, const ObjDev& b,
-                                              float u[3][3]) {
+// The segment alone: true iff [ta, tb] = [max(t_near, 0), min(t_far, t_max)]
+// is non-empty (box lo, hi).
+__device__ __forceinline__ bool clip_segment(const float o[3], const float d[3], float tmax, const float lo[3],
+                                             const float hi[3], float& ta, float& tb) {
 #pragma clang fp contract(off)
     float tn = -INFINITY, tf = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (d[a] == 0.0f) {
-            if (o[a] < b.lo[a] || o[a] > b.hi[a]) return 0;
+            if (o[a] < lo[a] || o[a] > hi[a]) return false;
             continue;
         }
-        float t0 = (b.lo[a] - o[a]) / d[a];
-        float t1 = (b.hi[a] - o[a]) / d[a];
+        float t0 = (lo[a] - o[a]) / d[a];
+        float t1 = (hi[a] - o[a]) / d[a];
         float l = t0 < t1 ? t0 : t1, h = t0 < t1 ? t1 : t0;
         if (l > tn) tn = l;
         if (h < tf) tf = h;
     }
-    float ta = tn > 0.0f ? tn : 0.0f;
-    float tb = tf < tmax ? tf : tmax;
-    if (!(ta <= tb)) return 0;
+    ta = tn > 0.0f ? tn : 0.0f;
+    tb = tf < tmax ? tf : tmax;
+    return ta <= tb;
+}
+
+__device__ __forceinline__ int clip_normalise(const float o[3], const float d[3], float tmax, const ObjDev& b,
+                                              float u[3][3]) {
+#pragma clang fp contract(off)
+    float ta, tb;
+    if (!clip_segment(o, d, tmax, b.lo, b.hi, ta, tb)) return 0;
     float len2 = d[0] * d[0];
     len2 = len2 + d[1] * d[1];
     len2 = len2 + d[2] * d[2];

@@ -179,6 +179,15 @@ int64_t image_table_elems(int32_t N);
 hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
                               const int32_t* res, int levels, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+size_t pairs_workspace_bytes(int64_t n_rays);
+hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const ObjDev* objs, int32_t K,
+                               int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
+                               uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s);
+hipError_t launch_combine_pairs(const uint32_t* pair_ray, const float* vis, int64_t n_pairs, int64_t n_rays,
+                                uint8_t* ray_visible, hipStream_t s);
+// In-place exclusive scan of n <= 16M uint32 (block_sums: scan_block_sums(n) words).
+int64_t scan_block_sums(int64_t n);
+hipError_t launch_exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* block_sums, hipStream_t s);
 hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
                             hipStream_t s);
 

@@ -255,6 +255,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* hist,
 }
 
 
+int64_t scan_block_sums(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* block_sums, hipStream_t s) {
+    const int64_t tiles = scan_block_sums(n);
+    if (tiles > kScanTile) return hipErrorInvalidValue;  // more than 16M elements
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, data, n, block_sums);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, block_sums, tiles);
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, data, n, block_sums);
+    return hipGetLastError();
+}
+
 int order_bits(int32_t num_objects) {
     int bits = 4;
     while (bits > 0 && ((int64_t)num_objects << (3 * bits)) > 4096) --bits;

@@ -26,7 +26,8 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
-           "nif_calibrate_fp8", "nif_get_error_flags", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
+           "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
            "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
            "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
@@ -68,6 +69,9 @@ def lib():
             "nif_set_mlp": (i32, [vp, i32, vp]),
             "nif_set_fp8_scales": (i32, [vp, i32, vp]),
             "nif_get_error_flags": (i32, [vp, vp, i32, vp]),
+            "nif_pairs_workspace_bytes": (sz, [vp, i64]),
+            "nif_expand_pairs": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "nif_combine_pairs": (i32, [vp, vp, vp, i64, i64, vp, vp]),
             "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
             "nif_prepare": (i32, [vp, i32, vp]),
@@ -251,6 +255,35 @@ class Context:
     def set_fp8_scales(self, m: int, scales):
         s = np.ascontiguousarray(scales, np.float32)
         _check(lib().nif_set_fp8_scales(self.h, m, s.ctypes.data), "nif_set_fp8_scales")
+
+    def expand_pairs(self, rays, tmax, max_pairs=None):
+        """(pair_rays, pair_tmax, pair_ids, pair_ray) of the rays' AABB hits, ray order."""
+        t = self.torch
+        n = tmax.shape[0]
+        ws = t.empty(max(1, int(lib().nif_pairs_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
+        cnt = t.zeros(1, dtype=t.int64, device=self.device)
+        for _ in range(2):
+            m = max(1, n if max_pairs is None else max_pairs)
+            pr = t.empty((m, 6), dtype=t.float32, device=self.device)
+            pt = t.empty(m, dtype=t.float32, device=self.device)
+            pi = t.empty(m, dtype=t.int32, device=self.device)
+            pray = t.empty(m, dtype=t.int32, device=self.device)
+            _check(lib().nif_expand_pairs(self.h, _ptr(rays), _ptr(tmax), n, m, _ptr(pr), _ptr(pt), _ptr(pi),
+                                          _ptr(pray), _ptr(cnt), _ptr(ws), ws.numel(), _stream()), "nif_expand_pairs")
+            total = int(cnt.item())
+            if total <= m:
+                return pr[:total], pt[:total], pi[:total], pray[:total]
+            max_pairs = total
+        raise RuntimeError("pair count changed between calls")
+
+    def combine_pairs(self, pair_ray, visibility, n_rays, out=None):
+        """Per-ray visibility (uint8): 0 iff some pair of the ray is below 0.5."""
+        t = self.torch
+        if out is None:
+            out = t.empty(n_rays, dtype=t.uint8, device=self.device)
+        _check(lib().nif_combine_pairs(self.h, _ptr(pair_ray), _ptr(visibility), pair_ray.shape[0], n_rays, _ptr(out),
+                                       _stream()), "nif_combine_pairs")
+        return out
 
     def error_flags(self, clear: bool = True) -> int:
         """Domain-error bits of the queries since the last clear (1 invalid ray, 2 bad object id)."""

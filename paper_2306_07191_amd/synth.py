@@ -327,3 +327,77 @@ def multi_train_batch(box, obj: int, step: int, n: int = 262144):
     ctr = 0.5 * (box[:3].astype(np.float64) + box[3:])
     half = 0.5 * float((box[3:].astype(np.float64) - box[:3]).max())
     return rays_sphere_to_box(n, box, rng(CFG_MULTI, 5, obj, step), radius=3.0 * half, center=ctr)
+
+
+# --------------------------------------------------------------------------
+# Large scene: 64 displaced spheres on a ground plane, 30M triangles in all,
+# a 1920 x 1080 grid of ground points, 4 light samples per pixel.
+# --------------------------------------------------------------------------
+SCENE_OBJECTS = 64
+SCENE_TRIANGLES = 30_000_000
+SCENE_X, SCENE_Z = 24.0, 13.5          # ground half extents
+SCENE_LIGHT_Y, SCENE_LIGHT_HALF = 30.0, 2.0
+SCENE_W, SCENE_H, SCENE_SPP = 1920, 1080, 4
+
+
+def scene_layout():
+    """Triangle targets, (n_lon, n_rings), radii and centres of the 64 objects:
+    counts log-uniform in [1e3, 2e6] rescaled to sum to 30M, radii U(0.5, 1.5),
+    centres uniform on the ground, sunk to y = 0.9 r."""
+    g = rng(CFG_SCENE, 0)
+    t = np.exp(g.uniform(math.log(1e3), math.log(2e6), SCENE_OBJECTS))
+    t *= SCENE_TRIANGLES / t.sum()
+    dims = [uv_sphere_dims(int(round(x))) for x in t]
+    radii = g.uniform(0.5, 1.5, SCENE_OBJECTS)
+    centers = np.stack([g.uniform(-SCENE_X, SCENE_X, SCENE_OBJECTS), 0.9 * radii,
+                        g.uniform(-SCENE_Z, SCENE_Z, SCENE_OBJECTS)], axis=1)
+    counts = np.array([2 * a + 2 * a * (b - 1) for a, b in dims], np.int64)
+    return dict(dims=dims, radii=radii, centers=centers, tri_counts=counts)
+
+
+def scene_meshes():
+    """The 64 meshes (float32 [T_k, 3, 3] each), displacement amplitude 0.2."""
+    lay = scene_layout()
+    return [displaced_uv_sphere(a, b, lay["centers"][k], float(lay["radii"][k]), 0.2, rng(CFG_SCENE, 0, k))
+            for k, (a, b) in enumerate(lay["dims"])]
+
+
+def scene_rays(light_seed: int = 0):
+    """Shadow rays of the frame: pixel (i, j) -> ground point (x, 0, z) at the
+    pixel centre, 4 light samples per pixel stratified 2 x 2 on the 4 x 4 light
+    at height 30 and jittered; d unit (float32), t_max = distance to the
+    sample.  Order: row j, column i, sample.  Returns rays [N, 6], t_max [N]."""
+    i = (np.arange(SCENE_W) + 0.5) / SCENE_W
+    j = (np.arange(SCENE_H) + 0.5) / SCENE_H
+    gx = -SCENE_X + 2 * SCENE_X * i
+    gz = -SCENE_Z + 2 * SCENE_Z * j
+    n_pix = SCENE_W * SCENE_H
+    o = np.zeros((n_pix, SCENE_SPP, 3))
+    o[:, :, 0] = np.tile(gx, SCENE_H)[:, None]
+    o[:, :, 2] = np.repeat(gz, SCENE_W)[:, None]
+    g = rng(CFG_SCENE, 6, light_seed)
+    jit = g.uniform(size=(n_pix, SCENE_SPP, 2))
+    sx = np.array([0, 1, 0, 1])[None, :]
+    sz = np.array([0, 0, 1, 1])[None, :]
+    lx = -SCENE_LIGHT_HALF + SCENE_LIGHT_HALF * (sx + jit[:, :, 0])
+    lz = -SCENE_LIGHT_HALF + SCENE_LIGHT_HALF * (sz + jit[:, :, 1])
+    light = np.stack([lx, np.full_like(lx, SCENE_LIGHT_Y), lz], axis=-1)
+    o32 = o.reshape(-1, 3).astype(np.float32)
+    v = light.reshape(-1, 3).astype(np.float32) - o32
+    d = _normalize32(v)
+    tmax = np.sqrt((v.astype(np.float64) ** 2).sum(axis=1)).astype(np.float32)
+    return np.concatenate([o32, d], axis=1).astype(np.float32), tmax
+
+
+def scene_workload(light_seed: int = 0, with_mesh: bool = True):
+    meshes = scene_meshes() if with_mesh else None
+    lay = scene_layout()
+    if with_mesh:
+        boxes = np.stack([mesh_aabb(m) for m in meshes])
+    else:  # the undisplaced bounds widened by the displacement amplitude
+        r = (1.2 * lay["radii"])[:, None]
+        boxes = np.concatenate([lay["centers"] - r, lay["centers"] + r], axis=1).astype(np.float32)
+    rays, tmax = scene_rays(light_seed)
+    mlps = np.stack([xavier_mlp(FRAME, rng(CFG_SCENE, 3, k)) for k in range(SCENE_OBJECTS)])
+    return dict(shape=FRAME, tris=meshes, tri_counts=lay["tri_counts"], aabb=boxes, rays=rays, tmax=tmax,
+                mlps=mlps, mlp_index=np.arange(SCENE_OBJECTS, dtype=np.int32))
