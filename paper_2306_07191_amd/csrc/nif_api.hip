@@ -6,6 +6,7 @@
 
 #include <stdlib.h>
 
+#include <algorithm>
 #include <memory>
 #include <string>
 #include <vector>
@@ -77,7 +78,60 @@ struct nif_ctx {
     std::vector<void*> images;  // per object, built by nif_prepare
     bool images_ready = false;
     uint32_t* d_flags = nullptr;  // domain-error bits of queries (nif_get_error_flags)
+    BoxGroup* d_groups = nullptr;  // box groups for the pair expansion (16..64 objects)
+    int32_t num_groups = 0;
 };
+
+// Groups of up to 8 objects consecutive in the Morton order of their box
+// centres (10 bits per axis over the scene bounds), for 16 to 64 objects.
+static std::vector<BoxGroup> build_groups(const std::vector<ObjDev>& od) {
+    std::vector<BoxGroup> g;
+    const int K = (int)od.size();
+    if (K < 16 || K > 64) return g;
+    float slo[3], shi[3];
+    for (int a = 0; a < 3; ++a) {
+        slo[a] = INFINITY;
+        shi[a] = -INFINITY;
+        for (const ObjDev& o : od) {
+            slo[a] = fminf(slo[a], 0.5f * (o.lo[a] + o.hi[a]));
+            shi[a] = fmaxf(shi[a], 0.5f * (o.lo[a] + o.hi[a]));
+        }
+    }
+    auto spread = [](uint64_t v) {
+        uint64_t r = 0;
+        for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+        return r;
+    };
+    std::vector<std::pair<uint64_t, int>> key(K);
+    for (int k = 0; k < K; ++k) {
+        uint64_t m = 0;
+        for (int a = 0; a < 3; ++a) {
+            const float ext = shi[a] - slo[a];
+            const float u = ext > 0.0f ? (0.5f * (od[k].lo[a] + od[k].hi[a]) - slo[a]) / ext : 0.0f;
+            const uint64_t q = (uint64_t)fminf(fmaxf(u * 1023.0f, 0.0f), 1023.0f);
+            m |= spread(q) << a;
+        }
+        key[k] = {m, k};
+    }
+    std::sort(key.begin(), key.end());
+    for (int i = 0; i < K; i += 8) {
+        BoxGroup b{};
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = INFINITY;
+            b.hi[a] = -INFINITY;
+        }
+        for (int j = i; j < i + 8 && j < K; ++j) {
+            const ObjDev& o = od[key[j].second];
+            for (int a = 0; a < 3; ++a) {
+                b.lo[a] = fminf(b.lo[a], o.lo[a]);
+                b.hi[a] = fmaxf(b.hi[a], o.hi[a]);
+            }
+            b.members |= 1ull << key[j].second;
+        }
+        g.push_back(b);
+    }
+    return g;
+}
 
 static void free_images(nif_ctx* c) {
     for (auto& p : c->images)
@@ -173,6 +227,7 @@ extern "C" void nif_destroy(nif_ctx* c) {
     if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
     free_images(c);
     if (c->d_flags) (void)hipFree(c->d_flags);
+    if (c->d_groups) (void)hipFree(c->d_groups);
     delete c;
 }
 
@@ -275,6 +330,12 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     }
     if (!c->d_objs) HIP_TRY(hipMalloc(&c->d_objs, sizeof(ObjDev) * c->K));
     HIP_TRY(hipMemcpy(c->d_objs, od.data(), sizeof(ObjDev) * c->K, hipMemcpyHostToDevice));
+    const std::vector<BoxGroup> groups = build_groups(od);
+    if (!groups.empty()) {
+        if (!c->d_groups) HIP_TRY(hipMalloc(&c->d_groups, sizeof(BoxGroup) * 8));
+        HIP_TRY(hipMemcpy(c->d_groups, groups.data(), sizeof(BoxGroup) * groups.size(), hipMemcpyHostToDevice));
+    }
+    c->num_groups = (int32_t)groups.size();
     // weights, packed on the device from the binary32 masters
     const int flav = dtype;
     const PackInfo& P = c->pack[flav];
@@ -454,7 +515,7 @@ extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* i
 
 extern "C" size_t nif_pairs_workspace_bytes(const nif_ctx* c, int64_t n_rays) {
     if (!c || n_rays < 0) return 0;
-    return pairs_workspace_bytes(n_rays);
+    return pairs_workspace_bytes(n_rays, c->K);
 }
 
 extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,
@@ -469,9 +530,9 @@ extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const floa
         return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL pair output");
     if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: at most 2^24 rays per call");
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
-    const size_t need = pairs_workspace_bytes(n_rays);
+    const size_t need = pairs_workspace_bytes(n_rays, c->K);
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
-    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->d_objs, c->K, max_pairs, pair_rays, pair_tmax, pair_ids,
+    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->d_objs, c->K, c->d_groups, c->num_groups, max_pairs, pair_rays, pair_tmax, pair_ids,
                                 pair_ray, pair_count, ws, (hipStream_t)stream));
     return ok();
 }

@@ -179,10 +179,17 @@ int64_t image_table_elems(int32_t N);
 hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
                               const int32_t* res, int levels, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
-size_t pairs_workspace_bytes(int64_t n_rays);
+// Up to 8 objects (of at most 64) whose boxes are near each other, for the
+// pair expansion: the union box and the member set.
+struct BoxGroup {
+    float lo[3], hi[3];
+    uint64_t members;
+};
+size_t pairs_workspace_bytes(int64_t n_rays, int32_t K);
 hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const ObjDev* objs, int32_t K,
-                               int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
-                               uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s);
+                               const BoxGroup* groups, int32_t num_groups, int64_t max_pairs, float* pair_rays,
+                               float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray, int64_t* total, void* ws,
+                               hipStream_t s);
 hipError_t launch_combine_pairs(const uint32_t* pair_ray, const float* vis, int64_t n_pairs, int64_t n_rays,
                                 uint8_t* ray_visible, hipStream_t s);
 // In-place exclusive scan of n <= 16M uint32 (block_sums: scan_block_sums(n) words).

@@ -62,10 +62,14 @@ __device__ __forceinline__ bool maybe_hit(const RayPre& r, const float lo[3], co
     return ta <= tb;
 }
 
+// With at most 64 objects the count pass also keeps every ray's hit mask, and
+// the emit pass reads it instead of testing the boxes again.
 __global__ __launch_bounds__(kPairThreads) void pairs_count_kernel(const float* __restrict__ rays,
                                                                    const float* __restrict__ tmax, int64_t n,
                                                                    const ObjDev* __restrict__ objs, int32_t K,
-                                                                   uint32_t* __restrict__ counts) {
+                                                                   const BoxGroup* __restrict__ groups, int32_t G,
+                                                                   uint32_t* __restrict__ counts,
+                                                                   uint64_t* __restrict__ masks) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         float o[3], d[3];
 #pragma unroll
@@ -77,12 +81,33 @@ __global__ __launch_bounds__(kPairThreads) void pairs_count_kernel(const float* 
         uint32_t c = 0;
         const bool ok = !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
         const RayPre pre = ray_pre(o, d, tm);
-        for (int32_t k = 0; ok && k < K; ++k) {
-            float ta, tb;
-            if (maybe_hit(pre, objs[k].lo, objs[k].hi))
-                c += clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb) ? 1u : 0u;
+        uint64_t mk = 0;
+        if (G > 0) {  // groups first: a box in a group lies inside the group's box
+            for (int32_t g = 0; ok && g < G; ++g) {
+                if (!maybe_hit(pre, groups[g].lo, groups[g].hi)) continue;
+                uint64_t mem = groups[g].members;
+                while (mem) {
+                    const int k = __builtin_ctzll(mem);
+                    mem &= mem - 1;
+                    float ta, tb;
+                    if (maybe_hit(pre, objs[k].lo, objs[k].hi) &&
+                        clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb)) {
+                        ++c;
+                        mk |= 1ull << k;
+                    }
+                }
+            }
+        } else {
+            for (int32_t k = 0; ok && k < K; ++k) {
+                float ta, tb;
+                if (maybe_hit(pre, objs[k].lo, objs[k].hi) && clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb)) {
+                    ++c;
+                    if (k < 64) mk |= 1ull << k;
+                }
+            }
         }
         counts[r] = c;
+        if (masks) masks[r] = mk;
     }
 }
 
@@ -94,6 +119,7 @@ __global__ __launch_bounds__(kPairThreads) void pairs_emit_kernel(const float* _
                                                                   float* __restrict__ pair_tmax,
                                                                   int32_t* __restrict__ pair_ids,
                                                                   uint32_t* __restrict__ pair_ray,
+                                                                  const uint64_t* __restrict__ masks,
                                                                   int64_t* __restrict__ total) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         float o[3], d[3];
@@ -106,10 +132,17 @@ __global__ __launch_bounds__(kPairThreads) void pairs_emit_kernel(const float* _
         int64_t p = offsets[r];
         const bool ok = !(query_error_bits(o, d, tm, 0, 1) & 1u);
         const RayPre pre = ray_pre(o, d, tm);
+        uint64_t mk = masks ? masks[r] : 0;
         for (int32_t k = 0; ok && k < K; ++k) {
-            float ta, tb;
-            if (!maybe_hit(pre, objs[k].lo, objs[k].hi) || !clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb))
-                continue;
+            if (masks) {  // ascending set bits of the stored mask
+                if (!mk) break;
+                k = __builtin_ctzll(mk);
+                mk &= mk - 1;
+            } else {
+                float ta, tb;
+                if (!maybe_hit(pre, objs[k].lo, objs[k].hi) || !clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb))
+                    continue;
+            }
             if (p < max_pairs) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -144,9 +177,9 @@ __global__ void combine_pairs_kernel(const uint32_t* __restrict__ pair_ray, cons
     }
 }
 
-size_t pairs_workspace_bytes(int64_t n_rays) {
+size_t pairs_workspace_bytes(int64_t n_rays, int32_t K) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return al((size_t)n_rays * 4) + al((size_t)scan_block_sums(n_rays) * 4);
+    return al((size_t)n_rays * 4) + al((size_t)scan_block_sums(n_rays) * 4) + (K <= 64 ? al((size_t)n_rays * 8) : 0);
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -155,19 +188,22 @@ static unsigned grid_for(int64_t n, int threads) {
 }
 
 hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const ObjDev* objs, int32_t K,
-                               int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
+                               const BoxGroup* groups, int32_t num_groups, int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
                                uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     uint32_t* counts = reinterpret_cast<uint32_t*>(ws);
     uint32_t* sums = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(ws) + al((size_t)n * 4));
+    uint64_t* masks = K <= 64 ? reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + al((size_t)n * 4) +
+                                                          al((size_t)scan_block_sums(n) * 4))
+                              : nullptr;
     hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
     if (n == 0) return hipGetLastError();
     hipLaunchKernelGGL(pairs_count_kernel, dim3(grid_for(n, kPairThreads)), dim3(kPairThreads), 0, s, rays, tmax, n,
-                       objs, K, counts);
+                       objs, K, K <= 64 ? groups : nullptr, K <= 64 ? num_groups : 0, counts, masks);
     hipError_t e = launch_exclusive_scan_u32(counts, n, sums, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pairs_emit_kernel, dim3(grid_for(n, kPairThreads)), dim3(kPairThreads), 0, s, rays, tmax, n,
-                       objs, K, counts, max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray, total);
+                       objs, K, counts, max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray, masks, total);
     return hipGetLastError();
 }
 

@@ -30,9 +30,10 @@ def _scene(n=20000, K=12, seed=5):
                 tmax=tmax, ids=np.zeros(n, np.int32))
 
 
-def test_pairs_match_oracle_and_combine():
+@pytest.mark.parametrize("K", [12, 40, 70])  # boxes one by one with hit masks, box groups, no masks
+def test_pairs_match_oracle_and_combine(K):
     import torch
-    w = _scene()
+    w = _scene(K=K)
     ctx, model = make_pair(w, grid_amp=0.5)
     ctx.prepare("f32")
     rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
