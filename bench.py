@@ -552,6 +552,8 @@ def main():
     n = w["ids"].shape[0]
     log(f"workload ready in {time.perf_counter() - t0:.1f}s: {n} queries")
     ctx = nif.Context(sh)
+    # one object: room for the z-y-pair query image (4x the grid, 8.4 GB)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 2)
     ctx.set_mlp(0, torch.from_numpy(w["mlps"][0]).cuda())
     grid = ctx.alloc_grid()
     ctx.set_object(0, w["aabb"][0], grid, 0)
@@ -629,7 +631,7 @@ def main():
     achieved_tflops = flops * n / kern / 1e12
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_TFLOPS[HEADLINE_DTYPE],
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic(),
-                "kernel": "nif_query_kernel<bf16, L=8, f16 grid> (fused clip+encode+MLP)",
+                "kernel": "nif_query_kernel<bf16, L=8, f16 grid, z-y-pair image> (fused clip+encode+MLP)",
                 "algorithmic_flop_per_launch": flops * n, "kernel_us": kern * 1e6,
                 "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6}
     log(f"step {sec * 1e6:.1f} us (order {(sec - kern) * 1e6:.1f} us, fused kernel {kern * 1e6:.1f} us)")
@@ -658,6 +660,7 @@ def main():
         "dtype": HEADLINE_DTYPE,
         "data": "synthetic (seeded frame scene: 2,073,600 ground-to-area-light shadow rays; init-distribution latents and Xavier weights)",
         "config": {"workload": "frame: 1920x1080 shadow rays, 1 object, 8 levels 16..512, 2 binary16 latents, MLP 48-64x4-1",
+                   "grid_image": "z-y-pair",
                    "queries": n, "levels": sh.levels, "res_min": sh.res_min, "res_max": sh.res_max,
                    "hidden": sh.hidden, "width": sh.width, "grid_dtype": sh.grid_dtype},
         "roofline": roofline,

@@ -161,10 +161,12 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * nif_prepare also builds, for every object, a context-owned query image of
  * its grid in which the four latent pairs of a cell face (x..x+1, y..y+1) are
  * one 16-byte span, halving the gathers of a lookup; it costs twice the grid's
- * memory per object and is rebuilt by every nif_prepare.  Outputs are
- * bit-identical.  0 = gather from the grids (and, when ordering, also sort
- * each 4,096-query window by an 8-bit-per-axis Morton key, which pays off
- * only without the image). */
+ * memory per object and is rebuilt by every nif_prepare.  2 = a z-y-pair
+ * image in which the eight corners of a cell are one 32-byte span (one cache
+ * line for most cells), four times the grid's memory.  Outputs are
+ * bit-identical in every mode.  0 = gather from the grids (and, when
+ * ordering, also sort each 4,096-query window by an 8-bit-per-axis Morton
+ * key, which pays off only without an image). */
 enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2 };
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 

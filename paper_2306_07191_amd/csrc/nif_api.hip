@@ -193,12 +193,6 @@ extern "C" nif_status nif_create(const nif_model_desc* desc, int32_t num_objects
         }
     c->toff[3 * d.levels] = o;
     c->grid_elems = o;
-    o = 0;
-    for (int k = 0; k < 3 * d.levels; ++k) {
-        c->ioff[k] = o;
-        o += image_table_elems(c->res[k % d.levels]);
-    }
-    c->ioff[3 * d.levels] = o;
     c->P = (int64_t)d.width * c->din + (int64_t)(d.hidden_layers - 1) * d.width * d.width + d.width;
     c->image_mode = d.grid_dtype == NIF_F16 ? 1 : 0;
     c->objs.resize(num_objects);
@@ -308,10 +302,17 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     }
     // query images of the grids (rebuilt on every call: the grids may have changed)
     if (c->image_mode) {
+        int64_t o = 0;
+        for (int k = 0; k < 3 * c->d.levels; ++k) {
+            c->ioff[k] = o;
+            o += image_table_elems(c->res[k % c->d.levels], c->image_mode);
+        }
+        c->ioff[3 * c->d.levels] = o;
         if (c->images.size() != (size_t)c->K) c->images.assign(c->K, nullptr);
         for (int k = 0; k < c->K; ++k) {
             if (!c->images[k]) HIP_TRY(hipMalloc(&c->images[k], (size_t)c->ioff[3 * c->d.levels] * 2));
-            HIP_TRY(launch_build_image(c->objs[k].grid, c->images[k], c->toff, c->ioff, c->res, c->d.levels, s));
+            HIP_TRY(launch_build_image(c->objs[k].grid, c->images[k], c->toff, c->ioff, c->res, c->d.levels,
+                                       c->image_mode, s));
         }
         c->images_ready = true;
     }
@@ -373,11 +374,11 @@ extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) 
         c->order_mode = (int32_t)value;
         return ok();
     case NIF_OPT_GRID_IMAGE:
-        if (value < 0 || value > 1) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_GRID_IMAGE takes 0 or 1");
-        if (value == 1 && c->d.grid_dtype != NIF_F16)
+        if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_GRID_IMAGE takes 0, 1 or 2");
+        if (value > 0 && c->d.grid_dtype != NIF_F16)
             return fail(NIF_ERR_UNSUPPORTED, "NIF_OPT_GRID_IMAGE needs binary16 grids");
-        if (value == 0) free_images(c);
         if ((int32_t)value != c->image_mode) {
+            free_images(c);  // sizes differ between kinds
             c->image_mode = (int32_t)value;
             for (bool& p : c->prepared) p = false;
         }
@@ -403,7 +404,7 @@ static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const 
     FwdArgs a{};
     a.flags = c->d_flags;
     a.blocks_per_cu = blocks_per_cu;
-    a.use_image = c->image_mode && c->images_ready;
+    a.use_image = c->images_ready ? c->image_mode : 0;
     for (int k = 0; k < 3 * c->d.levels; ++k) a.ioff[k] = c->ioff[k];
     a.perm = perm;
     a.rays = rays;
@@ -483,7 +484,7 @@ extern "C" nif_status nif_query_ordered(nif_ctx* c, int32_t dtype, const float* 
 
 static void fill_common(const nif_ctx* c, FwdArgs& a) {
     a.flags = c->d_flags;
-    a.use_image = c->image_mode && c->images_ready;
+    a.use_image = c->images_ready ? c->image_mode : 0;
     for (int k = 0; k < 3 * c->d.levels; ++k) a.ioff[k] = c->ioff[k];
     a.objs = c->d_objs;
     a.num_objects = c->K;
@@ -853,7 +854,7 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
         p->sched = sc;
     } else {
         // autotune: every candidate once untimed, then the best of three timed runs
-        const Sched cand[] = {{0, 4}, {0, 8}, {0, 16}, {1, 4}, {1, 8}, {1, 16}, {2, 2}, {2, 4}, {2, 8}, {2, 16}};
+        const Sched cand[] = {{0, 8}, {0, 16}, {0, 32}, {1, 8}, {1, 16}, {1, 32}, {2, 4}, {2, 8}, {2, 16}, {2, 32}};
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));

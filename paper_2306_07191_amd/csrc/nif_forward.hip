@@ -234,6 +234,50 @@ __device__ __forceinline__ void encode_half_image(const float u[3][3], int half,
     }
 }
 
+// The same lookups from the z-y-pair image: entry (x, y, z) holds the latent
+// pairs of (x, y, z), (x, y+1, z), (x, y, z+1), (x, y+1, z+1), so the eight
+// corners of a cell are 32 contiguous bytes (entries x and x+1): two 16-byte
+// loads from one cache line (except when the pair straddles a line), same
+// corner order as encode_half.
+template <int L>
+__device__ __forceinline__ void encode_half_image2(const float u[3][3], int half, const GLOBAL _Float16* img,
+                                                   const FwdArgs& A, float* x) {
+    constexpr int NL = 3 * L / 2;
+    constexpr int G = NL < kImageBatch ? NL : kImageBatch;
+    static_assert(NL % G == 0, "batch must divide the lookups");
+#pragma unroll
+    for (int t0 = 0; t0 < NL; t0 += G) {
+        float w[G][3];
+        uint32_t q[G][2][4];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            uint32_t c[3];
+            const int k = lookup_cell<L>(u, half, t0 + i, A, c, w[i]);
+            const uint32_t N = (uint32_t)A.res[k % L], N1 = N + 1;
+            const uint32_t ent = (c[2] * N + c[1]) * N1 + c[0];  // entries of 8 latents (16 bytes)
+            const GLOBAL uint32_t* p = reinterpret_cast<const GLOBAL uint32_t*>(img + A.ioff[k]) + (uint64_t)ent * 4;
+#pragma unroll
+            for (int bx = 0; bx < 2; ++bx) {
+                const GLOBAL uint32_t* pf = p + 4 * bx;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) q[i][bx][j] = pf[j];  // one 16-byte load per x
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            float cw[8];
+            corner_weights(w[i], cw);
+            // entry dwords: (y, z), (y+1, z), (y, z+1), (y+1, z+1) -> corners bx + 2 by + 4 bz
+            f16x2v g[8];
+#pragma unroll
+            for (int bx = 0; bx < 2; ++bx)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) g[bx + 2 * j] = half_pair(q[i][bx][j]);
+            interp_pairs(cw, g, x[2 * (t0 + i)], x[2 * (t0 + i) + 1]);
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // MLP on MFMA.
 // ----------------------------------------------------------------------------
@@ -417,7 +461,7 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
 // ----------------------------------------------------------------------------
 // MODE 0: fused query.  MODE 1: grid stage only (writes the MLP inputs and the
 // clip status).  MODE 2: inference stage only (reads MLP inputs, one MLP).
-template <int FLAV, int L, typename GT, int MODE, bool IMG>
+template <int FLAV, int L, typename GT, int MODE, int IMG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == kF32 ? 2 : 3))) void nif_query_kernel(FwdArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int KH1 = 3 * L;  // layer-1 local inputs per half: 3L/2 lookups x 2 latents
@@ -504,8 +548,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
                 status = clip_normalise(o, d, tm, ob, u);
                 if (status == 1) {
                     mlp = ob.mlp;
-                    if constexpr (IMG)
+                    if constexpr (IMG == 1)
                         encode_half_image<L>(u, half, (const GLOBAL _Float16*)(ob.image), A, xin);
+                    else if constexpr (IMG == 2)
+                        encode_half_image2<L>(u, half, (const GLOBAL _Float16*)(ob.image), A, xin);
                     else
                         encode_half<L, GT>(u, half, (const GLOBAL GT*)(ob.grid), A, xin);
                 }
@@ -557,12 +603,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
     }
 }
 
-template <int FLAV, int L, typename GT, int MODE, bool IMG>
+template <int FLAV, int L, typename GT, int MODE, int IMG>
 static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     FwdArgs a = a0;
     const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
     // persistent-style grid: a few blocks per CU, a multiple of the 8 XCDs
-    int64_t blocks = (int64_t)num_cus * (a.blocks_per_cu > 0 ? a.blocks_per_cu : 8);
+    int64_t blocks = (int64_t)num_cus * (a.blocks_per_cu > 0 ? a.blocks_per_cu : 16);
     if (blocks > tiles) blocks = tiles;
     blocks = (blocks + 7) / 8 * 8;
     a.num_tiles = (int32_t)tiles;
@@ -580,17 +626,19 @@ static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
 
 template <int FLAV, int MODE>
 static hipError_t launch_f(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
-    const bool img = MODE != 2 && grid_dtype == 1 && a.use_image;
+    const int img = MODE != 2 && grid_dtype == 1 ? a.use_image : 0;
     if (levels == 8) {
         if (grid_dtype == 1)
-            return img ? launch_t<FLAV, 8, _Float16, MODE, true>(a, num_cus, s)
-                       : launch_t<FLAV, 8, _Float16, MODE, false>(a, num_cus, s);
-        return launch_t<FLAV, 8, float, MODE, false>(a, num_cus, s);
+            return img == 2   ? launch_t<FLAV, 8, _Float16, MODE, 2>(a, num_cus, s)
+                   : img == 1 ? launch_t<FLAV, 8, _Float16, MODE, 1>(a, num_cus, s)
+                              : launch_t<FLAV, 8, _Float16, MODE, 0>(a, num_cus, s);
+        return launch_t<FLAV, 8, float, MODE, 0>(a, num_cus, s);
     }
     if (grid_dtype == 1)
-        return img ? launch_t<FLAV, 4, _Float16, MODE, true>(a, num_cus, s)
-                   : launch_t<FLAV, 4, _Float16, MODE, false>(a, num_cus, s);
-    return launch_t<FLAV, 4, float, MODE, false>(a, num_cus, s);
+        return img == 2   ? launch_t<FLAV, 4, _Float16, MODE, 2>(a, num_cus, s)
+               : img == 1 ? launch_t<FLAV, 4, _Float16, MODE, 1>(a, num_cus, s)
+                          : launch_t<FLAV, 4, _Float16, MODE, 0>(a, num_cus, s);
+    return launch_t<FLAV, 4, float, MODE, 0>(a, num_cus, s);
 }
 
 hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {
@@ -667,7 +715,9 @@ hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t 
 // ----------------------------------------------------------------------------
 // y-pair query image of a binary16 grid.
 // ----------------------------------------------------------------------------
-int64_t image_table_elems(int32_t N) { return (int64_t)(N + 1) * N * (N + 1) * 4; }
+int64_t image_table_elems(int32_t N, int kind) {
+    return kind == 2 ? (int64_t)(N + 1) * N * N * 8 : (int64_t)(N + 1) * N * (N + 1) * 4;
+}
 
 __global__ void build_image_kernel(const uint32_t* __restrict__ grid, uint2* __restrict__ img, int64_t toff_pairs,
                                    int64_t ioff_entries, int32_t N) {
@@ -681,10 +731,33 @@ __global__ void build_image_kernel(const uint32_t* __restrict__ grid, uint2* __r
     }
 }
 
+__global__ void build_image2_kernel(const uint32_t* __restrict__ grid, uint4* __restrict__ img, int64_t toff_pairs,
+                                    int64_t ioff_entries, int32_t N) {
+    const int64_t N1 = N + 1;
+    const int64_t entries = N1 * N * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % N1, r = i / N1;
+        const int64_t y = r % N, z = r / N;
+        const int64_t v = (z * N1 + y) * N1 + x;  // vertex (x, y, z)
+        const int64_t sz = N1 * N1;
+        img[ioff_entries + i] =
+            make_uint4(grid[toff_pairs + v], grid[toff_pairs + v + N1], grid[toff_pairs + v + sz],
+                       grid[toff_pairs + v + sz + N1]);
+    }
+}
+
 hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
-                              const int32_t* res, int levels, hipStream_t s) {
+                              const int32_t* res, int levels, int kind, hipStream_t s) {
     for (int k = 0; k < 3 * levels; ++k) {
         const int32_t N = res[k % levels];
+        if (kind == 2) {
+            const int64_t entries = (int64_t)(N + 1) * N * N;
+            const int64_t blocks = (entries + 255) / 256 < 65536 ? (entries + 255) / 256 : 65536;
+            hipLaunchKernelGGL(build_image2_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                               reinterpret_cast<const uint32_t*>(grid), reinterpret_cast<uint4*>(image), toff[k] / 2,
+                               ioff[k] / 8, N);
+            continue;
+        }
         const int64_t entries = (int64_t)(N + 1) * N * (N + 1);
         const int64_t blocks = (entries + 255) / 256 < 65536 ? (entries + 255) / 256 : 65536;
         // offsets in latents: the grid's 2 latents per vertex are one dword, an

@@ -67,8 +67,8 @@ struct FwdArgs {
     int32_t tiles_per_block_num;  // tiles are split evenly: block b gets [b*T/G, (b+1)*T/G)
     int32_t num_tiles;
     int32_t xcd_stride;           // logical block = (b % 8) * xcd_stride + b / 8
-    int32_t blocks_per_cu;        // persistent grid size per compute unit (0: 8)
-    int32_t use_image;            // gather from the objects' y-pair images
+    int32_t blocks_per_cu;        // persistent grid size per compute unit (0: 16)
+    int32_t use_image;            // gather from the objects' images: 0 none, 1 y-pair, 2 z-y-pair
     uint32_t* flags;              // domain-error bits of the launch are OR-ed in here (nullable)
     int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
 };
@@ -175,9 +175,12 @@ hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hip
 // vertex (x, y, z) then those of (x, y+1, z); entries are x-fastest, so one
 // 16-byte load at entry (x, y, z) returns the four corners (x..x+1, y..y+1) of
 // a cell face.
-int64_t image_table_elems(int32_t N);
+// z-y-pair image (kind 2): entry (x, y, z), x in [0, N], y, z in [0, N-1],
+// holds the latent pairs of (x, y, z), (x, y+1, z), (x, y, z+1), (x, y+1, z+1);
+// the eight corners of a cell are then 32 contiguous bytes.
+int64_t image_table_elems(int32_t N, int kind);
 hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
-                              const int32_t* res, int levels, hipStream_t s);
+                              const int32_t* res, int levels, int kind, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // Up to 8 objects (of at most 64) whose boxes are near each other, for the
 // pair expansion: the union box and the member set.

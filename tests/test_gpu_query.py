@@ -277,15 +277,16 @@ def test_grid_image_is_bit_identical():
     ctx, model = make_pair(w, grid_amp=0.5)
     rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
     outs = {}
-    for img in (0, 1):
+    for img in (0, 1, 2):
         ctx.set_option(nif.NIF_OPT_GRID_IMAGE, img)
         for dtype in ("f32", "bf16"):
             outs[img, dtype] = run_query(ctx, w, dtype)
         ctx.prepare("f32")
         outs[img, "x"] = ctx.encode(rays, ids, tmax)[0].cpu().numpy()
-    for key in ("f32", "bf16", "x"):
-        np.testing.assert_array_equal(outs[0, key][0] if key != "x" else outs[0, key],
-                                      outs[1, key][0] if key != "x" else outs[1, key])
+    for img in (1, 2):
+        for key in ("f32", "bf16", "x"):
+            np.testing.assert_array_equal(outs[0, key][0] if key != "x" else outs[0, key],
+                                          outs[img, key][0] if key != "x" else outs[img, key])
     check_outputs(*outs[1, "f32"], model.forward(w["rays"], w["ids"], w["tmax"]), "f32", "image f32")
     # a changed grid is seen after nif_prepare
     ctx.init_grid(0, GRID_SEED + 1, 0.5)
