@@ -509,14 +509,70 @@ def run_scene(args):
     ctx.close()
 
 
+def run_tiny(args):
+    """The small case: 2,048 random triangles, 16,384 rays from a radius-3
+    sphere, 4 levels 4..32 with binary32 latents U(-1e-4, 1e-4), MLP
+    24-64x3-1, binary32 path.  Error against the binary64 oracle, labels by
+    brute force (oracle) and by the GPU BVH, misclassification of the
+    untrained model, oracle vs GPU queries/s.  Latency-bound: no roofline."""
+    import torch
+    from oracle import oracle as O
+    from paper_2306_07191_amd import nif, synth as S
+    w = S.tiny_workload()
+    n = w["ids"].shape[0]
+    ctx = nif.Context(w["shape"])
+    ctx.set_mlp(0, torch.from_numpy(w["mlps"][0]).cuda())
+    ctx.set_object(0, w["aabb"][0], ctx.alloc_grid(), 0)
+    ctx.init_grid(0, GRID_SEED, 1e-4)
+    ctx.prepare("f32")
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    y = torch.empty(n, device="cuda")
+    sec = time_launches(lambda: ctx.query(rays, ids, tmax, dtype="f32", out=y), args.steps, args.warmup)
+    model = O.Model(w["shape"], w["aabb"], w["mlps"], grid_seed=GRID_SEED, grid_amp=1e-4)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ref = model.forward(w["rays"], w["ids"], w["tmax"], nthreads=cores)
+    osec = time.perf_counter() - t0
+    hit = ref["status"] == 1
+    rel = np.abs(y.cpu().numpy().astype(np.float64)[hit] - ref["y"][hit]) / ref["y"][hit]
+    t0 = time.perf_counter()
+    exact = O.anyhit_brute(w["tris"], w["rays"], w["tmax"], nthreads=cores)
+    bsec = time.perf_counter() - t0
+    bvh = nif.BVH(w["tris"])
+    glab = bvh.anyhit(rays, tmax).cpu().numpy()
+    bvh.close()
+    mis = float(((y.cpu().numpy() >= 0.5) != (exact == 1)).mean())
+    log(f"tiny: {sec * 1e6:.1f} us = {n / sec / 1e6:.1f} M queries/s; max rel error {rel.max():.2e}, "
+        f"median {np.median(rel):.2e}; GPU BVH labels agree {float((glab == exact).mean()):.6f}; "
+        f"occluded {1 - exact.mean():.3f}")
+    out = {
+        "metric": "shadow-ray visibility queries/sec at stated error vs FP64 oracle",
+        "value": n / sec, "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded tiny scene: 2,048 random triangles, 16,384 rays)",
+        "config": {"workload": "tiny: 1 object, 2,048 triangles, 16,384 rays, 4 levels 4..32, binary32 latents, "
+                               "MLP 24-64x3-1", "queries": n},
+        "roofline": None,
+        "cpu_baseline": {"value": n / osec, "unit": "queries/s", "cores": cores, "kind": "oracle",
+                         "sample": f"all {n} tiny queries, binary64 encode+MLP"},
+        "error_vs_oracle": {"max_rel": float(rel.max()), "median_rel": float(np.median(rel))},
+        "labels": {"occluded_fraction": float(1 - exact.mean()), "gpu_bvh_agreement": float((glab == exact).mean()),
+                   "brute_force_oracle_rays_per_s": n / bsec},
+        "misclassification_untrained_f32": mis,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=("frame", "batched", "scene"), default="frame",
-                    help="frame: single-object 1920x1080 frame (default); batched: 32 objects, 4M Zipf queries; "
+    ap.add_argument("--workload", choices=("frame", "tiny", "batched", "scene"), default="frame",
+                    help="frame: single-object 1920x1080 frame (default); tiny: the 16,384-ray case; "
+                         "batched: 32 objects, 4M Zipf queries; "
                          "scene: 64 objects, 30M triangles, 8.3M shadow rays")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
@@ -545,6 +601,9 @@ def main():
         return
     if args.workload == "scene":
         run_scene(args)
+        return
+    if args.workload == "tiny":
+        run_tiny(args)
         return
     t0 = time.perf_counter()
     w = S.frame_workload(with_mesh=False)
@@ -629,11 +688,28 @@ def main():
     kern = sum(ev[2 * k + 1].elapsed_time(ev[2 * k + 2]) for k in range(args.steps)) / 1e3 / args.steps
     value = n / sec
     achieved_tflops = flops * n / kern / 1e12
+    # cold caches: a 512 MB write between launches evicts L2 and the Infinity Cache
+    cold = None
+    if not args.quick:
+        flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        ks = []
+        for _ in range(5):
+            flush.fill_(1.0)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
+            ctx.query_ordered(rays, ids, tmax, perm, dtype=HEADLINE_DTYPE, out=y)
+            ev1.record(s)
+            torch.cuda.synchronize()
+            ks.append(ev0.elapsed_time(ev1) / 1e3)
+        del flush
+        cold = {"kernel_us_median": float(np.median(ks)) * 1e6}
+        log(f"cold fused kernel: {cold['kernel_us_median']:.1f} us")
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_TFLOPS[HEADLINE_DTYPE],
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic(),
                 "kernel": "nif_query_kernel<bf16, L=8, f16 grid, z-y-pair image> (fused clip+encode+MLP)",
                 "algorithmic_flop_per_launch": flops * n, "kernel_us": kern * 1e6,
-                "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6}
+                "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6,
+                "gather_rate_per_s": 3 * sh.levels * 8 * n / kern, "cold": cold}
     log(f"step {sec * 1e6:.1f} us (order {(sec - kern) * 1e6:.1f} us, fused kernel {kern * 1e6:.1f} us)")
 
     cpu = None
