@@ -250,13 +250,14 @@ typedef struct {
 
 /* Training buffers.
  * nif_set_object_train: latent gradient, Adam moments m and v (dev,
- *   grid_elems floats each) and the touched-vertex bitmap (dev,
- *   nif_touched_bytes) of object obj.  grad and touched must be all zero
+ *   grid_elems floats each) and the touched-latent flags (dev,
+ *   nif_touched_bytes: one byte per 64 latents) of object obj.  grad and
+ *   touched must be all zero
  *   before the first step; steps with Adam leave them zero again; m and v
  *   start at zero.
  * nif_set_mlp_train: Adam moments of MLP mlp (dev, mlp_params floats each,
  *   zero at the start). */
-nif_status nif_set_object_train(nif_ctx* ctx, int32_t obj, float* grad, float* m, float* v, uint32_t* touched);
+nif_status nif_set_object_train(nif_ctx* ctx, int32_t obj, float* grad, float* m, float* v, void* touched);
 nif_status nif_set_mlp_train(nif_ctx* ctx, int32_t mlp, float* m, float* v);
 size_t nif_touched_bytes(const nif_ctx* ctx);
 

@@ -45,7 +45,7 @@ struct ObjHost {
     float* grad = nullptr;  // training buffers
     float* m = nullptr;
     float* v = nullptr;
-    uint32_t* touched = nullptr;
+    void* touched = nullptr;  // dirty flag per 64 latents (training)
 };
 
 struct nif_ctx {
@@ -623,12 +623,12 @@ extern "C" nif_status nif_mlp(nif_ctx* c, int32_t dtype, int32_t mlp, const floa
 
 extern "C" size_t nif_touched_bytes(const nif_ctx* c) {
     if (!c) return 0;
-    const int64_t vertices = c->grid_elems / c->d.feats;
-    return (size_t)((vertices + 31) / 32) * 4;
+    const int64_t chunks = (c->grid_elems + 63) / 64;  // one flag byte per 64 latents
+    return (size_t)((chunks + 3) / 4) * 4;
 }
 
 extern "C" nif_status nif_set_object_train(nif_ctx* c, int32_t obj, float* grad, float* m, float* v,
-                                           uint32_t* touched) {
+                                           void* touched) {
     if (!c || !grad || !m || !v || !touched) return fail(NIF_ERR_INVALID_ARG, "nif_set_object_train: NULL argument");
     if (obj < 0 || obj >= c->K) return fail(NIF_ERR_INVALID_ARG, "object %d out of range", obj);
     ObjHost& o = c->objs[obj];
@@ -727,7 +727,7 @@ static nif_status train_common(nif_ctx* c, int32_t mlp, const float* rays, const
     A.grid_grad = reinterpret_cast<float* const*>(c->d_train_tab + 0 * K);
     A.grid_m = reinterpret_cast<float* const*>(c->d_train_tab + 1 * K);
     A.grid_v = reinterpret_cast<float* const*>(c->d_train_tab + 2 * K);
-    A.touched = reinterpret_cast<uint32_t* const*>(c->d_train_tab + 3 * K);
+    A.touched = reinterpret_cast<uint8_t* const*>(c->d_train_tab + 3 * K);
     A.grids = c->d_train_tab + 4 * K;
     A.master = c->masters[mlp];
     A.mlp_m = c->mlp_m[mlp];
@@ -743,9 +743,8 @@ static nif_status train_common(nif_ctx* c, int32_t mlp, const float* rays, const
         A.adam.bc1 = (float)(1.0 - pow((double)adam->beta1, step));
         A.adam.bc2 = (float)(1.0 - pow((double)adam->beta2, step));
     }
-    const int64_t vertices = c->grid_elems / c->d.feats;
-    std::vector<int64_t> words(K, (vertices + 31) / 32);
-    HIP_TRY(launch_train(A, wsp, objs.data(), (int32_t)objs.size(), words.data(), c->d.grid_dtype, c->d.levels,
+    std::vector<int64_t> elems(K, c->grid_elems);
+    HIP_TRY(launch_train(A, wsp, objs.data(), (int32_t)objs.size(), elems.data(), c->d.grid_dtype, c->d.levels,
                          c->num_cus, s));
     if (adam) invalidate(c);  // the masters changed: packed copies are stale
     return ok();

@@ -125,7 +125,7 @@ struct TrainArgs {
     float* const* grid_grad;
     float* const* grid_m;
     float* const* grid_v;
-    uint32_t* const* touched;
+    uint8_t* const* touched;  // dirty flag per 64 latents
     void* const* grids;
     float* master;
     float* mlp_m;
@@ -152,7 +152,7 @@ size_t calib_workspace_bytes(int64_t n, int din);
 hipError_t launch_calibrate(const FwdArgs& enc, int levels, int grid_dtype, int num_cus, int32_t mlp, const float* W,
                             int din, int hidden, void* ws, unsigned* amax_host, hipStream_t s);
 hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_t num_obj_of_mlp,
-                        const int64_t* words_per_obj, int grid_dtype, int levels, int num_cus, hipStream_t s);
+                        const int64_t* elems_per_obj, int grid_dtype, int levels, int num_cus, hipStream_t s);
 
 size_t backward_image_bytes(int hidden);
 hipError_t launch_pack_forward(const float* W, uint8_t* out, const PackInfo& P, int flav, int din, int width,

@@ -17,13 +17,13 @@
 //     delta in a [feature][slot] workspace; the deltas are propagated with the
 //     transposed weight image; the feature gradient g_x comes out in the lane
 //     that encoded those features, which then scatter-adds weight * g_x into
-//     the grid gradient (binary32 atomics) and marks the touched vertices.
+//     the grid gradient (binary32 atomics) and flags the touched chunks.
 //  T2 train_dw_kernel: dW_j = sum over slots of delta_j x input_j (split-K on
 //     binary32 MFMA, one 32x32 tile per wave, deterministic per-chunk partials),
 //     then train_dw_reduce_kernel sums the partials in chunk order.
 //  T3 adam_mlp_kernel: dense Adam on the MLP master (binary32).
 //  T4 adam_grid_kernel: Adam on latents whose gradient is non-zero this step,
-//     found through the touched bitmap; clears gradient and bitmap.
+//     found through the dirty chunk flags; clears gradient and flags.
 #include <hip/hip_fp16.h>
 
 #include "nif_device.h"
@@ -86,7 +86,7 @@ __global__ void fill_zero_kernel(uint32_t* p, int n) {
 }
 
 // Gradient scatter of one interpolation corner: adds (v0, v1) to the two
-// latents at gg + el and marks the vertex in the touched bitmap.  Lanes with
+// latents at gg + el and flags their chunk.  Lanes with
 // gg == nullptr take no part.  Queries are ordered, so at the coarse levels
 // many lanes of a wave hit the same vertex, and same-address atomics serialise
 // in the L2: lanes are first grouped by (table, element) address, leader first,
@@ -95,18 +95,17 @@ __global__ void fill_zero_kernel(uint32_t* p, int n) {
 constexpr int kPeel = 6;
 
 // Global-address-space atomics: generic (flat) atomics would also wait on the
-// LDS counter.
-__device__ __forceinline__ void add_and_mark(float* p, uint32_t* tb, int64_t vtx, float s0, float s1) {
+// LDS counter.  The chunk of 64 latents holding the pair is flagged dirty with a
+// plain byte store (no read, no atomic): the Adam pass visits dirty chunks only.
+constexpr int kChunkShift = 6;  // latents per dirty flag: 64
+__device__ __forceinline__ void add_and_mark(float* p, uint8_t* dirty, int64_t el, float s0, float s1) {
     GLOBAL float* gp = (GLOBAL float*)p;
     if (s0 != 0.0f) __builtin_amdgcn_global_atomic_fadd_f32(gp, s0);
     if (s1 != 0.0f) __builtin_amdgcn_global_atomic_fadd_f32(gp + 1, s1);
-    const uint32_t bit = 1u << (vtx & 31);
-    GLOBAL uint32_t* word = (GLOBAL uint32_t*)tb + (vtx >> 5);
-    if (!(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
-        __hip_atomic_fetch_or(word, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (s0 != 0.0f || s1 != 0.0f) ((GLOBAL uint8_t*)dirty)[el >> kChunkShift] = 1;
 }
 
-__device__ __forceinline__ void scatter_corner(float* gg, uint32_t* tb, int64_t el, float v0, float v1, int lane) {
+__device__ __forceinline__ void scatter_corner(float* gg, uint8_t* tb, int64_t el, float v0, float v1, int lane) {
     const uintptr_t addr = gg ? (uintptr_t)(gg + el) : 0;
     uint64_t pend = __ballot(gg != nullptr);
     for (int it = 0; it < kPeel && pend; ++it) {
@@ -124,10 +123,10 @@ __device__ __forceinline__ void scatter_corner(float* gg, uint32_t* tb, int64_t 
                 s1 += __shfl_xor(s1, off);
             }
         }
-        if (lane == leader) add_and_mark(gg + el, tb, el / kFeats, s0, s1);
+        if (lane == leader) add_and_mark(gg + el, tb, el, s0, s1);
         pend &= ~grp;
     }
-    if ((pend >> lane) & 1) add_and_mark(gg + el, tb, el / kFeats, v0, v1);
+    if ((pend >> lane) & 1) add_and_mark(gg + el, tb, el, v0, v1);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
         // ---- scatter into the grid gradient; mark touched vertices
         if (!__ballot(active)) continue;  // wave-uniform
         float* gg = active ? A.grid_grad[id] : nullptr;
-        uint32_t* tb = active ? A.touched[id] : nullptr;
+        uint8_t* tb = active ? A.touched[id] : nullptr;
 #pragma unroll
         for (int t = 0; t < NL; ++t) {
             int64_t base;
@@ -412,28 +411,26 @@ __global__ void adam_mlp_kernel(TrainArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) *A.loss_out = B ? *A.loss_sum * inv : 0.0f;
 }
 
+// One wave per dirty chunk of 64 latents (coalesced): Adam on the latents
+// whose gradient is non-zero, gradient and flag cleared.
 template <typename GT>
-__global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t words) {
+__global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t elems) {
     const unsigned B = *A.count;
     const float inv = B ? 1.0f / (float)B : 0.0f;
     GLOBAL float* gg = (GLOBAL float*)A.grid_grad[obj];
     GLOBAL float* gm = (GLOBAL float*)A.grid_m[obj];
     GLOBAL float* gv = (GLOBAL float*)A.grid_v[obj];
-    GLOBAL uint32_t* tb = (GLOBAL uint32_t*)A.touched[obj];
+    GLOBAL uint8_t* dirty = (GLOBAL uint8_t*)A.touched[obj];
     GLOBAL GT* theta = (GLOBAL GT*)A.grids[obj];
-    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words; wi += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t bits = tb[wi];
-        if (!bits) continue;
-        tb[wi] = 0;
-        while (bits) {
-            const int b = __builtin_ctz(bits);
-            bits &= bits - 1;
-            const int64_t vtx = wi * 32 + b;
-#pragma unroll
-            for (int f = 0; f < kFeats; ++f) {
-                const int64_t el = vtx * kFeats + f;
-                const float graw = gg[el];
-                if (graw == 0.0f) continue;  // untouched this step: latent and moments keep their values
+    const int lane = threadIdx.x & 63;
+    const int64_t chunks = (elems + 63) >> kChunkShift;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ch < chunks; ch += waves) {
+        if (!dirty[ch]) continue;  // wave-uniform
+        const int64_t el = (ch << kChunkShift) + lane;
+        if (el < elems) {
+            const float graw = gg[el];
+            if (graw != 0.0f) {  // zero gradient: latent and moments keep their values
                 gg[el] = 0.0f;
                 float m = gm[el], v = gv[el];
                 const float th = adam_update((float)theta[el], graw * inv, m, v, A.adam);
@@ -442,27 +439,25 @@ __global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t words) {
                 theta[el] = (GT)th;
             }
         }
+        if (lane == 0) dirty[ch] = 0;
     }
 }
 
-// Gradient-only mode: scale the accumulated latent gradient by 1/B on the
-// touched vertices and clear the bitmap (the caller owns and clears the gradient).
-__global__ void scale_grid_grad_kernel(TrainArgs A, int32_t obj, int64_t words) {
+// Gradient-only mode: scale the accumulated latent gradient by 1/B in the dirty
+// chunks and clear the flags (the caller owns and clears the gradient).
+__global__ void scale_grid_grad_kernel(TrainArgs A, int32_t obj, int64_t elems) {
     const unsigned B = *A.count;
     const float inv = A.grad_y ? 1.0f : B ? 1.0f / (float)B : 0.0f;
-    float* gg = A.grid_grad[obj];
-    uint32_t* tb = A.touched[obj];
-    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words; wi += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t bits = tb[wi];
-        if (!bits) continue;
-        tb[wi] = 0;
-        while (bits) {
-            const int b = __builtin_ctz(bits);
-            bits &= bits - 1;
-            const int64_t vtx = wi * 32 + b;
-#pragma unroll
-            for (int f = 0; f < kFeats; ++f) gg[vtx * kFeats + f] *= inv;
-        }
+    GLOBAL float* gg = (GLOBAL float*)A.grid_grad[obj];
+    GLOBAL uint8_t* dirty = (GLOBAL uint8_t*)A.touched[obj];
+    const int lane = threadIdx.x & 63;
+    const int64_t chunks = (elems + 63) >> kChunkShift;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ch < chunks; ch += waves) {
+        if (!dirty[ch]) continue;
+        const int64_t el = (ch << kChunkShift) + lane;
+        if (el < elems) gg[el] *= inv;
+        if (lane == 0) dirty[ch] = 0;
     }
 }
 
@@ -491,7 +486,7 @@ size_t train_workspace_bytes(int64_t n, int din, int hidden, int64_t P, int64_t*
 }
 
 hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_t num_obj_of_mlp,
-                        const int64_t* words_per_obj, int grid_dtype, int levels, int num_cus, hipStream_t s) {
+                        const int64_t* elems_per_obj, int grid_dtype, int levels, int num_cus, hipStream_t s) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     int64_t chunk;
     train_workspace_bytes(A.n, A.din, A.hidden, A.P, &chunk);
@@ -538,14 +533,15 @@ hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_
         hipLaunchKernelGGL(mlp_grad_only_kernel, dim3((unsigned)((A.P + 255) / 256)), dim3(256), 0, s, A);
     for (int i = 0; i < num_obj_of_mlp; ++i) {
         const int32_t k = obj_of_mlp[i];
-        const int64_t words = words_per_obj[k];
-        const unsigned gb = (unsigned)((words + 255) / 256 < 65536 ? (words + 255) / 256 : 65536);
+        const int64_t elems = elems_per_obj[k];
+        const int64_t chunks = (elems + 63) >> kChunkShift;
+        const unsigned gb = (unsigned)((chunks + 3) / 4 < 65536 ? (chunks + 3) / 4 : 65536);  // 4 waves per block
         if (!A.apply_adam)
-            hipLaunchKernelGGL(scale_grid_grad_kernel, dim3(gb), dim3(256), 0, s, A, k, words);
+            hipLaunchKernelGGL(scale_grid_grad_kernel, dim3(gb), dim3(256), 0, s, A, k, elems);
         else if (grid_dtype == 1)
-            hipLaunchKernelGGL(adam_grid_kernel<_Float16>, dim3(gb), dim3(256), 0, s, A, k, words);
+            hipLaunchKernelGGL(adam_grid_kernel<_Float16>, dim3(gb), dim3(256), 0, s, A, k, elems);
         else
-            hipLaunchKernelGGL(adam_grid_kernel<float>, dim3(gb), dim3(256), 0, s, A, k, words);
+            hipLaunchKernelGGL(adam_grid_kernel<float>, dim3(gb), dim3(256), 0, s, A, k, elems);
     }
     return hipGetLastError();
 }
