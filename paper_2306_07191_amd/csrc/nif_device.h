@@ -58,6 +58,22 @@ __device__ __forceinline__ int clip_normalise(const float o[3], const float d[3]
     return 1;
 }
 
+// Entry point only (the ordering key): same segment test and same entry
+// coordinates as clip_normalise.
+__device__ __forceinline__ int clip_entry(const float o[3], const float d[3], float tmax, const ObjDev& b,
+                                          float uin[3]) {
+#pragma clang fp contract(off)
+    float ta, tb;
+    if (!clip_segment(o, d, tmax, b.lo, b.hi, ta, tb)) return 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float pin = o[a] + ta * d[a];
+        float ui = (pin - b.lo[a]) / b.ext[a];
+        uin[a] = ui > 0.0f ? (ui < 1.0f ? ui : 1.0f) : 0.0f;
+    }
+    return 1;
+}
+
 __device__ __forceinline__ bool valid_query(const float o[3], const float d[3], float tmax, int32_t id, int32_t K) {
     bool ok = true;
 #pragma unroll

@@ -84,8 +84,8 @@ struct OrderArgs {
     uint32_t num_buckets;  // (num_objects << 3 bits) + 1; the last holds misses and invalid queries
     int64_t tile;          // queries per block
     int64_t num_tiles;
-    uint32_t* table;       // num_buckets x num_tiles counts, then offsets
-    uint32_t* block_sums;
+    uint32_t* table;       // num_tiles x num_buckets counts, then per-bucket offsets over the tiles
+    uint32_t* block_sums;  // per bucket: total, then offset of the bucket
     uint16_t* key;         // bucket of every query
     uint32_t* fine;        // finer key of every query
     uint32_t* coarse;      // bucket order (before the window refinement)

@@ -8,14 +8,16 @@
 // AABB or are invalid go to a last bucket.
 //
 // Passes (no global atomics): (1) each block counts the buckets of its tile of
-// queries in LDS and writes the non-zero counts into a (bucket x tile) table;
-// (2) exclusive scan of that table in bucket-major order; (3) each block ranks
-// its queries inside (bucket, tile) with LDS counters and scatters
-// perm[offset + rank] = query.  The order inside a (bucket, tile) cell depends
-// on LDS atomic arrival; (4) every window of 4096 consecutive entries is then
-// sorted by a finer key (8 Morton bits per axis) in LDS, so that a wave's 32
-// queries cover a few finest-level cells (ties keep the bucket order).  The outputs do not depend on the
-// order, because every query is computed independently of its neighbours.
+// queries in LDS and writes them as one row of a (tile x bucket) table;
+// (2) per bucket, exclusive scan over the tiles, then exclusive scan of the
+// bucket totals; (3) each block ranks its queries inside (bucket, tile) with
+// LDS counters and scatters perm[bucket offset + tile offset + rank] = query.
+// The order inside a (bucket, tile) cell depends on LDS atomic arrival;
+// (4) optionally, every window of 4096 consecutive entries is then sorted by a
+// finer key (8 Morton bits per axis) in LDS, so that a wave's 32 queries cover
+// a few finest-level cells (ties keep the bucket order).  The outputs do not
+// depend on the order, because every query is computed independently of its
+// neighbours.
 #include <rocprim/block/block_radix_sort.hpp>
 
 #include "nif_device.h"
@@ -52,22 +54,40 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 // (object, Morton code with fine_bits per axis), 0xffffffff for a miss.  The
 // coarse code is a prefix of the fine one, so ordering by the fine key refines
 // the bucket order.
-__device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i, uint32_t* fine) {
-    const uint32_t cells = 1u << A.fine_bits;
+struct QueryIn {
+    float o[3], d[3], tm;
+    int32_t id;
+};
+
+__device__ __forceinline__ QueryIn load_query(const OrderArgs& A, int64_t i) {
+    QueryIn q;
     const float* r = A.rays + i * 6;
-    float o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
-    const float tm = A.tmax[i];
-    const int32_t id = A.ids[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.o[a] = r[a];
+        q.d[a] = r[3 + a];
+    }
+    q.tm = A.tmax[i];
+    q.id = A.ids[i];
+    return q;
+}
+
+__device__ __forceinline__ uint32_t order_key(const OrderArgs& A, const QueryIn& q, uint32_t* fine) {
+    const uint32_t cells = 1u << A.fine_bits;
+    const float* o = q.o;
+    const float* d = q.d;
+    const float tm = q.tm;
+    const int32_t id = q.id;
     uint32_t b = A.num_buckets - 1;
     *fine = 0xffffffffu;
     if (valid_query(o, d, tm, id, A.num_objects)) {
-        float u[3][3];
+        float uin[3];
         const ObjDev ob = A.objs[id];
-        if (clip_normalise(o, d, tm, ob, u)) {
+        if (clip_entry(o, d, tm, ob, uin)) {
             uint32_t c[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                uint32_t v = (uint32_t)(u[0][a] * (float)cells);  // u in [0, 1]
+                uint32_t v = (uint32_t)(uin[a] * (float)cells);  // u in [0, 1]
                 c[a] = v < cells ? v : cells - 1;
             }
             const uint32_t m = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
@@ -79,8 +99,9 @@ __device__ __forceinline__ uint32_t order_key(const OrderArgs& A, int64_t i, uin
 }
 
 // Pass 1: bucket of every query of the block's tile, counted in LDS; the
-// non-zero counts go to table[bucket * num_tiles + tile] (the table is zeroed).
+// counts of every bucket go to row `tile` of the table (tile-major).
 constexpr int kOrderThreads = 1024;
+constexpr int64_t kOrderTile = 8192;  // queries per block
 __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A) {
     extern __shared__ uint32_t cnt[];
     for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cnt[k] = 0;
@@ -88,26 +109,95 @@ __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A)
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
     for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
         uint32_t fine;
-        const uint32_t b = order_key(A, i, &fine);
+        const uint32_t b = order_key(A, load_query(A, i), &fine);
         A.key[i] = (uint16_t)b;
         if (!A.no_refine) A.fine[i] = fine;
         atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x)
-        if (cnt[k]) A.table[(int64_t)k * A.num_tiles + blockIdx.x] = cnt[k];
+    uint32_t* row = A.table + (int64_t)blockIdx.x * A.num_buckets;  // this tile's counts, every bucket
+    for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) row[k] = cnt[k];
 }
 
-// Pass 3: rank inside (bucket, tile) with an LDS counter; scatter.
+// Pass 2a: for every bucket, exclusive scan of its counts over the tiles (in
+// place) and the bucket's total.  A block takes 64 buckets; its 64 x 16
+// threads each own a segment of the tiles of one bucket: segment sums, their
+// exclusive scan in LDS, then the segment's offsets.
+constexpr int kScanBuckets = 64, kScanSegs = 16;
+__global__ __launch_bounds__(kScanBuckets* kScanSegs) void order_tile_scan_kernel(uint32_t* table, int64_t tiles,
+                                                                                  uint32_t nb, uint32_t* totals) {
+    __shared__ uint32_t seg_sum[kScanSegs][kScanBuckets];
+    const int lb = threadIdx.x % kScanBuckets, sg = threadIdx.x / kScanBuckets;
+    const uint32_t b = blockIdx.x * kScanBuckets + lb;
+    const int64_t per = (tiles + kScanSegs - 1) / kScanSegs;
+    const int64_t t0 = sg * per, t1 = t0 + per < tiles ? t0 + per : tiles;
+    uint32_t sum = 0;
+    if (b < nb)
+        for (int64_t t = t0; t < t1; ++t) sum += table[t * nb + b];
+    seg_sum[sg][lb] = sum;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int j = 0; j < sg; ++j) run += seg_sum[j][lb];
+    if (b < nb) {
+        for (int64_t t = t0; t < t1; ++t) {
+            const uint32_t v = table[t * nb + b];
+            table[t * nb + b] = run;
+            run += v;
+        }
+        if (sg == kScanSegs - 1) totals[b] = run;
+    }
+}
+
+// Pass 2b: exclusive scan of the bucket totals (at most 4097), one block.
+__global__ __launch_bounds__(1024) void order_bucket_scan_kernel(uint32_t* totals, uint32_t nb) {
+    __shared__ uint32_t part[1024];
+    constexpr int kPer = 5;  // 1024 x 5 >= 4097
+    const int tid = threadIdx.x;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t i = tid * kPer + j;
+        v[j] = i < nb ? totals[i] : 0u;
+        sum += v[j];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the thread sums
+        const uint32_t add = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t i = tid * kPer + j;
+        if (i < nb) totals[i] = run;
+        run += v[j];
+    }
+}
+
+// Pass 3: rank inside (bucket, tile) with an LDS counter; scatter to
+// bucket offset + tile offset + rank.
 __global__ __launch_bounds__(kOrderThreads) void order_rank_kernel(OrderArgs A) {
     extern __shared__ uint32_t cur[];
     for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cur[k] = 0;
     __syncthreads();
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
-    for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
-        const uint32_t b = A.key[i];
+    constexpr int kPer = kOrderTile / kOrderThreads;
+    uint32_t key[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = begin + threadIdx.x + (int64_t)j * kOrderThreads;
+        key[j] = i < end ? A.key[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = begin + threadIdx.x + (int64_t)j * kOrderThreads;
+        if (i >= end) continue;
+        const uint32_t b = key[j];
         const uint32_t r = atomicAdd(&cur[b], 1u);
-        A.coarse[A.table[(int64_t)b * A.num_tiles + blockIdx.x] + r] = (uint32_t)i;
+        A.coarse[A.block_sums[b] + A.table[(int64_t)blockIdx.x * A.num_buckets + b] + r] = (uint32_t)i;
     }
 }
 
@@ -282,10 +372,9 @@ static int fine_bits(int32_t num_objects) {
     return fb > 8 ? 8 : fb;
 }
 
-static constexpr int64_t kOrderTile = 8192;  // queries per block
 
 struct OrderLayout {
-    int64_t nb, tiles, table, scan_tiles;
+    int64_t nb, tiles, table;
     size_t off_table, off_sums, off_key, off_fine, off_coarse, off_perm, total;
 };
 
@@ -296,10 +385,9 @@ static OrderLayout order_layout(int64_t n, int32_t num_objects) {
     L.nb = ((int64_t)num_objects << (3 * bits)) + 1;
     L.tiles = (n + kOrderTile - 1) / kOrderTile;
     L.table = L.nb * L.tiles;
-    L.scan_tiles = (L.table + kScanTile - 1) / kScanTile;
     L.off_table = 0;
-    L.off_sums = al(L.table * 4);
-    L.off_key = L.off_sums + al(L.scan_tiles * 4);
+    L.off_sums = al(L.table * 4);  // bucket totals, then offsets
+    L.off_key = L.off_sums + al(L.nb * 4);
     L.off_fine = L.off_key + al(n * 2);
     L.off_coarse = L.off_fine + al(n * 4);
     L.off_perm = L.off_coarse + al(n * 4);
@@ -315,7 +403,6 @@ size_t order_workspace_bytes(int64_t n, int32_t num_objects) {
 hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out) {
     if (A.num_objects > 4096) return hipErrorInvalidValue;
     const OrderLayout L = order_layout(A.n, A.num_objects);
-    if (L.scan_tiles > kScanTile) return hipErrorInvalidValue;  // > 16M table entries
     A.bits = order_bits(A.num_objects);
     A.fine_bits = fine_bits(A.num_objects);
     if (A.fine_bits < A.bits) A.fine_bits = A.bits;
@@ -331,14 +418,10 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     if (!A.perm) A.perm = reinterpret_cast<uint32_t*>(p + L.off_perm);  // else the caller's buffer
     *perm_out = A.perm;
     const size_t lds = (size_t)L.nb * 4;
-    const unsigned fb = (unsigned)((L.table + 255) / 256 < 4096 ? (L.table + 255) / 256 : 4096);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(fb), dim3(256), 0, s, A.table, L.table, 0u);
     hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)L.scan_tiles), dim3(kScanThreads), 0, s, A.table, L.table,
-                       A.block_sums);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, A.block_sums, L.scan_tiles);
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)L.scan_tiles), dim3(kScanThreads), 0, s, A.table, L.table,
-                       A.block_sums);
+    hipLaunchKernelGGL(order_tile_scan_kernel, dim3((unsigned)((L.nb + kScanBuckets - 1) / kScanBuckets)),
+                       dim3(kScanBuckets * kScanSegs), 0, s, A.table, L.tiles, (uint32_t)L.nb, A.block_sums);
+    hipLaunchKernelGGL(order_bucket_scan_kernel, dim3(1), dim3(1024), 0, s, A.block_sums, (uint32_t)L.nb);
     if (A.no_refine) {
         A.coarse = A.perm;  // the bucket order is the result
         hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
