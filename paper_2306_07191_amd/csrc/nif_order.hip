@@ -9,9 +9,10 @@
 //
 // Passes (no global atomics): (1) each block counts the buckets of its tile of
 // queries in LDS and writes them as one row of a (tile x bucket) table;
-// (2) per bucket, exclusive scan over the tiles, then exclusive scan of the
-// bucket totals; (3) each block ranks its queries inside (bucket, tile) with
-// LDS counters and scatters perm[bucket offset + tile offset + rank] = query.
+// (2) per bucket, exclusive scan over the tiles and the bucket's total;
+// (3) each block scans the bucket totals into bucket offsets, ranks its
+// queries inside (bucket, tile) with LDS counters and scatters
+// perm[bucket offset + tile offset + rank] = query.
 // The order inside a (bucket, tile) cell depends on LDS atomic arrival;
 // (4) optionally, every window of 4096 consecutive entries is then sorted by a
 // finer key (8 Morton bits per axis) in LDS, so that a wave's 32 queries cover
@@ -119,11 +120,11 @@ __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A)
     for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) row[k] = cnt[k];
 }
 
-// Pass 2a: for every bucket, exclusive scan of its counts over the tiles (in
-// place) and the bucket's total.  A block takes 64 buckets; its 64 x 16
+// Pass 2: for every bucket, exclusive scan of its counts over the tiles (in
+// place) and the bucket's total.  A block takes 16 buckets; its 16 x 64
 // threads each own a segment of the tiles of one bucket: segment sums, their
 // exclusive scan in LDS, then the segment's offsets.
-constexpr int kScanBuckets = 64, kScanSegs = 16;
+constexpr int kScanBuckets = 16, kScanSegs = 64;
 __global__ __launch_bounds__(kScanBuckets* kScanSegs) void order_tile_scan_kernel(uint32_t* table, int64_t tiles,
                                                                                   uint32_t nb, uint32_t* totals) {
     __shared__ uint32_t seg_sum[kScanSegs][kScanBuckets];
@@ -148,56 +149,77 @@ __global__ __launch_bounds__(kScanBuckets* kScanSegs) void order_tile_scan_kerne
     }
 }
 
-// Pass 2b: exclusive scan of the bucket totals (at most 4097), one block.
-__global__ __launch_bounds__(1024) void order_bucket_scan_kernel(uint32_t* totals, uint32_t nb) {
-    __shared__ uint32_t part[1024];
-    constexpr int kPer = 5;  // 1024 x 5 >= 4097
-    const int tid = threadIdx.x;
-    uint32_t v[kPer], sum = 0;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const uint32_t i = tid * kPer + j;
-        v[j] = i < nb ? totals[i] : 0u;
-        sum += v[j];
-    }
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the thread sums
-        const uint32_t add = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += add;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - sum;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const uint32_t i = tid * kPer + j;
-        if (i < nb) totals[i] = run;
-        run += v[j];
-    }
-}
-
-// Pass 3: rank inside (bucket, tile) with an LDS counter; scatter to
-// bucket offset + tile offset + rank.
+// Pass 3: every block turns the bucket totals into bucket offsets (an
+// exclusive scan of at most 4097 values, redone by each block rather than in a
+// one-block pass of its own), adds its tile's offsets, then ranks its queries
+// inside (bucket, tile) with LDS counters and scatters to bucket offset + tile
+// offset + rank.
+constexpr int kMaxBuckets = 4097;
+constexpr int kRankPer = (kMaxBuckets + kOrderThreads - 1) / kOrderThreads;  // buckets per thread
 __global__ __launch_bounds__(kOrderThreads) void order_rank_kernel(OrderArgs A) {
-    extern __shared__ uint32_t cur[];
-    for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cur[k] = 0;
-    __syncthreads();
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wave_sum[kOrderThreads / 64];
+    const uint32_t nb = A.num_buckets;
+    uint32_t* base = lds;     // nb offsets
+    uint32_t* cur = lds + nb;  // nb rank counters
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
     constexpr int kPer = kOrderTile / kOrderThreads;
-    uint32_t key[kPer];
+    uint32_t key[kPer], trow[kRankPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const int64_t i = begin + threadIdx.x + (int64_t)j * kOrderThreads;
+        const int64_t i = begin + tid + (int64_t)j * kOrderThreads;
         key[j] = i < end ? A.key[i] : 0u;
     }
+    const uint32_t* row = A.table + (int64_t)blockIdx.x * nb;
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+        const uint32_t k = tid + j * kOrderThreads;
+        trow[j] = k < nb ? row[k] : 0u;
+        if (k < nb) base[k] = A.block_sums[k];
+    }
+    __syncthreads();
+    // Thread t owns buckets [t * kRankPer, (t + 1) * kRankPer).
+    uint32_t v[kRankPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+        const uint32_t k = tid * kRankPer + j;
+        v[j] = k < nb ? base[k] : 0u;
+        sum += v[j];
+    }
+    uint32_t x = sum;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_sum[w] = x;
+    __syncthreads();
+    uint32_t run = x - sum;
+    for (int j = 0; j < w; ++j) run += wave_sum[j];
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+        const uint32_t k = tid * kRankPer + j;
+        if (k < nb) base[k] = run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+        const uint32_t k = tid + j * kOrderThreads;
+        if (k < nb) {
+            base[k] += trow[j];
+            cur[k] = 0;
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const int64_t i = begin + threadIdx.x + (int64_t)j * kOrderThreads;
+        const int64_t i = begin + tid + (int64_t)j * kOrderThreads;
         if (i >= end) continue;
         const uint32_t b = key[j];
         const uint32_t r = atomicAdd(&cur[b], 1u);
-        A.coarse[A.block_sums[b] + A.table[(int64_t)blockIdx.x * A.num_buckets + b] + r] = (uint32_t)i;
+        A.coarse[base[b] + r] = (uint32_t)i;
     }
 }
 
@@ -421,13 +443,12 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
     hipLaunchKernelGGL(order_tile_scan_kernel, dim3((unsigned)((L.nb + kScanBuckets - 1) / kScanBuckets)),
                        dim3(kScanBuckets * kScanSegs), 0, s, A.table, L.tiles, (uint32_t)L.nb, A.block_sums);
-    hipLaunchKernelGGL(order_bucket_scan_kernel, dim3(1), dim3(1024), 0, s, A.block_sums, (uint32_t)L.nb);
     if (A.no_refine) {
         A.coarse = A.perm;  // the bucket order is the result
-        hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
+        hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), 2 * lds, s, A);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), lds, s, A);
+    hipLaunchKernelGGL(order_rank_kernel, dim3((unsigned)L.tiles), dim3(kOrderThreads), 2 * lds, s, A);
     hipLaunchKernelGGL(order_refine_kernel, dim3((unsigned)((A.n + kRefine - 1) / kRefine)), dim3(256), 0, s, A);
     return hipGetLastError();
 }
