@@ -664,11 +664,12 @@ def main():
     # the fused query kernel; events around the kernel give its own duration
     ctx.prepare(HEADLINE_DTYPE)
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    recs = torch.empty((n, 8), dtype=torch.float32, device="cuda")  # the queries as 32-byte records
     ows = torch.empty(max(1, nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
 
     def step():
-        ctx.order(rays, ids, tmax, perm=perm, ws=ows)
-        ctx.query_ordered(rays, ids, tmax, perm, dtype=HEADLINE_DTYPE, out=y)
+        ctx.order_packed(rays, ids, tmax, perm=perm, packed=recs, ws=ows)
+        ctx.query_packed(recs, perm, dtype=HEADLINE_DTYPE, out=y)
 
     for _ in range(args.warmup):
         step()
@@ -678,9 +679,9 @@ def main():
     w0 = time.perf_counter()
     ev[0].record(s)
     for k in range(args.steps):
-        ctx.order(rays, ids, tmax, perm=perm, ws=ows)
+        ctx.order_packed(rays, ids, tmax, perm=perm, packed=recs, ws=ows)
         ev[2 * k + 1].record(s)
-        ctx.query_ordered(rays, ids, tmax, perm, dtype=HEADLINE_DTYPE, out=y)
+        ctx.query_packed(recs, perm, dtype=HEADLINE_DTYPE, out=y)
         ev[2 * k + 2].record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -697,7 +698,7 @@ def main():
             flush.fill_(1.0)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(s)
-            ctx.query_ordered(rays, ids, tmax, perm, dtype=HEADLINE_DTYPE, out=y)
+            ctx.query_packed(recs, perm, dtype=HEADLINE_DTYPE, out=y)
             ev1.record(s)
             torch.cuda.synchronize()
             ks.append(ev0.elapsed_time(ev1) / 1e3)

@@ -156,7 +156,8 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
 /* Options.  NIF_OPT_ORDER: before a query, bucket-sort the queries by
  * (object, Morton code of the AABB entry point) so that a wave's gathers share
  * cache lines and waves use one MLP: 0 never, 1 always, 2 (default) when
- * n >= 65536.  Changes nif_workspace_bytes.
+ * n >= 65536.  Changes nif_workspace_bytes (the ordering workspace plus the
+ * queries as 32-byte records, see nif_order_packed).
  * NIF_OPT_GRID_IMAGE (binary16 grids only): 1 (default for binary16 grids) =
  * nif_prepare also builds, for every object, a context-owned query image of
  * its grid in which the four latent pairs of a cell face (x..x+1, y..y+1) are
@@ -195,13 +196,26 @@ nif_status nif_query(nif_ctx* ctx, int32_t dtype, const float* rays, const int32
  *   and invalid queries last.  ws: nif_order_workspace_bytes(ctx, n) bytes.
  *   Needs nif_prepare (any dtype) for the object table.
  * nif_query_ordered: as nif_query, processing query perm[i] in slot i; perm
- *   must be a permutation of [0, n) (any order gives the same outputs). */
+ *   must be a permutation of [0, n) (any order gives the same outputs).
+ * nif_order_packed: as nif_order, and the ordering pass, which reads every
+ *   query anyway, also stores query i as one 32-byte record: packed (dev,
+ *   n x 8 floats, 16-byte aligned) row i = {ox, oy, oz, dx, dy, dz, t_max,
+ *   object id (int32 bit pattern)}.  The query kernel, whose reads through
+ *   perm are scattered, then fetches one 32-byte span per query instead of
+ *   pieces of three arrays.
+ * nif_query_packed: as nif_query_ordered with the queries given as those
+ *   records (row perm[i] is computed in slot i, output perm[i]).  nif_query
+ *   with ordering does the same internally. */
 size_t nif_order_workspace_bytes(const nif_ctx* ctx, int64_t n);
 nif_status nif_order(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max, int64_t n,
                      uint32_t* perm, void* ws, size_t ws_bytes, void* stream);
 nif_status nif_query_ordered(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids,
                              const float* t_max, const uint32_t* perm, int64_t n, float* visibility, float* logits,
                              void* stream);
+nif_status nif_order_packed(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max, int64_t n,
+                            uint32_t* perm, float* packed, void* ws, size_t ws_bytes, void* stream);
+nif_status nif_query_packed(nif_ctx* ctx, int32_t dtype, const float* packed, const uint32_t* perm, int64_t n,
+                            float* visibility, float* logits, void* stream);
 
 /* Query plans for repeated batches on fixed buffers (the batched form: rays
  * of many objects of uneven size in one persistent launch, Sec. 4.1 issues one

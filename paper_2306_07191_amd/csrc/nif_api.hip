@@ -358,12 +358,21 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
 
 static size_t train_bytes(const nif_ctx* c, int64_t n);
 
+// Ordering workspace followed by the queries as 32-byte records (the ordering
+// layout is a multiple of 256 bytes).
+static size_t order_packed_bytes(const nif_ctx* c, int64_t n) {
+    return order_workspace_bytes(n, c->K) + (size_t)n * 32;
+}
+static float4* records_in(const nif_ctx* c, void* ws, int64_t n) {
+    return reinterpret_cast<float4*>(reinterpret_cast<uint8_t*>(ws) + order_workspace_bytes(n, c->K));
+}
+
 extern "C" size_t nif_workspace_bytes(const nif_ctx* c, int64_t n, int32_t mode) {
     if (!c || n < 0) return 0;
     if (mode == 2) return calib_workspace_bytes(n, c->din);  // also n = 0: the maxima words
     if (n == 0) return 0;
     if (mode == 1) return train_bytes(c, n);
-    return uses_order(c, n) ? order_workspace_bytes(n, c->K) : 0;
+    return uses_order(c, n) ? order_packed_bytes(c, n) : 0;
 }
 
 extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) {
@@ -400,8 +409,9 @@ static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, 
 
 static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
                             const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s,
-                            int32_t blocks_per_cu = 0) {
+                            int32_t blocks_per_cu = 0, const float4* qrec = nullptr) {
     FwdArgs a{};
+    a.qrec = qrec;
     a.flags = c->d_flags;
     a.blocks_per_cu = blocks_per_cu;
     a.use_image = c->images_ready ? c->image_mode : 0;
@@ -427,8 +437,9 @@ static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const 
 
 static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
                             uint32_t* perm_dst, void* ws, const uint32_t** perm, hipStream_t s,
-                            bool refine = true) {
+                            bool refine = true, float4* qrec = nullptr) {
     OrderArgs o{};
+    o.qrec = qrec;
     o.no_refine = refine ? 0 : 1;
     o.rays = rays;
     o.ids = ids;
@@ -449,11 +460,13 @@ extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, co
     if (ws_bytes < need || (need > 0 && !ws)) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
     const uint32_t* perm = nullptr;
+    float4* qrec = nullptr;
     if (need > 0) {
-        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, !c->image_mode);
+        qrec = records_in(c, ws, n);
+        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, !c->image_mode, qrec);
         if (st != NIF_OK) return st;
     }
-    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream);
+    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec);
 }
 
 extern "C" size_t nif_order_workspace_bytes(const nif_ctx* c, int64_t n) {
@@ -470,6 +483,33 @@ extern "C" nif_status nif_order(nif_ctx* c, const float* rays, const int32_t* id
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
     const uint32_t* p = nullptr;
     return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, !c->image_mode);
+}
+
+extern "C" nif_status nif_order_packed(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax,
+                                       int64_t n, uint32_t* perm, float* packed, void* ws, size_t ws_bytes,
+                                       void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, perm, "nif_order_packed");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    if (!packed) return fail(NIF_ERR_INVALID_ARG, "nif_order_packed: NULL packed");
+    if (reinterpret_cast<uintptr_t>(packed) % 16 != 0)
+        return fail(NIF_ERR_INVALID_ARG, "nif_order_packed: packed must be 16-byte aligned");
+    const size_t need = order_workspace_bytes(n, c->K);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    const uint32_t* p = nullptr;
+    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, !c->image_mode,
+                     reinterpret_cast<float4*>(packed));
+}
+
+extern "C" nif_status nif_query_packed(nif_ctx* c, int32_t dtype, const float* packed, const uint32_t* perm,
+                                       int64_t n, float* vis, float* logits, void* stream) {
+    nif_status st = check_query_args(c, dtype, packed, perm, packed, n, vis, "nif_query_packed");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    if (reinterpret_cast<uintptr_t>(packed) % 16 != 0)
+        return fail(NIF_ERR_INVALID_ARG, "nif_query_packed: packed must be 16-byte aligned");
+    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    return run_query(c, dtype, nullptr, nullptr, nullptr, perm, n, vis, logits, (hipStream_t)stream, 0,
+                     reinterpret_cast<const float4*>(packed));
 }
 
 extern "C" nif_status nif_query_ordered(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids,
@@ -798,11 +838,14 @@ struct nif_plan {
 
 static nif_status plan_run(nif_plan* p, const Sched& sc, hipStream_t s) {
     const uint32_t* perm = nullptr;
+    float4* qrec = nullptr;
     if (sc.order > 0) {
-        nif_status st = run_order(p->c, p->rays, p->ids, p->tmax, p->n, nullptr, p->ws, &perm, s, sc.order == 2);
+        qrec = records_in(p->c, p->ws, p->n);
+        nif_status st = run_order(p->c, p->rays, p->ids, p->tmax, p->n, nullptr, p->ws, &perm, s, sc.order == 2, qrec);
         if (st != NIF_OK) return st;
     }
-    return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu);
+    return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu,
+                     qrec);
 }
 
 static bool parse_int_key(const char* js, const char* key, int32_t* v) {
@@ -819,7 +862,7 @@ static bool parse_int_key(const char* js, const char* key, int32_t* v) {
 
 extern "C" size_t nif_plan_workspace_bytes(const nif_ctx* c, int64_t n) {
     if (!c || n <= 0) return 0;
-    return order_workspace_bytes(n, c->K);
+    return order_packed_bytes(c, n);
 }
 
 extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids,
@@ -831,7 +874,7 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
     if (st != NIF_OK) return st;
     if (n == 0) return fail(NIF_ERR_INVALID_ARG, "nif_plan_create: n must be > 0");
     if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
-    const size_t need = order_workspace_bytes(n, c->K);
+    const size_t need = order_packed_bytes(c, n);
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     std::unique_ptr<nif_plan> p(new nif_plan);
     p->c = c;

@@ -456,6 +456,12 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
     return zp + __shfl_xor(zp, 32);
 }
 
+// Object id of the query in processing slot `slot` (slot < n).
+__device__ __forceinline__ int32_t slot_object(const FwdArgs& A, int64_t slot) {
+    const int64_t q = A.perm ? (int64_t)A.perm[slot] : slot;
+    return A.qrec ? __float_as_int(A.qrec[2 * q + 1].w) : A.ids[q];
+}
+
 // ----------------------------------------------------------------------------
 // The fused kernel.
 // ----------------------------------------------------------------------------
@@ -481,8 +487,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
     // MLP of the block: that of the first query of its first tile
     int32_t blk_mlp = A.fixed_mlp;
     if (MODE == 0) {
-        int64_t q0 = t_begin * kQueriesPerBlock;
-        int32_t id0 = A.ids[A.perm ? (int64_t)A.perm[q0] : q0];
+        const int32_t id0 = slot_object(A, t_begin * kQueriesPerBlock);
         if (id0 >= 0 && id0 < A.num_objects) blk_mlp = A.objs[id0].mlp;
     }
     if (MODE != 1) {
@@ -497,8 +502,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
         if (MODE == 0 && tile > t_begin) {
             // ordered queries change MLP at object boundaries: follow the MLP of
             // the tile's first query (a block-uniform decision)
-            const int64_t q0 = tile * kQueriesPerBlock;
-            const int32_t id0 = A.ids[A.perm ? (int64_t)A.perm[q0] : q0];
+            const int32_t id0 = slot_object(A, tile * kQueriesPerBlock);
             const int32_t m = id0 >= 0 && id0 < A.num_objects ? A.objs[id0].mlp : blk_mlp;
             if (m != blk_mlp) {
                 __syncthreads();
@@ -517,11 +521,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
         float tm = 0.0f;
         int32_t id = -1;
         if (inb && MODE != 2) {
-            const float* r = A.rays + q * 6;
+            if (A.qrec) {  // one 32-byte record instead of three arrays
+                const float4 r0 = A.qrec[2 * q], r1 = A.qrec[2 * q + 1];
+                o[0] = r0.x; o[1] = r0.y; o[2] = r0.z;
+                d[0] = r0.w; d[1] = r1.x; d[2] = r1.y;
+                tm = r1.z;
+                id = __float_as_int(r1.w);
+            } else {
+                const float* r = A.rays + q * 6;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
-            tm = A.tmax[q];
-            id = A.ids[q];
+                for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
+                tm = A.tmax[q];
+                id = A.ids[q];
+            }
         }
         // status: 1 query, 0 miss (visible), -1 invalid, -2 out of range
         int status = -2;

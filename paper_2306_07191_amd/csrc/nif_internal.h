@@ -71,6 +71,7 @@ struct FwdArgs {
     int32_t use_image;            // gather from the objects' images: 0 none, 1 y-pair, 2 z-y-pair
     uint32_t* flags;              // domain-error bits of the launch are OR-ed in here (nullable)
     int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
+    const float4* qrec;           // nullable: query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
 };
 
 struct OrderArgs {
@@ -92,6 +93,7 @@ struct OrderArgs {
     int32_t fine_bits;
     int32_t no_refine;     // 1: bucket order only (skip the window sort)
     uint32_t* perm;
+    float4* qrec;          // nullable: receives query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
 };
 
 int order_bits(int32_t num_objects);

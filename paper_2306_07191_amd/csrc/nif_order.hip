@@ -110,7 +110,12 @@ __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A)
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
     for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
         uint32_t fine;
-        const uint32_t b = order_key(A, load_query(A, i), &fine);
+        const QueryIn q = load_query(A, i);
+        if (A.qrec) {  // the query as one 32-byte record, for the gathers through the order
+            A.qrec[2 * i] = make_float4(q.o[0], q.o[1], q.o[2], q.d[0]);
+            A.qrec[2 * i + 1] = make_float4(q.d[1], q.d[2], q.tm, __int_as_float(q.id));
+        }
+        const uint32_t b = order_key(A, q, &fine);
         A.key[i] = (uint16_t)b;
         if (!A.no_refine) A.fine[i] = fine;
         atomicAdd(&cnt[b], 1u);

@@ -29,6 +29,7 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
            "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
            "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
+           "nif_order_packed", "nif_query_packed",
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
            "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
            "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit",
@@ -80,6 +81,8 @@ def lib():
             "nif_order_workspace_bytes": (sz, [vp, i64]),
             "nif_order": (i32, [vp, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_query_ordered": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp]),
+            "nif_order_packed": (i32, [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+            "nif_query_packed": (i32, [vp, i32, vp, vp, i64, vp, vp, vp]),
             "nif_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
             "nif_plan_workspace_bytes": (sz, [vp, i64]),
             "nif_plan_create": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, C.c_char_p, vp, vp]),
@@ -346,6 +349,31 @@ class Context:
             out = t.empty(n, dtype=t.float32, device=self.device)
         _check(lib().nif_query_ordered(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(perm), n,
                                        _ptr(out), _ptr(logits), _stream()), "nif_query_ordered")
+        return out
+
+    def order_packed(self, rays, ids, tmax, perm=None, packed=None, ws=None):
+        """Ordering step that also stores every query as a 32-byte record:
+        (perm, packed [n, 8] float32 rows o, d, t_max, object id bits)."""
+        t = self.torch
+        n = ids.shape[0]
+        if perm is None:
+            perm = t.empty(n, dtype=t.int32, device=self.device)
+        if packed is None:
+            packed = t.empty((n, 8), dtype=t.float32, device=self.device)
+        if ws is None:
+            ws = t.empty(max(1, int(lib().nif_order_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
+        _check(lib().nif_order_packed(self.h, _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(perm), _ptr(packed),
+                                      _ptr(ws), ws.numel(), _stream()), "nif_order_packed")
+        return perm, packed
+
+    def query_packed(self, packed, perm, dtype: str = "f32", out=None, logits=None):
+        """Query on the records of order_packed, in the order perm; outputs in query order."""
+        t = self.torch
+        n = perm.shape[0]
+        if out is None:
+            out = t.empty(n, dtype=t.float32, device=self.device)
+        _check(lib().nif_query_packed(self.h, DTYPES[dtype], _ptr(packed), _ptr(perm), n, _ptr(out),
+                                      _ptr(logits), _stream()), "nif_query_packed")
         return out
 
     def encode(self, rays, ids, tmax):

@@ -241,6 +241,45 @@ def test_order_is_a_grouped_permutation():
     assert (np.diff(ids[perm[:nh]]) >= 0).all()          # grouped by object
 
 
+def test_packed_query_records():
+    """The ordering pass can also store every query as one 32-byte record
+    (row i = query i, bit for bit); the query on the records through the order
+    (nif_query with ordering reads them internally) gives the outputs of the
+    unordered query, with and without a query image (bucket order alone, or
+    bucket order and the window sort)."""
+    import torch
+    from paper_2306_07191_amd import nif
+    n = 40000
+    w = S.frame_workload(n_rays=n, with_mesh=False)
+    w["rays"][::89, 3:] *= -1.0     # misses
+    w["tmax"][::1003] = np.nan      # invalid queries
+    w["ids"][::2001] = 5            # object id out of range
+    ctx, model = make_pair(w, grid_amp=0.5)
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    ctx.set_option(nif.NIF_OPT_ORDER, 0)
+    base = {dt: run_query(ctx, w, dt) for dt in ("f32", "bf16")}
+    check_outputs(*base["f32"], model.forward(w["rays"], w["ids"], w["tmax"]), "f32", "unordered f32")
+    expect = np.concatenate([w["rays"], w["tmax"][:, None], w["ids"].view(np.float32)[:, None]], axis=1)
+    ctx.set_option(nif.NIF_OPT_ORDER, 1)
+    for img in (0, 1, 2):
+        ctx.set_option(nif.NIF_OPT_GRID_IMAGE, img)
+        for dt in ("f32", "bf16"):
+            got = run_query(ctx, w, dt)
+            np.testing.assert_array_equal(got[0], base[dt][0])
+            np.testing.assert_array_equal(got[1], base[dt][1])
+        ctx.prepare("bf16")
+        perm, rec = ctx.order_packed(rays, ids, tmax)
+        p = perm.cpu().numpy().view(np.uint32).astype(np.int64)
+        assert np.array_equal(np.sort(p), np.arange(n))
+        np.testing.assert_array_equal(rec.cpu().numpy().view(np.uint32), expect.view(np.uint32))
+        y = ctx.query_packed(rec, perm, dtype="bf16")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(y.cpu().numpy().astype(np.float64), base["bf16"][0])
+    bad = torch.empty(8 * n + 1, dtype=torch.float32, device="cuda")[1:]  # 4-byte offset
+    with pytest.raises(nif.NifError):
+        ctx.order_packed(rays, ids, tmax, packed=bad)
+
+
 def test_gpu_bvh_labels_match_oracle():
     """GPU BVH any-hit (binary32 watertight test) vs the oracle's exact binary64 labels."""
     import torch
