@@ -1,0 +1,184 @@
+"""Pins of the binary64 oracle of the paper's own networks (outer and inner
+NIF networks with spherical 2D grids, Sec. 3.1, Sec. 3.2, Sec. 5, Table 1)
+against closed forms, invariants and hand-computed cases."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import paper_nets as PN
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+BOX = np.array([[-1.0, -2.0, 0.5, 3.0, 2.0, 1.5]], np.float32)  # non-cubic on purpose
+
+
+def test_network_sizes_match_table_1_and_memory_footprint():
+    """Sec. 5: 18 kB (outer) and 21 kB (inner) of binary32 weights, with the
+    inputs of Table 1 (3+3 and 5+5+3 latents) and no biases."""
+    assert PN.OUTER["R"] == GOLD["outer_grid"]["R"] and PN.OUTER["N"] == GOLD["outer_grid"]["N"]
+    assert PN.INNER["R"] == GOLD["inner_grid_2d"]["R"] and PN.INNER["N"] == GOLD["inner_grid_2d"]["N"]
+    assert PN.INNER["R1"] == GOLD["inner_grid_1d"]["R"] and PN.INNER["N1"] == GOLD["inner_grid_1d"]["N"]
+    assert PN.mlp_params(0) == 6 * 64 + 64 * 64 + 64 == 4544
+    assert PN.mlp_params(1) == 13 * 48 + 2 * 48 * 48 + 48 == 5280
+    assert round(PN.mlp_params(0) * 4 / 1024) == GOLD["outer_network_runtime_kB"]["value"]
+    assert round(PN.mlp_params(1) * 4 / 1024) == GOLD["inner_network_runtime_kB"]["value"]
+
+
+def test_rounding_matches_the_c_oracle():
+    """numpy RNE to bf16 / f16 agrees with the C oracle's rounding (itself
+    pinned on bit patterns and ties) on normal, f16-subnormal and tie values."""
+    g = np.random.default_rng(3)
+    vals = np.concatenate([g.normal(size=300), g.normal(size=300) * 1e-5, g.normal(size=100) * 1e-7,
+                           [1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -11, 2 ** -24 * 1.5, -(2 ** -24) * 2.5, 0.0]])
+    for fmt in ("bf16", "f16"):
+        np.testing.assert_array_equal(PN.round_to(vals, fmt), O.round_fmt_array(vals, fmt))
+
+
+def test_spherical_map_closed_forms():
+    q = np.array([[0, 0, 1], [0, 0, -1], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 0], [1, 1, 0]], float)
+    u, v = PN.sph(q)
+    np.testing.assert_allclose(u, [0, 1, 0.5, 0.5, 0.5, 0.5, 0, 0.5], atol=1e-15)
+    np.testing.assert_allclose(v, [0.5, 0.5, 0.5, 1.0, 0.75, 0.25, 0.5, 0.625], atol=1e-15)
+
+
+def _outside_rays(g, n, box, back=0.0):
+    lo, hi = box[0, :3].astype(float), box[0, 3:].astype(float)
+    target = lo + g.uniform(0.05, 0.95, (n, 3)) * (hi - lo)
+    dirs = g.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    o = target - (6.0 + back) * dirs
+    return np.concatenate([o, dirs], 1).astype(np.float32)
+
+
+def test_outer_transform_is_invariant_along_the_ray():
+    """Sec. 2 and Sec. 3.1: moving the origin back along d (still outside the
+    box) gives the same entry point, so the same (p', d')."""
+    g = np.random.default_rng(4)
+    n = 500
+    rays = _outside_rays(g, n, BOX)
+    ids = np.zeros(n, np.int32)
+    tmax = np.full(n, np.inf, np.float32)
+    a = PN.transform(rays, ids, tmax, BOX)
+    moved = rays.astype(np.float64).copy()
+    moved[:, :3] -= 3.0 * moved[:, 3:]
+    b = PN.transform(moved.astype(np.float32), ids, tmax, BOX)
+    assert (a[0] == PN.CLS_OUTER).all() and (b[0] == PN.CLS_OUTER).all()
+    for k in (1, 2, 3, 4):  # binary32 inputs and clip: a few ulp of the entry point
+        np.testing.assert_allclose(a[k], b[k], atol=2e-6)
+    np.testing.assert_array_equal(a[3], b[3])  # the direction is exactly the same
+    np.testing.assert_array_equal(a[4], b[4])
+
+
+def test_entry_point_maps_to_its_face():
+    """A ray straight down the -z axis enters through the top face centre:
+    theta = 0 (u = 0); one along +x enters the x = lo face centre: u = 1/2, v = 1."""
+    rays = np.array([[1.0, 0.0, 9.0, 0.0, 0.0, -1.0], [-9.0, 0.0, 1.0, 1.0, 0.0, 0.0]], np.float32)
+    cls, pu, pv, du, dv, r = PN.transform(rays, np.zeros(2, np.int32), np.full(2, np.inf, np.float32), BOX)
+    assert list(cls) == [PN.CLS_OUTER] * 2
+    np.testing.assert_allclose([pu[0], pu[1], pv[1]], [0.0, 0.5, 1.0], atol=1e-15)
+    np.testing.assert_allclose([du[0], du[1], dv[1]], [1.0, 0.5, 0.5], atol=1e-15)
+    np.testing.assert_allclose(r, [1 / math.sqrt(3), 1 / math.sqrt(3)], atol=1e-15)
+
+
+def test_classes():
+    rays = np.array([[1, 0, 1, 0, 0, 1],            # origin inside: inner
+                     [1, 0, 9, 0, 0, -1],           # outside, towards the box: outer
+                     [1, 0, 9, 0, 0, 1],            # outside, away: miss
+                     [1, 0, 9, 0, 0, -1],           # t_max too short: miss
+                     [np.nan, 0, 0, 1, 0, 0],       # invalid
+                     [1, 0, 9, 0, 0, -1]], np.float32)
+    ids = np.array([0, 0, 0, 0, 0, 3], np.int32)
+    tmax = np.array([np.inf, np.inf, np.inf, 1.0, 1.0, 1.0], np.float32)
+    cls = PN.classify(rays, ids, tmax, BOX)[0]
+    assert list(cls) == [2, 1, 0, 0, -1, -1]
+    # the inner distance: centre -> 0, near a corner -> nearly 1
+    c = 0.5 * (BOX[0, :3] + BOX[0, 3:])
+    near = BOX[0, 3:] - 1e-3 * (BOX[0, 3:] - BOX[0, :3])
+    rr = np.array([[*c, 0, 0, 1], [*near, 1, 0, 0]], np.float32)
+    r = PN.transform(rr, np.zeros(2, np.int32), np.full(2, np.inf, np.float32), BOX)[5]
+    assert r[0] == 0.0 and 0.99 < r[1] < 1.0
+
+
+@pytest.mark.parametrize("R", [4, 256])
+def test_bilinear_reproduces_affine_fields(R):
+    """G[a, b] = alpha a + beta b + gamma per latent: the lookup returns
+    alpha s_u + beta s_v + gamma exactly (up to rounding); an all-ones grid
+    interpolates to 1; vertices are reproduced exactly."""
+    g = np.random.default_rng(5)
+    al, be, ga = g.normal(size=3), g.normal(size=3), g.normal(size=3)
+    a = np.arange(R)[:, None, None]
+    b = np.arange(R)[None, :, None]
+    G = al * a + be * b + ga
+    u, v = g.uniform(0, 1, 400), g.uniform(0, 1, 400)
+    u[:2], v[:2] = [0.0, 1.0], [1.0, 0.0]
+    got = PN.bilinear(G, u, v)
+    want = al * (u * (R - 1))[:, None] + be * (v * (R - 1))[:, None] + ga
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-11 * R)
+    np.testing.assert_allclose(PN.bilinear(np.ones((R, R, 5)), u, v), 1.0, atol=1e-14)
+    iu, iv = g.integers(0, R, 50), g.integers(0, R, 50)
+    Gr = g.normal(size=(R, R, 3))
+    np.testing.assert_allclose(PN.bilinear(Gr, iu / (R - 1), iv / (R - 1)), Gr[iu, iv], atol=1e-14)
+    G1 = g.normal(size=3) * np.arange(R)[:, None] + 2.0
+    r = g.uniform(0, 1, 100)
+    np.testing.assert_allclose(PN.linear(G1, r), G1[0] + (G1[1] - G1[0]) * (r * (R - 1))[:, None], atol=1e-11 * R)
+
+
+def test_mlp_hand_computed():
+    """2-2-1 leaky-ReLU network by hand: x = (1, 1), W1 = [[1, -2], [0.5, 1]]
+    -> pre-activations (-1, 1.5) -> (-s, 1.5) with the slope s -> z = 2(-s) + 3(1.5)."""
+    mats = [np.array([[1.0, -2.0], [0.5, 1.0]]), np.array([[2.0, 3.0]])]
+    z = PN.mlp_mats(np.array([[1.0, 1.0]]), mats)
+    assert z[0] == 2 * (-PN.LEAKY) + 4.5
+    # a second hidden layer W2 = identity applies the slope to -s once more
+    z2 = PN.mlp_mats(np.array([[1.0, 1.0]]), [mats[0], np.eye(2), mats[1]])
+    assert abs(z2[0] - (2 * (-PN.LEAKY * PN.LEAKY) + 4.5)) < 1e-15
+    assert abs(PN.LEAKY - 0.01) < 1e-9
+
+
+def test_quantised_equals_exact_when_representable():
+    """Weights, inputs and activations that bf16 and f16 hold exactly, with
+    positive pre-activations: the quantised MLP is the exact one."""
+    g = np.random.default_rng(6)
+    mats = [g.integers(1, 4, (64, 6)) / 8.0, g.integers(1, 4, (64, 64)) / 64.0, g.integers(-3, 4, (1, 64)) / 8.0]
+    x = g.integers(1, 4, (20, 6)) / 4.0
+    ref = PN.mlp_mats(x, mats)
+    for q in ("bf16", "f16"):
+        np.testing.assert_array_equal(PN.mlp_mats(x, mats, q), ref)
+
+
+def test_grid_layout_and_init_stream():
+    """One object's buffer: position, direction (and distance) grids back to
+    back; the latents are the generator's elements of key 2 obj + network."""
+    assert PN.grid_elems(0) == 2 * 256 * 256 * 3
+    assert PN.grid_elems(1) == 2 * 128 * 128 * 5 + 128 * 3
+    buf = O.init_grid(7, PN.init_key(3, 1), 1e-4, "f16", PN.grid_elems(1))
+    p, d, r = PN.split_grid(buf, 1)
+    assert p.shape == (128, 128, 5) and d.shape == (128, 128, 5) and r.shape == (128, 3)
+    assert np.array_equal(r.ravel(), buf[-384:])
+    vals = buf.view(np.float16).astype(np.float64)
+    assert np.abs(vals).max() <= PN.round_to(1e-4, "f16") and np.abs(vals).max() > 0.9e-4
+
+
+def test_forward_routes_by_class():
+    """Outer queries use the outer network, inner ones the inner network; a
+    miss is visible with z = +inf; invalid input gives NaN."""
+    g = np.random.default_rng(8)
+    w0 = g.uniform(-0.3, 0.3, PN.mlp_params(0))
+    w1 = g.uniform(-0.3, 0.3, PN.mlp_params(1))
+    go = [[g.normal(size=s) for s in PN.grid_shapes(0)]]
+    gi = [[g.normal(size=s) for s in PN.grid_shapes(1)]]
+    rays = np.array([[1, 0, 1, 0, 0, 1], [1, 0, 9, 0, 0, -1], [1, 0, 9, 0, 0, 1], [np.nan, 0, 0, 1, 0, 0]],
+                    np.float32)
+    ids = np.zeros(4, np.int32)
+    tmax = np.full(4, np.inf, np.float32)
+    out = PN.forward(rays, ids, tmax, BOX, go, gi, w0, w1)
+    assert list(out["cls"]) == [2, 1, 0, -1]
+    _, x1 = PN.features(1, rays[:1], ids[:1], tmax[:1], BOX, gi)
+    _, x0 = PN.features(0, rays[1:2], ids[1:2], tmax[1:2], BOX, go)
+    assert out["z"][0] == PN.mlp(x1, w1, 1)[0]
+    assert out["z"][1] == PN.mlp(x0, w0, 0)[0]
+    assert out["y"][2] == 1.0 and out["z"][2] == np.inf
+    assert np.isnan(out["y"][3])
