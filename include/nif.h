@@ -315,6 +315,48 @@ nif_status nif_backward(nif_ctx* ctx, int32_t mlp, const float* rays, const int3
                         const float* grad_visibility, int64_t n, float* mlp_grad, void* ws, size_t ws_bytes,
                         void* stream);
 
+/* The paper's own networks (Sec. 3.1, Sec. 3.2, Sec. 5 "Architecture",
+ * Table 1), forward pass.  A query whose origin lies strictly inside its
+ * object's AABB goes to the inner network, any other query that meets the
+ * AABB to the outer network; a miss is visible (1, logit +inf) and invalid
+ * input gives NaN, as for nif_query.
+ *   outer: position = the AABB entry point; q = (p - c) / h (c the box
+ *   centre, h its half extents); (u, v) = (theta / pi, (phi + pi) / (2 pi))
+ *   of the spherical angles of q and of d; bilinear lookups (vertex-aligned,
+ *   s = u (R - 1)) in a 256 x 256 grid of 3 latents for each; MLP 6-64-64-1.
+ *   inner: position = the origin; the same maps on 128 x 128 grids of 5
+ *   latents, plus r = |q| / sqrt(3) looked up linearly in a 1D grid of 128 x 3
+ *   latents; MLP 13-48-48-48-1.
+ *   Both MLPs: no biases, leaky ReLU (slope 0.01f) after every hidden layer,
+ *   sigmoid output; input order [position, direction(, distance)] latents.
+ * nif_paper_mlp_params / nif_paper_grid_elems: weights of network 0 (outer)
+ *   or 1 (inner) (4,544 / 5,280), and latents of one object's grid buffer for
+ *   that network (position grid, direction grid, distance grid, each row-major
+ *   [u][v][latent], back to back); -1 for another network number.
+ * nif_paper_create / destroy: a handle for num_objects objects.
+ * nif_paper_set_object: box (host, 6 floats lo, hi) and the object's two grid
+ *   buffers (dev, binary16, caller-owned).
+ * nif_paper_init_grid: fills one grid buffer with U[-amp, amp) latents of the
+ *   generator of nif_init_grid, keyed by 2 obj + network.
+ * nif_paper_set_mlp: the shared weights of a network (dev, binary32, W1
+ *   [width][din], W2..WH [width][width], w_out [width], row-major); copied, so
+ *   the buffer may be reused.  Synchronises `stream`.
+ * nif_paper_prepare: packs both networks' weights for dtype (NIF_F32,
+ *   NIF_F16 or NIF_BF16 operands, binary32 accumulation and output layer).
+ * nif_paper_query: visibility (and logits, nullable) of n queries, arrays as
+ *   in nif_query; two launches on `stream` (outer, then inner). */
+typedef struct nif_paper nif_paper;
+int64_t nif_paper_mlp_params(int32_t network);
+int64_t nif_paper_grid_elems(int32_t network);
+nif_status nif_paper_create(int32_t num_objects, nif_paper** out);
+void nif_paper_destroy(nif_paper* p);
+nif_status nif_paper_set_object(nif_paper* p, int32_t obj, const float* aabb, void* outer_grid, void* inner_grid);
+nif_status nif_paper_init_grid(nif_paper* p, int32_t obj, int32_t network, uint64_t seed, float amp, void* stream);
+nif_status nif_paper_set_mlp(nif_paper* p, int32_t network, const float* w, void* stream);
+nif_status nif_paper_prepare(nif_paper* p, int32_t dtype, void* stream);
+nif_status nif_paper_query(nif_paper* p, int32_t dtype, const float* rays, const int32_t* object_ids,
+                           const float* t_max, int64_t n, float* visibility, float* logits, void* stream);
+
 /* Plain BVH any-hit ray casting: exact shadow-ray labels for training and the
  * baseline the paper compares against (Sec. 6 "Performance Evaluation").
  * nif_bvh_create: builds a binned-SAH BVH on the host from num_tris

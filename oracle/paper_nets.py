@@ -228,6 +228,39 @@ def mlp_mats(x, mats, quant: str = "exact"):
     return h @ mats[H][0]
 
 
+def lowp_bound(x, w, network: int, fmt: str):
+    """Per-query bound on |y - y_exact| of the bf16 / f16 forms, by first-order
+    propagation of the rounding errors through the layers:
+      D_0 = (u + 2^-20) |x| + a      (input rounding, plus binary32 feature error)
+      E_j = |W_j| D_(j-1) + (u + g_K (1 + u)) |W_j| |h_(j-1)|   (pre-activation)
+      D_j = E_j + u |h_j| + a        (activation rounding, j < H; D_H = E_H)
+      |dz| <= |w_out| E_H + g_W |w_out| |h_H|,  |dy| <= |dz| / 4
+    with u the unit roundoff of fmt (2^-8 bf16, 2^-11 f16), a its subnormal
+    half-spacing, g_K = K 2^-24 / (1 - K 2^-24) for binary32 sums of K terms;
+    the leaky ReLU is 1-Lipschitz and the sigmoid's slope is at most 1/4.
+    h_j are the rounded activations of the emulated forward."""
+    u, a = {"bf16": (2.0 ** -8, 2.0 ** -134), "f16": (2.0 ** -11, 2.0 ** -25)}[fmt]
+    gam = lambda k: k * 2.0 ** -24 / (1 - k * 2.0 ** -24)
+    mats = split_weights(w, network)
+    H = len(mats) - 1
+    x = np.asarray(x, np.float64)
+    h = round_to(x, fmt)
+    D = (u + 2.0 ** -20) * np.abs(x) + a
+    E = None
+    for j in range(H):
+        Wj = mats[j]
+        aW = np.abs(Wj)
+        E = D @ aW.T + (u + gam(Wj.shape[1]) * (1 + u)) * (np.abs(h) @ aW.T)
+        hn = leaky(h @ round_to(Wj, fmt).T)
+        if j < H - 1:
+            hn = round_to(hn, fmt)
+            D = E + u * np.abs(hn) + a
+        h = hn
+    wo = np.abs(mats[H][0])
+    dz = E @ wo + gam(wo.size) * (np.abs(h) @ wo)
+    return dz / 4.0
+
+
 def features(network: int, rays, ids, tmax, aabb, grids):
     """Class per query and the MLP input x (n x din) of `network`; rows of
     other classes are zero.  grids: per object, the binary64 arrays of

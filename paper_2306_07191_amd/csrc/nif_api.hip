@@ -970,3 +970,187 @@ extern "C" void nif_plan_destroy(nif_plan* p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     delete p;
 }
+
+// ---------------------------------------------------------------------------
+// The paper's own networks (Sec. 3.1, Sec. 3.2, Sec. 5, Table 1): per object a
+// binary16 grid buffer for each network, one MLP per network shared by all
+// objects.  The MLPs are padded on the host to the 64-wide MFMA tiling (zero
+// rows and columns add exact zeros) and, for the inner network, the 13 inputs
+// are placed as [position 5, distance 0-1 | direction 5, distance 2, 0] so
+// that each half of a query's lanes holds one grid's latents.
+// ---------------------------------------------------------------------------
+struct PaperNet {
+    int din, din_pad, width, hidden;
+};
+static const PaperNet kPaperNets[2] = {{6, 6, 64, 2}, {13, 14, 48, 3}};
+
+static int64_t paper_params(int net) {
+    const PaperNet& p = kPaperNets[net];
+    return (int64_t)p.width * p.din + (int64_t)(p.hidden - 1) * p.width * p.width + p.width;
+}
+
+static int64_t paper_grid_elems(int net) { return net == 0 ? 2LL * 256 * 256 * 3 : 2LL * 128 * 128 * 5 + 128 * 3; }
+
+// padded input column -> original column of W1 (-1: zero)
+static int paper_w1_column(int net, int c) {
+    if (net == 0) return c;
+    static const int map[14] = {0, 1, 2, 3, 4, 10, 11, 5, 6, 7, 8, 9, 12, -1};
+    return map[c];
+}
+
+struct nif_paper {
+    int32_t K = 0;
+    int num_cus = 256;
+    std::vector<PaperObj> objs;
+    std::vector<bool> set;
+    float* d_master[2] = {nullptr, nullptr};
+    uint8_t* d_packed[2][3] = {};
+    PackInfo pack[2][3] = {};
+    bool prepared[3] = {false, false, false};
+    PaperObj* d_objs = nullptr;
+};
+
+extern "C" int64_t nif_paper_mlp_params(int32_t network) {
+    return network == 0 || network == 1 ? paper_params(network) : -1;
+}
+
+extern "C" int64_t nif_paper_grid_elems(int32_t network) {
+    return network == 0 || network == 1 ? paper_grid_elems(network) : -1;
+}
+
+extern "C" nif_status nif_paper_create(int32_t num_objects, nif_paper** out) {
+    if (!out) return fail(NIF_ERR_INVALID_ARG, "nif_paper_create: NULL out");
+    *out = nullptr;
+    if (num_objects < 1) return fail(NIF_ERR_INVALID_ARG, "nif_paper_create: need >= 1 object");
+    nif_paper* p = new nif_paper;
+    p->K = num_objects;
+    p->objs.resize(num_objects);
+    p->set.assign(num_objects, false);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        p->num_cus = cus;
+    *out = p;
+    return ok();
+}
+
+extern "C" void nif_paper_destroy(nif_paper* p) {
+    if (!p) return;
+    for (int n = 0; n < 2; ++n) {
+        if (p->d_master[n]) (void)hipFree(p->d_master[n]);
+        for (int f = 0; f < 3; ++f)
+            if (p->d_packed[n][f]) (void)hipFree(p->d_packed[n][f]);
+    }
+    if (p->d_objs) (void)hipFree(p->d_objs);
+    delete p;
+}
+
+extern "C" nif_status nif_paper_set_object(nif_paper* p, int32_t obj, const float* aabb, void* outer_grid,
+                                           void* inner_grid) {
+    if (!p || !aabb || !outer_grid || !inner_grid) return fail(NIF_ERR_INVALID_ARG, "nif_paper_set_object: NULL argument");
+    if (obj < 0 || obj >= p->K) return fail(NIF_ERR_INVALID_ARG, "object %d out of range", obj);
+    for (int a = 0; a < 3; ++a)
+        if (!(isfinite(aabb[a]) && isfinite(aabb[3 + a]) && aabb[3 + a] > aabb[a]))
+            return fail(NIF_ERR_INVALID_ARG, "object %d: AABB must be finite with hi > lo on every axis", obj);
+    PaperObj& o = p->objs[obj];
+    for (int a = 0; a < 3; ++a) {
+        o.lo[a] = aabb[a];
+        o.hi[a] = aabb[3 + a];
+    }
+    o.grid[0] = outer_grid;
+    o.grid[1] = inner_grid;
+    p->set[obj] = true;
+    for (bool& b : p->prepared) b = false;
+    return ok();
+}
+
+extern "C" nif_status nif_paper_init_grid(nif_paper* p, int32_t obj, int32_t network, uint64_t seed, float amp,
+                                          void* stream) {
+    if (!p) return fail(NIF_ERR_INVALID_ARG, "nif_paper_init_grid: NULL handle");
+    if (obj < 0 || obj >= p->K || !p->set[obj]) return fail(NIF_ERR_INVALID_ARG, "object %d not registered", obj);
+    if (network != 0 && network != 1) return fail(NIF_ERR_INVALID_ARG, "network must be 0 (outer) or 1 (inner)");
+    if (!isfinite(amp) || amp < 0.0f) return fail(NIF_ERR_INVALID_ARG, "amp must be finite and >= 0");
+    HIP_TRY(launch_init_grid(const_cast<void*>(p->objs[obj].grid[network]), NIF_F16, paper_grid_elems(network), seed,
+                             2ull * (uint64_t)obj + (uint64_t)network, amp, (hipStream_t)stream));
+    return ok();
+}
+
+extern "C" nif_status nif_paper_set_mlp(nif_paper* p, int32_t network, const float* w, void* stream) {
+    if (!p || !w) return fail(NIF_ERR_INVALID_ARG, "nif_paper_set_mlp: NULL argument");
+    if (network != 0 && network != 1) return fail(NIF_ERR_INVALID_ARG, "network must be 0 (outer) or 1 (inner)");
+    const PaperNet& N = kPaperNets[network];
+    const int64_t P = paper_params(network);
+    std::vector<float> src((size_t)P);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(src.data(), w, sizeof(float) * P, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // padded binary32 master: W1 [64][din_pad], W2..WH [64][64], w_out [64]
+    const int64_t Pp = (int64_t)kWidth * N.din_pad + (int64_t)(N.hidden - 1) * kWidth * kWidth + kWidth;
+    std::vector<float> dst((size_t)Pp, 0.0f);
+    for (int r = 0; r < N.width; ++r)
+        for (int c = 0; c < N.din_pad; ++c) {
+            const int oc = paper_w1_column(network, c);
+            if (oc >= 0) dst[(size_t)r * N.din_pad + c] = src[(size_t)r * N.din + oc];
+        }
+    int64_t so = (int64_t)N.width * N.din, dp = (int64_t)kWidth * N.din_pad;
+    for (int j = 1; j < N.hidden; ++j) {
+        for (int r = 0; r < N.width; ++r)
+            for (int c = 0; c < N.width; ++c) dst[(size_t)(dp + (int64_t)r * kWidth + c)] = src[(size_t)(so + (int64_t)r * N.width + c)];
+        so += (int64_t)N.width * N.width;
+        dp += (int64_t)kWidth * kWidth;
+    }
+    for (int c = 0; c < N.width; ++c) dst[(size_t)(dp + c)] = src[(size_t)(so + c)];
+    if (!p->d_master[network]) HIP_TRY(hipMalloc(&p->d_master[network], sizeof(float) * Pp));
+    HIP_TRY(hipMemcpy(p->d_master[network], dst.data(), sizeof(float) * Pp, hipMemcpyHostToDevice));
+    for (bool& b : p->prepared) b = false;
+    return ok();
+}
+
+extern "C" nif_status nif_paper_prepare(nif_paper* p, int32_t dtype, void* stream) {
+    if (!p) return fail(NIF_ERR_INVALID_ARG, "nif_paper_prepare: NULL handle");
+    if (dtype < 0 || dtype > 2) return fail(NIF_ERR_UNSUPPORTED, "the paper's networks run in binary32, FP16 or BF16");
+    for (int k = 0; k < p->K; ++k)
+        if (!p->set[k]) return fail(NIF_ERR_STATE, "object %d not registered", k);
+    for (int n = 0; n < 2; ++n)
+        if (!p->d_master[n]) return fail(NIF_ERR_STATE, "%s network has no weights", n ? "inner" : "outer");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!p->d_objs) HIP_TRY(hipMalloc(&p->d_objs, sizeof(PaperObj) * p->K));
+    HIP_TRY(hipMemcpy(p->d_objs, p->objs.data(), sizeof(PaperObj) * p->K, hipMemcpyHostToDevice));
+    for (int n = 0; n < 2; ++n) {
+        const PaperNet& N = kPaperNets[n];
+        PackInfo P = pack_info(dtype, N.din_pad, N.hidden);
+        if (!p->d_packed[n][dtype]) HIP_TRY(hipMalloc(&p->d_packed[n][dtype], (size_t)P.bytes));
+        p->pack[n][dtype] = P;
+        HIP_TRY(launch_pack_forward(p->d_master[n], p->d_packed[n][dtype], P, dtype, N.din_pad, kWidth, nullptr, s));
+    }
+    p->prepared[dtype] = true;
+    return ok();
+}
+
+extern "C" nif_status nif_paper_query(nif_paper* p, int32_t dtype, const float* rays, const int32_t* ids,
+                                      const float* tmax, int64_t n, float* vis, float* logits, void* stream) {
+    if (!p) return fail(NIF_ERR_INVALID_ARG, "nif_paper_query: NULL handle");
+    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_paper_query: n < 0");
+    if (dtype < 0 || dtype > 2) return fail(NIF_ERR_UNSUPPORTED, "the paper's networks run in binary32, FP16 or BF16");
+    if (n == 0) return ok();
+    if (!rays || !ids || !tmax || !vis) return fail(NIF_ERR_INVALID_ARG, "nif_paper_query: NULL input or output");
+    if (n > ((int64_t)1 << 31) - 1) return fail(NIF_ERR_UNSUPPORTED, "nif_paper_query: n must be below 2^31");
+    if (!p->prepared[dtype]) return fail(NIF_ERR_STATE, "not prepared for dtype %d", dtype);
+    for (int net = 0; net < 2; ++net) {
+        PaperArgs a{};
+        a.rays = rays;
+        a.ids = ids;
+        a.tmax = tmax;
+        a.n = n;
+        a.vis = vis;
+        a.logit = logits;
+        a.objs = p->d_objs;
+        a.num_objects = p->K;
+        a.hidden = kPaperNets[net].hidden;
+        a.packed = p->d_packed[net][dtype];
+        a.pack = p->pack[net][dtype];
+        HIP_TRY(launch_paper(dtype, net, a, p->num_cus, (hipStream_t)stream));
+    }
+    return ok();
+}

@@ -43,7 +43,7 @@ constexpr int roundup(int a, int b) { return (a + b - 1) / b * b; }
 
 // 16-byte packets per M-tile of a layer whose halves hold kh local inputs.
 constexpr int packets_for(int flav, int kh) {
-    return flav == kF32   ? roundup(kh, 1) * 4 / 16
+    return flav == kF32   ? (kh * 4 + 15) / 16
            : flav == kFP8 ? roundup(kh, 32) / 16
                           : roundup(kh, 8) * 2 / 16;
 }
@@ -306,9 +306,17 @@ __device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d) {
     return r;
 }
 
+// Hidden-layer activation: 0 ReLU, 1 leaky ReLU with slope kLeakySlope.
+constexpr float kLeakySlope = 0.01f;
+template <int ACT>
+__device__ __forceinline__ float activate(float v) {
+    if constexpr (ACT == 0) return v > 0.0f ? v : 0.0f;
+    return v > 0.0f ? v : kLeakySlope * v;
+}
+
 // Output of one MLP evaluation for the wave's 32 queries: z for this lane's query.
 // xin: this half's layer-1 local inputs (din/2 floats, zero for inactive queries).
-template <int FLAV, int KH1>
+template <int FLAV, int KH1, int ACT = 0>
 __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, int hidden, const float* xin,
                                          const float* scales, int lane) {
     const int half = lane >> 5;
@@ -392,7 +400,7 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
         for (int c = 0; c < 32; ++c) {
             float v = acc[c / 16][c % 16];
             if constexpr (FLAV == kFP8) v *= deq;
-            h[c] = v > 0.0f ? v : 0.0f;
+            h[c] = activate<ACT>(v);
         }
         acc[0] = f32x16{};
         acc[1] = f32x16{};
@@ -450,8 +458,7 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
     for (int c = 0; c < 32; ++c) {
         float v = acc[c / 16][c % 16];
         if constexpr (FLAV == kFP8) v *= deq;
-        v = v > 0.0f ? v : 0.0f;
-        zp = fmaf(wo[c], v, zp);
+        zp = fmaf(wo[c], activate<ACT>(v), zp);
     }
     return zp + __shfl_xor(zp, 32);
 }
@@ -674,6 +681,191 @@ hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hip
     case kBF16: return launch_f<kBF16, 2>(levels, 1, a, num_cus, s);
     case kF16: return launch_f<kF16, 2>(levels, 1, a, num_cus, s);
     case kFP8: return launch_f<kFP8, 2>(levels, 1, a, num_cus, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ----------------------------------------------------------------------------
+// The paper's own networks (Sec. 3.1, Sec. 3.2, Table 1): spherical 2D grids
+// of the position and the direction (plus a 1D distance grid for the inner
+// network), a leaky-ReLU MLP shared by every object.
+// ----------------------------------------------------------------------------
+constexpr int kOuterR = 256, kOuterN = 3;                               // Table 1
+constexpr int kInnerR = 128, kInnerN = 5, kInnerR1 = 128, kInnerN1 = 3;
+constexpr float kPi = 3.14159265358979f;
+
+// (u, v) = (theta / pi, (phi + pi) / (2 pi)) of the direction of q, in [0, 1];
+// q = 0 maps to theta = 0, phi = 0.
+__device__ __forceinline__ void sph_uv(const float q[3], float& u, float& v) {
+#pragma clang fp contract(off)
+    float l2 = q[0] * q[0];
+    l2 = l2 + q[1] * q[1];
+    l2 = l2 + q[2] * q[2];
+    const float len = sqrtf(l2);
+    float cz = len > 0.0f ? q[2] / len : 1.0f;
+    cz = fminf(fmaxf(cz, -1.0f), 1.0f);
+    const float theta = acosf(cz), phi = atan2f(q[1], q[0]);
+    u = fminf(fmaxf(theta / kPi, 0.0f), 1.0f);
+    v = fminf(fmaxf((phi + kPi) / (2.0f * kPi), 0.0f), 1.0f);
+}
+
+// Vertex-aligned cell and weight of u in [0, 1] on R samples.
+__device__ __forceinline__ uint32_t grid_cell(float u, int R, float& w) {
+#pragma clang fp contract(off)
+    const float s = u * (float)(R - 1);
+    uint32_t c = (uint32_t)floorf(s);
+    c = c < (uint32_t)(R - 2) ? c : (uint32_t)(R - 2);
+    w = s - (float)c;
+    return c;
+}
+
+// Bilinear lookup of N latents on an R x R grid (rows along u).
+template <int R, int N>
+__device__ __forceinline__ void lookup2d(const GLOBAL _Float16* g, float u, float v, float* out) {
+    float wa, wb;
+    const uint32_t a = grid_cell(u, R, wa), b = grid_cell(v, R, wb);
+    const GLOBAL _Float16* p00 = g + ((size_t)a * R + b) * N;
+    const GLOBAL _Float16* p10 = p00 + (size_t)R * N;
+    const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb), w01 = (1.0f - wa) * wb, w11 = wa * wb;
+#pragma unroll
+    for (int f = 0; f < N; ++f) {
+        float x = w00 * (float)p00[f];
+        x = fmaf(w10, (float)p10[f], x);
+        x = fmaf(w01, (float)p00[N + f], x);
+        out[f] = fmaf(w11, (float)p10[N + f], x);
+    }
+}
+
+template <int FLAV, int NET>
+__global__ __launch_bounds__(kBlock) void nif_paper_kernel(PaperArgs A) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr int KH1 = NET == 0 ? kOuterN : kInnerN + 2;  // layer-1 inputs per half (inner padded 13 -> 14)
+    constexpr int R = NET == 0 ? kOuterR : kInnerR, N = NET == 0 ? kOuterN : kInnerN;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int qlane = lane & 31;
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * A.xcd_stride + (b >> 3);
+    const int64_t t_begin = (int64_t)lb * A.num_tiles / A.tiles_per_block_num;
+    const int64_t t_end = (int64_t)(lb + 1) * A.num_tiles / A.tiles_per_block_num;
+    if (t_begin >= t_end) return;
+    {
+        const int nvec = (int)(A.pack.bytes / 16);
+        for (int i = threadIdx.x; i < nvec; i += kBlock)
+            reinterpret_cast<i32x4*>(smem)[i] = reinterpret_cast<const i32x4*>(A.packed)[i];
+    }
+    __syncthreads();
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        const int64_t q = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
+        const bool inb = q < A.n;
+        float o[3] = {0, 0, 0}, d[3] = {1, 0, 0};
+        float tm = 0.0f;
+        int32_t id = -1;
+        if (inb) {
+            const float* r = A.rays + q * 6;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
+            tm = A.tmax[q];
+            id = A.ids[q];
+        }
+        // class: -2 out of range, -1 invalid, 0 miss, 1 outer, 2 inner
+        int cls = -2;
+        float xin[KH1];
+#pragma unroll
+        for (int c = 0; c < KH1; ++c) xin[c] = 0.0f;
+        if (inb) {
+            const uint32_t err = query_error_bits(o, d, tm, id, A.num_objects);
+            if (err) {
+                cls = -1;
+                if (NET == 0 && A.flags) __hip_atomic_fetch_or(A.flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+#pragma clang fp contract(off)
+                const PaperObj ob = A.objs[id];
+                float ta, tb;
+                if (!clip_segment(o, d, tm, ob.lo, ob.hi, ta, tb)) {
+                    cls = 0;
+                } else {
+                    bool inside = true;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) inside = inside && o[a] > ob.lo[a] && o[a] < ob.hi[a];
+                    cls = inside ? 2 : 1;
+                }
+                if (cls == NET + 1) {
+                    // q = (p - c) / h with p the entry point (outer) or the origin (inner)
+                    float qv[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float p = NET == 0 ? o[a] + ta * d[a] : o[a];
+                        const float c = (ob.lo[a] + ob.hi[a]) * 0.5f, h = (ob.hi[a] - ob.lo[a]) * 0.5f;
+                        qv[a] = (p - c) / h;
+                    }
+                    // half 0: position grid, half 1: direction grid (same instructions)
+                    float sv[3], u, v;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) sv[a] = half ? d[a] : qv[a];
+                    sph_uv(sv, u, v);
+                    const GLOBAL _Float16* g = (const GLOBAL _Float16*)ob.grid[NET] + (size_t)half * R * R * N;
+                    lookup2d<R, N>(g, u, v, xin);
+                    if constexpr (NET == 1) {
+                        // distance grid: half 0 keeps latents 0, 1, half 1 latent 2
+                        float l2 = qv[0] * qv[0];
+                        l2 = l2 + qv[1] * qv[1];
+                        l2 = l2 + qv[2] * qv[2];
+                        const float r = fminf(sqrtf(l2) / 1.7320508f, 1.0f);
+                        float w;
+                        const uint32_t c = grid_cell(r, kInnerR1, w);
+                        const GLOBAL _Float16* gr = (const GLOBAL _Float16*)ob.grid[NET] + (size_t)2 * R * R * N + c * kInnerN1;
+                        float rv[kInnerN1];
+#pragma unroll
+                        for (int f = 0; f < kInnerN1; ++f) rv[f] = fmaf(w, (float)gr[kInnerN1 + f], (1.0f - w) * (float)gr[f]);
+                        xin[N] = half ? rv[2] : rv[0];
+                        xin[N + 1] = half ? 0.0f : rv[1];
+                    }
+                }
+            }
+        }
+        const bool mine = cls == NET + 1;
+        float z = 0.0f;
+        if (__ballot(mine)) z = run_mlp<FLAV, KH1, 1>(smem, A.pack, A.hidden, xin, nullptr, lane);
+        if (inb && half == 0) {
+            if (mine) {
+                if (A.vis) A.vis[q] = 1.0f / (1.0f + expf(-z));
+                if (A.logit) A.logit[q] = z;
+            } else if (NET == 0 && cls == 0) {
+                if (A.vis) A.vis[q] = 1.0f;
+                if (A.logit) A.logit[q] = INFINITY;
+            } else if (NET == 0 && cls < 0) {
+                if (A.vis) A.vis[q] = NAN;
+                if (A.logit) A.logit[q] = NAN;
+            }
+        }
+    }
+}
+
+template <int FLAV, int NET>
+static hipError_t launch_paper_t(const PaperArgs& a0, int num_cus, hipStream_t s) {
+    PaperArgs a = a0;
+    const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    int64_t blocks = (int64_t)num_cus * 8;
+    if (blocks > tiles) blocks = tiles;
+    blocks = (blocks + 7) / 8 * 8;
+    a.num_tiles = (int32_t)tiles;
+    a.tiles_per_block_num = (int32_t)blocks;
+    a.xcd_stride = (int32_t)(blocks / 8);
+    hipLaunchKernelGGL((nif_paper_kernel<FLAV, NET>), dim3((unsigned)blocks), dim3(kBlock), lds_bytes(a.pack), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_paper(int flavor, int network, const PaperArgs& a, int num_cus, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    switch (flavor * 2 + network) {
+    case kF32 * 2 + 0: return launch_paper_t<kF32, 0>(a, num_cus, s);
+    case kF32 * 2 + 1: return launch_paper_t<kF32, 1>(a, num_cus, s);
+    case kBF16 * 2 + 0: return launch_paper_t<kBF16, 0>(a, num_cus, s);
+    case kBF16 * 2 + 1: return launch_paper_t<kBF16, 1>(a, num_cus, s);
+    case kF16 * 2 + 0: return launch_paper_t<kF16, 0>(a, num_cus, s);
+    case kF16 * 2 + 1: return launch_paper_t<kF16, 1>(a, num_cus, s);
     }
     return hipErrorInvalidValue;
 }

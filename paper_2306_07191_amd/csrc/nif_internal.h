@@ -74,6 +74,33 @@ struct FwdArgs {
     const float4* qrec;           // nullable: query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
 };
 
+// The paper's own networks: per object its box and its grid buffer of each
+// network (binary16: position grid, direction grid, and for the inner network
+// the distance grid, back to back).
+struct PaperObj {
+    float lo[3], hi[3];
+    const void* grid[2];
+};
+
+struct PaperArgs {
+    const float* rays;
+    const int32_t* ids;
+    const float* tmax;
+    int64_t n;
+    float* vis;
+    float* logit;
+    const PaperObj* objs;
+    int32_t num_objects;
+    int32_t hidden;
+    const uint8_t* packed;  // the network's MLP image (pack_forward layout, padded to width 64)
+    PackInfo pack;
+    int32_t num_tiles, tiles_per_block_num, xcd_stride;
+    uint32_t* flags;
+};
+
+// network 0 (outer) writes misses and invalid queries too; 1 (inner) only its own queries.
+hipError_t launch_paper(int flavor, int network, const PaperArgs& a, int num_cus, hipStream_t s);
+
 struct OrderArgs {
     const float* rays;
     const int32_t* ids;

@@ -33,6 +33,8 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
            "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
            "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit",
+           "nif_paper_mlp_params", "nif_paper_grid_elems", "nif_paper_create", "nif_paper_destroy",
+           "nif_paper_set_object", "nif_paper_init_grid", "nif_paper_set_mlp", "nif_paper_prepare", "nif_paper_query",
            "nif_last_error", "nif_version"]
 
 
@@ -100,6 +102,15 @@ def lib():
             "nif_bvh_destroy": (None, [vp]),
             "nif_bvh_num_nodes": (i64, [vp]),
             "nif_bvh_anyhit": (i32, [vp, vp, vp, i64, vp, vp]),
+            "nif_paper_mlp_params": (i64, [i32]),
+            "nif_paper_grid_elems": (i64, [i32]),
+            "nif_paper_create": (i32, [i32, vp]),
+            "nif_paper_destroy": (None, [vp]),
+            "nif_paper_set_object": (i32, [vp, i32, vp, vp, vp]),
+            "nif_paper_init_grid": (i32, [vp, i32, i32, C.c_uint64, C.c_float, vp]),
+            "nif_paper_set_mlp": (i32, [vp, i32, vp, vp]),
+            "nif_paper_prepare": (i32, [vp, i32, vp]),
+            "nif_paper_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp]),
             "nif_last_error": (C.c_char_p, []),
             "nif_version": (C.c_char_p, []),
         }
@@ -148,6 +159,71 @@ class BVH:
     def close(self):
         if getattr(self, "h", None):
             lib().nif_bvh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PaperModel:
+    """The paper's own outer and inner networks (spherical 2D grids, leaky-ReLU
+    MLPs shared by all objects) over num_objects objects; grid buffers are
+    binary16 torch tensors owned here."""
+
+    def __init__(self, num_objects: int = 1, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().nif_paper_create(num_objects, C.byref(h)), "nif_paper_create")
+        self.h = h
+        self.K = num_objects
+        self.grids = [[None, None] for _ in range(num_objects)]
+        self._w = [None, None]
+
+    @staticmethod
+    def mlp_params(network: int) -> int:
+        return int(lib().nif_paper_mlp_params(network))
+
+    @staticmethod
+    def grid_elems(network: int) -> int:
+        return int(lib().nif_paper_grid_elems(network))
+
+    def set_object(self, obj: int, aabb, grids=None):
+        t = self.torch
+        if grids is None:
+            grids = [t.zeros(self.grid_elems(n), dtype=t.float16, device=self.device) for n in (0, 1)]
+        self.grids[obj] = list(grids)
+        box = (C.c_float * 6)(*[float(v) for v in np.asarray(aabb, np.float32).ravel()])
+        _check(lib().nif_paper_set_object(self.h, obj, box, _ptr(grids[0]), _ptr(grids[1])), "nif_paper_set_object")
+
+    def init_grid(self, obj: int, network: int, seed: int, amp: float):
+        _check(lib().nif_paper_init_grid(self.h, obj, network, seed, amp, _stream()), "nif_paper_init_grid")
+
+    def set_mlp(self, network: int, w):
+        t = self.torch
+        w = t.as_tensor(np.asarray(w, np.float32) if not isinstance(w, t.Tensor) else w).to(self.device, t.float32)
+        self._w[network] = w.contiguous()
+        _check(lib().nif_paper_set_mlp(self.h, network, _ptr(self._w[network]), _stream()), "nif_paper_set_mlp")
+
+    def prepare(self, dtype: str):
+        _check(lib().nif_paper_prepare(self.h, DTYPES[dtype], _stream()), "nif_paper_prepare")
+
+    def query(self, rays, ids, tmax, dtype: str = "f32", out=None, logits=None):
+        t = self.torch
+        n = ids.shape[0]
+        if out is None:
+            out = t.empty(n, dtype=t.float32, device=self.device)
+        _check(lib().nif_paper_query(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(out),
+                                     _ptr(logits), _stream()), "nif_paper_query")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nif_paper_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -227,6 +227,31 @@ def xavier_mlp(shape: ModelShape, gen: np.random.Generator) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+# The paper's own networks (Sec. 5 "Architecture", Table 1): (out, in) of each
+# weight matrix, hidden layers then the output row.
+PAPER_LAYERS = {0: [(64, 6), (64, 64), (1, 64)], 1: [(48, 13), (48, 48), (48, 48), (1, 48)]}
+
+
+def xavier_layers(shapes, gen: np.random.Generator) -> np.ndarray:
+    """Flat float32 Glorot-uniform weights of row-major [out][in] matrices."""
+    parts = []
+    for out_f, in_f in shapes:
+        lim = math.sqrt(6.0 / (in_f + out_f))
+        parts.append(gen.uniform(-lim, lim, size=out_f * in_f))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def rays_inside_box(n: int, aabb: np.ndarray, gen: np.random.Generator):
+    """Origins uniform strictly inside the box (5 %..95 % of each extent), unit
+    directions uniform on the sphere, t_max = +inf: rays of the inner network
+    (secondary rays that start on a surface inside the AABB)."""
+    lo, hi = aabb[:3].astype(np.float64), aabb[3:].astype(np.float64)
+    o = lo[None, :] + gen.uniform(0.05, 0.95, size=(n, 3)) * (hi - lo)[None, :]
+    d = _normalize32(gen.standard_normal(size=(n, 3)).astype(np.float32))
+    rays = np.concatenate([o.astype(np.float32), d], axis=1).astype(np.float32)
+    return rays, np.full(n, np.inf, dtype=np.float32)
+
+
 def scaled_mlp(shape: ModelShape, gen: np.random.Generator, gain: float) -> np.ndarray:
     """Xavier weights multiplied by gain: a wider logit range for parity cases."""
     return (xavier_mlp(shape, gen).astype(np.float64) * gain).astype(np.float32)

@@ -182,3 +182,20 @@ def test_forward_routes_by_class():
     assert out["z"][1] == PN.mlp(x0, w0, 0)[0]
     assert out["y"][2] == 1.0 and out["z"][2] == np.inf
     assert np.isnan(out["y"][3])
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16"])
+@pytest.mark.parametrize("network", [0, 1])
+def test_lowp_bound_covers_the_emulated_rounding(fmt, network):
+    """The emulated bf16 / f16 forward is one realisation of the rounding the
+    bound covers: |y_q - y_exact| stays within it for every query, and the
+    bound is far below the decision margin of typical queries."""
+    g = np.random.default_rng(10 + network)
+    w = np.concatenate([g.uniform(-math.sqrt(6 / (i + o)), math.sqrt(6 / (i + o)), o * i)
+                        for o, i in PN.layer_shapes(network)])
+    x = g.normal(size=(3000, PN.din(network))) * 0.3
+    y = 1 / (1 + np.exp(-PN.mlp(x, w, network)))
+    yq = 1 / (1 + np.exp(-PN.mlp(x, w, network, fmt)))
+    bnd = PN.lowp_bound(x, w, network, fmt)
+    assert (np.abs(yq - y) <= bnd).all() and np.isfinite(bnd).all()
+    assert np.median(bnd) < 0.5  # below the decision margin of a typical query
