@@ -68,7 +68,7 @@ def measured_traffic():
         return None
     rec = json.load(open(path))
     src = b"".join(open(os.path.join(ROOT, "paper_2306_07191_amd", "csrc", f), "rb").read()
-                   for f in ("nif_forward.hip", "nif_device.h"))
+                   for f in ("nif_forward.hip", "nif_device.h", "nif_mlp.h"))
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
     return rec["traffic_bytes_per_launch"]
@@ -509,6 +509,77 @@ def run_scene(args):
     ctx.close()
 
 
+def run_paper(args):
+    """The paper's own networks (outer: spherical 2D grids 256 x 256 x 3, MLP
+    6-64-64-1; inner: 128 x 128 x 5 grids plus a 128 x 3 distance grid, MLP
+    13-48-48-48-1; leaky ReLU, shared by all objects) on the frame scene:
+    2,073,600 ground-to-light shadow rays (outer network), 2,073,600 rays from
+    points on the object to the light (inner network), and the two interleaved.
+    Latents U(-1e-4, 1e-4), Xavier weights.  One launch per query batch."""
+    import torch
+    from paper_2306_07191_amd import nif, synth as S
+    n = 1920 * 1080
+    box = S.frame_aabb()
+    outer, tout = S.rays_ground_to_light(n, S.rng(S.CFG_FRAME, 1))
+    inner, tin = S.rays_surface_to_light(n, S.frame_mesh(), S.rng(S.CFG_FRAME, 8))
+    mixed = np.empty_like(outer)
+    mixed[0::2], mixed[1::2] = outer[0::2], inner[1::2]
+    tmix = np.where(np.arange(n) % 2 == 0, tout, tin).astype(np.float32)
+    ws = [S.xavier_layers(S.PAPER_LAYERS[k], S.rng(S.CFG_FRAME, 3, 10 + k)) for k in (0, 1)]
+    pm = nif.PaperModel(1)
+    pm.set_object(0, box)
+    for net in (0, 1):
+        pm.init_grid(0, net, GRID_SEED, 1e-4)
+        pm.set_mlp(net, ws[net])
+    ids = torch.zeros(n, dtype=torch.int32, device="cuda")
+    y = torch.empty(n, device="cuda")
+    cases = {"outer": (outer, tout), "inner": (inner, tin), "mixed": (mixed, tmix)}
+    dev = {k: (torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda()) for k, (r, t) in cases.items()}
+    flop = {"outer": 2 * 4544, "inner": 2 * 5280, "mixed": 4544 + 5280}  # per query, unpadded
+    res = {}
+    for dt in ("f32", "f16", "bf16"):
+        pm.prepare(dt)
+        for k, (r, t) in dev.items():
+            sec = time_launches(lambda: pm.query(r, ids, t, dt, out=y), args.steps, args.warmup)
+            res[f"{k}_{dt}"] = {"queries_per_s": n / sec, "us": sec * 1e6,
+                                "tflops": flop[k] * n / sec / 1e12, "io_tb_s": 36 * n / sec / 1e12}
+            log(f"paper {k} {dt}: {sec * 1e6:.1f} us = {n / sec / 1e9:.2f} G queries/s, "
+                f"{36 * n / sec / 1e12:.2f} TB/s of query I/O, {flop[k] * n / sec / 1e12:.0f} TFLOP/s")
+    head = res["outer_bf16"]
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        from oracle import paper_nets as PN
+        m = 200000
+        sel = np.linspace(0, n - 1, m).astype(np.int64)
+        grids = [[PN.split_grid(O.init_grid(GRID_SEED, PN.init_key(0, net), 1e-4, "f16", PN.grid_elems(net))
+                                .view(np.float16).astype(np.float64), net)] for net in (0, 1)]
+        t0 = time.perf_counter()
+        PN.forward(outer[sel], np.zeros(m, np.int32), tout[sel], box[None, :], grids[0], grids[1], ws[0], ws[1])
+        dt_ = time.perf_counter() - t0
+        cpu = {"value": m / dt_, "unit": "queries/s", "cores": 1, "kind": "oracle",
+               "sample": f"{m} of {n} outer frame queries (evenly strided), binary64 numpy, one thread"}
+    out = {
+        "metric": "shadow-ray visibility queries/sec at stated error vs FP64 oracle",
+        "value": head["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["us"] / 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded frame scene: ground-to-light and surface-to-light shadow rays; "
+                "U(-1e-4, 1e-4) latents, Xavier weights)",
+        "config": {"workload": "paper networks: frame 1920x1080 shadow rays through the outer network "
+                               "(256x256x3 spherical grids, MLP 6-64-64-1, leaky ReLU)", "queries": n},
+        "roofline": {"bound": "hbm", "achieved": head["io_tb_s"] * 1e3, "peak": 8000.0, "unit": "GB/s",
+                     "frac": head["io_tb_s"] * 1e3 / 8000.0, "traffic": None,
+                     "kernel": "nif_paper_kernel<bf16> (clip + spherical transform + bilinear lookups + MLP)",
+                     "algorithmic_bytes_per_query": 36, "mfma_tflops": head["tflops"],
+                     "mfma_frac": head["tflops"] / PEAK_TFLOPS["bf16"]},
+        "cpu_baseline": cpu,
+        "per_case": res,
+    }
+    print(json.dumps(out), flush=True)
+    pm.close()
+
+
 def run_tiny(args):
     """The small case: 2,048 random triangles, 16,384 rays from a radius-3
     sphere, 4 levels 4..32 with binary32 latents U(-1e-4, 1e-4), MLP
@@ -570,10 +641,11 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=("frame", "tiny", "batched", "scene"), default="frame",
+    ap.add_argument("--workload", choices=("frame", "tiny", "batched", "scene", "paper"), default="frame",
                     help="frame: single-object 1920x1080 frame (default); tiny: the 16,384-ray case; "
                          "batched: 32 objects, 4M Zipf queries; "
-                         "scene: 64 objects, 30M triangles, 8.3M shadow rays")
+                         "scene: 64 objects, 30M triangles, 8.3M shadow rays; "
+                         "paper: the paper's outer / inner networks on the frame scene")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--quick", action="store_true",
@@ -604,6 +676,9 @@ def main():
         return
     if args.workload == "tiny":
         run_tiny(args)
+        return
+    if args.workload == "paper":
+        run_paper(args)
         return
     t0 = time.perf_counter()
     w = S.frame_workload(with_mesh=False)

@@ -344,7 +344,8 @@ nif_status nif_backward(nif_ctx* ctx, int32_t mlp, const float* rays, const int3
  * nif_paper_prepare: packs both networks' weights for dtype (NIF_F32,
  *   NIF_F16 or NIF_BF16 operands, binary32 accumulation and output layer).
  * nif_paper_query: visibility (and logits, nullable) of n queries, arrays as
- *   in nif_query; two launches on `stream` (outer, then inner). */
+ *   in nif_query; one launch on `stream`, in which every wave runs the MLP of
+ *   each network that one of its queries needs. */
 typedef struct nif_paper nif_paper;
 int64_t nif_paper_mlp_params(int32_t network);
 int64_t nif_paper_grid_elems(int32_t network);

@@ -1056,6 +1056,8 @@ extern "C" nif_status nif_paper_set_object(nif_paper* p, int32_t obj, const floa
     for (int a = 0; a < 3; ++a) {
         o.lo[a] = aabb[a];
         o.hi[a] = aabb[3 + a];
+        o.c[a] = (float)(0.5 * ((double)aabb[a] + (double)aabb[3 + a]));
+        o.ih[a] = (float)(2.0 / ((double)aabb[3 + a] - (double)aabb[a]));
     }
     o.grid[0] = outer_grid;
     o.grid[1] = inner_grid;
@@ -1137,20 +1139,20 @@ extern "C" nif_status nif_paper_query(nif_paper* p, int32_t dtype, const float* 
     if (!rays || !ids || !tmax || !vis) return fail(NIF_ERR_INVALID_ARG, "nif_paper_query: NULL input or output");
     if (n > ((int64_t)1 << 31) - 1) return fail(NIF_ERR_UNSUPPORTED, "nif_paper_query: n must be below 2^31");
     if (!p->prepared[dtype]) return fail(NIF_ERR_STATE, "not prepared for dtype %d", dtype);
+    PaperArgs a{};
+    a.rays = rays;
+    a.ids = ids;
+    a.tmax = tmax;
+    a.n = n;
+    a.vis = vis;
+    a.logit = logits;
+    a.objs = p->d_objs;
+    a.num_objects = p->K;
     for (int net = 0; net < 2; ++net) {
-        PaperArgs a{};
-        a.rays = rays;
-        a.ids = ids;
-        a.tmax = tmax;
-        a.n = n;
-        a.vis = vis;
-        a.logit = logits;
-        a.objs = p->d_objs;
-        a.num_objects = p->K;
-        a.hidden = kPaperNets[net].hidden;
-        a.packed = p->d_packed[net][dtype];
-        a.pack = p->pack[net][dtype];
-        HIP_TRY(launch_paper(dtype, net, a, p->num_cus, (hipStream_t)stream));
+        a.hidden[net] = kPaperNets[net].hidden;
+        a.packed[net] = p->d_packed[net][dtype];
+        a.pack[net] = p->pack[net][dtype];
     }
+    HIP_TRY(launch_paper(dtype, a, p->num_cus, (hipStream_t)stream));
     return ok();
 }

@@ -23,30 +23,9 @@
 
 #include "nif_device.h"
 #include "nif_internal.h"
+#include "nif_mlp.h"
 
 namespace nif {
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef int i32x8 __attribute__((ext_vector_type(8)));
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <int FLAV> struct FT;
-template <> struct FT<kF32> { static constexpr int ebytes = 4, kstep = 1; };
-template <> struct FT<kBF16> { static constexpr int ebytes = 2, kstep = 8; };
-template <> struct FT<kF16> { static constexpr int ebytes = 2, kstep = 8; };
-template <> struct FT<kFP8> { static constexpr int ebytes = 1, kstep = 32; };
-
-constexpr int roundup(int a, int b) { return (a + b - 1) / b * b; }
-
-// 16-byte packets per M-tile of a layer whose halves hold kh local inputs.
-constexpr int packets_for(int flav, int kh) {
-    return flav == kF32   ? (kh * 4 + 15) / 16
-           : flav == kFP8 ? roundup(kh, 32) / 16
-                          : roundup(kh, 8) * 2 / 16;
-}
 
 PackInfo pack_info(int flavor, int din, int hidden) {
     PackInfo p{};
@@ -67,7 +46,6 @@ PackInfo pack_info(int flavor, int din, int hidden) {
 
 size_t lds_bytes(const PackInfo& p) { return (size_t)p.bytes; }
 
-#define GLOBAL __attribute__((address_space(1)))
 
 typedef _Float16 f16x2v __attribute__((ext_vector_type(2)));
 
@@ -276,191 +254,6 @@ __device__ __forceinline__ void encode_half_image2(const float u[3][3], int half
             interp_pairs(cw, g, x[2 * (t0 + i)], x[2 * (t0 + i) + 1]);
         }
     }
-}
-
-// ----------------------------------------------------------------------------
-// MLP on MFMA.
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ i32x4 load_packet(const uint8_t* img, int idx) {
-    return *reinterpret_cast<const i32x4*>(img + (int64_t)idx * 16);
-}
-
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-// two floats -> packed pair, round to nearest even
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
-}
-__device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
-}
-// four floats -> four OCP E4M3 bytes, round to nearest even, saturated to +-448
-__device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d) {
-    a = fminf(fmaxf(a, -448.0f), 448.0f);
-    b = fminf(fmaxf(b, -448.0f), 448.0f);
-    c = fminf(fmaxf(c, -448.0f), 448.0f);
-    d = fminf(fmaxf(d, -448.0f), 448.0f);
-    int r = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    r = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, r, true);
-    return r;
-}
-
-// Hidden-layer activation: 0 ReLU, 1 leaky ReLU with slope kLeakySlope.
-constexpr float kLeakySlope = 0.01f;
-template <int ACT>
-__device__ __forceinline__ float activate(float v) {
-    if constexpr (ACT == 0) return v > 0.0f ? v : 0.0f;
-    return v > 0.0f ? v : kLeakySlope * v;
-}
-
-// Output of one MLP evaluation for the wave's 32 queries: z for this lane's query.
-// xin: this half's layer-1 local inputs (din/2 floats, zero for inactive queries).
-template <int FLAV, int KH1, int ACT = 0>
-__device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, int hidden, const float* xin,
-                                         const float* scales, int lane) {
-    const int half = lane >> 5;
-    f32x16 acc[2];
-    // ------------------------------------------------------------------ layer 1
-    {
-        constexpr int PK = packets_for(FLAV, KH1);
-        const uint8_t* L1 = img + P.layer_off[0];
-        acc[0] = f32x16{};
-        acc[1] = f32x16{};
-        if constexpr (FLAV == kF32) {
-#pragma unroll
-            for (int p = 0; p < PK; ++p) {
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    // bit-cast the whole packet: this compiler mis-reads a bit_cast
-                    // of a single vector element (it takes element 0)
-                    const f32x4 af = __builtin_bit_cast(f32x4, load_packet(L1, (mt * PK + p) * 64 + lane));
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int c = 4 * p + q;
-                        float b = c < KH1 ? xin[c] : 0.0f;
-                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], b, acc[mt], 0, 0, 0);
-                    }
-                }
-            }
-        } else if constexpr (FLAV == kBF16 || FLAV == kF16) {
-#pragma unroll
-            for (int p = 0; p < PK; ++p) {
-                i32x4 b4;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int c = 8 * p + 2 * q;
-                    float v0 = c < KH1 ? xin[c] : 0.0f, v1 = c + 1 < KH1 ? xin[c + 1] : 0.0f;
-                    b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(v0, v1) : pack_f16x2(v0, v1));
-                }
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    i32x4 a4 = load_packet(L1, (mt * PK + p) * 64 + lane);
-                    if constexpr (FLAV == kBF16)
-                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a4),
-                                                                          __builtin_bit_cast(bf16x8, b4), acc[mt], 0, 0, 0);
-                    else
-                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a4),
-                                                                         __builtin_bit_cast(f16x8, b4), acc[mt], 0, 0, 0);
-                }
-            }
-        } else {  // FP8: one K-step of 32 local positions
-            const float inv = 1.0f / scales[hidden + 0];
-            i32x8 b8;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                float v[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int c = 4 * q + t;
-                    v[t] = c < KH1 ? xin[c] * inv : 0.0f;
-                }
-                b8[q] = pack_fp8x4(v[0], v[1], v[2], v[3]);
-            }
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
-                i32x4 lo = load_packet(L1, (mt * 2 + 0) * 64 + lane);
-                i32x4 hi = load_packet(L1, (mt * 2 + 1) * 64 + lane);
-                i32x8 a8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-                acc[mt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[mt], 0, 0, 0, 0, 0, 0);
-            }
-        }
-    }
-    // ------------------------------------------------------------------ hidden layers 2..H
-    for (int j = 1; j < hidden; ++j) {
-        const uint8_t* Lj = img + P.layer_off[j];
-        float deq = 1.0f, inv_next = 1.0f;
-        if constexpr (FLAV == kFP8) {
-            deq = scales[j - 1] * scales[hidden + j - 1];
-            inv_next = 1.0f / scales[hidden + j];
-        }
-        // activations of the previous layer: local c = 16 mt + r
-        float h[32];
-#pragma unroll
-        for (int c = 0; c < 32; ++c) {
-            float v = acc[c / 16][c % 16];
-            if constexpr (FLAV == kFP8) v *= deq;
-            h[c] = activate<ACT>(v);
-        }
-        acc[0] = f32x16{};
-        acc[1] = f32x16{};
-        if constexpr (FLAV == kF32) {
-#pragma unroll
-            for (int p = 0; p < 8; ++p) {
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    const f32x4 af = __builtin_bit_cast(f32x4, load_packet(Lj, (mt * 8 + p) * 64 + lane));
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], h[4 * p + q], acc[mt], 0, 0, 0);
-                }
-            }
-        } else if constexpr (FLAV == kBF16 || FLAV == kF16) {
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                i32x4 b4;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(h[8 * p + 2 * q], h[8 * p + 2 * q + 1])
-                                                : pack_f16x2(h[8 * p + 2 * q], h[8 * p + 2 * q + 1]));
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    i32x4 a4 = load_packet(Lj, (mt * 4 + p) * 64 + lane);
-                    if constexpr (FLAV == kBF16)
-                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a4),
-                                                                          __builtin_bit_cast(bf16x8, b4), acc[mt], 0, 0, 0);
-                    else
-                        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a4),
-                                                                         __builtin_bit_cast(f16x8, b4), acc[mt], 0, 0, 0);
-                }
-            }
-        } else {
-            i32x8 b8;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                b8[q] = pack_fp8x4(h[4 * q] * inv_next, h[4 * q + 1] * inv_next, h[4 * q + 2] * inv_next,
-                                   h[4 * q + 3] * inv_next);
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
-                i32x4 lo = load_packet(Lj, (mt * 2 + 0) * 64 + lane);
-                i32x4 hi = load_packet(Lj, (mt * 2 + 1) * 64 + lane);
-                i32x8 a8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-                acc[mt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[mt], 0, 0, 0, 0, 0, 0);
-            }
-        }
-    }
-    // ------------------------------------------------------------------ output layer (binary32)
-    const float* wo = reinterpret_cast<const float*>(img + P.layer_off[hidden]) + half * 32;
-    float deq = 1.0f;
-    if constexpr (FLAV == kFP8) deq = scales[hidden - 1] * scales[2 * hidden - 1];
-    float zp = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 32; ++c) {
-        float v = acc[c / 16][c % 16];
-        if constexpr (FLAV == kFP8) v *= deq;
-        zp = fmaf(wo[c], activate<ACT>(v), zp);
-    }
-    return zp + __shfl_xor(zp, 32);
 }
 
 // Object id of the query in processing slot `slot` (slot < n).
@@ -681,191 +474,6 @@ hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hip
     case kBF16: return launch_f<kBF16, 2>(levels, 1, a, num_cus, s);
     case kF16: return launch_f<kF16, 2>(levels, 1, a, num_cus, s);
     case kFP8: return launch_f<kFP8, 2>(levels, 1, a, num_cus, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-// ----------------------------------------------------------------------------
-// The paper's own networks (Sec. 3.1, Sec. 3.2, Table 1): spherical 2D grids
-// of the position and the direction (plus a 1D distance grid for the inner
-// network), a leaky-ReLU MLP shared by every object.
-// ----------------------------------------------------------------------------
-constexpr int kOuterR = 256, kOuterN = 3;                               // Table 1
-constexpr int kInnerR = 128, kInnerN = 5, kInnerR1 = 128, kInnerN1 = 3;
-constexpr float kPi = 3.14159265358979f;
-
-// (u, v) = (theta / pi, (phi + pi) / (2 pi)) of the direction of q, in [0, 1];
-// q = 0 maps to theta = 0, phi = 0.
-__device__ __forceinline__ void sph_uv(const float q[3], float& u, float& v) {
-#pragma clang fp contract(off)
-    float l2 = q[0] * q[0];
-    l2 = l2 + q[1] * q[1];
-    l2 = l2 + q[2] * q[2];
-    const float len = sqrtf(l2);
-    float cz = len > 0.0f ? q[2] / len : 1.0f;
-    cz = fminf(fmaxf(cz, -1.0f), 1.0f);
-    const float theta = acosf(cz), phi = atan2f(q[1], q[0]);
-    u = fminf(fmaxf(theta / kPi, 0.0f), 1.0f);
-    v = fminf(fmaxf((phi + kPi) / (2.0f * kPi), 0.0f), 1.0f);
-}
-
-// Vertex-aligned cell and weight of u in [0, 1] on R samples.
-__device__ __forceinline__ uint32_t grid_cell(float u, int R, float& w) {
-#pragma clang fp contract(off)
-    const float s = u * (float)(R - 1);
-    uint32_t c = (uint32_t)floorf(s);
-    c = c < (uint32_t)(R - 2) ? c : (uint32_t)(R - 2);
-    w = s - (float)c;
-    return c;
-}
-
-// Bilinear lookup of N latents on an R x R grid (rows along u).
-template <int R, int N>
-__device__ __forceinline__ void lookup2d(const GLOBAL _Float16* g, float u, float v, float* out) {
-    float wa, wb;
-    const uint32_t a = grid_cell(u, R, wa), b = grid_cell(v, R, wb);
-    const GLOBAL _Float16* p00 = g + ((size_t)a * R + b) * N;
-    const GLOBAL _Float16* p10 = p00 + (size_t)R * N;
-    const float w00 = (1.0f - wa) * (1.0f - wb), w10 = wa * (1.0f - wb), w01 = (1.0f - wa) * wb, w11 = wa * wb;
-#pragma unroll
-    for (int f = 0; f < N; ++f) {
-        float x = w00 * (float)p00[f];
-        x = fmaf(w10, (float)p10[f], x);
-        x = fmaf(w01, (float)p00[N + f], x);
-        out[f] = fmaf(w11, (float)p10[N + f], x);
-    }
-}
-
-template <int FLAV, int NET>
-__global__ __launch_bounds__(kBlock) void nif_paper_kernel(PaperArgs A) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    constexpr int KH1 = NET == 0 ? kOuterN : kInnerN + 2;  // layer-1 inputs per half (inner padded 13 -> 14)
-    constexpr int R = NET == 0 ? kOuterR : kInnerR, N = NET == 0 ? kOuterN : kInnerN;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int half = lane >> 5;
-    const int qlane = lane & 31;
-    const int b = blockIdx.x;
-    const int lb = (b & 7) * A.xcd_stride + (b >> 3);
-    const int64_t t_begin = (int64_t)lb * A.num_tiles / A.tiles_per_block_num;
-    const int64_t t_end = (int64_t)(lb + 1) * A.num_tiles / A.tiles_per_block_num;
-    if (t_begin >= t_end) return;
-    {
-        const int nvec = (int)(A.pack.bytes / 16);
-        for (int i = threadIdx.x; i < nvec; i += kBlock)
-            reinterpret_cast<i32x4*>(smem)[i] = reinterpret_cast<const i32x4*>(A.packed)[i];
-    }
-    __syncthreads();
-    for (int64_t tile = t_begin; tile < t_end; ++tile) {
-        const int64_t q = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
-        const bool inb = q < A.n;
-        float o[3] = {0, 0, 0}, d[3] = {1, 0, 0};
-        float tm = 0.0f;
-        int32_t id = -1;
-        if (inb) {
-            const float* r = A.rays + q * 6;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
-            tm = A.tmax[q];
-            id = A.ids[q];
-        }
-        // class: -2 out of range, -1 invalid, 0 miss, 1 outer, 2 inner
-        int cls = -2;
-        float xin[KH1];
-#pragma unroll
-        for (int c = 0; c < KH1; ++c) xin[c] = 0.0f;
-        if (inb) {
-            const uint32_t err = query_error_bits(o, d, tm, id, A.num_objects);
-            if (err) {
-                cls = -1;
-                if (NET == 0 && A.flags) __hip_atomic_fetch_or(A.flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-#pragma clang fp contract(off)
-                const PaperObj ob = A.objs[id];
-                float ta, tb;
-                if (!clip_segment(o, d, tm, ob.lo, ob.hi, ta, tb)) {
-                    cls = 0;
-                } else {
-                    bool inside = true;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) inside = inside && o[a] > ob.lo[a] && o[a] < ob.hi[a];
-                    cls = inside ? 2 : 1;
-                }
-                if (cls == NET + 1) {
-                    // q = (p - c) / h with p the entry point (outer) or the origin (inner)
-                    float qv[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const float p = NET == 0 ? o[a] + ta * d[a] : o[a];
-                        const float c = (ob.lo[a] + ob.hi[a]) * 0.5f, h = (ob.hi[a] - ob.lo[a]) * 0.5f;
-                        qv[a] = (p - c) / h;
-                    }
-                    // half 0: position grid, half 1: direction grid (same instructions)
-                    float sv[3], u, v;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) sv[a] = half ? d[a] : qv[a];
-                    sph_uv(sv, u, v);
-                    const GLOBAL _Float16* g = (const GLOBAL _Float16*)ob.grid[NET] + (size_t)half * R * R * N;
-                    lookup2d<R, N>(g, u, v, xin);
-                    if constexpr (NET == 1) {
-                        // distance grid: half 0 keeps latents 0, 1, half 1 latent 2
-                        float l2 = qv[0] * qv[0];
-                        l2 = l2 + qv[1] * qv[1];
-                        l2 = l2 + qv[2] * qv[2];
-                        const float r = fminf(sqrtf(l2) / 1.7320508f, 1.0f);
-                        float w;
-                        const uint32_t c = grid_cell(r, kInnerR1, w);
-                        const GLOBAL _Float16* gr = (const GLOBAL _Float16*)ob.grid[NET] + (size_t)2 * R * R * N + c * kInnerN1;
-                        float rv[kInnerN1];
-#pragma unroll
-                        for (int f = 0; f < kInnerN1; ++f) rv[f] = fmaf(w, (float)gr[kInnerN1 + f], (1.0f - w) * (float)gr[f]);
-                        xin[N] = half ? rv[2] : rv[0];
-                        xin[N + 1] = half ? 0.0f : rv[1];
-                    }
-                }
-            }
-        }
-        const bool mine = cls == NET + 1;
-        float z = 0.0f;
-        if (__ballot(mine)) z = run_mlp<FLAV, KH1, 1>(smem, A.pack, A.hidden, xin, nullptr, lane);
-        if (inb && half == 0) {
-            if (mine) {
-                if (A.vis) A.vis[q] = 1.0f / (1.0f + expf(-z));
-                if (A.logit) A.logit[q] = z;
-            } else if (NET == 0 && cls == 0) {
-                if (A.vis) A.vis[q] = 1.0f;
-                if (A.logit) A.logit[q] = INFINITY;
-            } else if (NET == 0 && cls < 0) {
-                if (A.vis) A.vis[q] = NAN;
-                if (A.logit) A.logit[q] = NAN;
-            }
-        }
-    }
-}
-
-template <int FLAV, int NET>
-static hipError_t launch_paper_t(const PaperArgs& a0, int num_cus, hipStream_t s) {
-    PaperArgs a = a0;
-    const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
-    int64_t blocks = (int64_t)num_cus * 8;
-    if (blocks > tiles) blocks = tiles;
-    blocks = (blocks + 7) / 8 * 8;
-    a.num_tiles = (int32_t)tiles;
-    a.tiles_per_block_num = (int32_t)blocks;
-    a.xcd_stride = (int32_t)(blocks / 8);
-    hipLaunchKernelGGL((nif_paper_kernel<FLAV, NET>), dim3((unsigned)blocks), dim3(kBlock), lds_bytes(a.pack), s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_paper(int flavor, int network, const PaperArgs& a, int num_cus, hipStream_t s) {
-    if (a.n <= 0) return hipSuccess;
-    switch (flavor * 2 + network) {
-    case kF32 * 2 + 0: return launch_paper_t<kF32, 0>(a, num_cus, s);
-    case kF32 * 2 + 1: return launch_paper_t<kF32, 1>(a, num_cus, s);
-    case kBF16 * 2 + 0: return launch_paper_t<kBF16, 0>(a, num_cus, s);
-    case kBF16 * 2 + 1: return launch_paper_t<kBF16, 1>(a, num_cus, s);
-    case kF16 * 2 + 0: return launch_paper_t<kF16, 0>(a, num_cus, s);
-    case kF16 * 2 + 1: return launch_paper_t<kF16, 1>(a, num_cus, s);
     }
     return hipErrorInvalidValue;
 }

@@ -79,6 +79,7 @@ struct FwdArgs {
 // the distance grid, back to back).
 struct PaperObj {
     float lo[3], hi[3];
+    float c[3], ih[3];  // box centre and reciprocal half extents
     const void* grid[2];
 };
 
@@ -91,15 +92,15 @@ struct PaperArgs {
     float* logit;
     const PaperObj* objs;
     int32_t num_objects;
-    int32_t hidden;
-    const uint8_t* packed;  // the network's MLP image (pack_forward layout, padded to width 64)
-    PackInfo pack;
+    int32_t hidden[2];
+    const uint8_t* packed[2];  // each network's MLP image (pack_forward layout, padded to width 64)
+    PackInfo pack[2];
     int32_t num_tiles, tiles_per_block_num, xcd_stride;
     uint32_t* flags;
 };
 
-// network 0 (outer) writes misses and invalid queries too; 1 (inner) only its own queries.
-hipError_t launch_paper(int flavor, int network, const PaperArgs& a, int num_cus, hipStream_t s);
+// Both networks in one launch: outer and inner queries, misses and invalid input.
+hipError_t launch_paper(int flavor, const PaperArgs& a, int num_cus, hipStream_t s);
 
 struct OrderArgs {
     const float* rays;

@@ -252,6 +252,27 @@ def rays_inside_box(n: int, aabb: np.ndarray, gen: np.random.Generator):
     return rays, np.full(n, np.inf, dtype=np.float32)
 
 
+def rays_surface_to_light(n: int, tris: np.ndarray, gen: np.random.Generator, light_y=FRAME_LIGHT_Y,
+                          light_half=FRAME_LIGHT_HALF):
+    """Shadow rays of the inner network: origins at uniform barycentric points of
+    uniformly chosen triangles (on the object, so inside its AABB), aimed at
+    uniform points of the frame's area light; t_max = the distance."""
+    t = tris[gen.integers(0, tris.shape[0], n)].astype(np.float64).reshape(n, 3, 3)
+    a, b = gen.uniform(size=n), gen.uniform(size=n)
+    flip = a + b > 1.0
+    a, b = np.where(flip, 1.0 - a, a), np.where(flip, 1.0 - b, b)
+    o = t[:, 0] + a[:, None] * (t[:, 1] - t[:, 0]) + b[:, None] * (t[:, 2] - t[:, 0])
+    lp = np.empty((n, 3))
+    lp[:, 0] = gen.uniform(-light_half, light_half, n)
+    lp[:, 1] = light_y
+    lp[:, 2] = gen.uniform(-light_half, light_half, n)
+    o32 = o.astype(np.float32)
+    v = lp.astype(np.float32) - o32
+    d = _normalize32(v)
+    tmax = np.sqrt((v.astype(np.float64) ** 2).sum(axis=1)).astype(np.float32)
+    return np.concatenate([o32, d], axis=1).astype(np.float32), tmax
+
+
 def scaled_mlp(shape: ModelShape, gen: np.random.Generator, gain: float) -> np.ndarray:
     """Xavier weights multiplied by gain: a wider logit range for parity cases."""
     return (xavier_mlp(shape, gen).astype(np.float64) * gain).astype(np.float32)
