@@ -61,6 +61,15 @@ __device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d) {
     return r;
 }
 
+// ReLU of a pair of rounded binary16 / bfloat16 values (sign and magnitude):
+// as signed 16-bit integers the negative ones, -0 included, are below 0, so
+// max(x, 0) keeps a non-negative value and turns the others into +0, which is
+// the ReLU of the unrounded value rounded (rounding keeps the sign).
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int relu_pair16(int x) {
+    return __builtin_bit_cast(int, __builtin_elementwise_max(__builtin_bit_cast(i16x2, x), i16x2{0, 0}));
+}
+
 // Hidden-layer activation: 0 ReLU, 1 leaky ReLU with slope kLeakySlope.
 constexpr float kLeakySlope = 0.01f;
 template <int ACT>
@@ -155,7 +164,8 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
         for (int c = 0; c < 32; ++c) {
             float v = acc[c / 16][c % 16];
             if constexpr (FLAV == kFP8) v *= deq;
-            h[c] = activate<ACT>(v);
+            // 16-bit operands with ReLU: rounded first, the ReLU taken on the packed pairs
+            h[c] = (ACT == 0 && (FLAV == kBF16 || FLAV == kF16)) ? v : activate<ACT>(v);
         }
         acc[0] = f32x16{};
         acc[1] = f32x16{};
@@ -175,9 +185,11 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
             for (int p = 0; p < 4; ++p) {
                 i32x4 b4;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 4; ++q) {
                     b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(h[8 * p + 2 * q], h[8 * p + 2 * q + 1])
                                                 : pack_f16x2(h[8 * p + 2 * q], h[8 * p + 2 * q + 1]));
+                    if constexpr (ACT == 0) b4[q] = relu_pair16(b4[q]);
+                }
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt) {
                     i32x4 a4 = load_packet(Lj, (mt * 4 + p) * 64 + lane);
