@@ -261,6 +261,81 @@ def lowp_bound(x, w, network: int, fmt: str):
     return dz / 4.0
 
 
+def _corners2d(R, u, v):
+    """Vertex indices (a, b) and weights of the four corners, order (0,0),
+    (1,0), (0,1), (1,1), of a vertex-aligned bilinear lookup."""
+    su, sv = u * (R - 1), v * (R - 1)
+    a = np.minimum(np.floor(su), R - 2).astype(np.int64)
+    b = np.minimum(np.floor(sv), R - 2).astype(np.int64)
+    wa, wb = su - a, sv - b
+    return [(a, b, (1 - wa) * (1 - wb)), (a + 1, b, wa * (1 - wb)), (a, b + 1, (1 - wa) * wb), (a + 1, b + 1, wa * wb)]
+
+
+def leaky_grad(a):
+    """Derivative of the leaky ReLU, the slope at a = 0."""
+    return np.where(a > 0, 1.0, LEAKY)
+
+
+def train_grads(network: int, rays, ids, tmax, labels, aabb, grids, w):
+    """L2 training loss of `network` (Sec. 5 "Training": L2 loss) over the
+    queries of its class, L = (1/B) sum (y - t)^2 with t = label (1 visible),
+    and its gradients by back-propagation (Fig. 2: the latents are trained
+    with the MLP): returns (loss, B, dW flat like w, per-object grid
+    gradients as arrays of grid_shapes)."""
+    cls, pu, pv, du, dv, r = transform(rays, ids, tmax, aabb)
+    want = CLS_OUTER if network == 0 else CLS_INNER
+    s = np.nonzero(cls == want)[0]
+    B = s.size
+    mats = split_weights(w, network)
+    H = len(mats) - 1
+    K = len(grids)
+    ggrids = [[np.zeros(sh) for sh in grid_shapes(network)] for _ in range(K)]
+    dW = [np.zeros_like(m) for m in mats]
+    if B == 0:
+        return 0.0, 0, np.concatenate([d.ravel() for d in dW]), ggrids
+    ids_s = np.asarray(ids, np.int64)[s]
+    _, x = features(network, rays, ids, tmax, aabb, grids)
+    x = x[s]
+    t = (np.asarray(labels)[s] != 0).astype(np.float64)
+    hs, acts = [x], []
+    h = x
+    for j in range(H):
+        a = h @ mats[j].T
+        acts.append(a)
+        h = leaky(a)
+        hs.append(h)
+    z = h @ mats[H][0]
+    y = 1.0 / (1.0 + np.exp(-z))
+    loss = float(np.mean((y - t) ** 2))
+    dz = 2.0 * (y - t) / B * y * (1.0 - y)
+    dW[H][0] = dz @ hs[H]
+    delta = dz[:, None] * mats[H][0][None, :] * leaky_grad(acts[H - 1])
+    for j in range(H - 1, -1, -1):
+        dW[j] = delta.T @ hs[j]
+        back = delta @ mats[j]
+        if j > 0:
+            delta = back * leaky_grad(acts[j - 1])
+    gx = back  # dL/dx, n x din
+    R, N = (OUTER["R"], OUTER["N"]) if network == 0 else (INNER["R"], INNER["N"])
+    for k in range(K):
+        sel = np.nonzero(ids_s == k)[0]
+        if sel.size == 0:
+            continue
+        for gi, (uu, vv, cols) in enumerate(((pu[s][sel], pv[s][sel], slice(0, N)),
+                                             (du[s][sel], dv[s][sel], slice(N, 2 * N)))):
+            for a, b, wt in _corners2d(R, uu, vv):
+                np.add.at(ggrids[k][gi], (a, b), wt[:, None] * gx[sel][:, cols])
+        if network == 1:
+            R1 = INNER["R1"]
+            sr = r[s][sel] * (R1 - 1)
+            a = np.minimum(np.floor(sr), R1 - 2).astype(np.int64)
+            wr = sr - a
+            g1 = gx[sel][:, 2 * N:]
+            np.add.at(ggrids[k][2], a, (1 - wr)[:, None] * g1)
+            np.add.at(ggrids[k][2], a + 1, wr[:, None] * g1)
+    return loss, B, np.concatenate([d.ravel() for d in dW]), ggrids
+
+
 def features(network: int, rays, ids, tmax, aabb, grids):
     """Class per query and the MLP input x (n x din) of `network`; rows of
     other classes are zero.  grids: per object, the binary64 arrays of

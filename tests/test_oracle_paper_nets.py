@@ -199,3 +199,89 @@ def test_lowp_bound_covers_the_emulated_rounding(fmt, network):
     bnd = PN.lowp_bound(x, w, network, fmt)
     assert (np.abs(yq - y) <= bnd).all() and np.isfinite(bnd).all()
     assert np.median(bnd) < 0.5  # below the decision margin of a typical query
+
+
+def _train_case(network, n=48, seed=20):
+    g = np.random.default_rng(seed)
+    if network == 0:
+        rays = _outside_rays(g, n, BOX)
+    else:
+        lo, hi = BOX[0, :3].astype(float), BOX[0, 3:].astype(float)
+        o = lo + g.uniform(0.1, 0.9, (n, 3)) * (hi - lo)
+        d = g.normal(size=(n, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        rays = np.concatenate([o, d], 1).astype(np.float32)
+    ids = np.zeros(n, np.int32)
+    tmax = np.full(n, np.inf, np.float32)
+    labels = g.integers(0, 2, n).astype(np.uint8)
+    w = np.concatenate([g.uniform(-0.6, 0.6, o_ * i_) for o_, i_ in PN.layer_shapes(network)])
+    grids = [[g.normal(size=sh) * 0.3 for sh in PN.grid_shapes(network)]]
+    return rays, ids, tmax, labels, w, grids
+
+
+def _loss(network, rays, ids, tmax, labels, w, grids):
+    """L2 loss and the sign pattern of every pre-activation (to skip
+    perturbations that cross a kink of the leaky ReLU)."""
+    cls, x = PN.features(network, rays, ids, tmax, BOX, grids)
+    s = cls == (PN.CLS_OUTER if network == 0 else PN.CLS_INNER)
+    y = 1 / (1 + np.exp(-PN.mlp(x[s], w, network)))
+    mats = PN.split_weights(w, network)
+    h, signs = x[s], []
+    for m in mats[:-1]:
+        a = h @ m.T
+        signs.append(a > 0)
+        h = PN.leaky(a)
+    return np.mean((y - (labels[s] != 0)) ** 2), np.concatenate([g.ravel() for g in signs])
+
+
+def _fd(network, rays, ids, tmax, labels, wp, wm, gp, gm, h):
+    lp, sp = _loss(network, rays, ids, tmax, labels, wp, gp)
+    lm, sm = _loss(network, rays, ids, tmax, labels, wm, gm)
+    return (lp - lm) / (2 * h) if np.array_equal(sp, sm) else None
+
+
+@pytest.mark.parametrize("network", [0, 1])
+def test_train_gradients_match_finite_differences(network):
+    """Central differences of the binary64 L2 loss: MLP weights (all layers)
+    and latents of every grid the queries touch."""
+    rays, ids, tmax, labels, w, grids = _train_case(network)
+    loss, B, dW, gg = PN.train_grads(network, rays, ids, tmax, labels, BOX, grids, w)
+    assert B == 48 and abs(loss - _loss(network, rays, ids, tmax, labels, w, grids)[0]) < 1e-15
+    g = np.random.default_rng(21)
+    h = 1e-6
+    checked = 0
+    for i in g.choice(w.size, 40, replace=False):
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = _fd(network, rays, ids, tmax, labels, wp, wm, grids, grids, h)
+        if fd is not None:
+            checked += 1
+            assert abs(fd - dW[i]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9, (i, fd, dW[i])
+    for gi in range(len(gg[0])):
+        nz = np.argwhere(gg[0][gi] != 0)
+        assert len(nz) > 0
+        for idx in nz[g.choice(len(nz), min(15, len(nz)), replace=False)]:
+            idx = tuple(idx)
+            gp = [a.copy() for a in grids[0]]
+            gm = [a.copy() for a in grids[0]]
+            gp[gi][idx] += h
+            gm[gi][idx] -= h
+            fd = _fd(network, rays, ids, tmax, labels, w, w, [gp], [gm], h)
+            if fd is not None:
+                checked += 1
+                assert abs(fd - gg[0][gi][idx]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9, (gi, idx, fd, gg[0][gi][idx])
+    assert checked >= 60
+
+
+def test_l2_loss_closed_form():
+    """Zero weights: z = 0, y = 1/2, L = 1/4 for any labels, dL/dz = 2 (1/2 - t) / B / 4."""
+    rays, ids, tmax, labels, w, grids = _train_case(0, n=10)
+    loss, B, dW, _ = PN.train_grads(0, rays, ids, tmax, labels, BOX, grids, np.zeros_like(w))
+    assert loss == 0.25 and B == 10 and not dW.any()
+    # only the output row sees a gradient when the hidden weights are zero but w_out is not:
+    # h = 0, so dW_out = 0 too
+    w2 = np.zeros_like(w)
+    w2[-64:] = 1.0
+    _, _, dW2, gg = PN.train_grads(0, rays, ids, tmax, labels, BOX, grids, w2)
+    assert not dW2.any() and not any(a.any() for a in gg[0])
