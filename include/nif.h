@@ -358,6 +358,34 @@ nif_status nif_paper_prepare(nif_paper* p, int32_t dtype, void* stream);
 nif_status nif_paper_query(nif_paper* p, int32_t dtype, const float* rays, const int32_t* object_ids,
                            const float* t_max, int64_t n, float* visibility, float* logits, void* stream);
 
+/* Training of the paper's networks (Sec. 5 "Training": L2 loss, Adam; the
+ * latents are trained with the MLP, Fig. 2), binary32.
+ * nif_paper_set_train: the binary32 master weights of `network` (dev, the
+ *   layout of nif_paper_set_mlp; updated in place by Adam, and also copied
+ *   into the inference weights as nif_paper_set_mlp does) and its Adam
+ *   moments m, v (dev, same size, caller-initialised).  Synchronises `stream`.
+ * nif_paper_set_object_train: for object obj and `network`, the binary32
+ *   latent gradient and Adam moments (dev, nif_paper_grid_elems(network)
+ *   floats each).
+ * nif_paper_train_step: one step on the n queries (dev arrays as in
+ *   nif_query; labels dev, n bytes, 1 = visible) of which those of the
+ *   network's class form the batch B: L = (1/B) sum (y - t)^2.  Gradients of
+ *   the MLP (mlp_grad, dev, nullable) and of every object's latents (its
+ *   grid_grad buffer, zeroed first); with adam != NULL also Adam step `step`
+ *   (1-based) on the master (dense) and on the binary16 latents whose
+ *   gradient is non-zero (moments kept elsewhere), after which the latent
+ *   gradient reads 0 and nif_paper_prepare must run again before a query.
+ *   loss (dev, nullable) receives L (0 when B = 0).  ws: at least
+ *   nif_paper_train_workspace_bytes(p, network, n) bytes (dev). */
+nif_status nif_paper_set_train(nif_paper* p, int32_t network, float* w, float* m, float* v, void* stream);
+nif_status nif_paper_set_object_train(nif_paper* p, int32_t obj, int32_t network, float* grid_grad, float* grid_m,
+                                      float* grid_v);
+size_t nif_paper_train_workspace_bytes(const nif_paper* p, int32_t network, int64_t n);
+nif_status nif_paper_train_step(nif_paper* p, int32_t network, const float* rays, const int32_t* object_ids,
+                                const float* t_max, const uint8_t* labels, int64_t n, int32_t step,
+                                const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
+                                void* stream);
+
 /* Plain BVH any-hit ray casting: exact shadow-ray labels for training and the
  * baseline the paper compares against (Sec. 6 "Performance Evaluation").
  * nif_bvh_create: builds a binned-SAH BVH on the host from num_tris

@@ -145,11 +145,10 @@ def classify(rays, ids, tmax, aabb):
 
 
 def sph(q):
-    """(u, v) in [0, 1]^2 of the spherical angles of the rows of q (binary64)."""
+    """(u, v) in [0, 1]^2 of the spherical angles of the rows of q (binary64);
+    the polar angle as atan2(sqrt(x^2 + y^2), z), well conditioned everywhere."""
     q = np.asarray(q, np.float64)
-    r = np.sqrt((q * q).sum(1))
-    cz = np.where(r > 0, q[:, 2] / np.where(r > 0, r, 1.0), 1.0)
-    theta = np.arccos(np.clip(cz, -1.0, 1.0))
+    theta = np.arctan2(np.sqrt(q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1]), q[:, 2])  # polar angle, 0 for q = 0
     phi = np.arctan2(q[:, 1], q[:, 0])
     u = np.clip(theta / math.pi, 0.0, 1.0)
     v = np.clip((phi + math.pi) / (2.0 * math.pi), 0.0, 1.0)

@@ -1008,6 +1008,14 @@ struct nif_paper {
     PackInfo pack[2][3] = {};
     bool prepared[3] = {false, false, false};
     PaperObj* d_objs = nullptr;
+    // training: per network the caller's master and moments, per object and
+    // network the latent gradient and moments; device tables of those pointers
+    float* w[2] = {nullptr, nullptr};
+    float* mlp_m[2] = {nullptr, nullptr};
+    float* mlp_v[2] = {nullptr, nullptr};
+    std::vector<float*> gg[2], gm[2], gv[2];
+    void** d_tab[2] = {nullptr, nullptr};
+    bool tab_dirty[2] = {true, true};
 };
 
 extern "C" int64_t nif_paper_mlp_params(int32_t network) {
@@ -1026,6 +1034,11 @@ extern "C" nif_status nif_paper_create(int32_t num_objects, nif_paper** out) {
     p->K = num_objects;
     p->objs.resize(num_objects);
     p->set.assign(num_objects, false);
+    for (int n = 0; n < 2; ++n) {
+        p->gg[n].assign(num_objects, nullptr);
+        p->gm[n].assign(num_objects, nullptr);
+        p->gv[n].assign(num_objects, nullptr);
+    }
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
@@ -1042,6 +1055,8 @@ extern "C" void nif_paper_destroy(nif_paper* p) {
             if (p->d_packed[n][f]) (void)hipFree(p->d_packed[n][f]);
     }
     if (p->d_objs) (void)hipFree(p->d_objs);
+    for (int n = 0; n < 2; ++n)
+        if (p->d_tab[n]) (void)hipFree(p->d_tab[n]);
     delete p;
 }
 
@@ -1063,6 +1078,7 @@ extern "C" nif_status nif_paper_set_object(nif_paper* p, int32_t obj, const floa
     o.grid[1] = inner_grid;
     p->set[obj] = true;
     for (bool& b : p->prepared) b = false;
+    p->tab_dirty[0] = p->tab_dirty[1] = true;
     return ok();
 }
 
@@ -1154,5 +1170,106 @@ extern "C" nif_status nif_paper_query(nif_paper* p, int32_t dtype, const float* 
         a.pack[net] = p->pack[net][dtype];
     }
     HIP_TRY(launch_paper(dtype, a, p->num_cus, (hipStream_t)stream));
+    return ok();
+}
+
+extern "C" nif_status nif_paper_set_train(nif_paper* p, int32_t network, float* w, float* m, float* v, void* stream) {
+    if (!p || !w || !m || !v) return fail(NIF_ERR_INVALID_ARG, "nif_paper_set_train: NULL argument");
+    if (network != 0 && network != 1) return fail(NIF_ERR_INVALID_ARG, "network must be 0 (outer) or 1 (inner)");
+    nif_status st = nif_paper_set_mlp(p, network, w, stream);  // the inference master starts from w
+    if (st != NIF_OK) return st;
+    p->w[network] = w;
+    p->mlp_m[network] = m;
+    p->mlp_v[network] = v;
+    return ok();
+}
+
+extern "C" nif_status nif_paper_set_object_train(nif_paper* p, int32_t obj, int32_t network, float* grid_grad,
+                                                 float* grid_m, float* grid_v) {
+    if (!p || !grid_grad || !grid_m || !grid_v) return fail(NIF_ERR_INVALID_ARG, "nif_paper_set_object_train: NULL argument");
+    if (obj < 0 || obj >= p->K || !p->set[obj]) return fail(NIF_ERR_INVALID_ARG, "object %d not registered", obj);
+    if (network != 0 && network != 1) return fail(NIF_ERR_INVALID_ARG, "network must be 0 (outer) or 1 (inner)");
+    p->gg[network][obj] = grid_grad;
+    p->gm[network][obj] = grid_m;
+    p->gv[network][obj] = grid_v;
+    p->tab_dirty[network] = true;
+    return ok();
+}
+
+extern "C" size_t nif_paper_train_workspace_bytes(const nif_paper* p, int32_t network, int64_t n) {
+    if (!p || n < 0 || (network != 0 && network != 1)) return 0;
+    return paper_train_workspace_bytes(network, n);
+}
+
+extern "C" nif_status nif_paper_train_step(nif_paper* p, int32_t network, const float* rays, const int32_t* ids,
+                                           const float* tmax, const uint8_t* labels, int64_t n, int32_t step,
+                                           const nif_adam* adam, float* loss, float* mlp_grad, void* ws,
+                                           size_t ws_bytes, void* stream) {
+    if (!p) return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: NULL handle");
+    if (network != 0 && network != 1) return fail(NIF_ERR_INVALID_ARG, "network must be 0 (outer) or 1 (inner)");
+    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: n < 0");
+    if (n > 0 && (!rays || !ids || !tmax || !labels)) return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: NULL input");
+    if (n > ((int64_t)1 << 31) - 1) return fail(NIF_ERR_UNSUPPORTED, "nif_paper_train_step: n must be below 2^31");
+    if (adam && step < 1) return fail(NIF_ERR_INVALID_ARG, "step must be >= 1");
+    if (adam && !(adam->lr > 0.0f && adam->beta1 >= 0.0f && adam->beta1 < 1.0f && adam->beta2 >= 0.0f &&
+                  adam->beta2 < 1.0f && adam->eps >= 0.0f))
+        return fail(NIF_ERR_INVALID_ARG, "invalid Adam hyper-parameters");
+    if (!p->w[network]) return fail(NIF_ERR_STATE, "network %d has no training buffers", network);
+    for (int k = 0; k < p->K; ++k) {
+        if (!p->set[k]) return fail(NIF_ERR_STATE, "object %d not registered", k);
+        if (!p->gg[network][k]) return fail(NIF_ERR_STATE, "object %d has no training buffers for network %d", k, network);
+    }
+    const size_t need = paper_train_workspace_bytes(network, n);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    const int K = p->K;
+    if (!p->d_objs) HIP_TRY(hipMalloc(&p->d_objs, sizeof(PaperObj) * K));
+    if (!p->d_tab[network]) HIP_TRY(hipMalloc(&p->d_tab[network], sizeof(void*) * 4 * K));
+    if (p->tab_dirty[network]) {
+        std::vector<void*> tab((size_t)4 * K);
+        for (int k = 0; k < K; ++k) {
+            tab[k] = p->gg[network][k];
+            tab[K + k] = p->gm[network][k];
+            tab[2 * K + k] = p->gv[network][k];
+            tab[3 * K + k] = const_cast<void*>(p->objs[k].grid[network]);
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpy(p->d_tab[network], tab.data(), sizeof(void*) * tab.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_objs, p->objs.data(), sizeof(PaperObj) * K, hipMemcpyHostToDevice));
+        p->tab_dirty[network] = false;
+    }
+    const int64_t ge = paper_grid_elems(network);
+    for (int k = 0; k < K; ++k) HIP_TRY(launch_paper_zero(p->gg[network][k], ge, s));
+    PaperTrainArgs a{};
+    a.rays = rays;
+    a.ids = ids;
+    a.tmax = tmax;
+    a.labels = labels;
+    a.n = n;
+    a.objs = p->d_objs;
+    a.num_objects = K;
+    a.w = p->w[network];
+    a.mlp_m = p->mlp_m[network];
+    a.mlp_v = p->mlp_v[network];
+    a.padded = p->d_master[network];
+    float* const* tab = reinterpret_cast<float* const*>(p->d_tab[network]);
+    a.grid_grad = tab;
+    a.grid_m = tab + K;
+    a.grid_v = tab + 2 * K;
+    a.grid = reinterpret_cast<void* const*>(tab + 3 * K);
+    a.grad_out = mlp_grad;
+    a.loss_out = loss;
+    a.use_adam = adam ? 1 : 0;
+    if (adam) {
+        a.adam.lr = adam->lr;
+        a.adam.beta1 = adam->beta1;
+        a.adam.beta2 = adam->beta2;
+        a.adam.eps = adam->eps;
+        a.adam.bc1 = (float)(1.0 - std::pow((double)adam->beta1, step));
+        a.adam.bc2 = (float)(1.0 - std::pow((double)adam->beta2, step));
+    }
+    HIP_TRY(launch_paper_train(network, a, ws, s));
+    if (adam)
+        for (bool& b : p->prepared) b = false;  // the weights changed: nif_paper_prepare packs them again
     return ok();
 }

@@ -102,6 +102,43 @@ struct PaperArgs {
 // Both networks in one launch: outer and inner queries, misses and invalid input.
 hipError_t launch_paper(int flavor, const PaperArgs& a, int num_cus, hipStream_t s);
 
+struct AdamDev {
+    float lr, beta1, beta2, eps;
+    float bc1, bc2;  // 1 - beta^step
+};
+
+// Training of one of the paper's networks (binary32, L2 loss).
+struct PaperTrainArgs {
+    const float* rays;
+    const int32_t* ids;
+    const float* tmax;
+    const uint8_t* labels;  // 1 = visible
+    int64_t n;
+    const PaperObj* objs;
+    int32_t num_objects;
+    float* w;               // binary32 master, unpadded [W1 | W2..WH | w_out], updated by Adam
+    float* mlp_m;
+    float* mlp_v;
+    float* padded;          // the inference master (64-wide), refreshed after the update
+    float* ws_h;            // rows h0 [n][din], h1..hH [n][width]
+    float* ws_d;            // rows delta_1..delta_H [n][width]
+    float* dz;              // [n], dL/dz times the batch size
+    float* const* grid_grad;  // per object: gradient of this network's grid buffer (binary32)
+    float* const* grid_m;
+    float* const* grid_v;
+    void* const* grid;        // per object: the binary16 grid buffer
+    float* dw;              // [P] sums over the batch
+    float* loss_sum;
+    uint32_t* count;        // queries of this network's class
+    float* grad_out;        // nullable: dL/dW
+    float* loss_out;        // nullable
+    AdamDev adam;
+    int32_t use_adam;
+};
+size_t paper_train_workspace_bytes(int network, int64_t n);
+hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream_t s);
+hipError_t launch_paper_zero(float* p, int64_t n, hipStream_t s);
+
 struct OrderArgs {
     const float* rays;
     const int32_t* ids;
@@ -128,10 +165,6 @@ int order_bits(int32_t num_objects);
 size_t order_workspace_bytes(int64_t n, int32_t num_objects);
 hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out);
 
-struct AdamDev {
-    float lr, beta1, beta2, eps;
-    float bc1, bc2;  // 1 - beta^step
-};
 
 struct TrainArgs {
     const float* rays;

@@ -16,15 +16,14 @@ constexpr int kInnerR = 128, kInnerN = 5, kInnerR1 = 128, kInnerN1 = 3;
 constexpr float kPi = 3.14159265358979f, kInvPi = 0.318309886183791f, kInv2Pi = 0.159154943091895f;
 
 // (u, v) = (theta / pi, (phi + pi) / (2 pi)) of the direction of q, in [0, 1];
-// q = 0 maps to theta = 0, phi = 0.
+// q = 0 maps to theta = 0, phi = 0 (atan2 of two zeros).
 __device__ __forceinline__ void sph_uv(const float q[3], float& u, float& v) {
 #pragma clang fp contract(off)
-    float l2 = q[0] * q[0];
-    l2 = l2 + q[1] * q[1];
-    l2 = l2 + q[2] * q[2];
-    float cz = l2 > 0.0f ? q[2] * rsqrtf(l2) : 1.0f;
-    cz = fminf(fmaxf(cz, -1.0f), 1.0f);
-    const float theta = acosf(cz), phi = atan2f(q[1], q[0]);
+    float rxy2 = q[0] * q[0];
+    rxy2 = rxy2 + q[1] * q[1];
+    // polar angle as atan2(|q_xy|, q_z): well conditioned near the poles, where
+    // arccos of q_z / |q| is not
+    const float theta = atan2f(sqrtf(rxy2), q[2]), phi = atan2f(q[1], q[0]);
     u = fminf(fmaxf(theta * kInvPi, 0.0f), 1.0f);
     v = fminf(fmaxf((phi + kPi) * kInv2Pi, 0.0f), 1.0f);
 }
@@ -215,6 +214,353 @@ hipError_t launch_paper(int flavor, const PaperArgs& a, int num_cus, hipStream_t
     case kF16: return launch_paper_t<kF16>(a, num_cus, s);
     }
     return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Training of the paper's networks (Sec. 5 "Training": L2 loss and Adam; the
+// latents are trained with the MLP through back-propagation, Fig. 2).
+// Binary32, one thread per query (the paper trains on batches of 2^11 and
+// 2^12 rays): forward with the rows of every layer kept in the workspace, then
+// the deltas, then the latent gradients scattered with binary32 atomics.
+// Sums over the batch are scaled by 1/B (B = the queries of the network's
+// class) where they are consumed.
+// ---------------------------------------------------------------------------
+template <int NET> struct PaperDims;
+template <> struct PaperDims<0> { static constexpr int din = 6, width = 64, hidden = 2, N = kOuterN, R = kOuterR; };
+template <> struct PaperDims<1> { static constexpr int din = 13, width = 48, hidden = 3, N = kInnerN, R = kInnerR; };
+template <int NET> constexpr int paper_params() {
+    using D = PaperDims<NET>;
+    return D::width * D::din + (D::hidden - 1) * D::width * D::width + D::width;
+}
+
+__device__ __forceinline__ float leaky_grad(float h) { return h > 0.0f ? 1.0f : kLeakySlope; }
+
+// Grid coordinates of a query: position (u, v), direction (u, v), distance r.
+template <int NET>
+__device__ __forceinline__ void paper_coords(const float o[3], const float d[3], float ta, const PaperObj& ob,
+                                             float pu[2], float du[2], float& r) {
+#pragma clang fp contract(off)
+    float qv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float p = NET == 0 ? o[a] + ta * d[a] : o[a];
+        qv[a] = (p - ob.c[a]) * ob.ih[a];
+    }
+    sph_uv(qv, pu[0], pu[1]);
+    sph_uv(d, du[0], du[1]);
+    float l2 = qv[0] * qv[0];
+    l2 = l2 + qv[1] * qv[1];
+    l2 = l2 + qv[2] * qv[2];
+    r = fminf(sqrtf(l2) / 1.7320508f, 1.0f);
+}
+
+// Class of a query (as in the forward kernel) and its segment start.
+__device__ __forceinline__ int paper_class(const float o[3], const float d[3], float tm, int32_t id, int32_t K,
+                                           const PaperObj* objs, float& ta) {
+    ta = 0.0f;
+    if (query_error_bits(o, d, tm, id, K)) return -1;
+    const PaperObj& ob = objs[id];
+    float tb;
+    if (!clip_segment(o, d, tm, ob.lo, ob.hi, ta, tb)) return 0;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inside = inside && o[a] > ob.lo[a] && o[a] < ob.hi[a];
+    return inside ? 2 : 1;
+}
+
+template <int NET>
+__global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
+    using D = PaperDims<NET>;
+    constexpr int W = D::width, DI = D::din, H = D::hidden, N = D::N, R = D::R;
+    constexpr int P = paper_params<NET>();
+    __shared__ float w[P];
+    for (int i = threadIdx.x; i < P; i += blockDim.x) w[i] = A.w[i];
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.n) return;
+    auto hrow = [&](int j) { return A.ws_h + (j == 0 ? q * DI : A.n * DI + ((int64_t)(j - 1) * A.n + q) * W); };
+    auto drow = [&](int j) { return A.ws_d + ((int64_t)(j - 1) * A.n + q) * W; };
+    float o[3], d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[a] = A.rays[q * 6 + a];
+        d[a] = A.rays[q * 6 + 3 + a];
+    }
+    const float tm = A.tmax[q];
+    const int32_t id = A.ids[q];
+    float ta;
+    const int cls = paper_class(o, d, tm, id, A.num_objects, A.objs, ta);
+    if (cls != NET + 1) {  // not in this network's batch: zero rows
+        for (int i = 0; i < DI; ++i) hrow(0)[i] = 0.0f;
+        for (int j = 1; j <= H; ++j)
+            for (int i = 0; i < W; ++i) hrow(j)[i] = drow(j)[i] = 0.0f;
+        A.dz[q] = 0.0f;
+        return;
+    }
+    const PaperObj ob = A.objs[id];
+    const GLOBAL _Float16* g = (const GLOBAL _Float16*)ob.grid[NET];
+    float pu[2], du[2], r;
+    paper_coords<NET>(o, d, ta, ob, pu, du, r);
+    float x[DI];
+    lookup2d<R, N>(g, pu[0], pu[1], x);
+    lookup2d<R, N>(g + (size_t)R * R * N, du[0], du[1], x + N);
+    if constexpr (NET == 1) {
+        float wr;
+        const uint32_t c = grid_cell(r, kInnerR1, wr);
+        const GLOBAL _Float16* gr = g + (size_t)2 * R * R * N + c * kInnerN1;
+#pragma unroll
+        for (int f = 0; f < kInnerN1; ++f) x[2 * N + f] = fmaf(wr, (float)gr[kInnerN1 + f], (1.0f - wr) * (float)gr[f]);
+    }
+    for (int i = 0; i < DI; ++i) hrow(0)[i] = x[i];
+    // forward: rows of every layer in the workspace
+    int off = 0;
+    for (int j = 1; j <= H; ++j) {
+        const int in = j == 1 ? DI : W;
+        const float* hin = hrow(j - 1);
+        float* hout = hrow(j);
+        for (int k = 0; k < W; ++k) {
+            float a = 0.0f;
+            for (int i = 0; i < in; ++i) a = fmaf(w[off + k * in + i], hin[i], a);
+            hout[k] = fmaxf(a, kLeakySlope * a);
+        }
+        off += W * in;
+    }
+    float z = 0.0f;
+    {
+        const float* hH = hrow(H);
+        for (int k = 0; k < W; ++k) z = fmaf(w[off + k], hH[k], z);
+    }
+    const float y = 1.0f / (1.0f + expf(-z));
+    const float t = A.labels[q] ? 1.0f : 0.0f;
+    atomicAdd(A.loss_sum, (y - t) * (y - t));
+    atomicAdd(A.count, 1u);
+    const float dz = 2.0f * (y - t) * y * (1.0f - y);
+    A.dz[q] = dz;
+    // deltas, layer H down to 1; the input gradient from W1
+    {
+        const float* hH = hrow(H);
+        float* dH = drow(H);
+        for (int k = 0; k < W; ++k) dH[k] = dz * w[off + k] * leaky_grad(hH[k]);
+    }
+    float gx[DI];
+    for (int j = H; j >= 1; --j) {
+        const int in = j == 1 ? DI : W;
+        off -= W * in;
+        const float* dj = drow(j);
+        if (j > 1) {
+            const float* hprev = hrow(j - 1);
+            float* dprev = drow(j - 1);
+            for (int i = 0; i < W; ++i) {
+                float b = 0.0f;
+                for (int k = 0; k < W; ++k) b = fmaf(w[off + k * W + i], dj[k], b);
+                dprev[i] = b * leaky_grad(hprev[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < DI; ++i) {
+                float b = 0.0f;
+                for (int k = 0; k < W; ++k) b = fmaf(w[off + k * DI + i], dj[k], b);
+                gx[i] = b;
+            }
+        }
+    }
+    // latent gradients: bilinear corners of the position and direction grids
+    // (and the two samples of the distance grid)
+    float* gg = A.grid_grad[id];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        float wa, wb;
+        const uint32_t a = grid_cell(e ? du[0] : pu[0], R, wa), b = grid_cell(e ? du[1] : pu[1], R, wb);
+        float* base = gg + (size_t)e * R * R * N + ((size_t)a * R + b) * N;
+        const float cw[4] = {(1.0f - wa) * (1.0f - wb), wa * (1.0f - wb), (1.0f - wa) * wb, wa * wb};
+        const size_t co[4] = {0, (size_t)R * N, N, (size_t)R * N + N};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int f = 0; f < N; ++f) atomicAdd(base + co[c] + f, cw[c] * gx[e * N + f]);
+    }
+    if constexpr (NET == 1) {
+        float wr;
+        const uint32_t c = grid_cell(r, kInnerR1, wr);
+        float* base = gg + (size_t)2 * R * R * N + c * kInnerN1;
+#pragma unroll
+        for (int f = 0; f < kInnerN1; ++f) {
+            atomicAdd(base + f, (1.0f - wr) * gx[2 * N + f]);
+            atomicAdd(base + kInnerN1 + f, wr * gx[2 * N + f]);
+        }
+    }
+}
+
+// dW sums: thread = one weight, blockIdx.y = a chunk of the batch.
+constexpr int kDwChunk = 1024;
+template <int NET>
+__global__ __launch_bounds__(256) void paper_dw_kernel(PaperTrainArgs A) {
+    using D = PaperDims<NET>;
+    constexpr int W = D::width, DI = D::din, H = D::hidden;
+    constexpr int P = paper_params<NET>();
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    // locate (layer j, row k, column i)
+    int j = 1, rem = p, in = DI;
+    while (j <= H && rem >= W * in) {
+        rem -= W * in;
+        ++j;
+        in = W;
+    }
+    const int64_t q0 = (int64_t)blockIdx.y * kDwChunk;
+    const int64_t q1 = q0 + kDwChunk < A.n ? q0 + kDwChunk : A.n;
+    float s = 0.0f;
+    if (j <= H) {  // hidden layer j: sum over q of delta_j[q][k] h_(j-1)[q][i]
+        const int k = rem / in, i = rem % in;
+        const float* dj = A.ws_d + (int64_t)(j - 1) * A.n * W;
+        const float* hp = j == 1 ? A.ws_h : A.ws_h + A.n * DI + (int64_t)(j - 2) * A.n * W;
+        for (int64_t q = q0; q < q1; ++q) s = fmaf(dj[q * W + k], hp[q * in + i], s);
+    } else {  // output row: sum over q of dz[q] h_H[q][i]
+        const float* hH = A.ws_h + A.n * DI + (int64_t)(H - 1) * A.n * W;
+        for (int64_t q = q0; q < q1; ++q) s = fmaf(A.dz[q], hH[q * W + rem], s);
+    }
+    atomicAdd(A.dw + p, s);
+}
+
+__global__ void paper_zero_kernel(float* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void paper_zero_counters_kernel(float* loss_sum, uint32_t* count) {
+    if (threadIdx.x == 0) {
+        *loss_sum = 0.0f;
+        *count = 0u;
+    }
+}
+
+__device__ __forceinline__ float paper_adam(float theta, float g, float& m, float& v, const AdamDev& a) {
+    m = a.beta1 * m + (1.0f - a.beta1) * g;
+    v = a.beta2 * v + (1.0f - a.beta2) * g * g;
+    const float mh = m / a.bc1, vh = v / a.bc2;
+    return theta - a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+// MLP: scale by 1/B, optional gradient output, dense Adam on the master and
+// the matching entry of the 64-wide inference master.
+template <int NET>
+__global__ void paper_mlp_update_kernel(PaperTrainArgs A) {
+    using D = PaperDims<NET>;
+    constexpr int W = D::width, DI = D::din, H = D::hidden;
+    constexpr int P = paper_params<NET>();
+    constexpr int DP = NET == 0 ? 6 : 14;  // padded input width of the inference master
+    const unsigned B = *A.count;
+    const float inv = B ? 1.0f / (float)B : 0.0f;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const float g = A.dw[p] * inv;
+        if (A.grad_out) A.grad_out[p] = g;
+        if (!A.use_adam || B == 0) continue;
+        float m = A.mlp_m[p], v = A.mlp_v[p];
+        const float th = paper_adam(A.w[p], g, m, v, A.adam);
+        A.w[p] = th;
+        A.mlp_m[p] = m;
+        A.mlp_v[p] = v;
+        // position in the padded master
+        int64_t dst;
+        if (p < W * DI) {
+            const int k = p / DI, i = p % DI;
+            int ip = i;
+            if (NET == 1) ip = i < 5 ? i : i < 10 ? i + 2 : i == 10 ? 5 : i == 11 ? 6 : 12;
+            dst = (int64_t)k * DP + ip;
+        } else if (p < W * DI + (H - 1) * W * W) {
+            const int rr = p - W * DI, jj = rr / (W * W), k = (rr % (W * W)) / W, i = rr % W;
+            dst = (int64_t)kWidth * DP + (int64_t)jj * kWidth * kWidth + (int64_t)k * kWidth + i;
+        } else {
+            dst = (int64_t)kWidth * DP + (int64_t)(H - 1) * kWidth * kWidth + (p - W * DI - (H - 1) * W * W);
+        }
+        if (A.padded) A.padded[dst] = th;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) *A.loss_out = B ? *A.loss_sum * inv : 0.0f;
+}
+
+// Latents of one object: scale by 1/B; with Adam, lazy update of the binary16
+// latents whose gradient is non-zero (their gradient then cleared).
+__global__ void paper_grid_update_kernel(PaperTrainArgs A, int32_t obj, int64_t elems) {
+    const unsigned B = *A.count;
+    const float inv = B ? 1.0f / (float)B : 0.0f;
+    float* gg = A.grid_grad[obj];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < elems; e += (int64_t)gridDim.x * blockDim.x) {
+        const float g = gg[e] * inv;
+        if (!A.use_adam) {
+            gg[e] = g;
+            continue;
+        }
+        if (g == 0.0f) continue;
+        gg[e] = 0.0f;
+        float m = A.grid_m[obj][e], v = A.grid_v[obj][e];
+        __half* th = reinterpret_cast<__half*>(A.grid[obj]) + e;
+        const float nt = paper_adam(__half2float(*th), g, m, v, A.adam);
+        A.grid_m[obj][e] = m;
+        A.grid_v[obj][e] = v;
+        *th = __float2half_rn(nt);
+    }
+}
+
+static int64_t paper_grid_elems_dev(int network) {
+    return network == 0 ? 2LL * kOuterR * kOuterR * kOuterN
+                        : 2LL * kInnerR * kInnerR * kInnerN + (int64_t)kInnerR1 * kInnerN1;
+}
+
+size_t paper_train_workspace_bytes(int network, int64_t n) {
+    const int din = network == 0 ? 6 : 13, W = network == 0 ? 64 : 48, H = network == 0 ? 2 : 3;
+    const int P = W * din + (H - 1) * W * W + W;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return al((size_t)n * (din + (size_t)H * W) * 4) + al((size_t)n * H * W * 4) + al((size_t)n * 4) +
+           al((size_t)P * 4) + 256;
+}
+
+hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream_t s) {
+    const int din = network == 0 ? 6 : 13, W = network == 0 ? 64 : 48, H = network == 0 ? 2 : 3;
+    const int P = W * din + (H - 1) * W * W + W;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    uint8_t* p = reinterpret_cast<uint8_t*>(ws);
+    a.ws_h = reinterpret_cast<float*>(p);
+    p += al((size_t)a.n * (din + (size_t)H * W) * 4);
+    a.ws_d = reinterpret_cast<float*>(p);
+    p += al((size_t)a.n * H * W * 4);
+    a.dz = reinterpret_cast<float*>(p);
+    p += al((size_t)a.n * 4);
+    a.dw = reinterpret_cast<float*>(p);
+    p += al((size_t)P * 4);
+    a.loss_sum = reinterpret_cast<float*>(p);
+    a.count = reinterpret_cast<uint32_t*>(p + 4);
+    hipLaunchKernelGGL(paper_zero_counters_kernel, dim3(1), dim3(64), 0, s, a.loss_sum, a.count);
+    hipLaunchKernelGGL(paper_zero_kernel, dim3((P + 255) / 256), dim3(256), 0, s, a.dw, (int64_t)P);
+    // the latent gradients of every object are sums over this batch only
+    const int64_t ge = paper_grid_elems_dev(network);
+    if (a.n > 0) {
+        const unsigned blocks = (unsigned)((a.n + 255) / 256);
+        if (network == 0)
+            hipLaunchKernelGGL(paper_train_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(paper_train_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
+        const dim3 g2((unsigned)((P + 255) / 256), (unsigned)((a.n + kDwChunk - 1) / kDwChunk));
+        if (network == 0)
+            hipLaunchKernelGGL(paper_dw_kernel<0>, g2, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(paper_dw_kernel<1>, g2, dim3(256), 0, s, a);
+    }
+    if (network == 0)
+        hipLaunchKernelGGL(paper_mlp_update_kernel<0>, dim3((P + 255) / 256), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(paper_mlp_update_kernel<1>, dim3((P + 255) / 256), dim3(256), 0, s, a);
+    for (int k = 0; k < a.num_objects; ++k)
+        hipLaunchKernelGGL(paper_grid_update_kernel, dim3((unsigned)((ge + 255) / 256 < 2048 ? (ge + 255) / 256 : 2048)),
+                           dim3(256), 0, s, a, k, ge);
+    return hipGetLastError();
+}
+
+// Zero one object's latent gradient (before a step's scatter).
+hipError_t launch_paper_zero(float* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(paper_zero_kernel, dim3((unsigned)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048)), dim3(256),
+                       0, s, p, n);
+    return hipGetLastError();
 }
 
 }  // namespace nif

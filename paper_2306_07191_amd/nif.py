@@ -35,6 +35,8 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit",
            "nif_paper_mlp_params", "nif_paper_grid_elems", "nif_paper_create", "nif_paper_destroy",
            "nif_paper_set_object", "nif_paper_init_grid", "nif_paper_set_mlp", "nif_paper_prepare", "nif_paper_query",
+           "nif_paper_set_train", "nif_paper_set_object_train", "nif_paper_train_workspace_bytes",
+           "nif_paper_train_step",
            "nif_last_error", "nif_version"]
 
 
@@ -111,6 +113,10 @@ def lib():
             "nif_paper_set_mlp": (i32, [vp, i32, vp, vp]),
             "nif_paper_prepare": (i32, [vp, i32, vp]),
             "nif_paper_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp]),
+            "nif_paper_set_train": (i32, [vp, i32, vp, vp, vp, vp]),
+            "nif_paper_set_object_train": (i32, [vp, i32, i32, vp, vp, vp]),
+            "nif_paper_train_workspace_bytes": (sz, [vp, i32, i64]),
+            "nif_paper_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
             "nif_last_error": (C.c_char_p, []),
             "nif_version": (C.c_char_p, []),
         }
@@ -220,6 +226,46 @@ class PaperModel:
         _check(lib().nif_paper_query(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(out),
                                      _ptr(logits), _stream()), "nif_paper_query")
         return out
+
+    def setup_training(self, network: int, w=None):
+        """Training buffers of `network`: binary32 master (from w, or the weights
+        given to set_mlp), zero Adam moments, and per object the latent gradient
+        and moments.  Returns the master tensor (updated in place by Adam)."""
+        t = self.torch
+        if w is None:
+            w = self._w[network]
+        master = t.as_tensor(np.asarray(w, np.float32) if not isinstance(w, t.Tensor) else w).to(
+            self.device, t.float32).clone().contiguous()
+        m, v = t.zeros_like(master), t.zeros_like(master)
+        self._train = getattr(self, "_train", {})
+        self._train[network] = {"w": master, "m": m, "v": v, "grids": []}
+        _check(lib().nif_paper_set_train(self.h, network, _ptr(master), _ptr(m), _ptr(v), _stream()),
+               "nif_paper_set_train")
+        n = self.grid_elems(network)
+        for k in range(self.K):
+            bufs = [t.zeros(n, dtype=t.float32, device=self.device) for _ in range(3)]
+            self._train[network]["grids"].append(bufs)
+            _check(lib().nif_paper_set_object_train(self.h, k, network, _ptr(bufs[0]), _ptr(bufs[1]), _ptr(bufs[2])),
+                   "nif_paper_set_object_train")
+        return master
+
+    def grid_grad(self, obj: int, network: int):
+        return self._train[network]["grids"][obj][0]
+
+    def train_step(self, network: int, rays, ids, tmax, labels, step: int = 1, adam=None, mlp_grad=None, ws=None):
+        """One step; returns the loss tensor (device scalar).  adam: (lr, beta1,
+        beta2, eps) or None for gradients only."""
+        t = self.torch
+        n = ids.shape[0]
+        if ws is None:
+            ws = t.empty(max(1, int(lib().nif_paper_train_workspace_bytes(self.h, network, n))), dtype=t.uint8,
+                         device=self.device)
+        loss = t.zeros(1, dtype=t.float32, device=self.device)
+        ad = None if adam is None else C.byref(Adam(*[float(a) for a in adam]))
+        _check(lib().nif_paper_train_step(self.h, network, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(labels), n, step,
+                                          ad, _ptr(loss), _ptr(mlp_grad), _ptr(ws), ws.numel(), _stream()),
+               "nif_paper_train_step")
+        return loss
 
     def close(self):
         if getattr(self, "h", None):

@@ -168,3 +168,87 @@ def test_paper_argument_errors():
         pm.set_object(0, np.array([0, 0, 0, 1, 0, 1], np.float32))
     pm.prepare("f32")
     pm.query(r[:0], i[:0], t[:0], "f32")  # n = 0 is a no-op
+
+
+def _rel_err(got, want):
+    got, want = np.asarray(got, np.float64).ravel(), np.asarray(want, np.float64).ravel()
+    return float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)), float(np.abs(got - want).max())
+
+
+@pytest.mark.parametrize("network", [0, 1])
+def test_paper_training_matches_oracle(network):
+    """L2 loss, MLP gradient and latent gradients of one batch (the paper's 2^11 /
+    2^12 rays) against the binary64 oracle; then one Adam step (Sec. 5:
+    lr 5e-3, beta 0.9 / 0.999, eps 1e-15) against the oracle's update; then the
+    loss goes down over further steps on the batch."""
+    import torch
+    n = 2048 if network == 0 else 4096
+    rays, ids, tmax = workload(n, 31 + network)
+    labels = np.random.default_rng(40 + network).integers(0, 2, n).astype(np.uint8)
+    amp = 0.05
+    go, gi = oracle_grids(amp)
+    w = weights()[network]
+    # A pre-activation within the binary32 error of the features (about 1e-4 of
+    # the layer's largest) may sit on the other side of the leaky ReLU's kink on
+    # the GPU, which changes that query's backward pass: such queries are left
+    # out of the batch (given an invalid object id) so that both sides take the
+    # same branch.  The ones kept are at least 1e-3 of the largest away from 0
+    # (ten times the measured feature error).
+    cls, x = PN.features(network, rays, ids, tmax, BOXES, go if network == 0 else gi)
+    s = np.nonzero(cls == network + 1)[0]
+    h, near = x[s], np.zeros(s.size, bool)
+    for m in PN.split_weights(w, network)[:-1]:
+        a = h @ m.T
+        near |= (np.abs(a) < 1e-3 * np.abs(a).max()).any(1)
+        h = PN.leaky(a)
+    ids = ids.copy()
+    ids[s[near]] = BOXES.shape[0] + 2
+    assert near.mean() < 0.6
+    pm = make_model(amp)
+    master = pm.setup_training(network)
+    P = pm.mlp_params(network)
+    grad = torch.empty(P, device="cuda")
+    args = [torch.from_numpy(a).cuda() for a in (rays, ids, tmax, labels)]
+    loss = pm.train_step(network, *args, step=1, adam=None, mlp_grad=grad)
+    torch.cuda.synchronize()
+    loss64, B, dW, gg = PN.train_grads(network, rays, ids, tmax, labels, BOXES, go if network == 0 else gi, w)
+    assert B > n // 8
+    assert abs(float(loss.item()) - loss64) <= 1e-5 * loss64
+    rel, mx = _rel_err(grad.cpu().numpy(), dW)
+    print(f"paper train net {network}: loss {loss64:.6f}, dW rel {rel:.2e}")
+    assert rel <= 1e-4 and mx <= 1e-3 * np.abs(dW).max()
+    ggpu = []
+    for k in range(BOXES.shape[0]):
+        got = pm.grid_grad(k, network).cpu().numpy()
+        ggpu.append(got)
+        want = np.concatenate([a.ravel() for a in gg[k]])
+        rel, mx = _rel_err(got, want)
+        print(f"  object {k} latent gradient rel {rel:.2e}, {int((want != 0).sum())} touched")
+        assert rel <= 1e-4 and mx <= 1e-3 * np.abs(want).max()
+        # the same latents are touched, except corners whose weight is about 0 where
+        # binary32 and binary64 coordinates pick neighbouring cells
+        one_side = (got != 0) != (want != 0)
+        assert np.abs(np.where(one_side, got - want, 0)).max() <= 1e-4 * np.abs(want).max()
+    # one Adam step from zero moments
+    hp = (5e-3, 0.9, 0.999, 1e-15)
+    pm.train_step(network, *args, step=1, adam=hp)
+    torch.cuda.synchronize()
+    w_new, _, _ = O.adam_step(w.astype(np.float64), np.zeros_like(dW), np.zeros_like(dW), dW, 1, *hp, lazy=False)
+    big = np.abs(dW) > 1e-4 * np.abs(dW).max()  # the first step moves by lr sign(g): skip sign-ambiguous entries
+    np.testing.assert_allclose(master.cpu().numpy()[big], w_new[big], rtol=0, atol=1e-6)
+    for k in range(BOXES.shape[0]):
+        want = np.concatenate([a.ravel() for a in gg[k]])
+        g0 = O.init_grid(SEED, PN.init_key(k, network), amp, "f16", PN.grid_elems(network)).view(np.float16)
+        th, _, _ = O.adam_step(g0.astype(np.float64), np.zeros_like(want), np.zeros_like(want), want, 1, *hp, lazy=True)
+        got = pm.grids[k][network].cpu().numpy().astype(np.float64)
+        sel = np.abs(want) > 1e-4 * np.abs(want).max()
+        np.testing.assert_allclose(got[sel], th.astype(np.float16).astype(np.float64)[sel], rtol=0, atol=1e-3 * amp)
+        untouched = (want == 0) & (ggpu[k] == 0)  # lazy rule: zero gradient, latent kept
+        np.testing.assert_array_equal(got[untouched], g0.astype(np.float64)[untouched])
+    # further steps on the batch lower the loss
+    losses = [float(pm.train_step(network, *args, step=s, adam=hp).item()) for s in range(2, 40)]
+    print(f"  loss {loss64:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.8 * loss64
+    pm.prepare("bf16")  # the trained weights pack again for queries
+    y, _ = run(pm, rays, ids, tmax, "bf16")
+    assert np.isfinite(y[PN.classify(rays, ids, tmax, BOXES)[0] > 0]).all()
