@@ -521,7 +521,8 @@ def run_paper(args):
     n = 1920 * 1080
     box = S.frame_aabb()
     outer, tout = S.rays_ground_to_light(n, S.rng(S.CFG_FRAME, 1))
-    inner, tin = S.rays_surface_to_light(n, S.frame_mesh(), S.rng(S.CFG_FRAME, 8))
+    mesh = S.frame_mesh()
+    inner, tin = S.rays_surface_to_light(n, mesh, S.rng(S.CFG_FRAME, 8), offset=1e-3)
     mixed = np.empty_like(outer)
     mixed[0::2], mixed[1::2] = outer[0::2], inner[1::2]
     tmix = np.where(np.arange(n) % 2 == 0, tout, tin).astype(np.float32)
@@ -545,6 +546,46 @@ def run_paper(args):
                                 "tflops": flop[k] * n / sec / 1e12, "io_tb_s": 36 * n / sec / 1e12}
             log(f"paper {k} {dt}: {sec * 1e6:.1f} us = {n / sec / 1e9:.2f} G queries/s, "
                 f"{36 * n / sec / 1e12:.2f} TB/s of query I/O, {flop[k] * n / sec / 1e12:.0f} TFLOP/s")
+    # training (Sec. 5 "Training": L2 loss, Adam lr 5e-3, beta 0.9 / 0.999, eps 1e-15,
+    # batches of 2^11 outer and 2^12 inner rays), labels from the GPU BVH of the mesh
+    bvh = nif.BVH(mesh)
+    hp = (5e-3, 0.9, 0.999, 1e-15)
+    train = {}
+    labels_full = {k: bvh.anyhit(*dev[k]) for k in ("outer", "inner")}
+    for net, key, batch in ((0, "outer", 2048), (1, "inner", 4096)):
+        pm.setup_training(net)
+        batches = []
+        for step in range(1, 65):
+            g = S.rng(S.CFG_TRAIN, 5, 1000 * net + step)
+            if net == 0:
+                r_, t_ = S.rays_ground_to_light(batch, g)
+            else:
+                r_, t_ = S.rays_surface_to_light(batch, mesh, g, offset=1e-3)
+            rt, tt = torch.from_numpy(r_).cuda(), torch.from_numpy(t_).cuda()
+            batches.append((rt, torch.zeros(batch, dtype=torch.int32, device="cuda"), tt, bvh.anyhit(rt, tt)))
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        losses = []
+        ev[0].record()
+        for step, b in enumerate(batches, 1):
+            losses.append(pm.train_step(net, *b, step=step, adam=hp))
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        losses = [float(l.item()) for l in losses]
+        train[key] = {"batch": batch, "steps": 64, "train_rays_per_s": batch * 64 / (ms / 1e3),
+                      "ms_per_step": ms / 64, "loss_first": losses[0], "loss_last": losses[-1]}
+        log(f"paper train {key}: 64 x {batch} rays in {ms:.1f} ms = {batch * 64 / ms * 1e3 / 1e6:.2f} M rays/s; "
+            f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    for dt in ("f32", "bf16"):
+        pm.prepare(dt)
+        for key in ("outer", "inner"):
+            yq = pm.query(dev[key][0], ids, dev[key][1], dt)
+            mis = float(((yq >= 0.5) != (labels_full[key] == 1)).float().mean().item())
+            train[key][f"misclassified_{dt}"] = mis
+            log(f"paper {key} {dt}: misclassification after training {100 * mis:.2f} % "
+                f"(occluded {100 * (1 - labels_full[key].float().mean().item()):.1f} %)")
+    bvh.close()
     head = res["outer_bf16"]
     cpu = None
     if not args.no_cpu:
@@ -575,6 +616,7 @@ def run_paper(args):
                      "mfma_frac": head["tflops"] / PEAK_TFLOPS["bf16"]},
         "cpu_baseline": cpu,
         "per_case": res,
+        "training": train,
     }
     print(json.dumps(out), flush=True)
     pm.close()

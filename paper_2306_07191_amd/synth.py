@@ -253,10 +253,12 @@ def rays_inside_box(n: int, aabb: np.ndarray, gen: np.random.Generator):
 
 
 def rays_surface_to_light(n: int, tris: np.ndarray, gen: np.random.Generator, light_y=FRAME_LIGHT_Y,
-                          light_half=FRAME_LIGHT_HALF):
+                          light_half=FRAME_LIGHT_HALF, offset: float = 0.0):
     """Shadow rays of the inner network: origins at uniform barycentric points of
     uniformly chosen triangles (on the object, so inside its AABB), aimed at
-    uniform points of the frame's area light; t_max = the distance."""
+    uniform points of the frame's area light; t_max = the distance.  offset > 0
+    moves each origin that far towards the light (and shortens t_max), so that
+    exact labels do not count the surface the ray starts on."""
     t = tris[gen.integers(0, tris.shape[0], n)].astype(np.float64).reshape(n, 3, 3)
     a, b = gen.uniform(size=n), gen.uniform(size=n)
     flip = a + b > 1.0
@@ -266,6 +268,9 @@ def rays_surface_to_light(n: int, tris: np.ndarray, gen: np.random.Generator, li
     lp[:, 0] = gen.uniform(-light_half, light_half, n)
     lp[:, 1] = light_y
     lp[:, 2] = gen.uniform(-light_half, light_half, n)
+    if offset > 0.0:
+        u = lp - o
+        o = o + offset * u / np.linalg.norm(u, axis=1, keepdims=True)
     o32 = o.astype(np.float32)
     v = lp.astype(np.float32) - o32
     d = _normalize32(v)
