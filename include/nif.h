@@ -386,6 +386,26 @@ nif_status nif_paper_train_step(nif_paper* p, int32_t network, const float* rays
                                 const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* Light importance sampling of training rays (Sec. 5 "Training": directions
+ * drawn in proportion to radiant flux from a tabulated CDF searched by
+ * bisection; Sec. 6 "Comparison of Sampling Method").
+ * nif_light_create: num_tris emitting triangles (host, 9 floats each, non-
+ *   degenerate) with radiance (host, >= 0, not all 0); flux pi L A, running
+ *   sums in triangle order / total as the binary32 table (last entry 1),
+ *   copied to the current device (the handle owns it).
+ * nif_light_sample: for n shading points (dev, n x 3) and random numbers u
+ *   (dev, n x 3, in [0, 1)): triangle = first table entry > u0; point =
+ *   v0 + b1 (v1 - v0) + b2 (v2 - v0), b1 = 1 - sqrt(u1), b2 = u2 sqrt(u1);
+ *   rays (dev, n x 6) = the point x and the unit direction to the light
+ *   point, t_max (dev, n) = the distance, pdf (dev, n, nullable) = the
+ *   solid-angle density P(tri) / area * dist^2 / |n . d|, tri (dev, n,
+ *   nullable) = the triangle chosen. */
+typedef struct nif_light nif_light;
+nif_status nif_light_create(const float* tris, const float* radiance, int64_t num_tris, nif_light** out);
+void nif_light_destroy(nif_light* light);
+nif_status nif_light_sample(const nif_light* light, const float* points, const float* u, int64_t n, float* rays,
+                            float* t_max, float* pdf, int32_t* tri, void* stream);
+
 /* Plain BVH any-hit ray casting: exact shadow-ray labels for training and the
  * baseline the paper compares against (Sec. 6 "Performance Evaluation").
  * nif_bvh_create: builds a binned-SAH BVH on the host from num_tris

@@ -1273,3 +1273,44 @@ extern "C" nif_status nif_paper_train_step(nif_paper* p, int32_t network, const 
         for (bool& b : p->prepared) b = false;  // the weights changed: nif_paper_prepare packs them again
     return ok();
 }
+
+// ---------------------------------------------------------------------------
+// Light importance sampling of training rays (Sec. 5 "Training").
+// ---------------------------------------------------------------------------
+struct nif_light {
+    void* table = nullptr;
+};
+
+extern "C" nif_status nif_light_create(const float* tris, const float* radiance, int64_t num_tris, nif_light** out) {
+    if (!out) return fail(NIF_ERR_INVALID_ARG, "nif_light_create: NULL out");
+    *out = nullptr;
+    if (!tris || !radiance) return fail(NIF_ERR_INVALID_ARG, "nif_light_create: NULL argument");
+    if (num_tris < 1 || num_tris > ((int64_t)1 << 30)) return fail(NIF_ERR_INVALID_ARG, "nif_light_create: num_tris out of range");
+    for (int64_t i = 0; i < 9 * num_tris; ++i)
+        if (!isfinite(tris[i])) return fail(NIF_ERR_INVALID_ARG, "nif_light_create: non-finite vertex");
+    void* h = nullptr;
+    const char* why = nullptr;
+    hipError_t e = light_create(tris, radiance, num_tris, &h, &why);
+    if (why) return fail(NIF_ERR_INVALID_ARG, "nif_light_create: %s", why);
+    if (e != hipSuccess) return fail(NIF_ERR_HIP, "nif_light_create: %s", hipGetErrorString(e));
+    nif_light* l = new nif_light;
+    l->table = h;
+    *out = l;
+    return ok();
+}
+
+extern "C" void nif_light_destroy(nif_light* l) {
+    if (!l) return;
+    light_destroy(l->table);
+    delete l;
+}
+
+extern "C" nif_status nif_light_sample(const nif_light* l, const float* points, const float* u, int64_t n, float* rays,
+                                       float* t_max, float* pdf, int32_t* tri, void* stream) {
+    if (!l) return fail(NIF_ERR_INVALID_ARG, "nif_light_sample: NULL handle");
+    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_light_sample: n < 0");
+    if (n == 0) return ok();
+    if (!points || !u || !rays || !t_max) return fail(NIF_ERR_INVALID_ARG, "nif_light_sample: NULL input or output");
+    HIP_TRY(launch_light_sample(l->table, points, u, n, rays, t_max, pdf, tri, (hipStream_t)stream));
+    return ok();
+}

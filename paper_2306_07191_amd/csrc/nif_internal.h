@@ -139,6 +139,13 @@ size_t paper_train_workspace_bytes(int network, int64_t n);
 hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream_t s);
 hipError_t launch_paper_zero(float* p, int64_t n, hipStream_t s);
 
+// Light importance sampling (opaque table on the device).
+hipError_t light_create(const float* tris, const float* radiance, int64_t L, void** out, const char** why);
+void light_destroy(void* h);
+int32_t light_count(const void* h);
+hipError_t launch_light_sample(const void* h, const float* points, const float* u, int64_t n, float* rays,
+                               float* tmax, float* pdf, int32_t* which, hipStream_t s);
+
 struct OrderArgs {
     const float* rays;
     const int32_t* ids;

@@ -36,7 +36,7 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_paper_mlp_params", "nif_paper_grid_elems", "nif_paper_create", "nif_paper_destroy",
            "nif_paper_set_object", "nif_paper_init_grid", "nif_paper_set_mlp", "nif_paper_prepare", "nif_paper_query",
            "nif_paper_set_train", "nif_paper_set_object_train", "nif_paper_train_workspace_bytes",
-           "nif_paper_train_step",
+           "nif_paper_train_step", "nif_light_create", "nif_light_destroy", "nif_light_sample",
            "nif_last_error", "nif_version"]
 
 
@@ -117,6 +117,9 @@ def lib():
             "nif_paper_set_object_train": (i32, [vp, i32, i32, vp, vp, vp]),
             "nif_paper_train_workspace_bytes": (sz, [vp, i32, i64]),
             "nif_paper_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
+            "nif_light_create": (i32, [vp, vp, i64, vp]),
+            "nif_light_destroy": (None, [vp]),
+            "nif_light_sample": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
             "nif_last_error": (C.c_char_p, []),
             "nif_version": (C.c_char_p, []),
         }
@@ -165,6 +168,40 @@ class BVH:
     def close(self):
         if getattr(self, "h", None):
             lib().nif_bvh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Light:
+    """Light importance sampling table (flux CDF) of emitting triangles."""
+
+    def __init__(self, tris, radiance):
+        t = np.ascontiguousarray(tris, np.float32).reshape(-1, 9)
+        r = np.ascontiguousarray(radiance, np.float32).reshape(-1)
+        h = C.c_void_p()
+        _check(lib().nif_light_create(t.ctypes.data, r.ctypes.data, t.shape[0], C.byref(h)), "nif_light_create")
+        self.h = h
+
+    def sample(self, points, u, want_pdf: bool = True, want_tri: bool = True):
+        """(rays [n, 6], t_max [n], pdf [n] or None, tri [n] or None) on the device."""
+        import torch
+        n = points.shape[0]
+        rays = torch.empty((n, 6), dtype=torch.float32, device=points.device)
+        tmax = torch.empty(n, dtype=torch.float32, device=points.device)
+        pdf = torch.empty(n, dtype=torch.float32, device=points.device) if want_pdf else None
+        tri = torch.empty(n, dtype=torch.int32, device=points.device) if want_tri else None
+        _check(lib().nif_light_sample(self.h, _ptr(points), _ptr(u), n, _ptr(rays), _ptr(tmax), _ptr(pdf), _ptr(tri),
+                                      _stream()), "nif_light_sample")
+        return rays, tmax, pdf, tri
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nif_light_destroy(self.h)
             self.h = None
 
     def __del__(self):
