@@ -586,6 +586,19 @@ def run_paper(args):
             log(f"paper {key} {dt}: misclassification after training {100 * mis:.2f} % "
                 f"(occluded {100 * (1 - labels_full[key].float().mean().item()):.1f} %)")
     bvh.close()
+    # light importance sampling of training rays: 10,000 emitting triangles with
+    # log-normal radiance above the scene, one sample per ground point
+    g = S.rng(S.CFG_TRAIN, 6)
+    nl = 10000
+    lc = np.stack([g.uniform(-3, 3, nl), g.uniform(4.5, 5.5, nl), g.uniform(-3, 3, nl)], 1)
+    ltris = (lc[:, None, :] + g.normal(size=(nl, 3, 3)) * 0.05).reshape(nl, 9).astype(np.float32)
+    light = nif.Light(ltris, np.exp(g.normal(size=nl)).astype(np.float32))
+    pts = dev["outer"][0][:, :3].contiguous()
+    uu = torch.from_numpy(g.uniform(size=(n, 3)).astype(np.float32)).cuda()
+    sec = time_launches(lambda: light.sample(pts, uu), args.steps, args.warmup)
+    light_rate = {"samples": n, "triangles": nl, "us": sec * 1e6, "samples_per_s": n / sec}
+    log(f"light sampling: {n} samples over {nl} triangles in {sec * 1e6:.1f} us = {n / sec / 1e9:.2f} G/s")
+    light.close()
     head = res["outer_bf16"]
     cpu = None
     if not args.no_cpu:
@@ -617,6 +630,7 @@ def run_paper(args):
         "cpu_baseline": cpu,
         "per_case": res,
         "training": train,
+        "light_sampling": light_rate,
     }
     print(json.dumps(out), flush=True)
     pm.close()
