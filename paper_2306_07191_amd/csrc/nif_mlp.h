@@ -50,15 +50,20 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
 __device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
 }
-// four floats -> four OCP E4M3 bytes, round to nearest even, saturated to +-448
-__device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d) {
-    a = fminf(fmaxf(a, -448.0f), 448.0f);
-    b = fminf(fmaxf(b, -448.0f), 448.0f);
-    c = fminf(fmaxf(c, -448.0f), 448.0f);
-    d = fminf(fmaxf(d, -448.0f), 448.0f);
+// four floats in [-448, 448] -> four OCP E4M3 bytes, round to nearest even
+__device__ __forceinline__ int pack_fp8x4_clamped(float a, float b, float c, float d) {
     int r = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    r = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, r, true);
-    return r;
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, r, true);
+}
+// saturated to +-448 first (the conversion itself does not saturate)
+__device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d) {
+    return pack_fp8x4_clamped(__builtin_amdgcn_fmed3f(a, -448.0f, 448.0f), __builtin_amdgcn_fmed3f(b, -448.0f, 448.0f),
+                              __builtin_amdgcn_fmed3f(c, -448.0f, 448.0f), __builtin_amdgcn_fmed3f(d, -448.0f, 448.0f));
+}
+// ReLU and saturation in one step (the scale is positive): median of (x, 0, 448)
+__device__ __forceinline__ int pack_fp8x4_relu(float a, float b, float c, float d) {
+    return pack_fp8x4_clamped(__builtin_amdgcn_fmed3f(a, 0.0f, 448.0f), __builtin_amdgcn_fmed3f(b, 0.0f, 448.0f),
+                              __builtin_amdgcn_fmed3f(c, 0.0f, 448.0f), __builtin_amdgcn_fmed3f(d, 0.0f, 448.0f));
 }
 
 // ReLU of a pair of rounded binary16 / bfloat16 values (sign and magnitude):
@@ -165,7 +170,8 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
             float v = acc[c / 16][c % 16];
             if constexpr (FLAV == kFP8) v *= deq;
             // 16-bit operands with ReLU: rounded first, the ReLU taken on the packed pairs
-            h[c] = (ACT == 0 && (FLAV == kBF16 || FLAV == kF16)) ? v : activate<ACT>(v);
+            // with ReLU, 16-bit and FP8 operands take the ReLU at packing time
+            h[c] = (ACT == 0 && FLAV != kF32) ? v : activate<ACT>(v);
         }
         acc[0] = f32x16{};
         acc[1] = f32x16{};
@@ -205,7 +211,7 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
             i32x8 b8;
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                b8[q] = pack_fp8x4(h[4 * q] * inv_next, h[4 * q + 1] * inv_next, h[4 * q + 2] * inv_next,
+                b8[q] = pack_fp8x4_relu(h[4 * q] * inv_next, h[4 * q + 1] * inv_next, h[4 * q + 2] * inv_next,
                                    h[4 * q + 3] * inv_next);
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
