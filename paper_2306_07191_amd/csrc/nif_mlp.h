@@ -164,12 +164,13 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
             inv_next = 1.0f / scales[hidden + j];
         }
         // activations of the previous layer: local c = 16 mt + r
+        // FP8: dequantise and scale for the next layer's codes in one product
+        const float qs = deq * inv_next;
         float h[32];
 #pragma unroll
         for (int c = 0; c < 32; ++c) {
             float v = acc[c / 16][c % 16];
-            if constexpr (FLAV == kFP8) v *= deq;
-            // 16-bit operands with ReLU: rounded first, the ReLU taken on the packed pairs
+            if constexpr (FLAV == kFP8) v *= qs;
             // with ReLU, 16-bit and FP8 operands take the ReLU at packing time
             h[c] = (ACT == 0 && FLAV != kF32) ? v : activate<ACT>(v);
         }
@@ -211,8 +212,7 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
             i32x8 b8;
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                b8[q] = pack_fp8x4_relu(h[4 * q] * inv_next, h[4 * q + 1] * inv_next, h[4 * q + 2] * inv_next,
-                                   h[4 * q + 3] * inv_next);
+                b8[q] = pack_fp8x4_relu(h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]);
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
                 i32x4 lo = load_packet(Lj, (mt * 2 + 0) * 64 + lane);
