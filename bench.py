@@ -783,12 +783,23 @@ def main():
         enc_sec = time_launches(lambda: ctx.encode(rays, ids, tmax), max(5, args.steps // 5), 2)
         mlp_sec = time_launches(lambda: ctx.mlp(feats, dtype=HEADLINE_DTYPE), max(5, args.steps // 5), 2)
         mlp_tflops = flops * n / mlp_sec / 1e12
+        del feats
+        # the same with the features stored in the MLP's own 16-bit format (half the bytes)
+        f16s, _ = ctx.encode16(rays, ids, tmax, HEADLINE_DTYPE)
+        enc16_sec = time_launches(lambda: ctx.encode16(rays, ids, tmax, HEADLINE_DTYPE), max(5, args.steps // 5), 2)
+        z16 = torch.empty(n, dtype=torch.float32, device="cuda")
+        mlp16_sec = time_launches(lambda: ctx.mlp16(f16s, HEADLINE_DTYPE, out=z16), max(5, args.steps // 5), 2)
+        mlp16_tflops = flops * n / mlp16_sec / 1e12
         stages = {"encode_us": enc_sec * 1e6, "mlp_us": mlp_sec * 1e6, "mlp_tflops": mlp_tflops,
                   "mlp_frac_of_peak": mlp_tflops / PEAK_TFLOPS[HEADLINE_DTYPE],
+                  "encode16_us": enc16_sec * 1e6, "mlp16_us": mlp16_sec * 1e6, "mlp16_tflops": mlp16_tflops,
+                  "mlp16_frac_of_peak": mlp16_tflops / PEAK_TFLOPS[HEADLINE_DTYPE],
                   "encode_gather_rate_per_s": 3 * sh.levels * 8 * n / enc_sec}
         log(f"stages: encode {enc_sec * 1e6:.1f} us, mlp ({HEADLINE_DTYPE}) {mlp_sec * 1e6:.1f} us "
-            f"= {mlp_tflops:.1f} TFLOP/s ({100 * mlp_tflops / PEAK_TFLOPS[HEADLINE_DTYPE]:.1f}% of peak)")
-        del feats
+            f"= {mlp_tflops:.1f} TFLOP/s ({100 * mlp_tflops / PEAK_TFLOPS[HEADLINE_DTYPE]:.1f}% of peak); "
+            f"16-bit features: encode {enc16_sec * 1e6:.1f} us, mlp {mlp16_sec * 1e6:.1f} us = {mlp16_tflops:.1f} "
+            f"TFLOP/s ({100 * mlp16_tflops / PEAK_TFLOPS[HEADLINE_DTYPE]:.1f}% of peak)")
+        del f16s
         ctx.set_option(nif.NIF_OPT_ORDER, 2)
 
     # the contract timing for the headline dtype: a step is the ordering pass plus

@@ -251,11 +251,20 @@ void nif_plan_destroy(nif_plan* plan);
  *   nullable): 1 = the segment meets the AABB, 0 = miss (features 0),
  *   -1 = invalid query.  Needs nif_prepare (any dtype) for the object table.
  * nif_mlp: logits z (dev, n) of MLP `mlp` on given features (dev, n x din),
- *   in `dtype` arithmetic as nif_query. */
+ *   in `dtype` arithmetic as nif_query.
+ * nif_encode16 / nif_mlp16: the same with the features stored as 16-bit
+ *   values of format fmt / dtype (NIF_F16 or NIF_BF16, rounded to nearest-
+ *   even; dev, 8-byte aligned, n x din values): the MLP rounds its input to
+ *   that format anyway, so nif_mlp16 on nif_encode16's features gives the
+ *   logits of nif_query with that dtype, reading half the bytes. */
 nif_status nif_encode(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max, int64_t n,
                       float* features, int32_t* status, void* stream);
 nif_status nif_mlp(nif_ctx* ctx, int32_t dtype, int32_t mlp, const float* features, int64_t n, float* logits,
                    void* stream);
+nif_status nif_encode16(nif_ctx* ctx, int32_t fmt, const float* rays, const int32_t* object_ids, const float* t_max,
+                        int64_t n, void* features, int32_t* status, void* stream);
+nif_status nif_mlp16(nif_ctx* ctx, int32_t dtype, int32_t mlp, const void* features, int64_t n, float* logits,
+                     void* stream);
 
 /* Adam hyper-parameters (Sec. 5 "Training"). */
 typedef struct {

@@ -533,8 +533,8 @@ static void fill_common(const nif_ctx* c, FwdArgs& a) {
     for (int l = 0; l < c->d.levels; ++l) a.res[l] = c->res[l];
 }
 
-extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
-                                 float* features, int32_t* status, void* stream) {
+static nif_status encode_impl(nif_ctx* c, int32_t feat16, const float* rays, const int32_t* ids, const float* tmax,
+                              int64_t n, void* features, int32_t* status, void* stream) {
     if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_encode: NULL context");
     if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_encode: n < 0");
     if (n == 0) return ok();
@@ -547,11 +547,25 @@ extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* i
     a.ids = ids;
     a.tmax = tmax;
     a.n = n;
-    a.features = features;
+    a.features = reinterpret_cast<float*>(features);
+    a.feat16 = feat16;
     a.status_out = status;
     a.pack = c->pack[kF32];
     HIP_TRY(launch_encode(c->d.levels, c->d.grid_dtype, a, c->num_cus, (hipStream_t)stream));
     return ok();
+}
+
+extern "C" nif_status nif_encode(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
+                                 float* features, int32_t* status, void* stream) {
+    return encode_impl(c, 0, rays, ids, tmax, n, features, status, stream);
+}
+
+extern "C" nif_status nif_encode16(nif_ctx* c, int32_t fmt, const float* rays, const int32_t* ids, const float* tmax,
+                                   int64_t n, void* features, int32_t* status, void* stream) {
+    if (fmt != NIF_F16 && fmt != NIF_BF16) return fail(NIF_ERR_UNSUPPORTED, "nif_encode16: format must be NIF_F16 or NIF_BF16");
+    if (reinterpret_cast<uintptr_t>(features) % 8 != 0)
+        return fail(NIF_ERR_INVALID_ARG, "nif_encode16: features must be 8-byte aligned");
+    return encode_impl(c, fmt, rays, ids, tmax, n, features, status, stream);
 }
 
 extern "C" size_t nif_pairs_workspace_bytes(const nif_ctx* c, int64_t n_rays) {
@@ -637,8 +651,8 @@ extern "C" nif_status nif_calibrate_fp8(nif_ctx* c, int32_t mlp, const float* ra
     return ok();
 }
 
-extern "C" nif_status nif_mlp(nif_ctx* c, int32_t dtype, int32_t mlp, const float* features, int64_t n,
-                              float* logits, void* stream) {
+static nif_status mlp_impl(nif_ctx* c, int32_t dtype, int32_t feat16, int32_t mlp, const void* features, int64_t n,
+                           float* logits, void* stream) {
     if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_mlp: NULL context");
     if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_mlp: n < 0");
     if (dtype < 0 || dtype > 3) return fail(NIF_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
@@ -650,15 +664,32 @@ extern "C" nif_status nif_mlp(nif_ctx* c, int32_t dtype, int32_t mlp, const floa
     FwdArgs a{};
     fill_common(c, a);
     a.n = n;
-    a.features = const_cast<float*>(features);
+    a.features = reinterpret_cast<float*>(const_cast<void*>(features));
+    a.feat16 = feat16;
     a.fixed_mlp = mlp;
     a.logit = logits;
     a.vis = nullptr;
     a.packed = c->d_packed[dtype];
     a.pack = c->pack[dtype];
     a.fp8_scales = dtype == kFP8 ? c->d_scales : nullptr;
-    HIP_TRY(launch_mlp(dtype, c->d.levels, a, c->num_cus, (hipStream_t)stream));
+    if (feat16)
+        HIP_TRY(launch_mlp16(dtype, c->d.levels, a, c->num_cus, (hipStream_t)stream));
+    else
+        HIP_TRY(launch_mlp(dtype, c->d.levels, a, c->num_cus, (hipStream_t)stream));
     return ok();
+}
+
+extern "C" nif_status nif_mlp(nif_ctx* c, int32_t dtype, int32_t mlp, const float* features, int64_t n,
+                              float* logits, void* stream) {
+    return mlp_impl(c, dtype, 0, mlp, features, n, logits, stream);
+}
+
+extern "C" nif_status nif_mlp16(nif_ctx* c, int32_t dtype, int32_t mlp, const void* features, int64_t n,
+                                float* logits, void* stream) {
+    if (dtype != NIF_F16 && dtype != NIF_BF16) return fail(NIF_ERR_UNSUPPORTED, "nif_mlp16: dtype must be NIF_F16 or NIF_BF16");
+    if (reinterpret_cast<uintptr_t>(features) % 8 != 0)
+        return fail(NIF_ERR_INVALID_ARG, "nif_mlp16: features must be 8-byte aligned");
+    return mlp_impl(c, dtype, dtype, mlp, features, n, logits, stream);
 }
 
 extern "C" size_t nif_touched_bytes(const nif_ctx* c) {

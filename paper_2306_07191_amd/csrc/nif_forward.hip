@@ -27,6 +27,8 @@
 
 namespace nif {
 
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
 PackInfo pack_info(int flavor, int din, int hidden) {
     PackInfo p{};
     p.din = din;
@@ -345,9 +347,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
             if (inb) {
                 status = 1;
                 mlp = A.fixed_mlp;
-                const float* src = A.features + q * (2 * KH1) + half * KH1;
+                if (A.feat16) {  // 16-bit features convert exactly; the MLP rounds them to themselves
+                    const i32x2* src = reinterpret_cast<const i32x2*>(A.features) + (q * (2 * KH1) + half * KH1) / 4;
 #pragma unroll
-                for (int c = 0; c < KH1; ++c) xin[c] = src[c];
+                    for (int v = 0; v < KH1 / 4; ++v) {
+                        const i32x2 w = src[v];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const uint16_t b = (uint16_t)((uint32_t)w[e / 2] >> (16 * (e % 2)));
+                            xin[4 * v + e] = A.feat16 == kBF16 ? (float)__builtin_bit_cast(__bf16, b)
+                                                               : (float)__builtin_bit_cast(_Float16, b);
+                        }
+                    }
+                } else {
+                    const float* src = A.features + q * (2 * KH1) + half * KH1;
+#pragma unroll
+                    for (int c = 0; c < KH1; ++c) xin[c] = src[c];
+                }
             }
         } else if (inb) {
             const uint32_t err = query_error_bits(o, d, tm, id, A.num_objects);
@@ -370,12 +386,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
             }
         }
         if (MODE == 1) {
-            if (inb) {
+            if (inb && A.feat16) {  // rounded to nearest-even, as the MLP would
+                i32x2* dst = reinterpret_cast<i32x2*>(A.features) + (q * (2 * KH1) + half * KH1) / 4;
+#pragma unroll
+                for (int v = 0; v < KH1 / 4; ++v) {
+                    i32x2 w;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float a = xin[4 * v + 2 * e], b = xin[4 * v + 2 * e + 1];
+                        w[e] = (int)(A.feat16 == kBF16 ? pack_bf16x2(a, b) : pack_f16x2(a, b));
+                    }
+                    dst[v] = w;
+                }
+            } else if (inb) {
                 float* dst = A.features + q * (2 * KH1) + half * KH1;
 #pragma unroll
                 for (int c = 0; c < KH1; ++c) dst[c] = xin[c];
-                if (half == 0 && A.status_out) A.status_out[q] = status;
             }
+            if (inb && half == 0 && A.status_out) A.status_out[q] = status;
             continue;
         }
         // waterfall over the distinct MLPs of the wave's queries
@@ -413,6 +441,72 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
             if (A.logit) A.logit[q] = zo;
         }
     }
+}
+
+// Inference stage on 16-bit features stored in the MLP's operand format: the
+// packed pairs go to the first MFMA as they are, and each wave loads its next
+// tile's features while the current tile runs.
+template <int FLAV, int L>
+__global__ __launch_bounds__(kBlock) void nif_mlp16_kernel(FwdArgs A) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr int KH1 = 3 * L;
+    constexpr int NW = KH1 / 2;  // packed words per lane
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int qlane = lane & 31;
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * A.xcd_stride + (b >> 3);
+    const int64_t t_begin = (int64_t)lb * A.num_tiles / A.tiles_per_block_num;
+    const int64_t t_end = (int64_t)(lb + 1) * A.num_tiles / A.tiles_per_block_num;
+    if (t_begin >= t_end) return;
+    {
+        const uint8_t* src = A.packed + (int64_t)A.fixed_mlp * A.pack.bytes;
+        const int nvec = (int)(A.pack.bytes / 16);
+        for (int i = threadIdx.x; i < nvec; i += kBlock)
+            reinterpret_cast<i32x4*>(smem)[i] = reinterpret_cast<const i32x4*>(src)[i];
+    }
+    __syncthreads();
+    auto load = [&](int64_t tile, int* w) {
+        const int64_t q = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
+        const i32x2* src = reinterpret_cast<const i32x2*>(A.features) + (q * (2 * KH1) + half * KH1) / 4;
+#pragma unroll
+        for (int v = 0; v < NW / 2; ++v) {
+            const i32x2 t = q < A.n ? src[v] : i32x2{0, 0};
+            w[2 * v] = t[0];
+            w[2 * v + 1] = t[1];
+        }
+    };
+    int cur[NW], nxt[NW];
+    load(t_begin, nxt);
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) cur[i] = nxt[i];
+        if (tile + 1 < t_end) load(tile + 1, nxt);
+        const float z = run_mlp<FLAV, KH1, 0, true>(smem, A.pack, A.hidden, nullptr, nullptr, lane, cur);
+        const int64_t q = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
+        if (q < A.n && half == 0 && A.logit) A.logit[q] = z;
+    }
+}
+
+template <int FLAV, int L>
+static hipError_t launch_mlp16_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
+    FwdArgs a = a0;
+    const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    int64_t blocks = (int64_t)num_cus * (a.blocks_per_cu > 0 ? a.blocks_per_cu : 16);
+    if (blocks > tiles) blocks = tiles;
+    blocks = (blocks + 7) / 8 * 8;
+    a.num_tiles = (int32_t)tiles;
+    a.tiles_per_block_num = (int32_t)blocks;
+    a.xcd_stride = (int32_t)(blocks / 8);
+    hipLaunchKernelGGL((nif_mlp16_kernel<FLAV, L>), dim3((unsigned)blocks), dim3(kBlock), lds_bytes(a.pack), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp16(int flavor, int levels, const FwdArgs& a, int num_cus, hipStream_t s) {
+    if (flavor == kBF16) return levels == 8 ? launch_mlp16_t<kBF16, 8>(a, num_cus, s) : launch_mlp16_t<kBF16, 4>(a, num_cus, s);
+    if (flavor == kF16) return levels == 8 ? launch_mlp16_t<kF16, 8>(a, num_cus, s) : launch_mlp16_t<kF16, 4>(a, num_cus, s);
+    return hipErrorInvalidValue;
 }
 
 template <int FLAV, int L, typename GT, int MODE, int IMG>

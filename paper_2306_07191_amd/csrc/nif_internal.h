@@ -62,6 +62,7 @@ struct FwdArgs {
     int32_t res[kMaxLevels];
     const uint32_t* perm;    // processing order: query perm[q] is handled in slot q (null = identity)
     float* features;         // grid stage output / inference stage input: n x din, or null
+    int32_t feat16;          // features stored as 16-bit values: 0 binary32, kF16 or kBF16
     int32_t* status_out;     // grid stage: 1 query, 0 miss, -1 invalid (nullable)
     int32_t fixed_mlp;       // inference stage: the MLP used by every query
     int32_t tiles_per_block_num;  // tiles are split evenly: block b gets [b*T/G, (b+1)*T/G)
@@ -240,6 +241,7 @@ size_t lds_bytes(const PackInfo& p);
 hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s);
 hipError_t launch_encode(int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s);
 hipError_t launch_mlp(int flavor, int levels, const FwdArgs& a, int num_cus, hipStream_t s);
+hipError_t launch_mlp16(int flavor, int levels, const FwdArgs& a, int num_cus, hipStream_t s);
 // y-pair query image of a binary16 grid: for every table (N cells per axis),
 // entry (x, y, z), x, z in [0, N], y in [0, N-1], holds the two latents of
 // vertex (x, y, z) then those of (x, y+1, z); entries are x-fastest, so one

@@ -85,9 +85,10 @@ __device__ __forceinline__ float activate(float v) {
 
 // Output of one MLP evaluation for the wave's 32 queries: z for this lane's query.
 // xin: this half's layer-1 local inputs (din/2 floats, zero for inactive queries).
-template <int FLAV, int KH1, int ACT = 0>
+// PRE (16-bit operands): xpk holds those inputs already as packed pairs.
+template <int FLAV, int KH1, int ACT = 0, bool PRE = false>
 __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, int hidden, const float* xin,
-                                         const float* scales, int lane) {
+                                         const float* scales, int lane, const int* xpk = nullptr) {
     const int half = lane >> 5;
     f32x16 acc[2];
     // ------------------------------------------------------------------ layer 1
@@ -119,8 +120,12 @@ __device__ __forceinline__ float run_mlp(const uint8_t* img, const PackInfo& P, 
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int c = 8 * p + 2 * q;
-                    float v0 = c < KH1 ? xin[c] : 0.0f, v1 = c + 1 < KH1 ? xin[c + 1] : 0.0f;
-                    b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(v0, v1) : pack_f16x2(v0, v1));
+                    if constexpr (PRE) {
+                        b4[q] = c < KH1 ? xpk[c / 2] : 0;
+                    } else {
+                        float v0 = c < KH1 ? xin[c] : 0.0f, v1 = c + 1 < KH1 ? xin[c + 1] : 0.0f;
+                        b4[q] = (int)(FLAV == kBF16 ? pack_bf16x2(v0, v1) : pack_f16x2(v0, v1));
+                    }
                 }
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt) {

@@ -28,6 +28,7 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
            "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_encode16", "nif_mlp16",
            "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
@@ -95,6 +96,8 @@ def lib():
             "nif_plan_destroy": (None, [vp]),
             "nif_encode": (i32, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "nif_mlp": (i32, [vp, i32, i32, vp, i64, vp, vp]),
+            "nif_encode16": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp]),
+            "nif_mlp16": (i32, [vp, i32, i32, vp, i64, vp, vp]),
             "nif_set_object_train": (i32, [vp, i32, vp, vp, vp, vp]),
             "nif_set_mlp_train": (i32, [vp, i32, vp, vp]),
             "nif_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
@@ -533,6 +536,26 @@ class Context:
             out = t.empty(n, dtype=t.float32, device=self.device)
         _check(lib().nif_query_packed(self.h, DTYPES[dtype], _ptr(packed), _ptr(perm), n, _ptr(out),
                                       _ptr(logits), _stream()), "nif_query_packed")
+        return out
+
+    def encode16(self, rays, ids, tmax, fmt: str = "bf16"):
+        """Grid stage alone with 16-bit features: (features [n, din] int16 bit
+        patterns of fmt, status [n])."""
+        t = self.torch
+        n = ids.shape[0]
+        f = t.empty((n, self.shape.din), dtype=t.int16, device=self.device)
+        st = t.empty(n, dtype=t.int32, device=self.device)
+        _check(lib().nif_encode16(self.h, DTYPES[fmt], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(f), _ptr(st),
+                                  _stream()), "nif_encode16")
+        return f, st
+
+    def mlp16(self, features, dtype: str = "bf16", mlp: int = 0, out=None):
+        """Inference stage on 16-bit features of format dtype; logits [n]."""
+        t = self.torch
+        n = features.shape[0]
+        if out is None:
+            out = t.empty(n, dtype=t.float32, device=self.device)
+        _check(lib().nif_mlp16(self.h, DTYPES[dtype], mlp, _ptr(features), n, _ptr(out), _stream()), "nif_mlp16")
         return out
 
     def encode(self, rays, ids, tmax):

@@ -120,3 +120,32 @@ def test_fp8_calibration_matches_oracle(shape_name):
     e = torch.empty(0, device="cuda")
     got0 = ctx.calibrate_fp8(e.view(0, 6), e.int(), e, mlp=0)
     assert (got0[H:] == 1.0).all()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16"])
+@pytest.mark.parametrize("shape_name", ["tiny", "frame_small"])
+def test_16bit_stages_match_fused_query(fmt, shape_name):
+    """nif_encode16 stores the binary32 features rounded to nearest-even (bit
+    patterns equal to torch's conversion of nif_encode's features), and nif_mlp16
+    on them gives nif_query's logits bit for bit (the MLP rounds its input to
+    the same format)."""
+    import torch
+    from paper_2306_07191_amd import nif
+    w = S.tiny_workload(n_rays=3001) if shape_name == "tiny" else S.frame_workload(n_rays=3001, with_mesh=False)
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_ORDER, 0)
+    ctx.prepare(fmt)
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    f32, st = ctx.encode(rays, ids, tmax)
+    f16, st16 = ctx.encode16(rays, ids, tmax, fmt)
+    tdt = torch.bfloat16 if fmt == "bf16" else torch.float16
+    assert torch.equal(f16, f32.to(tdt).view(torch.int16))
+    assert torch.equal(st, st16)
+    z = ctx.mlp16(f16, fmt)
+    zq = torch.empty_like(z)
+    ctx.query(rays, ids, tmax, dtype=fmt, logits=zq)
+    torch.cuda.synchronize()
+    hit = (st == 1).cpu().numpy()
+    np.testing.assert_array_equal(z.cpu().numpy()[hit], zq.cpu().numpy()[hit])
+    with pytest.raises(nif.NifError):
+        ctx.mlp16(f16, "f32")
