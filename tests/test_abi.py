@@ -81,3 +81,50 @@ def test_validation_before_device_work():
         assert L.nif_last_error() != b""
     finally:
         L.nif_destroy(h)
+
+
+def test_paper_network_and_light_validation_on_the_host():
+    """The paper's networks, light sampling and the 16-bit stages reject bad
+    arguments before any device work."""
+    L = nif.lib()
+    assert L.nif_paper_mlp_params(0) == 4544 and L.nif_paper_mlp_params(1) == 5280
+    assert L.nif_paper_mlp_params(2) == -1 and L.nif_paper_grid_elems(-1) == -1
+    assert L.nif_paper_grid_elems(0) == 2 * 256 * 256 * 3 and L.nif_paper_grid_elems(1) == 2 * 128 * 128 * 5 + 128 * 3
+    h = C.c_void_p()
+    assert L.nif_paper_create(0, C.byref(h)) == -1
+    assert L.nif_paper_create(1, C.byref(h)) == 0
+    try:
+        fake = C.c_void_p(4096)
+        box = np.array([0, 0, 0, 1, 1, 1], np.float32)
+        flat = np.array([0, 0, 0, 1, 0, 1], np.float32)
+        assert L.nif_paper_set_object(h, 1, box.ctypes.data, fake, fake) == -1   # object out of range
+        assert L.nif_paper_set_object(h, 0, flat.ctypes.data, fake, fake) == -1  # degenerate box
+        assert L.nif_paper_set_object(h, 0, box.ctypes.data, None, fake) == -1
+        assert L.nif_paper_set_object(h, 0, box.ctypes.data, fake, fake) == 0
+        assert L.nif_paper_prepare(h, 3, None) == -2      # no FP8 form
+        assert L.nif_paper_prepare(h, 0, None) == -5      # no weights yet
+        assert L.nif_paper_query(h, 0, fake, fake, fake, 10, fake, None, None) == -5  # not prepared
+        assert L.nif_paper_query(h, 0, fake, fake, fake, 0, fake, None, None) == 0    # n = 0
+        assert L.nif_paper_train_step(h, 2, fake, fake, fake, fake, 10, 1, None, None, None, fake, 1 << 30, None) == -1
+        assert L.nif_paper_train_step(h, 0, fake, fake, fake, fake, 10, 1, None, None, None, fake, 1 << 30, None) == -5
+        assert L.nif_paper_set_object_train(h, 0, 2, fake, fake, fake) == -1
+    finally:
+        L.nif_paper_destroy(h)
+    lh = C.c_void_p()
+    tri = np.array([[0, 5, 0, 1, 5, 0, 0, 5, 1]], np.float32)
+    line = np.array([[0, 5, 0, 1, 5, 0, 2, 5, 0]], np.float32)
+    one = np.ones(1, np.float32)
+    assert L.nif_light_create(line.ctypes.data, one.ctypes.data, 1, C.byref(lh)) == -1          # zero area
+    assert L.nif_light_create(tri.ctypes.data, (-one).ctypes.data, 1, C.byref(lh)) == -1       # negative
+    assert L.nif_light_create(tri.ctypes.data, np.zeros(1, np.float32).ctypes.data, 1, C.byref(lh)) == -1  # no flux
+    assert L.nif_light_create(tri.ctypes.data, one.ctypes.data, 0, C.byref(lh)) == -1           # no triangles
+    c = C.c_void_p()
+    assert L.nif_create(C.byref(_desc()), 1, 1, C.byref(c)) == 0
+    try:
+        fake = C.c_void_p(4096)
+        assert L.nif_encode16(c, 0, fake, fake, fake, 10, fake, None, None) == -2  # binary32 is not a 16-bit format
+        assert L.nif_encode16(c, 2, fake, fake, fake, 10, C.c_void_p(4098), None, None) == -1  # misaligned
+        assert L.nif_mlp16(c, 3, 0, fake, 10, fake, None) == -2                    # FP8 is not 16-bit
+        assert L.nif_order_packed(c, fake, fake, fake, 10, fake, C.c_void_p(4100), fake, 1 << 30, None) == -1  # misaligned
+    finally:
+        L.nif_destroy(c)
