@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
 }
 
 // dW sums: thread = one weight, blockIdx.y = a chunk of the batch.
-constexpr int kDwChunk = 1024;
+constexpr int kDwChunk = 64;  // the paper's batches are small: many short chunks fill the chip
 template <int NET>
 __global__ __launch_bounds__(256) void paper_dw_kernel(PaperTrainArgs A) {
     using D = PaperDims<NET>;
@@ -534,11 +534,12 @@ hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream
     // the latent gradients of every object are sums over this batch only
     const int64_t ge = paper_grid_elems_dev(network);
     if (a.n > 0) {
-        const unsigned blocks = (unsigned)((a.n + 255) / 256);
+        // one wave per block: a 2^11-query batch spreads over 32 compute units
+        const unsigned blocks = (unsigned)((a.n + 63) / 64);
         if (network == 0)
-            hipLaunchKernelGGL(paper_train_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(paper_train_kernel<0>, dim3(blocks), dim3(64), 0, s, a);
         else
-            hipLaunchKernelGGL(paper_train_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(paper_train_kernel<1>, dim3(blocks), dim3(64), 0, s, a);
         const dim3 g2((unsigned)((P + 255) / 256), (unsigned)((a.n + kDwChunk - 1) / kDwChunk));
         if (network == 0)
             hipLaunchKernelGGL(paper_dw_kernel<0>, g2, dim3(256), 0, s, a);
