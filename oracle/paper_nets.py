@@ -275,12 +275,14 @@ def leaky_grad(a):
     return np.where(a > 0, 1.0, LEAKY)
 
 
-def train_grads(network: int, rays, ids, tmax, labels, aabb, grids, w):
+def train_grads(network: int, rays, ids, tmax, labels, aabb, grids, w, grad_y=None):
     """L2 training loss of `network` (Sec. 5 "Training": L2 loss) over the
     queries of its class, L = (1/B) sum (y - t)^2 with t = label (1 visible),
     and its gradients by back-propagation (Fig. 2: the latents are trained
     with the MLP): returns (loss, B, dW flat like w, per-object grid
-    gradients as arrays of grid_shapes)."""
+    gradients as arrays of grid_shapes).  With grad_y (dL/dy per query) the
+    gradients are those of that upstream gradient instead (dL/dz = g y (1 - y),
+    no labels, no 1/B) and the loss is None."""
     cls, pu, pv, du, dv, r = transform(rays, ids, tmax, aabb)
     want = CLS_OUTER if network == 0 else CLS_INNER
     s = np.nonzero(cls == want)[0]
@@ -295,7 +297,7 @@ def train_grads(network: int, rays, ids, tmax, labels, aabb, grids, w):
     ids_s = np.asarray(ids, np.int64)[s]
     _, x = features(network, rays, ids, tmax, aabb, grids)
     x = x[s]
-    t = (np.asarray(labels)[s] != 0).astype(np.float64)
+    t = None if grad_y is not None else (np.asarray(labels)[s] != 0).astype(np.float64)
     hs, acts = [x], []
     h = x
     for j in range(H):
@@ -305,8 +307,12 @@ def train_grads(network: int, rays, ids, tmax, labels, aabb, grids, w):
         hs.append(h)
     z = h @ mats[H][0]
     y = 1.0 / (1.0 + np.exp(-z))
-    loss = float(np.mean((y - t) ** 2))
-    dz = 2.0 * (y - t) / B * y * (1.0 - y)
+    if grad_y is not None:
+        loss = None
+        dz = np.asarray(grad_y, np.float64)[s] * y * (1.0 - y)
+    else:
+        loss = float(np.mean((y - t) ** 2))
+        dz = 2.0 * (y - t) / B * y * (1.0 - y)
     dW[H][0] = dz @ hs[H]
     delta = dz[:, None] * mats[H][0][None, :] * leaky_grad(acts[H - 1])
     for j in range(H - 1, -1, -1):

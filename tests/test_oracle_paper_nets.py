@@ -285,3 +285,36 @@ def test_l2_loss_closed_form():
     w2[-64:] = 1.0
     _, _, dW2, gg = PN.train_grads(0, rays, ids, tmax, labels, BOX, grids, w2)
     assert not dW2.any() and not any(a.any() for a in gg[0])
+
+
+def test_upstream_gradient_form_matches_finite_differences():
+    """With a given dL/dy the gradients are those of L = sum g y over the
+    network's queries (central differences of that sum)."""
+    network = 1
+    rays, ids, tmax, labels, w, grids = _train_case(network, n=40, seed=30)
+    gy = np.random.default_rng(31).normal(size=rays.shape[0])
+    loss, B, dW, gg = PN.train_grads(network, rays, ids, tmax, None, BOX, grids, w, grad_y=gy)
+    assert loss is None
+
+    def f(wv, gr):
+        cls, x = PN.features(network, rays, ids, tmax, BOX, gr)
+        s = cls == PN.CLS_INNER
+        y = 1 / (1 + np.exp(-PN.mlp(x[s], wv, network)))
+        return float((gy[s] * y).sum())
+    h = 1e-6
+    g = np.random.default_rng(32)
+    for i in g.choice(w.size, 25, replace=False):
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (f(wp, grids) - f(wm, grids)) / (2 * h)
+        assert abs(fd - dW[i]) <= 1e-5 * max(1e-3, abs(fd)) + 1e-8, (i, fd, dW[i])
+    nz = np.argwhere(gg[0][2] != 0)
+    for idx in nz[:6]:
+        idx = tuple(idx)
+        gp = [a.copy() for a in grids[0]]
+        gm = [a.copy() for a in grids[0]]
+        gp[2][idx] += h
+        gm[2][idx] -= h
+        fd = (f(w, [gp]) - f(w, [gm])) / (2 * h)
+        assert abs(fd - gg[0][2][idx]) <= 1e-5 * max(1e-3, abs(fd)) + 1e-8
