@@ -394,6 +394,14 @@ nif_status nif_paper_train_step(nif_paper* p, int32_t network, const float* rays
                                 const float* t_max, const uint8_t* labels, int64_t n, int32_t step,
                                 const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
                                 void* stream);
+/* nif_paper_backward: as nif_paper_train_step without labels or Adam, for a
+ * given dL/dy per query (grad_visibility, dev, n): dL/dz = g y (1 - y) for
+ * the network's queries, no 1/B; mlp_grad (dev, nullable) and every object's
+ * grid_grad buffer receive dL/dW and dL/dlatents (the torch.autograd bridge
+ * PaperVisibility calls it for each network). */
+nif_status nif_paper_backward(nif_paper* p, int32_t network, const float* rays, const int32_t* object_ids,
+                              const float* t_max, const float* grad_visibility, int64_t n, float* mlp_grad,
+                              void* ws, size_t ws_bytes, void* stream);
 
 /* Light importance sampling of training rays (Sec. 5 "Training": directions
  * drawn in proportion to radiant flux from a tabulated CDF searched by

@@ -1232,14 +1232,15 @@ extern "C" size_t nif_paper_train_workspace_bytes(const nif_paper* p, int32_t ne
     return paper_train_workspace_bytes(network, n);
 }
 
-extern "C" nif_status nif_paper_train_step(nif_paper* p, int32_t network, const float* rays, const int32_t* ids,
-                                           const float* tmax, const uint8_t* labels, int64_t n, int32_t step,
-                                           const nif_adam* adam, float* loss, float* mlp_grad, void* ws,
-                                           size_t ws_bytes, void* stream) {
+static nif_status paper_train_common(nif_paper* p, int32_t network, const float* rays, const int32_t* ids,
+                                     const float* tmax, const uint8_t* labels, const float* grad_y, int64_t n,
+                                     int32_t step, const nif_adam* adam, float* loss, float* mlp_grad, void* ws,
+                                     size_t ws_bytes, void* stream) {
     if (!p) return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: NULL handle");
     if (network != 0 && network != 1) return fail(NIF_ERR_INVALID_ARG, "network must be 0 (outer) or 1 (inner)");
     if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: n < 0");
-    if (n > 0 && (!rays || !ids || !tmax || !labels)) return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: NULL input");
+    if (n > 0 && (!rays || !ids || !tmax || (!labels && !grad_y)))
+        return fail(NIF_ERR_INVALID_ARG, "nif_paper_train_step: NULL input");
     if (n > ((int64_t)1 << 31) - 1) return fail(NIF_ERR_UNSUPPORTED, "nif_paper_train_step: n must be below 2^31");
     if (adam && step < 1) return fail(NIF_ERR_INVALID_ARG, "step must be >= 1");
     if (adam && !(adam->lr > 0.0f && adam->beta1 >= 0.0f && adam->beta1 < 1.0f && adam->beta2 >= 0.0f &&
@@ -1289,7 +1290,8 @@ extern "C" nif_status nif_paper_train_step(nif_paper* p, int32_t network, const 
     a.grid_v = tab + 2 * K;
     a.grid = reinterpret_cast<void* const*>(tab + 3 * K);
     a.grad_out = mlp_grad;
-    a.loss_out = loss;
+    a.loss_out = grad_y ? nullptr : loss;
+    a.grad_y = grad_y;
     a.use_adam = adam ? 1 : 0;
     if (adam) {
         a.adam.lr = adam->lr;
@@ -1344,4 +1346,20 @@ extern "C" nif_status nif_light_sample(const nif_light* l, const float* points, 
     if (!points || !u || !rays || !t_max) return fail(NIF_ERR_INVALID_ARG, "nif_light_sample: NULL input or output");
     HIP_TRY(launch_light_sample(l->table, points, u, n, rays, t_max, pdf, tri, (hipStream_t)stream));
     return ok();
+}
+
+extern "C" nif_status nif_paper_train_step(nif_paper* p, int32_t network, const float* rays, const int32_t* ids,
+                                           const float* tmax, const uint8_t* labels, int64_t n, int32_t step,
+                                           const nif_adam* adam, float* loss, float* mlp_grad, void* ws,
+                                           size_t ws_bytes, void* stream) {
+    return paper_train_common(p, network, rays, ids, tmax, labels, nullptr, n, step, adam, loss, mlp_grad, ws,
+                              ws_bytes, stream);
+}
+
+extern "C" nif_status nif_paper_backward(nif_paper* p, int32_t network, const float* rays, const int32_t* ids,
+                                         const float* tmax, const float* grad_visibility, int64_t n, float* mlp_grad,
+                                         void* ws, size_t ws_bytes, void* stream) {
+    if (n > 0 && !grad_visibility) return fail(NIF_ERR_INVALID_ARG, "nif_paper_backward: NULL grad_visibility");
+    return paper_train_common(p, network, rays, ids, tmax, nullptr, grad_visibility, n, 1, nullptr, nullptr, mlp_grad,
+                              ws, ws_bytes, stream);
 }

@@ -135,6 +135,7 @@ struct PaperTrainArgs {
     float* loss_out;        // nullable
     AdamDev adam;
     int32_t use_adam;
+    const float* grad_y;    // nullable: dL/dy per query instead of labels (gradients only, no 1/B)
 };
 size_t paper_train_workspace_bytes(int network, int64_t n);
 hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream_t s);

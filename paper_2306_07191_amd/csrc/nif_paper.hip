@@ -331,10 +331,15 @@ __global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
         for (int k = 0; k < W; ++k) z = fmaf(w[off + k], hH[k], z);
     }
     const float y = 1.0f / (1.0f + expf(-z));
-    const float t = A.labels[q] ? 1.0f : 0.0f;
-    atomicAdd(A.loss_sum, (y - t) * (y - t));
+    float dz;
+    if (A.grad_y) {  // a given dL/dy: the chain rule through the sigmoid
+        dz = A.grad_y[q] * y * (1.0f - y);
+    } else {
+        const float t = A.labels[q] ? 1.0f : 0.0f;
+        atomicAdd(A.loss_sum, (y - t) * (y - t));
+        dz = 2.0f * (y - t) * y * (1.0f - y);
+    }
     atomicAdd(A.count, 1u);
-    const float dz = 2.0f * (y - t) * y * (1.0f - y);
     A.dz[q] = dz;
     // deltas, layer H down to 1; the input gradient from W1
     {
@@ -450,7 +455,7 @@ __global__ void paper_mlp_update_kernel(PaperTrainArgs A) {
     constexpr int P = paper_params<NET>();
     constexpr int DP = NET == 0 ? 6 : 14;  // padded input width of the inference master
     const unsigned B = *A.count;
-    const float inv = B ? 1.0f / (float)B : 0.0f;
+    const float inv = A.grad_y ? 1.0f : B ? 1.0f / (float)B : 0.0f;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         const float g = A.dw[p] * inv;
         if (A.grad_out) A.grad_out[p] = g;
@@ -482,7 +487,7 @@ __global__ void paper_mlp_update_kernel(PaperTrainArgs A) {
 // latents whose gradient is non-zero (their gradient then cleared).
 __global__ void paper_grid_update_kernel(PaperTrainArgs A, int32_t obj, int64_t elems) {
     const unsigned B = *A.count;
-    const float inv = B ? 1.0f / (float)B : 0.0f;
+    const float inv = A.grad_y ? 1.0f : B ? 1.0f / (float)B : 0.0f;
     float* gg = A.grid_grad[obj];
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < elems; e += (int64_t)gridDim.x * blockDim.x) {
         const float g = gg[e] * inv;

@@ -37,7 +37,7 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_paper_mlp_params", "nif_paper_grid_elems", "nif_paper_create", "nif_paper_destroy",
            "nif_paper_set_object", "nif_paper_init_grid", "nif_paper_set_mlp", "nif_paper_prepare", "nif_paper_query",
            "nif_paper_set_train", "nif_paper_set_object_train", "nif_paper_train_workspace_bytes",
-           "nif_paper_train_step", "nif_light_create", "nif_light_destroy", "nif_light_sample",
+           "nif_paper_train_step", "nif_paper_backward", "nif_light_create", "nif_light_destroy", "nif_light_sample",
            "nif_last_error", "nif_version"]
 
 
@@ -120,6 +120,7 @@ def lib():
             "nif_paper_set_object_train": (i32, [vp, i32, i32, vp, vp, vp]),
             "nif_paper_train_workspace_bytes": (sz, [vp, i32, i64]),
             "nif_paper_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
+            "nif_paper_backward": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_light_create": (i32, [vp, vp, i64, vp]),
             "nif_light_destroy": (None, [vp]),
             "nif_light_sample": (i32, [vp, vp, vp, i64, vp, vp, vp, vp, vp]),
@@ -306,6 +307,16 @@ class PaperModel:
                                           ad, _ptr(loss), _ptr(mlp_grad), _ptr(ws), ws.numel(), _stream()),
                "nif_paper_train_step")
         return loss
+
+    def backward(self, network: int, rays, ids, tmax, grad_y, mlp_grad=None):
+        """Gradients of a given dL/dy through `network` (MLP into mlp_grad, latents
+        into each object's grid_grad buffer)."""
+        t = self.torch
+        n = ids.shape[0]
+        ws = t.empty(max(1, int(lib().nif_paper_train_workspace_bytes(self.h, network, n))), dtype=t.uint8,
+                     device=self.device)
+        _check(lib().nif_paper_backward(self.h, network, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(grad_y), n,
+                                        _ptr(mlp_grad), _ptr(ws), ws.numel(), _stream()), "nif_paper_backward")
 
     def close(self):
         if getattr(self, "h", None):

@@ -252,3 +252,52 @@ def test_paper_training_matches_oracle(network):
     pm.prepare("bf16")  # the trained weights pack again for queries
     y, _ = run(pm, rays, ids, tmax, "bf16")
     assert np.isfinite(y[PN.classify(rays, ids, tmax, BOXES)[0] > 0]).all()
+
+
+def _drop_near_kinks(network, rays, ids, tmax, grids, w, margin=1e-3):
+    """ids with the queries of `network` whose pre-activations lie within
+    margin x the layer's largest of zero made invalid (see the training test)."""
+    cls, x = PN.features(network, rays, ids, tmax, BOXES, grids)
+    s = np.nonzero(cls == network + 1)[0]
+    h, near = x[s], np.zeros(s.size, bool)
+    for m in PN.split_weights(w, network)[:-1]:
+        a = h @ m.T
+        near |= (np.abs(a) < margin * np.abs(a).max()).any(1)
+        h = PN.leaky(a)
+    ids = ids.copy()
+    ids[s[near]] = BOXES.shape[0] + 2
+    return ids
+
+
+def test_paper_autograd_matches_oracle():
+    """PaperVisibility (torch.autograd.Function): y.backward(g) gives, for both
+    networks, the MLP gradients and the latent gradients of the binary64
+    oracle's upstream-gradient form."""
+    import torch
+    from paper_2306_07191_amd.autograd import paper_visibility
+    amp = 0.05
+    rays, ids, tmax = workload(3000, 51)
+    go, gi = oracle_grids(amp)
+    w0, w1 = weights()
+    ids = _drop_near_kinks(0, rays, ids, tmax, go, w0)
+    ids = _drop_near_kinks(1, rays, ids, tmax, gi, w1)
+    pm = make_model(amp)
+    wo, wi = pm.setup_training(0), pm.setup_training(1)
+    wo.requires_grad_(True)
+    wi.requires_grad_(True)
+    R, I, T = (torch.from_numpy(a).cuda() for a in (rays, ids, tmax))
+    y = paper_visibility(pm, R, I, T, wo, wi)
+    g = np.random.default_rng(52).normal(size=ids.shape[0]).astype(np.float32)
+    y.backward(torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    for net, (wt, grids, w) in enumerate(((wo, go, w0), (wi, gi, w1))):
+        _, B, dW, gg = PN.train_grads(net, rays, ids, tmax, None, BOXES, grids, w, grad_y=g.astype(np.float64))
+        assert B > 300
+        rel, mx = _rel_err(wt.grad.cpu().numpy(), dW)
+        print(f"paper autograd net {net}: dW rel {rel:.2e} over {B} queries")
+        assert rel <= 1e-4 and mx <= 1e-3 * np.abs(dW).max()
+        for k in range(BOXES.shape[0]):
+            got = pm.grid_grad(k, net).cpu().numpy()
+            want = np.concatenate([a.ravel() for a in gg[k]])
+            rel, mx = _rel_err(got, want)
+            assert rel <= 1e-4 and mx <= 1e-3 * np.abs(want).max()
