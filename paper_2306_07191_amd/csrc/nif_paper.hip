@@ -268,18 +268,45 @@ __device__ __forceinline__ int paper_class(const float o[3], const float d[3], f
     return inside ? 2 : 1;
 }
 
+// One query per thread, 64 threads per block. The layer inputs sit in
+// registers, the weights and every hidden layer's outputs in LDS (one column
+// per thread, so the per-thread accesses are bank-conflict free), and the rows
+// of the workspace are only written, for the dW sums.
+constexpr int kTrainBlock = 64;
+
+// out[k] = leaky(sum_i w[k IN + i] in[i]), i ascending, for k < W.
+template <int IN, int W>
+__device__ __forceinline__ void paper_train_layer(const float* w, const float (&in)[W], float* col, float* row) {
+    for (int k = 0; k < W; ++k) {
+        float a = 0.0f;
+#pragma unroll
+        for (int i = 0; i < IN; ++i) a = fmaf(w[k * IN + i], in[i], a);
+        const float h = fmaxf(a, kLeakySlope * a);
+        col[k * kTrainBlock] = h;
+        row[k] = h;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void paper_train_load(const float* col, float (&v)[W]) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = col[k * kTrainBlock];
+}
+
 template <int NET>
-__global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
+__global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs A) {
     using D = PaperDims<NET>;
     constexpr int W = D::width, DI = D::din, H = D::hidden, N = D::N, R = D::R;
     constexpr int P = paper_params<NET>();
-    __shared__ float w[P];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) w[i] = A.w[i];
+    __shared__ __attribute__((aligned(16))) float w[P];
+    __shared__ float act[H * W * kTrainBlock];  // act[(j - 1) W + k][thread]: layer j's output k
+    for (int i = threadIdx.x; i < P; i += kTrainBlock) w[i] = A.w[i];
     __syncthreads();
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
     if (q >= A.n) return;
     auto hrow = [&](int j) { return A.ws_h + (j == 0 ? q * DI : A.n * DI + ((int64_t)(j - 1) * A.n + q) * W); };
     auto drow = [&](int j) { return A.ws_d + ((int64_t)(j - 1) * A.n + q) * W; };
+    auto col = [&](int j) { return act + (j - 1) * W * kTrainBlock + threadIdx.x; };
     float o[3], d[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -301,7 +328,9 @@ __global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
     const GLOBAL _Float16* g = (const GLOBAL _Float16*)ob.grid[NET];
     float pu[2], du[2], r;
     paper_coords<NET>(o, d, ta, ob, pu, du, r);
-    float x[DI];
+    float x[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) x[i] = 0.0f;
     lookup2d<R, N>(g, pu[0], pu[1], x);
     lookup2d<R, N>(g + (size_t)R * R * N, du[0], du[1], x + N);
     if constexpr (NET == 1) {
@@ -311,25 +340,22 @@ __global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
 #pragma unroll
         for (int f = 0; f < kInnerN1; ++f) x[2 * N + f] = fmaf(wr, (float)gr[kInnerN1 + f], (1.0f - wr) * (float)gr[f]);
     }
+#pragma unroll
     for (int i = 0; i < DI; ++i) hrow(0)[i] = x[i];
-    // forward: rows of every layer in the workspace
-    int off = 0;
-    for (int j = 1; j <= H; ++j) {
-        const int in = j == 1 ? DI : W;
-        const float* hin = hrow(j - 1);
-        float* hout = hrow(j);
-        for (int k = 0; k < W; ++k) {
-            float a = 0.0f;
-            for (int i = 0; i < in; ++i) a = fmaf(w[off + k * in + i], hin[i], a);
-            hout[k] = fmaxf(a, kLeakySlope * a);
-        }
-        off += W * in;
+    // forward: layer j's outputs to LDS and to row j of the workspace
+    paper_train_layer<DI, W>(w, x, col(1), hrow(1));
+    int off = W * DI;
+    float v[W];
+#pragma unroll
+    for (int j = 2; j <= H; ++j) {
+        paper_train_load<W>(col(j - 1), v);
+        paper_train_layer<W, W>(w + off, v, col(j), hrow(j));
+        off += W * W;
     }
+    paper_train_load<W>(col(H), v);  // h_H
     float z = 0.0f;
-    {
-        const float* hH = hrow(H);
-        for (int k = 0; k < W; ++k) z = fmaf(w[off + k], hH[k], z);
-    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) z = fmaf(w[off + k], v[k], z);
     const float y = 1.0f / (1.0f + expf(-z));
     float dz;
     if (A.grad_y) {  // a given dL/dy: the chain rule through the sigmoid
@@ -341,33 +367,39 @@ __global__ __launch_bounds__(256) void paper_train_kernel(PaperTrainArgs A) {
     }
     atomicAdd(A.count, 1u);
     A.dz[q] = dz;
-    // deltas, layer H down to 1; the input gradient from W1
+    // deltas, layer H down to 1 (v holds the current layer's delta); each
+    // layer's delta replaces the layer's outputs in LDS
     {
-        const float* hH = hrow(H);
         float* dH = drow(H);
-        for (int k = 0; k < W; ++k) dH[k] = dz * w[off + k] * leaky_grad(hH[k]);
-    }
-    float gx[DI];
-    for (int j = H; j >= 1; --j) {
-        const int in = j == 1 ? DI : W;
-        off -= W * in;
-        const float* dj = drow(j);
-        if (j > 1) {
-            const float* hprev = hrow(j - 1);
-            float* dprev = drow(j - 1);
-            for (int i = 0; i < W; ++i) {
-                float b = 0.0f;
-                for (int k = 0; k < W; ++k) b = fmaf(w[off + k * W + i], dj[k], b);
-                dprev[i] = b * leaky_grad(hprev[i]);
-            }
-        } else {
 #pragma unroll
-            for (int i = 0; i < DI; ++i) {
-                float b = 0.0f;
-                for (int k = 0; k < W; ++k) b = fmaf(w[off + k * DI + i], dj[k], b);
-                gx[i] = b;
-            }
+        for (int k = 0; k < W; ++k) {
+            v[k] = dz * w[off + k] * leaky_grad(v[k]);
+            dH[k] = v[k];
         }
+    }
+#pragma unroll
+    for (int j = H; j >= 2; --j) {
+        off -= W * W;
+        float* c = col(j - 1);
+        float* dprev = drow(j - 1);
+        for (int i = 0; i < W; ++i) {
+            float b = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W; ++k) b = fmaf(w[off + k * W + i], v[k], b);
+            const float e = b * leaky_grad(c[i * kTrainBlock]);
+            c[i * kTrainBlock] = e;
+            dprev[i] = e;
+        }
+        paper_train_load<W>(c, v);
+    }
+    off -= W * DI;
+    float gx[DI];
+#pragma unroll
+    for (int i = 0; i < DI; ++i) {
+        float b = 0.0f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) b = fmaf(w[off + k * DI + i], v[k], b);
+        gx[i] = b;
     }
     // latent gradients: bilinear corners of the position and direction grids
     // (and the two samples of the distance grid)
@@ -540,11 +572,11 @@ hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream
     const int64_t ge = paper_grid_elems_dev(network);
     if (a.n > 0) {
         // one wave per block: a 2^11-query batch spreads over 32 compute units
-        const unsigned blocks = (unsigned)((a.n + 63) / 64);
+        const unsigned blocks = (unsigned)((a.n + kTrainBlock - 1) / kTrainBlock);
         if (network == 0)
-            hipLaunchKernelGGL(paper_train_kernel<0>, dim3(blocks), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(paper_train_kernel<0>, dim3(blocks), dim3(kTrainBlock), 0, s, a);
         else
-            hipLaunchKernelGGL(paper_train_kernel<1>, dim3(blocks), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(paper_train_kernel<1>, dim3(blocks), dim3(kTrainBlock), 0, s, a);
         const dim3 g2((unsigned)((P + 255) / 256), (unsigned)((a.n + kDwChunk - 1) / kDwChunk));
         if (network == 0)
             hipLaunchKernelGGL(paper_dw_kernel<0>, g2, dim3(256), 0, s, a);
