@@ -293,6 +293,51 @@ __device__ __forceinline__ void paper_train_load(const float* col, float (&v)[W]
     for (int k = 0; k < W; ++k) v[k] = col[k * kTrainBlock];
 }
 
+// Adds v[m] to dst + off[m] for every active lane of the wave. Lanes with the
+// same dst (rays of one batch towards a small light share direction cells)
+// are summed first, by the lowest of them, in lane order, from LDS scratch of
+// M x 64 floats: one atomic per group and value instead of one per lane.
+// GROUP false: plain atomics (where the cells are spread, the grouping costs
+// more than the contention it removes).
+template <bool GROUP, int M>
+__device__ __forceinline__ void grouped_atomic_add(float* dst, const int (&off)[M], const float (&v)[M],
+                                                   float* scratch) {
+    if constexpr (!GROUP) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) atomicAdd(dst + off[m], v[m]);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < M; ++m) scratch[m * 64 + lane] = v[m];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t key = (uint64_t)dst;
+    const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+    uint64_t todo = __ballot(1), peers = 0;
+    while (todo) {
+        const int l = __builtin_ctzll(todo);
+        const bool same = klo == (uint32_t)__builtin_amdgcn_readlane((int)klo, l) &&
+                          khi == (uint32_t)__builtin_amdgcn_readlane((int)khi, l);
+        const uint64_t g = __ballot(same);
+        if (same) peers = g;
+        todo &= ~g;
+    }
+    if (lane == __builtin_ctzll(peers)) {
+        float acc[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] = v[m];
+        for (uint64_t rest = peers & (peers - 1); rest; rest &= rest - 1) {
+            const int p = __builtin_ctzll(rest);
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] += scratch[m * 64 + p];
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) atomicAdd(dst + off[m], acc[m]);
+    }
+}
+
 template <int NET>
 __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs A) {
     using D = PaperDims<NET>;
@@ -300,6 +345,7 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
     constexpr int P = paper_params<NET>();
     __shared__ __attribute__((aligned(16))) float w[P];
     __shared__ float act[H * W * kTrainBlock];  // act[(j - 1) W + k][thread]: layer j's output k
+    static_assert(kTrainBlock == 64 && 4 * N * 64 <= H * W * kTrainBlock, "one wave per block; scratch of the adds");
     for (int i = threadIdx.x; i < P; i += kTrainBlock) w[i] = A.w[i];
     __syncthreads();
     const int64_t q = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
@@ -402,7 +448,9 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
         gx[i] = b;
     }
     // latent gradients: bilinear corners of the position and direction grids
-    // (and the two samples of the distance grid)
+    // (and the two samples of the distance grid); the hidden outputs in LDS
+    // are spent, so their space is the scratch of the grouped adds (inner
+    // network: rays from one surface share distance and direction cells)
     float* gg = A.grid_grad[id];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -410,21 +458,32 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
         const uint32_t a = grid_cell(e ? du[0] : pu[0], R, wa), b = grid_cell(e ? du[1] : pu[1], R, wb);
         float* base = gg + (size_t)e * R * R * N + ((size_t)a * R + b) * N;
         const float cw[4] = {(1.0f - wa) * (1.0f - wb), wa * (1.0f - wb), (1.0f - wa) * wb, wa * wb};
-        const size_t co[4] = {0, (size_t)R * N, N, (size_t)R * N + N};
+        const int co[4] = {0, R * N, N, R * N + N};
+        float gv[4 * N];
+        int go[4 * N];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int f = 0; f < N; ++f) atomicAdd(base + co[c] + f, cw[c] * gx[e * N + f]);
+            for (int f = 0; f < N; ++f) {
+                gv[c * N + f] = cw[c] * gx[e * N + f];
+                go[c * N + f] = co[c] + f;
+            }
+        grouped_atomic_add<NET == 1, 4 * N>(base, go, gv, act);
     }
     if constexpr (NET == 1) {
         float wr;
         const uint32_t c = grid_cell(r, kInnerR1, wr);
         float* base = gg + (size_t)2 * R * R * N + c * kInnerN1;
+        float gv[2 * kInnerN1];
+        int go[2 * kInnerN1];
 #pragma unroll
         for (int f = 0; f < kInnerN1; ++f) {
-            atomicAdd(base + f, (1.0f - wr) * gx[2 * N + f]);
-            atomicAdd(base + kInnerN1 + f, wr * gx[2 * N + f]);
+            gv[f] = (1.0f - wr) * gx[2 * N + f];
+            gv[kInnerN1 + f] = wr * gx[2 * N + f];
+            go[f] = f;
+            go[kInnerN1 + f] = kInnerN1 + f;
         }
+        grouped_atomic_add<true, 2 * kInnerN1>(base, go, gv, act);
     }
 }
 
