@@ -505,15 +505,31 @@ __global__ __launch_bounds__(256) void paper_dw_kernel(PaperTrainArgs A) {
     }
     const int64_t q0 = (int64_t)blockIdx.y * kDwChunk;
     const int64_t q1 = q0 + kDwChunk < A.n ? q0 + kDwChunk : A.n;
-    float s = 0.0f;
-    if (j <= H) {  // hidden layer j: sum over q of delta_j[q][k] h_(j-1)[q][i]
+    // s = sum over q in [q0, q1), ascending, of a[q sa] b[q sb]; a full chunk
+    // unrolled so that its loads are in flight together
+    const float *a, *b;
+    int64_t sa, sb;
+    if (j <= H) {  // hidden layer j: delta_j[q][k] h_(j-1)[q][i]
         const int k = rem / in, i = rem % in;
-        const float* dj = A.ws_d + (int64_t)(j - 1) * A.n * W;
-        const float* hp = j == 1 ? A.ws_h : A.ws_h + A.n * DI + (int64_t)(j - 2) * A.n * W;
-        for (int64_t q = q0; q < q1; ++q) s = fmaf(dj[q * W + k], hp[q * in + i], s);
-    } else {  // output row: sum over q of dz[q] h_H[q][i]
-        const float* hH = A.ws_h + A.n * DI + (int64_t)(H - 1) * A.n * W;
-        for (int64_t q = q0; q < q1; ++q) s = fmaf(A.dz[q], hH[q * W + rem], s);
+        a = A.ws_d + (int64_t)(j - 1) * A.n * W + k;
+        b = (j == 1 ? A.ws_h : A.ws_h + A.n * DI + (int64_t)(j - 2) * A.n * W) + i;
+        sa = W;
+        sb = in;
+    } else {  // output row: dz[q] h_H[q][i]
+        a = A.dz;
+        b = A.ws_h + A.n * DI + (int64_t)(H - 1) * A.n * W + rem;
+        sa = 1;
+        sb = W;
+    }
+    float s = 0.0f;
+    a += q0 * sa;
+    b += q0 * sb;
+    const int cnt = (int)(q1 - q0), ia = (int)sa, ib = (int)sb;
+    if (cnt == kDwChunk) {
+#pragma unroll 16
+        for (int t = 0; t < kDwChunk; ++t) s = fmaf(a[t * ia], b[t * ib], s);
+    } else {
+        for (int t = 0; t < cnt; ++t) s = fmaf(a[t * ia], b[t * ib], s);
     }
     atomicAdd(A.dw + p, s);
 }
