@@ -268,21 +268,31 @@ __device__ __forceinline__ int paper_class(const float o[3], const float d[3], f
     return inside ? 2 : 1;
 }
 
-// One query per thread, 64 threads per block. The layer inputs sit in
-// registers, the weights and every hidden layer's outputs in LDS (one column
-// per thread, so the per-thread accesses are bank-conflict free), and the rows
-// of the workspace are only written, for the dW sums.
-constexpr int kTrainBlock = 64;
+// Four lanes per query (lanes 4t .. 4t + 3 of a 64-thread block hold query
+// t), so that a small batch fills four times as many waves: lane s of a query
+// computes the outputs k = s, s + 4, ... of every layer. The layer inputs sit
+// in registers, the weights and every hidden layer's outputs in LDS (one
+// column per query, read by the query's four lanes), and the rows of the
+// workspace are only written, for the dW sums.
+constexpr int kTrainBlock = 64, kTrainSplit = 4, kTrainQ = kTrainBlock / kTrainSplit;
 
-// out[k] = leaky(sum_i w[k IN + i] in[i]), i ascending, for k < W.
+// The LDS writes of every lane of the wave before the reads that follow.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// out[k] = leaky(sum_i w[k IN + i] in[i]), i ascending, for this lane's k.
 template <int IN, int W>
-__device__ __forceinline__ void paper_train_layer(const float* w, const float (&in)[W], float* col, float* row) {
-    for (int k = 0; k < W; ++k) {
+__device__ __forceinline__ void paper_train_layer(const float* w, const float (&in)[W], float* col, float* row,
+                                                  int sub) {
+    for (int k = sub; k < W; k += kTrainSplit) {
         float a = 0.0f;
 #pragma unroll
         for (int i = 0; i < IN; ++i) a = fmaf(w[k * IN + i], in[i], a);
         const float h = fmaxf(a, kLeakySlope * a);
-        col[k * kTrainBlock] = h;
+        col[k * kTrainQ] = h;
         row[k] = h;
     }
 }
@@ -290,7 +300,7 @@ __device__ __forceinline__ void paper_train_layer(const float* w, const float (&
 template <int W>
 __device__ __forceinline__ void paper_train_load(const float* col, float (&v)[W]) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) v[k] = col[k * kTrainBlock];
+    for (int k = 0; k < W; ++k) v[k] = col[k * kTrainQ];
 }
 
 // Adds v[m] to dst + off[m] for every active lane of the wave. Lanes with the
@@ -343,16 +353,19 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
     using D = PaperDims<NET>;
     constexpr int W = D::width, DI = D::din, H = D::hidden, N = D::N, R = D::R;
     constexpr int P = paper_params<NET>();
+    constexpr int S = kTrainSplit;
     __shared__ __attribute__((aligned(16))) float w[P];
-    __shared__ float act[H * W * kTrainBlock];  // act[(j - 1) W + k][thread]: layer j's output k
-    static_assert(kTrainBlock == 64 && 4 * N * 64 <= H * W * kTrainBlock, "one wave per block; scratch of the adds");
+    __shared__ float act[H * W * kTrainQ];  // act[(j - 1) W + k][query]: layer j's output k
+    static_assert(kTrainBlock == 64 && N * 64 <= H * W * kTrainQ && W % S == 0,
+                  "one wave per block; scratch of the adds; whole output groups");
     for (int i = threadIdx.x; i < P; i += kTrainBlock) w[i] = A.w[i];
     __syncthreads();
-    const int64_t q = (int64_t)blockIdx.x * kTrainBlock + threadIdx.x;
-    if (q >= A.n) return;
+    const int sub = threadIdx.x % S, ql = threadIdx.x / S;
+    const int64_t q = (int64_t)blockIdx.x * kTrainQ + ql;
+    if (q >= A.n) return;  // the four lanes of a query leave together
     auto hrow = [&](int j) { return A.ws_h + (j == 0 ? q * DI : A.n * DI + ((int64_t)(j - 1) * A.n + q) * W); };
     auto drow = [&](int j) { return A.ws_d + ((int64_t)(j - 1) * A.n + q) * W; };
-    auto col = [&](int j) { return act + (j - 1) * W * kTrainBlock + threadIdx.x; };
+    auto col = [&](int j) { return act + (j - 1) * W * kTrainQ + ql; };
     float o[3], d[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -364,10 +377,10 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
     float ta;
     const int cls = paper_class(o, d, tm, id, A.num_objects, A.objs, ta);
     if (cls != NET + 1) {  // not in this network's batch: zero rows
-        for (int i = 0; i < DI; ++i) hrow(0)[i] = 0.0f;
+        for (int i = sub; i < DI; i += S) hrow(0)[i] = 0.0f;
         for (int j = 1; j <= H; ++j)
-            for (int i = 0; i < W; ++i) hrow(j)[i] = drow(j)[i] = 0.0f;
-        A.dz[q] = 0.0f;
+            for (int i = sub; i < W; i += S) hrow(j)[i] = drow(j)[i] = 0.0f;
+        if (sub == 0) A.dz[q] = 0.0f;
         return;
     }
     const PaperObj ob = A.objs[id];
@@ -387,18 +400,21 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
         for (int f = 0; f < kInnerN1; ++f) x[2 * N + f] = fmaf(wr, (float)gr[kInnerN1 + f], (1.0f - wr) * (float)gr[f]);
     }
 #pragma unroll
-    for (int i = 0; i < DI; ++i) hrow(0)[i] = x[i];
+    for (int i = 0; i < DI; ++i)
+        if (i % S == sub) hrow(0)[i] = x[i];
     // forward: layer j's outputs to LDS and to row j of the workspace
-    paper_train_layer<DI, W>(w, x, col(1), hrow(1));
+    paper_train_layer<DI, W>(w, x, col(1), hrow(1), sub);
     int off = W * DI;
     float v[W];
 #pragma unroll
     for (int j = 2; j <= H; ++j) {
+        wave_lds_sync();
         paper_train_load<W>(col(j - 1), v);
-        paper_train_layer<W, W>(w + off, v, col(j), hrow(j));
+        paper_train_layer<W, W>(w + off, v, col(j), hrow(j), sub);
         off += W * W;
     }
-    paper_train_load<W>(col(H), v);  // h_H
+    wave_lds_sync();
+    paper_train_load<W>(col(H), v);  // h_H (every lane of the query forms z)
     float z = 0.0f;
 #pragma unroll
     for (int k = 0; k < W; ++k) z = fmaf(w[off + k], v[k], z);
@@ -408,19 +424,22 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
         dz = A.grad_y[q] * y * (1.0f - y);
     } else {
         const float t = A.labels[q] ? 1.0f : 0.0f;
-        atomicAdd(A.loss_sum, (y - t) * (y - t));
+        if (sub == 0) atomicAdd(A.loss_sum, (y - t) * (y - t));
         dz = 2.0f * (y - t) * y * (1.0f - y);
     }
-    atomicAdd(A.count, 1u);
-    A.dz[q] = dz;
-    // deltas, layer H down to 1 (v holds the current layer's delta); each
-    // layer's delta replaces the layer's outputs in LDS
+    if (sub == 0) {
+        atomicAdd(A.count, 1u);
+        A.dz[q] = dz;
+    }
+    // deltas, layer H down to 1 (v holds the current layer's delta, whole, in
+    // every lane of the query); each layer's delta replaces the layer's
+    // outputs in LDS
     {
         float* dH = drow(H);
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             v[k] = dz * w[off + k] * leaky_grad(v[k]);
-            dH[k] = v[k];
+            if (k % S == sub) dH[k] = v[k];
         }
     }
 #pragma unroll
@@ -428,14 +447,15 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
         off -= W * W;
         float* c = col(j - 1);
         float* dprev = drow(j - 1);
-        for (int i = 0; i < W; ++i) {
+        for (int i = sub; i < W; i += S) {
             float b = 0.0f;
 #pragma unroll
             for (int k = 0; k < W; ++k) b = fmaf(w[off + k * W + i], v[k], b);
-            const float e = b * leaky_grad(c[i * kTrainBlock]);
-            c[i * kTrainBlock] = e;
+            const float e = b * leaky_grad(c[i * kTrainQ]);
+            c[i * kTrainQ] = e;
             dprev[i] = e;
         }
+        wave_lds_sync();
         paper_train_load<W>(c, v);
     }
     off -= W * DI;
@@ -447,43 +467,44 @@ __global__ __launch_bounds__(kTrainBlock) void paper_train_kernel(PaperTrainArgs
         for (int k = 0; k < W; ++k) b = fmaf(w[off + k * DI + i], v[k], b);
         gx[i] = b;
     }
-    // latent gradients: bilinear corners of the position and direction grids
-    // (and the two samples of the distance grid); the hidden outputs in LDS
-    // are spent, so their space is the scratch of the grouped adds (inner
-    // network: rays from one surface share distance and direction cells)
+    // latent gradients: lane s of a query takes bilinear corner s of the
+    // position and direction grids (lanes 0 and 1 the two samples of the
+    // distance grid); the hidden outputs in LDS are spent, so their space is
+    // the scratch of the grouped adds (inner network: rays from one surface
+    // share distance and direction cells)
+    wave_lds_sync();
     float* gg = A.grid_grad[id];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         float wa, wb;
         const uint32_t a = grid_cell(e ? du[0] : pu[0], R, wa), b = grid_cell(e ? du[1] : pu[1], R, wb);
-        float* base = gg + (size_t)e * R * R * N + ((size_t)a * R + b) * N;
-        const float cw[4] = {(1.0f - wa) * (1.0f - wb), wa * (1.0f - wb), (1.0f - wa) * wb, wa * wb};
-        const int co[4] = {0, R * N, N, R * N + N};
-        float gv[4 * N];
-        int go[4 * N];
+        const float fa = sub & 1 ? wa : 1.0f - wa, fb = sub & 2 ? wb : 1.0f - wb;
+        const float cw = fa * fb;
+        float* dst = gg + (size_t)e * R * R * N + ((size_t)(a + (sub & 1)) * R + b + (sub >> 1)) * N;
+        float gv[N];
+        int go[N];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int f = 0; f < N; ++f) {
-                gv[c * N + f] = cw[c] * gx[e * N + f];
-                go[c * N + f] = co[c] + f;
-            }
-        grouped_atomic_add<NET == 1, 4 * N>(base, go, gv, act);
+        for (int f = 0; f < N; ++f) {
+            gv[f] = cw * gx[e * N + f];
+            go[f] = f;
+        }
+        grouped_atomic_add<NET == 1, N>(dst, go, gv, act);
     }
     if constexpr (NET == 1) {
-        float wr;
-        const uint32_t c = grid_cell(r, kInnerR1, wr);
-        float* base = gg + (size_t)2 * R * R * N + c * kInnerN1;
-        float gv[2 * kInnerN1];
-        int go[2 * kInnerN1];
+        if (sub < 2) {
+            float wr;
+            const uint32_t c = grid_cell(r, kInnerR1, wr);
+            float* dst = gg + (size_t)2 * R * R * N + (c + sub) * kInnerN1;
+            const float cw = sub ? wr : 1.0f - wr;
+            float gv[kInnerN1];
+            int go[kInnerN1];
 #pragma unroll
-        for (int f = 0; f < kInnerN1; ++f) {
-            gv[f] = (1.0f - wr) * gx[2 * N + f];
-            gv[kInnerN1 + f] = wr * gx[2 * N + f];
-            go[f] = f;
-            go[kInnerN1 + f] = kInnerN1 + f;
+            for (int f = 0; f < kInnerN1; ++f) {
+                gv[f] = cw * gx[2 * N + f];
+                go[f] = f;
+            }
+            grouped_atomic_add<true, kInnerN1>(dst, go, gv, act);
         }
-        grouped_atomic_add<true, 2 * kInnerN1>(base, go, gv, act);
     }
 }
 
@@ -647,7 +668,7 @@ hipError_t launch_paper_train(int network, PaperTrainArgs a, void* ws, hipStream
     const int64_t ge = paper_grid_elems_dev(network);
     if (a.n > 0) {
         // one wave per block: a 2^11-query batch spreads over 32 compute units
-        const unsigned blocks = (unsigned)((a.n + kTrainBlock - 1) / kTrainBlock);
+        const unsigned blocks = (unsigned)((a.n + kTrainQ - 1) / kTrainQ);
         if (network == 0)
             hipLaunchKernelGGL(paper_train_kernel<0>, dim3(blocks), dim3(kTrainBlock), 0, s, a);
         else
