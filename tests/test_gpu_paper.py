@@ -269,6 +269,47 @@ def _drop_near_kinks(network, rays, ids, tmax, grids, w, margin=1e-3):
     return ids
 
 
+@pytest.mark.parametrize("network,n", [(0, 1), (0, 23), (0, 1001), (1, 1), (1, 37), (1, 999)])
+def test_paper_training_ragged_batches(network, n):
+    """Loss, MLP gradient and latent gradients of batches that end inside a
+    block of queries and inside a 64-query chunk of the dW sums (and a batch of
+    one query) against the binary64 oracle."""
+    import torch
+    amp = 0.05
+    rays, ids, tmax = workload(n, 61 + n + network)
+    labels = np.random.default_rng(62 + n).integers(0, 2, n).astype(np.uint8)
+    go, gi = oracle_grids(amp)
+    grids, w = (go if network == 0 else gi), weights()[network]
+    if n == 1:  # the first query of this network's class clear of the kinks
+        r, i, t = workload(64, 60 + network)
+        for k in np.nonzero(PN.classify(r, i, t, BOXES)[0] == network + 1)[0]:
+            one = (r[k:k + 1].copy(), i[k:k + 1].copy(), t[k:k + 1].copy())
+            if _drop_near_kinks(network, *one, grids, w)[0] == one[1][0]:
+                rays, ids, tmax = one
+                break
+    ids = _drop_near_kinks(network, rays, ids, tmax, grids, w)
+    pm = make_model(amp)
+    pm.setup_training(network)
+    grad = torch.empty(pm.mlp_params(network), device="cuda")
+    args = [torch.from_numpy(a).cuda() for a in (rays, ids, tmax, labels)]
+    loss = pm.train_step(network, *args, step=1, adam=None, mlp_grad=grad)
+    torch.cuda.synchronize()
+    loss64, B, dW, gg = PN.train_grads(network, rays, ids, tmax, labels, BOXES, grids, w)
+    assert B >= 1
+    assert abs(float(loss.item()) - loss64) <= 1e-5 * loss64 + 1e-12
+    rel, mx = _rel_err(grad.cpu().numpy(), dW)
+    print(f"paper train net {network} n {n}: {B} queries, dW rel {rel:.2e}")
+    assert rel <= 1e-4 and mx <= 1e-3 * np.abs(dW).max()
+    for k in range(BOXES.shape[0]):
+        got = pm.grid_grad(k, network).cpu().numpy()
+        want = np.concatenate([a.ravel() for a in gg[k]])
+        if not want.any():
+            assert np.abs(got).max() <= 1e-6
+            continue
+        rel, mx = _rel_err(got, want)
+        assert rel <= 1e-4 and mx <= 1e-3 * np.abs(want).max()
+
+
 def test_paper_autograd_matches_oracle():
     """PaperVisibility (torch.autograd.Function): y.backward(g) gives, for both
     networks, the MLP gradients and the latent gradients of the binary64
