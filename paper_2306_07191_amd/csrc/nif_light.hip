@@ -19,22 +19,42 @@ struct LightTri {
     float pa;                   // P(triangle) / area
 };
 
-__global__ void light_sample_kernel(const float* __restrict__ tab, const LightTri* __restrict__ tri, int32_t L,
-                                    const float* __restrict__ points, const float* __restrict__ u, int64_t n,
-                                    float* __restrict__ rays, float* __restrict__ tmax, float* __restrict__ pdf,
-                                    int32_t* __restrict__ which) {
+// First entry of tab[0, L) greater than u0 (the last one if none).
+__device__ __forceinline__ int32_t cdf_search(const float* tab, int32_t L, float u0) {
+    int32_t lo = 0, hi = L - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (tab[mid] > u0)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Tables of up to this many entries are searched in LDS (64 KB), each
+// persistent block reading the table once; larger ones in global memory.
+constexpr int32_t kLightLdsEntries = 16384;
+constexpr int kLightBlock = 256, kLightLdsBlocks = 1024;
+
+template <bool LDS>
+__global__ __launch_bounds__(kLightBlock) void light_sample_kernel(
+    const float* __restrict__ tab, const LightTri* __restrict__ tri, int32_t L, const float* __restrict__ points,
+    const float* __restrict__ u, int64_t n, float* __restrict__ rays, float* __restrict__ tmax,
+    float* __restrict__ pdf, int32_t* __restrict__ which) {
 #pragma clang fp contract(off)
+    extern __shared__ float stab[];
+    if constexpr (LDS) {
+        for (int32_t i = threadIdx.x; i < L; i += kLightBlock) stab[i] = tab[i];
+        __syncthreads();
+    }
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const float u0 = u[3 * k], u1 = u[3 * k + 1], u2 = u[3 * k + 2];
-        // first table entry greater than u0 (the last one if none)
-        int32_t lo = 0, hi = L - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (tab[mid] > u0)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
+        int32_t lo;
+        if constexpr (LDS)
+            lo = cdf_search(stab, L, u0);
+        else
+            lo = cdf_search(tab, L, u0);
         const LightTri t = tri[lo];
         const float su = sqrtf(u1), b1 = 1.0f - su, b2 = u2 * su;
         float x[3], v[3];
@@ -162,9 +182,17 @@ hipError_t launch_light_sample(const void* h, const float* points, const float* 
                                float* tmax, float* pdf, int32_t* which, hipStream_t s) {
     const LightTable* lt = reinterpret_cast<const LightTable*>(h);
     if (n <= 0) return hipSuccess;
-    const int64_t b = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
-    hipLaunchKernelGGL(light_sample_kernel, dim3((unsigned)b), dim3(256), 0, s, lt->d_tab, lt->d_tri, lt->L, points, u,
-                       n, rays, tmax, pdf, which);
+    const int64_t need = (n + kLightBlock - 1) / kLightBlock;
+    if (lt->L <= kLightLdsEntries) {
+        const int64_t b = need < kLightLdsBlocks ? need : kLightLdsBlocks;
+        hipLaunchKernelGGL(light_sample_kernel<true>, dim3((unsigned)b), dim3(kLightBlock),
+                           (size_t)lt->L * sizeof(float), s, lt->d_tab, lt->d_tri, lt->L, points, u, n, rays, tmax,
+                           pdf, which);
+    } else {
+        const int64_t b = need < 65536 ? need : 65536;
+        hipLaunchKernelGGL(light_sample_kernel<false>, dim3((unsigned)b), dim3(kLightBlock), 0, s, lt->d_tab,
+                           lt->d_tri, lt->L, points, u, n, rays, tmax, pdf, which);
+    }
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ def _lights(L, g):
     return tris, rad
 
 
-@pytest.mark.parametrize("L,n", [(1, 1000), (300, 100000), (5000, 65537)])
+@pytest.mark.parametrize("L,n", [(1, 1000), (300, 100000), (5000, 65537), (16384, 3000), (20000, 40000)])
 def test_light_sampling_matches_oracle(L, n):
     import torch
     from paper_2306_07191_amd import nif
