@@ -485,30 +485,13 @@ static double gamma32(int K) {
 
 #define U32 (0x1p-24)
 
-/* Sum of the 8 largest values of a[0..K). */
-static double top8_sum(const double* a, int K) {
-    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < K; ++i) {
-        double v = a[i];
-        if (v <= t[7]) continue;
-        int j = 7;
-        while (j > 0 && t[j - 1] < v) { t[j] = t[j - 1]; --j; }
-        t[j] = v;
-    }
-    return t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6] + t[7];
-}
-
-/* Accumulation drift of one K-term dot product on the device.
- *  - binary32 partial sums in any order: gamma_K sum|p| (Higham, Sec. 3.1).
- *  - FP8 matrix-core products are summed in blocks of 8; inside a block every
- *    product is truncated to 13 fraction bits below the block's largest
- *    product (measured on the target device), and the block sums are combined
- *    in binary32.  For any assignment of the K products to blocks the error is
- *    below 7 * 2^-13 * (sum of the 8 largest |p|) + gamma_8 sum|p|. */
-static double acc_drift(int quant, int K, const double* absprod, double mag) {
-    if (quant != 3) return gamma32(K) * mag;
-    return 7.0 * ldexp(1.0, -13) * top8_sum(absprod, K) + gamma32(8) * mag;
-}
+/* Accumulation drift of one K-term dot product on the device: binary32
+ * partial sums in any order, gamma_K sum|p| (Higham, Sec. 3.1).  This is the
+ * model for every dtype; for FP8 operands the matrix core's internal
+ * summation is not specified by a published source, so the FP8 comparison
+ * with this emulation is reported, and the FP8 parity criterion is the
+ * per-query bound against the unquantised binary64 result instead. */
+static double acc_drift(int K, double mag) { return gamma32(K) * mag; }
 
 /* gmax[i] = largest |latent| among the corners of feature i.  A binary32
  * evaluation of the trilinear interpolant is within 16 u gmax of the exact
@@ -556,18 +539,16 @@ static void mlp_forward(const orc_model* m, const double* W, const double* sc, c
         Kl[j] = K;
         for (int o = 0; o < Wd; ++o) {
             double acc = 0.0, err = 0.0, mag = 0.0, prop2 = 0.0;
-            double absprod[ORC_MAXDIN];
             for (int i = 0; i < K; ++i) {
                 double w = Wj[(int64_t)o * K + i];
                 double wq = qweight(w, q, sw);
                 acc += wq * hq[i];
                 err += fabs(wq - w) * (fabs(hq[i]) + eps[i]) + fabs(w) * eps[i];
-                absprod[i] = fabs(wq * hq[i]);
-                mag += absprod[i];
+                mag += fabs(wq * hq[i]);
                 prop2 += (wq * dr[i]) * (wq * dr[i]);
             }
             a[o] = acc;
-            const double local = acc_drift(q, K, absprod, mag) + 1e-300;
+            const double local = acc_drift(K, mag) + 1e-300;
             enew[o] = err + local;
             dnew[o] = local + sqrt(prop2);
         }

@@ -341,11 +341,67 @@ def train_grads(network: int, rays, ids, tmax, labels, aabb, grids, w, grad_y=No
     return loss, B, np.concatenate([d.ravel() for d in dW]), ggrids
 
 
-def features(network: int, rays, ids, tmax, aabb, grids):
+def transform32(rays, ids, tmax, aabb):
+    """transform() with every step in binary32 (numpy float32: the entry point,
+    q = (p - c) / h, the angles and r), for sizing how far a binary32
+    evaluation of the same definitions can move the features."""
+    cls, ta, _ = classify(rays, ids, tmax, aabb)
+    f = np.float32
+    r32 = np.asarray(rays, np.float32)
+    o, d = r32[:, :3], r32[:, 3:]
+    K = aabb.shape[0]
+    box = np.asarray(aabb, np.float32)[np.clip(np.asarray(ids, np.int64), 0, K - 1)]
+    c = (box[:, :3] + box[:, 3:]) * f(0.5)
+    h = (box[:, 3:] - box[:, :3]) * f(0.5)
+    t = np.where(cls == CLS_OUTER, ta, f(0)).astype(np.float32)
+    with np.errstate(invalid="ignore", over="ignore"):
+        p = (o + t[:, None] * d).astype(np.float32)
+        q = np.where(np.isfinite(p), (p - c) / h, f(0)).astype(np.float32)
+
+    def sph32(v):
+        theta = np.arctan2(np.sqrt(v[:, 0] * v[:, 0] + v[:, 1] * v[:, 1]), v[:, 2])
+        phi = np.arctan2(v[:, 1], v[:, 0])
+        return (np.clip(theta / f(math.pi), 0, 1).astype(np.float64),
+                np.clip((phi + f(math.pi)) / f(2 * math.pi), 0, 1).astype(np.float64))
+    pu, pv = sph32(q)
+    du, dv = sph32(np.where(np.isfinite(d), d, f(1)).astype(np.float32))
+    r = np.clip(np.sqrt((q * q).sum(1)) / f(math.sqrt(3.0)), 0, 1).astype(np.float64)
+    return cls, pu, pv, du, dv, r
+
+
+def kink_ambiguous(network: int, rays, ids, tmax, aabb, grids, w, factor: float = 8.0):
+    """Per query of `network`'s class: True when some hidden pre-activation a
+    lies so close to the leaky ReLU's kink that a binary32 evaluation may put
+    it on the other side, so that the query's backward pass (the slope, Sec. 5
+    "Architecture") may differ from the binary64 one.  The margin of unit i of
+    layer j is factor x (|a32 - a64| + g_K sum_k |W_ik h_k|): a32 from the
+    features of transform32, a64 from the binary64 ones, plus the worst-case
+    drift of a K-term binary32 sum (g_K = K 2^-24 / (1 - K 2^-24)).  Queries
+    of other classes are False."""
+    cls, x64 = features(network, rays, ids, tmax, aabb, grids)
+    x32 = features(network, rays, ids, tmax, aabb, grids, coords=transform32(rays, ids, tmax, aabb))[1]
+    s = np.nonzero(cls == (CLS_OUTER if network == 0 else CLS_INNER))[0]
+    mats = split_weights(w, network)
+    out = np.zeros(cls.shape[0], bool)
+    h64, h32 = x64[s], x32[s]
+    near = np.zeros(s.size, bool)
+    for m in mats[:-1]:
+        a64, a32 = h64 @ m.T, h32 @ m.T
+        K = m.shape[1]
+        g = K * 2.0 ** -24 / (1 - K * 2.0 ** -24)
+        margin = factor * (np.abs(a32 - a64) + g * (np.abs(h64) @ np.abs(m).T))
+        near |= (np.abs(a64) <= margin).any(1)
+        h64, h32 = leaky(a64), leaky(a32)
+    out[s] = near
+    return out
+
+
+def features(network: int, rays, ids, tmax, aabb, grids, coords=None):
     """Class per query and the MLP input x (n x din) of `network`; rows of
     other classes are zero.  grids: per object, the binary64 arrays of
-    grid_shapes(network)."""
-    cls, pu, pv, du, dv, r = transform(rays, ids, tmax, aabb)
+    grid_shapes(network).  coords: the output of transform() to use (default:
+    transform() of the queries)."""
+    cls, pu, pv, du, dv, r = transform(rays, ids, tmax, aabb) if coords is None else coords
     want = CLS_OUTER if network == 0 else CLS_INNER
     n = cls.shape[0]
     x = np.zeros((n, din(network)))

@@ -19,14 +19,15 @@ def test_eight_hidden_layers_all_dtypes_and_gradients():
     w["shape"] = sh
     w["mlps"] = (S.xavier_mlp(sh, S.rng(90, 3)) * 1.5).astype(np.float32)[None]
     ctx, model = make_pair(w, grid_amp=0.5)
+    exact = model.forward(w["rays"], w["ids"], w["tmax"])
     for dtype in ("f32", "bf16", "f16"):
-        ref = model.with_(quant="exact" if dtype == "f32" else dtype).forward(w["rays"], w["ids"], w["tmax"])
-        check_outputs(*run_query(ctx, w, dtype), ref, dtype, f"hidden 8 {dtype}")
+        ref = exact if dtype == "f32" else model.with_(quant=dtype).forward(w["rays"], w["ids"], w["tmax"])
+        check_outputs(*run_query(ctx, w, dtype), ref, dtype, f"hidden 8 {dtype}", exact=exact)
     sc = fp8_scales_from_oracle(model, w)
     for m in range(sc.shape[0]):
         ctx.set_fp8_scales(m, sc[m])
     ref = model.with_(quant="fp8", fp8_scales=sc).forward(w["rays"], w["ids"], w["tmax"])
-    check_outputs(*run_query(ctx, w, "fp8"), ref, "fp8", "hidden 8 fp8")
+    check_outputs(*run_query(ctx, w, "fp8"), ref, "fp8", "hidden 8 fp8", exact=exact)
     # training gradients through all eight layers
     labels = O.BVH(w["tris"]).anyhit(w["rays"], w["tmax"])
     ctx.prepare("f32")

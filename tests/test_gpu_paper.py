@@ -188,22 +188,14 @@ def test_paper_training_matches_oracle(network):
     amp = 0.05
     go, gi = oracle_grids(amp)
     w = weights()[network]
-    # A pre-activation within the binary32 error of the features (about 1e-4 of
-    # the layer's largest) may sit on the other side of the leaky ReLU's kink on
-    # the GPU, which changes that query's backward pass: such queries are left
-    # out of the batch (given an invalid object id) so that both sides take the
-    # same branch.  The ones kept are at least 1e-3 of the largest away from 0
-    # (ten times the measured feature error).
-    cls, x = PN.features(network, rays, ids, tmax, BOXES, go if network == 0 else gi)
-    s = np.nonzero(cls == network + 1)[0]
-    h, near = x[s], np.zeros(s.size, bool)
-    for m in PN.split_weights(w, network)[:-1]:
-        a = h @ m.T
-        near |= (np.abs(a) < 1e-3 * np.abs(a).max()).any(1)
-        h = PN.leaky(a)
-    ids = ids.copy()
-    ids[s[near]] = BOXES.shape[0] + 2
-    assert near.mean() < 0.6
+    # A query with a hidden pre-activation within reach of binary32 rounding of
+    # the leaky ReLU's kink may take the other slope on the GPU, which changes
+    # its backward pass; the oracle sizes that reach per query and unit (binary32
+    # vs binary64 features, plus the binary32 summation drift) and such queries
+    # are left out of the batch (given an invalid object id).
+    ids, frac = _drop_near_kinks(network, rays, ids, tmax, go if network == 0 else gi, w)
+    print(f"paper train net {network}: {100 * frac:.2f} % of the batch near a kink, left out")
+    assert frac <= 0.05
     pm = make_model(amp)
     master = pm.setup_training(network)
     P = pm.mlp_params(network)
@@ -254,19 +246,15 @@ def test_paper_training_matches_oracle(network):
     assert np.isfinite(y[PN.classify(rays, ids, tmax, BOXES)[0] > 0]).all()
 
 
-def _drop_near_kinks(network, rays, ids, tmax, grids, w, margin=1e-3):
-    """ids with the queries of `network` whose pre-activations lie within
-    margin x the layer's largest of zero made invalid (see the training test)."""
-    cls, x = PN.features(network, rays, ids, tmax, BOXES, grids)
-    s = np.nonzero(cls == network + 1)[0]
-    h, near = x[s], np.zeros(s.size, bool)
-    for m in PN.split_weights(w, network)[:-1]:
-        a = h @ m.T
-        near |= (np.abs(a) < margin * np.abs(a).max()).any(1)
-        h = PN.leaky(a)
+def _drop_near_kinks(network, rays, ids, tmax, grids, w):
+    """ids with the queries of `network` that the oracle finds near a leaky-ReLU
+    kink (PN.kink_ambiguous) made invalid, and the fraction of the network's
+    queries so left out."""
+    amb = PN.kink_ambiguous(network, rays, ids, tmax, BOXES, grids, w)
+    cls = PN.classify(rays, ids, tmax, BOXES)[0]
     ids = ids.copy()
-    ids[s[near]] = BOXES.shape[0] + 2
-    return ids
+    ids[amb] = BOXES.shape[0] + 2
+    return ids, float(amb.sum() / max(1, (cls == network + 1).sum()))
 
 
 @pytest.mark.parametrize("network,n", [(0, 1), (0, 23), (0, 1001), (1, 1), (1, 37), (1, 999)])
@@ -284,10 +272,11 @@ def test_paper_training_ragged_batches(network, n):
         r, i, t = workload(64, 60 + network)
         for k in np.nonzero(PN.classify(r, i, t, BOXES)[0] == network + 1)[0]:
             one = (r[k:k + 1].copy(), i[k:k + 1].copy(), t[k:k + 1].copy())
-            if _drop_near_kinks(network, *one, grids, w)[0] == one[1][0]:
+            if _drop_near_kinks(network, *one, grids, w)[0][0] == one[1][0]:
                 rays, ids, tmax = one
                 break
-    ids = _drop_near_kinks(network, rays, ids, tmax, grids, w)
+    ids, frac = _drop_near_kinks(network, rays, ids, tmax, grids, w)
+    assert frac <= 0.05 or n < 100
     pm = make_model(amp)
     pm.setup_training(network)
     grad = torch.empty(pm.mlp_params(network), device="cuda")
@@ -320,8 +309,9 @@ def test_paper_autograd_matches_oracle():
     rays, ids, tmax = workload(3000, 51)
     go, gi = oracle_grids(amp)
     w0, w1 = weights()
-    ids = _drop_near_kinks(0, rays, ids, tmax, go, w0)
-    ids = _drop_near_kinks(1, rays, ids, tmax, gi, w1)
+    ids, f0 = _drop_near_kinks(0, rays, ids, tmax, go, w0)
+    ids, f1 = _drop_near_kinks(1, rays, ids, tmax, gi, w1)
+    assert f0 <= 0.05 and f1 <= 0.05
     pm = make_model(amp)
     wo, wi = pm.setup_training(0), pm.setup_training(1)
     wo.requires_grad_(True)

@@ -10,14 +10,6 @@ from gpu_util import GRID_SEED, check_outputs, fp8_scales_from_oracle, make_pair
 pytestmark = pytest.mark.gpu
 
 
-def _lowp_vs_exact(y, ref_q, ref_exact):
-    """Reduced precision vs the unquantised binary64 result: within the per-query bound."""
-    hit = ref_exact["status"] == 1
-    dy = np.abs(y[hit] - ref_exact["y"][hit])
-    assert (dy <= ref_q["ybound"][hit]).all()
-    return float(dy.max(initial=0)), float(np.percentile(dy, 99.9))
-
-
 def test_init_grid_bit_exact():
     import torch
     for sh in (S.TINY, S.FRAME):
@@ -55,8 +47,7 @@ def test_query_lowp_tiny(dtype, amp):
     ref_x = model.forward(w["rays"], w["ids"], w["tmax"])
     ref_q = model.with_(quant=dtype).forward(w["rays"], w["ids"], w["tmax"])
     y, z = run_query(ctx, w, dtype)
-    st = check_outputs(y, z, ref_q, dtype, f"tiny {dtype} amp={amp}")
-    st["vs_exact_max_dy"], st["vs_exact_p999_dy"] = _lowp_vs_exact(y, ref_q, ref_x)
+    st = check_outputs(y, z, ref_q, dtype, f"tiny {dtype} amp={amp}", exact=ref_x)
     print(dtype, "tiny", amp, st)
 
 
@@ -69,8 +60,7 @@ def test_query_fp8_tiny(amp):
     ref_q = model_q.forward(w["rays"], w["ids"], w["tmax"])
     ref_x = model.forward(w["rays"], w["ids"], w["tmax"])
     y, z = run_query(ctx, w, "fp8")
-    st = check_outputs(y, z, ref_q, "fp8", f"tiny fp8 amp={amp}")
-    st["vs_exact_max_dy"], st["vs_exact_p999_dy"] = _lowp_vs_exact(y, ref_q, ref_x)
+    st = check_outputs(y, z, ref_q, "fp8", f"tiny fp8 amp={amp}", exact=ref_x)
     print("fp8 tiny", amp, st)
 
 
@@ -169,12 +159,85 @@ def test_query_frame_full_size_sampled(amp):
     scales = fp8_scales_from_oracle(model, dict(w, rays=rays, ids=ids, tmax=tmax))
     for m in range(1):
         ctx.set_fp8_scales(m, scales[m])
+    exact = model.forward(rays, ids, tmax)
     for dtype in ("f32", "bf16", "f16", "fp8"):
         mq = model.with_(quant="exact" if dtype == "f32" else dtype, fp8_scales=scales if dtype == "fp8" else None)
-        ref = mq.forward(rays, ids, tmax)
+        ref = exact if dtype == "f32" else mq.forward(rays, ids, tmax)
         y, z = run_query(ctx, w, dtype, sel=sel)
-        st = check_outputs(y, z, ref, dtype, f"frame {dtype} amp={amp}")
+        st = check_outputs(y, z, ref, dtype, f"frame {dtype} amp={amp}", exact=exact)
         print("frame", dtype, amp, st)
+    del ctx
+    torch.cuda.empty_cache()
+
+
+def _binary64_case(name):
+    """(workload, sampled query indices or None): all 16,384 tiny queries, or
+    3,000 frame queries plus the last 40 (the frame's 2.1 GB grid is regenerated
+    lazily by the oracle)."""
+    if name == "tiny":
+        return S.tiny_workload(), None
+    w = S.frame_workload(with_mesh=False)
+    sel = np.sort(np.random.default_rng(1).choice(w["ids"].shape[0], 3000, replace=False))
+    return w, np.concatenate([sel, np.arange(w["ids"].shape[0] - 40, w["ids"].shape[0])])
+
+
+def _sub(w, sel):
+    return (w["rays"], w["ids"], w["tmax"]) if sel is None else (w["rays"][sel], w["ids"][sel], w["tmax"][sel])
+
+
+@pytest.mark.parametrize("name", ["tiny", "frame"])
+def test_query_f32_vs_binary64_at_init(name):
+    """The binary32 path against the binary64 oracle with clip, normalisation
+    and cell coordinates in binary64 too (no step in binary32), at the paper's
+    initialisation (latents U(-1e-4, 1e-4), Sec. 5 "Initialization"): every
+    query within 1e-5 relative of y64, the stated tolerance of the binary32
+    path."""
+    import torch
+    w, sel = _binary64_case(name)
+    ctx, _ = make_pair(w, grid_amp=1e-4)
+    m64 = O.Model(w["shape"], w["aabb"], w["mlps"], mlp_index=w["mlp_index"], grid_seed=GRID_SEED, grid_amp=1e-4,
+                  coord_mode=1)
+    ref = m64.forward(*_sub(w, sel))
+    y, z = run_query(ctx, w, "f32", sel=sel)
+    hit = ref["status"] == 1
+    assert hit.sum() > 0.5 * hit.size
+    assert (y[~hit] == 1.0).all() and np.isfinite(y[hit]).all()
+    rel = np.abs(y[hit] - ref["y"][hit]) / ref["y"][hit]
+    print(f"{name}: {hit.sum()} queries, f32 vs binary64 max rel {rel.max():.3e}, p99.9 {np.percentile(rel, 99.9):.3e}")
+    assert (rel <= 1e-5).all(), rel.max()
+    del ctx
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["tiny", "frame"])
+@pytest.mark.parametrize("amp", [0.5, 1.0])
+def test_error_split_vs_binary64(name, amp):
+    """Latents U(-amp, amp), where the logits span a useful range: the error of
+    every dtype against the binary64 oracle (binary64 coordinates), next to the
+    part a correct binary32 clip and cell-coordinate step contributes by itself
+    (the oracle run with those steps in binary32).  The binary32 path is no
+    further from binary64 than that part plus the stated 1e-5 relative."""
+    import torch
+    w, sel = _binary64_case(name)
+    ctx, model = make_pair(w, grid_amp=amp)
+    q = _sub(w, sel)
+    m64 = model.with_(coord_mode=1)
+    ref64 = m64.forward(*q)
+    ref32c = model.forward(*q)  # binary32 clip and cell coordinates, binary64 otherwise
+    hit = (ref64["status"] == 1) & (ref32c["status"] == 1)
+    split = np.abs(ref32c["y"][hit] - ref64["y"][hit])
+    scales = fp8_scales_from_oracle(model, dict(w, rays=q[0], ids=q[1], tmax=q[2]))
+    ctx.set_fp8_scales(0, scales[0])
+    rows = {"binary32 coordinates (oracle)": split}
+    for dtype in ("f32", "f16", "bf16", "fp8"):
+        y, _ = run_query(ctx, w, dtype, sel=sel)
+        dy = np.abs(y[hit] - ref64["y"][hit])
+        rows[dtype] = dy
+        if dtype == "f32":
+            assert (dy <= split + 1e-5 * ref64["y"][hit]).all(), (dy - split).max()
+    for k, v in rows.items():
+        print(f"{name} amp={amp} {k:>30}: |y - y64| max {v.max():.3e}, p99.9 {np.percentile(v, 99.9):.3e}, "
+              f"median {np.median(v):.3e}")
     del ctx
     torch.cuda.empty_cache()
 
@@ -210,7 +273,8 @@ def test_ordering_is_transparent(dtype):
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     ref = model.forward(rays, ids, tmax)
-    check_outputs(outs[1][0], outs[1][1], ref, dtype, f"ordered {dtype}")
+    exact = model.with_(quant="exact").forward(rays, ids, tmax) if dtype != "f32" else None
+    check_outputs(outs[1][0], outs[1][1], ref, dtype, f"ordered {dtype}", exact=exact)
 
 
 def test_order_is_a_grouped_permutation():

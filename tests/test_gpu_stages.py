@@ -149,3 +149,57 @@ def test_16bit_stages_match_fused_query(fmt, shape_name):
     np.testing.assert_array_equal(z.cpu().numpy()[hit], zq.cpu().numpy()[hit])
     with pytest.raises(nif.NifError):
         ctx.mlp16(f16, "f32")
+
+
+def _hand_cases(q, fp8: bool):
+    """(hidden, {(layer, row, col): weight}, w_out[0], x[0], scales or None, expected z):
+    the hand-computed nets of the oracle's rounding-position pins, embedded in
+    unit 0 of a 64-wide MLP whose other weights are zero."""
+    e = 0.75 * q
+    s2 = [1.0] * 4 if fp8 else None
+    s1 = [1.0] * 2 if fp8 else None
+    cases = [
+        (2, {(0, 0, 0): 1.0, (1, 0, 0): 1.0}, 1.0, 1 + e, s2, 1 + q),            # input rounded
+        (2, {(0, 0, 0): 1 + e, (1, 0, 0): 1.0}, 1.0, 1.0, s2, 1 + q),            # W1 rounded
+        (2, {(0, 0, 0): 1.0, (1, 0, 0): 1 + e}, 1.0, 1.0, s2, 1 + q),            # W2 rounded
+        (2, {(0, 0, 0): 1 + q, (1, 0, 0): 1 + q}, 1.0, 1 + q, s2, 1 + 3 * q + 2 * q * q),  # h1 rounded, h2 not
+        (2, {(0, 0, 0): 1.0, (1, 0, 0): 1.0}, 1 + e, 1.0, s2, 1 + e),            # w_out binary32
+        (1, {(0, 0, 0): 1 + q}, 1.0, 1 + q, s1, 1 + 2 * q + q * q),               # last activation not rounded
+    ]
+    if fp8:
+        cases += [
+            (1, {(0, 0, 0): 1.0}, 1.0, 1.0, [1.0, 0.75], 1.03125),                # s_x: 0.75 E4M3(1 / 0.75)
+            (1, {(0, 0, 0): 1.0}, 1.0, 1.0, [0.75, 1.0], 1.03125),                # s_W
+            (2, {(0, 0, 0): 1.0, (1, 0, 0): 1.0}, 1.0, 1.0, [1.0, 1.0, 1.0, 0.75], 1.03125),
+            (1, {(0, 0, 0): 1.0}, 1.0, 500.0, [1.0, 1.0], 448.0),                # saturation
+        ]
+    return cases
+
+
+@pytest.mark.parametrize("dtype,q", [("bf16", 2.0 ** -7), ("f16", 2.0 ** -10), ("fp8", 2.0 ** -3)])
+def test_rounding_positions_hand_computed(dtype, q):
+    """The reduced-precision MLP rounds its input, its hidden weights and every
+    hidden activation except the last, and keeps the output layer in binary32:
+    the hand-computed logits of the oracle's pins, bit for bit (every product
+    and sum here is exact in binary32)."""
+    import torch
+    from paper_2306_07191_amd import nif
+    for hidden, wts, wout, x0, scales, want in _hand_cases(q, dtype == "fp8"):
+        sh = S.ModelShape(levels=4, res_min=4, res_max=32, feats=2, hidden=hidden, width=64, grid_dtype="f32")
+        W = np.zeros(sh.mlp_params, np.float32)
+        offs = [0, sh.width * sh.din]
+        for (layer, r, c), v in wts.items():
+            k = sh.din if layer == 0 else sh.width
+            W[offs[layer] + r * k + c] = v
+        W[sh.mlp_params - sh.width] = wout
+        ctx = nif.Context(sh)
+        ctx.set_mlp(0, torch.from_numpy(W).cuda())
+        ctx.set_object(0, np.array([0, 0, 0, 1, 1, 1], np.float32), ctx.alloc_grid(), 0)
+        if scales is not None:
+            ctx.set_fp8_scales(0, np.asarray(scales, np.float32))
+        ctx.prepare(dtype)
+        x = np.zeros((33, sh.din), np.float32)
+        x[:, 0] = x0
+        z = ctx.mlp(torch.from_numpy(x).cuda(), dtype=dtype).cpu().numpy().astype(np.float64)
+        assert (z == want).all(), (dtype, hidden, wts, wout, x0, scales, z[0], want)
+        ctx.close()

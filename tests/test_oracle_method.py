@@ -352,6 +352,63 @@ def test_fp8_calibration_zero_weights_and_no_queries():
     assert (s == 1.0).all()
 
 
+def _round_net(H, mats, wout, quant, scales=None):
+    """A width-2 net with din = 3 (levels 1, feats 1), weights given row-major."""
+    sh = S.ModelShape(levels=1, res_min=2, res_max=2, feats=1, hidden=H, width=2, grid_dtype="f32")
+    w = np.concatenate([np.ravel(m) for m in mats] + [np.ravel(wout)]).astype(np.float32)
+    assert w.size == sh.mlp_params
+    sc = None if scales is None else np.asarray(scales, np.float64)[None, :]
+    return O.Model(sh, UNIT_BOX, w[None, :], quant=quant, fp8_scales=sc)
+
+
+@pytest.mark.parametrize("quant,q", [("bf16", 2.0 ** -7), ("f16", 2.0 ** -10), ("fp8", 2.0 ** -3)])
+def test_rounding_positions_hand_computed(quant, q):
+    """Where the reduced-precision forms round: the MLP input, every hidden
+    weight matrix, every hidden activation except the last, and nothing in
+    the binary32 output layer.  q is the spacing of the format on [1, 2)
+    (7, 10 and 3 fraction bits); 1 + 3q/4 rounds to 1 + q (nearest), and
+    1 + 2q + q^2 to 1 + 2q (q^2 < q/2).  Each net below routes one value
+    through unit 0 and has all other weights zero, and its expected logit is
+    worked out by hand; moving any one rounding changes that logit (noted per
+    case).  FP8 uses unit scales here, so its codes are the E4M3 values."""
+    e = 0.75 * q
+    sc2 = [1.0] * 4 if quant == "fp8" else None
+    sc1 = [1.0] * 2 if quant == "fp8" else None
+    I3 = [[1, 0, 0], [0, 0, 0]]
+    I2 = [[1, 0], [0, 0]]
+    one = np.array([[1.0, 0, 0]])
+    # input rounded: x = 1 + 3q/4 -> 1 + q (unrounded input would give 1 + 3q/4)
+    assert _round_net(2, [I3, I2], [1, 0], quant, sc2).mlp_only(np.array([[1 + e, 0, 0]]))[0] == 1 + q
+    # first-layer weight rounded (else 1 + 3q/4)
+    assert _round_net(2, [[[1 + e, 0, 0], [0, 0, 0]], I2], [1, 0], quant, sc2).mlp_only(one)[0] == 1 + q
+    # hidden-layer weight rounded (else 1 + 3q/4)
+    assert _round_net(2, [I3, [[1 + e, 0], [0, 0]]], [1, 0], quant, sc2).mlp_only(one)[0] == 1 + q
+    # h_1 = (1+q)^2 = 1 + 2q + q^2 rounded to 1 + 2q (else the q^2 term stays); the last
+    # activation a_2 = (1+q)(1+2q) = 1 + 3q + 2q^2 is not rounded (else 1 + 3q)
+    d = _round_net(2, [[[1 + q, 0, 0], [0, 0, 0]], [[1 + q, 0], [0, 0]]], [1, 0], quant, sc2)
+    assert d.mlp_only(np.array([[1 + q, 0, 0]]))[0] == 1 + 3 * q + 2 * q * q
+    # binary32 output weight, not rounded (else 1 + q)
+    assert _round_net(2, [I3, I2], [1 + e, 0], quant, sc2).mlp_only(one)[0] == 1 + e
+    # one hidden layer: h_1 is the last activation, not rounded (else 1 + 2q)
+    g = _round_net(1, [[[1 + q, 0, 0], [0, 0, 0]]], [1, 0], quant, sc1)
+    assert g.mlp_only(np.array([[1 + q, 0, 0]]))[0] == 1 + 2 * q + q * q
+
+
+def test_fp8_scales_hand_computed():
+    """FP8 per-layer scales: a layer input h becomes s_x E4M3(h / s_x) and a weight
+    s_W E4M3(w / s_W).  With s = 0.75, 1 / 0.75 = 1.333.. lies between the E4M3
+    values 1.25 and 1.375 and rounds to 1.375, so 1 -> 0.75 * 1.375 = 1.03125
+    (an unscaled rounding would keep 1).  E4M3 has no infinity: 500 saturates
+    to 448."""
+    I3 = [[1, 0, 0], [0, 0, 0]]
+    I2 = [[1, 0], [0, 0]]
+    one = np.array([[1.0, 0, 0]])
+    assert _round_net(1, [I3], [1, 0], "fp8", [1.0, 0.75]).mlp_only(one)[0] == 1.03125   # s_x of layer 1
+    assert _round_net(1, [I3], [1, 0], "fp8", [0.75, 1.0]).mlp_only(one)[0] == 1.03125   # s_W of layer 1
+    assert _round_net(2, [I3, I2], [1, 0], "fp8", [1.0, 1.0, 1.0, 0.75]).mlp_only(one)[0] == 1.03125  # s_x, layer 2
+    assert _round_net(1, [I3], [1, 0], "fp8", [1.0, 1.0]).mlp_only(np.array([[500.0, 0, 0]]))[0] == 448.0
+
+
 @pytest.mark.parametrize("q", ["bf16", "f16"])
 def test_quantised_within_bound(q):
     w = S.tiny_workload(n_rays=3000)
