@@ -24,10 +24,12 @@
  *  - Per-query domain errors never fail a call: a non-finite origin or
  *    direction, a zero direction, t_max NaN or negative, or an object id
  *    outside [0, num_objects) give visibility = NaN.
- *  - The context owns host metadata and two small device tables (objects,
- *    packed weights), allocated by nif_prepare and freed by nif_destroy.
- *    Grids, master weights, gradients, optimiser state, inputs, outputs and
- *    workspaces are the caller's.  No C++ exception crosses this interface.
+ *  - The context owns host metadata and small device tables that it
+ *    allocates itself (object table, packed weights per dtype, FP8 scales, the
+ *    error word, box groups, training pointer tables and the binary32 weight
+ *    images of the MLP being trained: kilobytes per object or MLP).  Grids,
+ *    query images, master weights, gradients, optimiser state, inputs, outputs
+ *    and workspaces are the caller's.  No C++ exception crosses this interface.
  */
 #ifndef NIF_H
 #define NIF_H
@@ -55,8 +57,11 @@ typedef enum { NIF_F32 = 0, NIF_F16 = 1, NIF_BF16 = 2, NIF_FP8_E4M3 = 3 } nif_dt
  * N_l = round(res_min * (res_max/res_min)^(l/(levels-1))) cells per axis and
  * (N_l+1)^3 vertices of `feats` latents, stored as grid_dtype (NIF_F32 or
  * NIF_F16; the paper keeps latents in half, Sec. 5 "Memory Footprint").
- * MLP: input 3*levels*feats, `hidden_layers` ReLU layers of `width`, one
- * sigmoid output, no biases (Sec. 5 "Architecture").
+ * MLP: input 3*levels*feats, `hidden_layers` hidden layers of `width`, one
+ * sigmoid output (Sec. 5 "Architecture").  The hidden activation is ReLU and
+ * there are no biases: both are this library's choices for this network
+ * family (the paper uses leaky ReLU, see nif_paper_*, and does not mention
+ * biases).
  * Supported by the kernels: feats = 2, width = 64, levels in {4, 8},
  * 1 <= hidden_layers <= 8, res_max <= 1024. */
 typedef struct {
@@ -108,7 +113,8 @@ nif_status nif_set_fp8_scales(nif_ctx* ctx, int32_t mlp, const float* scales);
  *   pair_ray (source ray index).  *pair_count (dev, int64) receives the number
  *   of pairs, also when it exceeds max_pairs (then only the first max_pairs
  *   are written: call again with more room).  Invalid rays (non-finite,
- *   zero direction, t_max NaN or negative) have no pairs.  n_rays <= 2^24.  Needs
+ *   zero direction, t_max NaN or negative) have no pairs.  n_rays <= 2^24 and
+ *   n_rays x num_objects < 2^32 (else NIF_ERR_UNSUPPORTED).  Needs
  *   nif_prepare; ws: nif_pairs_workspace_bytes(ctx, n_rays) bytes (dev).
  * nif_combine_pairs: ray_visible (dev, n_rays bytes) = 0 iff some pair p of
  *   the ray (pair_ray[p], dev) has visibility[p] < 0.5 (dev), else 1. */
@@ -128,8 +134,9 @@ nif_status nif_combine_pairs(nif_ctx* ctx, const uint32_t* pair_ray, const float
 enum { NIF_FLAG_INVALID_RAY = 1, NIF_FLAG_BAD_OBJECT = 2 };
 nif_status nif_get_error_flags(nif_ctx* ctx, uint32_t* flags, int32_t clear, void* stream);
 
-/* FP8 calibration of MLP `mlp` (per-layer scaling for the E4M3 path; the
- * paper runs its networks in reduced precision, Sec. 4.2 and Sec. 5): runs the
+/* FP8 calibration of MLP `mlp` (per-layer scaling for the E4M3 path, a
+ * precision option of this library beyond the paper's binary32 and 16-bit
+ * weights, Sec. 5): runs the
  * binary32 encoding and layers 1..H-1 over the n queries (dev arrays as
  * nif_query) whose object uses `mlp` and whose segment meets the AABB, and
  * sets s_W[j] = max|W_j| / 448 and s_x[j] = max |input of layer j| / 448
@@ -158,18 +165,30 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * cache lines and waves use one MLP: 0 never, 1 always, 2 (default) when
  * n >= 65536.  Changes nif_workspace_bytes (the ordering workspace plus the
  * queries as 32-byte records, see nif_order_packed).
- * NIF_OPT_GRID_IMAGE (binary16 grids only): 1 (default for binary16 grids) =
- * nif_prepare also builds, for every object, a context-owned query image of
- * its grid in which the four latent pairs of a cell face (x..x+1, y..y+1) are
- * one 16-byte span, halving the gathers of a lookup; it costs twice the grid's
- * memory per object and is rebuilt by every nif_prepare.  2 = a z-y-pair
- * image in which the eight corners of a cell are one 32-byte span (one cache
- * line for most cells), four times the grid's memory.  Outputs are
- * bit-identical in every mode.  0 = gather from the grids (and, when
- * ordering, also sort each 4,096-query window by an 8-bit-per-axis Morton
- * key, which pays off only without an image). */
+ * NIF_OPT_GRID_IMAGE (binary16 grids only): 0 (default) = gather from the
+ * grids (and, when ordering, also sort each 4,096-query window by an
+ * 8-bit-per-axis Morton key, which pays off only without an image).  1 =
+ * queries gather from a query image of each object's grid in which the four
+ * latent pairs of a cell face (x..x+1, y..y+1) are one 16-byte span, halving
+ * the gathers of a lookup (twice the grid's memory); 2 = a z-y-pair image in
+ * which the eight corners of a cell are one 32-byte span (one cache line for
+ * most cells; four times the grid's memory).  The image buffers are the
+ * caller's: nif_image_bytes gives the size of one object's image for the
+ * current mode, nif_set_image registers one per object, and nif_prepare
+ * (re)builds them from the grids.  Changing the mode forgets the registered
+ * buffers.  Outputs are bit-identical in every mode. */
 enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2 };
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
+
+/* Query images (NIF_OPT_GRID_IMAGE 1 or 2): nif_image_bytes is the size in
+ * bytes of one object's image for the current mode (0 when the mode is 0).
+ * nif_set_image registers object obj's image buffer (dev, caller-owned,
+ * 256-byte aligned, at least nif_image_bytes bytes, else NIF_ERR_WORKSPACE;
+ * NIF_ERR_STATE when the mode is 0).  nif_prepare fails with NIF_ERR_STATE
+ * while an object has no image.  The buffer must stay allocated while the
+ * context (or a plan of it) may launch a query. */
+size_t nif_image_bytes(const nif_ctx* ctx);
+nif_status nif_set_image(nif_ctx* ctx, int32_t obj, void* image, size_t bytes);
 
 /* Workspace bytes needed by nif_query (mode 0), nif_train_step (mode 1) or
  * nif_calibrate_fp8 (mode 2) for n queries. */
@@ -229,9 +248,14 @@ nif_status nif_query_packed(nif_ctx* ctx, int32_t dtype, const float* packed, co
  *   Then captures the ordering and query kernels into a HIP graph.  Writes the
  *   outputs while tuning; synchronises `stream`.  ws: at least
  *   nif_plan_workspace_bytes(ctx, n) bytes (dev), kept by the plan.  Needs
- *   nif_prepare(ctx, dtype); later nif_prepare calls (new weights) are seen by
- *   the plan, nif_set_object calls are not.
+ *   nif_prepare(ctx, dtype); later nif_prepare calls (new weights, new latents)
+ *   are seen by the plan.
  * nif_plan_launch: replays the graph on `stream` (same outputs as nif_query).
+ *   Refused with NIF_ERR_STATE, before anything is enqueued, when the context
+ *   changed in a way the captured graph cannot follow (nif_set_object,
+ *   nif_set_image or a NIF_OPT_GRID_IMAGE change since the capture: create a
+ *   new plan) or is not prepared for the plan's dtype (a training step or
+ *   nif_set_mlp since the last nif_prepare: call nif_prepare again).
  * nif_plan_tuning: the chosen schedule as JSON (host buffer buf of buf_bytes).
  * nif_plan_destroy: frees the plan (not the caller's buffers). */
 typedef struct nif_plan nif_plan;

@@ -72,11 +72,14 @@ struct nif_ctx {
     bool train_tab_dirty = true;
     uint8_t* d_train_fwd = nullptr;  // binary32 forward image of the MLP being trained
     float* d_train_bwd = nullptr;    // backward image
-    // y-pair query images of binary16 grids (NIF_OPT_GRID_IMAGE)
+    // query images of binary16 grids (NIF_OPT_GRID_IMAGE), caller-owned buffers
     int32_t image_mode = 0;
     int64_t ioff[3 * kMaxLevels + 1];
-    std::vector<void*> images;  // per object, built by nif_prepare
+    std::vector<void*> images;  // per object, registered by nif_set_image, built by nif_prepare
     bool images_ready = false;
+    // bumped by every change that a captured plan cannot follow (image mode,
+    // object table, option changes); a plan refuses to launch once it differs
+    uint64_t epoch = 1;
     uint32_t* d_flags = nullptr;  // domain-error bits of queries (nif_get_error_flags)
     BoxGroup* d_groups = nullptr;  // box groups for the pair expansion (16..64 objects)
     int32_t num_groups = 0;
@@ -133,11 +136,17 @@ static std::vector<BoxGroup> build_groups(const std::vector<ObjDev>& od) {
     return g;
 }
 
-static void free_images(nif_ctx* c) {
-    for (auto& p : c->images)
-        if (p) (void)hipFree(p);
-    c->images.clear();
+static void drop_images(nif_ctx* c) {
+    c->images.assign(c->K, nullptr);
     c->images_ready = false;
+}
+
+// Elements of one object's query image for image kind `mode` (0: none).
+static int64_t image_elems(const nif_ctx* c, int32_t mode) {
+    if (mode == 0) return 0;
+    int64_t o = 0;
+    for (int k = 0; k < 3 * c->d.levels; ++k) o += image_table_elems(c->res[k % c->d.levels], mode);
+    return o;
 }
 
 static bool uses_order(const nif_ctx* c, int64_t n) {
@@ -194,7 +203,8 @@ extern "C" nif_status nif_create(const nif_model_desc* desc, int32_t num_objects
     c->toff[3 * d.levels] = o;
     c->grid_elems = o;
     c->P = (int64_t)d.width * c->din + (int64_t)(d.hidden_layers - 1) * d.width * d.width + d.width;
-    c->image_mode = d.grid_dtype == NIF_F16 ? 1 : 0;
+    c->image_mode = 0;
+    c->images.assign(num_objects, nullptr);
     c->objs.resize(num_objects);
     c->masters.assign(num_mlps, nullptr);
     c->fp8.resize(num_mlps);
@@ -219,7 +229,6 @@ extern "C" void nif_destroy(nif_ctx* c) {
     if (c->d_train_tab) (void)hipFree(c->d_train_tab);
     if (c->d_train_fwd) (void)hipFree(c->d_train_fwd);
     if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
-    free_images(c);
     if (c->d_flags) (void)hipFree(c->d_flags);
     if (c->d_groups) (void)hipFree(c->d_groups);
     delete c;
@@ -253,6 +262,7 @@ extern "C" nif_status nif_set_object(nif_ctx* c, int32_t obj, const float* aabb,
     o.mlp = mlp_index;
     o.set = true;
     invalidate(c);
+    ++c->epoch;
     return ok();
 }
 
@@ -294,13 +304,18 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         if (!c->masters[m]) return fail(NIF_ERR_STATE, "MLP %d not registered", m);
         if (dtype == NIF_FP8_E4M3 && c->fp8[m].empty()) return fail(NIF_ERR_STATE, "MLP %d has no FP8 scales", m);
     }
+    if (c->image_mode)
+        for (int k = 0; k < c->K; ++k)
+            if (!c->images[k])
+                return fail(NIF_ERR_STATE, "object %d has no query image buffer (nif_image_bytes, nif_set_image)", k);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     if (!c->d_flags) {
         HIP_TRY(hipMalloc(&c->d_flags, 256));
         HIP_TRY(launch_fill_u32(c->d_flags, 1, 0u, s));
     }
-    // query images of the grids (rebuilt on every call: the grids may have changed)
+    // query images of the grids, in the caller's buffers (rebuilt on every
+    // call: the grids may have changed)
     if (c->image_mode) {
         int64_t o = 0;
         for (int k = 0; k < 3 * c->d.levels; ++k) {
@@ -308,12 +323,9 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
             o += image_table_elems(c->res[k % c->d.levels], c->image_mode);
         }
         c->ioff[3 * c->d.levels] = o;
-        if (c->images.size() != (size_t)c->K) c->images.assign(c->K, nullptr);
-        for (int k = 0; k < c->K; ++k) {
-            if (!c->images[k]) HIP_TRY(hipMalloc(&c->images[k], (size_t)c->ioff[3 * c->d.levels] * 2));
+        for (int k = 0; k < c->K; ++k)
             HIP_TRY(launch_build_image(c->objs[k].grid, c->images[k], c->toff, c->ioff, c->res, c->d.levels,
                                        c->image_mode, s));
-        }
         c->images_ready = true;
     }
     // object table
@@ -387,13 +399,37 @@ extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) 
         if (value > 0 && c->d.grid_dtype != NIF_F16)
             return fail(NIF_ERR_UNSUPPORTED, "NIF_OPT_GRID_IMAGE needs binary16 grids");
         if ((int32_t)value != c->image_mode) {
-            free_images(c);  // sizes differ between kinds
+            drop_images(c);  // sizes differ between kinds: the caller registers new buffers
             c->image_mode = (int32_t)value;
             for (bool& p : c->prepared) p = false;
+            ++c->epoch;
         }
         return ok();
     }
     return fail(NIF_ERR_INVALID_ARG, "unknown option %d", option);
+}
+
+extern "C" size_t nif_image_bytes(const nif_ctx* c) {
+    if (!c) return 0;
+    return (size_t)image_elems(c, c->image_mode) * 2;
+}
+
+extern "C" nif_status nif_set_image(nif_ctx* c, int32_t obj, void* image, size_t bytes) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_set_image: NULL context");
+    if (obj < 0 || obj >= c->K) return fail(NIF_ERR_INVALID_ARG, "object %d out of range [0, %d)", obj, c->K);
+    if (c->image_mode == 0) return fail(NIF_ERR_STATE, "nif_set_image: NIF_OPT_GRID_IMAGE is 0");
+    if (!image) return fail(NIF_ERR_INVALID_ARG, "nif_set_image: NULL image");
+    if (reinterpret_cast<uintptr_t>(image) % 256 != 0)
+        return fail(NIF_ERR_INVALID_ARG, "nif_set_image: image must be 256-byte aligned");
+    const size_t need = nif_image_bytes(c);
+    if (bytes < need) return fail(NIF_ERR_WORKSPACE, "nif_set_image: need %zu bytes", need);
+    if (c->images[obj] != image) {
+        c->images[obj] = image;
+        c->images_ready = false;
+        for (bool& p : c->prepared) p = false;
+        ++c->epoch;
+    }
+    return ok();
 }
 
 static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, const void* ids, const void* tmax,
@@ -584,6 +620,9 @@ extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const floa
     if (max_pairs > 0 && (!pair_rays || !pair_tmax || !pair_ids || !pair_ray))
         return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL pair output");
     if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: at most 2^24 rays per call");
+    // per-ray counts and their scan are 32-bit: the total must stay below 2^32
+    if ((uint64_t)n_rays * (uint64_t)c->K >= ((uint64_t)1 << 32))
+        return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: n_rays x num_objects must be below 2^32");
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
     const size_t need = pairs_workspace_bytes(n_rays, c->K);
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
@@ -863,6 +902,7 @@ struct nif_plan {
     Sched sched{2, 8};
     float tuned_us = -1.0f;  // time of the chosen schedule (-1: given, not tuned)
     int32_t candidates = 0;
+    uint64_t epoch = 0;  // the context's epoch at capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -977,12 +1017,19 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
         if (p->graph) (void)hipGraphDestroy(p->graph);
         return fail(NIF_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
     }
+    p->epoch = c->epoch;
     *out = p.release();
     return ok();
 }
 
 extern "C" nif_status nif_plan_launch(nif_plan* p, void* stream) {
     if (!p || !p->exec) return fail(NIF_ERR_INVALID_ARG, "nif_plan_launch: NULL plan");
+    if (p->c->epoch != p->epoch)
+        return fail(NIF_ERR_STATE, "nif_plan_launch: the context changed since capture (object, image or option); "
+                                   "create a new plan");
+    if (!p->c->prepared[p->dtype])
+        return fail(NIF_ERR_STATE, "nif_plan_launch: context not prepared for dtype %d (weights changed since the "
+                                   "last nif_prepare)", p->dtype);
     HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
     return ok();
 }

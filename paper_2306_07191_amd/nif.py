@@ -29,7 +29,7 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
            "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
            "nif_encode16", "nif_mlp16",
-           "nif_set_option", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
+           "nif_set_option", "nif_image_bytes", "nif_set_image", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
            "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
@@ -83,6 +83,8 @@ def lib():
             "nif_prepare": (i32, [vp, i32, vp]),
             "nif_workspace_bytes": (sz, [vp, i64, i32]),
             "nif_set_option": (i32, [vp, i32, i64]),
+            "nif_image_bytes": (sz, [vp]),
+            "nif_set_image": (i32, [vp, i32, vp, sz]),
             "nif_order_workspace_bytes": (sz, [vp, i64]),
             "nif_order": (i32, [vp, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_query_ordered": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, vp]),
@@ -399,6 +401,13 @@ class Context:
         self.mlps = [None] * num_mlps
         self.mlp_index = np.zeros(num_objects, np.int32)
         self.aabb = np.zeros((num_objects, 6), np.float32)
+        # query images (NIF_OPT_GRID_IMAGE) are the caller's: allocated here,
+        # registered with nif_set_image at the next prepare; on by default for
+        # binary16 grids (the y-pair image, twice the grid's memory)
+        self.image_mode = 0
+        self.images = [None] * num_objects
+        if shape.grid_dtype == "f16":
+            self.set_option(NIF_OPT_GRID_IMAGE, 1)
 
     def close(self):
         if getattr(self, "h", None):
@@ -482,10 +491,20 @@ class Context:
         _check(lib().nif_init_grid(self.h, k, seed, amp, _stream()), "nif_init_grid")
 
     def prepare(self, dtype: str):
+        if self.image_mode:
+            t = self.torch
+            nb = int(lib().nif_image_bytes(self.h))
+            for k in range(self.K):
+                if self.images[k] is None:
+                    self.images[k] = t.empty(nb, dtype=t.uint8, device=self.device)
+                    _check(lib().nif_set_image(self.h, k, _ptr(self.images[k]), nb), "nif_set_image")
         _check(lib().nif_prepare(self.h, DTYPES[dtype], _stream()), "nif_prepare")
 
     def set_option(self, option: int, value: int):
         _check(lib().nif_set_option(self.h, option, value), "nif_set_option")
+        if option == NIF_OPT_GRID_IMAGE and value != self.image_mode:
+            self.image_mode = value
+            self.images = [None] * self.K  # the library forgot them; sizes differ between kinds
 
     def workspace_bytes(self, n: int, mode: int = 0) -> int:
         return int(lib().nif_workspace_bytes(self.h, n, mode))

@@ -128,3 +128,57 @@ def test_paper_network_and_light_validation_on_the_host():
         assert L.nif_order_packed(c, fake, fake, fake, 10, fake, C.c_void_p(4100), fake, 1 << 30, None) == -1  # misaligned
     finally:
         L.nif_destroy(c)
+
+
+def test_query_image_is_caller_owned():
+    """NIF_OPT_GRID_IMAGE images live in caller buffers: nif_image_bytes gives
+    their size for the mode (kind 1: (N+1) x N x (N+1) entries of 4 latents
+    per table; kind 2: (N+1) x N x N entries of 8), nif_set_image checks the
+    buffer, and nif_prepare refuses while an object has none."""
+    L = nif.lib()
+    h = C.c_void_p()
+    assert L.nif_create(C.byref(_desc(grid_dtype=1)), 2, 1, C.byref(h)) == 0
+    try:
+        res = [4, 8, 16, 32]
+        fake = C.c_void_p(1 << 20)
+        assert L.nif_image_bytes(h) == 0                       # default: no image
+        assert L.nif_set_image(h, 0, fake, 1 << 30) == -5       # mode 0 has no image
+        for kind, per in ((1, lambda N: (N + 1) * N * (N + 1) * 4), (2, lambda N: (N + 1) * N * N * 8)):
+            assert L.nif_set_option(h, 2, kind) == 0
+            need = 3 * sum(per(N) for N in res) * 2
+            assert L.nif_image_bytes(h) == need
+            assert L.nif_set_image(h, 2, fake, need) == -1           # object out of range
+            assert L.nif_set_image(h, 0, None, need) == -1
+            assert L.nif_set_image(h, 0, C.c_void_p((1 << 20) + 64), need) == -1  # not 256-byte aligned
+            assert L.nif_set_image(h, 0, fake, need - 1) == -3       # too small
+            assert L.nif_set_image(h, 0, fake, need) == 0
+        box = np.array([0, 0, 0, 1, 1, 1], np.float32)
+        w = C.c_void_p(1 << 21)
+        for k in range(2):
+            assert L.nif_set_object(h, k, box.ctypes.data, w, 0) == 0
+        assert L.nif_set_mlp(h, 0, w) == 0
+        assert L.nif_prepare(h, 0, None) == -5  # object 1 has no image buffer
+        assert b"nif_set_image" in L.nif_last_error()
+        # binary32 grids have no image form
+        h2 = C.c_void_p()
+        assert L.nif_create(C.byref(_desc()), 1, 1, C.byref(h2)) == 0
+        assert L.nif_set_option(h2, 2, 1) == -2
+        L.nif_destroy(h2)
+    finally:
+        L.nif_destroy(h)
+
+
+def test_expand_pairs_total_stays_32_bit():
+    """The pair counts are scanned in 32 bits: a call whose rays x objects could
+    reach 2^32 pairs is refused on the host."""
+    L = nif.lib()
+    h = C.c_void_p()
+    assert L.nif_create(C.byref(_desc()), 4096, 1, C.byref(h)) == 0
+    try:
+        fake = C.c_void_p(4096)
+        cnt = C.c_void_p(8192)
+        n = (1 << 32) // 4096  # n x K = 2^32
+        assert L.nif_expand_pairs(h, fake, fake, n, 0, None, None, None, None, cnt, fake, 1 << 40, None) == -2
+        assert b"2^32" in L.nif_last_error()
+    finally:
+        L.nif_destroy(h)

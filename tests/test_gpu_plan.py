@@ -71,3 +71,54 @@ def test_plan_rejects_bad_arguments():
         nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning='{"order": 5, "blocks_per_cu": 4}')
     with pytest.raises(nif.NifError):
         nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning='{"blocks_per_cu": 4}')
+
+
+def test_plan_refuses_a_changed_context():
+    """A captured plan is refused (NIF_ERR_STATE, on the host, before any kernel)
+    once the context changed in a way its graph cannot follow: a new query-image
+    mode (whose old buffers the caller may free), a re-registered object, or
+    weights changed since the last nif_prepare.  After nif_prepare alone it
+    launches again; after the others a new plan gives the eager outputs."""
+    import torch
+    from paper_2306_07191_amd import nif
+    sh = S.ModelShape(levels=4, res_min=4, res_max=32, feats=2, hidden=3, width=64, grid_dtype="f16")
+    w = _multi_tiny(n_objects=3, n_rays=20000)
+    w["shape"] = sh
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("bf16")
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    sched = '{"order": 1, "blocks_per_cu": 4}'
+    plan = nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning=sched)
+    plan.launch()
+    y0 = ctx.query(rays, ids, tmax, dtype="bf16")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(plan.out.cpu().numpy(), y0.cpu().numpy())
+    # weights re-registered: refused until nif_prepare, then the same outputs
+    ctx.set_mlp(0, ctx.mlps[0])
+    with pytest.raises(nif.NifError) as e:
+        plan.launch()
+    assert e.value.status == -5
+    ctx.prepare("bf16")
+    plan.out.zero_()
+    plan.launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(plan.out.cpu().numpy(), y0.cpu().numpy())
+    # another image mode: the captured graph read the old images
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 2)
+    ctx.prepare("bf16")
+    with pytest.raises(nif.NifError) as e:
+        plan.launch()
+    assert e.value.status == -5
+    # an object registered again
+    plan2 = nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning=sched)
+    ctx.set_object(1, w["aabb"][1], ctx.grids[1], int(w["mlp_index"][1]))
+    ctx.prepare("bf16")
+    with pytest.raises(nif.NifError) as e:
+        plan2.launch()
+    assert e.value.status == -5
+    plan3 = nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning=sched)
+    plan3.launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(plan3.out.cpu().numpy(), y0.cpu().numpy())
+    for p in (plan, plan2, plan3):
+        p.close()
