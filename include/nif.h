@@ -208,6 +208,23 @@ size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode);
 nif_status nif_query(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids, const float* t_max,
                      int64_t n, float* visibility, float* logits, void* ws, size_t ws_bytes, void* stream);
 
+/* nif_query for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and outputs as nif_query, without a workspace: the ordering
+ * workspace and the 32-byte query records live in a static device array of
+ * NIF_QUERY_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU, held
+ * from the first call on that GPU until the process ends.  The call allocates
+ * nothing (no hipMalloc, no hipFree).  n is limited by that array:
+ * nif_workspace_bytes(ctx, n, 0) must not exceed it, else NIF_ERR_UNSUPPORTED
+ * before anything is enqueued (64 MiB holds about 1.39 million queries of one
+ * object).  Every call on one GPU uses that GPU's array: calls that may
+ * overlap in time on one GPU (other streams, other host threads, other
+ * contexts) race on it and must be serialised by the caller, for instance by
+ * issuing them on one stream. */
+#define NIF_QUERY_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+nif_status nif_query_noalloc(nif_ctx* ctx, int32_t dtype, const float* rays, const int32_t* object_ids,
+                             const float* t_max, int64_t n, float* visibility, float* logits, void* stream);
+
 /* The ordering step and the query on a given order, as two calls (nif_query
  * runs both when NIF_OPT_ORDER selects ordering).
  * nif_order: perm (dev, n uint32) receives a permutation of [0, n): queries

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -488,13 +489,11 @@ static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, c
     return ok();
 }
 
-extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
-                                int64_t n, float* vis, float* logits, void* ws, size_t ws_bytes, void* stream) {
-    nif_status st = check_query_args(c, dtype, rays, ids, tmax, n, vis, "nif_query");
-    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
-    const size_t need = nif_workspace_bytes(c, n, 0);
-    if (ws_bytes < need || (need > 0 && !ws)) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
-    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+// The query after argument checks: ordering into ws (need > 0 bytes of it,
+// nothing in it has to start at zero), then the fused kernel.
+static nif_status query_in(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
+                           int64_t n, float* vis, float* logits, void* ws, size_t need, void* stream) {
+    nif_status st = NIF_OK;
     const uint32_t* perm = nullptr;
     float4* qrec = nullptr;
     if (need > 0) {
@@ -503,6 +502,62 @@ extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, co
         if (st != NIF_OK) return st;
     }
     return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec);
+}
+
+extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
+                                int64_t n, float* vis, float* logits, void* ws, size_t ws_bytes, void* stream) {
+    nif_status st = check_query_args(c, dtype, rays, ids, tmax, n, vis, "nif_query");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    const size_t need = nif_workspace_bytes(c, n, 0);
+    if (ws_bytes < need || (need > 0 && !ws)) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    return query_in(c, dtype, rays, ids, tmax, n, vis, logits, ws, need, stream);
+}
+
+// Scratch of nif_query_noalloc: the ordering workspace and the 32-byte query
+// records, in a static device array instead of a caller workspace.  Every GPU
+// the library runs on holds its own copy at its own address; the host-side
+// name `scratch` is not that address, so the address is looked up once per
+// device and only the looked-up pointer is handed to kernels.
+static __device__ __align__(256) uint8_t scratch[NIF_QUERY_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+static nif_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(NIF_ERR_UNSUPPORTED, "nif_query_noalloc: device %d beyond the %d supported", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(NIF_ERR_HIP, "nif_query_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NIF_OK;
+}
+
+extern "C" nif_status nif_query_noalloc(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids,
+                                        const float* tmax, int64_t n, float* vis, float* logits, void* stream) {
+    nif_status st = check_query_args(c, dtype, rays, ids, tmax, n, vis, "nif_query_noalloc");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    const size_t need = nif_workspace_bytes(c, n, 0);
+    if (need > (size_t)NIF_QUERY_NOALLOC_SCRATCH_BYTES)
+        return fail(NIF_ERR_UNSUPPORTED,
+                    "nif_query_noalloc: %lld queries need %zu bytes of scratch, the library holds %zu; "
+                    "use nif_query with a workspace or split the batch",
+                    (long long)n, need, (size_t)NIF_QUERY_NOALLOC_SCRATCH_BYTES);
+    if (!c->prepared[dtype]) return fail(NIF_ERR_STATE, "context not prepared for dtype %d", dtype);
+    void* ws = nullptr;
+    if (need > 0) {
+        st = scratch_of_current_device(&ws);
+        if (st != NIF_OK) return st;
+    }
+    return query_in(c, dtype, rays, ids, tmax, n, vis, logits, ws, need, stream);
 }
 
 extern "C" size_t nif_order_workspace_bytes(const nif_ctx* c, int64_t n) {

@@ -27,7 +27,7 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
-           "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_encode", "nif_mlp",
+           "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
            "nif_encode16", "nif_mlp16",
            "nif_set_option", "nif_image_bytes", "nif_set_image", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
@@ -91,6 +91,7 @@ def lib():
             "nif_order_packed": (i32, [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
             "nif_query_packed": (i32, [vp, i32, vp, vp, i64, vp, vp, vp]),
             "nif_query": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+            "nif_query_noalloc": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp]),
             "nif_plan_workspace_bytes": (sz, [vp, i64]),
             "nif_plan_create": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, C.c_char_p, vp, vp]),
             "nif_plan_launch": (i32, [vp, vp]),
@@ -520,6 +521,15 @@ class Context:
             ws = t.empty(wsb, dtype=t.uint8, device=self.device)
         _check(lib().nif_query(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(out),
                                _ptr(logits), _ptr(ws), 0 if ws is None else ws.numel(), _stream()), "nif_query")
+        return out
+
+    def query_noalloc(self, rays, ids, tmax, dtype: str = "f32", out=None, logits=None):
+        """nif_query_noalloc: as query, with the library's static scratch instead of a workspace."""
+        n = ids.shape[0]
+        if out is None:
+            out = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        _check(lib().nif_query_noalloc(self.h, DTYPES[dtype], _ptr(rays), _ptr(ids), _ptr(tmax), n, _ptr(out),
+                                       _ptr(logits), _stream()), "nif_query_noalloc")
         return out
 
     def order(self, rays, ids, tmax, perm=None, ws=None):

@@ -72,6 +72,14 @@ def test_validation_before_device_work():
         assert L.nif_query(h, 0, None, fake, fake, 10, fake, None, None, 0, None) == -1  # NULL rays
         assert L.nif_query(h, 7, fake, fake, fake, 10, fake, None, None, 0, None) == -2  # unknown dtype
         assert L.nif_query(h, 0, fake, fake, fake, 10, fake, None, None, 0, None) == -5  # not prepared
+        assert L.nif_query_noalloc(h, 0, fake, fake, fake, -1, fake, None, None) == -1  # n < 0
+        assert L.nif_query_noalloc(h, 0, fake, fake, fake, 0, fake, None, None) == 0   # n = 0: no-op
+        assert L.nif_query_noalloc(h, 0, fake, None, fake, 10, fake, None, None) == -1  # NULL ids
+        assert L.nif_query_noalloc(h, 0, fake, fake, fake, 10, fake, None, None) == -5  # not prepared
+        # more queries than the static scratch holds: refused, whatever the state
+        assert L.nif_workspace_bytes(h, 2_000_000, 0) > 64 * 1024 * 1024
+        assert L.nif_query_noalloc(h, 0, fake, fake, fake, 2_000_000, fake, None, None) == -2
+        assert b"scratch" in L.nif_last_error()
         assert L.nif_prepare(h, 0, None) == -5  # object 1 and the MLP are not registered
         sc = np.array([1, 1, 1, 0, 1, 1], np.float32)
         assert L.nif_set_fp8_scales(h, 0, sc.ctypes.data) == -1  # zero scale
