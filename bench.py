@@ -1,21 +1,26 @@
 """Benchmark of the neural visibility query path on one MI355X.
 
-Workload (the single-object frame): 1920 x 1080 = 2,073,600 shadow rays from a
-4 x 4 ground quad to a 0.5 x 0.5 area light, one object (a 1M-triangle displaced
-sphere; only its AABB is used by the query), grids of 8 levels 16..512 with 2
-binary16 latents per vertex (2.1 GB), MLP 48 -> 4 x 64 ReLU -> 1, Xavier weights,
-latents U(-1e-4, 1e-4).  Inputs are synthetic and seeded, resident in HBM
-before timing.  A step is one nif_query over all 2,073,600 (ray, object)
-queries: AABB clip, normalisation, multi-resolution encoding, MLP, sigmoid,
-write-back.
+Default workload (the large scene): 64 displaced spheres totalling 30M
+triangles, 1920 x 1080 ground points x 4 light samples = 8,294,400 shadow rays
+to a 4 x 4 area light; every (ray, object) pair whose AABB the ray meets is one
+query (3.3M pairs); per-object grids of 8 levels 16..512 with 2 binary16
+latents per vertex (2.1 GB each, 134 GB in all) and per-object MLPs 48 -> 4 x
+64 ReLU -> 1, each trained 64 steps on a second frame with BVH labels.  Inputs
+are synthetic and seeded, resident in HBM before timing.  A step is pair
+expansion, ordering of the pairs, the fused query kernel (AABB clip,
+normalisation, multi-resolution encoding, MLP, sigmoid, write-back) and the
+per-ray combination, in FP16 MLP arithmetic; FP8, BF16 and binary32 are timed
+beside it, and the GPU BVH any-hit over all 30M triangles on the same rays.
+The error of every dtype against the binary64 oracle on the trained models
+and the oracle's own rate on the host cores come from an evenly strided
+sample of the pairs.
 
-Besides the headline query step (not part of its timing): the four MLP
-dtypes with and without ordering, the binary64 oracle on the host cores, the
-GPU BVH any-hit baseline on the same rays, online training (64 steps of
-262,144 rays with BVH labels) and the misclassification per dtype afterwards.
+The single-object frame (2,073,600 ground-to-light rays, one object with a
+z-y-pair query image; per-dtype rates, the two-stage form, online training
+and misclassification) follows as the key "frame".  Other workloads:
+--workload frame | tiny | batched | paper.
 
-Prints ONE JSON line (see the keys below).  --gpus N > 1 is refused: this path
-runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -31,7 +36,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HEADLINE_DTYPE = "bf16"
+HEADLINE_DTYPE = "bf16"  # the single-object frame
+SCENE_DTYPE = "f16"  # the large scene (the default line): the paper's 16-bit weights
 PEAK_TFLOPS = {"bf16": 2500.0, "f16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
 GRID_SEED = 2024
@@ -59,11 +65,12 @@ def time_launches(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed counter run,
-    or None when the kernel source has changed since those counters were taken."""
+def measured_traffic(name: str):
+    """HBM bytes per launch of the fused kernel from the committed counter run
+    profiles/query_<name>_traffic.json, or None when there is none or the kernel
+    source has changed since those counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "query_frame_bf16_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"query_{name}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -338,16 +345,97 @@ def run_batched(args):
     ctx.close()
 
 
+def scene_oracle_errors(ctx, w, sh, pairs, gpu_y, scales, budget_s: float = 12.0):
+    """Error of the GPU outputs against the binary64 oracle on the trained
+    per-object models, over an evenly strided sample of the scene's pairs.
+    The oracle runs with binary64 clip and cell coordinates (no binary32 step)
+    on each object's trained latents and weights, copied to the host one
+    object at a time.  Per dtype: max and p99.9 of |y - y64| and, for the
+    reduced-precision dtypes, of the oracle's per-query rounding bound (the
+    propagated bound of the unquantised result), and the count of queries
+    above their bound.  Also the oracle's own rate (the CPU baseline)."""
+    import torch
+    from oracle import oracle as O
+    pr_np, pi_np, pt_np = pairs
+    P = pi_np.shape[0]
+    K = ctx.K
+    cores = len(os.sched_getaffinity(0))
+    mlps = np.stack([ctx.mlps[k].cpu().numpy() for k in range(ctx.M)])
+    # pilot rate on object 0's generated latents fixes the sample size
+    pilot = O.Model(sh, w["aabb"], mlps, mlp_index=w["mlp_index"], grid_seed=GRID_SEED, grid_amp=1e-4, coord_mode=1)
+    m0 = min(P, 20000)
+    t0 = time.perf_counter()
+    pilot.forward(pr_np[:m0], pi_np[:m0], pt_np[:m0], nthreads=cores)
+    rate = m0 / (time.perf_counter() - t0)
+    m = int(min(P, max(m0, rate * budget_s)))
+    sel = np.linspace(0, P - 1, m).astype(np.int64)
+    mb = min(m, 200000)  # the rounding bounds: a sub-sample
+    selb = sel[np.linspace(0, m - 1, mb).astype(np.int64)]
+    y64 = np.empty(m)
+    y32c = np.empty(mb)  # binary32-coordinate oracle: the error split of the binary32 path
+    bounds = {dt: np.empty(mb) for dt in ("f16", "bf16", "fp8")}
+    ids_s = pi_np[sel]
+    ids_b = pi_np[selb]
+    exact_s = 0.0
+    for k in range(K):
+        ik = np.nonzero(ids_s == k)[0]
+        jk = np.nonzero(ids_b == k)[0]
+        if ik.size == 0 and jk.size == 0:
+            continue
+        grids = [None] * K
+        grids[k] = ctx.grids[k].view(torch.int16).cpu().numpy().view(np.uint16)
+        model = O.Model(sh, w["aabb"], mlps, mlp_index=w["mlp_index"], grids=grids, coord_mode=1, fp8_scales=scales)
+        if ik.size:
+            q = sel[ik]
+            t0 = time.perf_counter()
+            y64[ik] = model.forward(pr_np[q], pi_np[q], pt_np[q], nthreads=cores)["y"]
+            exact_s += time.perf_counter() - t0
+        if jk.size:
+            q = selb[jk]
+            for dt in bounds:
+                bounds[dt][jk] = model.with_(quant=dt).forward(pr_np[q], pi_np[q], pt_np[q], nthreads=cores)["ybound"]
+            y32c[jk] = model.with_(coord_mode=0).forward(pr_np[q], pi_np[q], pt_np[q], nthreads=cores)["y"]
+        del grids, model
+    errs = {}
+    pos = np.searchsorted(sel, selb)
+    big = y64 >= 1e-6  # relative errors where the sigmoid has not underflowed in binary32
+    for dt, y in gpu_y.items():
+        e = np.abs(y[sel].astype(np.float64) - y64)
+        rel = e[big] / y64[big]
+        r = {"max_abs": float(e.max()), "p99.9_abs": float(np.quantile(e, 0.999)),
+             "max_rel_y64_ge_1e-6": float(rel.max()), "frac_rel_le_1e-5": float((rel <= 1e-5).mean()),
+             "queries": int(m)}
+        if dt == "f32":
+            # split: the same binary32 path against the oracle whose clip and cell
+            # coordinates are binary32 in the kernel's operation order
+            e32 = np.abs(y[selb].astype(np.float64) - y32c)
+            r["vs_binary32_coordinate_oracle"] = {"max_abs": float(e32.max()),
+                                                  "p99.9_abs": float(np.quantile(e32, 0.999)),
+                                                  "queries": int(mb)}
+            r["coordinate_rounding_alone"] = {"max_abs": float(np.abs(y32c - y64[pos]).max()),
+                                              "p99.9_abs": float(np.quantile(np.abs(y32c - y64[pos]), 0.999))}
+        if dt in bounds:
+            eb = np.abs(y[selb].astype(np.float64) - y64[pos])
+            r.update({"bound_max": float(bounds[dt].max()), "bound_p99.9": float(np.quantile(bounds[dt], 0.999)),
+                      "above_bound": int((eb > bounds[dt]).sum()), "bound_queries": int(mb)})
+        errs[dt] = r
+    cpu = {"value": m / exact_s, "unit": "queries/s", "cores": cores, "kind": "oracle",
+           "sample": f"{m} of {P} scene (ray, object) pairs, evenly strided, binary64 clip+encode+MLP on the "
+                     f"trained per-object models, {cores} threads"}
+    return cpu, errs
+
+
 def run_scene(args):
-    """Large scene: 64 displaced spheres (30M triangles, log-uniform sizes) on a
-    48 x 27 ground plane, 1920 x 1080 ground points x 4 light samples =
-    8,294,400 shadow rays to a 4 x 4 light at height 30.  Queries are the
-    (ray, object) pairs whose AABB the ray meets (found on the GPU).  Each
-    object's MLP and grids are trained 64 steps on the pairs of a second frame
-    (other light samples) with labels from that object's GPU BVH, FP8 scales
-    calibrated on them.  A step is pair expansion + query + per-ray
-    combination; compared per MLP dtype, and against the GPU BVH any-hit over
-    all 30M triangles on the same rays."""
+    """Large scene (the headline): 64 displaced spheres (30M triangles,
+    log-uniform sizes) on a 48 x 27 ground plane, 1920 x 1080 ground points x 4
+    light samples = 8,294,400 shadow rays to a 4 x 4 light at height 30.
+    Queries are the (ray, object) pairs whose AABB the ray meets (found on the
+    GPU).  Each object's MLP and grids are trained 64 steps on the pairs of a
+    second frame (other light samples) with labels from that object's GPU BVH,
+    FP8 scales calibrated on them.  A step is pair expansion, ordering of the
+    pairs, the fused query kernel and the per-ray combination; timed per MLP
+    dtype, and compared with the GPU BVH any-hit over all 30M triangles on the
+    same rays.  Returns the result dict."""
     import torch
     from paper_2306_07191_amd import nif, synth as S
     t0 = time.perf_counter()
@@ -371,12 +459,12 @@ def run_scene(args):
     bvh = nif.BVH(np.concatenate(w["tris"]))
     build_s = time.perf_counter() - tb
     labels = torch.empty(n, dtype=torch.uint8, device="cuda")
-    bvh_sec = time_launches(lambda: bvh.anyhit(rays, tmax, out=labels), 5, 1)
+    bvh_sec = time_launches(lambda: bvh.anyhit(rays, tmax, out=labels), 10, 2)
     lab = labels.cpu().numpy()
     bvh_nodes = bvh.num_nodes
     bvh.close()
     log(f"GPU BVH over all triangles: {bvh_nodes} nodes (host build {build_s:.1f}s), any-hit "
-        f"{bvh_sec * 1e3:.2f} ms = {n / bvh_sec / 1e9:.3f} G rays/s; occluded {1 - lab.mean():.3f}")
+        f"{bvh_sec * 1e3:.3f} ms = {n / bvh_sec / 1e9:.3f} G rays/s; occluded {1 - lab.mean():.3f}")
 
     # training frame: pairs per object, labels from each object's BVH
     tr_r, tr_t = S.scene_rays(light_seed=1)
@@ -391,12 +479,13 @@ def run_scene(args):
     tws = torch.empty(max(1, ctx.workspace_bytes(nb, 1)), dtype=torch.uint8, device="cuda")
     g = np.random.default_rng(5)
     train_ms, n_train = 0.0, 0
+    scales = np.ones((K, 2 * sh.hidden), np.float64)
     for k in range(K):
         idx = torch.from_numpy(order[bounds[k]:bounds[k + 1]]).cuda()
         m = idx.numel()
-        if m == 0:  # no pair of the training frame: keep the initial model, scales from the weights
+        if m == 0 or args.no_train:  # no pair of the training frame: the initial model, scales from the weights
             e = torch.empty(0, device="cuda")
-            ctx.calibrate_fp8(e.view(0, 6), e.int(), e, mlp=k)
+            scales[k] = ctx.calibrate_fp8(e.view(0, 6), e.int(), e, mlp=k)
             continue
         rk, tk = p_rays[idx].contiguous(), p_tmax[idx].contiguous()
         ik = torch.full((m,), k, dtype=torch.int32, device="cuda")
@@ -421,11 +510,13 @@ def run_scene(args):
             n_train += args_[1].numel()
         ctx.prepare("f32")
         c = min(m, CALIB_QUERIES)
-        ctx.calibrate_fp8(rk[:c], ik[:c], tk[:c], mlp=k)
+        scales[k] = ctx.calibrate_fp8(rk[:c], ik[:c], tk[:c], mlp=k)
     del p_rays, p_tmax, p_ids
-    log(f"trained {K} objects x {TRAIN_STEPS} steps: {n_train / (train_ms / 1e3) / 1e6:.1f} M pairs/s")
+    train_rate = n_train / (train_ms / 1e3) if train_ms > 0 else None
+    log(f"trained {K} objects x {TRAIN_STEPS} steps: {(train_rate or 0) / 1e6:.1f} M pairs/s")
 
-    # the timed step: expansion into preallocated buffers, query, combination
+    # the timed step, into preallocated buffers: pair expansion, ordering of the
+    # pairs (with their 32-byte records), the fused query kernel, combination
     L = nif.lib()
     pws = torch.empty(max(1, int(L.nif_pairs_workspace_bytes(ctx.h, n))), dtype=torch.uint8, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -441,45 +532,78 @@ def run_scene(args):
                                       nif._stream()), "nif_expand_pairs")
 
     expand()
-    P = int(cnt.item())
+    P = int(cnt.item())  # the same rays every step: the pair count is fixed
     assert P <= maxp
     yq = torch.empty(P, dtype=torch.float32, device="cuda")
-    qws = torch.empty(max(1, ctx.workspace_bytes(P)), dtype=torch.uint8, device="cuda")
+    perm = torch.empty(P, dtype=torch.int32, device="cuda")
+    recs = torch.empty((P, 8), dtype=torch.float32, device="cuda")
+    ows = torch.empty(max(1, int(L.nif_order_workspace_bytes(ctx.h, P))), dtype=torch.uint8, device="cuda")
     vis = torch.empty(n, dtype=torch.uint8, device="cuda")
-    res = {}
+    flops = 2 * (sh.din * sh.width + (sh.hidden - 1) * sh.width * sh.width + sh.width)  # 30,848 per query
+    res, gpu_y = {}, {}
     mask_ref = lab.reshape(-1, S.SCENE_SPP).mean(axis=1)
-    for dt in ("fp8", "bf16", "f32"):
+    stream = torch.cuda.current_stream()
+    for dt in ((SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")):
         ctx.prepare(dt)
+        steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
 
-        def step():
+        def stages(ev=None):
             expand()
-            ctx.query(pr[:P], pi[:P], pt[:P], dtype=dt, out=yq, ws=qws)
+            if ev: ev[0].record(stream)
+            ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
+            if ev: ev[1].record(stream)
+            ctx.query_packed(recs, perm, dtype=dt, out=yq)
+            if ev: ev[2].record(stream)
             ctx.combine_pairs(pray[:P], yq, n, out=vis)
 
-        sec = time_launches(step, args.steps if dt == "fp8" else max(5, args.steps // 2), args.warmup)
+        for _ in range(args.warmup):
+            stages()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        w0 = time.perf_counter()
+        b0.record(stream)
+        marks[0].record(stream)
+        for k in range(steps):
+            stages(evs[k])
+            marks[k + 1].record(stream)
+        b1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        sec = b0.elapsed_time(b1) / 1e3 / steps
+        part = lambda a, b: sum(a(k).elapsed_time(b(k)) for k in range(steps)) / 1e3 / steps
+        t_exp = part(lambda k: marks[k], lambda k: evs[k][0])
+        t_ord = part(lambda k: evs[k][0], lambda k: evs[k][1])
+        t_q = part(lambda k: evs[k][1], lambda k: evs[k][2])
+        t_comb = part(lambda k: evs[k][2], lambda k: marks[k + 1])
         v = vis.cpu().numpy()
+        gpu_y[dt] = yq.cpu().numpy().copy()
         mis = float((v != lab).mean())
         mse = float(((v.reshape(-1, S.SCENE_SPP).mean(axis=1) - mask_ref) ** 2).mean())
         psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
         res[dt] = {"ms": sec * 1e3, "rays_per_s": n / sec, "pairs_per_s": P / sec, "misclassification": mis,
-                   "psnr_db": psnr}
-        log(f"{dt}: step {sec * 1e3:.3f} ms = {n / sec / 1e9:.3f} G rays/s ({P / sec / 1e9:.3f} G pairs/s), "
-            f"misclassification {100 * mis:.3f} %, mask PSNR {psnr:.2f} dB")
-    e_sec = time_launches(expand, 5, 1)
+                   "psnr_db": psnr, "stage_ms": {"pair_expansion": t_exp * 1e3, "ordering": t_ord * 1e3,
+                                                 "query_kernel": t_q * 1e3, "combination": t_comb * 1e3},
+                   "query_kernel_tflops": flops * P / t_q / 1e12, "wall_s": wall}
+        log(f"{dt}: step {sec * 1e3:.3f} ms = {n / sec / 1e9:.3f} G rays/s ({P / sec / 1e9:.3f} G pairs/s): expansion "
+            f"{t_exp * 1e3:.3f}, ordering {t_ord * 1e3:.3f}, query kernel {t_q * 1e3:.3f} "
+            f"({flops * P / t_q / 1e12:.0f} TFLOP/s), combination {t_comb * 1e3:.3f} ms; misclassification "
+            f"{100 * mis:.3f} %, mask PSNR {psnr:.2f} dB")
+    if "f32" in res:
+        for dt in res:
+            res[dt]["added_misclassification_vs_f32"] = res[dt]["misclassification"] - res["f32"]["misclassification"]
 
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as O
-        pr_np, pi_np, pt_np = pr[:P].cpu().numpy(), pi[:P].cpu().numpy(), pt[:P].cpu().numpy()
-        model = O.Model(sh, w["aabb"], w["mlps"], mlp_index=w["mlp_index"], grid_seed=GRID_SEED, grid_amp=1e-4)
-        cores = len(os.sched_getaffinity(0))
-        sel = np.linspace(0, P - 1, min(P, 200000)).astype(np.int64)
-        ts = time.perf_counter()
-        model.forward(pr_np[sel], pi_np[sel], pt_np[sel], nthreads=cores)
-        dt_ = time.perf_counter() - ts
-        cpu = {"value": sel.size / dt_, "unit": "queries/s", "cores": cores, "kind": "oracle",
-               "sample": f"{sel.size} of {P} scene pairs (evenly strided), binary64 encode+MLP"}
-    head = res["fp8"]
+    cpu, errs = None, None
+    if not (args.no_cpu or args.quick):
+        pairs = (pr[:P].cpu().numpy(), pi[:P].cpu().numpy(), pt[:P].cpu().numpy())
+        t0 = time.perf_counter()
+        cpu, errs = scene_oracle_errors(ctx, w, sh, pairs, gpu_y, scales)
+        log(f"oracle on trained models ({time.perf_counter() - t0:.1f}s): {cpu['value']:.0f} queries/s on "
+            f"{cpu['cores']} cores; errors {json.dumps(errs)}")
+    head = res[SCENE_DTYPE]
+    tq = head["stage_ms"]["query_kernel"] / 1e3
+    achieved = flops * P / tq / 1e12
     out = {
         "metric": "shadow-ray visibility queries/sec at stated error vs FP64 oracle",
         "value": head["pairs_per_s"],
@@ -491,22 +615,29 @@ def run_scene(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp8",
-        "data": "synthetic (seeded 64-object scene, 30M triangles; per-object trained models)",
+        "dtype": SCENE_DTYPE,
+        "data": "synthetic (seeded 64-object scene, 30M triangles; per-object models trained on a second frame)",
         "config": {"workload": "scene: 64 objects, 30M triangles, 1920x1080 x 4 light samples = 8,294,400 shadow "
-                               "rays, (ray, object) pairs, 8 levels 16..512, MLP 48-64x4-1 per object",
-                   "rays": n, "pairs": P, "objects": K},
-        "roofline": None,
+                               "rays, (ray, object) pairs, 8 levels 16..512, 2 binary16 latents, MLP 48-64x4-1 "
+                               "per object",
+                   "rays": n, "pairs": P, "objects": K, "triangles": int(w["tri_counts"].sum()),
+                   "step": "pair expansion + pair ordering + fused query kernel + per-ray combination",
+                   "value_is": "(ray, object) queries per second; rays_per_s is in per_dtype"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE], "traffic": measured_traffic("scene"),
+                     "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, no image> (fused clip+encode+MLP)",
+                     "algorithmic_flop_per_launch": flops * P, "kernel_us": tq * 1e6},
         "cpu_baseline": cpu,
+        "error_vs_binary64_oracle_trained": errs,
         "per_dtype": res,
-        "pair_expansion_ms": e_sec * 1e3,
         "bvh_all_triangles": {"ms": bvh_sec * 1e3, "rays_per_s": n / bvh_sec, "nodes": bvh_nodes,
-                              "host_build_s": build_s},
+                              "host_build_s": build_s, "occluded_fraction": float(1 - lab.mean())},
+        "speedup_vs_bvh": bvh_sec * 1e3 / head["ms"],
         "paper_context_ms": {"nif": 4.54, "bvh": 5.27, "gpu": "RX 7900 XT, 30M triangles, 1920x1080"},
-        "train_pairs_per_s": n_train / (train_ms / 1e3),
+        "train_pairs_per_s": train_rate,
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 def run_paper(args):
@@ -636,6 +767,56 @@ def run_paper(args):
     pm.close()
 
 
+def run_train(args):
+    """Online training alone on the frame scene (the training configuration):
+    TRAIN_STEPS steps of 262,144 fresh ground-to-light rays, labels from the GPU
+    BVH of the 1M-triangle mesh, binary cross-entropy, backward through the
+    MLP and the grid interpolation, Adam (lr 1e-2, betas 0.9 / 0.99).  Reports
+    train rays/s (label generation timed apart) and the loss curve."""
+    import torch
+    from paper_2306_07191_amd import nif, synth as S
+    w = S.frame_workload(with_mesh=True, n_rays=1)
+    sh = w["shape"]
+    ctx = nif.Context(sh)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    ctx.set_mlp(0, torch.from_numpy(w["mlps"][0]).cuda())
+    ctx.set_object(0, w["aabb"][0], ctx.alloc_grid(), 0)
+    ctx.init_grid(0, GRID_SEED, 1e-4)
+    ctx.prepare("f32")
+    bvh = nif.BVH(w["tris"])
+    steps = TRAIN_STEPS if not args.quick else min(TRAIN_STEPS, max(4, args.steps))
+    batches = [S.train_batch(s) for s in range(steps)]
+    nb = batches[0][0].shape[0]
+    tr = [(torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda()) for r, t in batches]
+    tid = torch.zeros(nb, dtype=torch.int32, device="cuda")
+    tl = [bvh.anyhit(r, t) for r, t in tr]
+    bvh.close()
+    ctx.setup_training()
+    tws = torch.empty(max(1, ctx.workspace_bytes(nb, 1)), dtype=torch.uint8, device="cuda")
+    losses = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for s in range(steps):
+        ctx.train_step(tr[s][0], tid, tr[s][1], tl[s], step=s + 1, loss=losses[s:s + 1], ws=tws)
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
+    train_s = sum(step_ms) / 1e3
+    curve = [round(float(v), 5) for v in losses.cpu().numpy()]
+    log(f"train: {steps} x {nb} rays in {train_s * 1e3:.1f} ms = {steps * nb / train_s / 1e6:.1f} M rays/s; "
+        f"median step {np.median(step_ms):.3f} ms; loss {curve[0]:.4f} -> {curve[-1]:.4f}")
+    out = {"metric": "train-step rays/s", "value": steps * nb / train_s, "unit": "rays/s", "n_gpus": 1,
+           "steps": steps, "warmup": 0, "ms_per_step": float(np.median(step_ms)), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded frame scene, fresh ground-to-light rays per step, GPU BVH labels)",
+           "config": {"workload": "train: 1 object, batches of 262,144 rays, 8 levels 16..512, binary16 latents, "
+                                  "MLP 48-64x4-1, BCE, Adam lr 1e-2 betas 0.9/0.99", "batch": nb},
+           "loss_curve": curve}
+    ctx.close()
+    return out
+
+
 def run_tiny(args):
     """The small case: 2,048 random triangles, 16,384 rays from a radius-3
     sphere, 4 levels 4..32 with binary32 latents U(-1e-4, 1e-4), MLP
@@ -697,11 +878,15 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=("frame", "tiny", "batched", "scene", "paper"), default="frame",
-                    help="frame: single-object 1920x1080 frame (default); tiny: the 16,384-ray case; "
-                         "batched: 32 objects, 4M Zipf queries; "
-                         "scene: 64 objects, 30M triangles, 8.3M shadow rays; "
-                         "paper: the paper's outer / inner networks on the frame scene")
+    ap.add_argument("--workload", choices=("frame", "tiny", "batched", "scene", "paper", "train"), default="scene",
+                    help="scene (default): 64 objects, 30M triangles, 8.3M shadow rays, followed by the "
+                         "single-object frame as an extra key; frame: the single-object 1920x1080 frame alone; "
+                         "tiny: the 16,384-ray case; batched: 32 objects, 4M Zipf queries; "
+                         "paper: the paper's outer / inner networks on the frame scene; "
+                         "train: online training on the frame scene alone")
+    ap.add_argument("--no-frame", action="store_true", help="scene: skip the single-object frame key")
+    ap.add_argument("--no-train", action="store_true",
+                    help="scene: skip the per-object training (initial models; for counter runs of the query step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--quick", action="store_true",
@@ -727,15 +912,30 @@ def main():
     if args.workload == "batched":
         run_batched(args)
         return
-    if args.workload == "scene":
-        run_scene(args)
-        return
     if args.workload == "tiny":
         run_tiny(args)
         return
     if args.workload == "paper":
         run_paper(args)
         return
+    if args.workload == "frame":
+        print(json.dumps(run_frame(args)), flush=True)
+        return
+    if args.workload == "train":
+        print(json.dumps(run_train(args)), flush=True)
+        return
+    out = run_scene(args)
+    if not (args.quick or args.no_frame):
+        torch.cuda.empty_cache()
+        out["frame"] = run_frame(args)
+    print(json.dumps(out), flush=True)
+
+
+def run_frame(args):
+    """Single-object frame: 2,073,600 ground-to-light shadow rays, one object
+    with a z-y-pair query image.  Returns the result dict."""
+    import torch
+    from paper_2306_07191_amd import nif, synth as S
     t0 = time.perf_counter()
     w = S.frame_workload(with_mesh=False)
     sh = w["shape"]
@@ -803,8 +1003,13 @@ def main():
         ctx.set_option(nif.NIF_OPT_ORDER, 2)
 
     # the contract timing for the headline dtype: a step is the ordering pass plus
-    # the fused query kernel; events around the kernel give its own duration
+    # the fused query kernel; events around the kernel give its own duration.
+    # nif_prepare rebuilds the query image from the grid: timed on its own
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
     ctx.prepare(HEADLINE_DTYPE)
+    torch.cuda.synchronize()
+    image_ms = (time.perf_counter() - ti) * 1e3
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     recs = torch.empty((n, 8), dtype=torch.float32, device="cuda")  # the queries as 32-byte records
     ows = torch.empty(max(1, nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
@@ -848,7 +1053,7 @@ def main():
         cold = {"kernel_us_median": float(np.median(ks)) * 1e6}
         log(f"cold fused kernel: {cold['kernel_us_median']:.1f} us")
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_TFLOPS[HEADLINE_DTYPE],
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic(),
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic("frame_bf16"),
                 "kernel": "nif_query_kernel<bf16, L=8, f16 grid, z-y-pair image> (fused clip+encode+MLP)",
                 "algorithmic_flop_per_launch": flops * n, "kernel_us": kern * 1e6,
                 "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6,
@@ -889,9 +1094,12 @@ def main():
         "error_vs_oracle_on_cpu_sample": errs,
         "train_and_labels": train,
         "wall_s_timed_region": wall,
+        "image_build_ms": image_ms,
+        "image_build_note": "nif_prepare rebuilds the z-y-pair query image of the 2.1 GB grid (and packs the "
+                            "weights); it reruns after every training step and is not part of the step",
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 if __name__ == "__main__":
