@@ -699,6 +699,31 @@ void orc_status(const orc_model* m, int64_t n, const float* rays, const int32_t*
     }
 }
 
+/* Segment ends [t_a, t_b] of n queries (+inf, +inf for a miss, NaN for an
+ * invalid query), in the model's coordinate precision: what the depth output
+ * is measured against (t = t_a + y (t_b - t_a)). */
+void orc_segment(const orc_model* m, int64_t n, const float* rays, const int32_t* ids, const float* tmax, double* ta,
+                 double* tb) {
+    for (int64_t i = 0; i < n; ++i) {
+        const float* r = rays + 6 * i;
+        ta[i] = tb[i] = NAN;
+        if (!valid_query(r, tmax[i], ids[i], m->num_objects)) continue;
+        const float* bx = m->aabb + 6 * (int64_t)ids[i];
+        int hit;
+        if (m->coord_mode == 0) {
+            float a, b;
+            hit = clip32(r, r + 3, tmax[i], bx, bx + 3, &a, &b);
+            ta[i] = a;
+            tb[i] = b;
+        } else {
+            double o[3], d[3], lo[3], hi[3];
+            for (int k = 0; k < 3; ++k) { o[k] = r[k]; d[k] = r[3 + k]; lo[k] = bx[k]; hi[k] = bx[3 + k]; }
+            hit = clip64(o, d, (double)tmax[i], lo, hi, &ta[i], &tb[i]);
+        }
+        if (!hit) ta[i] = tb[i] = INFINITY;
+    }
+}
+
 void orc_forward(const orc_model* m, int64_t n, const float* rays, const int32_t* ids, const float* tmax,
                  double* z, double* y, int32_t* status, double* ztol, double* ybound, int32_t* flags,
                  double* x_out, int nthreads) {
@@ -994,7 +1019,9 @@ void orc_grid_grad_at(const orc_model* m, int32_t obj, int64_t n, const float* r
  * Double-sided.
  * ====================================================================== */
 
-int orc_ray_tri(const double o[3], const double d[3], double tmax, const float* tri) {
+/* The same test returning the hit distance: 1 and *t = T / det (binary64) when
+ * the triangle is hit with 0 < t < tmax, else 0. */
+int orc_ray_tri_t(const double o[3], const double d[3], double tmax, const float* tri, double* t_out) {
     int kz = 0;
     double ad[3] = {fabs(d[0]), fabs(d[1]), fabs(d[2])};
     if (ad[1] > ad[kz]) kz = 1;
@@ -1023,7 +1050,12 @@ int orc_ray_tri(const double o[3], const double d[3], double tmax, const float* 
     /* 0 < T/det < tmax */
     if (!(T > 0.0)) return 0;
     if (!isinf(tmax) && !(T < tmax * det)) return 0;
+    if (t_out) *t_out = T / det;
     return 1;
+}
+
+int orc_ray_tri(const double o[3], const double d[3], double tmax, const float* tri) {
+    return orc_ray_tri_t(o, d, tmax, tri, NULL);
 }
 
 typedef struct {
@@ -1191,4 +1223,68 @@ static void bvh_range(void* p, int64_t b, int64_t e) {
 void orc_anyhit_bvh(const orc_bvh* h, int64_t n, const float* rays, const float* tmax, uint8_t* vis, int nthreads) {
     bvh_job J = {h, rays, tmax, vis};
     parallel_for(n, nthreads, bvh_range, &J);
+}
+
+/* Closest hit (primary rays; the depth of Sec. 7's primary-ray use of the
+ * network): t_hit[i] = min over triangles of the hit distance T / det of the
+ * test above with 0 < t < t_max, +inf when none.  Brute force, then a BVH walk
+ * that prunes boxes beyond the best hit so far with the same widened slab test
+ * (a box holding a closer hit is never pruned, so the minimum is the brute
+ * force's, bit for bit). */
+typedef struct {
+    int64_t T;
+    const float* tris;
+    const float *rays, *tmax;
+    double* t_hit;
+} closest_brute_job;
+
+static void closest_brute_range(void* p, int64_t b, int64_t e) {
+    closest_brute_job* J = (closest_brute_job*)p;
+    for (int64_t i = b; i < e; ++i) {
+        const float* r = J->rays + 6 * i;
+        double o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
+        double best = INFINITY, t;
+        for (int64_t k = 0; k < J->T; ++k)
+            if (orc_ray_tri_t(o, d, (double)J->tmax[i], J->tris + 9 * k, &t) && t < best) best = t;
+        J->t_hit[i] = best;
+    }
+}
+
+void orc_closest_brute(int64_t T, const float* tris, int64_t n, const float* rays, const float* tmax, double* t_hit,
+                       int nthreads) {
+    closest_brute_job J = {T, tris, rays, tmax, t_hit};
+    parallel_for(n, nthreads, closest_brute_range, &J);
+}
+
+typedef struct { const orc_bvh* h; const float *rays, *tmax; double* t_hit; } closest_bvh_job;
+
+static void closest_bvh_range(void* p, int64_t b, int64_t e) {
+    closest_bvh_job* J = (closest_bvh_job*)p;
+    const orc_bvh* h = J->h;
+    int64_t stack[128];
+    for (int64_t i = b; i < e; ++i) {
+        const float* r = J->rays + 6 * i;
+        double o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
+        const double tm = (double)J->tmax[i];
+        double best = INFINITY, t;
+        int sp = 0;
+        if (h->T > 0) stack[sp++] = 0;
+        while (sp) {
+            const orc_node* nd = &h->nodes[stack[--sp]];
+            if (!box_hit(nd, o, d, best < tm ? best : tm)) continue;
+            if (nd->left < 0) {
+                for (int64_t k = nd->first; k < nd->first + nd->count; ++k)
+                    if (orc_ray_tri_t(o, d, tm, h->tris + 9 * h->idx[k], &t) && t < best) best = t;
+            } else {
+                stack[sp++] = nd->left;
+                stack[sp++] = nd->right;
+            }
+        }
+        J->t_hit[i] = best;
+    }
+}
+
+void orc_closest_bvh(const orc_bvh* h, int64_t n, const float* rays, const float* tmax, double* t_hit, int nthreads) {
+    closest_bvh_job J = {h, rays, tmax, t_hit};
+    parallel_for(n, nthreads, closest_bvh_range, &J);
 }

@@ -71,6 +71,7 @@ def lib():
             "orc_query_detail": (C.c_int, [vp, vp, i32, C.c_float, vp, vp, vp, vp]),
             "orc_mlp_only": (None, [vp, i32, i64, vp, vp, vp]),
             "orc_status": (None, [vp, i64, vp, vp, vp, vp]),
+            "orc_segment": (None, [vp, i64, vp, vp, vp, vp, vp]),
             "orc_backward": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_backward_given": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_grid_grad_dense": (None, [vp, i32, i64, vp, vp, vp, vp, vp]),
@@ -80,6 +81,9 @@ def lib():
             "orc_bvh_build": (vp, [i64, vp]),
             "orc_bvh_free": (None, [vp]),
             "orc_anyhit_bvh": (None, [vp, i64, vp, vp, vp, C.c_int]),
+            "orc_ray_tri_t": (C.c_int, [vp, vp, d, vp, vp]),
+            "orc_closest_brute": (None, [i64, vp, i64, vp, vp, vp, C.c_int]),
+            "orc_closest_bvh": (None, [vp, i64, vp, vp, vp, C.c_int]),
             "orc_default_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -219,6 +223,53 @@ class Model:
         st = np.empty(ids.shape[0], np.int32)
         lib().orc_status(self.ref, ids.shape[0], _p(rays), _p(ids), _p(tmax), _p(st))
         return st
+
+    def segment(self, rays, ids, tmax):
+        """[t_a, t_b] of every query (+inf for a miss, NaN for an invalid one)."""
+        rays = np.ascontiguousarray(rays, np.float32)
+        ids = np.ascontiguousarray(ids, np.int32)
+        tmax = np.ascontiguousarray(tmax, np.float32)
+        n = ids.shape[0]
+        ta, tb = np.empty(n), np.empty(n)
+        lib().orc_segment(self.ref, n, _p(rays), _p(ids), _p(tmax), _p(ta), _p(tb))
+        return ta, tb
+
+    # ---- depth output for primary rays (Sec. 7: the network can encode the
+    # ---- depth of the first hit instead of visibility) ------------------
+    def depth_targets(self, rays, ids, tmax, t_hit):
+        """Normalised depth s = (t_hit - t_a) / (t_b - t_a) clamped to [0, 1] of
+        the queries that meet their AABB, whose closest hit is finite and whose
+        segment has t_b > t_a; NaN elsewhere (no target)."""
+        ta, tb = self.segment(rays, ids, tmax)
+        t_hit = np.asarray(t_hit, np.float64)
+        ok = np.isfinite(ta) & np.isfinite(tb) & np.isfinite(t_hit) & (tb > ta)
+        s = np.full(ta.shape, np.nan)
+        s[ok] = np.clip((t_hit[ok] - ta[ok]) / (tb[ok] - ta[ok]), 0.0, 1.0)
+        return s
+
+    def depth_loss_backward(self, rays, ids, tmax, t_hit, nthreads: int = 0):
+        """L2 depth loss (the paper trains with L2, Sec. 5 "Training") over the B
+        queries with a target: L = (1/B) sum (y - s)^2, y = sigmoid(z); its
+        gradients through the upstream-gradient backward with dL/dy = 2 (y - s) / B.
+        Returns (loss, B, mlp_grads [M, P], gx [n, din])."""
+        s = self.depth_targets(rays, ids, tmax, t_hit)
+        f = self.forward(rays, ids, tmax, nthreads=nthreads)
+        ok = np.isfinite(s) & (f["status"] == 1)
+        B = int(ok.sum())
+        gy = np.zeros(s.shape[0])
+        if B:
+            gy[ok] = 2.0 * (f["y"][ok] - s[ok]) / B
+        _, g, gx = self.backward_given(rays, ids, tmax, gy, nthreads=nthreads)
+        loss = float(((f["y"][ok] - s[ok]) ** 2).mean()) if B else 0.0
+        return loss, B, g, gx
+
+    def depth(self, rays, ids, tmax, nthreads: int = 0):
+        """Predicted closest-hit distance t_a + y (t_b - t_a) (+inf for a miss)."""
+        ta, tb = self.segment(rays, ids, tmax)
+        y = self.forward(rays, ids, tmax, nthreads=nthreads)["y"]
+        t = ta + y * (tb - ta)
+        t[np.isinf(ta)] = np.inf
+        return t
 
     def expand_pairs(self, rays, tmax):
         """(Sec. 4.1) The (ray, object) pairs whose segment meets the object's AABB,
@@ -383,6 +434,25 @@ def anyhit_brute(tris, rays, tmax, nthreads: int = 0) -> np.ndarray:
     return vis
 
 
+def ray_tri_t(o, d, tmax, tri):
+    """Hit distance of the watertight test (binary64), or None for a miss."""
+    o = np.ascontiguousarray(o, np.float64)
+    d = np.ascontiguousarray(d, np.float64)
+    t = np.ascontiguousarray(tri, np.float32).reshape(9)
+    out = C.c_double(0.0)
+    return out.value if lib().orc_ray_tri_t(_p(o), _p(d), float(tmax), _p(t), C.byref(out)) else None
+
+
+def closest_brute(tris, rays, tmax, nthreads: int = 0) -> np.ndarray:
+    """Closest-hit distance per ray (binary64; +inf when no hit with 0 < t < t_max)."""
+    tris = np.ascontiguousarray(tris, np.float32)
+    rays = np.ascontiguousarray(rays, np.float32)
+    tmax = np.ascontiguousarray(tmax, np.float32)
+    t = np.empty(rays.shape[0])
+    lib().orc_closest_brute(tris.shape[0], _p(tris), rays.shape[0], _p(rays), _p(tmax), _p(t), nthreads)
+    return t
+
+
 class BVH:
     def __init__(self, tris):
         self.tris = np.ascontiguousarray(tris, np.float32)
@@ -394,6 +464,13 @@ class BVH:
         vis = np.empty(rays.shape[0], np.uint8)
         lib().orc_anyhit_bvh(self.h, rays.shape[0], _p(rays), _p(tmax), _p(vis), nthreads)
         return vis
+
+    def closest(self, rays, tmax, nthreads: int = 0) -> np.ndarray:
+        rays = np.ascontiguousarray(rays, np.float32)
+        tmax = np.ascontiguousarray(tmax, np.float32)
+        t = np.empty(rays.shape[0])
+        lib().orc_closest_bvh(self.h, rays.shape[0], _p(rays), _p(tmax), _p(t), nthreads)
+        return t
 
     def __del__(self):
         if getattr(self, "h", None):

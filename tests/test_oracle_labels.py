@@ -75,3 +75,45 @@ def test_visible_when_no_triangles():
     empty = np.zeros((0, 3, 3), np.float32)
     assert (O.anyhit_brute(empty, w["rays"], w["tmax"]) == 1).all()
     assert (O.BVH(empty).anyhit(w["rays"], w["tmax"]) == 1).all()
+
+
+# ---- closest hit (primary rays: the depth the network can encode, Sec. 7) ----
+
+def test_closest_hit_hand_cases():
+    near = np.array([[-1, -1, 1, 2, -1, 1, -1, 2, 1]], np.float32)   # plane z = 1
+    far = np.array([[-1, -1, 3, 2, -1, 3, -1, 2, 3]], np.float32)    # plane z = 3
+    tris = np.concatenate([far, near])
+    rays = np.array([[0.2, 0.1, -2, 0, 0, 1],      # both planes: nearest at t = 3
+                     [0.2, 0.1, -2, 0, 0, 2],      # t in units of d: 1.5
+                     [0.2, 0.1, -2, 0, 0, 1],      # t_max = 3 exactly: the near hit is excluded (strict)
+                     [0.2, 0.1, 2, 0, 0, 1],       # between the planes, looking up: t = 1
+                     [0.2, 0.1, 2, 0, 0, -1],      # looking down: t = 1 (double-sided)
+                     [5.0, 5.0, -2, 0, 0, 1]],     # misses both
+                    np.float32)
+    tmax = np.array([np.inf, np.inf, 3.0, np.inf, np.inf, np.inf], np.float32)
+    t = O.closest_brute(tris, rays, tmax, nthreads=1)
+    np.testing.assert_array_equal(t, [3.0, 1.5, np.inf, 1.0, 1.0, np.inf])
+    np.testing.assert_array_equal(O.BVH(tris).closest(rays, tmax, nthreads=1), t)
+
+
+def test_closest_bvh_equals_brute_force_and_agrees_with_any_hit():
+    g = np.random.default_rng(7)
+    for trial in range(100):
+        T = int(g.integers(1, 200))
+        tris = S.random_triangles(T, g)
+        box = S.mesh_aabb(tris)
+        rays, tmax = S.rays_sphere_to_box(300, box, g)
+        tmax = np.where(g.uniform(size=300) < 0.3, g.uniform(0.5, 4.0, 300), tmax).astype(np.float32)
+        tb = O.closest_brute(tris, rays, tmax, nthreads=1)
+        np.testing.assert_array_equal(O.BVH(tris).closest(rays, tmax, nthreads=1), tb)
+        # a closest hit exists iff the any-hit test reports an occluder, and it lies in (0, t_max)
+        vis = O.anyhit_brute(tris, rays, tmax, nthreads=1)
+        np.testing.assert_array_equal(np.isfinite(tb), vis == 0)
+        hit = np.isfinite(tb)
+        assert (tb[hit] > 0).all() and (tb[hit] < tmax[hit]).all()
+        # and it is the smallest of the individual hit distances
+        k = int(np.nonzero(hit)[0][0]) if hit.any() else None
+        if k is not None:
+            ts = [O.ray_tri_t(rays[k, :3].astype(np.float64), rays[k, 3:].astype(np.float64), float(tmax[k]), tr)
+                  for tr in tris]
+            assert tb[k] == min(x for x in ts if x is not None)

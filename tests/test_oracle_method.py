@@ -547,3 +547,62 @@ def test_adam_first_step_closed_form_and_lazy():
     th2, m2, v2 = O.adam_step(th, m, v, np.array([0.0, 0.0, 0.0, 0.0]), step=2, lr=1e-2, beta1=0.9, beta2=0.99,
                               eps=1e-15, lazy=False)
     assert (m2 == 0.9 * m).all()
+
+
+# ---- depth output for primary rays (Sec. 7) ----
+
+def test_depth_target_closed_form():
+    """Axis-aligned rays through the unit box with the hit plane z = 0.3: the
+    segment is [t_a, t_b] = [2, 3] for an origin at z = -2 looking up z, so the
+    normalised depth of the hit at t = 2.3 is 0.3; a miss of the box has no
+    target, nor a ray without a hit."""
+    sh = S.TINY
+    m = O.Model(sh, UNIT_BOX, zero_mlp(sh), coord_mode=1)
+    rays = np.array([[0.5, 0.5, -2, 0, 0, 1], [0.5, 0.5, -2, 0, 0, 2], [3, 3, -2, 0, 0, 1], [0.5, 0.5, -2, 0, 0, 1]],
+                    np.float32)
+    ids = np.zeros(4, np.int32)
+    tmax = np.full(4, np.inf, np.float32)
+    ta, tb = m.segment(rays, ids, tmax)
+    np.testing.assert_array_equal(ta[:2], [2.0, 1.0])
+    np.testing.assert_array_equal(tb[:2], [3.0, 1.5])
+    assert np.isinf(ta[2]) and np.isinf(tb[2])
+    s = m.depth_targets(rays, ids, tmax, np.array([2.3, 1.15, 5.0, np.inf]))
+    np.testing.assert_allclose(s[:2], [0.3, 0.3], rtol=1e-12)
+    assert np.isnan(s[2]) and np.isnan(s[3])
+    # zero weights: y = 1/2, so the predicted depth is the segment's midpoint
+    np.testing.assert_allclose(m.depth(rays[:2], ids[:2], tmax[:2]), [2.5, 1.25], rtol=1e-12)
+
+
+def test_depth_loss_gradient_matches_finite_differences():
+    """L2 depth loss of the oracle: d/dtheta of (1/B) sum (y - s)^2 by central
+    differences (MLP weights and latents), targets from the exact closest hit."""
+    sh = S.TINY
+    wl = S.tiny_workload(n_rays=256)
+    t_hit = O.closest_brute(wl["tris"], wl["rays"], wl["tmax"])
+    g0 = O.init_grid(seed=8, obj=0, amp=0.5, grid_dtype="f32", count=O.Model(sh, UNIT_BOX, zero_mlp(sh)).grid_elems)
+    W = S.xavier_mlp(sh, S.rng(79, 3)).astype(np.float64) * 2.0
+
+    def loss_of(Wv, g):
+        return O.Model(sh, wl["aabb"], Wv[None, :], grids=[g], coord_mode=1).depth_loss_backward(
+            wl["rays"], wl["ids"], wl["tmax"], t_hit)[0]
+
+    m = O.Model(sh, wl["aabb"], W[None, :], grids=[g0], coord_mode=1)
+    loss, B, gW, gx = m.depth_loss_backward(wl["rays"], wl["ids"], wl["tmax"], t_hit)
+    assert 50 < B < 256 and loss > 0
+    rng = np.random.default_rng(11)
+    for k in rng.choice(sh.mlp_params, 20, replace=False):
+        h = 1e-6 * max(1.0, abs(W[k]))
+        Wp, Wm = W.copy(), W.copy()
+        Wp[k] += h
+        Wm[k] -= h
+        fd = (loss_of(Wp, g0) - loss_of(Wm, g0)) / (2 * h)
+        assert abs(fd - gW[0, k]) <= 1e-6 * max(1e-3, abs(gW[0, k])) + 1e-9, (k, fd, gW[0, k])
+    gg = m.grid_grad_dense(0, wl["rays"], wl["ids"], wl["tmax"], gx)
+    g64 = g0.astype(np.float64)
+    for k in rng.choice(np.nonzero(gg)[0], 10, replace=False):
+        gp, gm = g64.copy(), g64.copy()
+        gp[k] += 2.0 ** -14
+        gm[k] -= 2.0 ** -14
+        fd = (loss_of(W, gp.astype(np.float32)) - loss_of(W, gm.astype(np.float32))) / (
+            gp.astype(np.float32)[k] - gm.astype(np.float32)[k])
+        assert abs(fd - gg[k]) <= 1e-5 * abs(gg[k]) + 1e-10, (k, fd, gg[k])
