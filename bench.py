@@ -180,6 +180,69 @@ def train_and_compare(ctx, w, rays, ids, tmax, y):
             "misclassification": {"untrained_f32": mis_untrained, "trained": mis, "added_vs_f32": added}}
 
 
+def sampling_comparison():
+    """Training rays drawn by light importance sampling according to radiant
+    flux (Sec. 5 "Training": tabled CDF, bisection) against uniform sampling of
+    the same emitter (Sec. 6 "Comparison of Sampling Method").  Frame scene
+    (the 1M-triangle mesh, its box, MLP 48-64x4-1), an emitter of 288
+    triangles over a 3 x 3 square at height 5 with log-normal radiance.  Test
+    rays: the frame's 2,073,600 ground points, one light sample each drawn by
+    importance sampling, as a renderer draws them; exact labels from the GPU
+    BVH.  Each sampler trains a fresh model (same initial latents and weights)
+    for TRAIN_STEPS steps of 262,144 rays from uniform ground points, light
+    points from nif_light_sample (importance: flux CDF; uniform: the same
+    triangles with equal radiance, so uniform over the emitter's area), labels
+    from the BVH.  Reported: misclassification of the test rays and the PSNR
+    of the 1920 x 1080 visibility mask (one binary sample per pixel, so MSE is
+    the misclassified fraction)."""
+    import torch
+    from paper_2306_07191_amd import nif, synth as S
+    w = S.frame_workload(with_mesh=True, n_rays=1)
+    sh = w["shape"]
+    bvh = nif.BVH(w["tris"])
+    tris, rad = S.frame_emitter()
+    lights = {"importance": nif.Light(tris, rad), "uniform": nif.Light(tris, np.ones_like(rad))}
+    n = 1920 * 1080
+    g = S.rng(S.CFG_TRAIN, 6, 2)
+    pts = torch.from_numpy(S.ground_points(n, g)).cuda()
+    u = torch.from_numpy(g.uniform(size=(n, 3)).astype(np.float32)).cuda()
+    test_rays, test_tmax, _, _ = lights["importance"].sample(pts, u, want_pdf=False, want_tri=False)
+    test_lab = bvh.anyhit(test_rays, test_tmax).cpu().numpy()
+    ids = torch.zeros(n, dtype=torch.int32, device="cuda")
+    nb = 262144
+    tid = torch.zeros(nb, dtype=torch.int32, device="cuda")
+    res = {"test_occluded_fraction": float(1 - test_lab.mean())}
+    for name, light in lights.items():
+        ctx = nif.Context(sh)
+        ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+        ctx.set_mlp(0, torch.from_numpy(w["mlps"][0]).cuda())
+        ctx.set_object(0, w["aabb"][0], ctx.alloc_grid(), 0)
+        ctx.init_grid(0, GRID_SEED, 1e-4)
+        ctx.prepare("f32")
+        ctx.setup_training()
+        tws = torch.empty(max(1, ctx.workspace_bytes(nb, 1)), dtype=torch.uint8, device="cuda")
+        losses = torch.zeros(TRAIN_STEPS, device="cuda")
+        gs = S.rng(S.CFG_TRAIN, 6, 3)  # the same training points and random numbers for both samplers
+        for s_ in range(TRAIN_STEPS):
+            p_ = torch.from_numpy(S.ground_points(nb, gs)).cuda()
+            u_ = torch.from_numpy(gs.uniform(size=(nb, 3)).astype(np.float32)).cuda()
+            r_, t_, _, _ = light.sample(p_, u_, want_pdf=False, want_tri=False)
+            l_ = bvh.anyhit(r_, t_)
+            ctx.train_step(r_, tid, t_, l_, step=s_ + 1, loss=losses[s_:s_ + 1], ws=tws)
+        ctx.prepare("f32")
+        y = ctx.query(test_rays, ids, test_tmax, dtype="f32").cpu().numpy()
+        mis = float(((y >= 0.5) != (test_lab == 1)).mean())
+        res[name] = {"misclassification": mis, "mask_psnr_db": 10 * math.log10(1.0 / mis) if mis > 0 else None,
+                     "loss_first": float(losses[0].item()), "loss_last": float(losses[-1].item())}
+        log(f"sampling comparison, {name}: misclassification {100 * mis:.3f} % of {n} importance-sampled test "
+            f"rays, loss {res[name]['loss_first']:.4f} -> {res[name]['loss_last']:.4f}")
+        ctx.close()
+    for l_ in lights.values():
+        l_.close()
+    bvh.close()
+    return res
+
+
 def run_batched(args):
     """Batched uneven multi-object workload: 32 objects (UV spheres with
     log-uniform triangle counts in [1e3, 2e6]), each with its own binary16 grids
@@ -1069,6 +1132,7 @@ def run_frame(args):
     train = None
     if not args.quick:
         train = train_and_compare(ctx, w, rays, ids, tmax, y)
+    sampling = None if args.quick else sampling_comparison()
 
     out = {
         "metric": "shadow-ray visibility queries/sec at stated error vs FP64 oracle",
@@ -1093,6 +1157,7 @@ def run_frame(args):
         "stages": stages,
         "error_vs_oracle_on_cpu_sample": errs,
         "train_and_labels": train,
+        "sampling_comparison": sampling,
         "wall_s_timed_region": wall,
         "image_build_ms": image_ms,
         "image_build_note": "nif_prepare rebuilds the z-y-pair query image of the 2.1 GB grid (and packs the "

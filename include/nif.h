@@ -107,8 +107,12 @@ nif_status nif_set_fp8_scales(nif_ctx* ctx, int32_t mlp, const float* scales);
  * whose AABB a shadow ray meets; each such (ray, object) pair is one query; a
  * ray is visible iff all its pairs are, and a ray with no pair is visible).
  * nif_expand_pairs: for n_rays rays (dev, n x 6 floats) with t_max (dev),
- *   tests every registered object's AABB with the query's binary32 segment
- *   rule and writes the pairs in ray order, objects ascending: pair_rays (dev,
+ *   traverses a two-level box tree over the registered objects' AABBs (built
+ *   by nif_prepare; 64-wide nodes, one wavefront per node, culled by the
+ *   bounds of 64 consecutive rays, so rays given in a coherent order such as
+ *   pixel order traverse fastest), decides every candidate box with the
+ *   query's binary32 segment rule, and writes the pairs in ray order, objects
+ *   ascending (the same pairs as testing every box for every ray): pair_rays (dev,
  *   max_pairs x 6 floats, a copy of the ray), pair_tmax, pair_ids (object),
  *   pair_ray (source ray index).  *pair_count (dev, int64) receives the number
  *   of pairs, also when it exceeds max_pairs (then only the first max_pairs
@@ -176,8 +180,11 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * caller's: nif_image_bytes gives the size of one object's image for the
  * current mode, nif_set_image registers one per object, and nif_prepare
  * (re)builds them from the grids.  Changing the mode forgets the registered
- * buffers.  Outputs are bit-identical in every mode. */
-enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2 };
+ * buffers.  NIF_OPT_WINDOW_SORT: whether ordering (nif_query, nif_order,
+ * nif_order_packed) also sorts each 4,096-query window by the finer key:
+ * 0 never, 1 always, 2 (default) when NIF_OPT_GRID_IMAGE is 0.  Outputs are
+ * bit-identical in every mode. */
+enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2, NIF_OPT_WINDOW_SORT = 3 };
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 
 /* Query images (NIF_OPT_GRID_IMAGE 1 or 2): nif_image_bytes is the size in
@@ -334,7 +341,9 @@ size_t nif_touched_bytes(const nif_ctx* ctx);
  *   Loss: binary cross-entropy on the logit, mean over the B queries that take
  *   part; gradients dL/dz = (sigmoid(z) - label) / B, back-propagated through
  *   the ReLU MLP (binary32 MFMA) and into the grids: every interpolation corner
- *   of every lookup receives corner weight x feature gradient (binary32 atomics).
+ *   of every lookup receives corner weight x feature gradient (binary32; the
+ *   coarse levels' contributions are summed per block on chip first, so the
+ *   order of the additions varies from run to run).
  *   adam != NULL: bias-corrected Adam step number `step` (1-based) on every MLP
  *   weight and on every latent whose gradient is non-zero this step (the others
  *   keep latent and moments); latents are updated in binary32 and rounded to
@@ -349,6 +358,27 @@ size_t nif_touched_bytes(const nif_ctx* ctx);
 nif_status nif_train_step(nif_ctx* ctx, int32_t mlp, const float* rays, const int32_t* object_ids, const float* t_max,
                           const uint8_t* labels, int64_t n, int32_t step, const nif_adam* adam, float* loss,
                           float* mlp_grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Depth output for primary rays (Sec. 7: besides visibility, the network can
+ * encode other information about the first hit, such as its depth).  A
+ * context trained with nif_train_step_depth reads its visibility output y as
+ * the normalised position of the closest hit in the query's segment.
+ * nif_train_step_depth: as nif_train_step with the closest-hit distance
+ *   t_hit (dev, n floats, +inf for no hit, as from nif_bvh_closest) instead of
+ *   labels.  A query takes part when it meets its AABB, t_hit is finite and the
+ *   segment [t_a, t_b] has t_b > t_a; its target is s = (t_hit - t_a) /
+ *   (t_b - t_a) clamped to [0, 1] (binary32), and the loss is the mean of
+ *   (y - s)^2 over the B queries that take part (L2, as the paper trains,
+ *   Sec. 5 "Training"): dL/dz = 2 (y - s) y (1 - y) / B.  Everything else
+ *   (gradients, Adam, buffers, workspace) as nif_train_step.
+ * nif_depth_from_visibility: depth (dev, n floats) = t_a + y (t_b - t_a) for
+ *   the visibilities y (dev, n) of nif_query on the same queries; +inf for a
+ *   query that misses its AABB, NaN for an invalid one.  Needs nif_prepare. */
+nif_status nif_train_step_depth(nif_ctx* ctx, int32_t mlp, const float* rays, const int32_t* object_ids,
+                                const float* t_max, const float* t_hit, int64_t n, int32_t step, const nif_adam* adam,
+                                float* loss, float* mlp_grad, void* ws, size_t ws_bytes, void* stream);
+nif_status nif_depth_from_visibility(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max,
+                                     const float* visibility, int64_t n, float* depth, void* stream);
 
 /* Backward pass of a binary32 query for a given upstream gradient, so that the
  * query can sit inside a larger differentiable program (the gradients the
@@ -472,13 +502,18 @@ nif_status nif_light_sample(const nif_light* light, const float* points, const f
  * nif_bvh_anyhit: visible[i] (dev, n bytes) = 1 iff no triangle is hit at a
  *   distance t with 0 < t < t_max[i] along rays[i] (dev, n x 6 floats);
  *   binary32 watertight triangle test (Woop, Benthin, Wald, JCGT 2013),
- *   double-sided. */
+ *   double-sided.
+ * nif_bvh_closest: t_hit[i] (dev, n floats) = the smallest such t (binary32
+ *   T / det of the same test), +inf when there is none: the depth of primary
+ *   rays, the targets of nif_train_step_depth. */
 typedef struct nif_bvh nif_bvh;
 nif_status nif_bvh_create(const float* tris, int64_t num_tris, nif_bvh** out);
 void nif_bvh_destroy(nif_bvh* bvh);
 int64_t nif_bvh_num_nodes(const nif_bvh* bvh);
 nif_status nif_bvh_anyhit(const nif_bvh* bvh, const float* rays, const float* t_max, int64_t n, uint8_t* visible,
                           void* stream);
+nif_status nif_bvh_closest(const nif_bvh* bvh, const float* rays, const float* t_max, int64_t n, float* t_hit,
+                           void* stream);
 
 /* Thread-local text of the last error (empty after success). */
 const char* nif_last_error(void);

@@ -67,6 +67,7 @@ struct nif_ctx {
     int num_cus = 256;
     int device = 0;
     int32_t order_mode = 2;  // NIF_ORDER_AUTO
+    int32_t window_sort = 2;  // NIF_OPT_WINDOW_SORT: 2 = when there is no query image
     std::vector<float*> mlp_m, mlp_v;  // Adam moments per MLP
     // device tables of per-object training pointers: grad, m, v, touched, grid
     void** d_train_tab = nullptr;
@@ -82,59 +83,92 @@ struct nif_ctx {
     // object table, option changes); a plan refuses to launch once it differs
     uint64_t epoch = 1;
     uint32_t* d_flags = nullptr;  // domain-error bits of queries (nif_get_error_flags)
-    BoxGroup* d_groups = nullptr;  // box groups for the pair expansion (16..64 objects)
-    int32_t num_groups = 0;
+    uint8_t* d_tree = nullptr;  // box tree of the pair expansion (cluster boxes, member boxes, member ids)
+    PairTree tree{};
 };
 
-// Groups of up to 8 objects consecutive in the Morton order of their box
-// centres (10 bits per axis over the scene bounds), for 16 to 64 objects.
-static std::vector<BoxGroup> build_groups(const std::vector<ObjDev>& od) {
-    std::vector<BoxGroup> g;
+// Host side of the pair expansion's box tree (see PairTree): the flat layout
+// of its boxes and ids, and its root box.
+struct PairTreeHost {
+    std::vector<float> cbox, mbox;
+    std::vector<int32_t> mid;
+    int32_t C = 0;
+    float root[6];
+};
+
+static PairTreeHost build_pair_tree(const std::vector<ObjDev>& od) {
+    PairTreeHost t;
     const int K = (int)od.size();
-    if (K < 16 || K > 64) return g;
-    float slo[3], shi[3];
     for (int a = 0; a < 3; ++a) {
-        slo[a] = INFINITY;
-        shi[a] = -INFINITY;
+        t.root[a] = INFINITY;
+        t.root[3 + a] = -INFINITY;
         for (const ObjDev& o : od) {
-            slo[a] = fminf(slo[a], 0.5f * (o.lo[a] + o.hi[a]));
-            shi[a] = fmaxf(shi[a], 0.5f * (o.lo[a] + o.hi[a]));
+            t.root[a] = fminf(t.root[a], o.lo[a]);
+            t.root[3 + a] = fmaxf(t.root[3 + a], o.hi[a]);
         }
     }
-    auto spread = [](uint64_t v) {
-        uint64_t r = 0;
-        for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1ull) << (3 * b);
-        return r;
-    };
-    std::vector<std::pair<uint64_t, int>> key(K);
-    for (int k = 0; k < K; ++k) {
-        uint64_t m = 0;
+    std::vector<int> order(K);
+    for (int k = 0; k < K; ++k) order[k] = k;
+    if (K > 64) {  // clusters: runs of 64 in the Morton order of the box centres (10 bits per axis)
+        float slo[3], shi[3];
         for (int a = 0; a < 3; ++a) {
-            const float ext = shi[a] - slo[a];
-            const float u = ext > 0.0f ? (0.5f * (od[k].lo[a] + od[k].hi[a]) - slo[a]) / ext : 0.0f;
-            const uint64_t q = (uint64_t)fminf(fmaxf(u * 1023.0f, 0.0f), 1023.0f);
-            m |= spread(q) << a;
-        }
-        key[k] = {m, k};
-    }
-    std::sort(key.begin(), key.end());
-    for (int i = 0; i < K; i += 8) {
-        BoxGroup b{};
-        for (int a = 0; a < 3; ++a) {
-            b.lo[a] = INFINITY;
-            b.hi[a] = -INFINITY;
-        }
-        for (int j = i; j < i + 8 && j < K; ++j) {
-            const ObjDev& o = od[key[j].second];
-            for (int a = 0; a < 3; ++a) {
-                b.lo[a] = fminf(b.lo[a], o.lo[a]);
-                b.hi[a] = fmaxf(b.hi[a], o.hi[a]);
+            slo[a] = INFINITY;
+            shi[a] = -INFINITY;
+            for (const ObjDev& o : od) {
+                slo[a] = fminf(slo[a], 0.5f * (o.lo[a] + o.hi[a]));
+                shi[a] = fmaxf(shi[a], 0.5f * (o.lo[a] + o.hi[a]));
             }
-            b.members |= 1ull << key[j].second;
         }
-        g.push_back(b);
+        auto spread = [](uint64_t v) {
+            uint64_t r = 0;
+            for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+            return r;
+        };
+        std::vector<std::pair<uint64_t, int>> key(K);
+        for (int k = 0; k < K; ++k) {
+            uint64_t m = 0;
+            for (int a = 0; a < 3; ++a) {
+                const float ext = shi[a] - slo[a];
+                const float u = ext > 0.0f ? (0.5f * (od[k].lo[a] + od[k].hi[a]) - slo[a]) / ext : 0.0f;
+                const uint64_t q = (uint64_t)fminf(fmaxf(u * 1023.0f, 0.0f), 1023.0f);
+                m |= spread(q) << a;
+            }
+            key[k] = {m, k};
+        }
+        std::sort(key.begin(), key.end());
+        for (int k = 0; k < K; ++k) order[k] = key[k].second;
     }
-    return g;
+    t.C = (K + 63) / 64;
+    t.mbox.assign((size_t)t.C * 64 * 6, 0.0f);
+    t.mid.assign((size_t)t.C * 64, -1);
+    t.cbox.assign((size_t)t.C * 6, 0.0f);
+    for (int c = 0; c < t.C; ++c) {
+        float* cb = &t.cbox[(size_t)c * 6];
+        for (int a = 0; a < 3; ++a) {
+            cb[a] = INFINITY;
+            cb[3 + a] = -INFINITY;
+        }
+        for (int j = 0; j < 64; ++j) {
+            const int i = c * 64 + j;
+            float* mb = &t.mbox[(size_t)i * 6];
+            if (i >= K) {
+                for (int a = 0; a < 3; ++a) {
+                    mb[a] = INFINITY;
+                    mb[3 + a] = -INFINITY;
+                }
+                continue;
+            }
+            const ObjDev& o = od[order[i]];
+            t.mid[i] = order[i];
+            for (int a = 0; a < 3; ++a) {
+                mb[a] = o.lo[a];
+                mb[3 + a] = o.hi[a];
+                cb[a] = fminf(cb[a], o.lo[a]);
+                cb[3 + a] = fmaxf(cb[3 + a], o.hi[a]);
+            }
+        }
+    }
+    return t;
 }
 
 static void drop_images(nif_ctx* c) {
@@ -148,6 +182,11 @@ static int64_t image_elems(const nif_ctx* c, int32_t mode) {
     int64_t o = 0;
     for (int k = 0; k < 3 * c->d.levels; ++k) o += image_table_elems(c->res[k % c->d.levels], mode);
     return o;
+}
+
+// Whether the ordering also sorts every 4,096-query window by the fine key.
+static bool window_sorted(const nif_ctx* c) {
+    return c->window_sort == 2 ? c->image_mode == 0 : c->window_sort == 1;
 }
 
 static bool uses_order(const nif_ctx* c, int64_t n) {
@@ -231,7 +270,7 @@ extern "C" void nif_destroy(nif_ctx* c) {
     if (c->d_train_fwd) (void)hipFree(c->d_train_fwd);
     if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
     if (c->d_flags) (void)hipFree(c->d_flags);
-    if (c->d_groups) (void)hipFree(c->d_groups);
+    if (c->d_tree) (void)hipFree(c->d_tree);
     delete c;
 }
 
@@ -344,12 +383,19 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
     }
     if (!c->d_objs) HIP_TRY(hipMalloc(&c->d_objs, sizeof(ObjDev) * c->K));
     HIP_TRY(hipMemcpy(c->d_objs, od.data(), sizeof(ObjDev) * c->K, hipMemcpyHostToDevice));
-    const std::vector<BoxGroup> groups = build_groups(od);
-    if (!groups.empty()) {
-        if (!c->d_groups) HIP_TRY(hipMalloc(&c->d_groups, sizeof(BoxGroup) * 8));
-        HIP_TRY(hipMemcpy(c->d_groups, groups.data(), sizeof(BoxGroup) * groups.size(), hipMemcpyHostToDevice));
+    {  // the pair expansion's box tree: cluster boxes, member boxes, member ids, one buffer
+        const PairTreeHost t = build_pair_tree(od);
+        const size_t nc = t.cbox.size() * 4, nm = t.mbox.size() * 4, ni = t.mid.size() * 4;
+        if (!c->d_tree) HIP_TRY(hipMalloc(&c->d_tree, nc + nm + ni));
+        HIP_TRY(hipMemcpy(c->d_tree, t.cbox.data(), nc, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_tree + nc, t.mbox.data(), nm, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_tree + nc + nm, t.mid.data(), ni, hipMemcpyHostToDevice));
+        c->tree.cbox = reinterpret_cast<const float*>(c->d_tree);
+        c->tree.mbox = reinterpret_cast<const float*>(c->d_tree + nc);
+        c->tree.mid = reinterpret_cast<const int32_t*>(c->d_tree + nc + nm);
+        c->tree.C = t.C;
+        for (int a = 0; a < 6; ++a) c->tree.root[a] = t.root[a];
     }
-    c->num_groups = (int32_t)groups.size();
     // weights, packed on the device from the binary32 masters
     const int flav = dtype;
     const PackInfo& P = c->pack[flav];
@@ -394,6 +440,10 @@ extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) 
     case NIF_OPT_ORDER:
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_ORDER takes 0, 1 or 2");
         c->order_mode = (int32_t)value;
+        return ok();
+    case NIF_OPT_WINDOW_SORT:
+        if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_WINDOW_SORT takes 0, 1 or 2");
+        c->window_sort = (int32_t)value;
         return ok();
     case NIF_OPT_GRID_IMAGE:
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_GRID_IMAGE takes 0, 1 or 2");
@@ -498,7 +548,7 @@ static nif_status query_in(nif_ctx* c, int32_t dtype, const float* rays, const i
     float4* qrec = nullptr;
     if (need > 0) {
         qrec = records_in(c, ws, n);
-        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, !c->image_mode, qrec);
+        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, window_sorted(c), qrec);
         if (st != NIF_OK) return st;
     }
     return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec);
@@ -573,7 +623,7 @@ extern "C" nif_status nif_order(nif_ctx* c, const float* rays, const int32_t* id
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
     const uint32_t* p = nullptr;
-    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, !c->image_mode);
+    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, window_sorted(c));
 }
 
 extern "C" nif_status nif_order_packed(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax,
@@ -588,7 +638,7 @@ extern "C" nif_status nif_order_packed(nif_ctx* c, const float* rays, const int3
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
     const uint32_t* p = nullptr;
-    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, !c->image_mode,
+    return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, window_sorted(c),
                      reinterpret_cast<float4*>(packed));
 }
 
@@ -678,11 +728,11 @@ extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const floa
     // per-ray counts and their scan are 32-bit: the total must stay below 2^32
     if ((uint64_t)n_rays * (uint64_t)c->K >= ((uint64_t)1 << 32))
         return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: n_rays x num_objects must be below 2^32");
-    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    if (!c->d_objs || !c->d_tree) return fail(NIF_ERR_STATE, "context not prepared");
     const size_t need = pairs_workspace_bytes(n_rays, c->K);
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
-    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->d_objs, c->K, c->d_groups, c->num_groups, max_pairs, pair_rays, pair_tmax, pair_ids,
-                                pair_ray, pair_count, ws, (hipStream_t)stream));
+    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->tree, c->K, c->num_cus, max_pairs, pair_rays, pair_tmax,
+                                pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream));
     return ok();
 }
 
@@ -823,7 +873,7 @@ static size_t train_bytes(const nif_ctx* c, int64_t n) {
 static nif_status train_common(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids, const float* tmax,
                                const uint8_t* labels, const float* grad_y, int64_t n, int32_t step,
                                const nif_adam* adam, float* loss, float* mlp_grad, void* ws, size_t ws_bytes,
-                               void* stream) {
+                               void* stream, const float* t_hit = nullptr) {
     nif_status st = NIF_OK;
     if (mlp < 0 || mlp >= c->M) return fail(NIF_ERR_INVALID_ARG, "mlp %d out of range", mlp);
     if (adam && step < 1) return fail(NIF_ERR_INVALID_ARG, "step must be >= 1");
@@ -877,6 +927,7 @@ static nif_status train_common(nif_ctx* c, int32_t mlp, const float* rays, const
     A.tmax = tmax;
     A.labels = labels;
     A.grad_y = grad_y;
+    A.t_hit = t_hit;
     A.n = n;
     A.objs = c->d_objs;
     A.num_objects = K;
@@ -923,6 +974,27 @@ extern "C" nif_status nif_train_step(nif_ctx* c, int32_t mlp, const float* rays,
     if (st != NIF_OK) return st;
     return train_common(c, mlp, rays, ids, tmax, labels, nullptr, n, step, adam, loss, mlp_grad, ws, ws_bytes,
                         stream);
+}
+
+extern "C" nif_status nif_train_step_depth(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,
+                                           const float* tmax, const float* t_hit, int64_t n, int32_t step,
+                                           const nif_adam* adam, float* loss, float* mlp_grad, void* ws,
+                                           size_t ws_bytes, void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, t_hit, "nif_train_step_depth");
+    if (st != NIF_OK) return st;
+    return train_common(c, mlp, rays, ids, tmax, nullptr, nullptr, n, step, adam, loss, mlp_grad, ws, ws_bytes,
+                        stream, t_hit);
+}
+
+extern "C" nif_status nif_depth_from_visibility(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax,
+                                                const float* visibility, int64_t n, float* depth, void* stream) {
+    nif_status st = check_query_args(c, 0, rays, ids, tmax, n, visibility, "nif_depth_from_visibility");
+    if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
+    if (!depth) return fail(NIF_ERR_INVALID_ARG, "nif_depth_from_visibility: NULL depth");
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    HIP_TRY(launch_depth_from_visibility(rays, ids, tmax, visibility, n, c->d_objs, c->K, depth, c->num_cus,
+                                         (hipStream_t)stream));
+    return ok();
 }
 
 extern "C" nif_status nif_backward(nif_ctx* c, int32_t mlp, const float* rays, const int32_t* ids,

@@ -1,12 +1,14 @@
-// Plain BVH any-hit ray casting on the GPU: exact shadow-ray labels for
-// training (Sec. 4.2 trains on ray-object intersection results) and the
-// baseline the paper compares NIF against (Sec. 6 "Performance Evaluation":
-// BVH ray casting of the same shadow rays).
+// Plain BVH ray casting on the GPU: exact shadow-ray labels for training
+// (Sec. 4.2 trains on ray-object intersection results), the baseline the
+// paper compares NIF against (Sec. 6 "Performance Evaluation": BVH ray casting
+// of the same shadow rays), and closest-hit distances, the depth targets of
+// primary rays (Sec. 7).
 //
 // Builder (host): binned surface-area heuristic, 16 bins on the axis of
 // largest centroid extent, leaves of at most 4 triangles, depth-first node
 // order.  Traversal (device): one ray per thread, explicit stack, nearer
-// child first, early exit on the first hit with 0 < t < t_max.
+// child first; any-hit exits on the first hit with 0 < t < t_max, closest-hit
+// keeps the nearest and skips boxes beyond it.
 // Ray/triangle test: the watertight algorithm of Woop, Benthin and Wald
 // (JCGT 2013) in binary32, double-sided.
 #include <math.h>
@@ -148,7 +150,7 @@ static void build_bvh(const float* tris, int64_t T, std::vector<BNode>& nodes, s
 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool tri_hit(const float* v, const float o[3], const float d[3], int kx, int ky, int kz,
-                                        float Sx, float Sy, float Sz, float tmax) {
+                                        float Sx, float Sy, float Sz, float tmax, float* t_out = nullptr) {
     const float Ax = v[0 + kx] - o[kx], Ay = v[0 + ky] - o[ky], Az0 = v[0 + kz] - o[kz];
     const float Bx = v[3 + kx] - o[kx], By = v[3 + ky] - o[ky], Bz0 = v[3 + kz] - o[kz];
     const float Cx = v[6 + kx] - o[kx], Cy = v[6 + ky] - o[ky], Cz0 = v[6 + kz] - o[kz];
@@ -169,12 +171,18 @@ __device__ __forceinline__ bool tri_hit(const float* v, const float o[3], const 
     float T = U * (Sz * Az0) + V * (Sz * Bz0) + W * (Sz * Cz0);
     if (det < 0.0f) { T = -T; det = -det; }
     if (!(T > 0.0f)) return false;
-    return isinf(tmax) || T < tmax * det;
+    if (!(isinf(tmax) || T < tmax * det)) return false;
+    if (t_out) *t_out = T / det;
+    return true;
 }
 
-__global__ __launch_bounds__(256) void bvh_anyhit_kernel(const BNode* __restrict__ nodes, const Tri* __restrict__ tris,
-                                                         const float* __restrict__ rays, const float* __restrict__ tmaxv,
-                                                         int64_t n, uint8_t* __restrict__ vis) {
+// CLOSEST = false: any hit, vis[i] = 0 on the first hit with 0 < t < t_max.
+// CLOSEST = true: the nearest hit, t_hit[i] = its distance (+inf for none);
+// boxes beyond the best hit so far are skipped, nearer child first.
+template <bool CLOSEST>
+__global__ __launch_bounds__(256) void bvh_trace_kernel(const BNode* __restrict__ nodes, const Tri* __restrict__ tris,
+                                                        const float* __restrict__ rays, const float* __restrict__ tmaxv,
+                                                        int64_t n, uint8_t* __restrict__ vis, float* __restrict__ t_hit) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float* r = rays + 6 * i;
         const float o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
@@ -190,10 +198,11 @@ __global__ __launch_bounds__(256) void bvh_anyhit_kernel(const BNode* __restrict
         int sp = 0;
         int32_t node = 0;
         bool hit = false;
+        float best = INFINITY;  // closest hit so far
         // slab test widened by a few ulps so that rounding never drops a box the
         // triangle test would hit
         auto box = [&](const BNode& b, float& tn) {
-            float t0 = 0.0f, t1 = tmax;
+            float t0 = 0.0f, t1 = CLOSEST ? fminf(tmax, best) : tmax;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 float l = (b.lo[a] - o[a]) * inv[a], h = (b.hi[a] - o[a]) * inv[a];
@@ -209,9 +218,15 @@ __global__ __launch_bounds__(256) void bvh_anyhit_kernel(const BNode* __restrict
         while (true) {
             const BNode nd = nodes[node];
             if (nd.b <= 0) {  // leaf (possibly empty); children always have larger indices
-                for (int32_t k = nd.a; k < nd.a - nd.b; ++k)
-                    if (tri_hit(tris[k].v, o, d, kx, ky, kz, Sx, Sy, Sz, tmax)) { hit = true; break; }
-                if (hit || sp == 0) break;
+                for (int32_t k = nd.a; k < nd.a - nd.b; ++k) {
+                    float t;
+                    if (tri_hit(tris[k].v, o, d, kx, ky, kz, Sx, Sy, Sz, tmax, CLOSEST ? &t : nullptr)) {
+                        hit = true;
+                        if (!CLOSEST) break;
+                        best = fminf(best, t);
+                    }
+                }
+                if ((!CLOSEST && hit) || sp == 0) break;
                 node = stack[--sp];
                 continue;
             }
@@ -228,7 +243,8 @@ __global__ __launch_bounds__(256) void bvh_anyhit_kernel(const BNode* __restrict
                 node = stack[--sp];
             }
         }
-        vis[i] = hit ? 0 : 1;
+        if (CLOSEST) t_hit[i] = best;
+        else vis[i] = hit ? 0 : 1;
     }
 }
 
@@ -292,7 +308,19 @@ extern "C" nif_status nif_bvh_anyhit(const nif_bvh* h, const float* rays, const 
     if (!rays || !t_max || !visible) return NIF_ERR_INVALID_ARG;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(bvh_anyhit_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->d_nodes,
-                       h->d_tris, rays, t_max, n, visible);
+    hipLaunchKernelGGL(bvh_trace_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->d_nodes,
+                       h->d_tris, rays, t_max, n, visible, nullptr);
+    return hipGetLastError() == hipSuccess ? NIF_OK : NIF_ERR_HIP;
+}
+
+extern "C" nif_status nif_bvh_closest(const nif_bvh* h, const float* rays, const float* t_max, int64_t n, float* t_hit,
+                                      void* stream) {
+    if (!h || n < 0) return NIF_ERR_INVALID_ARG;
+    if (n == 0) return NIF_OK;
+    if (!rays || !t_max || !t_hit) return NIF_ERR_INVALID_ARG;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(bvh_trace_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->d_nodes,
+                       h->d_tris, rays, t_max, n, nullptr, t_hit);
     return hipGetLastError() == hipSuccess ? NIF_OK : NIF_ERR_HIP;
 }

@@ -34,10 +34,10 @@ __device__ __forceinline__ bool clip_segment(const float o[3], const float d[3],
     return ta <= tb;
 }
 
+// ta, tb receive the segment's ends (also when it is empty).
 __device__ __forceinline__ int clip_normalise(const float o[3], const float d[3], float tmax, const ObjDev& b,
-                                              float u[3][3]) {
+                                              float u[3][3], float& ta, float& tb) {
 #pragma clang fp contract(off)
-    float ta, tb;
     if (!clip_segment(o, d, tmax, b.lo, b.hi, ta, tb)) return 0;
     float len2 = d[0] * d[0];
     len2 = len2 + d[1] * d[1];
@@ -56,6 +56,12 @@ __device__ __forceinline__ int clip_normalise(const float o[3], const float d[3]
         u[2][a] = ud > 0.0f ? (ud < 1.0f ? ud : 1.0f) : 0.0f;
     }
     return 1;
+}
+
+__device__ __forceinline__ int clip_normalise(const float o[3], const float d[3], float tmax, const ObjDev& b,
+                                              float u[3][3]) {
+    float ta, tb;
+    return clip_normalise(o, d, tmax, b, u, ta, tb);
 }
 
 // Entry point only (the ordering key): same segment test and same entry

@@ -181,6 +181,7 @@ struct TrainArgs {
     const float* tmax;
     const uint8_t* labels;
     const float* grad_y;  // upstream dL/dy per query (backward mode) or null
+    const float* t_hit;   // closest-hit distance per query (depth mode: L2 on the normalised depth) or null
     int64_t n;
     const uint32_t* perm;
     const ObjDev* objs;
@@ -255,22 +256,30 @@ int64_t image_table_elems(int32_t N, int kind);
 hipError_t launch_build_image(const void* grid, void* image, const int64_t* toff, const int64_t* ioff,
                               const int32_t* res, int levels, int kind, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
-// Up to 8 objects (of at most 64) whose boxes are near each other, for the
-// pair expansion: the union box and the member set.
-struct BoxGroup {
-    float lo[3], hi[3];
-    uint64_t members;
+// Two-level 64-wide box tree of the pair expansion.  With at most 64 objects
+// one level: slot j of mbox / mid is object j.  Otherwise C <= 64 clusters of
+// up to 64 objects consecutive in the Morton order of their box centres:
+// cbox[c] is cluster c's union box, slots c*64 .. c*64+63 of mbox / mid its
+// members (empty slots: lo = +inf, hi = -inf, id -1).  root: union of all
+// boxes.  Boxes are lo xyz, hi xyz.
+struct PairTree {
+    const float* cbox;
+    const float* mbox;
+    const int32_t* mid;
+    int32_t C;
+    float root[6];
 };
 size_t pairs_workspace_bytes(int64_t n_rays, int32_t K);
-hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const ObjDev* objs, int32_t K,
-                               const BoxGroup* groups, int32_t num_groups, int64_t max_pairs, float* pair_rays,
-                               float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray, int64_t* total, void* ws,
-                               hipStream_t s);
+hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const PairTree& T, int32_t K,
+                               int num_cus, int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
+                               uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s);
+// t = t_a + y (t_b - t_a) of the query's segment; +inf for a miss, NaN for an
+// invalid query.
+hipError_t launch_depth_from_visibility(const float* rays, const int32_t* ids, const float* tmax, const float* vis,
+                                        int64_t n, const ObjDev* objs, int32_t K, float* depth, int num_cus,
+                                        hipStream_t s);
 hipError_t launch_combine_pairs(const uint32_t* pair_ray, const float* vis, int64_t n_pairs, int64_t n_rays,
                                 uint8_t* ray_visible, hipStream_t s);
-// In-place exclusive scan of n <= 16M uint32 (block_sums: scan_block_sums(n) words).
-int64_t scan_block_sums(int64_t n);
-hipError_t launch_exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* block_sums, hipStream_t s);
 hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
                             hipStream_t s);
 

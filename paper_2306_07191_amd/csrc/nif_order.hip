@@ -26,10 +26,6 @@
 
 namespace nif {
 
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;  // elements per scan block
-
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     v &= 0x3ffu;
     v = (v | (v << 16)) & 0x030000FFu;
@@ -289,99 +285,6 @@ __global__ __launch_bounds__(kRefineThreads) void order_refine_kernel(OrderArgs 
         const int i = threadIdx.x * kRefineItems + j;
         if (i < cnt) A.perm[w0 + i] = val[j];
     }
-}
-
-// Sum of the counts of one scan tile.
-__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* hist, int64_t n, uint32_t* sums) {
-    __shared__ uint32_t ws[kScanThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += hist[base + k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < kScanThreads / 64; ++w) t += ws[w];
-        sums[blockIdx.x] = t;
-    }
-}
-
-// Exclusive scan of up to kScanThreads * kScanItems tile sums, one block.
-__global__ __launch_bounds__(kScanThreads) void scan_top_kernel(uint32_t* sums, int64_t n) {
-    __shared__ uint32_t ws[kScanThreads / 64];
-    const int64_t base = threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? sums[base + k] : 0u;
-        s += v[k];
-    }
-    // inclusive scan of per-thread sums across the wave
-    const int lane = threadIdx.x & 63;
-    uint32_t inc = s;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t t = __shfl_up(inc, off);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) ws[threadIdx.x >> 6] = inc;
-    __syncthreads();
-    uint32_t wave_off = 0;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wave_off += ws[w];
-    uint32_t run = wave_off + inc - s;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) sums[base + k] = run;
-        run += v[k];
-    }
-}
-
-// Exclusive scan of one tile in place, offset by the tile's prefix.
-__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t* hist, int64_t n, const uint32_t* sums) {
-    __shared__ uint32_t ws[kScanThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? hist[base + k] : 0u;
-        s += v[k];
-    }
-    const int lane = threadIdx.x & 63;
-    uint32_t inc = s;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t t = __shfl_up(inc, off);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) ws[threadIdx.x >> 6] = inc;
-    __syncthreads();
-    uint32_t wave_off = 0;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wave_off += ws[w];
-    uint32_t run = sums[blockIdx.x] + wave_off + inc - s;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) hist[base + k] = run;
-        run += v[k];
-    }
-}
-
-
-int64_t scan_block_sums(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
-
-hipError_t launch_exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* block_sums, hipStream_t s) {
-    const int64_t tiles = scan_block_sums(n);
-    if (tiles > kScanTile) return hipErrorInvalidValue;  // more than 16M elements
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, data, n, block_sums);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, block_sums, tiles);
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, data, n, block_sums);
-    return hipGetLastError();
 }
 
 int order_bits(int32_t num_objects) {

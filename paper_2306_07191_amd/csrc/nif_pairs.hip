@@ -1,28 +1,54 @@
-// Pair expansion and per-ray combination for scenes of several objects.
+// Top-level stage of a scene: (ray, object) pair expansion and per-ray
+// combination.
 //
-// The method issues one neural query per (ray, object) pair whose segment
-// meets the object's AABB; a ray is visible iff every such pair is visible,
-// and a ray that meets no AABB is visible (Sec. 4.1).  The expansion uses the
-// same binary32 segment test as the query kernel, so a pair is emitted iff the
-// query would not report a miss.
+// The method keeps the top-level traversal over the objects' boxes and issues
+// one neural query per (ray, object) pair whose segment meets the object's
+// AABB, in a separate pass before the network runs (Sec. 4.1); a ray is
+// visible iff every such pair is visible, and a ray that meets no AABB is
+// visible.  The hit rule is the query kernel's binary32 segment test
+// (clip_segment), so a pair is emitted iff the query would not report a miss.
 //
-// Passes: (1) count the pairs of every ray; (2) exclusive scan of the counts;
-// (3) write the pairs in ray order, objects ascending within a ray, and the
-// total.
+// Traversal.  The boxes form a two-level tree whose nodes are 64 wide, the
+// width of a wavefront: level 1 holds up to 64 cluster boxes (or, with at most
+// 64 objects, the object boxes themselves), level 2 the up-to-64 object boxes
+// of each cluster, clusters being runs of 64 objects in the Morton order of
+// their box centres.  A wave takes 64 consecutive rays.  Each lane clips its
+// ray to the root box and bounds the clipped segment by a box with a relative
+// margin; the union of the 64 lane boxes is the wave's bundle.  One node is
+// then one compare per lane (lane j against child j) and a ballot, so the
+// traversal is wave-uniform, with no per-ray stack and no divergence.  Every
+// candidate object the ballots leave is tested by each lane against its own
+// ray: a reciprocal-multiply slab test decides unless the box is grazed within
+// 8 ulp, where the division test decides (see decide_hit).
+//
+// Why the bundle cull never drops a pair: if the binary32 test accepts box k,
+// its interval [ta, tb] lies inside the root interval [T0, T1] computed with
+// the widened reciprocal test (interval endpoints are monotone in the box
+// bounds under rounding, and box k lies inside the root box), and the real
+// point o + ta d lies within 2^-22 (|lo - o| + |hi - o|) of box k on every
+// axis (two roundings in each slab quotient).  The lane box is the segment
+// [T0, T1] with a margin of 2^-18 (|o| + |T0 d| + |T1 d| + |root bounds|) per
+// axis, which covers both roundings and the rounding of the endpoints with
+// room to spare, so box k overlaps the lane box and hence the bundle.
+//
+// Passes: (1) count: the hits of every ray (a 64-bit mask with at most 64
+// objects, else a count) and the total of every 256-ray tile; (2) an
+// exclusive scan of the tile totals in one block, which also writes the pair
+// total; (3) emit: per tile a block scan of the ray counts, then the pairs in
+// ray order, objects ascending within a ray.  The output is the same as a
+// test of every box for every ray.
 #include "nif_device.h"
 #include "nif_internal.h"
 
 namespace nif {
 
-constexpr int kPairThreads = 256;
+constexpr int kPairTile = 256;  // rays per block tile: four waves of 64
+constexpr int kPairScanThreads = 1024;
+constexpr float kUlp8 = 8.0f * 0x1p-24f;
 
-// Conservative rejection before the exact test: slab distances with a
-// reciprocal multiply instead of a division (within 2.5 ulp of the quotient)
-// and the interval widened by 8 ulp on each side, so a box the exact binary32
-// test accepts is never rejected here.  rcp(d) is only used for |d| >= 2^-100.
 struct RayPre {
     float o[3], d[3], inv[3], tm;
-    bool fast;
+    bool fast;  // no direction component with 0 < |d| < 2^-100
 };
 
 __device__ __forceinline__ RayPre ray_pre(const float o[3], const float d[3], float tm) {
@@ -39,89 +65,344 @@ __device__ __forceinline__ RayPre ray_pre(const float o[3], const float d[3], fl
     return r;
 }
 
-__device__ __forceinline__ bool maybe_hit(const RayPre& r, const float lo[3], const float hi[3]) {
+// Slab interval of a box with reciprocal multiplies (each end within 2^-22 of
+// the binary32 quotient), before widening or narrowing.  Returns false when
+// the ray is parallel to an axis and outside the box on it (exactly the
+// division test's rule).
+__device__ __forceinline__ bool slab_fast(const RayPre& r, const float lo[3], const float hi[3], float l[3],
+                                          float h[3], bool con[3]) {
 #pragma clang fp contract(off)
-    if (!r.fast) return true;
-    constexpr float kWiden = 8.0f * 0x1p-24f;
-    float tn = -INFINITY, tf = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (r.d[a] == 0.0f) {
+        con[a] = r.d[a] != 0.0f;
+        l[a] = -INFINITY;
+        h[a] = INFINITY;
+        if (!con[a]) {
             if (r.o[a] < lo[a] || r.o[a] > hi[a]) return false;
             continue;
         }
         const float t0 = (lo[a] - r.o[a]) * r.inv[a];
         const float t1 = (hi[a] - r.o[a]) * r.inv[a];
-        float l = fminf(t0, t1), h = fmaxf(t0, t1);
-        l -= kWiden * fabsf(l);
-        h += kWiden * fabsf(h);
-        tn = fmaxf(tn, l);
-        tf = fminf(tf, h);
+        l[a] = fminf(t0, t1);
+        h[a] = fmaxf(t0, t1);
     }
-    const float ta = fmaxf(tn, 0.0f), tb = fminf(tf, r.tm);
-    return ta <= tb;
+    return true;
 }
 
-// With at most 64 objects the count pass also keeps every ray's hit mask, and
-// the emit pass reads it instead of testing the boxes again.
-__global__ __launch_bounds__(kPairThreads) void pairs_count_kernel(const float* __restrict__ rays,
-                                                                   const float* __restrict__ tmax, int64_t n,
-                                                                   const ObjDev* __restrict__ objs, int32_t K,
-                                                                   const BoxGroup* __restrict__ groups, int32_t G,
-                                                                   uint32_t* __restrict__ counts,
-                                                                   uint64_t* __restrict__ masks) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        float o[3], d[3];
+// Widened interval [ta, tb]: contains the division test's interval (the
+// 2^-21 relative widening covers the 2^-22 error of the reciprocal form); an
+// infinite end becomes NaN under widening and drops out of fmaxf / fminf,
+// which can only widen further.
+__device__ __forceinline__ void widened(const RayPre& r, const float l[3], const float h[3], const bool con[3],
+                                        float& ta, float& tb) {
+#pragma clang fp contract(off)
+    float tn = -INFINITY, tf = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!con[a]) continue;
+        tn = fmaxf(tn, l[a] - kUlp8 * fabsf(l[a]));
+        tf = fminf(tf, h[a] + kUlp8 * fabsf(h[a]));
+    }
+    ta = fmaxf(tn, 0.0f);
+    tb = fminf(tf, r.tm);
+}
+
+// The binary32 division test's answer for one box, mostly without dividing:
+// empty widened interval -> miss; non-empty narrowed interval (ends moved
+// inwards by 2^-21, so contained in the division test's) -> hit; otherwise
+// (a graze within 8 ulp, a non-finite or tiny slab end, a tiny direction
+// component) the division test itself.
+__device__ __forceinline__ bool decide_hit(const RayPre& r, const float lo[3], const float hi[3]) {
+#pragma clang fp contract(off)
+    if (r.fast) {
+        float l[3], h[3];
+        bool con[3];
+        if (!slab_fast(r, lo, hi, l, h, con)) return false;
+        float ta, tb;
+        widened(r, l, h, con, ta, tb);
+        if (!(ta <= tb)) return false;
+        float tn = -INFINITY, tf = INFINITY;
+        bool sure = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!con[a]) continue;
+            const float al = fabsf(l[a]), ah = fabsf(h[a]);
+            sure = sure && al <= 0x1p100f && ah <= 0x1p100f && (al == 0.0f || al >= 0x1p-100f) &&
+                   (ah == 0.0f || ah >= 0x1p-100f);
+            tn = fmaxf(tn, l[a] + kUlp8 * al);
+            tf = fminf(tf, h[a] - kUlp8 * ah);
+        }
+        if (sure && fmaxf(tn, 0.0f) <= fminf(tf, r.tm)) return true;
+    }
+    float ta, tb;
+    return clip_segment(r.o, r.d, r.tm, lo, hi, ta, tb);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float lane_f(float v, int j) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
+}
+__device__ __forceinline__ float uniform_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// One lane's ray: validity, the reciprocal form and its bundle box.
+struct LaneRay {
+    RayPre pre;
+    bool active;
+    float blo[3], bhi[3];  // conservative box of the root-clipped segment (empty: +inf / -inf)
+};
+
+__device__ __forceinline__ LaneRay lane_ray(const float* __restrict__ rays, const float* __restrict__ tmax, int64_t r,
+                                            int64_t n, const PairTree& T) {
+#pragma clang fp contract(off)
+    LaneRay L;
+    float o[3] = {0, 0, 0}, d[3] = {1, 0, 0}, tm = -1.0f;
+    if (r < n) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             o[a] = rays[r * 6 + a];
             d[a] = rays[r * 6 + 3 + a];
         }
-        const float tm = tmax[r];
-        uint32_t c = 0;
-        const bool ok = !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
-        const RayPre pre = ray_pre(o, d, tm);
+        tm = tmax[r];
+    }
+    L.pre = ray_pre(o, d, tm);
+    L.active = r < n && !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        L.blo[a] = INFINITY;
+        L.bhi[a] = -INFINITY;
+    }
+    if (!L.active) return L;
+    if (!L.pre.fast) {  // no cull for this lane: the whole root box
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            L.blo[a] = T.root[a];
+            L.bhi[a] = T.root[3 + a];
+        }
+        return L;
+    }
+    float l[3], h[3];
+    bool con[3];
+    float t0, t1;
+    if (!slab_fast(L.pre, T.root, T.root + 3, l, h, con)) {
+        L.active = false;
+        return L;
+    }
+    widened(L.pre, l, h, con, t0, t1);
+    if (!(t0 <= t1)) {  // misses the root box: meets no object box
+        L.active = false;
+        return L;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float p0 = o[a] + t0 * d[a], p1 = o[a] + t1 * d[a];
+        float m = fabsf(o[a]) + fabsf(t0 * d[a]);
+        m = m + fabsf(t1 * d[a]);
+        m = m + fabsf(T.root[a]);
+        m = m + fabsf(T.root[3 + a]);
+        m = m * 0x1p-18f + 0x1p-100f;
+        L.blo[a] = fminf(p0, p1) - m;
+        L.bhi[a] = fmaxf(p0, p1) + m;
+    }
+    return L;
+}
+
+__device__ __forceinline__ bool overlaps(const float lo[3], const float hi[3], const float blo[3], const float bhi[3]) {
+    return lo[0] <= bhi[0] && lo[1] <= bhi[1] && lo[2] <= bhi[2] && hi[0] >= blo[0] && hi[1] >= blo[1] &&
+           hi[2] >= blo[2];
+}
+
+// Level-1 entry of lane j: object j (one cluster) or cluster j.  Empty slots
+// hold an empty box and id -1.
+struct LaneBox {
+    float lo[3], hi[3];
+    int32_t id;
+};
+
+__device__ __forceinline__ LaneBox level1_box(const PairTree& T, int lane) {
+    LaneBox b;
+    const float* src = T.C == 1 ? T.mbox : T.cbox;
+    const int cnt = T.C == 1 ? 64 : T.C;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = lane < cnt ? src[lane * 6 + a] : INFINITY;
+        b.hi[a] = lane < cnt ? src[lane * 6 + 3 + a] : -INFINITY;
+    }
+    b.id = T.C == 1 ? (lane < 64 ? T.mid[lane] : -1) : (lane < T.C ? lane : -1);
+    return b;
+}
+
+// Calls on_hit(object) in every lane whose ray the division test says meets
+// that object's box; wave-uniform control flow.
+template <typename F>
+__device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1, const PairTree& T, int lane,
+                                             F&& on_hit) {
+    float ulo[3], uhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ulo[a] = uniform_f(wave_min(R.blo[a]));
+        uhi[a] = uniform_f(wave_max(R.bhi[a]));
+    }
+    if (!(ulo[0] <= uhi[0])) return;  // no active lane (wave-uniform)
+    uint64_t cand = __ballot(B1.id >= 0 && overlaps(B1.lo, B1.hi, ulo, uhi));
+    while (cand) {
+        const int j = __builtin_ctzll(cand);
+        cand &= cand - 1;
+        if (T.C == 1) {
+            float lo[3], hi[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = lane_f(B1.lo[a], j);
+                hi[a] = lane_f(B1.hi[a], j);
+            }
+            const int32_t k = __builtin_amdgcn_readlane(B1.id, j);
+            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k);
+            continue;
+        }
+        // cluster j: its members, lane i holding member i
+        LaneBox m;
+        const int slot = j * 64 + lane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            m.lo[a] = T.mbox[slot * 6 + a];
+            m.hi[a] = T.mbox[slot * 6 + 3 + a];
+        }
+        m.id = T.mid[slot];
+        uint64_t mc = __ballot(m.id >= 0 && overlaps(m.lo, m.hi, ulo, uhi));
+        while (mc) {
+            const int i = __builtin_ctzll(mc);
+            mc &= mc - 1;
+            float lo[3], hi[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = lane_f(m.lo[a], i);
+                hi[a] = lane_f(m.hi[a], i);
+            }
+            const int32_t k = __builtin_amdgcn_readlane(m.id, i);
+            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[wave] = v;
+    __syncthreads();
+    const uint32_t t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive scan over the block's 256 threads.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += sh[w];
+    __syncthreads();
+    return base + x - v;
+}
+
+// Pass 1.  masks (K <= 64): bit k set iff the ray meets object k; else counts.
+__global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __restrict__ rays,
+                                                                const float* __restrict__ tmax, int64_t n, PairTree T,
+                                                                uint64_t* __restrict__ masks,
+                                                                uint32_t* __restrict__ counts,
+                                                                uint32_t* __restrict__ tile_sums) {
+    __shared__ uint32_t sh[4];
+    const int lane = threadIdx.x & 63;
+    const LaneBox B1 = level1_box(T, lane);
+    const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t r = tile * kPairTile + threadIdx.x;
+        const LaneRay R = lane_ray(rays, tmax, r, n, T);
         uint64_t mk = 0;
-        if (G > 0) {  // groups first: a box in a group lies inside the group's box
-            for (int32_t g = 0; ok && g < G; ++g) {
-                if (!maybe_hit(pre, groups[g].lo, groups[g].hi)) continue;
-                uint64_t mem = groups[g].members;
-                while (mem) {
-                    const int k = __builtin_ctzll(mem);
-                    mem &= mem - 1;
-                    float ta, tb;
-                    if (maybe_hit(pre, objs[k].lo, objs[k].hi) &&
-                        clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb)) {
-                        ++c;
-                        mk |= 1ull << k;
-                    }
-                }
-            }
-        } else {
-            for (int32_t k = 0; ok && k < K; ++k) {
-                float ta, tb;
-                if (maybe_hit(pre, objs[k].lo, objs[k].hi) && clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb)) {
-                    ++c;
-                    if (k < 64) mk |= 1ull << k;
-                }
-            }
+        uint32_t c = 0;
+        for_each_hit(R, B1, T, lane, [&](int32_t k) {
+            ++c;
+            mk |= 1ull << (k & 63);
+        });
+        if (r < n) {
+            if (masks) masks[r] = mk;
+            else counts[r] = c;
         }
-        counts[r] = c;
-        if (masks) masks[r] = mk;
+        const uint32_t s = block_sum(c, sh);
+        if (threadIdx.x == 0) tile_sums[tile] = s;
     }
 }
 
-__global__ __launch_bounds__(kPairThreads) void pairs_emit_kernel(const float* __restrict__ rays,
-                                                                  const float* __restrict__ tmax, int64_t n,
-                                                                  const ObjDev* __restrict__ objs, int32_t K,
-                                                                  const uint32_t* __restrict__ offsets,
-                                                                  int64_t max_pairs, float* __restrict__ pair_rays,
-                                                                  float* __restrict__ pair_tmax,
-                                                                  int32_t* __restrict__ pair_ids,
-                                                                  uint32_t* __restrict__ pair_ray,
-                                                                  const uint64_t* __restrict__ masks,
-                                                                  int64_t* __restrict__ total) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+// Pass 2: exclusive scan of the tile totals (one block); the pair total.
+__global__ __launch_bounds__(kPairScanThreads) void pairs_tile_scan_kernel(const uint32_t* __restrict__ sums,
+                                                                           int64_t tiles,
+                                                                           uint32_t* __restrict__ offs,
+                                                                           int64_t* __restrict__ total) {
+    __shared__ uint32_t part[kPairScanThreads];
+    const int t = threadIdx.x;
+    const int64_t per = (tiles + kPairScanThreads - 1) / kPairScanThreads;
+    const int64_t b = t * per, e = b + per < tiles ? b + per : tiles;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += sums[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kPairScanThreads; off <<= 1) {  // inclusive scan of the thread parts
+        const uint32_t y = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        offs[i] = run;
+        run += sums[i];
+    }
+    if (t == kPairScanThreads - 1) *total = (int64_t)part[t];
+}
+
+__device__ __forceinline__ void write_pair(int64_t p, const float o[3], const float d[3], float tm, int32_t k,
+                                           uint32_t ray, float* __restrict__ pair_rays, float* __restrict__ pair_tmax,
+                                           int32_t* __restrict__ pair_ids, uint32_t* __restrict__ pair_ray) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        pair_rays[p * 6 + a] = o[a];
+        pair_rays[p * 6 + 3 + a] = d[a];
+    }
+    pair_tmax[p] = tm;
+    pair_ids[p] = k;
+    pair_ray[p] = ray;
+}
+
+// Pass 3 with masks (at most 64 objects): ascending set bits.
+__global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
+    const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
+    const uint32_t* __restrict__ offs, int64_t max_pairs, float* __restrict__ pair_rays, float* __restrict__ pair_tmax,
+    int32_t* __restrict__ pair_ids, uint32_t* __restrict__ pair_ray) {
+    __shared__ uint32_t sh[4];
+    const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t r = tile * kPairTile + threadIdx.x;
+        uint64_t mk = r < n ? masks[r] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(mk);
+        int64_t p = (int64_t)offs[tile] + block_excl_scan(c, sh);
+        if (c == 0 || p >= max_pairs) continue;
         float o[3], d[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -129,33 +410,47 @@ __global__ __launch_bounds__(kPairThreads) void pairs_emit_kernel(const float* _
             d[a] = rays[r * 6 + 3 + a];
         }
         const float tm = tmax[r];
-        int64_t p = offsets[r];
-        const bool ok = !(query_error_bits(o, d, tm, 0, 1) & 1u);
-        const RayPre pre = ray_pre(o, d, tm);
-        uint64_t mk = masks ? masks[r] : 0;
-        for (int32_t k = 0; ok && k < K; ++k) {
-            if (masks) {  // ascending set bits of the stored mask
-                if (!mk) break;
-                k = __builtin_ctzll(mk);
-                mk &= mk - 1;
-            } else {
-                float ta, tb;
-                if (!maybe_hit(pre, objs[k].lo, objs[k].hi) || !clip_segment(o, d, tm, objs[k].lo, objs[k].hi, ta, tb))
-                    continue;
-            }
-            if (p < max_pairs) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    pair_rays[p * 6 + a] = o[a];
-                    pair_rays[p * 6 + 3 + a] = d[a];
-                }
-                pair_tmax[p] = tm;
-                pair_ids[p] = k;
-                pair_ray[p] = (uint32_t)r;
-            }
-            ++p;
+        while (mk && p < max_pairs) {
+            const int k = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            write_pair(p++, o, d, tm, k, (uint32_t)r, pair_rays, pair_tmax, pair_ids, pair_ray);
         }
-        if (r == n - 1) *total = p;  // offsets are exclusive: the last ray's end is the total
+    }
+}
+
+// Pass 3 with more than 64 objects: the traversal again, pairs written in
+// traversal order, then the ray's written ids sorted ascending in place (the
+// other fields are the same for every pair of a ray).
+__global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
+    const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, PairTree T,
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offs, int64_t max_pairs,
+    float* __restrict__ pair_rays, float* __restrict__ pair_tmax, int32_t* __restrict__ pair_ids,
+    uint32_t* __restrict__ pair_ray) {
+    __shared__ uint32_t sh[4];
+    const int lane = threadIdx.x & 63;
+    const LaneBox B1 = level1_box(T, lane);
+    const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t r = tile * kPairTile + threadIdx.x;
+        const uint32_t c = r < n ? counts[r] : 0u;
+        const int64_t p0 = (int64_t)offs[tile] + block_excl_scan(c, sh);
+        const LaneRay R = lane_ray(rays, tmax, r, n, T);
+        int64_t p = p0;
+        for_each_hit(R, B1, T, lane, [&](int32_t k) {
+            if (p < max_pairs) write_pair(p, R.pre.o, R.pre.d, R.pre.tm, k, (uint32_t)r, pair_rays, pair_tmax,
+                                          pair_ids, pair_ray);
+            ++p;
+        });
+        const int64_t e = p < max_pairs ? p : max_pairs;
+        for (int64_t i = p0 + 1; i < e; ++i) {  // insertion sort of the ray's ids
+            const int32_t v = pair_ids[i];
+            int64_t j = i - 1;
+            while (j >= p0 && pair_ids[j] > v) {
+                pair_ids[j + 1] = pair_ids[j];
+                --j;
+            }
+            pair_ids[j + 1] = v;
+        }
     }
 }
 
@@ -177,9 +472,46 @@ __global__ void combine_pairs_kernel(const uint32_t* __restrict__ pair_ray, cons
     }
 }
 
+// Depth output of primary-ray queries (Sec. 7: the network can encode the
+// first hit's depth): the visibility output read as the normalised position
+// of the hit in the query's segment.
+__global__ void depth_from_visibility_kernel(const float* __restrict__ rays, const int32_t* __restrict__ ids,
+                                             const float* __restrict__ tmax, const float* __restrict__ vis, int64_t n,
+                                             const ObjDev* __restrict__ objs, int32_t K, float* __restrict__ depth) {
+#pragma clang fp contract(off)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float o[3], d[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = rays[i * 6 + a];
+            d[a] = rays[i * 6 + 3 + a];
+        }
+        const float tm = tmax[i];
+        const int32_t id = ids[i];
+        float out = NAN;
+        if (valid_query(o, d, tm, id, K)) {
+            float ta, tb;
+            out = clip_segment(o, d, tm, objs[id].lo, objs[id].hi, ta, tb) ? ta + vis[i] * (tb - ta) : INFINITY;
+        }
+        depth[i] = out;
+    }
+}
+
+hipError_t launch_depth_from_visibility(const float* rays, const int32_t* ids, const float* tmax, const float* vis,
+                                        int64_t n, const ObjDev* objs, int32_t K, float* depth, int num_cus,
+                                        hipStream_t s) {
+    int64_t b = (n + 255) / 256;
+    if (b > (int64_t)num_cus * 16) b = (int64_t)num_cus * 16;
+    hipLaunchKernelGGL(depth_from_visibility_kernel, dim3((unsigned)(b > 0 ? b : 1)), dim3(256), 0, s, rays, ids, tmax,
+                       vis, n, objs, K, depth);
+    return hipGetLastError();
+}
+
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
 size_t pairs_workspace_bytes(int64_t n_rays, int32_t K) {
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return al((size_t)n_rays * 4) + al((size_t)scan_block_sums(n_rays) * 4) + (K <= 64 ? al((size_t)n_rays * 8) : 0);
+    const int64_t tiles = (n_rays + kPairTile - 1) / kPairTile;
+    return al256((size_t)n_rays * (K <= 64 ? 8 : 4)) + 2 * al256((size_t)tiles * 4);
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -187,23 +519,31 @@ static unsigned grid_for(int64_t n, int threads) {
     return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
 }
 
-hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const ObjDev* objs, int32_t K,
-                               const BoxGroup* groups, int32_t num_groups, int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
+hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const PairTree& T, int32_t K,
+                               int num_cus, int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
                                uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s) {
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    uint32_t* counts = reinterpret_cast<uint32_t*>(ws);
-    uint32_t* sums = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(ws) + al((size_t)n * 4));
-    uint64_t* masks = K <= 64 ? reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + al((size_t)n * 4) +
-                                                          al((size_t)scan_block_sums(n) * 4))
-                              : nullptr;
-    hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
-    if (n == 0) return hipGetLastError();
-    hipLaunchKernelGGL(pairs_count_kernel, dim3(grid_for(n, kPairThreads)), dim3(kPairThreads), 0, s, rays, tmax, n,
-                       objs, K, K <= 64 ? groups : nullptr, K <= 64 ? num_groups : 0, counts, masks);
-    hipError_t e = launch_exclusive_scan_u32(counts, n, sums, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pairs_emit_kernel, dim3(grid_for(n, kPairThreads)), dim3(kPairThreads), 0, s, rays, tmax, n,
-                       objs, K, counts, max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray, masks, total);
+    if (n == 0) {
+        hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
+        return hipGetLastError();
+    }
+    const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    uint8_t* p = reinterpret_cast<uint8_t*>(ws);
+    const bool use_mask = K <= 64;
+    uint64_t* masks = use_mask ? reinterpret_cast<uint64_t*>(p) : nullptr;
+    uint32_t* counts = use_mask ? nullptr : reinterpret_cast<uint32_t*>(p);
+    p += al256((size_t)n * (use_mask ? 8 : 4));
+    uint32_t* sums = reinterpret_cast<uint32_t*>(p);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(p + al256((size_t)tiles * 4));
+    const int64_t cap = (int64_t)num_cus * 8;  // persistent blocks
+    const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
+    hipLaunchKernelGGL(pairs_count_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, masks, counts, sums);
+    hipLaunchKernelGGL(pairs_tile_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, tiles, offs, total);
+    if (use_mask)
+        hipLaunchKernelGGL(pairs_emit_mask_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, masks, offs,
+                           max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
+    else
+        hipLaunchKernelGGL(pairs_emit_tree_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, counts, offs,
+                           max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
     return hipGetLastError();
 }
 

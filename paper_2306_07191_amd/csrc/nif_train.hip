@@ -17,7 +17,9 @@
 //     delta in a [feature][slot] workspace; the deltas are propagated with the
 //     transposed weight image; the feature gradient g_x comes out in the lane
 //     that encoded those features, which then scatter-adds weight * g_x into
-//     the grid gradient (binary32 atomics) and flags the touched chunks.
+//     the grid gradient and flags the touched chunks: coarse levels through a
+//     per-block LDS table flushed once per block, fine levels by binary32
+//     atomics.
 //  T2 train_dw_kernel: dW_j = sum over slots of delta_j x input_j (split-K on
 //     binary32 MFMA, one 32x32 tile per wave, deterministic per-chunk partials),
 //     then train_dw_reduce_kernel sums the partials in chunk order.
@@ -85,15 +87,6 @@ __global__ void fill_zero_kernel(uint32_t* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-// Gradient scatter of one interpolation corner: adds (v0, v1) to the two
-// latents at gg + el and flags their chunk.  Lanes with
-// gg == nullptr take no part.  Queries are ordered, so at the coarse levels
-// many lanes of a wave hit the same vertex, and same-address atomics serialise
-// in the L2: lanes are first grouped by (table, element) address, leader first,
-// for up to kPeel groups, each group summed across the wave and added by its
-// leader; lanes left after that add their own values.
-constexpr int kPeel = 6;
-
 // Global-address-space atomics: generic (flat) atomics would also wait on the
 // LDS counter.  The chunk of 64 latents holding the pair is flagged dirty with a
 // plain byte store (no read, no atomic): the Adam pass visits dirty chunks only.
@@ -105,28 +98,37 @@ __device__ __forceinline__ void add_and_mark(float* p, uint8_t* dirty, int64_t e
     if (s0 != 0.0f || s1 != 0.0f) ((GLOBAL uint8_t*)dirty)[el >> kChunkShift] = 1;
 }
 
-__device__ __forceinline__ void scatter_corner(float* gg, uint8_t* tb, int64_t el, float v0, float v1, int lane) {
-    const uintptr_t addr = gg ? (uintptr_t)(gg + el) : 0;
-    uint64_t pend = __ballot(gg != nullptr);
-    for (int it = 0; it < kPeel && pend; ++it) {
-        const int leader = __builtin_ctzll(pend);
-        const uintptr_t la = (uintptr_t)__shfl((long long)addr, leader);
-        const bool mine = ((pend >> lane) & 1) && addr == la;
-        const uint64_t grp = __ballot(mine);
-        float s0 = v0, s1 = v1;
-        if (__popcll(grp) > 1) {  // wave-uniform
-            s0 = mine ? v0 : 0.0f;
-            s1 = mine ? v1 : 0.0f;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                s0 += __shfl_xor(s0, off);
-                s1 += __shfl_xor(s1, off);
-            }
+// Coarse-level latent gradients are summed per block in an LDS hash table
+// before they reach memory.  A coarse table has few vertices, and every wave
+// of the batch adds into the same ones: same-address atomics from thousands
+// of waves serialise in the L2 (on MI355X the coarse levels' atomics took
+// about 70 % of a 262,144-ray step).  The table holds up to kAggSlots vertices (key = element
+// index / 2 of the vertex's first latent, values = the two latents' sums) of
+// the block's object; a vertex that finds no slot within kAggProbe probes, or
+// a query of another object, goes to global atomics directly.  The block adds
+// its table to the gradient once, after its last tile.
+constexpr int kAggBits = 12;
+constexpr int kAggSlots = 1 << kAggBits;
+constexpr int kAggProbe = 16;
+constexpr int kAggMaxRes = 128;  // levels of at most this many cells per axis are aggregated
+constexpr uint32_t kAggEmpty = 0xffffffffu;
+
+__device__ __forceinline__ bool agg_add(uint32_t* keys, float* v0, float* v1, uint32_t key, float s0, float s1) {
+    const uint32_t h = (key * 2654435761u) >> (32 - kAggBits);
+    for (int p = 0; p < kAggProbe; ++p) {
+        const uint32_t slot = (h + (uint32_t)p) & (kAggSlots - 1);
+        uint32_t cur = keys[slot];
+        if (cur == kAggEmpty) {
+            cur = atomicCAS(&keys[slot], kAggEmpty, key);
+            if (cur == kAggEmpty) cur = key;
         }
-        if (lane == leader) add_and_mark(gg + el, tb, el, s0, s1);
-        pend &= ~grp;
+        if (cur == key) {
+            atomicAdd(&v0[slot], s0);
+            atomicAdd(&v1[slot], s1);
+            return true;
+        }
     }
-    if ((pend >> lane) & 1) add_and_mark(gg + el, tb, el, v0, v1);
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -143,8 +145,28 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
     const int qlane = lane & 31;
     const int H = A.hidden;
     const int64_t n = A.n;
+    __shared__ uint32_t agg_key[kAggSlots];
+    __shared__ float agg_v0[kAggSlots], agg_v1[kAggSlots];
+    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+        agg_key[i] = kAggEmpty;
+        agg_v0[i] = 0.0f;
+        agg_v1[i] = 0.0f;
+    }
+    // a contiguous range of tiles per block: ordered queries, so the block's
+    // coarse cells repeat; its object is that of its first query
+    const int64_t tiles = (n + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles / gridDim.x;
+    const int64_t t_end = (int64_t)(blockIdx.x + 1) * tiles / gridDim.x;
+    int32_t agg_obj = -1;
+    if (t_begin < t_end) {
+        const int64_t s0 = t_begin * kQueriesPerBlock;
+        const int64_t q0 = A.perm ? (int64_t)A.perm[s0] : s0;
+        const int32_t id0 = A.ids[q0];
+        if (id0 >= 0 && id0 < A.num_objects && A.objs[id0].mlp == A.mlp) agg_obj = id0;
+    }
+    __syncthreads();
 
-    for (int64_t tile = blockIdx.x; tile * kQueriesPerBlock < n; tile += gridDim.x) {
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
         const int64_t slot = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
         const bool inb = slot < n;
         const int64_t q = inb && A.perm ? (int64_t)A.perm[slot] : slot;
@@ -161,9 +183,24 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
         bool active = false;
         float u[3][3];
         ObjDev ob{};
+        float seg_a = 0.0f, seg_b = 0.0f;
         if (inb && valid_query(o, d, tm, id, A.num_objects)) {
             ob = A.objs[id];
-            active = ob.mlp == A.mlp && clip_normalise(o, d, tm, ob, u) == 1;
+            active = ob.mlp == A.mlp && clip_normalise(o, d, tm, ob, u, seg_a, seg_b) == 1;
+        }
+        // depth mode: a query takes part only with a target, a finite closest
+        // hit and a segment of non-zero length
+        float s_tgt = 0.0f;
+        if (active && A.t_hit) {
+#pragma clang fp contract(off)
+            const float th = A.t_hit[q];
+            const float span = seg_b - seg_a;
+            const bool has = isfinite(th) && span > 0.0f;
+            if (has) {
+                const float sv = (th - seg_a) / span;
+                s_tgt = sv > 0.0f ? (sv < 1.0f ? sv : 1.0f) : 0.0f;
+            }
+            active = has;
         }
         // ---- encode
         float x[KH1];
@@ -267,6 +304,10 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
             const float sg = 1.0f / (1.0f + expf(-z));
             if (A.grad_y) {
                 dz = A.grad_y[q] * (sg * (1.0f - sg));
+            } else if (A.t_hit) {  // L2 on the normalised depth: d/dz (y - s)^2 = 2 (y - s) y (1 - y)
+                const float e = sg - s_tgt;
+                dz = 2.0f * e * (sg * (1.0f - sg));
+                lterm = e * e;
             } else {
                 const float t = A.labels[q] ? 1.0f : 0.0f;
                 dz = sg - t;
@@ -313,6 +354,7 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
         if (!__ballot(active)) continue;  // wave-uniform
         float* gg = active ? A.grid_grad[id] : nullptr;
         uint8_t* tb = active ? A.touched[id] : nullptr;
+        const bool agg_ok = active && id == agg_obj;
 #pragma unroll
         for (int t = 0; t < NL; ++t) {
             int64_t base;
@@ -321,22 +363,48 @@ __global__ __launch_bounds__(kBlock) void train_fb_kernel(TrainArgs A) {
             float w[3];
             lookup_geom<L>(u, half, t, A, base, sy, sz, w);
             const float g0 = acc[(2 * t) / 16][(2 * t) % 16], g1 = acc[(2 * t + 1) / 16][(2 * t + 1) % 16];
+            const int k = half ? NL + t : t;
+            const bool coarse = A.res[k % L] <= kAggMaxRes;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
                 const float wt = (bx ? w[0] : 1.0f - w[0]) * (by ? w[1] : 1.0f - w[1]) * (bz ? w[2] : 1.0f - w[2]);
                 const int64_t el = base + (bz ? sz : 0) + (by ? sy : 0) + bx * kFeats;
-                scatter_corner(gg, tb, el, wt * g0, wt * g1, lane);
+                const float s0 = wt * g0, s1 = wt * g1;
+                if (!active || (s0 == 0.0f && s1 == 0.0f)) continue;
+                if (coarse && agg_ok && agg_add(agg_key, agg_v0, agg_v1, (uint32_t)(el >> 1), s0, s1)) continue;
+                add_and_mark(gg + el, tb, el, s0, s1);
             }
+        }
+    }
+    // the block's coarse-level sums into the object's gradient
+    __syncthreads();
+    if (agg_obj >= 0) {
+        float* gg = A.grid_grad[agg_obj];
+        uint8_t* tb = A.touched[agg_obj];
+        for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+            const uint32_t key = agg_key[i];
+            if (key == kAggEmpty) continue;
+            const int64_t el = (int64_t)key << 1;
+            add_and_mark(gg + el, tb, el, agg_v0[i], agg_v1[i]);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // T2: dW partials.  blockIdx.y = layer (0..H-1 hidden layers, H = output row).
-// Each wave owns one 32x32 tile (mt, nt) of the layer's [out][in] gradient.
+// dW_j = D_j X_j^T over the chunk's slots: D_j the layer's output deltas
+// (64 x slots, or the 1 x slots dz row), X_j its inputs (kin x slots), both
+// [feature][slot] in the workspace.  The block stages kDwStep slots of every
+// row of D_j and X_j in LDS with coalesced row loads, then each wave owns one
+// 32x32 tile (mt, nt) of the [out][in] gradient and runs its binary32 MFMAs
+// from LDS, slots in ascending order.
 // ---------------------------------------------------------------------------
+constexpr int kDwStep = 64;             // slots per LDS stage
+constexpr int kDwLd = kDwStep + 1;      // padded row: lanes reading one slot of 32 rows hit 32 banks
 __global__ __launch_bounds__(256) void train_dw_kernel(TrainArgs A) {
+    __shared__ float sD[kWidth * kDwLd];
+    __shared__ float sX[kWidth * kDwLd];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int mt = wave >> 1, nt = wave & 1;
@@ -349,20 +417,31 @@ __global__ __launch_bounds__(256) void train_dw_kernel(TrainArgs A) {
     const int kin = j == 0 ? A.din : kWidth;
     const float* D = j < H ? A.delta + A.delta_off[j] : A.dz;
     const int rows = j < H ? kWidth : 1;
+    const int cols = j < H ? kin : kWidth;
     const float* X = A.act + A.act_off[j < H ? j : H];
     const int ro = 32 * mt + (lane & 31), co = 32 * nt + (lane & 31);
-    const bool rv = ro < rows, cv = co < (j < H ? kin : kWidth);
+    const bool live = !(j == H && mt == 1) && !(nt == 1 && cols <= 32);
     f32x16 acc = f32x16{};
-    if (!(j == H && mt == 1)) {
-        // K-step k takes slots s0 + 2k (lane half 0) and s0 + 2k + 1 (half 1);
-        // every lane runs every MFMA, a slot past the chunk contributes zero
-        const int64_t nsteps = (s1 - s0 + 1) / 2;
-        for (int64_t k = 0; k < nsteps; ++k) {
-            const int64_t s = s0 + 2 * k + (lane >> 5);
-            const bool sv = s < s1;
-            const float a = rv && sv ? D[(int64_t)ro * n + s] : 0.0f;
-            const float b = cv && sv ? X[(int64_t)co * n + s] : 0.0f;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    for (int64_t b0 = s0; b0 < s1; b0 += kDwStep) {
+        const int cnt = (int)(s1 - b0 < kDwStep ? s1 - b0 : kDwStep);
+        __syncthreads();
+        // stage: thread t loads slots (t % 64) of rows t / 64, t / 64 + 4, ...; zeros past the chunk
+        for (int r = threadIdx.x >> 6; r < kWidth; r += 4) {
+            const int sl = threadIdx.x & 63;
+            const bool in = sl < cnt;
+            sD[r * kDwLd + sl] = in && r < rows ? D[(int64_t)r * n + b0 + sl] : 0.0f;
+            sX[r * kDwLd + sl] = in && r < cols ? X[(int64_t)r * n + b0 + sl] : 0.0f;
+        }
+        __syncthreads();
+        if (live) {
+            // K-step k takes slots 2k (lane half 0) and 2k + 1 (half 1)
+#pragma unroll 8
+            for (int k = 0; k < kDwStep / 2; ++k) {
+                const int sl = 2 * k + (lane >> 5);
+                const float a = sD[ro * kDwLd + sl];
+                const float bv = sX[co * kDwLd + sl];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
+            }
         }
     }
     // partial tile -> partials[chunk][param]
@@ -411,8 +490,9 @@ __global__ void adam_mlp_kernel(TrainArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) *A.loss_out = B ? *A.loss_sum * inv : 0.0f;
 }
 
-// One wave per dirty chunk of 64 latents (coalesced): Adam on the latents
-// whose gradient is non-zero, gradient and flag cleared.
+// Adam on the latents whose gradient is non-zero, gradient and flag cleared.
+// A wave reads 64 chunk flags at once (one per lane), then visits the dirty
+// chunks among them, one coalesced 64-latent chunk at a time.
 template <typename GT>
 __global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t elems) {
     const unsigned B = *A.count;
@@ -424,22 +504,27 @@ __global__ void adam_grid_kernel(TrainArgs A, int32_t obj, int64_t elems) {
     GLOBAL GT* theta = (GLOBAL GT*)A.grids[obj];
     const int lane = threadIdx.x & 63;
     const int64_t chunks = (elems + 63) >> kChunkShift;
+    const int64_t groups = (chunks + 63) >> 6;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ch < chunks; ch += waves) {
-        if (!dirty[ch]) continue;  // wave-uniform
-        const int64_t el = (ch << kChunkShift) + lane;
-        if (el < elems) {
+    for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); gi < groups; gi += waves) {
+        const int64_t mine = (gi << 6) + lane;
+        const bool d = mine < chunks && dirty[mine];
+        uint64_t m = __ballot(d);
+        if (d) dirty[mine] = 0;
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            const int64_t el = (((gi << 6) + j) << kChunkShift) + lane;
+            if (el >= elems) continue;
             const float graw = gg[el];
-            if (graw != 0.0f) {  // zero gradient: latent and moments keep their values
-                gg[el] = 0.0f;
-                float m = gm[el], v = gv[el];
-                const float th = adam_update((float)theta[el], graw * inv, m, v, A.adam);
-                gm[el] = m;
-                gv[el] = v;
-                theta[el] = (GT)th;
-            }
+            if (graw == 0.0f) continue;  // zero gradient: latent and moments keep their values
+            gg[el] = 0.0f;
+            float mm = gm[el], vv = gv[el];
+            const float th = adam_update((float)theta[el], graw * inv, mm, vv, A.adam);
+            gm[el] = mm;
+            gv[el] = vv;
+            theta[el] = (GT)th;
         }
-        if (lane == 0) dirty[ch] = 0;
     }
 }
 
@@ -452,12 +537,19 @@ __global__ void scale_grid_grad_kernel(TrainArgs A, int32_t obj, int64_t elems) 
     GLOBAL uint8_t* dirty = (GLOBAL uint8_t*)A.touched[obj];
     const int lane = threadIdx.x & 63;
     const int64_t chunks = (elems + 63) >> kChunkShift;
+    const int64_t groups = (chunks + 63) >> 6;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ch < chunks; ch += waves) {
-        if (!dirty[ch]) continue;
-        const int64_t el = (ch << kChunkShift) + lane;
-        if (el < elems) gg[el] *= inv;
-        if (lane == 0) dirty[ch] = 0;
+    for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); gi < groups; gi += waves) {
+        const int64_t mine = (gi << 6) + lane;
+        const bool d = mine < chunks && dirty[mine];
+        uint64_t m = __ballot(d);
+        if (d) dirty[mine] = 0;
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            const int64_t el = (((gi << 6) + j) << kChunkShift) + lane;
+            if (el < elems) gg[el] *= inv;
+        }
     }
 }
 
@@ -472,7 +564,7 @@ __global__ void mlp_grad_only_kernel(TrainArgs A) {
 // ---------------------------------------------------------------------------
 size_t train_workspace_bytes(int64_t n, int din, int hidden, int64_t P, int64_t* chunk_out) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const int64_t chunk = 4096;
+    const int64_t chunk = 1024;  // dW split-K chunk: 256 chunks (x 5 layers) for a 262,144-ray batch
     const int64_t chunks = (n + chunk - 1) / chunk;
     if (chunk_out) *chunk_out = chunk;
     size_t b = 0;
@@ -512,7 +604,7 @@ hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_
     for (int j = 1; j <= A.hidden; ++j) A.w_off[j] = (int64_t)kWidth * A.din + (int64_t)(j - 1) * kWidth * kWidth;
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(p), 2);
     const int64_t tiles = (A.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
-    int64_t blocks = (int64_t)num_cus * 8;
+    int64_t blocks = (int64_t)num_cus * 3;  // three blocks of 48 KB of aggregation table per compute unit
     if (blocks > tiles) blocks = tiles;
     if (levels == 8) {
         if (grid_dtype == 1)
@@ -534,8 +626,9 @@ hipError_t launch_train(TrainArgs A, void* ws, const int32_t* obj_of_mlp, int32_
     for (int i = 0; i < num_obj_of_mlp; ++i) {
         const int32_t k = obj_of_mlp[i];
         const int64_t elems = elems_per_obj[k];
-        const int64_t chunks = (elems + 63) >> kChunkShift;
-        const unsigned gb = (unsigned)((chunks + 3) / 4 < 65536 ? (chunks + 3) / 4 : 65536);  // 4 waves per block
+        const int64_t groups = (((elems + 63) >> kChunkShift) + 63) >> 6;  // 64 chunk flags per wave step
+        const int64_t cap = (int64_t)num_cus * 32;
+        const unsigned gb = (unsigned)((groups + 3) / 4 < cap ? (groups + 3) / 4 : cap);  // 4 waves per block
         if (!A.apply_adam)
             hipLaunchKernelGGL(scale_grid_grad_kernel, dim3(gb), dim3(256), 0, s, A, k, elems);
         else if (grid_dtype == 1)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libnif.so")
 NIF_F32, NIF_F16, NIF_BF16, NIF_FP8_E4M3 = 0, 1, 2, 3
 NIF_OPT_ORDER = 1
 NIF_OPT_GRID_IMAGE = 2
+NIF_OPT_WINDOW_SORT = 3
 NIF_FLAG_INVALID_RAY = 1
 NIF_FLAG_BAD_OBJECT = 2
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
@@ -33,7 +34,8 @@ EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "n
            "nif_order_packed", "nif_query_packed",
            "nif_plan_workspace_bytes", "nif_plan_create", "nif_plan_launch", "nif_plan_tuning", "nif_plan_destroy",
            "nif_set_object_train", "nif_set_mlp_train", "nif_train_step", "nif_backward", "nif_touched_bytes",
-           "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit",
+           "nif_train_step_depth", "nif_depth_from_visibility",
+           "nif_bvh_create", "nif_bvh_destroy", "nif_bvh_num_nodes", "nif_bvh_anyhit", "nif_bvh_closest",
            "nif_paper_mlp_params", "nif_paper_grid_elems", "nif_paper_create", "nif_paper_destroy",
            "nif_paper_set_object", "nif_paper_init_grid", "nif_paper_set_mlp", "nif_paper_prepare", "nif_paper_query",
            "nif_paper_set_train", "nif_paper_set_object_train", "nif_paper_train_workspace_bytes",
@@ -105,11 +107,14 @@ def lib():
             "nif_set_mlp_train": (i32, [vp, i32, vp, vp]),
             "nif_train_step": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
             "nif_backward": (i32, [vp, i32, vp, vp, vp, vp, i64, vp, vp, sz, vp]),
+            "nif_train_step_depth": (i32, [vp, i32, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]),
+            "nif_depth_from_visibility": (i32, [vp, vp, vp, vp, vp, i64, vp, vp]),
             "nif_touched_bytes": (sz, [vp]),
             "nif_bvh_create": (i32, [vp, i64, vp]),
             "nif_bvh_destroy": (None, [vp]),
             "nif_bvh_num_nodes": (i64, [vp]),
             "nif_bvh_anyhit": (i32, [vp, vp, vp, i64, vp, vp]),
+            "nif_bvh_closest": (i32, [vp, vp, vp, i64, vp, vp]),
             "nif_paper_mlp_params": (i64, [i32]),
             "nif_paper_grid_elems": (i64, [i32]),
             "nif_paper_create": (i32, [i32, vp]),
@@ -170,6 +175,15 @@ class BVH:
         if out is None:
             out = torch.empty(n, dtype=torch.uint8, device=rays.device)
         _check(lib().nif_bvh_anyhit(self.h, _ptr(rays), _ptr(tmax), n, _ptr(out), _stream()), "nif_bvh_anyhit")
+        return out
+
+    def closest(self, rays, tmax, out=None):
+        """Closest-hit distance per ray (float32, +inf when none)."""
+        import torch
+        n = tmax.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=rays.device)
+        _check(lib().nif_bvh_closest(self.h, _ptr(rays), _ptr(tmax), n, _ptr(out), _stream()), "nif_bvh_closest")
         return out
 
     def close(self):
@@ -653,6 +667,27 @@ class Context:
         _check(lib().nif_train_step(self.h, mlp, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(labels), n, step,
                                     None if a is None else C.byref(a), _ptr(loss), _ptr(mlp_grad), _ptr(ws),
                                     ws.numel(), _stream()), "nif_train_step")
+
+    def train_step_depth(self, rays, ids, tmax, t_hit, step: int, mlp: int = 0, adam=(1e-2, 0.9, 0.99, 1e-15),
+                         loss=None, mlp_grad=None, ws=None):
+        """One training step of the depth output (L2 on the normalised closest-hit depth)."""
+        t = self.torch
+        n = ids.shape[0]
+        if ws is None:
+            ws = t.empty(max(1, self.workspace_bytes(n, 1)), dtype=t.uint8, device=self.device)
+        a = None if adam is None else Adam(*adam)
+        _check(lib().nif_train_step_depth(self.h, mlp, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(t_hit), n, step,
+                                          None if a is None else C.byref(a), _ptr(loss), _ptr(mlp_grad), _ptr(ws),
+                                          ws.numel(), _stream()), "nif_train_step_depth")
+
+    def depth_from_visibility(self, rays, ids, tmax, visibility, out=None):
+        """t_a + y (t_b - t_a) per query (+inf for a miss, NaN for an invalid query)."""
+        n = ids.shape[0]
+        if out is None:
+            out = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        _check(lib().nif_depth_from_visibility(self.h, _ptr(rays), _ptr(ids), _ptr(tmax), _ptr(visibility), n,
+                                               _ptr(out), _stream()), "nif_depth_from_visibility")
+        return out
 
     def backward(self, rays, ids, tmax, grad_y, mlp: int = 0, mlp_grad=None, ws=None):
         """dL/dW (into mlp_grad) and dL/dlatent (added to the registered grid gradient

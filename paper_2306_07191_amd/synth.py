@@ -210,6 +210,33 @@ def rays_ground_to_light(n: int, gen: np.random.Generator, quad_half=FRAME_QUAD_
     return np.concatenate([o32, d], axis=1).astype(np.float32), tmax
 
 
+def frame_emitter(cells: int = 12, half: float = 1.5, height: float = FRAME_LIGHT_Y, sigma: float = 1.5):
+    """An emitter above the frame scene for the sampling comparison: a
+    2 half x 2 half square at `height` split into cells x cells squares of
+    two triangles each, facing down, with log-normal radiance exp(sigma N(0,1))
+    per square (seeded), so that the flux is concentrated on a few squares.
+    Returns (triangles [2 cells^2, 9] float32, radiance [2 cells^2] float32)."""
+    g = rng(CFG_TRAIN, 6, 1)
+    e = np.linspace(-half, half, cells + 1)
+    tris, rad = [], []
+    for i in range(cells):
+        for j in range(cells):
+            x0, x1, z0, z1 = e[i], e[i + 1], e[j], e[j + 1]
+            L = float(np.exp(sigma * g.normal()))
+            tris.append([x0, height, z0, x1, height, z0, x1, height, z1])
+            tris.append([x0, height, z0, x1, height, z1, x0, height, z1])
+            rad += [L, L]
+    return np.asarray(tris, np.float32), np.asarray(rad, np.float32)
+
+
+def ground_points(n: int, gen: np.random.Generator, quad_half=FRAME_QUAD_HALF) -> np.ndarray:
+    """Uniform points of the ground quad (y = 0), float32 [n, 3]."""
+    p = np.zeros((n, 3), np.float32)
+    p[:, 0] = gen.uniform(-quad_half, quad_half, n)
+    p[:, 2] = gen.uniform(-quad_half, quad_half, n)
+    return p
+
+
 # --------------------------------------------------------------------------
 # MLP weights
 # --------------------------------------------------------------------------

@@ -61,3 +61,48 @@ def test_light_errors_and_empty():
     z = torch.zeros((0, 3), device="cuda")
     light.sample(z, z)  # n = 0 is a no-op
     light.close()
+
+
+def test_training_on_sampled_rays():
+    """Training batches drawn by light importance sampling (Sec. 5 "Training"):
+    shadow rays from points under the small scene's object to an emitter above
+    it, exact labels from the GPU BVH, a few training steps; the sampled rays
+    start at the given points and end on the emitter, both labels occur, and
+    the loss falls."""
+    import torch
+    from paper_2306_07191_amd import nif, synth as S
+    from gpu_util import make_pair
+    w = S.tiny_workload(n_rays=16)
+    ctx, _ = make_pair(w, grid_amp=1e-4)
+    ctx.prepare("f32")
+    ctx.setup_training()
+    g = np.random.default_rng(3)
+    L = 64
+    c = np.stack([g.uniform(-1.5, 1.5, L), np.full(L, 4.0), g.uniform(-1.5, 1.5, L)], 1)
+    tris = (c[:, None, :] + g.normal(size=(L, 3, 3)) * 0.2).reshape(L, 9).astype(np.float32)
+    light = nif.Light(tris, np.exp(g.normal(size=L)).astype(np.float32))
+    bvh = nif.BVH(w["tris"])
+    nb = 8192
+    ids = torch.zeros(nb, dtype=torch.int32, device="cuda")
+    losses = []
+    for step in range(1, 31):
+        pts = np.stack([g.uniform(-1.5, 1.5, nb), np.full(nb, -3.0), g.uniform(-1.5, 1.5, nb)], 1).astype(np.float32)
+        p = torch.from_numpy(pts).cuda()
+        u = torch.from_numpy(g.uniform(size=(nb, 3)).astype(np.float32)).cuda()
+        rays, tmax, _, tri = light.sample(p, u)
+        lab = bvh.anyhit(rays, tmax)
+        if step == 1:
+            r = rays.cpu().numpy().astype(np.float64)
+            np.testing.assert_array_equal(r[:, :3], pts)
+            end = r[:, :3] + tmax.cpu().numpy()[:, None].astype(np.float64) * r[:, 3:]
+            verts = tris.reshape(L, 3, 3)[tri.cpu().numpy()]
+            assert (end[:, 1] > verts[:, :, 1].min(1) - 1e-3).all() and (end[:, 1] < verts[:, :, 1].max(1) + 1e-3).all()
+            frac = float(lab.float().mean().item())
+            assert 0.05 < frac < 0.95, frac
+        loss = torch.zeros(1, device="cuda")
+        ctx.train_step(rays, ids, tmax, lab, step=step, loss=loss)
+        losses.append(float(loss.item()))
+    assert np.mean(losses[-5:]) < 0.9 * np.mean(losses[:5]), losses
+    light.close()
+    bvh.close()
+    ctx.close()

@@ -30,7 +30,102 @@ def _scene(n=20000, K=12, seed=5):
                 tmax=tmax, ids=np.zeros(n, np.int32))
 
 
-@pytest.mark.parametrize("K", [12, 40, 70])  # boxes one by one with hit masks, box groups, no masks
+def _grazing(w, g):
+    """Rays that graze boxes: origins on a face plane moving inside it, t_max
+    ending exactly at the entry distance, directions with components below
+    2^-100, and rays starting inside boxes."""
+    boxes, rays, tmax = w["aabb"], w["rays"], w["tmax"]
+    n, K = tmax.shape[0], boxes.shape[0]
+    m = n // 8
+    k = g.integers(0, K, m)
+    lo, hi = boxes[k, :3].astype(np.float64), boxes[k, 3:].astype(np.float64)
+    a = g.integers(0, 3, m)
+    face = np.where(g.uniform(size=m) < 0.5, lo[np.arange(m), a], hi[np.arange(m), a])
+    o = lo + g.uniform(-0.2, 1.2, (m, 3)) * (hi - lo)
+    o[np.arange(m), a] = face
+    d = g.normal(size=(m, 3))
+    d[np.arange(m), a] = 0.0                     # inside the face plane
+    tiny = g.uniform(size=m) < 0.3
+    d[tiny, a[tiny]] = 1e-35 * np.sign(g.normal(size=tiny.sum()))  # below 2^-100, not zero
+    sl = slice(0, m)
+    rays[sl, :3], rays[sl, 3:] = o.astype(np.float32), d.astype(np.float32)
+    tmax[sl] = np.inf
+    # t_max exactly at the box entry of a ray from outside
+    b = slice(m, 2 * m)
+    o2 = rays[b, :3].astype(np.float64)
+    tgt = lo + 0.5 * (hi - lo)
+    d2 = (tgt - o2).astype(np.float32)
+    rays[b, 3:] = d2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_in = np.max(np.minimum((lo - o2) / d2, (hi - o2) / d2), axis=1)
+    tmax[b] = np.where(np.isfinite(t_in), np.maximum(t_in, 0), np.inf).astype(np.float32)
+    # origins inside boxes
+    c = slice(2 * m, 3 * m)
+    rays[c, :3] = (lo + g.uniform(size=(m, 3)) * (hi - lo)).astype(np.float32)
+    return w
+
+
+def _check_pairs(ctx, model, w, rays_np, tmax_np, max_pairs=None, sample=None):
+    import torch
+    rays, tmax = torch.from_numpy(rays_np).cuda(), torch.from_numpy(tmax_np).cuda()
+    pr_rays, pr_tmax, pr_ids, pr_ray = ctx.expand_pairs(rays, tmax, max_pairs=max_pairs)
+    g_ray, g_obj = pr_ray.cpu().numpy().astype(np.int64), pr_ids.cpu().numpy()
+    if sample is None:
+        ref_ray, ref_obj = model.expand_pairs(rays_np, tmax_np)
+    else:  # the oracle on a sample of the rays; the GPU ran on all of them
+        r_s, o_s = model.expand_pairs(rays_np[sample], tmax_np[sample])
+        ref_ray, ref_obj = sample[r_s], o_s
+        keep = np.isin(g_ray, sample)
+        g_ray, g_obj = g_ray[keep], g_obj[keep]
+        assert (np.diff(pr_ray.cpu().numpy().astype(np.int64)) >= 0).all()  # ray order
+    np.testing.assert_array_equal(g_ray, ref_ray)
+    np.testing.assert_array_equal(g_obj, ref_obj)
+    return pr_rays, pr_tmax, pr_ids, pr_ray, ref_ray
+
+
+@pytest.mark.parametrize("K", [1, 12, 64, 70, 300])  # one level with hit masks (<= 64), clusters (> 64)
+def test_pairs_grazing_and_tiny_directions(K):
+    w = _grazing(_scene(n=16000, K=K, seed=11 + K), np.random.default_rng(K))
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    _, _, _, pr_ray, ref_ray = _check_pairs(ctx, model, w, w["rays"], w["tmax"])
+    assert ref_ray.size > 1000
+
+
+def test_pairs_far_from_origin():
+    """Boxes and rays around (3e4, -2e4, 1e4): the bundle margins are relative."""
+    w = _scene(n=16000, K=50, seed=3)
+    off = np.array([3e4, -2e4, 1e4], np.float32)
+    w["aabb"] = (w["aabb"] + np.concatenate([off, off])).astype(np.float32)
+    w["rays"][:, :3] += off
+    w = _grazing(w, np.random.default_rng(9))
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    _check_pairs(ctx, model, w, w["rays"], w["tmax"])
+
+
+@pytest.mark.parametrize("K", [64, 200])
+def test_pairs_coherent_scene_rays(K):
+    """The large scene's 8,294,400 shadow rays (pixel order, so every wave is a
+    coherent bundle) against 64 object boxes, or 200 boxes on the same ground;
+    the oracle checks every 13th (64 boxes) or 41st (200 boxes) ray."""
+    sc = S.scene_workload(light_seed=0, with_mesh=False)
+    boxes = sc["aabb"]
+    if K != boxes.shape[0]:
+        g = np.random.default_rng(4)
+        c = np.stack([g.uniform(-24, 24, K), g.uniform(0.2, 1.5, K), g.uniform(-13.5, 13.5, K)], 1)
+        h = g.uniform(0.3, 1.5, (K, 1))
+        boxes = np.concatenate([c - h, c + h], 1).astype(np.float32)
+    mlps = np.stack([S.xavier_mlp(S.TINY, S.rng(70, 3, 0))])
+    w = dict(shape=S.TINY, aabb=boxes, mlps=mlps, mlp_index=np.zeros(K, np.int32))
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    n = sc["tmax"].shape[0]
+    sample = np.arange(0, n, 13 if K == 64 else 41)
+    _check_pairs(ctx, model, w, sc["rays"], sc["tmax"], sample=sample)
+
+
+@pytest.mark.parametrize("K", [12, 40, 70])  # one level with hit masks (<= 64 objects), clusters (> 64)
 def test_pairs_match_oracle_and_combine(K):
     import torch
     w = _scene(K=K)
