@@ -754,12 +754,17 @@ int orc_query_detail(const orc_model* m, const float* ray, int32_t id, float tma
 }
 
 /* MLP alone on given inputs x [n][din] with MLP `mlp` (for tests). */
-void orc_mlp_only(const orc_model* m, int32_t mlp, int64_t n, const double* x, double* z, double* acts) {
+/* The MLP alone on given features; ztol / ybound (nullable) as orc_forward's
+ * (no interpolation drift: the features are given). */
+void orc_mlp_only(const orc_model* m, int32_t mlp, int64_t n, const double* x, double* z, double* acts, double* ztol,
+                  double* ybound) {
     for (int64_t i = 0; i < n; ++i) {
         orc_fwd o;
         mlp_forward(m, m->mlps[mlp], m->fp8_scales ? m->fp8_scales[mlp] : NULL, x + i * orc_din(m), NULL,
                     acts ? acts + i * (int64_t)m->hidden * m->width : NULL, &o);
         z[i] = o.z;
+        if (ztol) ztol[i] = o.ztol;
+        if (ybound) ybound[i] = o.ybound;
     }
 }
 
@@ -1287,4 +1292,138 @@ static void closest_bvh_range(void* p, int64_t b, int64_t e) {
 void orc_closest_bvh(const orc_bvh* h, int64_t n, const float* rays, const float* tmax, double* t_hit, int nthreads) {
     closest_bvh_job J = {h, rays, tmax, t_hit};
     parallel_for(n, nthreads, closest_bvh_range, &J);
+}
+
+/* ======================================================================
+ * The same watertight test evaluated in binary32, the precision the GPU
+ * caster decides hits in: each operation below is one binary32 operation
+ * (no contraction), and the three edge functions are recomputed in binary64
+ * when one of them is exactly zero, as the published algorithm prescribes
+ * for single precision.  The axis kz is the last index of the largest |d|
+ * component.  Hit distance T / det in binary32.  Used to check the GPU
+ * labels and closest hits decision for decision; the binary64 test above is
+ * the exact reference they are also compared with.
+ * ====================================================================== */
+int orc_ray_tri32_t(const float o[3], const float d[3], float tmax, const float* v, float* t_out) {
+    const float a0 = fabsf(d[0]), a1 = fabsf(d[1]), a2 = fabsf(d[2]);
+    int kz = a0 > a1 ? (a0 > a2 ? 0 : 2) : (a1 > a2 ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1, ky = kx == 2 ? 0 : kx + 1;
+    if (d[kz] < 0.0f) { int t = kx; kx = ky; ky = t; }
+    const float Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0f / d[kz];
+    const float Ax = v[0 + kx] - o[kx], Ay = v[0 + ky] - o[ky], Az0 = v[0 + kz] - o[kz];
+    const float Bx = v[3 + kx] - o[kx], By = v[3 + ky] - o[ky], Bz0 = v[3 + kz] - o[kz];
+    const float Cx = v[6 + kx] - o[kx], Cy = v[6 + ky] - o[ky], Cz0 = v[6 + kz] - o[kz];
+    const float ax = Ax - Sx * Az0, ay = Ay - Sy * Az0;
+    const float bx = Bx - Sx * Bz0, by = By - Sy * Bz0;
+    const float cx = Cx - Sx * Cz0, cy = Cy - Sy * Cz0;
+    float U = cx * by - cy * bx;
+    float V = ax * cy - ay * cx;
+    float W = bx * ay - by * ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)cx * by - (double)cy * bx);
+        V = (float)((double)ax * cy - (double)ay * cx);
+        W = (float)((double)bx * ay - (double)by * ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return 0;
+    float det = U + V + W;
+    if (det == 0.0f) return 0;
+    float T = U * (Sz * Az0) + V * (Sz * Bz0) + W * (Sz * Cz0);
+    if (det < 0.0f) { T = -T; det = -det; }
+    if (!(T > 0.0f)) return 0;
+    if (!(isinf(tmax) || T < tmax * det)) return 0;
+    if (t_out) *t_out = T / det;
+    return 1;
+}
+
+typedef struct {
+    int64_t T;
+    const float* tris;
+    const float *rays, *tmax;
+    uint8_t* vis;
+    float* t_hit;
+} brute32_job;
+
+static void brute32_range(void* p, int64_t b, int64_t e) {
+    brute32_job* J = (brute32_job*)p;
+    for (int64_t i = b; i < e; ++i) {
+        const float* r = J->rays + 6 * i;
+        float best = INFINITY, t;
+        int hit = 0;
+        for (int64_t k = 0; k < J->T; ++k)
+            if (orc_ray_tri32_t(r, r + 3, J->tmax[i], J->tris + 9 * k, &t)) {
+                hit = 1;
+                if (t < best) best = t;
+                if (!J->t_hit) break;
+            }
+        if (J->vis) J->vis[i] = hit ? 0 : 1;
+        if (J->t_hit) J->t_hit[i] = best;
+    }
+}
+
+/* Any-hit labels (vis, nullable) and closest-hit distances (t_hit, nullable)
+ * of the binary32 test over every triangle. */
+void orc_trace_brute32(int64_t T, const float* tris, int64_t n, const float* rays, const float* tmax, uint8_t* vis,
+                       float* t_hit, int nthreads) {
+    brute32_job J = {T, tris, rays, tmax, vis, t_hit};
+    parallel_for(n, nthreads, brute32_range, &J);
+}
+
+/* The same through the BVH above, whose node boxes are widened here by a
+ * relative 2^-16 (far above binary32 rounding of a hit point), so that no box
+ * holding a binary32 hit is skipped and the answer equals brute force. */
+static int box_hit_loose(const orc_node* nd, const double o[3], const double d[3], double tmax) {
+    double tn = 0.0, tf = tmax;
+    for (int a = 0; a < 3; ++a) {
+        const double pad = 0x1p-16 * (fabs(nd->lo[a]) + fabs(nd->hi[a]) + fabs(o[a]));
+        const double lo = nd->lo[a] - pad, hi = nd->hi[a] + pad;
+        if (d[a] == 0.0) {
+            if (o[a] < lo || o[a] > hi) return 0;
+            continue;
+        }
+        double t0 = (lo - o[a]) / d[a], t1 = (hi - o[a]) / d[a];
+        double l = fmin(t0, t1), h = fmax(t0, t1);
+        l -= 0x1p-16 * fabs(l);
+        h += 0x1p-16 * fabs(h);
+        if (l > tn) tn = l;
+        if (h < tf) tf = h;
+    }
+    return tn <= tf;
+}
+
+typedef struct { const orc_bvh* h; const float *rays, *tmax; uint8_t* vis; float* t_hit; } bvh32_job;
+
+static void bvh32_range(void* p, int64_t b, int64_t e) {
+    bvh32_job* J = (bvh32_job*)p;
+    const orc_bvh* h = J->h;
+    int64_t stack[128];
+    for (int64_t i = b; i < e; ++i) {
+        const float* r = J->rays + 6 * i;
+        const double o[3] = {r[0], r[1], r[2]}, d[3] = {r[3], r[4], r[5]};
+        const float tm = J->tmax[i];
+        float best = INFINITY, t;
+        int hit = 0, sp = 0;
+        if (h->T > 0) stack[sp++] = 0;
+        while (sp && !(hit && !J->t_hit)) {
+            const orc_node* nd = &h->nodes[stack[--sp]];
+            if (!box_hit_loose(nd, o, d, best < tm ? (double)best : (double)tm)) continue;
+            if (nd->left < 0) {
+                for (int64_t k = nd->first; k < nd->first + nd->count; ++k)
+                    if (orc_ray_tri32_t(r, r + 3, tm, h->tris + 9 * h->idx[k], &t)) {
+                        hit = 1;
+                        if (t < best) best = t;
+                    }
+            } else {
+                stack[sp++] = nd->left;
+                stack[sp++] = nd->right;
+            }
+        }
+        if (J->vis) J->vis[i] = hit ? 0 : 1;
+        if (J->t_hit) J->t_hit[i] = best;
+    }
+}
+
+void orc_trace_bvh32(const orc_bvh* h, int64_t n, const float* rays, const float* tmax, uint8_t* vis, float* t_hit,
+                     int nthreads) {
+    bvh32_job J = {h, rays, tmax, vis, t_hit};
+    parallel_for(n, nthreads, bvh32_range, &J);
 }

@@ -69,7 +69,7 @@ def lib():
             "orc_grid_offsets": (i64, [vp, vp]),
             "orc_forward": (None, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_query_detail": (C.c_int, [vp, vp, i32, C.c_float, vp, vp, vp, vp]),
-            "orc_mlp_only": (None, [vp, i32, i64, vp, vp, vp]),
+            "orc_mlp_only": (None, [vp, i32, i64, vp, vp, vp, vp, vp]),
             "orc_status": (None, [vp, i64, vp, vp, vp, vp]),
             "orc_segment": (None, [vp, i64, vp, vp, vp, vp, vp]),
             "orc_backward": (i64, [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
@@ -84,6 +84,9 @@ def lib():
             "orc_ray_tri_t": (C.c_int, [vp, vp, d, vp, vp]),
             "orc_closest_brute": (None, [i64, vp, i64, vp, vp, vp, C.c_int]),
             "orc_closest_bvh": (None, [vp, i64, vp, vp, vp, C.c_int]),
+            "orc_ray_tri32_t": (C.c_int, [vp, vp, C.c_float, vp, vp]),
+            "orc_trace_brute32": (None, [i64, vp, i64, vp, vp, vp, vp, C.c_int]),
+            "orc_trace_bvh32": (None, [vp, i64, vp, vp, vp, vp, C.c_int]),
             "orc_default_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -291,14 +294,19 @@ class Model:
         st = lib().orc_query_detail(self.ref, _p(r), int(obj), float(tmax), _p(u), _p(x), _p(ce), _p(cw))
         return st, u.reshape(3, 3), x, ce.reshape(3 * L, 8), cw.reshape(3 * L, 8)
 
-    def mlp_only(self, x, mlp: int = 0, want_acts: bool = False):
+    def mlp_only(self, x, mlp: int = 0, want_acts: bool = False, want_tol: bool = False):
         """Logits of MLP `mlp` on features x [n, din]; with want_acts also the
-        pre-activation outputs a_j = W_j h_{j-1} of the hidden layers [n, H, width]."""
+        pre-activation outputs a_j = W_j h_{j-1} of the hidden layers [n, H, width];
+        with want_tol a dict with z, ztol and ybound (as forward's)."""
         x = np.ascontiguousarray(x, np.float64).reshape(-1, self.shape.din)
         n = x.shape[0]
         z = np.empty(n)
         acts = np.empty((n, self.shape.hidden, self.shape.width)) if want_acts else None
-        lib().orc_mlp_only(self.ref, mlp, n, _p(x), _p(z), _p(acts))
+        ztol = np.empty(n) if want_tol else None
+        yb = np.empty(n) if want_tol else None
+        lib().orc_mlp_only(self.ref, mlp, n, _p(x), _p(z), _p(acts), _p(ztol), _p(yb))
+        if want_tol:
+            return dict(z=z, ztol=ztol, ybound=yb)
         return (z, acts) if want_acts else z
 
     def fp8_calibrate(self, rays, ids, tmax, mlp: int = 0):
@@ -453,6 +461,18 @@ def closest_brute(tris, rays, tmax, nthreads: int = 0) -> np.ndarray:
     return t
 
 
+def trace_brute32(tris, rays, tmax, nthreads: int = 0):
+    """(visible uint8, closest-hit float32) of the binary32 watertight test over
+    every triangle: the GPU caster's decisions, for exact comparison."""
+    tris = np.ascontiguousarray(tris, np.float32)
+    rays = np.ascontiguousarray(rays, np.float32)
+    tmax = np.ascontiguousarray(tmax, np.float32)
+    vis = np.empty(rays.shape[0], np.uint8)
+    t = np.empty(rays.shape[0], np.float32)
+    lib().orc_trace_brute32(tris.shape[0], _p(tris), rays.shape[0], _p(rays), _p(tmax), _p(vis), _p(t), nthreads)
+    return vis, t
+
+
 class BVH:
     def __init__(self, tris):
         self.tris = np.ascontiguousarray(tris, np.float32)
@@ -464,6 +484,15 @@ class BVH:
         vis = np.empty(rays.shape[0], np.uint8)
         lib().orc_anyhit_bvh(self.h, rays.shape[0], _p(rays), _p(tmax), _p(vis), nthreads)
         return vis
+
+    def trace32(self, rays, tmax, nthreads: int = 0):
+        """trace_brute32 through the BVH (same answer)."""
+        rays = np.ascontiguousarray(rays, np.float32)
+        tmax = np.ascontiguousarray(tmax, np.float32)
+        vis = np.empty(rays.shape[0], np.uint8)
+        t = np.empty(rays.shape[0], np.float32)
+        lib().orc_trace_bvh32(self.h, rays.shape[0], _p(rays), _p(tmax), _p(vis), _p(t), nthreads)
+        return vis, t
 
     def closest(self, rays, tmax, nthreads: int = 0) -> np.ndarray:
         rays = np.ascontiguousarray(rays, np.float32)

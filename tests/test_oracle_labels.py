@@ -117,3 +117,45 @@ def test_closest_bvh_equals_brute_force_and_agrees_with_any_hit():
             ts = [O.ray_tri_t(rays[k, :3].astype(np.float64), rays[k, 3:].astype(np.float64), float(tmax[k]), tr)
                   for tr in tris]
             assert tb[k] == min(x for x in ts if x is not None)
+
+
+# ---- the watertight test in binary32 (the GPU caster's precision) ----
+
+def test_binary32_test_hand_cases_and_watertightness():
+    near = np.array([[-1, -1, 1, 2, -1, 1, -1, 2, 1]], np.float32)
+    far = np.array([[-1, -1, 3, 2, -1, 3, -1, 2, 3]], np.float32)
+    rays = np.array([[0.2, 0.1, -2, 0, 0, 1], [0.2, 0.1, -2, 0, 0, 1], [5.0, 5.0, -2, 0, 0, 1]], np.float32)
+    vis, t = O.trace_brute32(np.concatenate([far, near]), rays, np.array([np.inf, 3.0, np.inf], np.float32), 1)
+    np.testing.assert_array_equal(vis, [0, 1, 1])  # t_max = 3 exactly excludes the hit at 3 (strict)
+    assert t[0] == np.float32(3.0) and np.isinf(t[1]) and np.isinf(t[2])
+    # two triangles sharing an edge: rays through points of the edge never leak
+    a = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0], np.float32)
+    b = np.array([1, 0, 0, 1, 1, 0, 0, 1, 0], np.float32)
+    g = np.random.default_rng(2)
+    s = g.uniform(0, 1, 2000)
+    p = np.stack([s, 1 - s, np.zeros_like(s)], 1)
+    o = p + g.normal(size=(2000, 3)) * [0.3, 0.3, 0.0] + [0, 0, 1.5]
+    r = np.concatenate([o, p - o], 1).astype(np.float32)
+    v, _ = O.trace_brute32(np.stack([a, b]), r, np.full(2000, np.inf, np.float32), 1)
+    assert (v == 0).all()
+
+
+def test_binary32_bvh_equals_brute_force_and_tracks_binary64():
+    g = np.random.default_rng(12)
+    agree = []
+    for trial in range(60):
+        T = int(g.integers(1, 300))
+        tris = S.random_triangles(T, g)
+        box = S.mesh_aabb(tris)
+        rays, tmax = S.rays_sphere_to_box(400, box, g)
+        tmax = np.where(g.uniform(size=400) < 0.3, g.uniform(0.5, 4.0, 400), tmax).astype(np.float32)
+        vb, tb = O.trace_brute32(tris, rays, tmax, nthreads=1)
+        vv, tv = O.BVH(tris).trace32(rays, tmax, nthreads=1)
+        np.testing.assert_array_equal(vv, vb)
+        np.testing.assert_array_equal(tv, tb)
+        v64 = O.anyhit_brute(tris, rays, tmax, nthreads=1)
+        agree.append((v64 == vb).mean())
+        t64 = O.closest_brute(tris, rays, tmax, nthreads=1)
+        both = np.isfinite(t64) & np.isfinite(tb)
+        assert (np.abs(tb[both] - t64[both]) <= 1e-5 * t64[both]).mean() >= 0.999
+    assert np.mean(agree) >= 0.999
