@@ -606,6 +606,23 @@ def run_scene(args):
     res, gpu_y = {}, {}
     mask_ref = lab.reshape(-1, S.SCENE_SPP).mean(axis=1)
     stream = torch.cuda.current_stream()
+    # schedule: ordering with or without the window sort (the finer Morton key),
+    # whichever makes the headline step faster on these pairs
+    ctx.prepare(SCENE_DTYPE)
+    sched = {}
+    for wsort in (1, 0):
+        ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
+
+        def one():
+            expand()
+            ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
+            ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
+            ctx.combine_pairs(pray[:P], yq, n, out=vis)
+
+        sched[wsort] = time_launches(one, 10, 3) * 1e3
+    window_sort = min(sched, key=sched.get)
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, window_sort)
+    log(f"step with window sort {sched[1]:.3f} ms, without {sched[0]:.3f} ms: window sort {'on' if window_sort else 'off'}")
     for dt in ((SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")):
         ctx.prepare(dt)
         steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
@@ -685,6 +702,7 @@ def run_scene(args):
                                "per object",
                    "rays": n, "pairs": P, "objects": K, "triangles": int(w["tri_counts"].sum()),
                    "step": "pair expansion + pair ordering + fused query kernel + per-ray combination",
+                   "window_sort": bool(window_sort), "step_ms_by_window_sort": {"on": sched[1], "off": sched[0]},
                    "value_is": "(ray, object) queries per second; rays_per_s is in per_dtype"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE], "traffic": measured_traffic("scene"),

@@ -266,9 +266,18 @@ nif_status nif_query_packed(nif_ctx* ctx, int32_t dtype, const float* packed, co
  * and workspace pointers and n; their contents may change between launches.
  * nif_plan_create: with tuning == NULL, times every candidate schedule
  *   (ordering off / bucket order / bucket order + window sort, times the
- *   persistent grid's blocks per compute unit) on these buffers and keeps the
- *   fastest; otherwise uses the schedule of the JSON string `tuning` (as
- *   written by nif_plan_tuning: keys "order" 0..2 and "blocks_per_cu" 1..32).
+ *   persistent grid's blocks per compute unit 4..32, times the fused kernel's
+ *   tile shape: shape 0 = 6 image lookups (or all 12 grid lookups) of a lane
+ *   half gathered together at 3 waves per SIMD (2 for binary32), shape 1 = 12
+ *   (6) at 2 waves per SIMD, shape 2 = 3 at 4 waves per SIMD; shapes 1 and 2
+ *   exist for 8-level binary16 grids) on these buffers and keeps the fastest;
+ *   otherwise uses the schedule of the JSON string `tuning` (as written by
+ *   nif_plan_tuning: keys "order" 0..2, "blocks_per_cu" 1..32 and optionally
+ *   "shape" 0..2).  When the environment variable NIF_PLAN_CACHE names a file,
+ *   a schedule tuned before for the same device architecture, compute-unit
+ *   count, model shape, object and MLP counts, image mode, dtype and n
+ *   (rounded up to a power of two) is read from it instead of tuning, and a
+ *   newly tuned one is appended to it (one JSON object per line).
  *   Then captures the ordering and query kernels into a HIP graph.  Writes the
  *   outputs while tuning; synchronises `stream`.  ws: at least
  *   nif_plan_workspace_bytes(ctx, n) bytes (dev), kept by the plan.  Needs
@@ -280,7 +289,10 @@ nif_status nif_query_packed(nif_ctx* ctx, int32_t dtype, const float* packed, co
  *   nif_set_image or a NIF_OPT_GRID_IMAGE change since the capture: create a
  *   new plan) or is not prepared for the plan's dtype (a training step or
  *   nif_set_mlp since the last nif_prepare: call nif_prepare again).
- * nif_plan_tuning: the chosen schedule as JSON (host buffer buf of buf_bytes).
+ * nif_plan_tuning: the chosen schedule as JSON (host buffer buf of buf_bytes):
+ *   order, blocks_per_cu, shape and its gather_batch and waves_per_simd,
+ *   queries_per_wave (32) and waves_per_block (4), tuned_us (-1 when given or
+ *   read from the cache), candidates, from_cache.
  * nif_plan_destroy: frees the plan (not the caller's buffers). */
 typedef struct nif_plan nif_plan;
 size_t nif_plan_workspace_bytes(const nif_ctx* ctx, int64_t n);

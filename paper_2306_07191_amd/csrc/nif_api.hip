@@ -496,9 +496,10 @@ static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, 
 
 static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
                             const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s,
-                            int32_t blocks_per_cu = 0, const float4* qrec = nullptr) {
+                            int32_t blocks_per_cu = 0, const float4* qrec = nullptr, int32_t shape = 0) {
     FwdArgs a{};
     a.qrec = qrec;
+    a.shape = shape;
     a.flags = c->d_flags;
     a.blocks_per_cu = blocks_per_cu;
     a.use_image = c->images_ready ? c->image_mode : 0;
@@ -1014,7 +1015,17 @@ extern "C" nif_status nif_backward(nif_ctx* c, int32_t mlp, const float* rays, c
 struct Sched {
     int32_t order;          // 0 none, 1 bucket order, 2 bucket order + window sort
     int32_t blocks_per_cu;  // persistent grid: blocks per compute unit
+    int32_t shape;          // tile shape of the fused kernel: gathers issued together, waves per SIMD
 };
+
+// The tile shape's parameters as the fused kernel instantiates them (8-level
+// binary16 grids; other grids run shape 0): gathers issued together per lane
+// half (image / grid path) and the waves per SIMD the registers are cut for.
+static void shape_params(int32_t shape, int32_t dtype, int32_t levels, int32_t image, int32_t* batch, int32_t* wpe) {
+    const int NL = 3 * levels / 2;
+    *batch = shape == 1 ? (image ? NL : NL / 2) : shape == 2 ? 3 : (image ? 6 : NL);
+    *wpe = shape == 1 ? 2 : shape == 2 ? 4 : (dtype == NIF_F32 ? 2 : 3);
+}
 
 struct nif_plan {
     nif_ctx* c = nullptr;
@@ -1026,9 +1037,10 @@ struct nif_plan {
     float* vis = nullptr;
     float* logits = nullptr;
     void* ws = nullptr;
-    Sched sched{2, 8};
+    Sched sched{2, 8, 0};
     float tuned_us = -1.0f;  // time of the chosen schedule (-1: given, not tuned)
     int32_t candidates = 0;
+    bool from_cache = false;
     uint64_t epoch = 0;  // the context's epoch at capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1043,7 +1055,58 @@ static nif_status plan_run(nif_plan* p, const Sched& sc, hipStream_t s) {
         if (st != NIF_OK) return st;
     }
     return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu,
-                     qrec);
+                     qrec, sc.shape);
+}
+
+// Tuning cache: a text file of one JSON object per line, {"key": "...",
+// "order": o, "blocks_per_cu": b, "shape": s}, named by the environment
+// variable NIF_PLAN_CACHE (no cache when unset).  The key holds the device
+// architecture and compute-unit count, the model shape, the number of objects
+// and MLPs, the query image mode, the dtype and n rounded up to a power of two.
+static std::string plan_key(const nif_ctx* c, int32_t dtype, int64_t n) {
+    hipDeviceProp_t prop{};
+    const char* arch = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.gcnArchName : "unknown";
+    int64_t nb = 1;
+    while (nb < n) nb <<= 1;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s|cu%d|L%d r%d-%d F%d g%d H%d W%d|K%d M%d|img%d|dtype%d|n%lld", arch, c->num_cus,
+             c->d.levels, c->d.res_min, c->d.res_max, c->d.feats, c->d.grid_dtype, c->d.hidden_layers, c->d.width, c->K,
+             c->M, c->image_mode, dtype, (long long)nb);
+    return buf;
+}
+
+static bool parse_int_key(const char* js, const char* key, int32_t* v);
+
+static bool cache_lookup(const std::string& key, Sched* sc) {
+    const char* path = getenv("NIF_PLAN_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    const std::string want = "\"key\": \"" + key + "\"";
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, want.c_str())) continue;
+        Sched s{2, 8, 0};
+        if (parse_int_key(line, "\"order\"", &s.order) && parse_int_key(line, "\"blocks_per_cu\"", &s.blocks_per_cu) &&
+            parse_int_key(line, "\"shape\"", &s.shape) && s.order >= 0 && s.order <= 2 && s.blocks_per_cu >= 1 &&
+            s.blocks_per_cu <= 32 && s.shape >= 0 && s.shape <= 2) {
+            *sc = s;  // the last matching line wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string& key, const Sched& sc, float us) {
+    const char* path = getenv("NIF_PLAN_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": \"%s\", \"order\": %d, \"blocks_per_cu\": %d, \"shape\": %d, \"tuned_us\": %.3f}\n",
+            key.c_str(), sc.order, sc.blocks_per_cu, sc.shape, (double)us);
+    fclose(f);
 }
 
 static bool parse_int_key(const char* js, const char* key, int32_t* v) {
@@ -1085,16 +1148,30 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
     p->logits = logits;
     p->ws = ws;
     hipStream_t s = (hipStream_t)stream;
+    const std::string key = plan_key(c, dtype, n);
+    Sched cached{2, 8, 0};
     if (tuning) {
-        Sched sc{2, 8};
+        Sched sc{2, 8, 0};
         if (!parse_int_key(tuning, "\"order\"", &sc.order) || !parse_int_key(tuning, "\"blocks_per_cu\"", &sc.blocks_per_cu))
             return fail(NIF_ERR_INVALID_ARG, "tuning string lacks \"order\" or \"blocks_per_cu\"");
-        if (sc.order < 0 || sc.order > 2 || sc.blocks_per_cu < 1 || sc.blocks_per_cu > 32)
-            return fail(NIF_ERR_INVALID_ARG, "tuning out of range (order 0..2, blocks_per_cu 1..32)");
+        (void)parse_int_key(tuning, "\"shape\"", &sc.shape);  // optional, default 0
+        if (sc.order < 0 || sc.order > 2 || sc.blocks_per_cu < 1 || sc.blocks_per_cu > 32 || sc.shape < 0 ||
+            sc.shape > 2)
+            return fail(NIF_ERR_INVALID_ARG, "tuning out of range (order 0..2, blocks_per_cu 1..32, shape 0..2)");
         p->sched = sc;
+    } else if (cache_lookup(key, &cached)) {
+        p->sched = cached;
+        p->from_cache = true;
     } else {
-        // autotune: every candidate once untimed, then the best of three timed runs
-        const Sched cand[] = {{0, 8}, {0, 16}, {0, 32}, {1, 8}, {1, 16}, {1, 32}, {2, 4}, {2, 8}, {2, 16}, {2, 32}};
+        // autotune: every candidate once untimed, then the best of three timed runs.
+        // Orderings x persistent grid sizes x tile shapes (shapes only where the
+        // kernel has them: 8-level binary16 grids)
+        std::vector<Sched> cand;
+        const int nshape = c->d.levels == 8 && c->d.grid_dtype == NIF_F16 ? 3 : 1;
+        for (int o = 0; o <= 2; ++o)
+            for (int b : {4, 8, 16, 32})
+                for (int sh = 0; sh < nshape; ++sh)
+                    if (!(o == 0 && b == 4)) cand.push_back(Sched{o, b, sh});
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
@@ -1122,6 +1199,7 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
         (void)hipEventDestroy(e1);
         if (st != NIF_OK) return st;
         p->tuned_us = best * 1e3f;
+        cache_store(key, p->sched, p->tuned_us);
     }
     // capture on a private stream (the caller's may be the legacy default stream)
     hipStream_t cs;
@@ -1163,8 +1241,14 @@ extern "C" nif_status nif_plan_launch(nif_plan* p, void* stream) {
 
 extern "C" nif_status nif_plan_tuning(const nif_plan* p, char* buf, size_t buf_bytes) {
     if (!p || !buf) return fail(NIF_ERR_INVALID_ARG, "nif_plan_tuning: NULL argument");
-    const int k = snprintf(buf, buf_bytes, "{\"order\": %d, \"blocks_per_cu\": %d, \"tuned_us\": %.3f, \"candidates\": %d}",
-                           p->sched.order, p->sched.blocks_per_cu, (double)p->tuned_us, p->candidates);
+    int32_t batch = 0, wpe = 0;
+    shape_params(p->sched.shape, p->dtype, p->c->d.levels, p->c->images_ready ? p->c->image_mode : 0, &batch, &wpe);
+    const int k = snprintf(buf, buf_bytes,
+                           "{\"order\": %d, \"blocks_per_cu\": %d, \"shape\": %d, \"gather_batch\": %d, "
+                           "\"waves_per_simd\": %d, \"queries_per_wave\": %d, \"waves_per_block\": %d, "
+                           "\"tuned_us\": %.3f, \"candidates\": %d, \"from_cache\": %s}",
+                           p->sched.order, p->sched.blocks_per_cu, p->sched.shape, batch, wpe, kQueriesPerWave,
+                           kBlock / 64, (double)p->tuned_us, p->candidates, p->from_cache ? "true" : "false");
     if (k < 0 || (size_t)k >= buf_bytes) return fail(NIF_ERR_INVALID_ARG, "nif_plan_tuning: buffer too small");
     return ok();
 }

@@ -151,6 +151,7 @@ static void build_bvh(const float* tris, int64_t T, std::vector<BNode>& nodes, s
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool tri_hit(const float* v, const float o[3], const float d[3], int kx, int ky, int kz,
                                         float Sx, float Sy, float Sz, float tmax, float* t_out = nullptr) {
+#pragma clang fp contract(off)
     const float Ax = v[0 + kx] - o[kx], Ay = v[0 + ky] - o[ky], Az0 = v[0 + kz] - o[kz];
     const float Bx = v[3 + kx] - o[kx], By = v[3 + ky] - o[ky], Bz0 = v[3 + kz] - o[kz];
     const float Cx = v[6 + kx] - o[kx], Cy = v[6 + ky] - o[ky], Cz0 = v[6 + kz] - o[kz];

@@ -114,55 +114,62 @@ __device__ __forceinline__ int lookup_cell(const float u[3][3], int half, int t,
 
 // Encode the lookups of lane half `half` from the grids: NL = 3L/2 lookups, 2
 // features each, local feature c = 2 t + f.  Rows (x, x+1) of the cell at
-// (y, z), (y+1, z), (y, z+1), (y+1, z+1) are one load each.
-template <int L, typename GT>
+// (y, z), (y+1, z), (y, z+1), (y+1, z+1) are one load each.  The loads of G
+// lookups are issued together before their interpolation (G divides NL; the
+// arithmetic does not depend on G).
+template <int L, typename GT, int G>
 __device__ __forceinline__ void encode_half(const float u[3][3], int half, const GLOBAL GT* grid, const FwdArgs& A,
                                             float* x) {
     constexpr int NL = 3 * L / 2;
+    static_assert(NL % G == 0, "batch must divide the lookups");
     constexpr int EW = sizeof(GT) == 2 ? 1 : 2;  // dwords per vertex
-    float w[NL][3];
-    uint32_t q[NL][4][2 * EW];
 #pragma unroll
-    for (int t = 0; t < NL; ++t) {
-        uint32_t c[3];
-        const int k = lookup_cell<L>(u, half, t, A, c, w[t]);
-        const uint32_t N1 = (uint32_t)A.res[k % L] + 1;
-        const uint32_t v = (c[2] * N1 + c[1]) * N1 + c[0];  // < 2^31 for N <= 1024
-        const GLOBAL uint32_t* p = reinterpret_cast<const GLOBAL uint32_t*>(grid + A.toff[k]) + (uint64_t)v * EW;
-        const uint32_t sy = N1 * EW, sz = N1 * N1 * EW;  // in dwords
+    for (int t0 = 0; t0 < NL; t0 += G) {
+        float w[G][3];
+        uint32_t q[G][4][2 * EW];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const GLOBAL uint32_t* pr = p;
-            if (r & 1) pr += sy;
-            if (r >> 1) pr += sz;
-#pragma unroll
-            for (int j = 0; j < 2 * EW; ++j) q[t][r][j] = pr[j];  // one 8- or 16-byte load
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-        float cw[8];
-        corner_weights(w[t], cw);
-        if constexpr (sizeof(GT) == 2) {
-            f16x2v g[8];
+        for (int i = 0; i < G; ++i) {
+            uint32_t c[3];
+            const int k = lookup_cell<L>(u, half, t0 + i, A, c, w[i]);
+            const uint32_t N1 = (uint32_t)A.res[k % L] + 1;
+            const uint32_t v = (c[2] * N1 + c[1]) * N1 + c[0];  // < 2^31 for N <= 1024
+            const GLOBAL uint32_t* p = reinterpret_cast<const GLOBAL uint32_t*>(grid + A.toff[k]) + (uint64_t)v * EW;
+            const uint32_t sy = N1 * EW, sz = N1 * N1 * EW;  // in dwords
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                g[2 * r] = half_pair(q[t][r][0]);      // (x, .)
-                g[2 * r + 1] = half_pair(q[t][r][1]);  // (x+1, .)
-            }
-            interp_pairs(cw, g, x[2 * t], x[2 * t + 1]);
-        } else {
-            float s0 = 0.0f, s1 = 0.0f;
+                const GLOBAL uint32_t* pr = p;
+                if (r & 1) pr += sy;
+                if (r >> 1) pr += sz;
 #pragma unroll
-            for (int cidx = 0; cidx < 8; ++cidx) {
-                const int r = cidx >> 1, bx = cidx & 1;
-                const float g0 = __builtin_bit_cast(float, q[t][r][2 * bx]);
-                const float g1 = __builtin_bit_cast(float, q[t][r][2 * bx + 1]);
-                s0 = cidx ? fmaf(cw[cidx], g0, s0) : cw[0] * g0;
-                s1 = cidx ? fmaf(cw[cidx], g1, s1) : cw[0] * g1;
+                for (int j = 0; j < 2 * EW; ++j) q[i][r][j] = pr[j];  // one 8- or 16-byte load
             }
-            x[2 * t] = s0;
-            x[2 * t + 1] = s1;
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int t = t0 + i;
+            float cw[8];
+            corner_weights(w[i], cw);
+            if constexpr (sizeof(GT) == 2) {
+                f16x2v g[8];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    g[2 * r] = half_pair(q[i][r][0]);      // (x, .)
+                    g[2 * r + 1] = half_pair(q[i][r][1]);  // (x+1, .)
+                }
+                interp_pairs(cw, g, x[2 * t], x[2 * t + 1]);
+            } else {
+                float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+                for (int cidx = 0; cidx < 8; ++cidx) {
+                    const int r = cidx >> 1, bx = cidx & 1;
+                    const float g0 = __builtin_bit_cast(float, q[i][r][2 * bx]);
+                    const float g1 = __builtin_bit_cast(float, q[i][r][2 * bx + 1]);
+                    s0 = cidx ? fmaf(cw[cidx], g0, s0) : cw[0] * g0;
+                    s1 = cidx ? fmaf(cw[cidx], g1, s1) : cw[0] * g1;
+                }
+                x[2 * t] = s0;
+                x[2 * t + 1] = s1;
+            }
         }
     }
 }
@@ -170,12 +177,10 @@ __device__ __forceinline__ void encode_half(const float u[3][3], int half, const
 // The same lookups from the y-pair image of a binary16 grid: two 16-byte loads
 // per lookup (the z and z+1 faces) instead of four row loads, same corner
 // order, so the features are bit-identical to encode_half.
-constexpr int kImageBatch = 6;  // lookups whose loads are issued together
-template <int L>
+template <int L, int G>
 __device__ __forceinline__ void encode_half_image(const float u[3][3], int half, const GLOBAL _Float16* img,
                                                   const FwdArgs& A, float* x) {
     constexpr int NL = 3 * L / 2;
-    constexpr int G = NL < kImageBatch ? NL : kImageBatch;
     static_assert(NL % G == 0, "batch must divide the lookups");
 #pragma unroll
     for (int t0 = 0; t0 < NL; t0 += G) {
@@ -219,11 +224,10 @@ __device__ __forceinline__ void encode_half_image(const float u[3][3], int half,
 // corners of a cell are 32 contiguous bytes (entries x and x+1): two 16-byte
 // loads from one cache line (except when the pair straddles a line), same
 // corner order as encode_half.
-template <int L>
+template <int L, int G>
 __device__ __forceinline__ void encode_half_image2(const float u[3][3], int half, const GLOBAL _Float16* img,
                                                    const FwdArgs& A, float* x) {
     constexpr int NL = 3 * L / 2;
-    constexpr int G = NL < kImageBatch ? NL : kImageBatch;
     static_assert(NL % G == 0, "batch must divide the lookups");
 #pragma unroll
     for (int t0 = 0; t0 < NL; t0 += G) {
@@ -269,8 +273,16 @@ __device__ __forceinline__ int32_t slot_object(const FwdArgs& A, int64_t slot) {
 // ----------------------------------------------------------------------------
 // MODE 0: fused query.  MODE 1: grid stage only (writes the MLP inputs and the
 // clip status).  MODE 2: inference stage only (reads MLP inputs, one MLP).
-template <int FLAV, int L, typename GT, int MODE, int IMG>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == kF32 ? 2 : 3))) void nif_query_kernel(FwdArgs A) {
+// Tile shapes of the fused kernel (chosen by the plan tuner): lookups whose
+// gathers are issued together, and the waves per SIMD the register budget is
+// cut for.  Shape 0 is the default.  The outputs do not depend on the shape.
+constexpr int shape_batch(int SH, int NL, bool image) {
+    return SH == 1 ? (image ? NL : NL / 2) : SH == 2 ? 3 : (image ? 6 : NL);
+}
+constexpr int shape_waves(int FLAV, int SH) { return SH == 1 ? 2 : SH == 2 ? 4 : (FLAV == kF32 ? 2 : 3); }
+
+template <int FLAV, int L, typename GT, int MODE, int IMG, int SH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_waves(FLAV, SH)))) void nif_query_kernel(FwdArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int KH1 = 3 * L;  // layer-1 local inputs per half: 3L/2 lookups x 2 latents
     const int lane = threadIdx.x & 63;
@@ -376,12 +388,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FLAV == 
                 status = clip_normalise(o, d, tm, ob, u);
                 if (status == 1) {
                     mlp = ob.mlp;
+                    constexpr int NL = 3 * L / 2;
                     if constexpr (IMG == 1)
-                        encode_half_image<L>(u, half, (const GLOBAL _Float16*)(ob.image), A, xin);
+                        encode_half_image<L, shape_batch(SH, NL, true)>(u, half, (const GLOBAL _Float16*)(ob.image),
+                                                                         A, xin);
                     else if constexpr (IMG == 2)
-                        encode_half_image2<L>(u, half, (const GLOBAL _Float16*)(ob.image), A, xin);
+                        encode_half_image2<L, shape_batch(SH, NL, true)>(u, half, (const GLOBAL _Float16*)(ob.image),
+                                                                          A, xin);
                     else
-                        encode_half<L, GT>(u, half, (const GLOBAL GT*)(ob.grid), A, xin);
+                        encode_half<L, GT, shape_batch(SH, NL, false)>(u, half, (const GLOBAL GT*)(ob.grid), A, xin);
                 }
             }
         }
@@ -509,7 +524,7 @@ hipError_t launch_mlp16(int flavor, int levels, const FwdArgs& a, int num_cus, h
     return hipErrorInvalidValue;
 }
 
-template <int FLAV, int L, typename GT, int MODE, int IMG>
+template <int FLAV, int L, typename GT, int MODE, int IMG, int SH>
 static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     FwdArgs a = a0;
     const int64_t tiles = (a.n + kQueriesPerBlock - 1) / kQueriesPerBlock;
@@ -522,12 +537,23 @@ static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     a.xcd_stride = (int32_t)(blocks / 8);
     const size_t lds = MODE == 1 ? 0 : lds_bytes(a.pack);
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE, IMG>,
+        hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE, IMG, SH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((nif_query_kernel<FLAV, L, GT, MODE, IMG>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((nif_query_kernel<FLAV, L, GT, MODE, IMG, SH>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
     return hipGetLastError();
+}
+
+// Shapes other than 0 exist for the fused query of 8-level binary16 grids
+// (the large workloads the plan tuner serves); elsewhere shape 0 runs.
+template <int FLAV, int MODE, int IMG>
+static hipError_t launch_shaped(const FwdArgs& a, int num_cus, hipStream_t s) {
+    if constexpr (MODE == 0) {
+        if (a.shape == 1) return launch_t<FLAV, 8, _Float16, MODE, IMG, 1>(a, num_cus, s);
+        if (a.shape == 2) return launch_t<FLAV, 8, _Float16, MODE, IMG, 2>(a, num_cus, s);
+    }
+    return launch_t<FLAV, 8, _Float16, MODE, IMG, 0>(a, num_cus, s);
 }
 
 template <int FLAV, int MODE>
@@ -535,16 +561,16 @@ static hipError_t launch_f(int levels, int grid_dtype, const FwdArgs& a, int num
     const int img = MODE != 2 && grid_dtype == 1 ? a.use_image : 0;
     if (levels == 8) {
         if (grid_dtype == 1)
-            return img == 2   ? launch_t<FLAV, 8, _Float16, MODE, 2>(a, num_cus, s)
-                   : img == 1 ? launch_t<FLAV, 8, _Float16, MODE, 1>(a, num_cus, s)
-                              : launch_t<FLAV, 8, _Float16, MODE, 0>(a, num_cus, s);
-        return launch_t<FLAV, 8, float, MODE, 0>(a, num_cus, s);
+            return img == 2   ? launch_shaped<FLAV, MODE, 2>(a, num_cus, s)
+                   : img == 1 ? launch_shaped<FLAV, MODE, 1>(a, num_cus, s)
+                              : launch_shaped<FLAV, MODE, 0>(a, num_cus, s);
+        return launch_t<FLAV, 8, float, MODE, 0, 0>(a, num_cus, s);
     }
     if (grid_dtype == 1)
-        return img == 2   ? launch_t<FLAV, 4, _Float16, MODE, 2>(a, num_cus, s)
-               : img == 1 ? launch_t<FLAV, 4, _Float16, MODE, 1>(a, num_cus, s)
-                          : launch_t<FLAV, 4, _Float16, MODE, 0>(a, num_cus, s);
-    return launch_t<FLAV, 4, float, MODE, 0>(a, num_cus, s);
+        return img == 2   ? launch_t<FLAV, 4, _Float16, MODE, 2, 0>(a, num_cus, s)
+               : img == 1 ? launch_t<FLAV, 4, _Float16, MODE, 1, 0>(a, num_cus, s)
+                          : launch_t<FLAV, 4, _Float16, MODE, 0, 0>(a, num_cus, s);
+    return launch_t<FLAV, 4, float, MODE, 0, 0>(a, num_cus, s);
 }
 
 hipError_t launch_forward(int flavor, int levels, int grid_dtype, const FwdArgs& a, int num_cus, hipStream_t s) {

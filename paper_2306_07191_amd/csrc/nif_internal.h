@@ -73,6 +73,7 @@ struct FwdArgs {
     uint32_t* flags;              // domain-error bits of the launch are OR-ed in here (nullable)
     int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
     const float4* qrec;           // nullable: query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
+    int32_t shape;                // tile shape of the fused query (0 default, 1, 2; see shape_batch)
 };
 
 // The paper's own networks: per object its box and its grid buffer of each

@@ -371,8 +371,8 @@ class Plan:
         return self.out
 
     def tuning(self) -> str:
-        buf = C.create_string_buffer(256)
-        _check(lib().nif_plan_tuning(self.h, buf, 256), "nif_plan_tuning")
+        buf = C.create_string_buffer(1024)
+        _check(lib().nif_plan_tuning(self.h, buf, 1024), "nif_plan_tuning")
         return buf.value.decode()
 
     def close(self):

@@ -49,13 +49,19 @@ def test_closest_hit_matches_oracle(case):
         tris, rays, tmax = w["tris"], w["rays"], w["tmax"]
         tmax = np.where(g.uniform(size=tmax.shape[0]) < 0.3, g.uniform(0.5, 4, tmax.shape[0]), tmax).astype(np.float32)
         ref = O.closest_brute(tris, rays, tmax)
+        _, ref32 = O.trace_brute32(tris, rays, tmax)
     else:
         tris = S.frame_mesh()
         rays, tmax = _camera_rays(20000, S.mesh_aabb(tris), g)
-        ref = O.BVH(tris).closest(rays, tmax)
+        ob = O.BVH(tris)
+        ref = ob.closest(rays, tmax)
+        _, ref32 = ob.trace32(rays, tmax)
     bvh = nif.BVH(tris)
-    t = bvh.closest(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy().astype(np.float64)
+    t32 = bvh.closest(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy()
     bvh.close()
+    # the nearest binary32 hit distance, decision for decision: bit-exact
+    np.testing.assert_array_equal(t32, ref32)
+    t = t32.astype(np.float64)
     both = np.isfinite(t) & np.isfinite(ref)
     agree = float((np.isfinite(t) == np.isfinite(ref)).mean())
     rel = np.abs(t[both] - ref[both]) / ref[both]

@@ -31,7 +31,8 @@ def test_plan_matches_eager_and_oracle_over_replays(dtype):
     z = torch.empty(ids.shape[0], device="cuda")
     plan = nif.Plan(ctx, rays, ids, tmax, dtype=dtype, logits=z)
     tun = json.loads(plan.tuning())
-    assert tun["candidates"] == 10 and tun["order"] in (0, 1, 2) and tun["tuned_us"] > 0
+    # 4-level grids: orderings x grid sizes (no tile shapes besides the default)
+    assert tun["candidates"] == 11 and tun["order"] in (0, 1, 2) and tun["tuned_us"] > 0 and tun["shape"] == 0
     torch.cuda.synchronize()
     check_outputs(plan.out.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64),
                   model.forward(w["rays"], w["ids"], w["tmax"]), dtype, f"plan {dtype}")
@@ -56,6 +57,52 @@ def test_plan_matches_eager_and_oracle_over_replays(dtype):
     np.testing.assert_array_equal(plan2.out.cpu().numpy(), plan.out.cpu().numpy())
     plan.close()
     plan2.close()
+
+
+def test_plan_tile_shapes_and_tuning_cache(tmp_path, monkeypatch):
+    """8-level binary16 grids (the frame's shape, two objects): the tuner also
+    times the fused kernel's tile shapes; every shape gives bit-identical
+    outputs; with NIF_PLAN_CACHE set a tuned schedule is stored, and the next
+    plan for the same key reads it instead of tuning."""
+    import torch
+    from paper_2306_07191_amd import nif
+    K, n = 2, 200000
+    w = S.multi_workload(n_objects=K, n_rays=n)
+    w["shape"] = S.FRAME
+    w["mlps"] = np.stack([S.xavier_mlp(S.FRAME, S.rng(61, 3, k)) for k in range(K)])
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    ctx.prepare("bf16")
+    rays, ids, tmax = (torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax"))
+    outs = []
+    for shape in (0, 1, 2):
+        p = nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning=f'{{"order": 2, "blocks_per_cu": 8, "shape": {shape}}}')
+        t = json.loads(p.tuning())
+        assert t["shape"] == shape and t["gather_batch"] == {0: 12, 1: 6, 2: 3}[shape]
+        assert t["waves_per_simd"] == {0: 3, 1: 2, 2: 4}[shape]
+        p.launch()
+        torch.cuda.synchronize()
+        outs.append(p.out.cpu().numpy().copy())
+        p.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+    cache = tmp_path / "plans.jsonl"
+    monkeypatch.setenv("NIF_PLAN_CACHE", str(cache))
+    p1 = nif.Plan(ctx, rays, ids, tmax, dtype="bf16")
+    t1 = json.loads(p1.tuning())
+    assert t1["candidates"] == 33 and not t1["from_cache"] and t1["tuned_us"] > 0
+    line = json.loads(cache.read_text().strip().splitlines()[-1])
+    assert "gfx950" in line["key"] and line["shape"] == t1["shape"] and line["order"] == t1["order"]
+    p2 = nif.Plan(ctx, rays, ids, tmax, dtype="bf16")
+    t2 = json.loads(p2.tuning())
+    assert t2["from_cache"] and t2["candidates"] == 0
+    assert (t2["order"], t2["blocks_per_cu"], t2["shape"]) == (t1["order"], t1["blocks_per_cu"], t1["shape"])
+    p2.launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(p2.out.cpu().numpy(), outs[0])
+    p1.close()
+    p2.close()
+    ctx.close()
 
 
 def test_plan_rejects_bad_arguments():

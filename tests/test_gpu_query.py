@@ -345,27 +345,35 @@ def test_packed_query_records():
 
 
 def test_gpu_bvh_labels_match_oracle():
-    """GPU BVH any-hit (binary32 watertight test) vs the oracle's exact binary64 labels."""
+    """GPU BVH any-hit (binary32 watertight test): every label equal to the
+    oracle's binary32 test over all triangles (the decision is taken in the
+    kernel's precision on both sides); agreement with the exact binary64
+    labels reported and bounded."""
     import torch
     from oracle import oracle as O
     from paper_2306_07191_amd import nif
     w = S.tiny_workload()
     w["tmax"] = np.where(np.arange(w["tmax"].size) % 3 == 0, 3.0, w["tmax"]).astype(np.float32)
-    ref = O.anyhit_brute(w["tris"], w["rays"], w["tmax"])
+    ref32, _ = O.trace_brute32(w["tris"], w["rays"], w["tmax"])
+    ref64 = O.anyhit_brute(w["tris"], w["rays"], w["tmax"])
     bvh = nif.BVH(w["tris"])
     got = bvh.anyhit(torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()).cpu().numpy()
-    agree = (got == ref).mean()
-    print("tiny labels agreement", agree, "visible", ref.mean())
-    assert agree >= 0.9999
+    print("tiny labels: binary32 oracle mismatches", int((got != ref32).sum()), "binary64 agreement",
+          (got == ref64).mean(), "visible", ref64.mean())
+    np.testing.assert_array_equal(got, ref32)
+    assert (got == ref64).mean() >= 0.9999
     # frame mesh, a sample of frame rays against the oracle BVH
     tris = S.frame_mesh()
     rays, tmax = S.rays_ground_to_light(20000, S.rng(2, 1))
-    ref = O.BVH(tris).anyhit(rays, tmax)
+    ob = O.BVH(tris)
+    ref32, _ = ob.trace32(rays, tmax)
+    ref64 = ob.anyhit(rays, tmax)
     bvh2 = nif.BVH(tris)
     got = bvh2.anyhit(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy()
-    agree = (got == ref).mean()
-    print("frame labels agreement", agree, "visible", ref.mean(), "nodes", bvh2.num_nodes)
-    assert agree >= 0.9999
+    print("frame labels: binary32 oracle mismatches", int((got != ref32).sum()), "binary64 agreement",
+          (got == ref64).mean(), "visible", ref64.mean(), "nodes", bvh2.num_nodes)
+    np.testing.assert_array_equal(got, ref32)
+    assert (got == ref64).mean() >= 0.9999
     empty = nif.BVH(np.zeros((0, 9), np.float32))
     assert (empty.anyhit(torch.from_numpy(rays).cuda(), torch.from_numpy(tmax).cuda()).cpu().numpy() == 1).all()
 

@@ -45,11 +45,20 @@ def test_mlp_matches_oracle(dtype):
     torch.cuda.synchronize()
     z = z.cpu().numpy().astype(np.float64)
     mq = model.with_(quant="exact" if dtype == "f32" else dtype)
-    zr = mq.mlp_only(x.astype(np.float64))
+    r = mq.mlp_only(x.astype(np.float64), want_tol=True)
+    zr = r["z"]
     err = np.abs(z - zr)
-    tol = 1e-5 * np.maximum(np.abs(zr), 1e-2) if dtype == "f32" else 2e-2 * np.maximum(np.abs(zr), 1e-1)
-    print(dtype, "max err", err.max(), "median", np.median(err))
-    assert (err <= tol).mean() >= 0.999, (err.max(), np.median(err))
+    print(dtype, "max err", err.max(), "median", np.median(err), "max err / ztol", (err / r["ztol"]).max())
+    if dtype == "f32":
+        assert (err <= 1e-5 * np.maximum(np.abs(zr), 1e-2)).all(), err.max()
+    else:
+        # emulated rounding: within the binary32-summation tolerance (plus one
+        # quantum at flagged rounding decisions) for >= 99.9 %, and every query's
+        # visibility within the propagated rounding bound of the unquantised result
+        assert (err <= r["ztol"]).mean() >= 0.999, (err / r["ztol"]).max()
+        ze = model.with_(quant="exact").mlp_only(x.astype(np.float64))
+        dy = np.abs(1 / (1 + np.exp(-z)) - 1 / (1 + np.exp(-ze)))
+        assert (dy <= r["ybound"]).all(), (dy / r["ybound"]).max()
 
 
 @pytest.mark.parametrize("hidden", [1, 2])

@@ -87,14 +87,29 @@ def test_adam_step_matches_oracle():
     T1, mT, vT = O.adam_step(theta0, gm, gv, gg64, 3, lazy=True, **hp)
     Wg = ctx.mlps[0].cpu().numpy().astype(np.float64)
     Tg = ctx.grids[0].cpu().numpy().astype(np.float64)
-    # Adam is smooth in g here (v > 0): the update error is dominated by the gradient's
-    # binary32 error; compare the steps themselves
-    dW, dWg = W1 - W0, Wg - W0
-    assert np.linalg.norm(dWg - dW) <= 1e-3 * np.linalg.norm(dW)
-    dT, dTg = T1 - theta0, Tg - theta0
+    # Element by element.  Adam is smooth in g here (v > 0), so the device's
+    # update differs from the oracle's by at most |d step / d g| times the
+    # gradient's binary32 error (bounded by the gradient parity criterion:
+    # 1e-3 of the largest |g|), plus the rounding of the stored value: a few
+    # binary32 ulps for the weights, one binary16 ulp for the latents.
+    def sens(theta, m, v, g):
+        h = 1e-6 * np.maximum(np.abs(g), 1e-12)
+        up = O.adam_step(theta, m, v, g + h, 3, lazy=False, **hp)[0]
+        dn = O.adam_step(theta, m, v, g - h, 3, lazy=False, **hp)[0]
+        return np.abs(up - dn) / (2 * h)
+    dgW = 1e-3 * np.abs(gW[0]).max()
+    tolW = sens(W0, mm, vv, gW[0]) * dgW + 4 * np.spacing(np.abs(W1).astype(np.float32)).astype(np.float64)
+    errW = np.abs(Wg - W1)
+    print("MLP Adam: max err / tol", (errW / tolW).max())
+    assert (errW <= tolW).all()
     touched = gg64 != 0
-    assert np.linalg.norm(dTg - dT) <= 1e-3 * np.linalg.norm(dT)
-    assert (dTg[~touched] == 0).all()  # lazy rule: untouched latents keep their value
+    dgT = 1e-3 * np.abs(gg64).max()
+    ulp16 = np.spacing(np.abs(T1[touched]).astype(np.float16)).astype(np.float64)
+    tolT = sens(theta0[touched], gm[touched], gv[touched], gg64[touched]) * dgT + ulp16
+    errT = np.abs(Tg[touched] - T1[touched])
+    print("latent Adam: max err / tol", (errT / tolT).max())
+    assert (errT <= tolT).all()
+    assert (Tg[~touched] == theta0[~touched]).all()  # lazy rule: untouched latents keep their value
     np.testing.assert_allclose(ctx.train_bufs[0][1].cpu().numpy()[~touched], gm[~touched])
     assert (ctx.train_bufs[0][0].cpu().numpy() == 0).all()  # gradient left zero
 
