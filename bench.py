@@ -81,6 +81,48 @@ def measured_traffic(name: str):
     return rec["traffic_bytes_per_launch"]
 
 
+def latent_footprint(rays, tmax, ids, aabb, level_res, feats: int, elem_bytes: int):
+    """Compulsory latent bytes of one launch over these queries: the number of
+    distinct grid vertices (object, table, level, vertex) that the trilinear
+    lookups of all queries touch, times F latents of elem_bytes each, and the
+    number of distinct 64-byte lines those vertices lie on.  Coordinates in
+    binary64 (a vertex on a cell boundary may differ from the kernel's binary32
+    choice; the count is a measurement, not a parity check).  Torch ops on the
+    queries' device.  Returns (vertices, bytes, lines64)."""
+    import torch
+    dev = rays.device
+    box = torch.as_tensor(np.asarray(aabb, np.float64), device=dev)
+    r = rays.double()
+    o, d = r[:, :3], r[:, 3:]
+    k = ids.long()
+    lo, hi = box[k, :3], box[k, 3:]
+    inv = 1.0 / d
+    t1, t2 = (lo - o) * inv, (hi - o) * inv
+    ta = torch.clamp(torch.minimum(t1, t2).amax(1), min=0.0)
+    tb = torch.minimum(torch.maximum(t1, t2).amin(1), tmax.double())
+    ok = ta <= tb
+    o, d, k, lo, hi, ta, tb = o[ok], d[ok], k[ok], lo[ok], hi[ok], ta[ok], tb[ok]
+    ext = hi - lo
+    u = [((o + ta[:, None] * d - lo) / ext).clamp(0, 1), ((o + tb[:, None] * d - lo) / ext).clamp(0, 1),
+         ((d / d.norm(dim=1, keepdim=True) + 1) * 0.5).clamp(0, 1)]
+    verts, lines = 0, 0
+    for ut in u:
+        for N in level_res:
+            N = int(N)
+            c = torch.clamp(torch.floor(ut * N).long(), max=N - 1)
+            keys = []
+            for cz in (0, 1):
+                for cy in (0, 1):
+                    for cx in (0, 1):
+                        v = ((c[:, 2] + cz) * (N + 1) + (c[:, 1] + cy)) * (N + 1) + (c[:, 0] + cx)
+                        keys.append(k * (1 << 40) + v)
+            keys = torch.unique(torch.cat(keys))
+            verts += keys.numel()
+            ln = (keys >> 40) * (1 << 40) + ((keys & ((1 << 40) - 1)) * feats * elem_bytes) // 64
+            lines += torch.unique(ln).numel()
+    return verts, verts * feats * elem_bytes, lines
+
+
 def cpu_baseline(w, gpu_y, budget_s: float = 12.0):
     """The binary64 oracle on the host cores over a bounded sample of the same
     queries; also the error of the GPU outputs on that sample."""
@@ -597,6 +639,8 @@ def run_scene(args):
     expand()
     P = int(cnt.item())  # the same rays every step: the pair count is fixed
     assert P <= maxp
+    # compulsory latent bytes of one query launch over these pairs
+    fp = latent_footprint(pr[:P], pt[:P], pi[:P], w["aabb"], ctx.level_res, sh.feats, 2)
     yq = torch.empty(P, dtype=torch.float32, device="cuda")
     perm = torch.empty(P, dtype=torch.int32, device="cuda")
     recs = torch.empty((P, 8), dtype=torch.float32, device="cuda")
@@ -607,22 +651,27 @@ def run_scene(args):
     mask_ref = lab.reshape(-1, S.SCENE_SPP).mean(axis=1)
     stream = torch.cuda.current_stream()
     # schedule: ordering with or without the window sort (the finer Morton key),
-    # whichever makes the headline step faster on these pairs
+    # and the fused kernel's tile shape, whichever makes the headline step
+    # fastest on these pairs
     ctx.prepare(SCENE_DTYPE)
     sched = {}
     for wsort in (1, 0):
-        ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
+        for shape in (0, 1, 2):
+            ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
+            ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
 
-        def one():
-            expand()
-            ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
-            ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
-            ctx.combine_pairs(pray[:P], yq, n, out=vis)
+            def one():
+                expand()
+                ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
+                ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
+                ctx.combine_pairs(pray[:P], yq, n, out=vis)
 
-        sched[wsort] = time_launches(one, 10, 3) * 1e3
-    window_sort = min(sched, key=sched.get)
+            sched[(wsort, shape)] = time_launches(one, 10, 3) * 1e3
+    window_sort, tile_shape = min(sched, key=sched.get)
     ctx.set_option(nif.NIF_OPT_WINDOW_SORT, window_sort)
-    log(f"step with window sort {sched[1]:.3f} ms, without {sched[0]:.3f} ms: window sort {'on' if window_sort else 'off'}")
+    ctx.set_option(nif.NIF_OPT_TILE_SHAPE, tile_shape)
+    log("step ms by (window sort, tile shape): " + ", ".join(f"{k}: {v:.3f}" for k, v in sched.items()) +
+        f"; chosen {(window_sort, tile_shape)}")
     for dt in ((SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")):
         ctx.prepare(dt)
         steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
@@ -674,8 +723,48 @@ def run_scene(args):
         for dt in res:
             res[dt]["added_misclassification_vs_f32"] = res[dt]["misclassification"] - res["f32"]["misclassification"]
 
+    # early-out form (Sec. 7): each ray's first box in round 1, the other pairs of
+    # the rays still visible in round 2; the same per-ray result with fewer queries
+    ctx.prepare(SCENE_DTYPE)
+    expand()  # the one-round result of the headline dtype, for comparison
+    ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
+    ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
+    vis_all = ctx.combine_pairs(pray[:P], yq, n)
+    vis2 = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def expand_round(rnd):
+        nif._check(L.nif_expand_pairs_round(ctx.h, rays.data_ptr(), tmax.data_ptr(), n, rnd, vis2.data_ptr(), maxp,
+                                            pr.data_ptr(), pt.data_ptr(), pi.data_ptr(), pray.data_ptr(),
+                                            cnt.data_ptr(), pws.data_ptr(), pws.numel(), nif._stream()),
+                   "nif_expand_pairs_round")
+
+    counts = []
+    for rnd in (1, 2):  # pair counts of the two rounds (fixed for these rays)
+        expand_round(rnd)
+        counts.append(int(cnt.item()))
+        ctx.order_packed(pr[:counts[-1]], pi[:counts[-1]], pt[:counts[-1]], perm=perm[:counts[-1]],
+                         packed=recs[:counts[-1]], ws=ows)
+        ctx.query_packed(recs[:counts[-1]], perm[:counts[-1]], dtype=SCENE_DTYPE, out=yq[:counts[-1]])
+        ctx.combine_pairs(pray[:counts[-1]], yq[:counts[-1]], n, out=vis2, accumulate=rnd == 2)
+    P1, P2 = counts
+
+    def early_out_step():
+        for rnd, Pr in ((1, P1), (2, P2)):
+            expand_round(rnd)
+            ctx.order_packed(pr[:Pr], pi[:Pr], pt[:Pr], perm=perm[:Pr], packed=recs[:Pr], ws=ows)
+            ctx.query_packed(recs[:Pr], perm[:Pr], dtype=SCENE_DTYPE, out=yq[:Pr])
+            ctx.combine_pairs(pray[:Pr], yq[:Pr], n, out=vis2, accumulate=rnd == 2)
+
+    eo_sec = time_launches(early_out_step, max(5, args.steps // 2), args.warmup)
+    early_out = {"ms": eo_sec * 1e3, "rays_per_s": n / eo_sec, "pairs_round1": P1, "pairs_round2": P2,
+                 "pairs_one_round": P, "same_ray_visibility": bool(torch.equal(vis2, vis_all)),
+                 "vs_one_round_ms": res[SCENE_DTYPE]["ms"]}
+    log(f"early-out ({SCENE_DTYPE}): {P1} + {P2} pairs in two rounds against {P} in one, step {eo_sec * 1e3:.3f} ms "
+        f"against {res[SCENE_DTYPE]['ms']:.3f} ms; same ray visibility: {early_out['same_ray_visibility']}")
+
     cpu, errs = None, None
     if not (args.no_cpu or args.quick):
+        expand()  # the one-round pairs again (the early-out rounds wrote over them), the order of gpu_y
         pairs = (pr[:P].cpu().numpy(), pi[:P].cpu().numpy(), pt[:P].cpu().numpy())
         t0 = time.perf_counter()
         cpu, errs = scene_oracle_errors(ctx, w, sh, pairs, gpu_y, scales)
@@ -683,7 +772,28 @@ def run_scene(args):
             f"{cpu['cores']} cores; errors {json.dumps(errs)}")
     head = res[SCENE_DTYPE]
     tq = head["stage_ms"]["query_kernel"] / 1e3
-    achieved = flops * P / tq / 1e12
+    # algorithmic work of one launch: FLOP of the MLPs, and compulsory bytes =
+    # 36 B of query I/O per query (32-byte record, 4-byte output) plus the
+    # distinct latents touched; the larger time at peak names the bound
+    alg_bytes = 36 * P + fp[1]
+    t_mfma, t_hbm = flops * P / (PEAK_TFLOPS[SCENE_DTYPE] * 1e12), alg_bytes / (HBM_PEAK_GBS * 1e9)
+    log(f"compulsory bytes per launch: {alg_bytes / 1e6:.1f} MB ({fp[0]} distinct vertices on {fp[2]} 64-byte "
+        f"lines): {t_hbm * 1e6:.1f} us at peak HBM against {t_mfma * 1e6:.1f} us of MFMA work")
+    if t_hbm >= t_mfma:
+        achieved = alg_bytes / tq / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    else:
+        achieved = flops * P / tq / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE]}
+    roof.update({"traffic": measured_traffic("scene"),
+                 "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, no image> (fused clip+encode+MLP)",
+                 "kernel_us": tq * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
+                 "distinct_latent_vertices": fp[0], "distinct_64b_lines": fp[2],
+                 "algorithmic_flop_per_launch": flops * P,
+                 "mfma_frac": flops * P / tq / 1e12 / PEAK_TFLOPS[SCENE_DTYPE],
+                 "t_min_us": {"hbm": t_hbm * 1e6, "mfma": t_mfma * 1e6}})
     out = {
         "metric": "shadow-ray visibility queries/sec at stated error vs FP64 oracle",
         "value": head["pairs_per_s"],
@@ -702,15 +812,14 @@ def run_scene(args):
                                "per object",
                    "rays": n, "pairs": P, "objects": K, "triangles": int(w["tri_counts"].sum()),
                    "step": "pair expansion + pair ordering + fused query kernel + per-ray combination",
-                   "window_sort": bool(window_sort), "step_ms_by_window_sort": {"on": sched[1], "off": sched[0]},
+                   "window_sort": bool(window_sort), "tile_shape": tile_shape,
+                   "step_ms_by_window_sort_and_shape": {f"{k[0]}/{k[1]}": v for k, v in sched.items()},
                    "value_is": "(ray, object) queries per second; rays_per_s is in per_dtype"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE], "traffic": measured_traffic("scene"),
-                     "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, no image> (fused clip+encode+MLP)",
-                     "algorithmic_flop_per_launch": flops * P, "kernel_us": tq * 1e6},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "error_vs_binary64_oracle_trained": errs,
         "per_dtype": res,
+        "early_out": early_out,
         "bvh_all_triangles": {"ms": bvh_sec * 1e3, "rays_per_s": n / bvh_sec, "nodes": bvh_nodes,
                               "host_build_s": build_s, "occluded_fraction": float(1 - lab.mean())},
         "speedup_vs_bvh": bvh_sec * 1e3 / head["ms"],
@@ -1094,6 +1203,15 @@ def run_frame(args):
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     recs = torch.empty((n, 8), dtype=torch.float32, device="cuda")  # the queries as 32-byte records
     ows = torch.empty(max(1, nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
+    # the fused kernel's tile shape: the fastest of the three on this step
+    shape_us = {}
+    for shape in (0, 1, 2):
+        ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
+        ctx.order_packed(rays, ids, tmax, perm=perm, packed=recs, ws=ows)
+        shape_us[shape] = time_launches(lambda: ctx.query_packed(recs, perm, dtype=HEADLINE_DTYPE, out=y), 10, 2) * 1e6
+    tile_shape = min(shape_us, key=shape_us.get)
+    ctx.set_option(nif.NIF_OPT_TILE_SHAPE, tile_shape)
+    log("fused kernel us by tile shape: " + ", ".join(f"{k}: {v:.1f}" for k, v in shape_us.items()))
 
     def step():
         ctx.order_packed(rays, ids, tmax, perm=perm, packed=recs, ws=ows)
@@ -1166,7 +1284,7 @@ def run_frame(args):
         "dtype": HEADLINE_DTYPE,
         "data": "synthetic (seeded frame scene: 2,073,600 ground-to-area-light shadow rays; init-distribution latents and Xavier weights)",
         "config": {"workload": "frame: 1920x1080 shadow rays, 1 object, 8 levels 16..512, 2 binary16 latents, MLP 48-64x4-1",
-                   "grid_image": "z-y-pair",
+                   "grid_image": "z-y-pair", "tile_shape": tile_shape, "kernel_us_by_tile_shape": shape_us,
                    "queries": n, "levels": sh.levels, "res_min": sh.res_min, "res_max": sh.res_max,
                    "hidden": sh.hidden, "width": sh.width, "grid_dtype": sh.grid_dtype},
         "roofline": roofline,

@@ -129,6 +129,24 @@ nif_status nif_expand_pairs(nif_ctx* ctx, const float* rays, const float* t_max,
 nif_status nif_combine_pairs(nif_ctx* ctx, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
                              int64_t n_rays, uint8_t* ray_visible, void* stream);
 
+/* The early-out form (Sec. 7: once one object is found to occlude a ray, its
+ * other objects need not be queried), in two rounds over the same rays:
+ * nif_expand_pairs_round with round = 1 writes each ray's first pair only, the
+ *   box the ray enters first (smallest t_a, ties to the smaller object id);
+ *   query them and combine with nif_combine_pairs.
+ * round = 2 writes the other pairs of the rays whose ray_visible (dev, n_rays
+ *   bytes, from round 1) is non-zero; query them and combine with
+ *   nif_combine_pairs_and, which only clears ray_visible[r] for a pair below
+ *   0.5 (no reset to 1).
+ * The per-ray result equals nif_combine_pairs over all of nif_expand_pairs'
+ * pairs.  Other arguments, order and limits as nif_expand_pairs. */
+nif_status nif_expand_pairs_round(nif_ctx* ctx, const float* rays, const float* t_max, int64_t n_rays, int32_t round,
+                                  const uint8_t* ray_visible, int64_t max_pairs, float* pair_rays, float* pair_tmax,
+                                  int32_t* pair_ids, uint32_t* pair_ray, int64_t* pair_count, void* ws,
+                                  size_t ws_bytes, void* stream);
+nif_status nif_combine_pairs_and(nif_ctx* ctx, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
+                                 int64_t n_rays, uint8_t* ray_visible, void* stream);
+
 /* Domain-error bits OR-ed together by every nif_query, nif_query_ordered,
  * nif_encode and plan launch of this context since the last clear: queries
  * whose output is NaN.  NIF_FLAG_INVALID_RAY: non-finite origin or direction,
@@ -182,9 +200,11 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * (re)builds them from the grids.  Changing the mode forgets the registered
  * buffers.  NIF_OPT_WINDOW_SORT: whether ordering (nif_query, nif_order,
  * nif_order_packed) also sorts each 4,096-query window by the finer key:
- * 0 never, 1 always, 2 (default) when NIF_OPT_GRID_IMAGE is 0.  Outputs are
- * bit-identical in every mode. */
-enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2, NIF_OPT_WINDOW_SORT = 3 };
+ * 0 never, 1 always, 2 (default) when NIF_OPT_GRID_IMAGE is 0.
+ * NIF_OPT_TILE_SHAPE: the fused kernel's tile shape (0 default, 1, 2; see
+ * nif_plan_create) for queries outside plans.  Outputs are bit-identical in
+ * every mode. */
+enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2, NIF_OPT_WINDOW_SORT = 3, NIF_OPT_TILE_SHAPE = 4 };
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 
 /* Query images (NIF_OPT_GRID_IMAGE 1 or 2): nif_image_bytes is the size in
@@ -197,8 +217,10 @@ nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 size_t nif_image_bytes(const nif_ctx* ctx);
 nif_status nif_set_image(nif_ctx* ctx, int32_t obj, void* image, size_t bytes);
 
-/* Workspace bytes needed by nif_query (mode 0), nif_train_step (mode 1) or
- * nif_calibrate_fp8 (mode 2) for n queries. */
+/* Workspace bytes needed by nif_query (mode 0: with ordering, the ordering
+ * workspace, the 32-byte query records and the fused kernel's tile counters;
+ * 0 without ordering), nif_train_step (mode 1) or nif_calibrate_fp8 (mode 2)
+ * for n queries. */
 size_t nif_workspace_bytes(const nif_ctx* ctx, int64_t n, int32_t mode);
 
 /* Visibility of n (ray, object) queries (Sec. 4.1: one query per object AABB
@@ -248,7 +270,16 @@ nif_status nif_query_noalloc(nif_ctx* ctx, int32_t dtype, const float* rays, con
  *   pieces of three arrays.
  * nif_query_packed: as nif_query_ordered with the queries given as those
  *   records (row perm[i] is computed in slot i, output perm[i]).  nif_query
- *   with ordering does the same internally. */
+ *   with ordering does the same internally.
+ * Tiles of the fused kernel: the blocks on each XCD take the tiles of that
+ * XCD's contiguous share of the order from a counter, so that the queries in
+ * flight on an XCD are neighbours in the order and share its L2.  nif_query
+ * and plans keep those counters (2 KiB) in their workspace; nif_query_ordered,
+ * nif_query_packed and nif_query without ordering take a block of a ring of
+ * 64 such blocks that the context allocates in nif_prepare, the next block
+ * per call.  So at most 64 of those calls on one context may be in flight at
+ * once (calls on one stream never overlap); more, from several streams or
+ * threads, must be serialised by the caller. */
 size_t nif_order_workspace_bytes(const nif_ctx* ctx, int64_t n);
 nif_status nif_order(nif_ctx* ctx, const float* rays, const int32_t* object_ids, const float* t_max, int64_t n,
                      uint32_t* perm, void* ws, size_t ws_bytes, void* stream);

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -49,6 +50,8 @@ struct ObjHost {
     void* touched = nullptr;  // dirty flag per 64 latents (training)
 };
 
+constexpr int kTileRing = 64;  // tile-counter blocks per context for calls without a workspace
+
 struct nif_ctx {
     nif_model_desc d;
     int32_t K, M;
@@ -68,6 +71,7 @@ struct nif_ctx {
     int device = 0;
     int32_t order_mode = 2;  // NIF_ORDER_AUTO
     int32_t window_sort = 2;  // NIF_OPT_WINDOW_SORT: 2 = when there is no query image
+    int32_t tile_shape = 0;   // NIF_OPT_TILE_SHAPE: fused kernel shape outside plans
     std::vector<float*> mlp_m, mlp_v;  // Adam moments per MLP
     // device tables of per-object training pointers: grad, m, v, touched, grid
     void** d_train_tab = nullptr;
@@ -83,6 +87,10 @@ struct nif_ctx {
     // object table, option changes); a plan refuses to launch once it differs
     uint64_t epoch = 1;
     uint32_t* d_flags = nullptr;  // domain-error bits of queries (nif_get_error_flags)
+    // tile counters of fused-query calls that bring no workspace: a ring of
+    // kTileRing blocks, one per call in turn
+    uint8_t* d_tile_ring = nullptr;
+    std::atomic<uint32_t> tile_ring_next{0};
     uint8_t* d_tree = nullptr;  // box tree of the pair expansion (cluster boxes, member boxes, member ids)
     PairTree tree{};
 };
@@ -270,6 +278,7 @@ extern "C" void nif_destroy(nif_ctx* c) {
     if (c->d_train_fwd) (void)hipFree(c->d_train_fwd);
     if (c->d_train_bwd) (void)hipFree(c->d_train_bwd);
     if (c->d_flags) (void)hipFree(c->d_flags);
+    if (c->d_tile_ring) (void)hipFree(c->d_tile_ring);
     if (c->d_tree) (void)hipFree(c->d_tree);
     delete c;
 }
@@ -354,6 +363,7 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         HIP_TRY(hipMalloc(&c->d_flags, 256));
         HIP_TRY(launch_fill_u32(c->d_flags, 1, 0u, s));
     }
+    if (!c->d_tile_ring) HIP_TRY(hipMalloc(&c->d_tile_ring, kTileRing * kTileCtrBytes));
     // query images of the grids, in the caller's buffers (rebuilt on every
     // call: the grids may have changed)
     if (c->image_mode) {
@@ -417,13 +427,17 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
 
 static size_t train_bytes(const nif_ctx* c, int64_t n);
 
-// Ordering workspace followed by the queries as 32-byte records (the ordering
-// layout is a multiple of 256 bytes).
+// Ordering workspace, the queries as 32-byte records, then the fused query's
+// tile counters (the ordering layout is a multiple of 256 bytes).
 static size_t order_packed_bytes(const nif_ctx* c, int64_t n) {
-    return order_workspace_bytes(n, c->K) + (size_t)n * 32;
+    return order_workspace_bytes(n, c->K) + ((size_t)n * 32 + 255) / 256 * 256 + kTileCtrBytes;
 }
 static float4* records_in(const nif_ctx* c, void* ws, int64_t n) {
     return reinterpret_cast<float4*>(reinterpret_cast<uint8_t*>(ws) + order_workspace_bytes(n, c->K));
+}
+static uint32_t* tile_ctr_in(const nif_ctx* c, void* ws, int64_t n) {
+    return reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(ws) + order_workspace_bytes(n, c->K) +
+                                       ((size_t)n * 32 + 255) / 256 * 256);
 }
 
 extern "C" size_t nif_workspace_bytes(const nif_ctx* c, int64_t n, int32_t mode) {
@@ -444,6 +458,10 @@ extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) 
     case NIF_OPT_WINDOW_SORT:
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_WINDOW_SORT takes 0, 1 or 2");
         c->window_sort = (int32_t)value;
+        return ok();
+    case NIF_OPT_TILE_SHAPE:
+        if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_TILE_SHAPE takes 0, 1 or 2");
+        c->tile_shape = (int32_t)value;
         return ok();
     case NIF_OPT_GRID_IMAGE:
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_GRID_IMAGE takes 0, 1 or 2");
@@ -494,12 +512,21 @@ static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, 
     return NIF_OK;
 }
 
+// The fused query.  tile_ctr: the launch's tile counters from the caller's
+// workspace, or null for the next block of the context's ring.
 static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
                             const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s,
-                            int32_t blocks_per_cu = 0, const float4* qrec = nullptr, int32_t shape = 0) {
+                            int32_t blocks_per_cu = 0, const float4* qrec = nullptr, int32_t shape = -1,
+                            uint32_t* tile_ctr = nullptr) {
     FwdArgs a{};
+    if (!tile_ctr) {
+        if (!c->d_tile_ring) return fail(NIF_ERR_STATE, "context not prepared");
+        const uint32_t slot = c->tile_ring_next.fetch_add(1, std::memory_order_relaxed) % kTileRing;
+        tile_ctr = reinterpret_cast<uint32_t*>(c->d_tile_ring + (size_t)slot * kTileCtrBytes);
+    }
+    a.tile_ctr = tile_ctr;
     a.qrec = qrec;
-    a.shape = shape;
+    a.shape = shape >= 0 ? shape : c->tile_shape;
     a.flags = c->d_flags;
     a.blocks_per_cu = blocks_per_cu;
     a.use_image = c->images_ready ? c->image_mode : 0;
@@ -552,7 +579,8 @@ static nif_status query_in(nif_ctx* c, int32_t dtype, const float* rays, const i
         st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, window_sorted(c), qrec);
         if (st != NIF_OK) return st;
     }
-    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec);
+    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec, -1,
+                     need > 0 ? tile_ctr_in(c, ws, n) : nullptr);
 }
 
 extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
@@ -715,36 +743,66 @@ extern "C" size_t nif_pairs_workspace_bytes(const nif_ctx* c, int64_t n_rays) {
     return pairs_workspace_bytes(n_rays, c->K);
 }
 
+static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays, int32_t round,
+                               const uint8_t* ray_visible, int64_t max_pairs, float* pair_rays, float* pair_tmax,
+                               int32_t* pair_ids, uint32_t* pair_ray, int64_t* pair_count, void* ws, size_t ws_bytes,
+                               void* stream, const char* where) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "%s: NULL context", where);
+    if (n_rays < 0 || max_pairs < 0) return fail(NIF_ERR_INVALID_ARG, "%s: negative size", where);
+    if (!pair_count) return fail(NIF_ERR_INVALID_ARG, "%s: NULL pair_count", where);
+    if (n_rays > 0 && (!rays || !tmax)) return fail(NIF_ERR_INVALID_ARG, "%s: NULL rays", where);
+    if (max_pairs > 0 && (!pair_rays || !pair_tmax || !pair_ids || !pair_ray))
+        return fail(NIF_ERR_INVALID_ARG, "%s: NULL pair output", where);
+    if (round < 0 || round > 2) return fail(NIF_ERR_INVALID_ARG, "%s: round must be 1 or 2", where);
+    if (round == 2 && n_rays > 0 && !ray_visible) return fail(NIF_ERR_INVALID_ARG, "%s: NULL ray_visible", where);
+    if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "%s: at most 2^24 rays per call", where);
+    // per-ray counts and their scan are 32-bit: the total must stay below 2^32
+    if ((uint64_t)n_rays * (uint64_t)c->K >= ((uint64_t)1 << 32))
+        return fail(NIF_ERR_UNSUPPORTED, "%s: n_rays x num_objects must be below 2^32", where);
+    if (!c->d_objs || !c->d_tree) return fail(NIF_ERR_STATE, "context not prepared");
+    const size_t need = pairs_workspace_bytes(n_rays, c->K);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->tree, c->K, c->num_cus, round, ray_visible, max_pairs,
+                                pair_rays, pair_tmax, pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream));
+    return ok();
+}
+
 extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,
                                        int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
                                        uint32_t* pair_ray, int64_t* pair_count, void* ws, size_t ws_bytes,
                                        void* stream) {
-    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL context");
-    if (n_rays < 0 || max_pairs < 0) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: negative size");
-    if (!pair_count) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL pair_count");
-    if (n_rays > 0 && (!rays || !tmax)) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL rays");
-    if (max_pairs > 0 && (!pair_rays || !pair_tmax || !pair_ids || !pair_ray))
-        return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs: NULL pair output");
-    if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: at most 2^24 rays per call");
-    // per-ray counts and their scan are 32-bit: the total must stay below 2^32
-    if ((uint64_t)n_rays * (uint64_t)c->K >= ((uint64_t)1 << 32))
-        return fail(NIF_ERR_UNSUPPORTED, "nif_expand_pairs: n_rays x num_objects must be below 2^32");
-    if (!c->d_objs || !c->d_tree) return fail(NIF_ERR_STATE, "context not prepared");
-    const size_t need = pairs_workspace_bytes(n_rays, c->K);
-    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
-    HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->tree, c->K, c->num_cus, max_pairs, pair_rays, pair_tmax,
-                                pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream));
+    return expand_pairs(c, rays, tmax, n_rays, 0, nullptr, max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray,
+                        pair_count, ws, ws_bytes, stream, "nif_expand_pairs");
+}
+
+extern "C" nif_status nif_expand_pairs_round(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,
+                                             int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
+                                             float* pair_rays, float* pair_tmax, int32_t* pair_ids,
+                                             uint32_t* pair_ray, int64_t* pair_count, void* ws, size_t ws_bytes,
+                                             void* stream) {
+    if (round != 1 && round != 2) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs_round: round must be 1 or 2");
+    return expand_pairs(c, rays, tmax, n_rays, round, ray_visible, max_pairs, pair_rays, pair_tmax, pair_ids,
+                        pair_ray, pair_count, ws, ws_bytes, stream, "nif_expand_pairs_round");
+}
+
+static nif_status combine(nif_ctx* c, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
+                          int64_t n_rays, uint8_t* ray_visible, bool init, void* stream, const char* where) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "%s: NULL context", where);
+    if (n_pairs < 0 || n_rays < 0) return fail(NIF_ERR_INVALID_ARG, "%s: negative size", where);
+    if ((n_pairs > 0 && (!pair_ray || !visibility)) || (n_rays > 0 && !ray_visible))
+        return fail(NIF_ERR_INVALID_ARG, "%s: NULL argument", where);
+    HIP_TRY(launch_combine_pairs(pair_ray, visibility, n_pairs, n_rays, ray_visible, init, (hipStream_t)stream));
     return ok();
 }
 
 extern "C" nif_status nif_combine_pairs(nif_ctx* c, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
                                         int64_t n_rays, uint8_t* ray_visible, void* stream) {
-    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_combine_pairs: NULL context");
-    if (n_pairs < 0 || n_rays < 0) return fail(NIF_ERR_INVALID_ARG, "nif_combine_pairs: negative size");
-    if ((n_pairs > 0 && (!pair_ray || !visibility)) || (n_rays > 0 && !ray_visible))
-        return fail(NIF_ERR_INVALID_ARG, "nif_combine_pairs: NULL argument");
-    HIP_TRY(launch_combine_pairs(pair_ray, visibility, n_pairs, n_rays, ray_visible, (hipStream_t)stream));
-    return ok();
+    return combine(c, pair_ray, visibility, n_pairs, n_rays, ray_visible, true, stream, "nif_combine_pairs");
+}
+
+extern "C" nif_status nif_combine_pairs_and(nif_ctx* c, const uint32_t* pair_ray, const float* visibility,
+                                            int64_t n_pairs, int64_t n_rays, uint8_t* ray_visible, void* stream) {
+    return combine(c, pair_ray, visibility, n_pairs, n_rays, ray_visible, false, stream, "nif_combine_pairs_and");
 }
 
 extern "C" nif_status nif_get_error_flags(nif_ctx* c, uint32_t* flags, int32_t clear, void* stream) {
@@ -1055,7 +1113,7 @@ static nif_status plan_run(nif_plan* p, const Sched& sc, hipStream_t s) {
         if (st != NIF_OK) return st;
     }
     return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu,
-                     qrec, sc.shape);
+                     qrec, sc.shape, tile_ctr_in(p->c, p->ws, p->n));
 }
 
 // Tuning cache: a text file of one JSON object per line, {"key": "...",

@@ -290,18 +290,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
     const int half = lane >> 5;
     const int qlane = lane & 31;
 
-    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous share of the tiles so that neighbouring queries share its L2
+    // Blocks are dispatched round-robin over the 8 XCDs; each XCD takes a
+    // contiguous share of the tiles so that neighbouring queries share its L2.
+    // With tile counters, the XCD's blocks take the share's tiles in order from
+    // the XCD's counter, so the tiles in flight on an XCD at any moment are
+    // neighbours in the query order (and blocks that finish early take more);
+    // without, block b takes a fixed contiguous run of the share.
     const int b = blockIdx.x;
-    const int lb = (b & 7) * A.xcd_stride + (b >> 3);
+    const int xcd = b & 7;
+    const int lb = xcd * A.xcd_stride + (b >> 3);
     const int64_t t_begin = (int64_t)lb * A.num_tiles / A.tiles_per_block_num;
     const int64_t t_end = (int64_t)(lb + 1) * A.num_tiles / A.tiles_per_block_num;
-    if (t_begin >= t_end) return;
+    const int64_t share_begin = (int64_t)xcd * A.num_tiles / 8;
+    const int64_t lim = A.tile_ctr ? (int64_t)(xcd + 1) * A.num_tiles / 8 : t_end;
+    __shared__ int64_t next_tile;
+    auto tile_at = [&](int64_t i) -> int64_t {  // block-uniform: every thread calls it
+        if (!A.tile_ctr) return t_begin + i;
+        __syncthreads();
+        if (threadIdx.x == 0) next_tile = share_begin + (int64_t)atomicAdd(A.tile_ctr + xcd * kTileCtrStride, 1u);
+        __syncthreads();
+        return next_tile;
+    };
+    const int64_t first_tile = tile_at(0);
+    if (first_tile >= lim) return;
 
     // MLP of the block: that of the first query of its first tile
     int32_t blk_mlp = A.fixed_mlp;
     if (MODE == 0) {
-        const int32_t id0 = slot_object(A, t_begin * kQueriesPerBlock);
+        const int32_t id0 = slot_object(A, first_tile * kQueriesPerBlock);
         if (id0 >= 0 && id0 < A.num_objects) blk_mlp = A.objs[id0].mlp;
     }
     if (MODE != 1) {
@@ -312,8 +328,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
     }
     __syncthreads();
 
-    for (int64_t tile = t_begin; tile < t_end; ++tile) {
-        if (MODE == 0 && tile > t_begin) {
+    for (int64_t it = 0;; ++it) {
+        const int64_t tile = it == 0 ? first_tile : tile_at(it);
+        if (tile >= lim) break;
+        if (MODE == 0 && it > 0) {
             // ordered queries change MLP at object boundaries: follow the MLP of
             // the tile's first query (a block-uniform decision)
             const int32_t id0 = slot_object(A, tile * kQueriesPerBlock);
@@ -524,6 +542,10 @@ hipError_t launch_mlp16(int flavor, int levels, const FwdArgs& a, int num_cus, h
     return hipErrorInvalidValue;
 }
 
+// Zero the tile counters right before the launch that uses them (a kernel,
+// not a memset, so that the pair can be captured into a graph).
+__global__ void tile_ctr_reset_kernel(uint32_t* ctr) { ctr[threadIdx.x] = 0u; }
+
 template <int FLAV, int L, typename GT, int MODE, int IMG, int SH>
 static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     FwdArgs a = a0;
@@ -535,6 +557,7 @@ static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     a.num_tiles = (int32_t)tiles;
     a.tiles_per_block_num = (int32_t)blocks;
     a.xcd_stride = (int32_t)(blocks / 8);
+    if (a.tile_ctr) hipLaunchKernelGGL(tile_ctr_reset_kernel, dim3(1), dim3(8 * kTileCtrStride), 0, s, a.tile_ctr);
     const size_t lds = MODE == 1 ? 0 : lds_bytes(a.pack);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE, IMG, SH>,

@@ -74,7 +74,13 @@ struct FwdArgs {
     int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
     const float4* qrec;           // nullable: query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
     int32_t shape;                // tile shape of the fused query (0 default, 1, 2; see shape_batch)
+    uint32_t* tile_ctr;           // fused query: per-XCD tile counters (kTileCtrBytes, zeroed by the launch); null = static tiles
 };
+
+// Tile counters of one fused-query launch: one 32-bit counter per XCD, each on
+// its own 256-byte line.
+constexpr int kTileCtrStride = 64;
+constexpr size_t kTileCtrBytes = 8 * kTileCtrStride * sizeof(uint32_t);
 
 // The paper's own networks: per object its box and its grid buffer of each
 // network (binary16: position grid, direction grid, and for the inner network
@@ -271,16 +277,20 @@ struct PairTree {
     float root[6];
 };
 size_t pairs_workspace_bytes(int64_t n_rays, int32_t K);
+// round: 0 every pair; 1 each ray's first pair; 2 the other pairs of the rays
+// with ray_visible != 0 (see nif_pairs.hip).
 hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const PairTree& T, int32_t K,
-                               int num_cus, int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
-                               uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s);
+                               int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
+                               float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
+                               int64_t* total, void* ws, hipStream_t s);
 // t = t_a + y (t_b - t_a) of the query's segment; +inf for a miss, NaN for an
 // invalid query.
 hipError_t launch_depth_from_visibility(const float* rays, const int32_t* ids, const float* tmax, const float* vis,
                                         int64_t n, const ObjDev* objs, int32_t K, float* depth, int num_cus,
                                         hipStream_t s);
+// init: set every ray visible first; else only clear the rays of occluded pairs.
 hipError_t launch_combine_pairs(const uint32_t* pair_ray, const float* vis, int64_t n_pairs, int64_t n_rays,
-                                uint8_t* ray_visible, hipStream_t s);
+                                uint8_t* ray_visible, bool init, hipStream_t s);
 hipError_t launch_init_grid(void* grid, int grid_dtype, int64_t count, uint64_t seed, uint64_t obj, float amp,
                             hipStream_t s);
 

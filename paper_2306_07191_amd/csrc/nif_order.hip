@@ -19,7 +19,6 @@
 // a few finest-level cells (ties keep the bucket order).  The outputs do not
 // depend on the order, because every query is computed independently of its
 // neighbours.
-#include <rocprim/block/block_radix_sort.hpp>
 
 #include "nif_device.h"
 #include "nif_internal.h"
@@ -227,15 +226,81 @@ __global__ __launch_bounds__(kOrderThreads) void order_rank_kernel(OrderArgs A) 
 // Pass 4: sort each window of kRefine consecutive entries of the bucket order
 // by the finer key (object, 8 Morton bits per axis).  The window holds one or a
 // few bucket runs, so its keys span a small range: keys are taken relative to
-// the window's minimum and radix-sorted (rocPRIM block radix sort, stable) over
+// the window's minimum and radix-sorted (a stable LDS radix sort, below) over
 // only the bits that range needs.
 constexpr int kRefineThreads = 256;
 constexpr int kRefineItems = 16;
 constexpr int kRefine = kRefineThreads * kRefineItems;
-using RefineSort = rocprim::block_radix_sort<uint32_t, kRefineThreads, kRefineItems, uint32_t>;
+constexpr int kDigit = 4;  // radix bits per pass
+constexpr int kBuckets = 1 << kDigit;
+
+// Stable LSD radix sort of the block's kRefine (key, value) pairs on the key's
+// low `bits` bits, in LDS.  Items are held blocked (thread t holds items
+// 16 t .. 16 t + 15 of the current order).  One pass per 4-bit digit: every
+// thread counts its items' digits into column t of a [digit][thread] table,
+// an exclusive scan of the table in digit-major order gives each (digit,
+// thread) its first destination, and items go there in their order, so that
+// equal digits keep their relative order.
+struct RefineSortStorage {
+    uint32_t key[kRefine];
+    uint32_t val[kRefine];
+    uint32_t table[kBuckets * kRefineThreads];
+    uint32_t part[kRefineThreads];
+};
+
+__device__ __forceinline__ void refine_radix_sort(uint32_t (&key)[kRefineItems], uint32_t (&val)[kRefineItems],
+                                                  RefineSortStorage& S, int bits) {
+    const int t = threadIdx.x;
+    for (int shift = 0; shift < bits; shift += kDigit) {
+        // thread t owns column t of the table: counts without atomics
+#pragma unroll
+        for (int b = 0; b < kBuckets; ++b) S.table[b * kRefineThreads + t] = 0;
+#pragma unroll
+        for (int j = 0; j < kRefineItems; ++j) ++S.table[((key[j] >> shift) & (kBuckets - 1)) * kRefineThreads + t];
+        __syncthreads();
+        // exclusive scan of the table (kBuckets x kRefineThreads entries, digit-major):
+        // thread t scans entries 16 t .. 16 t + 15, then the block scans the thread sums
+        constexpr int per = kBuckets * kRefineThreads / kRefineThreads;
+        uint32_t loc[per];
+        uint32_t run = 0;
+#pragma unroll
+        for (int e = 0; e < per; ++e) {
+            loc[e] = run;
+            run += S.table[t * per + e];
+        }
+        S.part[t] = run;
+        __syncthreads();
+        for (int off = 1; off < kRefineThreads; off <<= 1) {
+            const uint32_t y = t >= off ? S.part[t - off] : 0u;
+            __syncthreads();
+            S.part[t] += y;
+            __syncthreads();
+        }
+        const uint32_t base = t ? S.part[t - 1] : 0u;
+#pragma unroll
+        for (int e = 0; e < per; ++e) S.table[t * per + e] = base + loc[e];
+        __syncthreads();
+        // scatter in order: an item's destination is its (digit, thread) start plus the
+        // number of this thread's earlier items with the same digit
+#pragma unroll
+        for (int j = 0; j < kRefineItems; ++j) {
+            const uint32_t d = (key[j] >> shift) & (kBuckets - 1);
+            const uint32_t dst = S.table[d * kRefineThreads + t]++;
+            S.key[dst] = key[j];
+            S.val[dst] = val[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRefineItems; ++j) {
+            key[j] = S.key[t * kRefineItems + j];
+            val[j] = S.val[t * kRefineItems + j];
+        }
+        __syncthreads();
+    }
+}
 
 __global__ __launch_bounds__(kRefineThreads) void order_refine_kernel(OrderArgs A) {
-    __shared__ typename RefineSort::storage_type storage;
+    __shared__ RefineSortStorage storage;
     __shared__ uint32_t red_min[kRefineThreads / 64], red_max[kRefineThreads / 64];
     const int64_t w0 = (int64_t)blockIdx.x * kRefine;
     const int cnt = (int)(A.n - w0 < kRefine ? A.n - w0 : kRefine);
@@ -278,7 +343,7 @@ __global__ __launch_bounds__(kRefineThreads) void order_refine_kernel(OrderArgs 
             if (threadIdx.x * kRefineItems + j < cnt) key[j] -= mn;
         // padding keys (all ones) are >= every valid key in the low `bits` bits;
         // on a tie the stable sort keeps the padding, which comes last, last
-        RefineSort().sort(key, val, storage, 0, (unsigned)bits);
+        refine_radix_sort(key, val, storage, bits);
     }
 #pragma unroll
     for (int j = 0; j < kRefineItems; ++j) {

@@ -242,7 +242,7 @@ __device__ __forceinline__ LaneBox level1_box(const PairTree& T, int lane) {
     return b;
 }
 
-// Calls on_hit(object) in every lane whose ray the division test says meets
+// Calls on_hit(object, lo, hi) in every lane whose ray the division test says meets
 // that object's box; wave-uniform control flow.
 template <typename F>
 __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1, const PairTree& T, int lane,
@@ -266,7 +266,7 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
                 hi[a] = lane_f(B1.hi[a], j);
             }
             const int32_t k = __builtin_amdgcn_readlane(B1.id, j);
-            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k);
+            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k, lo, hi);
             continue;
         }
         // cluster j: its members, lane i holding member i
@@ -289,7 +289,7 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
                 hi[a] = lane_f(m.hi[a], i);
             }
             const int32_t k = __builtin_amdgcn_readlane(m.id, i);
-            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k);
+            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k, lo, hi);
         }
     }
 }
@@ -305,8 +305,8 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
     return t;
 }
 
-// Exclusive scan over the block's 256 threads.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh) {
+// Exclusive scan over the block's 256 threads; the block total in `total`.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t x = v;
 #pragma unroll
@@ -318,58 +318,103 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh) {
     __syncthreads();
     uint32_t base = 0;
     for (int w = 0; w < wave; ++w) base += sh[w];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
     __syncthreads();
     return base + x - v;
 }
 
-// Pass 1.  masks (K <= 64): bit k set iff the ray meets object k; else counts.
+// The count and emit passes run with the same grid; block b takes the
+// contiguous tiles [tile_begin(tiles), tile_begin(tiles, 1)), so one total per
+// block is all the scan between them needs.
+__device__ __forceinline__ int64_t tile_begin(int64_t tiles, int next = 0) {
+    return (int64_t)(blockIdx.x + next) * tiles / gridDim.x;
+}
+
+// Rounds of the early-out form (Sec. 7: once one object is found to occlude a
+// ray, its remaining objects need not be queried): round 0 = every pair;
+// round 1 = each ray's first pair only, the box it enters first (smallest
+// t_a, then the smaller object id); round 2 = the pairs round 1 left out, of
+// the rays still visible after it.  Rounds 1 and 2 together are round 0's
+// pairs less those of rays occluded in round 1.
+//
+// Pass 1.  masks (K <= 64): bit k set iff the ray's pair with object k is
+// emitted in this round; else counts (and, for rounds 1 and 2, the first
+// object per ray in first_obj).
 __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __restrict__ rays,
                                                                 const float* __restrict__ tmax, int64_t n, PairTree T,
+                                                                int32_t round, const uint8_t* __restrict__ ray_visible,
                                                                 uint64_t* __restrict__ masks,
                                                                 uint32_t* __restrict__ counts,
-                                                                uint32_t* __restrict__ tile_sums) {
+                                                                int32_t* __restrict__ first_obj,
+                                                                uint32_t* __restrict__ block_sums) {
     __shared__ uint32_t sh[4];
     const int lane = threadIdx.x & 63;
     const LaneBox B1 = level1_box(T, lane);
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    uint32_t block_total = 0;
+    for (int64_t tile = tile_begin(tiles); tile < tile_begin(tiles, 1); ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
         const LaneRay R = lane_ray(rays, tmax, r, n, T);
         uint64_t mk = 0;
         uint32_t c = 0;
-        for_each_hit(R, B1, T, lane, [&](int32_t k) {
+        float best_ta = INFINITY;
+        int32_t best_k = 0x7fffffff;
+        for_each_hit(R, B1, T, lane, [&](int32_t k, const float lo[3], const float hi[3]) {
             ++c;
             mk |= 1ull << (k & 63);
+            if (round) {  // the box entered first
+                float ta, tb;
+                (void)clip_segment(R.pre.o, R.pre.d, R.pre.tm, lo, hi, ta, tb);
+                if (ta < best_ta || (ta == best_ta && k < best_k)) {
+                    best_ta = ta;
+                    best_k = k;
+                }
+            }
         });
+        if (round == 1 && c) {
+            c = 1;
+            mk = 1ull << (best_k & 63);
+        } else if (round == 2 && c) {
+            if (r < n && ray_visible[r]) {
+                c -= 1;
+                mk &= ~(1ull << (best_k & 63));
+            } else {
+                c = 0;
+                mk = 0;
+            }
+        }
         if (r < n) {
             if (masks) masks[r] = mk;
             else counts[r] = c;
+            if (first_obj) first_obj[r] = best_k;
         }
-        const uint32_t s = block_sum(c, sh);
-        if (threadIdx.x == 0) tile_sums[tile] = s;
+        block_total += block_sum(c, sh);
     }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = block_total;
 }
 
-// Pass 2: exclusive scan of the tile totals (one block); the pair total.
-__global__ __launch_bounds__(kPairScanThreads) void pairs_tile_scan_kernel(const uint32_t* __restrict__ sums,
-                                                                           int64_t tiles,
-                                                                           uint32_t* __restrict__ offs,
-                                                                           int64_t* __restrict__ total) {
-    __shared__ uint32_t part[kPairScanThreads];
+// Pass 2: exclusive scan of the per-block totals (at most a few thousand
+// values, one block: each thread sums a short contiguous run, a scan of the
+// run totals, then the runs are written out); the pair total.
+__global__ __launch_bounds__(kPairScanThreads) void pairs_block_scan_kernel(const uint32_t* __restrict__ sums,
+                                                                            int64_t nb,
+                                                                            uint64_t* __restrict__ offs,
+                                                                            int64_t* __restrict__ total) {
+    __shared__ uint64_t part[kPairScanThreads];
     const int t = threadIdx.x;
-    const int64_t per = (tiles + kPairScanThreads - 1) / kPairScanThreads;
-    const int64_t b = t * per, e = b + per < tiles ? b + per : tiles;
-    uint32_t s = 0;
+    const int64_t per = (nb + kPairScanThreads - 1) / kPairScanThreads;
+    const int64_t b = t * per, e = b + per < nb ? b + per : nb;
+    uint64_t s = 0;
     for (int64_t i = b; i < e; ++i) s += sums[i];
     part[t] = s;
     __syncthreads();
-    for (int off = 1; off < kPairScanThreads; off <<= 1) {  // inclusive scan of the thread parts
-        const uint32_t y = t >= off ? part[t - off] : 0u;
+    for (int off = 1; off < kPairScanThreads; off <<= 1) {  // inclusive scan of the run totals
+        const uint64_t y = t >= off ? part[t - off] : 0ull;
         __syncthreads();
         part[t] += y;
         __syncthreads();
     }
-    uint32_t run = t ? part[t - 1] : 0u;
+    uint64_t run = t ? part[t - 1] : 0ull;
     for (int64_t i = b; i < e; ++i) {
         offs[i] = run;
         run += sums[i];
@@ -393,15 +438,18 @@ __device__ __forceinline__ void write_pair(int64_t p, const float o[3], const fl
 // Pass 3 with masks (at most 64 objects): ascending set bits.
 __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
-    const uint32_t* __restrict__ offs, int64_t max_pairs, float* __restrict__ pair_rays, float* __restrict__ pair_tmax,
+    const uint64_t* __restrict__ offs, int64_t max_pairs, float* __restrict__ pair_rays, float* __restrict__ pair_tmax,
     int32_t* __restrict__ pair_ids, uint32_t* __restrict__ pair_ray) {
     __shared__ uint32_t sh[4];
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    int64_t run = (int64_t)offs[blockIdx.x];
+    for (int64_t tile = tile_begin(tiles); tile < tile_begin(tiles, 1); ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
         uint64_t mk = r < n ? masks[r] : 0ull;
         const uint32_t c = (uint32_t)__popcll(mk);
-        int64_t p = (int64_t)offs[tile] + block_excl_scan(c, sh);
+        uint32_t tile_total;
+        int64_t p = run + block_excl_scan(c, sh, tile_total);
+        run += tile_total;
         if (c == 0 || p >= max_pairs) continue;
         float o[3], d[3];
 #pragma unroll
@@ -422,21 +470,27 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
 // traversal order, then the ray's written ids sorted ascending in place (the
 // other fields are the same for every pair of a ray).
 __global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
-    const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, PairTree T,
-    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offs, int64_t max_pairs,
-    float* __restrict__ pair_rays, float* __restrict__ pair_tmax, int32_t* __restrict__ pair_ids,
+    const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, PairTree T, int32_t round,
+    const int32_t* __restrict__ first_obj, const uint32_t* __restrict__ counts, const uint64_t* __restrict__ offs,
+    int64_t max_pairs, float* __restrict__ pair_rays, float* __restrict__ pair_tmax, int32_t* __restrict__ pair_ids,
     uint32_t* __restrict__ pair_ray) {
     __shared__ uint32_t sh[4];
     const int lane = threadIdx.x & 63;
     const LaneBox B1 = level1_box(T, lane);
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    int64_t run = (int64_t)offs[blockIdx.x];
+    for (int64_t tile = tile_begin(tiles); tile < tile_begin(tiles, 1); ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
         const uint32_t c = r < n ? counts[r] : 0u;
-        const int64_t p0 = (int64_t)offs[tile] + block_excl_scan(c, sh);
+        uint32_t tile_total;
+        const int64_t p0 = run + block_excl_scan(c, sh, tile_total);
+        run += tile_total;
         const LaneRay R = lane_ray(rays, tmax, r, n, T);
+        const int32_t first = round && r < n ? first_obj[r] : -1;
         int64_t p = p0;
-        for_each_hit(R, B1, T, lane, [&](int32_t k) {
+        for_each_hit(R, B1, T, lane, [&](int32_t k, const float*, const float*) {
+            // round 1: the first object only; round 2: the others (a ray with c = 0 writes none)
+            if ((round == 1 && k != first) || (round == 2 && k == first) || p >= p0 + (int64_t)c) return;
             if (p < max_pairs) write_pair(p, R.pre.o, R.pre.d, R.pre.tm, k, (uint32_t)r, pair_rays, pair_tmax,
                                           pair_ids, pair_ray);
             ++p;
@@ -509,9 +563,13 @@ hipError_t launch_depth_from_visibility(const float* rays, const int32_t* ids, c
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
+// masks (8 B per ray) or counts (4 B), per-block totals (4 B) and offsets
+// (8 B), first objects (4 B per ray, more than 64 objects only).  Sized by
+// tiles, which bounds the block count.
 size_t pairs_workspace_bytes(int64_t n_rays, int32_t K) {
     const int64_t tiles = (n_rays + kPairTile - 1) / kPairTile;
-    return al256((size_t)n_rays * (K <= 64 ? 8 : 4)) + 2 * al256((size_t)tiles * 4);
+    return al256((size_t)n_rays * (K <= 64 ? 8 : 4)) + al256((size_t)tiles * 4) + al256((size_t)tiles * 8) +
+           (K <= 64 ? 0 : al256((size_t)n_rays * 4));
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -520,8 +578,9 @@ static unsigned grid_for(int64_t n, int threads) {
 }
 
 hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const PairTree& T, int32_t K,
-                               int num_cus, int64_t max_pairs, float* pair_rays, float* pair_tmax, int32_t* pair_ids,
-                               uint32_t* pair_ray, int64_t* total, void* ws, hipStream_t s) {
+                               int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
+                               float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
+                               int64_t* total, void* ws, hipStream_t s) {
     if (n == 0) {
         hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
         return hipGetLastError();
@@ -533,23 +592,28 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
     uint32_t* counts = use_mask ? nullptr : reinterpret_cast<uint32_t*>(p);
     p += al256((size_t)n * (use_mask ? 8 : 4));
     uint32_t* sums = reinterpret_cast<uint32_t*>(p);
-    uint32_t* offs = reinterpret_cast<uint32_t*>(p + al256((size_t)tiles * 4));
+    p += al256((size_t)tiles * 4);
+    uint64_t* offs = reinterpret_cast<uint64_t*>(p);
+    p += al256((size_t)tiles * 8);
+    int32_t* first = use_mask ? nullptr : reinterpret_cast<int32_t*>(p);
     const int64_t cap = (int64_t)num_cus * 8;  // persistent blocks
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
-    hipLaunchKernelGGL(pairs_count_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, masks, counts, sums);
-    hipLaunchKernelGGL(pairs_tile_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, tiles, offs, total);
+    hipLaunchKernelGGL(pairs_count_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, ray_visible,
+                       masks, counts, round ? first : nullptr, sums);
+    hipLaunchKernelGGL(pairs_block_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, (int64_t)blocks, offs,
+                       total);
     if (use_mask)
         hipLaunchKernelGGL(pairs_emit_mask_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, masks, offs,
                            max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
     else
-        hipLaunchKernelGGL(pairs_emit_tree_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, counts, offs,
-                           max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
+        hipLaunchKernelGGL(pairs_emit_tree_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, first,
+                           counts, offs, max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
     return hipGetLastError();
 }
 
 hipError_t launch_combine_pairs(const uint32_t* pair_ray, const float* vis, int64_t n_pairs, int64_t n_rays,
-                                uint8_t* ray_visible, hipStream_t s) {
-    if (n_rays > 0)
+                                uint8_t* ray_visible, bool init, hipStream_t s) {
+    if (init && n_rays > 0)
         hipLaunchKernelGGL(combine_init_kernel, dim3(grid_for(n_rays, 256)), dim3(256), 0, s, ray_visible, n_rays);
     if (n_pairs > 0)
         hipLaunchKernelGGL(combine_pairs_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, pair_ray, vis, n_pairs,

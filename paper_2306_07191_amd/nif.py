@@ -19,6 +19,7 @@ NIF_F32, NIF_F16, NIF_BF16, NIF_FP8_E4M3 = 0, 1, 2, 3
 NIF_OPT_ORDER = 1
 NIF_OPT_GRID_IMAGE = 2
 NIF_OPT_WINDOW_SORT = 3
+NIF_OPT_TILE_SHAPE = 4
 NIF_FLAG_INVALID_RAY = 1
 NIF_FLAG_BAD_OBJECT = 2
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
@@ -28,7 +29,7 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
-           "nif_expand_pairs", "nif_combine_pairs", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
+           "nif_expand_pairs", "nif_combine_pairs", "nif_expand_pairs_round", "nif_combine_pairs_and", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
            "nif_encode16", "nif_mlp16",
            "nif_set_option", "nif_image_bytes", "nif_set_image", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
@@ -80,6 +81,8 @@ def lib():
             "nif_pairs_workspace_bytes": (sz, [vp, i64]),
             "nif_expand_pairs": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
             "nif_combine_pairs": (i32, [vp, vp, vp, i64, i64, vp, vp]),
+            "nif_expand_pairs_round": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "nif_combine_pairs_and": (i32, [vp, vp, vp, i64, i64, vp, vp]),
             "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
             "nif_prepare": (i32, [vp, i32, vp]),
@@ -456,8 +459,9 @@ class Context:
         s = np.ascontiguousarray(scales, np.float32)
         _check(lib().nif_set_fp8_scales(self.h, m, s.ctypes.data), "nif_set_fp8_scales")
 
-    def expand_pairs(self, rays, tmax, max_pairs=None):
-        """(pair_rays, pair_tmax, pair_ids, pair_ray) of the rays' AABB hits, ray order."""
+    def expand_pairs(self, rays, tmax, max_pairs=None, round: int = 0, ray_visible=None):
+        """(pair_rays, pair_tmax, pair_ids, pair_ray) of the rays' AABB hits, ray order.
+        round 1 / 2: the early-out form's rounds (nif_expand_pairs_round)."""
         t = self.torch
         n = tmax.shape[0]
         ws = t.empty(max(1, int(lib().nif_pairs_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
@@ -468,21 +472,28 @@ class Context:
             pt = t.empty(m, dtype=t.float32, device=self.device)
             pi = t.empty(m, dtype=t.int32, device=self.device)
             pray = t.empty(m, dtype=t.int32, device=self.device)
-            _check(lib().nif_expand_pairs(self.h, _ptr(rays), _ptr(tmax), n, m, _ptr(pr), _ptr(pt), _ptr(pi),
-                                          _ptr(pray), _ptr(cnt), _ptr(ws), ws.numel(), _stream()), "nif_expand_pairs")
+            if round:
+                _check(lib().nif_expand_pairs_round(self.h, _ptr(rays), _ptr(tmax), n, round, _ptr(ray_visible), m,
+                                                    _ptr(pr), _ptr(pt), _ptr(pi), _ptr(pray), _ptr(cnt), _ptr(ws),
+                                                    ws.numel(), _stream()), "nif_expand_pairs_round")
+            else:
+                _check(lib().nif_expand_pairs(self.h, _ptr(rays), _ptr(tmax), n, m, _ptr(pr), _ptr(pt), _ptr(pi),
+                                              _ptr(pray), _ptr(cnt), _ptr(ws), ws.numel(), _stream()), "nif_expand_pairs")
             total = int(cnt.item())
             if total <= m:
                 return pr[:total], pt[:total], pi[:total], pray[:total]
             max_pairs = total
         raise RuntimeError("pair count changed between calls")
 
-    def combine_pairs(self, pair_ray, visibility, n_rays, out=None):
-        """Per-ray visibility (uint8): 0 iff some pair of the ray is below 0.5."""
+    def combine_pairs(self, pair_ray, visibility, n_rays, out=None, accumulate: bool = False):
+        """Per-ray visibility (uint8): 0 iff some pair of the ray is below 0.5.
+        accumulate: only clear rays of occluded pairs in out (nif_combine_pairs_and)."""
         t = self.torch
         if out is None:
             out = t.empty(n_rays, dtype=t.uint8, device=self.device)
-        _check(lib().nif_combine_pairs(self.h, _ptr(pair_ray), _ptr(visibility), pair_ray.shape[0], n_rays, _ptr(out),
-                                       _stream()), "nif_combine_pairs")
+        f = lib().nif_combine_pairs_and if accumulate else lib().nif_combine_pairs
+        _check(f(self.h, _ptr(pair_ray), _ptr(visibility), pair_ray.shape[0], n_rays, _ptr(out), _stream()),
+               "nif_combine_pairs")
         return out
 
     def error_flags(self, clear: bool = True) -> int:

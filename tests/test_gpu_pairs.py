@@ -161,3 +161,46 @@ def test_pairs_empty_inputs():
     assert pr_ray.numel() == 0
     out = ctx.combine_pairs(pr_ray, e, 5)
     assert (out.cpu().numpy() == 1).all()  # rays without pairs are visible
+
+
+@pytest.mark.parametrize("K", [12, 70])  # hit masks (<= 64 objects), tree traversal (> 64)
+def test_early_out_rounds(K):
+    """The early-out form (Sec. 7): round 1 is each ray's first box (smallest
+    t_a, then the smaller id), round 2 the other pairs of the rays still
+    visible; querying both and combining gives the per-ray result of all
+    pairs, bit for bit."""
+    import torch
+    w = _scene(n=30000, K=K, seed=21)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
+    n = w["tmax"].shape[0]
+    ref_ray, ref_obj = model.expand_pairs(w["rays"], w["tmax"])
+    ta, _ = model.segment(w["rays"][ref_ray], ref_obj, w["tmax"][ref_ray])
+    # the oracle's first pair per ray: smallest t_a, ties to the smaller object id
+    order = np.lexsort((ref_obj, ta, ref_ray))
+    first_pos = order[np.r_[True, ref_ray[order][1:] != ref_ray[order][:-1]]]
+    first = {int(ref_ray[p]): int(ref_obj[p]) for p in first_pos}
+    assert sum(np.bincount(ref_ray, minlength=n) >= 2) > 1000  # many rays with several pairs
+    # round 1
+    _, _, r1_ids, r1_ray = ctx.expand_pairs(rays, tmax, round=1)
+    r1 = dict(zip(r1_ray.cpu().numpy().tolist(), r1_ids.cpu().numpy().tolist()))
+    assert r1 == first
+    # round 2 under a given visibility: the rest of the visible rays' pairs, in order
+    g = np.random.default_rng(4)
+    vis_in = (g.uniform(size=n) < 0.5).astype(np.uint8)
+    _, _, r2_ids, r2_ray = ctx.expand_pairs(rays, tmax, round=2, ray_visible=torch.from_numpy(vis_in).cuda())
+    keep = np.array([vis_in[r] == 1 and first[int(r)] != o for r, o in zip(ref_ray, ref_obj)], bool)
+    np.testing.assert_array_equal(r2_ray.cpu().numpy(), ref_ray[keep])
+    np.testing.assert_array_equal(r2_ids.cpu().numpy(), ref_obj[keep])
+    # end to end: two rounds of queries give the all-pairs result
+    pr, pt, pi, pray = ctx.expand_pairs(rays, tmax)
+    y_all = ctx.query(pr, pi, pt, dtype="f32")
+    full = ctx.combine_pairs(pray, y_all, n).cpu().numpy()
+    p1r, p1t, p1i, p1ray = ctx.expand_pairs(rays, tmax, round=1)
+    vis = ctx.combine_pairs(p1ray, ctx.query(p1r, p1i, p1t, dtype="f32"), n)
+    p2r, p2t, p2i, p2ray = ctx.expand_pairs(rays, tmax, round=2, ray_visible=vis)
+    ctx.combine_pairs(p2ray, ctx.query(p2r, p2i, p2t, dtype="f32"), n, out=vis, accumulate=True)
+    np.testing.assert_array_equal(vis.cpu().numpy(), full)
+    print(f"K={K}: {pray.numel()} pairs in one round, {p1ray.numel()} + {p2ray.numel()} in two")
+    assert p1ray.numel() + p2ray.numel() < pray.numel()

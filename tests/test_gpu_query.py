@@ -407,3 +407,115 @@ def test_grid_image_is_bit_identical():
     with pytest.raises(nif.NifError):  # binary32 grids have no image form
         c2, _ = make_pair(S.tiny_workload(n_rays=10), grid_amp=0.5)
         c2.set_option(nif.NIF_OPT_GRID_IMAGE, 1)
+
+
+def _order_coarse_offset(n: int, num_objects: int) -> int:
+    """Byte offset of the bucket order inside the ordering workspace, as the
+    library lays it out: count table (buckets x tiles), bucket totals, 16-bit
+    keys, fine keys, then the bucket order; each region 256-byte aligned."""
+    al = lambda b: (b + 255) // 256 * 256
+    bits = 4
+    while bits > 0 and (num_objects << (3 * bits)) > 4096:
+        bits -= 1
+    nb = (num_objects << (3 * bits)) + 1
+    tiles = (n + 8191) // 8192
+    return al(nb * tiles * 4) + al(nb * 4) + al(n * 2) + al(n * 4)
+
+
+def test_window_sort_orders_each_window_stably():
+    """The ordering's window sort: each window of 4,096 consecutive entries of
+    the bucket order is re-sorted, stably, by the finer key (the Morton code of
+    the binary32 entry point with 8 bits per axis, for one object); it permutes
+    entries only within their window.  The bucket order ranks a tile's queries
+    of one bucket with LDS atomics, so it can differ from call to call: the
+    window sort is compared with the bucket order of the same call, which the
+    workspace still holds, and with a separate call only through what is fixed
+    (each window's bucket counts)."""
+    import torch
+    from paper_2306_07191_amd import nif
+    n, win = 20000, 4096
+    w = S.frame_workload(n_rays=n, with_mesh=False)
+    w["rays"][::97, 3:] *= -1.0  # misses
+    w["rays"][1000:1400] = w["rays"][1000]  # identical queries: equal keys
+    w["tmax"][1000:1400] = w["tmax"][1000]
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_ORDER, 1)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    ctx.prepare("f32")
+    args = [torch.from_numpy(w[k]).cuda() for k in ("rays", "ids", "tmax")]
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, 0)
+    other = ctx.order(*args).cpu().numpy().astype(np.int64)
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, 1)
+    ws = torch.empty(int(nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
+    fine = ctx.order(*args, ws=ws).cpu().numpy().astype(np.int64)
+    off = _order_coarse_offset(n, 1)
+    coarse = ws[off:off + 4 * n].cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(np.sort(coarse), np.arange(n)) and np.array_equal(np.sort(fine), np.arange(n))
+
+    def spread3(v):
+        r = np.zeros_like(v)
+        for b in range(10):
+            r |= ((v >> b) & 1) << (3 * b)
+        return r
+
+    key = np.full(n, 0xFFFFFFFF, np.int64)
+    bucket = np.full(n, 4096, np.int64)
+    for i in range(n):
+        st, u, *_ = model.detail(w["rays"][i], 0, float(w["tmax"][i]))
+        if st == 1:
+            c = np.minimum((np.float32(u[0]) * np.float32(256)).astype(np.int64), 255)
+            key[i] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2)
+            bucket[i] = key[i] >> 12
+    assert (np.diff(bucket[coarse]) >= 0).all() and (np.diff(bucket[other]) >= 0).all()
+    ties = 0
+    for w0 in range(0, n, win):
+        a, b, o = coarse[w0:w0 + win], fine[w0:w0 + win], other[w0:w0 + win]
+        assert np.array_equal(np.sort(a), np.sort(b))           # the same entries
+        assert np.array_equal(np.sort(bucket[o]), np.sort(bucket[b]))
+        kb = key[b]
+        assert (np.diff(kb) >= 0).all()                          # sorted by the finer key
+        pos = {q: j for j, q in enumerate(a.tolist())}           # stable: ties keep the bucket order
+        for k in np.unique(kb):
+            same = b[kb == k]
+            ties += same.shape[0] - 1
+            assert (np.diff([pos[q] for q in same.tolist()]) > 0).all()
+    assert ties >= 399
+
+
+def test_concurrent_calls_on_streams():
+    """The fused kernel's blocks take their tiles from per-XCD counters: in the
+    caller's workspace for nif_query, from the context's ring of counter blocks
+    for nif_query_packed.  Calls in flight together on several streams, with
+    several launches per stream, each give the outputs of one call alone, bit
+    for bit, and the reference's within the binary32 tolerance."""
+    import torch
+    from paper_2306_07191_amd import nif
+    w = S.frame_workload(n_rays=300000, with_mesh=False)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_ORDER, 1)
+    ctx.prepare("f32")
+    rays, ids, tmax = (torch.from_numpy(np.ascontiguousarray(w[k])).cuda() for k in ("rays", "ids", "tmax"))
+    n = ids.shape[0]
+    alone_z = torch.empty(n, device="cuda")
+    alone = ctx.query(rays, ids, tmax, dtype="f32", logits=alone_z)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    recs = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    ows = torch.empty(int(nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
+    ctx.order_packed(rays, ids, tmax, perm=perm, packed=recs, ws=ows)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    outs_p = [[torch.full((n,), -1.0, device="cuda") for _ in range(3)] for _ in streams]
+    outs_q = [torch.full((n,), -1.0, device="cuda") for _ in streams]
+    wss = [torch.empty(int(nif.lib().nif_workspace_bytes(ctx.h, n, 0)), dtype=torch.uint8, device="cuda")
+           for _ in streams]
+    for si, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            for o in outs_p[si]:
+                ctx.query_packed(recs, perm, dtype="f32", out=o)
+            ctx.query(rays, ids, tmax, dtype="f32", out=outs_q[si], ws=wss[si])
+    torch.cuda.synchronize()
+    for si in range(len(streams)):
+        for o in outs_p[si] + [outs_q[si]]:
+            assert torch.equal(o, alone)
+    check_outputs(alone.cpu().numpy(), alone_z.cpu().numpy(), model.forward(w["rays"], w["ids"], w["tmax"]), "f32",
+                  "concurrent")
