@@ -65,10 +65,12 @@ def time_launches(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def measured_traffic(name: str):
-    """HBM bytes per launch of the fused kernel from the committed counter run
-    profiles/query_<name>_traffic.json, or None when there is none or the kernel
-    source has changed since those counters were taken."""
+def measured_traffic(name: str, shape: int):
+    """HBM bytes per launch of the fused kernel in tile shape `shape`, from the
+    committed counter run profiles/query_<name>_traffic.json (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration), or None when there is none for
+    that shape or the kernel source has changed since those counters were
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"query_{name}_traffic.json")
     if not os.path.exists(path):
@@ -78,7 +80,8 @@ def measured_traffic(name: str):
                    for f in ("nif_forward.hip", "nif_device.h", "nif_mlp.h"))
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    by_shape = rec.get("shapes", {}).get(str(shape))
+    return None if by_shape is None else by_shape["traffic_bytes_per_launch"]
 
 
 def latent_footprint(rays, tmax, ids, aabb, level_res, feats: int, elem_bytes: int):
@@ -787,8 +790,8 @@ def run_scene(args):
         achieved = flops * P / tq / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE]}
-    roof.update({"traffic": measured_traffic("scene"),
-                 "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, no image> (fused clip+encode+MLP)",
+    roof.update({"traffic": measured_traffic("scene", tile_shape), "tile_shape": tile_shape,
+                 "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, no image, tile shape {tile_shape}> (fused clip+encode+MLP)",
                  "kernel_us": tq * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
                  "distinct_latent_vertices": fp[0], "distinct_64b_lines": fp[2],
                  "algorithmic_flop_per_launch": flops * P,
@@ -1252,8 +1255,8 @@ def run_frame(args):
         cold = {"kernel_us_median": float(np.median(ks)) * 1e6}
         log(f"cold fused kernel: {cold['kernel_us_median']:.1f} us")
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_TFLOPS[HEADLINE_DTYPE],
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic("frame_bf16"),
-                "kernel": "nif_query_kernel<bf16, L=8, f16 grid, z-y-pair image> (fused clip+encode+MLP)",
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_TFLOPS[HEADLINE_DTYPE], "traffic": measured_traffic("frame_bf16", tile_shape),
+                "kernel": f"nif_query_kernel<bf16, L=8, f16 grid, z-y-pair image, tile shape {tile_shape}> (fused clip+encode+MLP)",
                 "algorithmic_flop_per_launch": flops * n, "kernel_us": kern * 1e6,
                 "step_us": sec * 1e6, "order_us": (sec - kern) * 1e6,
                 "gather_rate_per_s": 3 * sh.levels * 8 * n / kern, "cold": cold}

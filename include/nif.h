@@ -274,7 +274,7 @@ nif_status nif_query_noalloc(nif_ctx* ctx, int32_t dtype, const float* rays, con
  * Tiles of the fused kernel: the blocks on each XCD take the tiles of that
  * XCD's contiguous share of the order from a counter, so that the queries in
  * flight on an XCD are neighbours in the order and share its L2.  nif_query
- * and plans keep those counters (2 KiB) in their workspace; nif_query_ordered,
+ * and plans keep those counters (4 KiB) in their workspace; nif_query_ordered,
  * nif_query_packed and nif_query without ordering take a block of a ring of
  * 64 such blocks that the context allocates in nif_prepare, the next block
  * per call.  So at most 64 of those calls on one context may be in flight at

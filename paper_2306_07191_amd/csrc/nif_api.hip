@@ -363,7 +363,10 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         HIP_TRY(hipMalloc(&c->d_flags, 256));
         HIP_TRY(launch_fill_u32(c->d_flags, 1, 0u, s));
     }
-    if (!c->d_tile_ring) HIP_TRY(hipMalloc(&c->d_tile_ring, kTileRing * kTileCtrBytes));
+    if (!c->d_tile_ring) {  // zero once; every launch on a block leaves it zero
+        HIP_TRY(hipMalloc(&c->d_tile_ring, kTileRing * kTileCtrBytes));
+        HIP_TRY(hipMemset(c->d_tile_ring, 0, kTileRing * kTileCtrBytes));
+    }
     // query images of the grids, in the caller's buffers (rebuilt on every
     // call: the grids may have changed)
     if (c->image_mode) {
@@ -513,18 +516,21 @@ static nif_status check_query_args(nif_ctx* c, int32_t dtype, const void* rays, 
 }
 
 // The fused query.  tile_ctr: the launch's tile counters from the caller's
-// workspace, or null for the next block of the context's ring.
+// workspace (ctr_zero: the ordering pass before it zeroed them), or null for
+// the next block of the context's ring (zero between launches).
 static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
                             const uint32_t* perm, int64_t n, float* vis, float* logits, hipStream_t s,
                             int32_t blocks_per_cu = 0, const float4* qrec = nullptr, int32_t shape = -1,
-                            uint32_t* tile_ctr = nullptr) {
+                            uint32_t* tile_ctr = nullptr, bool ctr_zero = false) {
     FwdArgs a{};
     if (!tile_ctr) {
         if (!c->d_tile_ring) return fail(NIF_ERR_STATE, "context not prepared");
         const uint32_t slot = c->tile_ring_next.fetch_add(1, std::memory_order_relaxed) % kTileRing;
         tile_ctr = reinterpret_cast<uint32_t*>(c->d_tile_ring + (size_t)slot * kTileCtrBytes);
+        ctr_zero = true;
     }
     a.tile_ctr = tile_ctr;
+    a.tile_ctr_reset = ctr_zero ? 1 : 0;
     a.qrec = qrec;
     a.shape = shape >= 0 ? shape : c->tile_shape;
     a.flags = c->d_flags;
@@ -552,8 +558,9 @@ static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const 
 
 static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
                             uint32_t* perm_dst, void* ws, const uint32_t** perm, hipStream_t s,
-                            bool refine = true, float4* qrec = nullptr) {
+                            bool refine = true, float4* qrec = nullptr, uint32_t* zero_words = nullptr) {
     OrderArgs o{};
+    o.zero_words = zero_words;
     o.qrec = qrec;
     o.no_refine = refine ? 0 : 1;
     o.rays = rays;
@@ -574,13 +581,15 @@ static nif_status query_in(nif_ctx* c, int32_t dtype, const float* rays, const i
     nif_status st = NIF_OK;
     const uint32_t* perm = nullptr;
     float4* qrec = nullptr;
+    uint32_t* ctr = nullptr;
     if (need > 0) {
         qrec = records_in(c, ws, n);
-        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, window_sorted(c), qrec);
+        ctr = tile_ctr_in(c, ws, n);
+        st = run_order(c, rays, ids, tmax, n, nullptr, ws, &perm, (hipStream_t)stream, window_sorted(c), qrec, ctr);
         if (st != NIF_OK) return st;
     }
-    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec, -1,
-                     need > 0 ? tile_ctr_in(c, ws, n) : nullptr);
+    return run_query(c, dtype, rays, ids, tmax, perm, n, vis, logits, (hipStream_t)stream, 0, qrec, -1, ctr,
+                     ctr != nullptr);
 }
 
 extern "C" nif_status nif_query(nif_ctx* c, int32_t dtype, const float* rays, const int32_t* ids, const float* tmax,
@@ -1107,13 +1116,15 @@ struct nif_plan {
 static nif_status plan_run(nif_plan* p, const Sched& sc, hipStream_t s) {
     const uint32_t* perm = nullptr;
     float4* qrec = nullptr;
+    uint32_t* ctr = tile_ctr_in(p->c, p->ws, p->n);
     if (sc.order > 0) {
         qrec = records_in(p->c, p->ws, p->n);
-        nif_status st = run_order(p->c, p->rays, p->ids, p->tmax, p->n, nullptr, p->ws, &perm, s, sc.order == 2, qrec);
+        nif_status st = run_order(p->c, p->rays, p->ids, p->tmax, p->n, nullptr, p->ws, &perm, s, sc.order == 2, qrec,
+                                  ctr);
         if (st != NIF_OK) return st;
     }
     return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu,
-                     qrec, sc.shape, tile_ctr_in(p->c, p->ws, p->n));
+                     qrec, sc.shape, ctr, sc.order > 0);
 }
 
 // Tuning cache: a text file of one JSON object per line, {"key": "...",

@@ -281,6 +281,24 @@ constexpr int shape_batch(int SH, int NL, bool image) {
 }
 constexpr int shape_waves(int FLAV, int SH) { return SH == 1 ? 2 : SH == 2 ? 4 : (FLAV == kF32 ? 2 : 3); }
 
+// End of a launch that takes its tiles from counters: every block counts
+// itself out on its XCD's line, and the XCD's last block zeroes the XCD's two
+// counters for the next launch on them.  Every block's final, failing fetch
+// has returned its value (the block read it to stop) before the block counts
+// itself out, so no fetch can follow the zeroing; all of it is device-scope
+// atomics, and no fence is needed (a release fence per block would write back
+// the L2).  Per-XCD counts keep the end-of-launch atomics on eight lines
+// instead of one.
+__device__ __forceinline__ void finish_tiles(uint32_t* ctr) {
+    if (threadIdx.x != 0) return;
+    const int x = blockIdx.x & 7;
+    const uint32_t done = atomicAdd(ctr + (8 + x) * kTileCtrStride, 1u);
+    if (done == gridDim.x / 8 - 1) {  // the grid is a multiple of 8 blocks
+        atomicExch(ctr + x * kTileCtrStride, 0u);
+        atomicExch(ctr + (8 + x) * kTileCtrStride, 0u);
+    }
+}
+
 template <int FLAV, int L, typename GT, int MODE, int IMG, int SH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_waves(FLAV, SH)))) void nif_query_kernel(FwdArgs A) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -312,15 +330,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
         return next_tile;
     };
     const int64_t first_tile = tile_at(0);
-    if (first_tile >= lim) return;
 
-    // MLP of the block: that of the first query of its first tile
+    // MLP of the block: that of the first query of its first tile (a block
+    // without tiles goes straight to the end)
     int32_t blk_mlp = A.fixed_mlp;
-    if (MODE == 0) {
+    if (MODE == 0 && first_tile < lim) {
         const int32_t id0 = slot_object(A, first_tile * kQueriesPerBlock);
         if (id0 >= 0 && id0 < A.num_objects) blk_mlp = A.objs[id0].mlp;
     }
-    if (MODE != 1) {
+    if (MODE != 1 && first_tile < lim) {
         const uint8_t* src = A.packed + (int64_t)blk_mlp * A.pack.bytes;
         const int nvec = (int)(A.pack.bytes / 16);
         for (int i = threadIdx.x; i < nvec; i += kBlock)
@@ -474,6 +492,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
             if (A.logit) A.logit[q] = zo;
         }
     }
+    if (A.tile_ctr && A.tile_ctr_reset) finish_tiles(A.tile_ctr);
 }
 
 // Inference stage on 16-bit features stored in the MLP's operand format: the
@@ -542,8 +561,8 @@ hipError_t launch_mlp16(int flavor, int levels, const FwdArgs& a, int num_cus, h
     return hipErrorInvalidValue;
 }
 
-// Zero the tile counters right before the launch that uses them (a kernel,
-// not a memset, so that the pair can be captured into a graph).
+// Zero tile counters of unknown content right before the launch that uses
+// them (a kernel, not a memset, so that the pair can be captured into a graph).
 __global__ void tile_ctr_reset_kernel(uint32_t* ctr) { ctr[threadIdx.x] = 0u; }
 
 template <int FLAV, int L, typename GT, int MODE, int IMG, int SH>
@@ -557,7 +576,8 @@ static hipError_t launch_t(const FwdArgs& a0, int num_cus, hipStream_t s) {
     a.num_tiles = (int32_t)tiles;
     a.tiles_per_block_num = (int32_t)blocks;
     a.xcd_stride = (int32_t)(blocks / 8);
-    if (a.tile_ctr) hipLaunchKernelGGL(tile_ctr_reset_kernel, dim3(1), dim3(8 * kTileCtrStride), 0, s, a.tile_ctr);
+    if (a.tile_ctr && !a.tile_ctr_reset)  // counters of unknown content: zero them first
+        hipLaunchKernelGGL(tile_ctr_reset_kernel, dim3(1), dim3(kTileCtrWords), 0, s, a.tile_ctr);
     const size_t lds = MODE == 1 ? 0 : lds_bytes(a.pack);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)nif_query_kernel<FLAV, L, GT, MODE, IMG, SH>,

@@ -74,13 +74,16 @@ struct FwdArgs {
     int64_t ioff[3 * kMaxLevels];  // table offsets inside an image (elements)
     const float4* qrec;           // nullable: query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
     int32_t shape;                // tile shape of the fused query (0 default, 1, 2; see shape_batch)
-    uint32_t* tile_ctr;           // fused query: per-XCD tile counters (kTileCtrBytes, zeroed by the launch); null = static tiles
+    uint32_t* tile_ctr;           // fused query: tile counters (kTileCtrBytes); null = static tiles
+    int32_t tile_ctr_reset;       // 1: the counters are zero at launch and its last block zeroes them again;
+                                  // 0: of unknown content, zeroed by a kernel before the launch
 };
 
-// Tile counters of one fused-query launch: one 32-bit counter per XCD, each on
-// its own 256-byte line.
+// Tile counters of one fused-query launch: per XCD a 32-bit tile counter and
+// a count of its finished blocks, each on its own 256-byte line.
 constexpr int kTileCtrStride = 64;
-constexpr size_t kTileCtrBytes = 8 * kTileCtrStride * sizeof(uint32_t);
+constexpr int kTileCtrWords = 16 * kTileCtrStride;
+constexpr size_t kTileCtrBytes = kTileCtrWords * sizeof(uint32_t);
 
 // The paper's own networks: per object its box and its grid buffer of each
 // network (binary16: position grid, direction grid, and for the inner network
@@ -175,6 +178,7 @@ struct OrderArgs {
     int32_t no_refine;     // 1: bucket order only (skip the window sort)
     uint32_t* perm;
     float4* qrec;          // nullable: receives query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
+    uint32_t* zero_words;  // nullable: kTileCtrWords words the count pass zeroes (the next query's tile counters)
 };
 
 int order_bits(int32_t num_objects);

@@ -100,6 +100,8 @@ constexpr int kOrderThreads = 1024;
 constexpr int64_t kOrderTile = 8192;  // queries per block
 __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A) {
     extern __shared__ uint32_t cnt[];
+    if (A.zero_words && blockIdx.x == 0)
+        for (int k = threadIdx.x; k < kTileCtrWords; k += blockDim.x) A.zero_words[k] = 0u;
     for (uint32_t k = threadIdx.x; k < A.num_buckets; k += blockDim.x) cnt[k] = 0;
     __syncthreads();
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
@@ -237,26 +239,42 @@ constexpr int kBuckets = 1 << kDigit;
 // Stable LSD radix sort of the block's kRefine (key, value) pairs on the key's
 // low `bits` bits, in LDS.  Items are held blocked (thread t holds items
 // 16 t .. 16 t + 15 of the current order).  One pass per 4-bit digit: every
-// thread counts its items' digits into column t of a [digit][thread] table,
-// an exclusive scan of the table in digit-major order gives each (digit,
-// thread) its first destination, and items go there in their order, so that
-// equal digits keep their relative order.
+// thread counts its items' digits in registers (16 counters of 8 bits packed
+// in two 64-bit words) and writes them to column t of a [digit][thread]
+// table; an exclusive scan of the table in digit-major order gives each
+// (digit, thread) its first destination, and items go there in their order
+// (the table entry plus the thread's running count of that digit), so that
+// equal digits keep their relative order.  LDS indices are padded by one word
+// per 32 (lds_pad) so that the strided accesses of the blocked arrangement
+// fall into distinct banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+
 struct RefineSortStorage {
-    uint32_t key[kRefine];
-    uint32_t val[kRefine];
-    uint32_t table[kBuckets * kRefineThreads];
+    uint32_t key[kRefine + kRefine / 32];
+    uint32_t val[kRefine + kRefine / 32];
+    uint32_t table[kBuckets * kRefineThreads + kBuckets * kRefineThreads / 32];
     uint32_t part[kRefineThreads];
 };
 
+__device__ __forceinline__ uint32_t packed_count(uint64_t lo, uint64_t hi, uint32_t d) {
+    return (uint32_t)(((d < 8 ? lo : hi) >> (8 * (d & 7))) & 0xffu);
+}
+
 __device__ __forceinline__ void refine_radix_sort(uint32_t (&key)[kRefineItems], uint32_t (&val)[kRefineItems],
                                                   RefineSortStorage& S, int bits) {
+    static_assert(kBuckets == 16 && kRefineItems < 256, "8-bit packed counters of 16 digits");
     const int t = threadIdx.x;
     for (int shift = 0; shift < bits; shift += kDigit) {
-        // thread t owns column t of the table: counts without atomics
+        uint64_t lo = 0, hi = 0;
 #pragma unroll
-        for (int b = 0; b < kBuckets; ++b) S.table[b * kRefineThreads + t] = 0;
+        for (int j = 0; j < kRefineItems; ++j) {
+            const uint32_t d = (key[j] >> shift) & (kBuckets - 1);
+            const uint64_t one = 1ull << (8 * (d & 7));
+            lo += d < 8 ? one : 0ull;
+            hi += d < 8 ? 0ull : one;
+        }
 #pragma unroll
-        for (int j = 0; j < kRefineItems; ++j) ++S.table[((key[j] >> shift) & (kBuckets - 1)) * kRefineThreads + t];
+        for (int b = 0; b < kBuckets; ++b) S.table[lds_pad(b * kRefineThreads + t)] = packed_count(lo, hi, b);
         __syncthreads();
         // exclusive scan of the table (kBuckets x kRefineThreads entries, digit-major):
         // thread t scans entries 16 t .. 16 t + 15, then the block scans the thread sums
@@ -266,7 +284,7 @@ __device__ __forceinline__ void refine_radix_sort(uint32_t (&key)[kRefineItems],
 #pragma unroll
         for (int e = 0; e < per; ++e) {
             loc[e] = run;
-            run += S.table[t * per + e];
+            run += S.table[lds_pad(t * per + e)];
         }
         S.part[t] = run;
         __syncthreads();
@@ -278,22 +296,25 @@ __device__ __forceinline__ void refine_radix_sort(uint32_t (&key)[kRefineItems],
         }
         const uint32_t base = t ? S.part[t - 1] : 0u;
 #pragma unroll
-        for (int e = 0; e < per; ++e) S.table[t * per + e] = base + loc[e];
+        for (int e = 0; e < per; ++e) S.table[lds_pad(t * per + e)] = base + loc[e];
         __syncthreads();
-        // scatter in order: an item's destination is its (digit, thread) start plus the
-        // number of this thread's earlier items with the same digit
+        // scatter in order: the (digit, thread) start plus the thread's earlier items of that digit
+        uint64_t rlo = 0, rhi = 0;
 #pragma unroll
         for (int j = 0; j < kRefineItems; ++j) {
             const uint32_t d = (key[j] >> shift) & (kBuckets - 1);
-            const uint32_t dst = S.table[d * kRefineThreads + t]++;
-            S.key[dst] = key[j];
-            S.val[dst] = val[j];
+            const uint32_t dst = S.table[lds_pad(d * kRefineThreads + t)] + packed_count(rlo, rhi, d);
+            const uint64_t one = 1ull << (8 * (d & 7));
+            rlo += d < 8 ? one : 0ull;
+            rhi += d < 8 ? 0ull : one;
+            S.key[lds_pad(dst)] = key[j];
+            S.val[lds_pad(dst)] = val[j];
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kRefineItems; ++j) {
-            key[j] = S.key[t * kRefineItems + j];
-            val[j] = S.val[t * kRefineItems + j];
+            key[j] = S.key[lds_pad(t * kRefineItems + j)];
+            val[j] = S.val[lds_pad(t * kRefineItems + j)];
         }
         __syncthreads();
     }

@@ -512,10 +512,20 @@ __global__ void pairs_zero_total_kernel(int64_t* total) {
     if (threadIdx.x == 0) *total = 0;
 }
 
-// Ray visibility: 1 unless some pair of the ray has visibility < 0.5.
+// Ray visibility: 1 unless some pair of the ray has visibility < 0.5.  The
+// initial ones go out as 16-byte stores from the first 16-byte boundary on;
+// the bytes before it and after the last whole 16 bytes one by one.
 __global__ void combine_init_kernel(uint8_t* ray_visible, int64_t n_rays) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rays; r += (int64_t)gridDim.x * blockDim.x)
-        ray_visible[r] = 1;
+    const int64_t lead = (int64_t)((16u - (uint32_t)(reinterpret_cast<uintptr_t>(ray_visible) & 15u)) & 15u);
+    const int64_t head = lead < n_rays ? lead : n_rays;
+    const int64_t body = (n_rays - head) / 16;
+    const int64_t tail0 = head + body * 16;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint4* v = reinterpret_cast<uint4*>(ray_visible + head);
+    for (int64_t i = t; i < body; i += stride) v[i] = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    const int64_t edge = head + (n_rays - tail0);
+    for (int64_t i = t; i < edge; i += stride) ray_visible[i < head ? i : tail0 + (i - head)] = 1;
 }
 
 __global__ void combine_pairs_kernel(const uint32_t* __restrict__ pair_ray, const float* __restrict__ vis,
@@ -614,7 +624,8 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
 hipError_t launch_combine_pairs(const uint32_t* pair_ray, const float* vis, int64_t n_pairs, int64_t n_rays,
                                 uint8_t* ray_visible, bool init, hipStream_t s) {
     if (init && n_rays > 0)
-        hipLaunchKernelGGL(combine_init_kernel, dim3(grid_for(n_rays, 256)), dim3(256), 0, s, ray_visible, n_rays);
+        hipLaunchKernelGGL(combine_init_kernel, dim3(grid_for((n_rays + 15) / 16, 256)), dim3(256), 0, s, ray_visible,
+                           n_rays);
     if (n_pairs > 0)
         hipLaunchKernelGGL(combine_pairs_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, pair_ray, vis, n_pairs,
                            n_rays, ray_visible);

@@ -163,6 +163,29 @@ def test_pairs_empty_inputs():
     assert (out.cpu().numpy() == 1).all()  # rays without pairs are visible
 
 
+@pytest.mark.parametrize("offset", [0, 3])
+@pytest.mark.parametrize("n_rays", [1, 15, 17, 1000003])
+def test_combine_output_alignment(offset, n_rays):
+    """The per-ray output is written with 16-byte stores between its first and
+    last 16-byte boundaries and byte by byte around them: every ray of an
+    output that starts off a boundary and ends in the middle of 16 bytes is
+    set, bytes around the output are left alone."""
+    import torch
+    w = _scene(n=40)
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    g = np.random.default_rng(n_rays)
+    n_pairs = min(n_rays, 5000)
+    pray = np.sort(g.integers(0, n_rays, n_pairs)).astype(np.uint32)
+    y = g.uniform(0, 1, n_pairs).astype(np.float32)
+    buf = torch.full((n_rays + 64,), 7, dtype=torch.uint8, device="cuda")
+    out = buf[offset:offset + n_rays]
+    ctx.combine_pairs(torch.from_numpy(pray.view(np.int32)).cuda(), torch.from_numpy(y).cuda(), n_rays, out=out)
+    got = buf.cpu().numpy()
+    np.testing.assert_array_equal(got[offset:offset + n_rays], O.combine_pairs(pray, y, n_rays))
+    assert (got[:offset] == 7).all() and (got[offset + n_rays:] == 7).all()
+
+
 @pytest.mark.parametrize("K", [12, 70])  # hit masks (<= 64 objects), tree traversal (> 64)
 def test_early_out_rounds(K):
     """The early-out form (Sec. 7): round 1 is each ray's first box (smallest
