@@ -728,42 +728,46 @@ def run_scene(args):
 
     # early-out form (Sec. 7): each ray's first box in round 1, the other pairs of
     # the rays still visible in round 2; the same per-ray result with fewer queries
-    ctx.prepare(SCENE_DTYPE)
-    expand()  # the one-round result of the headline dtype, for comparison
-    ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
-    ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
-    vis_all = ctx.combine_pairs(pray[:P], yq, n)
-    vis2 = torch.empty(n, dtype=torch.uint8, device="cuda")
+    # (on request: its launches of the query kernel are smaller than the step's,
+    # and a kernel trace of the default run should average the step's launches)
+    early_out = None
+    if getattr(args, "early_out", False):
+        ctx.prepare(SCENE_DTYPE)
+        expand()  # the one-round result of the headline dtype, for comparison
+        ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
+        ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
+        vis_all = ctx.combine_pairs(pray[:P], yq, n)
+        vis2 = torch.empty(n, dtype=torch.uint8, device="cuda")
 
-    def expand_round(rnd):
-        nif._check(L.nif_expand_pairs_round(ctx.h, rays.data_ptr(), tmax.data_ptr(), n, rnd, vis2.data_ptr(), maxp,
-                                            pr.data_ptr(), pt.data_ptr(), pi.data_ptr(), pray.data_ptr(),
-                                            cnt.data_ptr(), pws.data_ptr(), pws.numel(), nif._stream()),
-                   "nif_expand_pairs_round")
+        def expand_round(rnd):
+            nif._check(L.nif_expand_pairs_round(ctx.h, rays.data_ptr(), tmax.data_ptr(), n, rnd, vis2.data_ptr(), maxp,
+                                                pr.data_ptr(), pt.data_ptr(), pi.data_ptr(), pray.data_ptr(),
+                                                cnt.data_ptr(), pws.data_ptr(), pws.numel(), nif._stream()),
+                       "nif_expand_pairs_round")
 
-    counts = []
-    for rnd in (1, 2):  # pair counts of the two rounds (fixed for these rays)
-        expand_round(rnd)
-        counts.append(int(cnt.item()))
-        ctx.order_packed(pr[:counts[-1]], pi[:counts[-1]], pt[:counts[-1]], perm=perm[:counts[-1]],
-                         packed=recs[:counts[-1]], ws=ows)
-        ctx.query_packed(recs[:counts[-1]], perm[:counts[-1]], dtype=SCENE_DTYPE, out=yq[:counts[-1]])
-        ctx.combine_pairs(pray[:counts[-1]], yq[:counts[-1]], n, out=vis2, accumulate=rnd == 2)
-    P1, P2 = counts
-
-    def early_out_step():
-        for rnd, Pr in ((1, P1), (2, P2)):
+        counts = []
+        for rnd in (1, 2):  # pair counts of the two rounds (fixed for these rays)
             expand_round(rnd)
-            ctx.order_packed(pr[:Pr], pi[:Pr], pt[:Pr], perm=perm[:Pr], packed=recs[:Pr], ws=ows)
-            ctx.query_packed(recs[:Pr], perm[:Pr], dtype=SCENE_DTYPE, out=yq[:Pr])
-            ctx.combine_pairs(pray[:Pr], yq[:Pr], n, out=vis2, accumulate=rnd == 2)
+            counts.append(int(cnt.item()))
+            ctx.order_packed(pr[:counts[-1]], pi[:counts[-1]], pt[:counts[-1]], perm=perm[:counts[-1]],
+                             packed=recs[:counts[-1]], ws=ows)
+            ctx.query_packed(recs[:counts[-1]], perm[:counts[-1]], dtype=SCENE_DTYPE, out=yq[:counts[-1]])
+            ctx.combine_pairs(pray[:counts[-1]], yq[:counts[-1]], n, out=vis2, accumulate=rnd == 2)
+        P1, P2 = counts
 
-    eo_sec = time_launches(early_out_step, max(5, args.steps // 2), args.warmup)
-    early_out = {"ms": eo_sec * 1e3, "rays_per_s": n / eo_sec, "pairs_round1": P1, "pairs_round2": P2,
-                 "pairs_one_round": P, "same_ray_visibility": bool(torch.equal(vis2, vis_all)),
-                 "vs_one_round_ms": res[SCENE_DTYPE]["ms"]}
-    log(f"early-out ({SCENE_DTYPE}): {P1} + {P2} pairs in two rounds against {P} in one, step {eo_sec * 1e3:.3f} ms "
-        f"against {res[SCENE_DTYPE]['ms']:.3f} ms; same ray visibility: {early_out['same_ray_visibility']}")
+        def early_out_step():
+            for rnd, Pr in ((1, P1), (2, P2)):
+                expand_round(rnd)
+                ctx.order_packed(pr[:Pr], pi[:Pr], pt[:Pr], perm=perm[:Pr], packed=recs[:Pr], ws=ows)
+                ctx.query_packed(recs[:Pr], perm[:Pr], dtype=SCENE_DTYPE, out=yq[:Pr])
+                ctx.combine_pairs(pray[:Pr], yq[:Pr], n, out=vis2, accumulate=rnd == 2)
+
+        eo_sec = time_launches(early_out_step, max(5, args.steps // 2), args.warmup)
+        early_out = {"ms": eo_sec * 1e3, "rays_per_s": n / eo_sec, "pairs_round1": P1, "pairs_round2": P2,
+                     "pairs_one_round": P, "same_ray_visibility": bool(torch.equal(vis2, vis_all)),
+                     "vs_one_round_ms": res[SCENE_DTYPE]["ms"]}
+        log(f"early-out ({SCENE_DTYPE}): {P1} + {P2} pairs in two rounds against {P} in one, step {eo_sec * 1e3:.3f} ms "
+            f"against {res[SCENE_DTYPE]['ms']:.3f} ms; same ray visibility: {early_out['same_ray_visibility']}")
 
     cpu, errs = None, None
     if not (args.no_cpu or args.quick):
@@ -1082,6 +1086,8 @@ def main():
                     help="scene: skip the per-object training (initial models; for counter runs of the query step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--early-out", action="store_true",
+                    help="scene: also time the two-round early-out form (Sec. 7)")
     ap.add_argument("--quick", action="store_true",
                     help="time the headline step only (no per-dtype sweep, no CPU baseline): for profilers")
     args = ap.parse_args()
