@@ -519,3 +519,45 @@ def test_concurrent_calls_on_streams():
             assert torch.equal(o, alone)
     check_outputs(alone.cpu().numpy(), alone_z.cpu().numpy(), model.forward(w["rays"], w["ids"], w["tmax"]), "f32",
                   "concurrent")
+
+
+@pytest.mark.parametrize("dtype", ["f16", "fp8"])
+def test_tile_shape_1_many_objects(dtype):
+    """Blocks reload their LDS weights when their next tile starts another
+    object: with 16 objects of their own MLPs and ordered queries (blocks cross
+    object boundaries often), tile shape 1 gives outputs bit-identical to shape
+    0 and within the reduced-precision criteria of the oracle, through
+    nif_query (tile counters in the workspace) and nif_query_packed (the
+    context's ring, launched three times)."""
+    import torch
+    from paper_2306_07191_amd import nif
+    K, n = 16, 120000
+    w = S.multi_workload(n_objects=K, n_rays=n)
+    w["shape"] = S.FRAME
+    w["mlps"] = np.stack([S.xavier_mlp(S.FRAME, S.rng(71, 3, k)) for k in range(K)])
+    w["mlp_index"] = np.arange(K, dtype=np.int32)
+    scales = None
+    if dtype == "fp8":
+        exact0 = O.Model(w["shape"], w["aabb"], w["mlps"], mlp_index=w["mlp_index"], grid_seed=GRID_SEED, grid_amp=0.5)
+        scales = fp8_scales_from_oracle(exact0, w, n_cal=n)
+    ctx, model = make_pair(w, grid_amp=0.5, quant=dtype, fp8_scales=scales)
+    ctx.set_option(nif.NIF_OPT_ORDER, 1)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    outs = {}
+    for shape in (0, 1):
+        ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
+        outs[shape] = run_query(ctx, w, dtype)
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    rays, ids, tmax = (torch.from_numpy(np.ascontiguousarray(w[k])).cuda() for k in ("rays", "ids", "tmax"))
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    recs = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    ows = torch.empty(int(nif.lib().nif_order_workspace_bytes(ctx.h, n)), dtype=torch.uint8, device="cuda")
+    ctx.order_packed(rays, ids, tmax, perm=perm, packed=recs, ws=ows)
+    for _ in range(3):  # the ring's blocks are left at zero by every launch
+        y = ctx.query_packed(recs, perm, dtype=dtype)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(y.cpu().numpy().astype(np.float64), outs[1][0])
+    ref = model.forward(w["rays"], w["ids"], w["tmax"])
+    exact = model.with_(quant="exact").forward(w["rays"], w["ids"], w["tmax"])
+    check_outputs(outs[1][0], outs[1][1], ref, dtype, f"shape 1 {dtype}", exact=exact)
