@@ -363,9 +363,10 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         HIP_TRY(hipMalloc(&c->d_flags, 256));
         HIP_TRY(launch_fill_u32(c->d_flags, 1, 0u, s));
     }
-    if (!c->d_tile_ring) {  // zero once; every launch on a block leaves it zero
+    if (!c->d_tile_ring) {  // zero once, on the stream of the weights; every launch on a block leaves it zero
         HIP_TRY(hipMalloc(&c->d_tile_ring, kTileRing * kTileCtrBytes));
-        HIP_TRY(hipMemset(c->d_tile_ring, 0, kTileRing * kTileCtrBytes));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_tile_ring), (int64_t)(kTileRing * kTileCtrBytes / 4),
+                                0u, s));
     }
     // query images of the grids, in the caller's buffers (rebuilt on every
     // call: the grids may have changed)
