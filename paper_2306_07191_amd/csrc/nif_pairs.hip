@@ -32,11 +32,11 @@
 // room to spare, so box k overlaps the lane box and hence the bundle.
 //
 // Passes: (1) count: the hits of every ray (a 64-bit mask with at most 64
-// objects, else a count) and the total of every 256-ray tile; (2) an
-// exclusive scan of the tile totals in one block, which also writes the pair
-// total; (3) emit: per tile a block scan of the ray counts, then the pairs in
-// ray order, objects ascending within a ray.  The output is the same as a
-// test of every box for every ray.
+// objects, else a count) and the total of every block's contiguous run of
+// 256-ray tiles; (2) an exclusive scan of the block totals in one block, which
+// also writes the pair total; (3) emit, over the same runs: per tile a block
+// scan of the ray counts, then the pairs in ray order, objects ascending
+// within a ray.  The output is the same as a test of every box for every ray.
 #include "nif_device.h"
 #include "nif_internal.h"
 
