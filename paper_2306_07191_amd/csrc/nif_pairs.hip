@@ -138,15 +138,30 @@ __device__ __forceinline__ bool decide_hit(const RayPre& r, const float lo[3], c
     return clip_segment(r.o, r.d, r.tm, lo, hi, ta, tb);
 }
 
+// Wave-wide min / max by DPP steps (quad permutes, row mirrors, row
+// broadcasts): lane 63 ends with the result over all 64 lanes.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+    const int x = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(x, x, CTRL, ROWS, 0xf, false));
+}
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
-    return v;
+    v = fminf(v, dpp_f<0xB1, 0xf>(v));
+    v = fminf(v, dpp_f<0x4E, 0xf>(v));
+    v = fminf(v, dpp_f<0x141, 0xf>(v));
+    v = fminf(v, dpp_f<0x140, 0xf>(v));
+    v = fminf(v, dpp_f<0x142, 0xa>(v));
+    v = fminf(v, dpp_f<0x143, 0xc>(v));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    return v;
+    v = fmaxf(v, dpp_f<0xB1, 0xf>(v));
+    v = fmaxf(v, dpp_f<0x4E, 0xf>(v));
+    v = fmaxf(v, dpp_f<0x141, 0xf>(v));
+    v = fmaxf(v, dpp_f<0x140, 0xf>(v));
+    v = fmaxf(v, dpp_f<0x142, 0xa>(v));
+    v = fmaxf(v, dpp_f<0x143, 0xc>(v));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 __device__ __forceinline__ float lane_f(float v, int j) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
