@@ -646,45 +646,63 @@ def run_scene(args):
     fp = latent_footprint(pr[:P], pt[:P], pi[:P], w["aabb"], ctx.level_res, sh.feats, 2)
     yq = torch.empty(P, dtype=torch.float32, device="cuda")
     perm = torch.empty(P, dtype=torch.int32, device="cuda")
-    recs = torch.empty((P, 8), dtype=torch.float32, device="cuda")
+    recs = torch.empty((maxp, 8), dtype=torch.float32, device="cuda")
+    keys = torch.empty(maxp, dtype=torch.int32, device="cuda")
+
+    def expand_packed():  # the pairs as query records with their ordering keys
+        nif._check(L.nif_expand_pairs_packed(ctx.h, rays.data_ptr(), tmax.data_ptr(), n, maxp, recs.data_ptr(),
+                                             pray.data_ptr(), keys.data_ptr(), cnt.data_ptr(), pws.data_ptr(),
+                                             pws.numel(), nif._stream()), "nif_expand_pairs_packed")
+
+    def expand_and_order(path, ev=None):
+        """Pair expansion then ordering, by one of two paths: "keys" writes the
+        query records and keys with the pairs and orders by the keys alone;
+        "arrays" writes the pairs as arrays and the ordering reads them and
+        writes the records."""
+        if path == "keys":
+            expand_packed()
+            if ev: ev.record(stream)
+            ctx.order_keys(keys[:P], perm=perm, ws=ows)
+        else:
+            expand()
+            if ev: ev.record(stream)
+            ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs[:P], ws=ows)
     ows = torch.empty(max(1, int(L.nif_order_workspace_bytes(ctx.h, P))), dtype=torch.uint8, device="cuda")
     vis = torch.empty(n, dtype=torch.uint8, device="cuda")
     flops = 2 * (sh.din * sh.width + (sh.hidden - 1) * sh.width * sh.width + sh.width)  # 30,848 per query
     res, gpu_y = {}, {}
     mask_ref = lab.reshape(-1, S.SCENE_SPP).mean(axis=1)
     stream = torch.cuda.current_stream()
-    # schedule: ordering with or without the window sort (the finer Morton key),
-    # and the fused kernel's tile shape, whichever makes the headline step
-    # fastest on these pairs
+    # schedule: the pair path, ordering with or without the window sort (the
+    # finer Morton key), and the fused kernel's tile shape, whichever makes the
+    # headline step fastest on these pairs
     ctx.prepare(SCENE_DTYPE)
     sched = {}
-    for wsort in (1, 0):
-        for shape in (0, 1, 2):
-            ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
-            ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
+    for path in ("keys", "arrays"):
+        for wsort in (1, 0):
+            for shape in (0, 1, 2):
+                ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
+                ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
 
-            def one():
-                expand()
-                ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
-                ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
-                ctx.combine_pairs(pray[:P], yq, n, out=vis)
+                def one():
+                    expand_and_order(path)
+                    ctx.query_packed(recs[:P], perm, dtype=SCENE_DTYPE, out=yq)
+                    ctx.combine_pairs(pray[:P], yq, n, out=vis)
 
-            sched[(wsort, shape)] = time_launches(one, 10, 3) * 1e3
-    window_sort, tile_shape = min(sched, key=sched.get)
+                sched[(path, wsort, shape)] = time_launches(one, 10, 3) * 1e3
+    pair_path, window_sort, tile_shape = min(sched, key=sched.get)
     ctx.set_option(nif.NIF_OPT_WINDOW_SORT, window_sort)
     ctx.set_option(nif.NIF_OPT_TILE_SHAPE, tile_shape)
-    log("step ms by (window sort, tile shape): " + ", ".join(f"{k}: {v:.3f}" for k, v in sched.items()) +
-        f"; chosen {(window_sort, tile_shape)}")
+    log("step ms by (pair path, window sort, tile shape): " + ", ".join(f"{k}: {v:.3f}" for k, v in sched.items()) +
+        f"; chosen {(pair_path, window_sort, tile_shape)}")
     for dt in ((SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")):
         ctx.prepare(dt)
         steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
 
         def stages(ev=None):
-            expand()
-            if ev: ev[0].record(stream)
-            ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
+            expand_and_order(pair_path, ev[0] if ev else None)
             if ev: ev[1].record(stream)
-            ctx.query_packed(recs, perm, dtype=dt, out=yq)
+            ctx.query_packed(recs[:P], perm, dtype=dt, out=yq)
             if ev: ev[2].record(stream)
             ctx.combine_pairs(pray[:P], yq, n, out=vis)
 
@@ -714,7 +732,8 @@ def run_scene(args):
         mis = float((v != lab).mean())
         mse = float(((v.reshape(-1, S.SCENE_SPP).mean(axis=1) - mask_ref) ** 2).mean())
         psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
-        res[dt] = {"ms": sec * 1e3, "rays_per_s": n / sec, "pairs_per_s": P / sec, "misclassification": mis,
+        res[dt] = {"ms": sec * 1e3, "rays_per_s": n / sec, "pairs_per_s": P / sec, "pair_path": pair_path,
+                   "misclassification": mis,
                    "psnr_db": psnr, "stage_ms": {"pair_expansion": t_exp * 1e3, "ordering": t_ord * 1e3,
                                                  "query_kernel": t_q * 1e3, "combination": t_comb * 1e3},
                    "query_kernel_tflops": flops * P / t_q / 1e12, "wall_s": wall}
@@ -734,8 +753,8 @@ def run_scene(args):
     if getattr(args, "early_out", False):
         ctx.prepare(SCENE_DTYPE)
         expand()  # the one-round result of the headline dtype, for comparison
-        ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs, ws=ows)
-        ctx.query_packed(recs, perm, dtype=SCENE_DTYPE, out=yq)
+        ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs[:P], ws=ows)
+        ctx.query_packed(recs[:P], perm, dtype=SCENE_DTYPE, out=yq)
         vis_all = ctx.combine_pairs(pray[:P], yq, n)
         vis2 = torch.empty(n, dtype=torch.uint8, device="cuda")
 
@@ -819,8 +838,8 @@ def run_scene(args):
                                "per object",
                    "rays": n, "pairs": P, "objects": K, "triangles": int(w["tri_counts"].sum()),
                    "step": "pair expansion + pair ordering + fused query kernel + per-ray combination",
-                   "window_sort": bool(window_sort), "tile_shape": tile_shape,
-                   "step_ms_by_window_sort_and_shape": {f"{k[0]}/{k[1]}": v for k, v in sched.items()},
+                   "pair_path": pair_path, "window_sort": bool(window_sort), "tile_shape": tile_shape,
+                   "step_ms_by_path_window_sort_and_shape": {"/".join(map(str, k)): v for k, v in sched.items()},
                    "value_is": "(ray, object) queries per second; rays_per_s is in per_dtype"},
         "roofline": roof,
         "cpu_baseline": cpu,

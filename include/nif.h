@@ -129,6 +129,30 @@ nif_status nif_expand_pairs(nif_ctx* ctx, const float* rays, const float* t_max,
 nif_status nif_combine_pairs(nif_ctx* ctx, const uint32_t* pair_ray, const float* visibility, int64_t n_pairs,
                              int64_t n_rays, uint8_t* ray_visible, void* stream);
 
+/* The top-level pass of Sec. 4.1 feeding the query stage directly:
+ * nif_expand_pairs_packed is nif_expand_pairs with the pairs written as the
+ * query records that nif_query_packed reads:
+ *   packed (dev, max_pairs x 8 floats, 16-byte aligned) row p = {ox, oy, oz,
+ *   dx, dy, dz, t_max, object id (int32 bit pattern)}, pair_ray as in
+ *   nif_expand_pairs, and keys (dev, max_pairs uint32, nullable) the
+ *   ordering key of each pair: (object id, Morton code of the binary32 AABB
+ *   entry point), the key nif_order and nif_order_packed compute for it.
+ *   Same pairs, order, counts, limits and workspace as nif_expand_pairs.
+ * nif_order_keys: the ordering (as nif_order) of n queries from their keys
+ *   (dev, n uint32, as written by nif_expand_pairs_packed), without reading
+ *   the queries: perm (dev, n uint32); ws: nif_order_workspace_bytes(ctx, n).
+ *   Keys must come from nif_expand_pairs_packed on the same context (the
+ *   object count fixes their layout); NIF_OPT_WINDOW_SORT applies as for
+ *   nif_order.
+ * A scene step is then nif_expand_pairs_packed, nif_order_keys,
+ * nif_query_packed and nif_combine_pairs, each pass reading what the one
+ * before wrote once. */
+nif_status nif_expand_pairs_packed(nif_ctx* ctx, const float* rays, const float* t_max, int64_t n_rays,
+                                   int64_t max_pairs, float* packed, uint32_t* pair_ray, uint32_t* keys,
+                                   int64_t* pair_count, void* ws, size_t ws_bytes, void* stream);
+nif_status nif_order_keys(nif_ctx* ctx, const uint32_t* keys, int64_t n, uint32_t* perm, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* The early-out form (Sec. 7: once one object is found to occlude a ray, its
  * other objects need not be queried), in two rounds over the same rays:
  * nif_expand_pairs_round with round = 1 writes each ray's first pair only, the

@@ -665,6 +665,28 @@ extern "C" nif_status nif_order(nif_ctx* c, const float* rays, const int32_t* id
     return run_order(c, rays, ids, tmax, n, perm, ws, &p, (hipStream_t)stream, window_sorted(c));
 }
 
+extern "C" nif_status nif_order_keys(nif_ctx* c, const uint32_t* keys, int64_t n, uint32_t* perm, void* ws,
+                                     size_t ws_bytes, void* stream) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_order_keys: NULL context");
+    if (n < 0) return fail(NIF_ERR_INVALID_ARG, "nif_order_keys: negative size");
+    if (n == 0) return ok();
+    if (!keys || !perm) return fail(NIF_ERR_INVALID_ARG, "nif_order_keys: NULL keys or perm");
+    if (n > ((int64_t)1 << 32) - 1) return fail(NIF_ERR_UNSUPPORTED, "nif_order_keys: n must be below 2^32");
+    const size_t need = order_workspace_bytes(n, c->K);
+    if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
+    if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    OrderArgs o{};
+    o.key_in = keys;
+    o.no_refine = window_sorted(c) ? 0 : 1;
+    o.n = n;
+    o.objs = c->d_objs;
+    o.num_objects = c->K;
+    o.perm = perm;
+    const uint32_t* p = nullptr;
+    HIP_TRY(launch_order(o, ws, (hipStream_t)stream, &p));
+    return ok();
+}
+
 extern "C" nif_status nif_order_packed(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax,
                                        int64_t n, uint32_t* perm, float* packed, void* ws, size_t ws_bytes,
                                        void* stream) {
@@ -756,13 +778,16 @@ extern "C" size_t nif_pairs_workspace_bytes(const nif_ctx* c, int64_t n_rays) {
 static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays, int32_t round,
                                const uint8_t* ray_visible, int64_t max_pairs, float* pair_rays, float* pair_tmax,
                                int32_t* pair_ids, uint32_t* pair_ray, int64_t* pair_count, void* ws, size_t ws_bytes,
-                               void* stream, const char* where) {
+                               void* stream, const char* where, float* packed = nullptr, uint32_t* keys = nullptr) {
     if (!c) return fail(NIF_ERR_INVALID_ARG, "%s: NULL context", where);
     if (n_rays < 0 || max_pairs < 0) return fail(NIF_ERR_INVALID_ARG, "%s: negative size", where);
     if (!pair_count) return fail(NIF_ERR_INVALID_ARG, "%s: NULL pair_count", where);
     if (n_rays > 0 && (!rays || !tmax)) return fail(NIF_ERR_INVALID_ARG, "%s: NULL rays", where);
-    if (max_pairs > 0 && (!pair_rays || !pair_tmax || !pair_ids || !pair_ray))
+    if (max_pairs > 0 && !pair_ray) return fail(NIF_ERR_INVALID_ARG, "%s: NULL pair output", where);
+    if (max_pairs > 0 && !packed && (!pair_rays || !pair_tmax || !pair_ids))
         return fail(NIF_ERR_INVALID_ARG, "%s: NULL pair output", where);
+    if (packed && reinterpret_cast<uintptr_t>(packed) % 16 != 0)
+        return fail(NIF_ERR_INVALID_ARG, "%s: packed must be 16-byte aligned", where);
     if (round < 0 || round > 2) return fail(NIF_ERR_INVALID_ARG, "%s: round must be 1 or 2", where);
     if (round == 2 && n_rays > 0 && !ray_visible) return fail(NIF_ERR_INVALID_ARG, "%s: NULL ray_visible", where);
     if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "%s: at most 2^24 rays per call", where);
@@ -773,8 +798,17 @@ static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax,
     const size_t need = pairs_workspace_bytes(n_rays, c->K);
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->tree, c->K, c->num_cus, round, ray_visible, max_pairs,
-                                pair_rays, pair_tmax, pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream));
+                                pair_rays, pair_tmax, pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream,
+                                reinterpret_cast<float4*>(packed), keys, c->d_objs));
     return ok();
+}
+
+extern "C" nif_status nif_expand_pairs_packed(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,
+                                              int64_t max_pairs, float* packed, uint32_t* pair_ray, uint32_t* keys,
+                                              int64_t* pair_count, void* ws, size_t ws_bytes, void* stream) {
+    if (max_pairs > 0 && !packed) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs_packed: NULL packed");
+    return expand_pairs(c, rays, tmax, n_rays, 0, nullptr, max_pairs, nullptr, nullptr, nullptr, pair_ray, pair_count,
+                        ws, ws_bytes, stream, "nif_expand_pairs_packed", packed, keys);
 }
 
 extern "C" nif_status nif_expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,

@@ -21,18 +21,10 @@
 // neighbours.
 
 #include "nif_device.h"
+#include "nif_order_key.h"
 #include "nif_internal.h"
 
 namespace nif {
-
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -69,29 +61,8 @@ __device__ __forceinline__ QueryIn load_query(const OrderArgs& A, int64_t i) {
 }
 
 __device__ __forceinline__ uint32_t order_key(const OrderArgs& A, const QueryIn& q, uint32_t* fine) {
-    const uint32_t cells = 1u << A.fine_bits;
-    const float* o = q.o;
-    const float* d = q.d;
-    const float tm = q.tm;
-    const int32_t id = q.id;
-    uint32_t b = A.num_buckets - 1;
-    *fine = 0xffffffffu;
-    if (valid_query(o, d, tm, id, A.num_objects)) {
-        float uin[3];
-        const ObjDev ob = A.objs[id];
-        if (clip_entry(o, d, tm, ob, uin)) {
-            uint32_t c[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                uint32_t v = (uint32_t)(uin[a] * (float)cells);  // u in [0, 1]
-                c[a] = v < cells ? v : cells - 1;
-            }
-            const uint32_t m = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
-            *fine = ((uint32_t)id << (3 * A.fine_bits)) | m;
-            b = ((uint32_t)id << (3 * A.bits)) | (m >> (3 * (A.fine_bits - A.bits)));
-        }
-    }
-    return b;
+    *fine = fine_order_key(q.o, q.d, q.tm, q.id, A.objs, A.num_objects, A.fine_bits);
+    return bucket_of_fine(*fine, A.fine_bits, A.bits, A.num_buckets);
 }
 
 // Pass 1: bucket of every query of the block's tile, counted in LDS; the
@@ -106,6 +77,12 @@ __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(OrderArgs A)
     __syncthreads();
     const int64_t begin = (int64_t)blockIdx.x * A.tile, end = begin + A.tile < A.n ? begin + A.tile : A.n;
     for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        if (A.key_in) {  // keys given (found with the pairs): the bucket is a prefix of the key
+            const uint32_t b = bucket_of_fine(A.key_in[i], A.fine_bits, A.bits, A.num_buckets);
+            A.key[i] = (uint16_t)b;
+            atomicAdd(&cnt[b], 1u);
+            continue;
+        }
         uint32_t fine;
         const QueryIn q = load_query(A, i);
         if (A.qrec) {  // the query as one 32-byte record, for the gathers through the order
@@ -381,11 +358,13 @@ int order_bits(int32_t num_objects) {
 
 // Fine key: object id and up to 8 Morton bits per axis in 31 bits, so that no
 // hit's key equals the miss key 0xffffffff.
-static int fine_bits(int32_t num_objects) {
+int order_fine_bits(int32_t num_objects) {
     int ob = 0;
     while (((int64_t)1 << ob) < num_objects) ++ob;
     int fb = (31 - ob) / 3;
-    return fb > 8 ? 8 : fb;
+    fb = fb > 8 ? 8 : fb;
+    const int b = order_bits(num_objects);  // the bucket is a prefix of the fine key
+    return fb < b ? b : fb;
 }
 
 
@@ -420,8 +399,7 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     if (A.num_objects > 4096) return hipErrorInvalidValue;
     const OrderLayout L = order_layout(A.n, A.num_objects);
     A.bits = order_bits(A.num_objects);
-    A.fine_bits = fine_bits(A.num_objects);
-    if (A.fine_bits < A.bits) A.fine_bits = A.bits;
+    A.fine_bits = order_fine_bits(A.num_objects);
     A.num_buckets = (uint32_t)L.nb;
     A.tile = kOrderTile;
     A.num_tiles = L.tiles;
@@ -431,6 +409,7 @@ hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** p
     A.key = reinterpret_cast<uint16_t*>(p + L.off_key);
     A.fine = reinterpret_cast<uint32_t*>(p + L.off_fine);
     A.coarse = reinterpret_cast<uint32_t*>(p + L.off_coarse);
+    if (A.key_in) A.fine = const_cast<uint32_t*>(A.key_in);  // the window sort reads the given keys
     if (!A.perm) A.perm = reinterpret_cast<uint32_t*>(p + L.off_perm);  // else the caller's buffer
     *perm_out = A.perm;
     const size_t lds = (size_t)L.nb * 4;

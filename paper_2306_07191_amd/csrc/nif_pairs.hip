@@ -38,6 +38,7 @@
 // scan of the ray counts, then the pairs in ray order, objects ascending
 // within a ray.  The output is the same as a test of every box for every ray.
 #include "nif_device.h"
+#include "nif_order_key.h"
 #include "nif_internal.h"
 
 namespace nif {
@@ -437,24 +438,55 @@ __global__ __launch_bounds__(kPairScanThreads) void pairs_block_scan_kernel(cons
     if (t == kPairScanThreads - 1) *total = (int64_t)part[t];
 }
 
+// Where the pairs go: separate arrays (pair_rays, pair_tmax, pair_ids), or
+// 32-byte query records {o, d.x}, {d.y, d.z, t_max, object id bits} with,
+// optionally, each pair's ordering key (the ordering's fine key, so that the
+// ordering need not read the pairs again); pair_ray always.
+struct PairOut {
+    float* pair_rays;
+    float* pair_tmax;
+    int32_t* pair_ids;
+    uint32_t* pair_ray;
+    float4* rec;
+    uint32_t* key;
+    const ObjDev* objs;
+    int32_t K;
+    int32_t fine_bits;
+};
+
 __device__ __forceinline__ void write_pair(int64_t p, const float o[3], const float d[3], float tm, int32_t k,
-                                           uint32_t ray, float* __restrict__ pair_rays, float* __restrict__ pair_tmax,
-                                           int32_t* __restrict__ pair_ids, uint32_t* __restrict__ pair_ray) {
+                                           uint32_t ray, const PairOut& out) {
+    if (out.rec) {
+        out.rec[2 * p] = make_float4(o[0], o[1], o[2], d[0]);
+        out.rec[2 * p + 1] = make_float4(d[1], d[2], tm, __int_as_float(k));
+        if (out.key) out.key[p] = fine_order_key(o, d, tm, k, out.objs, out.K, out.fine_bits);
+    } else {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        pair_rays[p * 6 + a] = o[a];
-        pair_rays[p * 6 + 3 + a] = d[a];
+        for (int a = 0; a < 3; ++a) {
+            out.pair_rays[p * 6 + a] = o[a];
+            out.pair_rays[p * 6 + 3 + a] = d[a];
+        }
+        out.pair_tmax[p] = tm;
+        out.pair_ids[p] = k;
     }
-    pair_tmax[p] = tm;
-    pair_ids[p] = k;
-    pair_ray[p] = ray;
+    out.pair_ray[p] = ray;
+}
+
+__device__ __forceinline__ int32_t pair_id(const PairOut& out, int64_t p) {
+    return out.rec ? __float_as_int(reinterpret_cast<const float*>(out.rec)[8 * p + 7]) : out.pair_ids[p];
+}
+
+__device__ __forceinline__ void set_pair_id(const PairOut& out, int64_t p, int32_t k) {
+    if (out.rec)
+        reinterpret_cast<float*>(out.rec)[8 * p + 7] = __int_as_float(k);
+    else
+        out.pair_ids[p] = k;
 }
 
 // Pass 3 with masks (at most 64 objects): ascending set bits.
 __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
-    const uint64_t* __restrict__ offs, int64_t max_pairs, float* __restrict__ pair_rays, float* __restrict__ pair_tmax,
-    int32_t* __restrict__ pair_ids, uint32_t* __restrict__ pair_ray) {
+    const uint64_t* __restrict__ offs, int64_t max_pairs, PairOut out) {
     __shared__ uint32_t sh[4];
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
     int64_t run = (int64_t)offs[blockIdx.x];
@@ -476,7 +508,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
         while (mk && p < max_pairs) {
             const int k = __builtin_ctzll(mk);
             mk &= mk - 1;
-            write_pair(p++, o, d, tm, k, (uint32_t)r, pair_rays, pair_tmax, pair_ids, pair_ray);
+            write_pair(p++, o, d, tm, k, (uint32_t)r, out);
         }
     }
 }
@@ -487,8 +519,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
 __global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
     const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, PairTree T, int32_t round,
     const int32_t* __restrict__ first_obj, const uint32_t* __restrict__ counts, const uint64_t* __restrict__ offs,
-    int64_t max_pairs, float* __restrict__ pair_rays, float* __restrict__ pair_tmax, int32_t* __restrict__ pair_ids,
-    uint32_t* __restrict__ pair_ray) {
+    int64_t max_pairs, PairOut out) {
     __shared__ uint32_t sh[4];
     const int lane = threadIdx.x & 63;
     const LaneBox B1 = level1_box(T, lane);
@@ -506,19 +537,21 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
         for_each_hit(R, B1, T, lane, [&](int32_t k, const float*, const float*) {
             // round 1: the first object only; round 2: the others (a ray with c = 0 writes none)
             if ((round == 1 && k != first) || (round == 2 && k == first) || p >= p0 + (int64_t)c) return;
-            if (p < max_pairs) write_pair(p, R.pre.o, R.pre.d, R.pre.tm, k, (uint32_t)r, pair_rays, pair_tmax,
-                                          pair_ids, pair_ray);
+            if (p < max_pairs) write_pair(p, R.pre.o, R.pre.d, R.pre.tm, k, (uint32_t)r, out);
             ++p;
         });
         const int64_t e = p < max_pairs ? p : max_pairs;
-        for (int64_t i = p0 + 1; i < e; ++i) {  // insertion sort of the ray's ids
-            const int32_t v = pair_ids[i];
+        for (int64_t i = p0 + 1; i < e; ++i) {  // insertion sort of the ray's ids, keys along
+            const int32_t v = pair_id(out, i);
+            const uint32_t kv = out.key ? out.key[i] : 0u;
             int64_t j = i - 1;
-            while (j >= p0 && pair_ids[j] > v) {
-                pair_ids[j + 1] = pair_ids[j];
+            while (j >= p0 && pair_id(out, j) > v) {
+                set_pair_id(out, j + 1, pair_id(out, j));
+                if (out.key) out.key[j + 1] = out.key[j];
                 --j;
             }
-            pair_ids[j + 1] = v;
+            set_pair_id(out, j + 1, v);
+            if (out.key) out.key[j + 1] = kv;
         }
     }
 }
@@ -605,7 +638,8 @@ static unsigned grid_for(int64_t n, int threads) {
 hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, const PairTree& T, int32_t K,
                                int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
                                float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
-                               int64_t* total, void* ws, hipStream_t s) {
+                               int64_t* total, void* ws, hipStream_t s, float4* rec, uint32_t* keys,
+                               const ObjDev* objs) {
     if (n == 0) {
         hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
         return hipGetLastError();
@@ -627,12 +661,13 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
                        masks, counts, round ? first : nullptr, sums);
     hipLaunchKernelGGL(pairs_block_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, (int64_t)blocks, offs,
                        total);
+    const PairOut out{pair_rays, pair_tmax, pair_ids, pair_ray, rec, keys, objs, K, order_fine_bits(K)};
     if (use_mask)
         hipLaunchKernelGGL(pairs_emit_mask_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, masks, offs,
-                           max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
+                           max_pairs, out);
     else
         hipLaunchKernelGGL(pairs_emit_tree_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, first,
-                           counts, offs, max_pairs, pair_rays, pair_tmax, pair_ids, pair_ray);
+                           counts, offs, max_pairs, out);
     return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 # every symbol include/nif.h declares
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
-           "nif_expand_pairs", "nif_combine_pairs", "nif_expand_pairs_round", "nif_combine_pairs_and", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
+           "nif_expand_pairs", "nif_combine_pairs", "nif_expand_pairs_round", "nif_combine_pairs_and",
+           "nif_expand_pairs_packed", "nif_order_keys", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
            "nif_encode16", "nif_mlp16",
            "nif_set_option", "nif_image_bytes", "nif_set_image", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
@@ -82,6 +83,8 @@ def lib():
             "nif_expand_pairs": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
             "nif_combine_pairs": (i32, [vp, vp, vp, i64, i64, vp, vp]),
             "nif_expand_pairs_round": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "nif_expand_pairs_packed": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp]),
+            "nif_order_keys": (i32, [vp, vp, i64, vp, vp, sz, vp]),
             "nif_combine_pairs_and": (i32, [vp, vp, vp, i64, i64, vp, vp]),
             "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
@@ -484,6 +487,38 @@ class Context:
                 return pr[:total], pt[:total], pi[:total], pray[:total]
             max_pairs = total
         raise RuntimeError("pair count changed between calls")
+
+    def expand_pairs_packed(self, rays, tmax, max_pairs=None, keys: bool = True):
+        """(packed [P, 8] float32 query records, pair_ray, keys or None) of the
+        rays' AABB hits in ray order (nif_expand_pairs_packed)."""
+        t = self.torch
+        n = tmax.shape[0]
+        ws = t.empty(max(1, int(lib().nif_pairs_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
+        cnt = t.zeros(1, dtype=t.int64, device=self.device)
+        for _ in range(2):
+            m = max(1, n if max_pairs is None else max_pairs)
+            rec = t.empty((m, 8), dtype=t.float32, device=self.device)
+            pray = t.empty(m, dtype=t.int32, device=self.device)
+            key = t.empty(m, dtype=t.int32, device=self.device) if keys else None
+            _check(lib().nif_expand_pairs_packed(self.h, _ptr(rays), _ptr(tmax), n, m, _ptr(rec), _ptr(pray), _ptr(key),
+                                                 _ptr(cnt), _ptr(ws), ws.numel(), _stream()), "nif_expand_pairs_packed")
+            total = int(cnt.item())
+            if total <= m:
+                return rec[:total], pray[:total], None if key is None else key[:total]
+            max_pairs = total
+        raise RuntimeError("pair count changed between calls")
+
+    def order_keys(self, keys, perm=None, ws=None):
+        """Ordering from the keys of expand_pairs_packed (nif_order_keys): perm."""
+        t = self.torch
+        n = keys.shape[0]
+        if perm is None:
+            perm = t.empty(n, dtype=t.int32, device=self.device)
+        if ws is None:
+            ws = t.empty(max(1, int(lib().nif_order_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
+        _check(lib().nif_order_keys(self.h, _ptr(keys), n, _ptr(perm), _ptr(ws), ws.numel(), _stream()),
+               "nif_order_keys")
+        return perm
 
     def combine_pairs(self, pair_ray, visibility, n_rays, out=None, accumulate: bool = False):
         """Per-ray visibility (uint8): 0 iff some pair of the ray is below 0.5.

@@ -227,3 +227,104 @@ def test_early_out_rounds(K):
     np.testing.assert_array_equal(vis.cpu().numpy(), full)
     print(f"K={K}: {pray.numel()} pairs in one round, {p1ray.numel()} + {p2ray.numel()} in two")
     assert p1ray.numel() + p2ray.numel() < pray.numel()
+
+
+def _fine_bits(K):
+    """Bits per axis of the ordering's fine key and of its bucket for K objects:
+    the object id and up to 8 Morton bits per axis fill 31 bits, and the
+    bucket count K x 8^bits stays at or below 4096."""
+    ob = 0
+    while (1 << ob) < K:
+        ob += 1
+    fb = min((31 - ob) // 3, 8)
+    bits = 4
+    while bits > 0 and (K << (3 * bits)) > 4096:
+        bits -= 1
+    return max(fb, bits), bits
+
+
+def _spread3(v):
+    r = np.zeros_like(v)
+    for b in range(10):
+        r |= ((v >> b) & 1) << (3 * b)
+    return r
+
+
+def _pair_keys(model, rays, tmax, pair_ray, pair_obj, fb):
+    """Ordering key of each pair from the oracle's binary32 AABB entry point:
+    (object id << 3 fb) | Morton code of the entry cell at 2^fb cells per axis,
+    0xffffffff where the oracle finds no segment."""
+    cells = np.float32(1 << fb)
+    key = np.full(pair_ray.shape[0], 0xFFFFFFFF, np.int64)
+    for p, (r, k) in enumerate(zip(pair_ray.tolist(), pair_obj.tolist())):
+        st, u, *_ = model.detail(rays[r], k, float(tmax[r]))
+        if st == 1:
+            c = np.minimum((np.float32(u[0]) * cells).astype(np.int64), (1 << fb) - 1)
+            key[p] = (k << (3 * fb)) | _spread3(c[0]) | (_spread3(c[1]) << 1) | (_spread3(c[2]) << 2)
+    return key
+
+
+@pytest.mark.parametrize("window_sort", [0, 1])
+@pytest.mark.parametrize("K", [12, 70, 300])  # hit masks (<= 64 objects), tree traversal (> 64)
+def test_packed_pairs_keys_and_key_ordering(K, window_sort):
+    """nif_expand_pairs_packed writes the pairs of nif_expand_pairs as query
+    records, bit for bit, with each pair's ordering key (object id and Morton
+    code of the entry point, checked against the oracle's entry point);
+    nif_order_keys on those keys gives the bucket sequence of nif_order_packed
+    on the pairs (and, with the window sort, every window sorted by key), and
+    the query outputs per pair are those of the path that reads the pairs."""
+    import torch
+    from paper_2306_07191_amd import nif
+    w = _grazing(_scene(n=12000, K=K, seed=31 + K), np.random.default_rng(K + 1))
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, window_sort)
+    ctx.prepare("f32")
+    rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
+    pr_rays, pr_tmax, pr_ids, pr_ray = ctx.expand_pairs(rays, tmax)
+    rec, pray, key = ctx.expand_pairs_packed(rays, tmax, max_pairs=100)  # too small: retried
+    P = pr_ray.shape[0]
+    assert P > 3000 and rec.shape[0] == P
+    np.testing.assert_array_equal(pray.cpu().numpy(), pr_ray.cpu().numpy())
+    r = rec.cpu().numpy()
+    np.testing.assert_array_equal(r[:, :6].view(np.uint32), pr_rays.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(r[:, 6].view(np.uint32), pr_tmax.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(r[:, 7].view(np.int32), pr_ids.cpu().numpy())
+    fb, bits = _fine_bits(K)
+    g_ray, g_obj = pr_ray.cpu().numpy().astype(np.int64), pr_ids.cpu().numpy().astype(np.int64)
+    kref = _pair_keys(model, w["rays"], w["tmax"], g_ray, g_obj, fb)
+    kg = key.cpu().numpy().view(np.uint32).astype(np.int64)
+    np.testing.assert_array_equal(kg, kref)
+    # the ordering from the keys against the ordering that reads the pairs
+    perm_k = ctx.order_keys(key).cpu().numpy().view(np.uint32).astype(np.int64)
+    perm_p, recs2 = ctx.order_packed(pr_rays, pr_ids, pr_tmax)
+    perm_p = perm_p.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(np.sort(perm_k), np.arange(P))
+    miss = (1 << (3 * bits)) * K
+    bucket = np.where(kref == 0xFFFFFFFF, miss, (kref >> (3 * fb)) << (3 * bits) | ((kref & ((1 << (3 * fb)) - 1)) >> (3 * (fb - bits))))
+    np.testing.assert_array_equal(bucket[perm_k], bucket[perm_p])
+    assert (np.diff(bucket[perm_k]) >= 0).all()
+    if window_sort:
+        for w0 in range(0, P, 4096):
+            assert (np.diff(kref[perm_k[w0:w0 + 4096]]) >= 0).all()
+    np.testing.assert_array_equal(r, recs2.cpu().numpy())
+    pk = torch.from_numpy(perm_k.astype(np.uint32).view(np.int32)).cuda()
+    y_k = ctx.query_packed(rec, pk, dtype="f32").cpu().numpy()
+    y_p = ctx.query(pr_rays, pr_ids, pr_tmax, dtype="f32").cpu().numpy()
+    np.testing.assert_array_equal(y_k.view(np.uint32), y_p.view(np.uint32))
+
+
+def test_packed_pairs_empty_and_no_keys():
+    import torch
+    w = _scene(n=3000, K=12)
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    e = torch.empty(0, device="cuda")
+    rec, pray, key = ctx.expand_pairs_packed(e.view(0, 6), e)
+    assert rec.shape[0] == 0 and pray.numel() == 0 and key.numel() == 0
+    assert ctx.order_keys(key).numel() == 0
+    rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
+    rec, pray, key = ctx.expand_pairs_packed(rays, tmax, keys=False)
+    assert key is None and rec.shape[0] > 1000
+    pr_rays, _, pr_ids, pr_ray = ctx.expand_pairs(rays, tmax)
+    np.testing.assert_array_equal(rec.cpu().numpy()[:, 7].view(np.int32), pr_ids.cpu().numpy())
+    np.testing.assert_array_equal(rec.cpu().numpy()[:, :6], pr_rays.cpu().numpy())
