@@ -139,30 +139,41 @@ __device__ __forceinline__ bool decide_hit(const RayPre& r, const float lo[3], c
     return clip_segment(r.o, r.d, r.tm, lo, hi, ta, tb);
 }
 
-// Wave-wide min / max by DPP steps (quad permutes, row mirrors, row
-// broadcasts): lane 63 ends with the result over all 64 lanes.
+// Wave-wide reductions by DPP steps (quad permutes, row mirrors, row
+// broadcasts): lane 63 ends with the result over all 64 lanes.  Floats are
+// reduced as integers whose order is theirs (non-negative: the bit pattern;
+// negative: its low 31 bits flipped), so each step is one integer min or max
+// with no NaN quieting; a NaN input drops out, as it does from fminf / fmaxf.
+// x from the DPP source lane; `id` (the operation's identity) in lanes of
+// masked-out rows.
 template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_f(float v) {
-    const int x = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(x, x, CTRL, ROWS, 0xf, false));
+__device__ __forceinline__ int32_t dpp_i(int32_t x, int32_t id) {
+    return __builtin_amdgcn_update_dpp(id, x, CTRL, ROWS, 0xf, false);
+}
+__device__ __forceinline__ int32_t order_int(float v) {
+    const int32_t i = __builtin_bit_cast(int32_t, v);
+    return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float order_float(int32_t i) {
+    return __builtin_bit_cast(float, i >= 0 ? i : i ^ 0x7fffffff);
+}
+template <typename Op>
+__device__ __forceinline__ int32_t wave_reduce(int32_t x, int32_t id, Op op) {
+    x = op(x, dpp_i<0xB1, 0xf>(x, id));
+    x = op(x, dpp_i<0x4E, 0xf>(x, id));
+    x = op(x, dpp_i<0x141, 0xf>(x, id));
+    x = op(x, dpp_i<0x140, 0xf>(x, id));
+    x = op(x, dpp_i<0x142, 0xa>(x, id));
+    x = op(x, dpp_i<0x143, 0xc>(x, id));
+    return __builtin_amdgcn_readlane(x, 63);
 }
 __device__ __forceinline__ float wave_min(float v) {
-    v = fminf(v, dpp_f<0xB1, 0xf>(v));
-    v = fminf(v, dpp_f<0x4E, 0xf>(v));
-    v = fminf(v, dpp_f<0x141, 0xf>(v));
-    v = fminf(v, dpp_f<0x140, 0xf>(v));
-    v = fminf(v, dpp_f<0x142, 0xa>(v));
-    v = fminf(v, dpp_f<0x143, 0xc>(v));
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    const int32_t x = order_int(v != v ? INFINITY : v);
+    return order_float(wave_reduce(x, INT32_MAX, [](int32_t a, int32_t b) { return a < b ? a : b; }));
 }
 __device__ __forceinline__ float wave_max(float v) {
-    v = fmaxf(v, dpp_f<0xB1, 0xf>(v));
-    v = fmaxf(v, dpp_f<0x4E, 0xf>(v));
-    v = fmaxf(v, dpp_f<0x141, 0xf>(v));
-    v = fmaxf(v, dpp_f<0x140, 0xf>(v));
-    v = fmaxf(v, dpp_f<0x142, 0xa>(v));
-    v = fmaxf(v, dpp_f<0x143, 0xc>(v));
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    const int32_t x = order_int(v != v ? -INFINITY : v);
+    return order_float(wave_reduce(x, INT32_MIN, [](int32_t a, int32_t b) { return a > b ? a : b; }));
 }
 __device__ __forceinline__ float lane_f(float v, int j) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
@@ -311,8 +322,7 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
 }
 
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    v = (uint32_t)wave_reduce((int32_t)v, 0, [](int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); });
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh[wave] = v;
     __syncthreads();
@@ -483,32 +493,83 @@ __device__ __forceinline__ void set_pair_id(const PairOut& out, int64_t p, int32
         out.pair_ids[p] = k;
 }
 
-// Pass 3 with masks (at most 64 objects): ascending set bits.
+// Records of up to kPairStage pairs of a tile are staged in LDS and stored as
+// one contiguous run (each lane's own pairs are scattered across the tile's
+// output, 32 bytes apart per pair of a ray).
+constexpr int kPairStage = 512;
+
+// Pass 3 with masks (at most 64 objects): ascending set bits.  The next
+// tile's masks are loaded one tile ahead, and a tile's rays before its scan,
+// so that a block's serial chain of tiles waits on memory as little as
+// possible; the object boxes for the keys are read from LDS.
 __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
     const uint64_t* __restrict__ offs, int64_t max_pairs, PairOut out) {
     __shared__ uint32_t sh[4];
+    __shared__ float4 srec[2 * kPairStage];
+    __shared__ uint32_t sray[kPairStage];
+    __shared__ ObjDev sobj[64];
+    if (out.key)
+        for (int i = threadIdx.x; i < out.K; i += kPairTile) sobj[i] = out.objs[i];
+    __syncthreads();
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    const int64_t t_end = tile_begin(tiles, 1);
     int64_t run = (int64_t)offs[blockIdx.x];
-    for (int64_t tile = tile_begin(tiles); tile < tile_begin(tiles, 1); ++tile) {
+    int64_t tile = tile_begin(tiles);
+    uint64_t mk_next = 0;
+    if (tile < t_end && tile * kPairTile + threadIdx.x < n) mk_next = masks[tile * kPairTile + threadIdx.x];
+    for (; tile < t_end; ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
-        uint64_t mk = r < n ? masks[r] : 0ull;
+        uint64_t mk = mk_next;
+        if (tile + 1 < t_end && r + kPairTile < n) mk_next = masks[r + kPairTile];
         const uint32_t c = (uint32_t)__popcll(mk);
-        uint32_t tile_total;
-        int64_t p = run + block_excl_scan(c, sh, tile_total);
-        run += tile_total;
-        if (c == 0 || p >= max_pairs) continue;
-        float o[3], d[3];
+        float o[3] = {0, 0, 0}, d[3] = {0, 0, 0}, tm = 0.0f;
+        if (c != 0) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            o[a] = rays[r * 6 + a];
-            d[a] = rays[r * 6 + 3 + a];
+            for (int a = 0; a < 3; ++a) {
+                o[a] = rays[r * 6 + a];
+                d[a] = rays[r * 6 + 3 + a];
+            }
+            tm = tmax[r];
         }
-        const float tm = tmax[r];
-        while (mk && p < max_pairs) {
-            const int k = __builtin_ctzll(mk);
-            mk &= mk - 1;
-            write_pair(p++, o, d, tm, k, (uint32_t)r, out);
+        uint32_t tile_total;
+        const uint32_t lp = block_excl_scan(c, sh, tile_total);
+        const int64_t base = run;
+        run += tile_total;
+        // block-uniform: stage the tile's records when they fit and none is cut off
+        const bool stage = out.rec && tile_total <= (uint32_t)kPairStage && base + tile_total <= max_pairs;
+        int64_t p = base + lp;
+        if (c != 0 && p < max_pairs) {
+            if (stage) {
+                for (uint32_t q = lp; mk; ++q) {
+                    const int k = __builtin_ctzll(mk);
+                    mk &= mk - 1;
+                    srec[2 * q] = make_float4(o[0], o[1], o[2], d[0]);
+                    srec[2 * q + 1] = make_float4(d[1], d[2], tm, __int_as_float(k));
+                    sray[q] = (uint32_t)r;
+                }
+            } else {
+                PairOut o2 = out;
+                o2.objs = sobj;
+                while (mk && p < max_pairs) {
+                    const int k = __builtin_ctzll(mk);
+                    mk &= mk - 1;
+                    write_pair(p++, o, d, tm, k, (uint32_t)r, o2);
+                }
+            }
+        }
+        if (stage) {  // stores of the tile's run; the keys with one lane per pair, not per ray
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < 2 * tile_total; i += kPairTile) out.rec[2 * base + i] = srec[i];
+            for (uint32_t i = threadIdx.x; i < tile_total; i += kPairTile) {
+                out.pair_ray[base + i] = sray[i];
+                if (out.key) {
+                    const float4 a = srec[2 * i], b = srec[2 * i + 1];
+                    const float qo[3] = {a.x, a.y, a.z}, qd[3] = {a.w, b.x, b.y};
+                    out.key[base + i] = fine_order_key(qo, qd, b.z, __float_as_int(b.w), sobj, out.K, out.fine_bits);
+                }
+            }
+            __syncthreads();
         }
     }
 }
