@@ -70,24 +70,23 @@ __device__ __forceinline__ RayPre ray_pre(const float o[3], const float d[3], fl
 // the binary32 quotient), before widening or narrowing.  Returns false when
 // the ray is parallel to an axis and outside the box on it (exactly the
 // division test's rule).
+// Branch-free: every axis is computed and the parallel ones are selected
+// away (their products may be NaN and are never used).
 __device__ __forceinline__ bool slab_fast(const RayPre& r, const float lo[3], const float hi[3], float l[3],
                                           float h[3], bool con[3]) {
 #pragma clang fp contract(off)
+    bool inside = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         con[a] = r.d[a] != 0.0f;
-        l[a] = -INFINITY;
-        h[a] = INFINITY;
-        if (!con[a]) {
-            if (r.o[a] < lo[a] || r.o[a] > hi[a]) return false;
-            continue;
-        }
         const float t0 = (lo[a] - r.o[a]) * r.inv[a];
         const float t1 = (hi[a] - r.o[a]) * r.inv[a];
-        l[a] = fminf(t0, t1);
-        h[a] = fmaxf(t0, t1);
+        const bool lt = t0 < t1;
+        l[a] = con[a] ? (lt ? t0 : t1) : -INFINITY;
+        h[a] = con[a] ? (lt ? t1 : t0) : INFINITY;
+        inside = inside && (con[a] || !(r.o[a] < lo[a] || r.o[a] > hi[a]));
     }
-    return true;
+    return inside;
 }
 
 // Widened interval [ta, tb]: contains the division test's interval (the
@@ -97,10 +96,10 @@ __device__ __forceinline__ bool slab_fast(const RayPre& r, const float lo[3], co
 __device__ __forceinline__ void widened(const RayPre& r, const float l[3], const float h[3], const bool con[3],
                                         float& ta, float& tb) {
 #pragma clang fp contract(off)
+    (void)con;  // a parallel axis has l = -inf, h = +inf, which widen to themselves
     float tn = -INFINITY, tf = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (!con[a]) continue;
         tn = fmaxf(tn, l[a] - kUlp8 * fabsf(l[a]));
         tf = fminf(tf, h[a] + kUlp8 * fabsf(h[a]));
     }
@@ -112,31 +111,34 @@ __device__ __forceinline__ void widened(const RayPre& r, const float l[3], const
 // empty widened interval -> miss; non-empty narrowed interval (ends moved
 // inwards by 2^-21, so contained in the division test's) -> hit; otherwise
 // (a graze within 8 ulp, a non-finite or tiny slab end, a tiny direction
-// component) the division test itself.
+// component) the division test itself.  The reciprocal form runs in every
+// lane without branches; lanes without r.fast take the division test.
 __device__ __forceinline__ bool decide_hit(const RayPre& r, const float lo[3], const float hi[3]) {
 #pragma clang fp contract(off)
-    if (r.fast) {
-        float l[3], h[3];
-        bool con[3];
-        if (!slab_fast(r, lo, hi, l, h, con)) return false;
-        float ta, tb;
-        widened(r, l, h, con, ta, tb);
-        if (!(ta <= tb)) return false;
-        float tn = -INFINITY, tf = INFINITY;
-        bool sure = true;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (!con[a]) continue;
-            const float al = fabsf(l[a]), ah = fabsf(h[a]);
-            sure = sure && al <= 0x1p100f && ah <= 0x1p100f && (al == 0.0f || al >= 0x1p-100f) &&
-                   (ah == 0.0f || ah >= 0x1p-100f);
-            tn = fmaxf(tn, l[a] + kUlp8 * al);
-            tf = fminf(tf, h[a] - kUlp8 * ah);
-        }
-        if (sure && fmaxf(tn, 0.0f) <= fminf(tf, r.tm)) return true;
-    }
+    float l[3], h[3];
+    bool con[3];
+    const bool inside = slab_fast(r, lo, hi, l, h, con);
     float ta, tb;
-    return clip_segment(r.o, r.d, r.tm, lo, hi, ta, tb);
+    widened(r, l, h, con, ta, tb);
+    const bool miss = !inside | !(ta <= tb);
+    float tn = -INFINITY, tf = INFINITY;
+    bool sure = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float al = fabsf(l[a]), ah = fabsf(h[a]);
+        const bool ok = (al <= 0x1p100f) & (ah <= 0x1p100f) & ((al == 0.0f) | (al >= 0x1p-100f)) &
+                        ((ah == 0.0f) | (ah >= 0x1p-100f));
+        sure = sure & (!con[a] | ok);
+        tn = con[a] ? fmaxf(tn, l[a] + kUlp8 * al) : tn;
+        tf = con[a] ? fminf(tf, h[a] - kUlp8 * ah) : tf;
+    }
+    const bool hit = sure & (fmaxf(tn, 0.0f) <= fminf(tf, r.tm));
+    bool res = !miss;
+    if (!(r.fast & (miss | hit))) {
+        float ta2, tb2;
+        res = clip_segment(r.o, r.d, r.tm, lo, hi, ta2, tb2);
+    }
+    return res;
 }
 
 // Wave-wide reductions by DPP steps (quad permutes, row mirrors, row
@@ -203,33 +205,16 @@ __device__ __forceinline__ LaneRay lane_ray(const float* __restrict__ rays, cons
         tm = tmax[r];
     }
     L.pre = ray_pre(o, d, tm);
-    L.active = r < n && !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        L.blo[a] = INFINITY;
-        L.bhi[a] = -INFINITY;
-    }
-    if (!L.active) return L;
-    if (!L.pre.fast) {  // no cull for this lane: the whole root box
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            L.blo[a] = T.root[a];
-            L.bhi[a] = T.root[3 + a];
-        }
-        return L;
-    }
+    const bool valid = (r < n) & !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
+    // The root box clip, without branches.  A lane with a tiny direction
+    // component is not culled (its bundle box is the whole root box); a
+    // lane whose ray misses the root box meets no object box.
     float l[3], h[3];
     bool con[3];
+    const bool inside = slab_fast(L.pre, T.root, T.root + 3, l, h, con);
     float t0, t1;
-    if (!slab_fast(L.pre, T.root, T.root + 3, l, h, con)) {
-        L.active = false;
-        return L;
-    }
     widened(L.pre, l, h, con, t0, t1);
-    if (!(t0 <= t1)) {  // misses the root box: meets no object box
-        L.active = false;
-        return L;
-    }
+    L.active = valid & (!L.pre.fast | (inside & (t0 <= t1)));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float p0 = o[a] + t0 * d[a], p1 = o[a] + t1 * d[a];
@@ -238,8 +223,9 @@ __device__ __forceinline__ LaneRay lane_ray(const float* __restrict__ rays, cons
         m = m + fabsf(T.root[a]);
         m = m + fabsf(T.root[3 + a]);
         m = m * 0x1p-18f + 0x1p-100f;
-        L.blo[a] = fminf(p0, p1) - m;
-        L.bhi[a] = fmaxf(p0, p1) + m;
+        const float lo_c = fminf(p0, p1) - m, hi_c = fmaxf(p0, p1) + m;
+        L.blo[a] = !L.active ? INFINITY : (L.pre.fast ? lo_c : T.root[a]);
+        L.bhi[a] = !L.active ? -INFINITY : (L.pre.fast ? hi_c : T.root[3 + a]);
     }
     return L;
 }
@@ -270,8 +256,9 @@ __device__ __forceinline__ LaneBox level1_box(const PairTree& T, int lane) {
 }
 
 // Calls on_hit(object, lo, hi) in every lane whose ray the division test says meets
-// that object's box; wave-uniform control flow.
-template <typename F>
+// that object's box; wave-uniform control flow.  ONE: the tree has one level
+// (at most 64 objects, T.C == 1).
+template <bool ONE, typename F>
 __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1, const PairTree& T, int lane,
                                              F&& on_hit) {
     float ulo[3], uhi[3];
@@ -285,7 +272,7 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
     while (cand) {
         const int j = __builtin_ctzll(cand);
         cand &= cand - 1;
-        if (T.C == 1) {
+        if constexpr (ONE) {
             float lo[3], hi[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -366,6 +353,8 @@ __device__ __forceinline__ int64_t tile_begin(int64_t tiles, int next = 0) {
 // Pass 1.  masks (K <= 64): bit k set iff the ray's pair with object k is
 // emitted in this round; else counts (and, for rounds 1 and 2, the first
 // object per ray in first_obj).
+// ONE: one-level tree (T.C == 1); ROUNDS: round != 0.
+template <bool ONE, bool ROUNDS>
 __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __restrict__ rays,
                                                                 const float* __restrict__ tmax, int64_t n, PairTree T,
                                                                 int32_t round, const uint8_t* __restrict__ ray_visible,
@@ -385,10 +374,10 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
         uint32_t c = 0;
         float best_ta = INFINITY;
         int32_t best_k = 0x7fffffff;
-        for_each_hit(R, B1, T, lane, [&](int32_t k, const float lo[3], const float hi[3]) {
+        for_each_hit<ONE>(R, B1, T, lane, [&](int32_t k, const float lo[3], const float hi[3]) {
             ++c;
             mk |= 1ull << (k & 63);
-            if (round) {  // the box entered first
+            if constexpr (ROUNDS) {  // the box entered first
                 float ta, tb;
                 (void)clip_segment(R.pre.o, R.pre.d, R.pre.tm, lo, hi, ta, tb);
                 if (ta < best_ta || (ta == best_ta && k < best_k)) {
@@ -397,10 +386,10 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
                 }
             }
         });
-        if (round == 1 && c) {
+        if (ROUNDS && round == 1 && c) {
             c = 1;
             mk = 1ull << (best_k & 63);
-        } else if (round == 2 && c) {
+        } else if (ROUNDS && round == 2 && c) {
             if (r < n && ray_visible[r]) {
                 c -= 1;
                 mk &= ~(1ull << (best_k & 63));
@@ -595,7 +584,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
         const LaneRay R = lane_ray(rays, tmax, r, n, T);
         const int32_t first = round && r < n ? first_obj[r] : -1;
         int64_t p = p0;
-        for_each_hit(R, B1, T, lane, [&](int32_t k, const float*, const float*) {
+        for_each_hit<false>(R, B1, T, lane, [&](int32_t k, const float*, const float*) {
             // round 1: the first object only; round 2: the others (a ray with c = 0 writes none)
             if ((round == 1 && k != first) || (round == 2 && k == first) || p >= p0 + (int64_t)c) return;
             if (p < max_pairs) write_pair(p, R.pre.o, R.pre.d, R.pre.tm, k, (uint32_t)r, out);
@@ -718,8 +707,10 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
     int32_t* first = use_mask ? nullptr : reinterpret_cast<int32_t*>(p);
     const int64_t cap = (int64_t)num_cus * 8;  // persistent blocks
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
-    hipLaunchKernelGGL(pairs_count_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, ray_visible,
-                       masks, counts, round ? first : nullptr, sums);
+    auto count = T.C == 1 ? (round ? pairs_count_kernel<true, true> : pairs_count_kernel<true, false>)
+                          : (round ? pairs_count_kernel<false, true> : pairs_count_kernel<false, false>);
+    hipLaunchKernelGGL(count, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, ray_visible, masks, counts,
+                       round ? first : nullptr, sums);
     hipLaunchKernelGGL(pairs_block_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, (int64_t)blocks, offs,
                        total);
     const PairOut out{pair_rays, pair_tmax, pair_ids, pair_ray, rec, keys, objs, K, order_fine_bits(K)};
