@@ -191,19 +191,31 @@ struct LaneRay {
     float blo[3], bhi[3];  // conservative box of the root-clipped segment (empty: +inf / -inf)
 };
 
-__device__ __forceinline__ LaneRay lane_ray(const float* __restrict__ rays, const float* __restrict__ tmax, int64_t r,
-                                            int64_t n, const PairTree& T) {
-#pragma clang fp contract(off)
-    LaneRay L;
-    float o[3] = {0, 0, 0}, d[3] = {1, 0, 0}, tm = -1.0f;
+// A lane's ray as read from memory (r >= n: a placeholder that is invalid).
+struct RayIn {
+    float o[3], d[3], tm;
+};
+
+__device__ __forceinline__ RayIn load_ray(const float* __restrict__ rays, const float* __restrict__ tmax, int64_t r,
+                                          int64_t n) {
+    RayIn q{{0, 0, 0}, {1, 0, 0}, -1.0f};
     if (r < n) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            o[a] = rays[r * 6 + a];
-            d[a] = rays[r * 6 + 3 + a];
+            q.o[a] = rays[r * 6 + a];
+            q.d[a] = rays[r * 6 + 3 + a];
         }
-        tm = tmax[r];
+        q.tm = tmax[r];
     }
+    return q;
+}
+
+__device__ __forceinline__ LaneRay lane_ray(const RayIn& q, int64_t r, int64_t n, const PairTree& T) {
+#pragma clang fp contract(off)
+    LaneRay L;
+    const float* o = q.o;
+    const float* d = q.d;
+    const float tm = q.tm;
     L.pre = ray_pre(o, d, tm);
     const bool valid = (r < n) & !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
     // The root box clip, without branches.  A lane with a tiny direction
@@ -366,10 +378,14 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
     const int lane = threadIdx.x & 63;
     const LaneBox B1 = level1_box(T, lane);
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    const int64_t t_end = tile_begin(tiles, 1);
     uint32_t block_total = 0;
-    for (int64_t tile = tile_begin(tiles); tile < tile_begin(tiles, 1); ++tile) {
+    RayIn q_next = load_ray(rays, tmax, tile_begin(tiles) * kPairTile + threadIdx.x, n);
+    for (int64_t tile = tile_begin(tiles); tile < t_end; ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
-        const LaneRay R = lane_ray(rays, tmax, r, n, T);
+        const RayIn q = q_next;  // this tile's ray; the next tile's is read before the work on this one
+        if (tile + 1 < t_end) q_next = load_ray(rays, tmax, r + kPairTile, n);
+        const LaneRay R = lane_ray(q, r, n, T);
         uint64_t mk = 0;
         uint32_t c = 0;
         float best_ta = INFINITY;
@@ -487,10 +503,10 @@ __device__ __forceinline__ void set_pair_id(const PairOut& out, int64_t p, int32
 // output, 32 bytes apart per pair of a ray).
 constexpr int kPairStage = 512;
 
-// Pass 3 with masks (at most 64 objects): ascending set bits.  The next
-// tile's masks are loaded one tile ahead, and a tile's rays before its scan,
-// so that a block's serial chain of tiles waits on memory as little as
-// possible; the object boxes for the keys are read from LDS.
+// Pass 3 with masks (at most 64 objects): ascending set bits.  Masks are
+// read two tiles ahead and rays (of rays with pairs) one tile ahead, so that
+// a block's serial chain of tiles waits on memory as little as possible; the
+// object boxes for the keys are read from LDS.
 __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
     const uint64_t* __restrict__ offs, int64_t max_pairs, PairOut out) {
@@ -505,22 +521,28 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     const int64_t t_end = tile_begin(tiles, 1);
     int64_t run = (int64_t)offs[blockIdx.x];
     int64_t tile = tile_begin(tiles);
-    uint64_t mk_next = 0;
-    if (tile < t_end && tile * kPairTile + threadIdx.x < n) mk_next = masks[tile * kPairTile + threadIdx.x];
+    auto mask_at = [&](int64_t t) -> uint64_t {
+        const int64_t r = t * kPairTile + threadIdx.x;
+        return t < t_end && r < n ? masks[r] : 0ull;
+    };
+    auto ray_at = [&](int64_t t, uint64_t m) -> RayIn {  // read only for rays with pairs
+        return load_ray(rays, tmax, m ? t * kPairTile + threadIdx.x : n, n);
+    };
+    // pipeline: masks two tiles ahead, rays one tile ahead
+    uint64_t mk_next = mask_at(tile);
+    RayIn q_next = ray_at(tile, mk_next);
+    uint64_t mk_next2 = mask_at(tile + 1);
     for (; tile < t_end; ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
         uint64_t mk = mk_next;
-        if (tile + 1 < t_end && r + kPairTile < n) mk_next = masks[r + kPairTile];
+        const RayIn q = q_next;
+        mk_next = mk_next2;
+        q_next = ray_at(tile + 1, mk_next);
+        mk_next2 = mask_at(tile + 2);
         const uint32_t c = (uint32_t)__popcll(mk);
-        float o[3] = {0, 0, 0}, d[3] = {0, 0, 0}, tm = 0.0f;
-        if (c != 0) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                o[a] = rays[r * 6 + a];
-                d[a] = rays[r * 6 + 3 + a];
-            }
-            tm = tmax[r];
-        }
+        const float* o = q.o;
+        const float* d = q.d;
+        const float tm = q.tm;
         uint32_t tile_total;
         const uint32_t lp = block_excl_scan(c, sh, tile_total);
         const int64_t base = run;
@@ -530,12 +552,12 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
         int64_t p = base + lp;
         if (c != 0 && p < max_pairs) {
             if (stage) {
-                for (uint32_t q = lp; mk; ++q) {
+                for (uint32_t j = lp; mk; ++j) {
                     const int k = __builtin_ctzll(mk);
                     mk &= mk - 1;
-                    srec[2 * q] = make_float4(o[0], o[1], o[2], d[0]);
-                    srec[2 * q + 1] = make_float4(d[1], d[2], tm, __int_as_float(k));
-                    sray[q] = (uint32_t)r;
+                    srec[2 * j] = make_float4(o[0], o[1], o[2], d[0]);
+                    srec[2 * j + 1] = make_float4(d[1], d[2], tm, __int_as_float(k));
+                    sray[j] = (uint32_t)r;
                 }
             } else {
                 PairOut o2 = out;
@@ -581,7 +603,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
         uint32_t tile_total;
         const int64_t p0 = run + block_excl_scan(c, sh, tile_total);
         run += tile_total;
-        const LaneRay R = lane_ray(rays, tmax, r, n, T);
+        const LaneRay R = lane_ray(load_ray(rays, tmax, r, n), r, n, T);
         const int32_t first = round && r < n ? first_obj[r] : -1;
         int64_t p = p0;
         for_each_hit<false>(R, B1, T, lane, [&](int32_t k, const float*, const float*) {
