@@ -533,6 +533,35 @@ def scene_oracle_errors(ctx, w, sh, pairs, gpu_y, scales, budget_s: float = 12.0
     return cpu, errs
 
 
+def to_query_images(ctx, log):
+    """Replace every object's grid by its y-pair query image (each cell face's
+    four latent pairs in one 16-byte span: half the gathers of a lookup, twice
+    the grid's bytes), one object at a time, so that each grid is released
+    before the next image is allocated: 64 images fit where the grids and the
+    images together would not.  Returns a description, or None (grids kept)
+    when the images would not fit."""
+    import torch
+    from paper_2306_07191_amd import nif
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 1)
+    nb = int(nif.lib().nif_image_bytes(ctx.h))
+    gb = ctx.grid_elems * 2
+    free, _ = torch.cuda.mem_get_info()
+    if free + ctx.K * (gb - nb) < 6e9:  # what would be left at the end, with room for the step's buffers
+        ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+        log(f"query images ({ctx.K} x {nb / 1e9:.2f} GB) would not fit: the grids stay")
+        return None
+    t0 = time.perf_counter()
+    for k in range(ctx.K):
+        ctx.build_image(k)
+        torch.cuda.synchronize()  # the build has read the grid
+        ctx.drop_grid(k)
+        torch.cuda.empty_cache()
+    free_end, _ = torch.cuda.mem_get_info()
+    log(f"grids replaced by y-pair query images in {time.perf_counter() - t0:.1f}s: {ctx.K} x {nb / 1e9:.2f} GB; "
+        f"{free_end / 1e9:.1f} GB free")
+    return f"y-pair query images (binary16, 16-byte cell faces, {ctx.K} x {nb / 1e9:.2f} GB), grids released"
+
+
 def run_scene(args):
     """Large scene (the headline): 64 displaced spheres (30M triangles,
     log-uniform sizes) on a 48 x 27 ground plane, 1920 x 1080 ground points x 4
@@ -670,9 +699,42 @@ def run_scene(args):
     ows = torch.empty(max(1, int(L.nif_order_workspace_bytes(ctx.h, P))), dtype=torch.uint8, device="cuda")
     vis = torch.empty(n, dtype=torch.uint8, device="cuda")
     flops = 2 * (sh.din * sh.width + (sh.hidden - 1) * sh.width * sh.width + sh.width)  # 30,848 per query
-    res, gpu_y = {}, {}
+    res = {}
     mask_ref = lab.reshape(-1, S.SCENE_SPP).mean(axis=1)
     stream = torch.cuda.current_stream()
+    dts = (SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")
+
+    def one_step(path, dt):
+        expand_and_order(path)
+        ctx.query_packed(recs[:P], perm, dtype=dt, out=yq)
+        ctx.combine_pairs(pray[:P], yq, n, out=vis)
+
+    # reference pass on the grids: every dtype's outputs (the oracle comparison
+    # runs on them, and the timed runs on the query images must reproduce them
+    # bit for bit) and the step on the grids, for comparison
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, 0)
+    ctx.set_option(nif.NIF_OPT_TILE_SHAPE, 1)
+    grid_y = {}
+    for dt in dts:
+        ctx.prepare(dt)
+        one_step("keys", dt)
+        grid_y[dt] = yq.cpu().numpy().copy()
+    ctx.prepare(SCENE_DTYPE)
+    grid_step_ms = time_launches(lambda: one_step("keys", SCENE_DTYPE), 20, 3) * 1e3
+    log(f"step on the grids ({SCENE_DTYPE}, keys path, tile shape 1): {grid_step_ms:.3f} ms")
+    cpu, errs = None, None
+    if not (args.no_cpu or args.quick):
+        expand()  # the pairs as arrays, in the order of grid_y
+        pairs = (pr[:P].cpu().numpy(), pi[:P].cpu().numpy(), pt[:P].cpu().numpy())
+        t0 = time.perf_counter()
+        cpu, errs = scene_oracle_errors(ctx, w, sh, pairs, grid_y, scales)
+        log(f"oracle on trained models ({time.perf_counter() - t0:.1f}s): {cpu['value']:.0f} queries/s on "
+            f"{cpu['cores']} cores; errors {json.dumps(errs)}")
+    # inference from query images in place of the grids (training is over)
+    ctx.train_bufs = []
+    ctx.mlp_moments = []
+    torch.cuda.empty_cache()
+    layout = to_query_images(ctx, log) if not args.scene_grids else None
     # schedule: the pair path, ordering with or without the window sort (the
     # finer Morton key), and the fused kernel's tile shape, whichever makes the
     # headline step fastest on these pairs
@@ -684,18 +746,13 @@ def run_scene(args):
                 ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
                 ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
 
-                def one():
-                    expand_and_order(path)
-                    ctx.query_packed(recs[:P], perm, dtype=SCENE_DTYPE, out=yq)
-                    ctx.combine_pairs(pray[:P], yq, n, out=vis)
-
-                sched[(path, wsort, shape)] = time_launches(one, 10, 3) * 1e3
+                sched[(path, wsort, shape)] = time_launches(lambda: one_step(path, SCENE_DTYPE), 10, 3) * 1e3
     pair_path, window_sort, tile_shape = min(sched, key=sched.get)
     ctx.set_option(nif.NIF_OPT_WINDOW_SORT, window_sort)
     ctx.set_option(nif.NIF_OPT_TILE_SHAPE, tile_shape)
     log("step ms by (pair path, window sort, tile shape): " + ", ".join(f"{k}: {v:.3f}" for k, v in sched.items()) +
         f"; chosen {(pair_path, window_sort, tile_shape)}")
-    for dt in ((SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")):
+    for dt in dts:
         ctx.prepare(dt)
         steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
 
@@ -728,19 +785,20 @@ def run_scene(args):
         t_q = part(lambda k: evs[k][1], lambda k: evs[k][2])
         t_comb = part(lambda k: evs[k][2], lambda k: marks[k + 1])
         v = vis.cpu().numpy()
-        gpu_y[dt] = yq.cpu().numpy().copy()
+        same = bool(np.array_equal(yq.cpu().numpy().view(np.uint32), grid_y[dt].view(np.uint32)))
         mis = float((v != lab).mean())
         mse = float(((v.reshape(-1, S.SCENE_SPP).mean(axis=1) - mask_ref) ** 2).mean())
         psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
         res[dt] = {"ms": sec * 1e3, "rays_per_s": n / sec, "pairs_per_s": P / sec, "pair_path": pair_path,
-                   "misclassification": mis,
+                   "outputs_identical_to_grid_path": same, "misclassification": mis,
                    "psnr_db": psnr, "stage_ms": {"pair_expansion": t_exp * 1e3, "ordering": t_ord * 1e3,
                                                  "query_kernel": t_q * 1e3, "combination": t_comb * 1e3},
                    "query_kernel_tflops": flops * P / t_q / 1e12, "wall_s": wall}
         log(f"{dt}: step {sec * 1e3:.3f} ms = {n / sec / 1e9:.3f} G rays/s ({P / sec / 1e9:.3f} G pairs/s): expansion "
             f"{t_exp * 1e3:.3f}, ordering {t_ord * 1e3:.3f}, query kernel {t_q * 1e3:.3f} "
             f"({flops * P / t_q / 1e12:.0f} TFLOP/s), combination {t_comb * 1e3:.3f} ms; misclassification "
-            f"{100 * mis:.3f} %, mask PSNR {psnr:.2f} dB")
+            f"{100 * mis:.3f} %, mask PSNR {psnr:.2f} dB; outputs identical to the grid path: {same}")
+        assert same, f"{dt}: the query images must reproduce the grid path's outputs bit for bit"
     if "f32" in res:
         for dt in res:
             res[dt]["added_misclassification_vs_f32"] = res[dt]["misclassification"] - res["f32"]["misclassification"]
@@ -788,14 +846,6 @@ def run_scene(args):
         log(f"early-out ({SCENE_DTYPE}): {P1} + {P2} pairs in two rounds against {P} in one, step {eo_sec * 1e3:.3f} ms "
             f"against {res[SCENE_DTYPE]['ms']:.3f} ms; same ray visibility: {early_out['same_ray_visibility']}")
 
-    cpu, errs = None, None
-    if not (args.no_cpu or args.quick):
-        expand()  # the one-round pairs again (the early-out rounds wrote over them), the order of gpu_y
-        pairs = (pr[:P].cpu().numpy(), pi[:P].cpu().numpy(), pt[:P].cpu().numpy())
-        t0 = time.perf_counter()
-        cpu, errs = scene_oracle_errors(ctx, w, sh, pairs, gpu_y, scales)
-        log(f"oracle on trained models ({time.perf_counter() - t0:.1f}s): {cpu['value']:.0f} queries/s on "
-            f"{cpu['cores']} cores; errors {json.dumps(errs)}")
     head = res[SCENE_DTYPE]
     tq = head["stage_ms"]["query_kernel"] / 1e3
     # algorithmic work of one launch: FLOP of the MLPs, and compulsory bytes =
@@ -813,8 +863,11 @@ def run_scene(args):
         achieved = flops * P / tq / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE]}
-    roof.update({"traffic": measured_traffic("scene", tile_shape), "tile_shape": tile_shape,
-                 "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, no image, tile shape {tile_shape}> (fused clip+encode+MLP)",
+    img = "y-pair image" if layout else "no image"
+    roof.update({"traffic": measured_traffic("scene_image" if layout else "scene", tile_shape),
+                 "tile_shape": tile_shape,
+                 "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, {img}, tile shape {tile_shape}> "
+                           "(fused clip+encode+MLP)",
                  "kernel_us": tq * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
                  "distinct_latent_vertices": fp[0], "distinct_64b_lines": fp[2],
                  "algorithmic_flop_per_launch": flops * P,
@@ -838,6 +891,7 @@ def run_scene(args):
                                "per object",
                    "rays": n, "pairs": P, "objects": K, "triangles": int(w["tri_counts"].sum()),
                    "step": "pair expansion + pair ordering + fused query kernel + per-ray combination",
+                   "latents": layout or "grids (binary16, vertex-major)", "step_ms_on_grids": grid_step_ms,
                    "pair_path": pair_path, "window_sort": bool(window_sort), "tile_shape": tile_shape,
                    "step_ms_by_path_window_sort_and_shape": {"/".join(map(str, k)): v for k, v in sched.items()},
                    "value_is": "(ray, object) queries per second; rays_per_s is in per_dtype"},
@@ -1105,6 +1159,8 @@ def main():
                     help="scene: skip the per-object training (initial models; for counter runs of the query step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--scene-grids", action="store_true",
+                    help="scene: time the queries on the grids instead of query images built from them")
     ap.add_argument("--early-out", action="store_true",
                     help="scene: also time the two-round early-out form (Sec. 7)")
     ap.add_argument("--quick", action="store_true",

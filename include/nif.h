@@ -89,7 +89,14 @@ nif_status nif_param_layout(const nif_ctx* ctx, int64_t* grid_elems, int64_t* ta
 
 /* Register object `obj`: its AABB (host, lo xyz then hi xyz; hi > lo on every
  * axis), its grid buffer (dev, grid_elems latents of grid_dtype) and the MLP
- * it uses.  Takes effect at the next nif_prepare. */
+ * it uses.  Takes effect at the next nif_prepare.  grid may be NULL once the
+ * object's query image is built (NIF_OPT_GRID_IMAGE 1 or 2, nif_build_image or
+ * nif_prepare), else NIF_ERR_STATE: the object is then answered from its
+ * image alone and its grid buffer may be freed, so that the images of many
+ * objects fit where their grids and images together would not.  Such an
+ * object keeps its image until a new grid, a new image buffer or another
+ * image mode is set; training calls and nif_init_grid refuse a context with
+ * such an object (NIF_ERR_STATE). */
 nif_status nif_set_object(nif_ctx* ctx, int32_t obj, const float* aabb, void* grid, int32_t mlp_index);
 
 /* Register MLP `mlp`: binary32 master weights (dev, mlp_params floats).  The
@@ -240,6 +247,12 @@ nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
  * context (or a plan of it) may launch a query. */
 size_t nif_image_bytes(const nif_ctx* ctx);
 nif_status nif_set_image(nif_ctx* ctx, int32_t obj, void* image, size_t bytes);
+
+/* Build object obj's query image from its grid now, on `stream` (nif_prepare
+ * builds every object's; this one alone, so that a grid can be released
+ * before the next image is allocated).  NIF_ERR_STATE when the image mode is
+ * 0 or the object has no image buffer or no grid. */
+nif_status nif_build_image(nif_ctx* ctx, int32_t obj, void* stream);
 
 /* Workspace bytes needed by nif_query (mode 0: with ordering, the ordering
  * workspace, the 32-byte query records and the fused kernel's tile counters;

@@ -44,6 +44,7 @@ struct ObjHost {
     void* grid = nullptr;
     int32_t mlp = -1;
     bool set = false;
+    bool image_built = false;  // its registered query image holds its current grid (nif_build_image, nif_prepare)
     float* grad = nullptr;  // training buffers
     float* m = nullptr;
     float* v = nullptr;
@@ -182,6 +183,26 @@ static PairTreeHost build_pair_tree(const std::vector<ObjDev>& od) {
 static void drop_images(nif_ctx* c) {
     c->images.assign(c->K, nullptr);
     c->images_ready = false;
+    for (ObjHost& o : c->objs) o.image_built = false;
+}
+
+// Offsets of the 3 L tables inside one object's query image.
+static void image_offsets(nif_ctx* c) {
+    int64_t o = 0;
+    for (int k = 0; k < 3 * c->d.levels; ++k) {
+        c->ioff[k] = o;
+        o += image_table_elems(c->res[k % c->d.levels], c->image_mode);
+    }
+    c->ioff[3 * c->d.levels] = o;
+}
+
+// Objects answered from their query image alone (no grid) cannot be trained
+// or read through their grid.
+static nif_status require_grids(const nif_ctx* c, const char* where) {
+    for (int k = 0; k < c->K; ++k)
+        if (c->objs[k].set && !c->objs[k].grid)
+            return fail(NIF_ERR_STATE, "%s: object %d has no grid (it is answered from its query image)", where, k);
+    return NIF_OK;
 }
 
 // Elements of one object's query image for image kind `mode` (0: none).
@@ -298,8 +319,11 @@ static void invalidate(nif_ctx* c) {
 }
 
 extern "C" nif_status nif_set_object(nif_ctx* c, int32_t obj, const float* aabb, void* grid, int32_t mlp_index) {
-    if (!c || !aabb || !grid) return fail(NIF_ERR_INVALID_ARG, "nif_set_object: NULL argument");
+    if (!c || !aabb) return fail(NIF_ERR_INVALID_ARG, "nif_set_object: NULL argument");
     if (obj < 0 || obj >= c->K) return fail(NIF_ERR_INVALID_ARG, "object %d out of range [0, %d)", obj, c->K);
+    if (!grid && !(c->image_mode && c->images[obj] && c->objs[obj].image_built))
+        return fail(NIF_ERR_STATE, "nif_set_object: object %d has no built query image to answer from without a grid",
+                    obj);
     if (mlp_index < 0 || mlp_index >= c->M) return fail(NIF_ERR_INVALID_ARG, "mlp %d out of range", mlp_index);
     for (int a = 0; a < 3; ++a) {
         if (!isfinite(aabb[a]) || !isfinite(aabb[3 + a]) || !(aabb[3 + a] > aabb[a]))
@@ -307,6 +331,7 @@ extern "C" nif_status nif_set_object(nif_ctx* c, int32_t obj, const float* aabb,
     }
     ObjHost& o = c->objs[obj];
     memcpy(o.aabb, aabb, sizeof o.aabb);
+    if (grid) o.image_built = false;  // a grid given again: the image is rebuilt from it
     o.grid = grid;
     o.mlp = mlp_index;
     o.set = true;
@@ -338,6 +363,7 @@ extern "C" nif_status nif_init_grid(nif_ctx* c, int32_t obj, uint64_t seed, floa
     if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_init_grid: NULL context");
     if (obj < 0 || obj >= c->K || !c->objs[obj].set)
         return fail(NIF_ERR_INVALID_ARG, "object %d not registered", obj);
+    if (!c->objs[obj].grid) return fail(NIF_ERR_STATE, "nif_init_grid: object %d has no grid", obj);
     if (!isfinite(amp) || amp < 0.0f) return fail(NIF_ERR_INVALID_ARG, "amp must be finite and >= 0");
     HIP_TRY(launch_init_grid(c->objs[obj].grid, c->d.grid_dtype, c->grid_elems, seed, (uint64_t)obj, amp,
                              (hipStream_t)stream));
@@ -357,6 +383,9 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
         for (int k = 0; k < c->K; ++k)
             if (!c->images[k])
                 return fail(NIF_ERR_STATE, "object %d has no query image buffer (nif_image_bytes, nif_set_image)", k);
+    for (int k = 0; k < c->K; ++k)
+        if (!c->objs[k].grid && !(c->image_mode && c->objs[k].image_built))
+            return fail(NIF_ERR_STATE, "object %d has neither a grid nor a built query image", k);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     if (!c->d_flags) {
@@ -369,17 +398,16 @@ extern "C" nif_status nif_prepare(nif_ctx* c, int32_t dtype, void* stream) {
                                 0u, s));
     }
     // query images of the grids, in the caller's buffers (rebuilt on every
-    // call: the grids may have changed)
+    // call: the grids may have changed; an object without a grid keeps the
+    // image built from its last grid)
     if (c->image_mode) {
-        int64_t o = 0;
-        for (int k = 0; k < 3 * c->d.levels; ++k) {
-            c->ioff[k] = o;
-            o += image_table_elems(c->res[k % c->d.levels], c->image_mode);
-        }
-        c->ioff[3 * c->d.levels] = o;
-        for (int k = 0; k < c->K; ++k)
+        image_offsets(c);
+        for (int k = 0; k < c->K; ++k) {
+            if (!c->objs[k].grid) continue;
             HIP_TRY(launch_build_image(c->objs[k].grid, c->images[k], c->toff, c->ioff, c->res, c->d.levels,
                                        c->image_mode, s));
+            c->objs[k].image_built = true;
+        }
         c->images_ready = true;
     }
     // object table
@@ -499,9 +527,24 @@ extern "C" nif_status nif_set_image(nif_ctx* c, int32_t obj, void* image, size_t
     if (c->images[obj] != image) {
         c->images[obj] = image;
         c->images_ready = false;
+        c->objs[obj].image_built = false;
         for (bool& p : c->prepared) p = false;
         ++c->epoch;
     }
+    return ok();
+}
+
+extern "C" nif_status nif_build_image(nif_ctx* c, int32_t obj, void* stream) {
+    if (!c) return fail(NIF_ERR_INVALID_ARG, "nif_build_image: NULL context");
+    if (obj < 0 || obj >= c->K || !c->objs[obj].set)
+        return fail(NIF_ERR_INVALID_ARG, "nif_build_image: object %d not registered", obj);
+    if (c->image_mode == 0) return fail(NIF_ERR_STATE, "nif_build_image: NIF_OPT_GRID_IMAGE is 0");
+    if (!c->images[obj]) return fail(NIF_ERR_STATE, "nif_build_image: object %d has no image buffer", obj);
+    if (!c->objs[obj].grid) return fail(NIF_ERR_STATE, "nif_build_image: object %d has no grid", obj);
+    image_offsets(c);
+    HIP_TRY(launch_build_image(c->objs[obj].grid, c->images[obj], c->toff, c->ioff, c->res, c->d.levels,
+                               c->image_mode, (hipStream_t)stream));
+    c->objs[obj].image_built = true;
     return ok();
 }
 
@@ -985,6 +1028,7 @@ static nif_status train_common(nif_ctx* c, int32_t mlp, const float* rays, const
         return fail(NIF_ERR_INVALID_ARG, "invalid Adam hyper-parameters");
     if (n == 0) return ok();
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    if (require_grids(c, "training") != NIF_OK) return NIF_ERR_STATE;
     if (!c->masters[mlp]) return fail(NIF_ERR_STATE, "MLP %d not registered", mlp);
     if (adam && (!c->mlp_m[mlp] || !c->mlp_v[mlp])) return fail(NIF_ERR_STATE, "MLP %d has no Adam moments", mlp);
     std::vector<int32_t> objs;

@@ -23,6 +23,7 @@ NIF_OPT_TILE_SHAPE = 4
 NIF_FLAG_INVALID_RAY = 1
 NIF_FLAG_BAD_OBJECT = 2
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}
+NIF_OK, NIF_ERR_INVALID_ARG, NIF_ERR_UNSUPPORTED, NIF_ERR_WORKSPACE, NIF_ERR_HIP, NIF_ERR_STATE = 0, -1, -2, -3, -4, -5
 STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3: "NIF_ERR_WORKSPACE",
           -4: "NIF_ERR_HIP", -5: "NIF_ERR_STATE"}
 
@@ -30,7 +31,7 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
            "nif_expand_pairs", "nif_combine_pairs", "nif_expand_pairs_round", "nif_combine_pairs_and",
-           "nif_expand_pairs_packed", "nif_order_keys", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
+           "nif_expand_pairs_packed", "nif_order_keys", "nif_build_image", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
            "nif_encode16", "nif_mlp16",
            "nif_set_option", "nif_image_bytes", "nif_set_image", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
@@ -85,6 +86,7 @@ def lib():
             "nif_expand_pairs_round": (i32, [vp, vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
             "nif_expand_pairs_packed": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp]),
             "nif_order_keys": (i32, [vp, vp, i64, vp, vp, sz, vp]),
+            "nif_build_image": (i32, [vp, i32, vp]),
             "nif_combine_pairs_and": (i32, [vp, vp, vp, i64, i64, vp, vp]),
             "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
@@ -550,6 +552,21 @@ class Context:
 
     def init_grid(self, k: int, seed: int, amp: float = 1e-4):
         _check(lib().nif_init_grid(self.h, k, seed, amp, _stream()), "nif_init_grid")
+
+    def build_image(self, k: int):
+        """Allocate (if needed) and build object k's query image now."""
+        t = self.torch
+        if self.images[k] is None:
+            nb = int(lib().nif_image_bytes(self.h))
+            self.images[k] = t.empty(nb, dtype=t.uint8, device=self.device)
+            _check(lib().nif_set_image(self.h, k, _ptr(self.images[k]), nb), "nif_set_image")
+        _check(lib().nif_build_image(self.h, k, _stream()), "nif_build_image")
+
+    def drop_grid(self, k: int):
+        """Answer object k from its built query image alone; its grid tensor is released."""
+        _check(lib().nif_set_object(self.h, k, self.aabb[k].ctypes.data, None, int(self.mlp_index[k])),
+               "nif_set_object")
+        self.grids[k] = None
 
     def prepare(self, dtype: str):
         if self.image_mode:

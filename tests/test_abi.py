@@ -65,7 +65,7 @@ def test_validation_before_device_work():
         assert L.nif_set_object(h, 2, box.ctypes.data, fake, 0) == -1  # object out of range
         assert L.nif_set_object(h, 0, box.ctypes.data, fake, 1) == -1  # MLP out of range
         assert L.nif_set_object(h, 0, flat.ctypes.data, fake, 0) == -1  # degenerate box
-        assert L.nif_set_object(h, 0, box.ctypes.data, None, 0) == -1
+        assert L.nif_set_object(h, 0, box.ctypes.data, None, 0) == -5  # no grid and no built query image
         assert L.nif_set_object(h, 0, box.ctypes.data, fake, 0) == 0
         assert L.nif_query(h, 0, fake, fake, fake, -1, fake, None, None, 0, None) == -1  # n < 0
         assert L.nif_query(h, 0, fake, fake, fake, 0, fake, None, None, 0, None) == 0   # n = 0: no-op

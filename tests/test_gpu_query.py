@@ -561,3 +561,50 @@ def test_tile_shape_1_many_objects(dtype):
     ref = model.forward(w["rays"], w["ids"], w["tmax"])
     exact = model.with_(quant="exact").forward(w["rays"], w["ids"], w["tmax"])
     check_outputs(outs[1][0], outs[1][1], ref, dtype, f"shape 1 {dtype}", exact=exact)
+
+
+def test_image_only_objects():
+    """Objects answered from their query image alone: nif_build_image builds
+    one object's image, nif_set_object without a grid keeps it and the grid
+    buffer is released.  Queries (FP32 and BF16) give the grid path's outputs
+    bit for bit, and the oracle's within the FP32 tolerance; nif_init_grid and
+    training refuse the context; a grid given again brings the grid back."""
+    import torch
+    from paper_2306_07191_amd import nif
+    n, K = 20000, 3
+    w = S.frame_workload(n_rays=n, with_mesh=False)
+    w["aabb"] = np.repeat(w["aabb"], K, axis=0)
+    w["mlps"] = np.repeat(w["mlps"], K, axis=0)
+    w["mlp_index"] = np.arange(K, dtype=np.int32)
+    w["ids"] = np.random.default_rng(3).integers(0, K, n).astype(np.int32)
+    w["ids"][::7] = 1
+    ctx, model = make_pair(w, grid_amp=0.5)
+    y_grid = {dt: run_query(ctx, w, dt) for dt in ("f32", "bf16")}
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 1)
+    for k in range(K):
+        ctx.build_image(k)
+    torch.cuda.synchronize()
+    for k in (0, 2):  # object 1 keeps its grid (its image is rebuilt by nif_prepare)
+        ctx.drop_grid(k)
+    torch.cuda.empty_cache()
+    for dt in ("f32", "bf16"):
+        y, z = run_query(ctx, w, dt)
+        np.testing.assert_array_equal(y, y_grid[dt][0])
+        np.testing.assert_array_equal(z, y_grid[dt][1])
+    check_outputs(*run_query(ctx, w, "f32"), model.forward(w["rays"], w["ids"], w["tmax"]), "f32", "image only")
+    with pytest.raises(nif.NifError) as e:
+        ctx.init_grid(0, GRID_SEED, 0.5)
+    assert e.value.status == nif.NIF_ERR_STATE
+    rays, ids, tmax = (torch.from_numpy(w[k][:64]).cuda() for k in ("rays", "ids", "tmax"))
+    with pytest.raises(nif.NifError) as e:
+        ctx.train_step(rays, ids, tmax, torch.ones(64, dtype=torch.uint8, device="cuda"), step=1)
+    assert e.value.status == nif.NIF_ERR_STATE
+    # another image mode forgets the images: objects without a grid cannot be prepared
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    with pytest.raises(nif.NifError) as e:
+        ctx.prepare("f32")
+    assert e.value.status == nif.NIF_ERR_STATE
+    for k in (0, 2):  # grids given again (same initial latents): the grid path's outputs
+        ctx.set_object(k, w["aabb"][k], ctx.alloc_grid(), int(w["mlp_index"][k]))
+        ctx.init_grid(k, GRID_SEED, 0.5)
+    np.testing.assert_array_equal(run_query(ctx, w, "f32")[0], y_grid["f32"][0])
