@@ -52,6 +52,8 @@ struct RayPre {
     bool fast;  // no direction component with 0 < |d| < 2^-100
 };
 
+// Boolean chains use & and | (not && and ||) so that they stay selects and
+// do not become branches.
 __device__ __forceinline__ RayPre ray_pre(const float o[3], const float d[3], float tm) {
     RayPre r;
     r.fast = true;
@@ -60,10 +62,19 @@ __device__ __forceinline__ RayPre ray_pre(const float o[3], const float d[3], fl
         r.o[a] = o[a];
         r.d[a] = d[a];
         r.inv[a] = __builtin_amdgcn_rcpf(d[a]);
-        r.fast = r.fast && (d[a] == 0.0f || fabsf(d[a]) >= 0x1p-100f);
+        r.fast = r.fast & ((d[a] == 0.0f) | (fabsf(d[a]) >= 0x1p-100f));
     }
     r.tm = tm;
     return r;
+}
+
+// A ray that can have pairs: finite origin and direction, a non-zero
+// direction, t_max not NaN and not negative (the query's domain rule).
+__device__ __forceinline__ bool ray_valid(const float o[3], const float d[3], float tm) {
+    bool ok = (d[0] != 0.0f) | (d[1] != 0.0f) | (d[2] != 0.0f);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = ok & (fabsf(o[a]) <= 0x1.fffffep127f) & (fabsf(d[a]) <= 0x1.fffffep127f);
+    return ok & (tm >= 0.0f);
 }
 
 // Slab interval of a box with reciprocal multiplies (each end within 2^-22 of
@@ -84,7 +95,7 @@ __device__ __forceinline__ bool slab_fast(const RayPre& r, const float lo[3], co
         const bool lt = t0 < t1;
         l[a] = con[a] ? (lt ? t0 : t1) : -INFINITY;
         h[a] = con[a] ? (lt ? t1 : t0) : INFINITY;
-        inside = inside && (con[a] || !(r.o[a] < lo[a] || r.o[a] > hi[a]));
+        inside = inside & (con[a] | !((r.o[a] < lo[a]) | (r.o[a] > hi[a])));
     }
     return inside;
 }
@@ -217,7 +228,7 @@ __device__ __forceinline__ LaneRay lane_ray(const RayIn& q, int64_t r, int64_t n
     const float* d = q.d;
     const float tm = q.tm;
     L.pre = ray_pre(o, d, tm);
-    const bool valid = (r < n) & !(query_error_bits(o, d, tm, 0, 1) & 1u);  // invalid rays have no pairs
+    const bool valid = (r < n) & ray_valid(o, d, tm);  // invalid rays have no pairs
     // The root box clip, without branches.  A lane with a tiny direction
     // component is not culled (its bundle box is the whole root box); a
     // lane whose ray misses the root box meets no object box.
@@ -243,8 +254,8 @@ __device__ __forceinline__ LaneRay lane_ray(const RayIn& q, int64_t r, int64_t n
 }
 
 __device__ __forceinline__ bool overlaps(const float lo[3], const float hi[3], const float blo[3], const float bhi[3]) {
-    return lo[0] <= bhi[0] && lo[1] <= bhi[1] && lo[2] <= bhi[2] && hi[0] >= blo[0] && hi[1] >= blo[1] &&
-           hi[2] >= blo[2];
+    return (lo[0] <= bhi[0]) & (lo[1] <= bhi[1]) & (lo[2] <= bhi[2]) & (hi[0] >= blo[0]) & (hi[1] >= blo[1]) &
+           (hi[2] >= blo[2]);
 }
 
 // Level-1 entry of lane j: object j (one cluster) or cluster j.  Empty slots
@@ -280,7 +291,7 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
         uhi[a] = uniform_f(wave_max(R.bhi[a]));
     }
     if (!(ulo[0] <= uhi[0])) return;  // no active lane (wave-uniform)
-    uint64_t cand = __ballot(B1.id >= 0 && overlaps(B1.lo, B1.hi, ulo, uhi));
+    uint64_t cand = __ballot((B1.id >= 0) & overlaps(B1.lo, B1.hi, ulo, uhi));
     while (cand) {
         const int j = __builtin_ctzll(cand);
         cand &= cand - 1;
@@ -304,7 +315,7 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
             m.hi[a] = T.mbox[slot * 6 + 3 + a];
         }
         m.id = T.mid[slot];
-        uint64_t mc = __ballot(m.id >= 0 && overlaps(m.lo, m.hi, ulo, uhi));
+        uint64_t mc = __ballot((m.id >= 0) & overlaps(m.lo, m.hi, ulo, uhi));
         while (mc) {
             const int i = __builtin_ctzll(mc);
             mc &= mc - 1;
