@@ -91,6 +91,30 @@ def test_validation_before_device_work():
         L.nif_destroy(h)
 
 
+def test_image_only_objects_validation_on_the_host():
+    """nif_build_image and nif_set_object without a grid are refused unless the
+    image mode is on, the object has an image buffer and a grid to build from,
+    and (for no grid) its image was built; all before any device work."""
+    L = nif.lib()
+    h = C.c_void_p()
+    assert L.nif_create(C.byref(_desc(grid_dtype=1)), 2, 1, C.byref(h)) == 0
+    try:
+        fake, img = C.c_void_p(4096), C.c_void_p(1 << 20)
+        box = np.array([0, 0, 0, 1, 1, 1], np.float32)
+        assert L.nif_build_image(h, 0, None) == -1  # object not registered
+        assert L.nif_set_object(h, 0, box.ctypes.data, fake, 0) == 0
+        assert L.nif_build_image(h, 2, None) == -1  # out of range
+        assert L.nif_build_image(h, 0, None) == -5  # image mode 0
+        assert L.nif_set_object(h, 0, box.ctypes.data, None, 0) == -5  # no image at all
+        assert L.nif_set_option(h, 2, 1) == 0
+        assert L.nif_build_image(h, 0, None) == -5  # no image buffer
+        assert L.nif_set_image(h, 0, img, L.nif_image_bytes(h)) == 0
+        assert L.nif_set_object(h, 0, box.ctypes.data, None, 0) == -5  # image registered, not built
+        assert L.nif_last_error() != b""
+    finally:
+        L.nif_destroy(h)
+
+
 def test_paper_network_and_light_validation_on_the_host():
     """The paper's networks, light sampling and the 16-bit stages reject bad
     arguments before any device work."""
