@@ -96,7 +96,8 @@ nif_status nif_param_layout(const nif_ctx* ctx, int64_t* grid_elems, int64_t* ta
  * objects fit where their grids and images together would not.  Such an
  * object keeps its image until a new grid, a new image buffer or another
  * image mode is set; training calls and nif_init_grid refuse a context with
- * such an object (NIF_ERR_STATE). */
+ * such an object, and nif_encode and nif_calibrate_fp8 while its images are
+ * not built (NIF_ERR_STATE). */
 nif_status nif_set_object(nif_ctx* ctx, int32_t obj, const float* aabb, void* grid, int32_t mlp_index);
 
 /* Register MLP `mlp`: binary32 master weights (dev, mlp_params floats).  The

@@ -786,6 +786,7 @@ static nif_status encode_impl(nif_ctx* c, int32_t feat16, const float* rays, con
     if (!rays || !ids || !tmax || !features) return fail(NIF_ERR_INVALID_ARG, "nif_encode: NULL input or output");
     if (n > (int64_t)1 << 36) return fail(NIF_ERR_UNSUPPORTED, "nif_encode: n too large");
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    if (!c->images_ready && require_grids(c, "nif_encode") != NIF_OK) return NIF_ERR_STATE;  // would read grids
     FwdArgs a{};
     fill_common(c, a);
     a.rays = rays;
@@ -913,6 +914,7 @@ extern "C" nif_status nif_calibrate_fp8(nif_ctx* c, int32_t mlp, const float* ra
     if (n > (int64_t)1 << 31) return fail(NIF_ERR_UNSUPPORTED, "nif_calibrate_fp8: n too large");
     if (!c->masters[mlp]) return fail(NIF_ERR_STATE, "MLP %d not registered", mlp);
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
+    if (!c->images_ready && require_grids(c, "nif_calibrate_fp8") != NIF_OK) return NIF_ERR_STATE;
     const size_t need = calib_workspace_bytes(n, c->din);
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     FwdArgs a{};

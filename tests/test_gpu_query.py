@@ -604,6 +604,13 @@ def test_image_only_objects():
     with pytest.raises(nif.NifError) as e:
         ctx.prepare("f32")
     assert e.value.status == nif.NIF_ERR_STATE
+    # the paths that would read the grids through the last prepared object table refuse too
+    with pytest.raises(nif.NifError) as e:
+        ctx.encode(rays, ids, tmax)
+    assert e.value.status == nif.NIF_ERR_STATE
+    with pytest.raises(nif.NifError) as e:
+        ctx.calibrate_fp8(rays, ids, tmax, mlp=0)
+    assert e.value.status == nif.NIF_ERR_STATE
     for k in (0, 2):  # grids given again (same initial latents): the grid path's outputs
         ctx.set_object(k, w["aabb"][k], ctx.alloc_grid(), int(w["mlp_index"][k]))
         ctx.init_grid(k, GRID_SEED, 0.5)
