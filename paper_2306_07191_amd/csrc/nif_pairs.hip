@@ -278,17 +278,24 @@ __device__ __forceinline__ LaneBox level1_box(const PairTree& T, int lane) {
     return b;
 }
 
-// Calls on_hit(object, lo, hi) in every lane whose ray the division test says meets
-// that object's box; wave-uniform control flow.  ONE: the tree has one level
-// (at most 64 objects, T.C == 1).
-template <bool ONE, typename F>
-__device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1, const PairTree& T, int lane,
+// Calls on_hit(i, object, lo, hi) for each of a lane's NR rays R[i] that the
+// division test says meets that object's box; wave-uniform control flow.  The
+// wave's bundle is the union of all its lanes' rays' boxes.  ONE: the tree
+// has one level (at most 64 objects, T.C == 1).
+template <bool ONE, int NR, typename F>
+__device__ __forceinline__ void for_each_hit(const LaneRay* R, const LaneBox& B1, const PairTree& T, int lane,
                                              F&& on_hit) {
     float ulo[3], uhi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        ulo[a] = uniform_f(wave_min(R.blo[a]));
-        uhi[a] = uniform_f(wave_max(R.bhi[a]));
+        float lo = R[0].blo[a], hi = R[0].bhi[a];
+#pragma unroll
+        for (int i = 1; i < NR; ++i) {
+            lo = fminf(lo, R[i].blo[a]);
+            hi = fmaxf(hi, R[i].bhi[a]);
+        }
+        ulo[a] = uniform_f(wave_min(lo));
+        uhi[a] = uniform_f(wave_max(hi));
     }
     if (!(ulo[0] <= uhi[0])) return;  // no active lane (wave-uniform)
     uint64_t cand = __ballot((B1.id >= 0) & overlaps(B1.lo, B1.hi, ulo, uhi));
@@ -303,7 +310,9 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
                 hi[a] = lane_f(B1.hi[a], j);
             }
             const int32_t k = __builtin_amdgcn_readlane(B1.id, j);
-            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k, lo, hi);
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                if (R[i].active && decide_hit(R[i].pre, lo, hi)) on_hit(i, k, lo, hi);
             continue;
         }
         // cluster j: its members, lane i holding member i
@@ -326,7 +335,9 @@ __device__ __forceinline__ void for_each_hit(const LaneRay& R, const LaneBox& B1
                 hi[a] = lane_f(m.hi[a], i);
             }
             const int32_t k = __builtin_amdgcn_readlane(m.id, i);
-            if (R.active && decide_hit(R.pre, lo, hi)) on_hit(k, lo, hi);
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (R[q].active && decide_hit(R[q].pre, lo, hi)) on_hit(q, k, lo, hi);
         }
     }
 }
@@ -391,6 +402,44 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
     const int64_t t_end = tile_begin(tiles, 1);
     uint32_t block_total = 0;
+    if constexpr (!ROUNDS) {
+        // Two rays per lane: a step covers two tiles (512 rays), wave w the 128
+        // consecutive rays from 128 w, lane l rays l and 64 + l of them, so that
+        // the bundle reductions and box reads serve 128 rays.  Rays past the
+        // block's tiles (an odd last tile) are inactive.
+        const int64_t rlim = t_end * kPairTile < n ? t_end * kPairTile : n;
+        const int64_t wbase = (int64_t)(threadIdx.x >> 6) * 128 + lane;
+        RayIn q_next[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            q_next[i] = load_ray(rays, tmax, tile_begin(tiles) * kPairTile + wbase + 64 * i, rlim);
+        for (int64_t tile = tile_begin(tiles); tile < t_end; tile += 2) {
+            LaneRay R[2];
+            int64_t r[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                r[i] = tile * kPairTile + wbase + 64 * i;
+                const RayIn q = q_next[i];  // the next step's rays are read before the work on these
+                if (tile + 2 < t_end) q_next[i] = load_ray(rays, tmax, r[i] + 2 * kPairTile, rlim);
+                R[i] = lane_ray(q, r[i], rlim, T);
+            }
+            uint64_t mk[2] = {0, 0};
+            uint32_t c[2] = {0, 0};
+            for_each_hit<ONE, 2>(R, B1, T, lane, [&](int i, int32_t k, const float*, const float*) {
+                ++c[i];
+                mk[i] |= 1ull << (k & 63);
+            });
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                if (r[i] < rlim) {
+                    if (masks) masks[r[i]] = mk[i];
+                    else counts[r[i]] = c[i];
+                }
+            block_total += block_sum(c[0] + c[1], sh);
+        }
+        if (threadIdx.x == 0) block_sums[blockIdx.x] = block_total;
+        return;
+    }
     RayIn q_next = load_ray(rays, tmax, tile_begin(tiles) * kPairTile + threadIdx.x, n);
     for (int64_t tile = tile_begin(tiles); tile < t_end; ++tile) {
         const int64_t r = tile * kPairTile + threadIdx.x;
@@ -401,7 +450,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
         uint32_t c = 0;
         float best_ta = INFINITY;
         int32_t best_k = 0x7fffffff;
-        for_each_hit<ONE>(R, B1, T, lane, [&](int32_t k, const float lo[3], const float hi[3]) {
+        for_each_hit<ONE, 1>(&R, B1, T, lane, [&](int, int32_t k, const float lo[3], const float hi[3]) {
             ++c;
             mk |= 1ull << (k & 63);
             if constexpr (ROUNDS) {  // the box entered first
@@ -617,7 +666,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_tree_kernel(
         const LaneRay R = lane_ray(load_ray(rays, tmax, r, n), r, n, T);
         const int32_t first = round && r < n ? first_obj[r] : -1;
         int64_t p = p0;
-        for_each_hit<false>(R, B1, T, lane, [&](int32_t k, const float*, const float*) {
+        for_each_hit<false, 1>(&R, B1, T, lane, [&](int, int32_t k, const float*, const float*) {
             // round 1: the first object only; round 2: the others (a ray with c = 0 writes none)
             if ((round == 1 && k != first) || (round == 2 && k == first) || p >= p0 + (int64_t)c) return;
             if (p < max_pairs) write_pair(p, R.pre.o, R.pre.d, R.pre.tm, k, (uint32_t)r, out);
