@@ -186,6 +186,24 @@ def test_combine_output_alignment(offset, n_rays):
     assert (got[:offset] == 7).all() and (got[offset + n_rays:] == 7).all()
 
 
+@pytest.mark.parametrize("start", [0, 1, 2, 3])
+def test_combine_inputs_off_16_byte_boundaries(start):
+    """Pair rays and visibilities read four at a time (16-byte loads) when both
+    start on a 16-byte boundary, one at a time otherwise: the same result."""
+    import torch
+    w = _scene(n=40)
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    g = np.random.default_rng(start)
+    n_rays, n_pairs = 100_003, 70_001
+    pray = np.sort(g.integers(0, n_rays, n_pairs + 3)).astype(np.uint32)
+    y = g.uniform(0, 1, n_pairs + 3).astype(np.float32)
+    pr_t = torch.from_numpy(pray.view(np.int32)).cuda()[start:start + n_pairs]
+    y_t = torch.from_numpy(y).cuda()[start:start + n_pairs]
+    out = ctx.combine_pairs(pr_t, y_t, n_rays).cpu().numpy()
+    np.testing.assert_array_equal(out, O.combine_pairs(pray[start:start + n_pairs], y[start:start + n_pairs], n_rays))
+
+
 @pytest.mark.parametrize("K", [12, 70])  # hit masks (<= 64 objects), tree traversal (> 64)
 def test_early_out_rounds(K):
     """The early-out form (Sec. 7): round 1 is each ray's first box (smallest
