@@ -736,22 +736,25 @@ def run_scene(args):
     torch.cuda.empty_cache()
     layout = to_query_images(ctx, log) if not args.scene_grids else None
     # schedule: the pair path, ordering with or without the window sort (the
-    # finer Morton key), and the fused kernel's tile shape, whichever makes the
-    # headline step fastest on these pairs
+    # finer Morton key), by the automatic bucket key or by object alone, and
+    # the fused kernel's tile shape, whichever makes the headline step fastest
+    # on these pairs
     ctx.prepare(SCENE_DTYPE)
     sched = {}
     for path in ("keys", "arrays"):
         for wsort in (1, 0):
-            for shape in (0, 1, 2):
-                ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
-                ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
-
-                sched[(path, wsort, shape)] = time_launches(lambda: one_step(path, SCENE_DTYPE), 10, 3) * 1e3
-    pair_path, window_sort, tile_shape = min(sched, key=sched.get)
+            for obits in (-1, 0):
+                for shape in (0, 1, 2):
+                    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
+                    ctx.set_option(nif.NIF_OPT_ORDER_BITS, obits)
+                    ctx.set_option(nif.NIF_OPT_TILE_SHAPE, shape)
+                    sched[(path, wsort, obits, shape)] = time_launches(lambda: one_step(path, SCENE_DTYPE), 10, 3) * 1e3
+    pair_path, window_sort, order_bits, tile_shape = min(sched, key=sched.get)
     ctx.set_option(nif.NIF_OPT_WINDOW_SORT, window_sort)
+    ctx.set_option(nif.NIF_OPT_ORDER_BITS, order_bits)
     ctx.set_option(nif.NIF_OPT_TILE_SHAPE, tile_shape)
-    log("step ms by (pair path, window sort, tile shape): " + ", ".join(f"{k}: {v:.3f}" for k, v in sched.items()) +
-        f"; chosen {(pair_path, window_sort, tile_shape)}")
+    log("step ms by (pair path, window sort, bucket bits, tile shape): " +
+        ", ".join(f"{k}: {v:.3f}" for k, v in sched.items()) + f"; chosen {(pair_path, window_sort, order_bits, tile_shape)}")
     for dt in dts:
         ctx.prepare(dt)
         steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
@@ -892,8 +895,9 @@ def run_scene(args):
                    "rays": n, "pairs": P, "objects": K, "triangles": int(w["tri_counts"].sum()),
                    "step": "pair expansion + pair ordering + fused query kernel + per-ray combination",
                    "latents": layout or "grids (binary16, vertex-major)", "step_ms_on_grids": grid_step_ms,
-                   "pair_path": pair_path, "window_sort": bool(window_sort), "tile_shape": tile_shape,
-                   "step_ms_by_path_window_sort_and_shape": {"/".join(map(str, k)): v for k, v in sched.items()},
+                   "pair_path": pair_path, "window_sort": bool(window_sort),
+                   "order_bucket_bits": "automatic" if order_bits < 0 else order_bits, "tile_shape": tile_shape,
+                   "step_ms_by_path_window_sort_bucket_bits_and_shape": {"/".join(map(str, k)): v for k, v in sched.items()},
                    "value_is": "(ray, object) queries per second; rays_per_s is in per_dtype"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -144,7 +144,9 @@ nif_status nif_combine_pairs(nif_ctx* ctx, const uint32_t* pair_ray, const float
  *   dx, dy, dz, t_max, object id (int32 bit pattern)}, pair_ray as in
  *   nif_expand_pairs, and keys (dev, max_pairs uint32, nullable) the
  *   ordering key of each pair: (object id, Morton code of the binary32 AABB
- *   entry point), the key nif_order and nif_order_packed compute for it.
+ *   entry point), the key nif_order and nif_order_packed compute for it;
+ *   when the ordering reads only the object (NIF_OPT_ORDER_BITS 0, window
+ *   sort off), its Morton part is left zero.
  *   Same pairs, order, counts, limits and workspace as nif_expand_pairs.
  * nif_order_keys: the ordering (as nif_order) of n queries from their keys
  *   (dev, n uint32, as written by nif_expand_pairs_packed), without reading
@@ -234,9 +236,19 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * nif_order_packed) also sorts each 4,096-query window by the finer key:
  * 0 never, 1 always, 2 (default) when NIF_OPT_GRID_IMAGE is 0.
  * NIF_OPT_TILE_SHAPE: the fused kernel's tile shape (0 default, 1, 2; see
- * nif_plan_create) for queries outside plans.  Outputs are bit-identical in
- * every mode. */
-enum { NIF_OPT_ORDER = 1, NIF_OPT_GRID_IMAGE = 2, NIF_OPT_WINDOW_SORT = 3, NIF_OPT_TILE_SHAPE = 4 };
+ * nif_plan_create) for queries outside plans.  NIF_OPT_ORDER_BITS: at most
+ * this many Morton bits per axis of the entry point in the ordering's bucket
+ * key (-1, the default: as many as 4,096 buckets allow, up to 4); 0 orders
+ * by object alone (many objects with many queries each gain little from the
+ * finer buckets).  Plans keep the value they were created with.  Outputs are
+ * bit-identical in every mode. */
+enum {
+    NIF_OPT_ORDER = 1,
+    NIF_OPT_GRID_IMAGE = 2,
+    NIF_OPT_WINDOW_SORT = 3,
+    NIF_OPT_TILE_SHAPE = 4,
+    NIF_OPT_ORDER_BITS = 5
+};
 nif_status nif_set_option(nif_ctx* ctx, int32_t option, int64_t value);
 
 /* Query images (NIF_OPT_GRID_IMAGE 1 or 2): nif_image_bytes is the size in

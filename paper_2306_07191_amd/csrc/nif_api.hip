@@ -73,6 +73,7 @@ struct nif_ctx {
     int32_t order_mode = 2;  // NIF_ORDER_AUTO
     int32_t window_sort = 2;  // NIF_OPT_WINDOW_SORT: 2 = when there is no query image
     int32_t tile_shape = 0;   // NIF_OPT_TILE_SHAPE: fused kernel shape outside plans
+    int32_t order_bits = -1;  // NIF_OPT_ORDER_BITS: bucket Morton bits per axis at most (-1: automatic)
     std::vector<float*> mlp_m, mlp_v;  // Adam moments per MLP
     // device tables of per-object training pointers: grad, m, v, touched, grid
     void** d_train_tab = nullptr;
@@ -491,6 +492,10 @@ extern "C" nif_status nif_set_option(nif_ctx* c, int32_t option, int64_t value) 
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_WINDOW_SORT takes 0, 1 or 2");
         c->window_sort = (int32_t)value;
         return ok();
+    case NIF_OPT_ORDER_BITS:
+        if (value < -1 || value > 4) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_ORDER_BITS takes -1 to 4");
+        c->order_bits = (int32_t)value;
+        return ok();
     case NIF_OPT_TILE_SHAPE:
         if (value < 0 || value > 2) return fail(NIF_ERR_INVALID_ARG, "NIF_OPT_TILE_SHAPE takes 0, 1 or 2");
         c->tile_shape = (int32_t)value;
@@ -613,6 +618,7 @@ static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, c
     o.n = n;
     o.objs = c->d_objs;
     o.num_objects = c->K;
+    o.max_bits = c->order_bits;
     o.perm = perm_dst;
     HIP_TRY(launch_order(o, ws, s, perm));
     return ok();
@@ -720,6 +726,7 @@ extern "C" nif_status nif_order_keys(nif_ctx* c, const uint32_t* keys, int64_t n
     if (!c->d_objs) return fail(NIF_ERR_STATE, "context not prepared");
     OrderArgs o{};
     o.key_in = keys;
+    o.max_bits = c->order_bits;
     o.no_refine = window_sorted(c) ? 0 : 1;
     o.n = n;
     o.objs = c->d_objs;
@@ -843,7 +850,8 @@ static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax,
     if (ws_bytes < need || !ws) return fail(NIF_ERR_WORKSPACE, "workspace too small: need %zu bytes", need);
     HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->tree, c->K, c->num_cus, round, ray_visible, max_pairs,
                                 pair_rays, pair_tmax, pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream,
-                                reinterpret_cast<float4*>(packed), keys, c->d_objs));
+                                reinterpret_cast<float4*>(packed), keys, c->d_objs,
+                                order_bucket_bits(c->K, c->order_bits) == 0 && !window_sorted(c)));
     return ok();
 }
 

@@ -180,9 +180,11 @@ struct OrderArgs {
     float4* qrec;          // nullable: receives query i as a 32-byte record {o, d.x}, {d.y, d.z, t_max, id bits}
     uint32_t* zero_words;  // nullable: kTileCtrWords words the count pass zeroes (the next query's tile counters)
     const uint32_t* key_in;  // nullable: given fine keys (no queries read, no records written)
+    int32_t max_bits = -1;   // bucket Morton bits per axis at most this (-1: order_bits alone)
 };
 
 int order_bits(int32_t num_objects);
+int order_bucket_bits(int32_t num_objects, int32_t max_bits);  // the bits a launch uses
 int order_fine_bits(int32_t num_objects);  // Morton bits per axis of the fine key
 size_t order_workspace_bytes(int64_t n, int32_t num_objects);
 hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out);
@@ -289,7 +291,7 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
                                int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
                                float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
                                int64_t* total, void* ws, hipStream_t s, float4* rec = nullptr,
-                               uint32_t* keys = nullptr, const ObjDev* objs = nullptr);
+                               uint32_t* keys = nullptr, const ObjDev* objs = nullptr, bool object_keys = false);
 // t = t_a + y (t_b - t_a) of the query's segment; +inf for a miss, NaN for an
 // invalid query.
 hipError_t launch_depth_from_visibility(const float* rays, const int32_t* ids, const float* tmax, const float* vis,

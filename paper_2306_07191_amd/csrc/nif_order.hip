@@ -373,10 +373,16 @@ struct OrderLayout {
     size_t off_table, off_sums, off_key, off_fine, off_coarse, off_perm, total;
 };
 
-static OrderLayout order_layout(int64_t n, int32_t num_objects) {
+int order_bucket_bits(int32_t num_objects, int32_t max_bits) {
+    const int b = order_bits(num_objects);
+    return max_bits >= 0 && max_bits < b ? max_bits : b;
+}
+
+// Regions of the ordering workspace for `bits` bucket bits per axis; the
+// workspace size is that of order_bits(num_objects), the largest.
+static OrderLayout order_layout(int64_t n, int32_t num_objects, int bits) {
     OrderLayout L{};
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const int bits = order_bits(num_objects);
     L.nb = ((int64_t)num_objects << (3 * bits)) + 1;
     L.tiles = (n + kOrderTile - 1) / kOrderTile;
     L.table = L.nb * L.tiles;
@@ -392,13 +398,13 @@ static OrderLayout order_layout(int64_t n, int32_t num_objects) {
 
 size_t order_workspace_bytes(int64_t n, int32_t num_objects) {
     if (num_objects > 4096) return 0;  // rejected by launch_order
-    return order_layout(n, num_objects).total;
+    return order_layout(n, num_objects, order_bits(num_objects)).total;
 }
 
 hipError_t launch_order(OrderArgs A, void* ws, hipStream_t s, const uint32_t** perm_out) {
     if (A.num_objects > 4096) return hipErrorInvalidValue;
-    const OrderLayout L = order_layout(A.n, A.num_objects);
-    A.bits = order_bits(A.num_objects);
+    A.bits = order_bucket_bits(A.num_objects, A.max_bits);
+    const OrderLayout L = order_layout(A.n, A.num_objects, A.bits);
     A.fine_bits = order_fine_bits(A.num_objects);
     A.num_buckets = (uint32_t)L.nb;
     A.tile = kOrderTile;

@@ -516,7 +516,9 @@ __global__ __launch_bounds__(kPairScanThreads) void pairs_block_scan_kernel(cons
 // Where the pairs go: separate arrays (pair_rays, pair_tmax, pair_ids), or
 // 32-byte query records {o, d.x}, {d.y, d.z, t_max, object id bits} with,
 // optionally, each pair's ordering key (the ordering's fine key, so that the
-// ordering need not read the pairs again); pair_ray always.
+// ordering need not read the pairs again; with object_keys, for an ordering
+// by object alone, the object's part of it with the Morton bits zero);
+// pair_ray always.
 struct PairOut {
     float* pair_rays;
     float* pair_tmax;
@@ -527,14 +529,21 @@ struct PairOut {
     const ObjDev* objs;
     int32_t K;
     int32_t fine_bits;
+    bool object_keys;
 };
+
+// The ordering key of a pair (a valid query that meets its box).
+__device__ __forceinline__ uint32_t pair_key(const float o[3], const float d[3], float tm, int32_t k,
+                                             const ObjDev* __restrict__ objs, const PairOut& out) {
+    return out.object_keys ? (uint32_t)k << (3 * out.fine_bits) : fine_order_key(o, d, tm, k, objs, out.K, out.fine_bits);
+}
 
 __device__ __forceinline__ void write_pair(int64_t p, const float o[3], const float d[3], float tm, int32_t k,
                                            uint32_t ray, const PairOut& out) {
     if (out.rec) {
         out.rec[2 * p] = make_float4(o[0], o[1], o[2], d[0]);
         out.rec[2 * p + 1] = make_float4(d[1], d[2], tm, __int_as_float(k));
-        if (out.key) out.key[p] = fine_order_key(o, d, tm, k, out.objs, out.K, out.fine_bits);
+        if (out.key) out.key[p] = pair_key(o, d, tm, k, out.objs, out);
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -574,7 +583,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     __shared__ float4 srec[2 * kPairStage];
     __shared__ uint32_t sray[kPairStage];
     __shared__ ObjDev sobj[64];
-    if (out.key)
+    if (out.key && !out.object_keys)
         for (int i = threadIdx.x; i < out.K; i += kPairTile) sobj[i] = out.objs[i];
     __syncthreads();
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
@@ -637,7 +646,7 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
                 if (out.key) {
                     const float4 a = srec[2 * i], b = srec[2 * i + 1];
                     const float qo[3] = {a.x, a.y, a.z}, qd[3] = {a.w, b.x, b.y};
-                    out.key[base + i] = fine_order_key(qo, qd, b.z, __float_as_int(b.w), sobj, out.K, out.fine_bits);
+                    out.key[base + i] = pair_key(qo, qd, b.z, __float_as_int(b.w), sobj, out);
                 }
             }
             __syncthreads();
@@ -793,7 +802,7 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
                                int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
                                float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
                                int64_t* total, void* ws, hipStream_t s, float4* rec, uint32_t* keys,
-                               const ObjDev* objs) {
+                               const ObjDev* objs, bool object_keys) {
     if (n == 0) {
         hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
         return hipGetLastError();
@@ -817,7 +826,7 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
                        round ? first : nullptr, sums);
     hipLaunchKernelGGL(pairs_block_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, (int64_t)blocks, offs,
                        total);
-    const PairOut out{pair_rays, pair_tmax, pair_ids, pair_ray, rec, keys, objs, K, order_fine_bits(K)};
+    const PairOut out{pair_rays, pair_tmax, pair_ids, pair_ray, rec, keys, objs, K, order_fine_bits(K), object_keys};
     if (use_mask)
         hipLaunchKernelGGL(pairs_emit_mask_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, masks, offs,
                            max_pairs, out);

@@ -20,6 +20,7 @@ NIF_OPT_ORDER = 1
 NIF_OPT_GRID_IMAGE = 2
 NIF_OPT_WINDOW_SORT = 3
 NIF_OPT_TILE_SHAPE = 4
+NIF_OPT_ORDER_BITS = 5
 NIF_FLAG_INVALID_RAY = 1
 NIF_FLAG_BAD_OBJECT = 2
 DTYPES = {"f32": NIF_F32, "f16": NIF_F16, "bf16": NIF_BF16, "fp8": NIF_FP8_E4M3}

@@ -111,6 +111,8 @@ def test_image_only_objects_validation_on_the_host():
         assert L.nif_set_image(h, 0, img, L.nif_image_bytes(h)) == 0
         assert L.nif_set_object(h, 0, box.ctypes.data, None, 0) == -5  # image registered, not built
         assert L.nif_last_error() != b""
+        assert L.nif_set_option(h, 5, 5) == -1 and L.nif_set_option(h, 5, -2) == -1  # NIF_OPT_ORDER_BITS range
+        assert L.nif_set_option(h, 5, 0) == 0 and L.nif_set_option(h, 5, -1) == 0
     finally:
         L.nif_destroy(h)
 

@@ -346,3 +346,40 @@ def test_packed_pairs_empty_and_no_keys():
     pr_rays, _, pr_ids, pr_ray = ctx.expand_pairs(rays, tmax)
     np.testing.assert_array_equal(rec.cpu().numpy()[:, 7].view(np.int32), pr_ids.cpu().numpy())
     np.testing.assert_array_equal(rec.cpu().numpy()[:, :6], pr_rays.cpu().numpy())
+
+
+@pytest.mark.parametrize("K", [12, 70])  # hit masks (<= 64 objects), tree traversal (> 64)
+def test_packed_pairs_order_by_object(K):
+    """With NIF_OPT_ORDER_BITS 0 and no window sort the ordering reads only the
+    object: nif_expand_pairs_packed leaves the keys' Morton part zero, and
+    nif_order_keys groups the pairs by object (the same object sequence as
+    nif_order_packed on the pairs); the query outputs per pair are those of the
+    path that reads the pairs, bit for bit.  With the window sort on, the keys
+    are the full ordering keys again."""
+    import torch
+    from paper_2306_07191_amd import nif
+    w = _scene(n=12000, K=K, seed=41 + K)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_ORDER_BITS, 0)
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, 0)
+    ctx.prepare("f32")
+    rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
+    pr_rays, pr_tmax, pr_ids, pr_ray = ctx.expand_pairs(rays, tmax)
+    rec, pray, key = ctx.expand_pairs_packed(rays, tmax)
+    fb, _ = _fine_bits(K)
+    g_obj = pr_ids.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(key.cpu().numpy().view(np.uint32).astype(np.int64), g_obj << (3 * fb))
+    perm_k = ctx.order_keys(key).cpu().numpy().view(np.uint32).astype(np.int64)
+    perm_p, _ = ctx.order_packed(pr_rays, pr_ids, pr_tmax)
+    perm_p = perm_p.cpu().numpy().view(np.uint32).astype(np.int64)
+    P = g_obj.shape[0]
+    assert np.array_equal(np.sort(perm_k), np.arange(P))
+    np.testing.assert_array_equal(g_obj[perm_k], np.sort(g_obj))
+    np.testing.assert_array_equal(g_obj[perm_p], np.sort(g_obj))
+    pk = torch.from_numpy(perm_k.astype(np.uint32).view(np.int32)).cuda()
+    np.testing.assert_array_equal(ctx.query_packed(rec, pk, dtype="f32").cpu().numpy().view(np.uint32),
+                                  ctx.query(pr_rays, pr_ids, pr_tmax, dtype="f32").cpu().numpy().view(np.uint32))
+    ctx.set_option(nif.NIF_OPT_WINDOW_SORT, 1)
+    _, _, key_ws = ctx.expand_pairs_packed(rays, tmax)
+    kref = _pair_keys(model, w["rays"], w["tmax"], pr_ray.cpu().numpy().astype(np.int64), g_obj, fb)
+    np.testing.assert_array_equal(key_ws.cpu().numpy().view(np.uint32).astype(np.int64), kref)

@@ -615,3 +615,38 @@ def test_image_only_objects():
         ctx.set_object(k, w["aabb"][k], ctx.alloc_grid(), int(w["mlp_index"][k]))
         ctx.init_grid(k, GRID_SEED, 0.5)
     np.testing.assert_array_equal(run_query(ctx, w, "f32")[0], y_grid["f32"][0])
+
+
+def test_order_bits_option_is_transparent():
+    """NIF_OPT_ORDER_BITS caps the entry-point Morton bits of the ordering's
+    bucket key (0: by object alone): the ordering is a permutation whose
+    buckets follow the capped key, and nif_query's outputs are those of the
+    automatic setting bit for bit, with and without the window sort."""
+    import torch
+    from paper_2306_07191_amd import nif
+    K, n = 16, 60000
+    w = S.multi_workload(n_objects=K, n_rays=n)
+    w["shape"] = S.FRAME
+    w["mlps"] = np.stack([S.xavier_mlp(S.FRAME, S.rng(71, 3, k)) for k in range(K)])
+    w["mlp_index"] = np.arange(K, dtype=np.int32)
+    ctx, model = make_pair(w, grid_amp=0.5)
+    ctx.set_option(nif.NIF_OPT_ORDER, 1)
+    ctx.set_option(nif.NIF_OPT_GRID_IMAGE, 0)
+    ref = run_query(ctx, w, "bf16")
+    rays, ids, tmax = (torch.from_numpy(np.ascontiguousarray(w[k])).cuda() for k in ("rays", "ids", "tmax"))
+    for ws in (0, 1):
+        ctx.set_option(nif.NIF_OPT_WINDOW_SORT, ws)
+        for bits in (0, 1, 3):
+            ctx.set_option(nif.NIF_OPT_ORDER_BITS, bits)
+            y, z = run_query(ctx, w, "bf16")
+            np.testing.assert_array_equal(y, ref[0])
+            np.testing.assert_array_equal(z, ref[1])
+            perm = ctx.order(rays, ids, tmax).cpu().numpy().view(np.uint32).astype(np.int64)
+            assert np.array_equal(np.sort(perm), np.arange(n))
+            if bits == 0 and ws == 0:  # by object alone; misses and invalid queries last
+                st = model.forward(w["rays"], w["ids"], w["tmax"])["status"]
+                obj = np.where(st == 1, w["ids"], K)
+                assert (np.diff(obj[perm]) >= 0).all()
+    ctx.set_option(nif.NIF_OPT_ORDER_BITS, -1)
+    with pytest.raises(nif.NifError):
+        ctx.set_option(nif.NIF_OPT_ORDER_BITS, 5)
