@@ -683,11 +683,22 @@ def run_scene(args):
                                              pray.data_ptr(), keys.data_ptr(), cnt.data_ptr(), pws.data_ptr(),
                                              pws.numel(), nif._stream()), "nif_expand_pairs_packed")
 
+    def expand_grouped():  # the pairs as query records, grouped by object: no ordering pass
+        nif._check(L.nif_expand_pairs_by_object(ctx.h, rays.data_ptr(), tmax.data_ptr(), n, maxp, recs.data_ptr(),
+                                                pray.data_ptr(), cnt.data_ptr(), None, pws.data_ptr(), pws.numel(),
+                                                nif._stream()), "nif_expand_pairs_by_object")
+
     def expand_and_order(path, ev=None):
-        """Pair expansion then ordering, by one of two paths: "keys" writes the
-        query records and keys with the pairs and orders by the keys alone;
+        """Pair expansion then ordering, by one of three paths: "grouped" writes
+        the query records grouped by object and needs no ordering; "keys" writes
+        the records and keys with the pairs and orders by the keys alone;
         "arrays" writes the pairs as arrays and the ordering reads them and
-        writes the records."""
+        writes the records.  Returns the order the query kernel reads the
+        records in (None: their own)."""
+        if path == "grouped":
+            expand_grouped()
+            if ev: ev.record(stream)
+            return None
         if path == "keys":
             expand_packed()
             if ev: ev.record(stream)
@@ -696,6 +707,7 @@ def run_scene(args):
             expand()
             if ev: ev.record(stream)
             ctx.order_packed(pr[:P], pi[:P], pt[:P], perm=perm, packed=recs[:P], ws=ows)
+        return perm
     ows = torch.empty(max(1, int(L.nif_order_workspace_bytes(ctx.h, P))), dtype=torch.uint8, device="cuda")
     vis = torch.empty(n, dtype=torch.uint8, device="cuda")
     flops = 2 * (sh.din * sh.width + (sh.hidden - 1) * sh.width * sh.width + sh.width)  # 30,848 per query
@@ -705,9 +717,11 @@ def run_scene(args):
     dts = (SCENE_DTYPE,) if args.quick else ("f16", "fp8", "bf16", "f32")
 
     def one_step(path, dt):
-        expand_and_order(path)
-        ctx.query_packed(recs[:P], perm, dtype=dt, out=yq)
+        ctx.query_packed(recs[:P], expand_and_order(path), dtype=dt, out=yq)
         ctx.combine_pairs(pray[:P], yq, n, out=vis)
+
+    # the grouped path's pair j is the ray-order pair group_order[j]
+    group_order = np.argsort(pi[:P].cpu().numpy(), kind="stable")
 
     # reference pass on the grids: every dtype's outputs (the oracle comparison
     # runs on them, and the timed runs on the query images must reproduce them
@@ -741,9 +755,9 @@ def run_scene(args):
     # on these pairs
     ctx.prepare(SCENE_DTYPE)
     sched = {}
-    for path in ("keys", "arrays"):
-        for wsort in (1, 0):
-            for obits in (-1, 0):
+    for path in ("grouped", "keys", "arrays"):
+        for wsort in ((0,) if path == "grouped" else (1, 0)):  # the grouped path has no ordering pass
+            for obits in ((-1,) if path == "grouped" else (-1, 0)):
                 for shape in (0, 1, 2):
                     ctx.set_option(nif.NIF_OPT_WINDOW_SORT, wsort)
                     ctx.set_option(nif.NIF_OPT_ORDER_BITS, obits)
@@ -760,9 +774,9 @@ def run_scene(args):
         steps = args.steps if dt == SCENE_DTYPE else max(5, args.steps // 2)
 
         def stages(ev=None):
-            expand_and_order(pair_path, ev[0] if ev else None)
+            order = expand_and_order(pair_path, ev[0] if ev else None)
             if ev: ev[1].record(stream)
-            ctx.query_packed(recs[:P], perm, dtype=dt, out=yq)
+            ctx.query_packed(recs[:P], order, dtype=dt, out=yq)
             if ev: ev[2].record(stream)
             ctx.combine_pairs(pray[:P], yq, n, out=vis)
 
@@ -788,7 +802,8 @@ def run_scene(args):
         t_q = part(lambda k: evs[k][1], lambda k: evs[k][2])
         t_comb = part(lambda k: evs[k][2], lambda k: marks[k + 1])
         v = vis.cpu().numpy()
-        same = bool(np.array_equal(yq.cpu().numpy().view(np.uint32), grid_y[dt].view(np.uint32)))
+        ref_y = grid_y[dt][group_order] if pair_path == "grouped" else grid_y[dt]
+        same = bool(np.array_equal(yq.cpu().numpy().view(np.uint32), ref_y.view(np.uint32)))
         mis = float((v != lab).mean())
         mse = float(((v.reshape(-1, S.SCENE_SPP).mean(axis=1) - mask_ref) ** 2).mean())
         psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")

@@ -156,12 +156,23 @@ nif_status nif_combine_pairs(nif_ctx* ctx, const uint32_t* pair_ray, const float
  *   nif_order.
  * A scene step is then nif_expand_pairs_packed, nif_order_keys,
  * nif_query_packed and nif_combine_pairs, each pass reading what the one
- * before wrote once. */
+ * before wrote once.
+ * nif_expand_pairs_by_object: the same records, grouped by object as the
+ *   top-level stage of Sec. 4.1 appends each object's inputs (objects
+ *   ascending, rays ascending within an object), for at most 64 objects (else
+ *   NIF_ERR_UNSUPPORTED): packed and pair_ray as in nif_expand_pairs_packed,
+ *   obj_offsets (dev, num_objects + 1 int64, nullable) the first pair of each
+ *   object and the total.  No ordering pass is needed: nif_query_packed reads
+ *   the records with a NULL perm.  Counts, limits and workspace as
+ *   nif_expand_pairs. */
 nif_status nif_expand_pairs_packed(nif_ctx* ctx, const float* rays, const float* t_max, int64_t n_rays,
                                    int64_t max_pairs, float* packed, uint32_t* pair_ray, uint32_t* keys,
                                    int64_t* pair_count, void* ws, size_t ws_bytes, void* stream);
 nif_status nif_order_keys(nif_ctx* ctx, const uint32_t* keys, int64_t n, uint32_t* perm, void* ws, size_t ws_bytes,
                           void* stream);
+nif_status nif_expand_pairs_by_object(nif_ctx* ctx, const float* rays, const float* t_max, int64_t n_rays,
+                                      int64_t max_pairs, float* packed, uint32_t* pair_ray, int64_t* pair_count,
+                                      int64_t* obj_offsets, void* ws, size_t ws_bytes, void* stream);
 
 /* The early-out form (Sec. 7: once one object is found to occlude a ray, its
  * other objects need not be queried), in two rounds over the same rays:
@@ -319,8 +330,10 @@ nif_status nif_query_noalloc(nif_ctx* ctx, int32_t dtype, const float* rays, con
  *   perm are scattered, then fetches one 32-byte span per query instead of
  *   pieces of three arrays.
  * nif_query_packed: as nif_query_ordered with the queries given as those
- *   records (row perm[i] is computed in slot i, output perm[i]).  nif_query
- *   with ordering does the same internally.
+ *   records (row perm[i] is computed in slot i, output perm[i]); perm may be
+ *   NULL: the records in their own order (already grouped, as
+ *   nif_expand_pairs_by_object writes them).  nif_query with ordering does
+ *   the same internally.
  * Tiles of the fused kernel: the blocks on each XCD take the tiles of that
  * XCD's contiguous share of the order from a counter, so that the queries in
  * flight on an XCD are neighbours in the order and share its L2.  nif_query

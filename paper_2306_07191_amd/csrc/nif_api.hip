@@ -755,7 +755,7 @@ extern "C" nif_status nif_order_packed(nif_ctx* c, const float* rays, const int3
 
 extern "C" nif_status nif_query_packed(nif_ctx* c, int32_t dtype, const float* packed, const uint32_t* perm,
                                        int64_t n, float* vis, float* logits, void* stream) {
-    nif_status st = check_query_args(c, dtype, packed, perm, packed, n, vis, "nif_query_packed");
+    nif_status st = check_query_args(c, dtype, packed, packed, packed, n, vis, "nif_query_packed");  // perm nullable
     if (st != NIF_OK || n == 0) return st == NIF_OK ? ok() : st;
     if (reinterpret_cast<uintptr_t>(packed) % 16 != 0)
         return fail(NIF_ERR_INVALID_ARG, "nif_query_packed: packed must be 16-byte aligned");
@@ -829,7 +829,8 @@ extern "C" size_t nif_pairs_workspace_bytes(const nif_ctx* c, int64_t n_rays) {
 static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays, int32_t round,
                                const uint8_t* ray_visible, int64_t max_pairs, float* pair_rays, float* pair_tmax,
                                int32_t* pair_ids, uint32_t* pair_ray, int64_t* pair_count, void* ws, size_t ws_bytes,
-                               void* stream, const char* where, float* packed = nullptr, uint32_t* keys = nullptr) {
+                               void* stream, const char* where, float* packed = nullptr, uint32_t* keys = nullptr,
+                               bool grouped = false, int64_t* obj_off = nullptr) {
     if (!c) return fail(NIF_ERR_INVALID_ARG, "%s: NULL context", where);
     if (n_rays < 0 || max_pairs < 0) return fail(NIF_ERR_INVALID_ARG, "%s: negative size", where);
     if (!pair_count) return fail(NIF_ERR_INVALID_ARG, "%s: NULL pair_count", where);
@@ -841,6 +842,7 @@ static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax,
         return fail(NIF_ERR_INVALID_ARG, "%s: packed must be 16-byte aligned", where);
     if (round < 0 || round > 2) return fail(NIF_ERR_INVALID_ARG, "%s: round must be 1 or 2", where);
     if (round == 2 && n_rays > 0 && !ray_visible) return fail(NIF_ERR_INVALID_ARG, "%s: NULL ray_visible", where);
+    if (grouped && c->K > 64) return fail(NIF_ERR_UNSUPPORTED, "%s: at most 64 objects", where);
     if (n_rays > ((int64_t)1 << 24)) return fail(NIF_ERR_UNSUPPORTED, "%s: at most 2^24 rays per call", where);
     // per-ray counts and their scan are 32-bit: the total must stay below 2^32
     if ((uint64_t)n_rays * (uint64_t)c->K >= ((uint64_t)1 << 32))
@@ -851,8 +853,26 @@ static nif_status expand_pairs(nif_ctx* c, const float* rays, const float* tmax,
     HIP_TRY(launch_expand_pairs(rays, tmax, n_rays, c->tree, c->K, c->num_cus, round, ray_visible, max_pairs,
                                 pair_rays, pair_tmax, pair_ids, pair_ray, pair_count, ws, (hipStream_t)stream,
                                 reinterpret_cast<float4*>(packed), keys, c->d_objs,
-                                order_bucket_bits(c->K, c->order_bits) == 0 && !window_sorted(c)));
+                                order_bucket_bits(c->K, c->order_bits) == 0 && !window_sorted(c), grouped, obj_off));
     return ok();
+}
+
+extern "C" nif_status nif_expand_pairs_by_object(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,
+                                                 int64_t max_pairs, float* packed, uint32_t* pair_ray,
+                                                 int64_t* pair_count, int64_t* obj_offsets, void* ws, size_t ws_bytes,
+                                                 void* stream) {
+    if (max_pairs > 0 && !packed) return fail(NIF_ERR_INVALID_ARG, "nif_expand_pairs_by_object: NULL packed");
+    if (c && n_rays == 0 && obj_offsets) {  // no rays: every object's run is empty
+        const nif_status st = expand_pairs(c, rays, tmax, 0, 0, nullptr, max_pairs, nullptr, nullptr, nullptr, pair_ray,
+                                           pair_count, ws, ws_bytes, stream, "nif_expand_pairs_by_object", packed,
+                                           nullptr, true, nullptr);
+        if (st != NIF_OK) return st;
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(obj_offsets), 2 * ((int64_t)c->K + 1), 0u,
+                                (hipStream_t)stream));
+        return ok();
+    }
+    return expand_pairs(c, rays, tmax, n_rays, 0, nullptr, max_pairs, nullptr, nullptr, nullptr, pair_ray, pair_count,
+                        ws, ws_bytes, stream, "nif_expand_pairs_by_object", packed, nullptr, true, obj_offsets);
 }
 
 extern "C" nif_status nif_expand_pairs_packed(nif_ctx* c, const float* rays, const float* tmax, int64_t n_rays,

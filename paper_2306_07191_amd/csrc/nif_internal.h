@@ -291,7 +291,8 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
                                int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
                                float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
                                int64_t* total, void* ws, hipStream_t s, float4* rec = nullptr,
-                               uint32_t* keys = nullptr, const ObjDev* objs = nullptr, bool object_keys = false);
+                               uint32_t* keys = nullptr, const ObjDev* objs = nullptr, bool object_keys = false,
+                               bool grouped = false, int64_t* obj_off = nullptr);
 // t = t_a + y (t_b - t_a) of the query's segment; +inf for a miss, NaN for an
 // invalid query.
 hipError_t launch_depth_from_visibility(const float* rays, const int32_t* ids, const float* tmax, const float* vis,

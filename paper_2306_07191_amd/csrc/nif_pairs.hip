@@ -45,6 +45,7 @@ namespace nif {
 
 constexpr int kPairTile = 256;  // rays per block tile: four waves of 64
 constexpr int kPairScanThreads = 1024;
+constexpr int kMaxPairBlocks = 8192;  // grid cap (1,024 compute units): sizes the per-object block table
 constexpr float kUlp8 = 8.0f * 0x1p-24f;
 
 struct RayPre {
@@ -188,6 +189,14 @@ __device__ __forceinline__ float wave_max(float v) {
     const int32_t x = order_int(v != v ? -INFINITY : v);
     return order_float(wave_reduce(x, INT32_MIN, [](int32_t a, int32_t b) { return a > b ? a : b; }));
 }
+// OR of a 64-bit value over the wave (in every lane: uniform).
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+    auto op = [](int32_t a, int32_t b) { return a | b; };
+    const uint32_t lo = (uint32_t)wave_reduce((int32_t)(uint32_t)v, 0, op);
+    const uint32_t hi = (uint32_t)wave_reduce((int32_t)(uint32_t)(v >> 32), 0, op);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ float lane_f(float v, int j) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
 }
@@ -395,13 +404,17 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
                                                                 uint64_t* __restrict__ masks,
                                                                 uint32_t* __restrict__ counts,
                                                                 int32_t* __restrict__ first_obj,
-                                                                uint32_t* __restrict__ block_sums) {
+                                                                uint32_t* __restrict__ block_sums,
+                                                                uint32_t* __restrict__ obj_counts) {
     __shared__ uint32_t sh[4];
+    __shared__ uint32_t hist[64];  // pairs of each object in the block (obj_counts)
     const int lane = threadIdx.x & 63;
     const LaneBox B1 = level1_box(T, lane);
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
     const int64_t t_end = tile_begin(tiles, 1);
     uint32_t block_total = 0;
+    if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+    __syncthreads();
     if constexpr (!ROUNDS) {
         // Two rays per lane: a step covers two tiles (512 rays), wave w the 128
         // consecutive rays from 128 w, lane l rays l and 64 + l of them, so that
@@ -435,9 +448,23 @@ __global__ __launch_bounds__(kPairTile) void pairs_count_kernel(const float* __r
                     if (masks) masks[r[i]] = mk[i];
                     else counts[r[i]] = c[i];
                 }
+            if (obj_counts) {  // per object: the wave's rays that meet it (ballots over the objects present)
+                uint64_t present = wave_or64(mk[0] | mk[1]);
+                while (present) {
+                    const int k = __builtin_ctzll(present);
+                    present &= present - 1;
+                    const uint32_t cnt = (uint32_t)__popcll(__ballot((mk[0] >> k) & 1ull)) +
+                                         (uint32_t)__popcll(__ballot((mk[1] >> k) & 1ull));
+                    if (lane == 0) atomicAdd(&hist[k], cnt);
+                }
+            }
             block_total += block_sum(c[0] + c[1], sh);
         }
         if (threadIdx.x == 0) block_sums[blockIdx.x] = block_total;
+        if (obj_counts) {  // object-major: entry k * gridDim.x + block
+            __syncthreads();
+            if (threadIdx.x < 64) obj_counts[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = hist[threadIdx.x];
+        }
         return;
     }
     RayIn q_next = load_ray(rays, tmax, tile_begin(tiles) * kPairTile + threadIdx.x, n);
@@ -654,6 +681,117 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     }
 }
 
+// Pass 3 grouped by object (at most 64 objects): the pairs of object k go to
+// obj_base[k] + local[k * gridDim.x + block] onwards (the scan of the
+// per-object block counts), in ray order within the block, so that the whole output is grouped
+// by object and in ray order within each object.  Per tile, each wave counts
+// its lanes of each object present (ballots), the waves' counts give each
+// lane its place, and the block's running count per object advances.
+__global__ __launch_bounds__(kPairTile) void pairs_emit_grouped_kernel(
+    const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
+    const uint32_t* __restrict__ local, const uint64_t* __restrict__ obj_base, int64_t max_pairs,
+    float4* __restrict__ rec, uint32_t* __restrict__ pair_ray) {
+    __shared__ uint64_t base[64];   // where the block's pairs of each object start
+    __shared__ uint32_t run[64];    // the block's pairs of each object in earlier tiles
+    __shared__ uint32_t wc[4][64];  // this tile's pairs of each object per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < 64) {
+        base[threadIdx.x] = obj_base[threadIdx.x] + local[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+        run[threadIdx.x] = 0;
+    }
+    const uint64_t lt = (1ull << lane) - 1ull;  // lanes below this one
+    const int64_t tiles = (n + kPairTile - 1) / kPairTile;
+    const int64_t t_end = tile_begin(tiles, 1);
+    int64_t tile = tile_begin(tiles);
+    auto mask_at = [&](int64_t t) -> uint64_t {
+        const int64_t r = t * kPairTile + threadIdx.x;
+        return t < t_end && r < n ? masks[r] : 0ull;
+    };
+    auto ray_at = [&](int64_t t, uint64_t m) -> RayIn {  // read only for rays with pairs
+        return load_ray(rays, tmax, m ? t * kPairTile + threadIdx.x : n, n);
+    };
+    uint64_t mk_next = mask_at(tile);
+    RayIn q_next = ray_at(tile, mk_next);
+    uint64_t mk_next2 = mask_at(tile + 1);
+    for (; tile < t_end; ++tile) {
+        const int64_t r = tile * kPairTile + threadIdx.x;
+        const uint64_t mk = mk_next;
+        const RayIn q = q_next;
+        mk_next = mk_next2;
+        q_next = ray_at(tile + 1, mk_next);
+        mk_next2 = mask_at(tile + 2);
+        wc[wave][lane] = 0;
+        __syncthreads();
+        const uint64_t present = wave_or64(mk);
+        for (uint64_t pm = present; pm; pm &= pm - 1) {
+            const int k = __builtin_ctzll(pm);
+            const uint64_t b = __ballot((mk >> k) & 1ull);
+            if (lane == 0) wc[wave][k] = (uint32_t)__popcll(b);
+        }
+        __syncthreads();
+        for (uint64_t pm = present; pm; pm &= pm - 1) {
+            const int k = __builtin_ctzll(pm);
+            const uint64_t b = __ballot((mk >> k) & 1ull);
+            if ((mk >> k) & 1ull) {
+                uint64_t p = base[k] + run[k] + (uint64_t)__popcll(b & lt);
+                for (int w = 0; w < wave; ++w) p += wc[w][k];
+                if ((int64_t)p < max_pairs) {
+                    rec[2 * p] = make_float4(q.o[0], q.o[1], q.o[2], q.d[0]);
+                    rec[2 * p + 1] = make_float4(q.d[1], q.d[2], q.tm, __int_as_float(k));
+                    pair_ray[p] = (uint32_t)r;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) run[threadIdx.x] += wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] + wc[3][threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// Scan of the per-object block counts, one block per object (64 blocks):
+// offs[k * blocks + b] = the pairs of object k in blocks before b, in u32
+// first; obj_tot[k] = object k's pairs.
+constexpr int kObjScanThreads = 256;
+__global__ __launch_bounds__(kObjScanThreads) void obj_scan_kernel(const uint32_t* __restrict__ counts,
+                                                                   int32_t blocks, uint32_t* __restrict__ local,
+                                                                   uint32_t* __restrict__ obj_tot) {
+    __shared__ uint32_t part[kObjScanThreads];
+    const int t = threadIdx.x, k = blockIdx.x;
+    const int per = (blocks + kObjScanThreads - 1) / kObjScanThreads;
+    const uint32_t* c = counts + (int64_t)k * blocks;
+    uint32_t s = 0;
+    for (int i = t * per; i < (t + 1) * per && i < blocks; ++i) s += c[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kObjScanThreads; off <<= 1) {
+        const uint32_t y = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0u;
+    for (int i = t * per; i < (t + 1) * per && i < blocks; ++i) {
+        local[(int64_t)k * blocks + i] = run;
+        run += c[i];
+    }
+    if (t == kObjScanThreads - 1) obj_tot[k] = part[t];
+}
+
+// Object bases (exclusive scan of the 64 totals, 64-bit), the pair total and,
+// if asked, each object's first pair and the total (obj_off, K + 1 entries).
+__global__ void obj_base_kernel(const uint32_t* __restrict__ obj_tot, int32_t K, uint64_t* __restrict__ obj_base,
+                                int64_t* __restrict__ total, int64_t* __restrict__ obj_off) {
+    if (threadIdx.x != 0) return;
+    uint64_t run = 0;
+    for (int k = 0; k < 64; ++k) {
+        obj_base[k] = run;
+        if (obj_off && k < K) obj_off[k] = (int64_t)run;
+        run += obj_tot[k];
+    }
+    *total = (int64_t)run;
+    if (obj_off) obj_off[K] = (int64_t)run;
+}
+
 // Pass 3 with more than 64 objects: the traversal again, pairs written in
 // traversal order, then the ray's written ids sorted ascending in place (the
 // other fields are the same for every pair of a ray).
@@ -787,10 +925,15 @@ static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 // masks (8 B per ray) or counts (4 B), per-block totals (4 B) and offsets
 // (8 B), first objects (4 B per ray, more than 64 objects only).  Sized by
 // tiles, which bounds the block count.
+// Masks (at most 64 objects) or counts, block totals and their offsets, then
+// (masks only, for the grouped form) the per-object block counts, their scan
+// within each object, the 64 object totals and bases; or (more than 64
+// objects) the first objects.
 size_t pairs_workspace_bytes(int64_t n_rays, int32_t K) {
     const int64_t tiles = (n_rays + kPairTile - 1) / kPairTile;
+    const int64_t blocks = tiles < kMaxPairBlocks ? tiles : kMaxPairBlocks;
     return al256((size_t)n_rays * (K <= 64 ? 8 : 4)) + al256((size_t)tiles * 4) + al256((size_t)tiles * 8) +
-           (K <= 64 ? 0 : al256((size_t)n_rays * 4));
+           (K <= 64 ? 2 * al256((size_t)64 * blocks * 4) + 256 + 512 : al256((size_t)n_rays * 4));
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -802,7 +945,7 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
                                int num_cus, int32_t round, const uint8_t* ray_visible, int64_t max_pairs,
                                float* pair_rays, float* pair_tmax, int32_t* pair_ids, uint32_t* pair_ray,
                                int64_t* total, void* ws, hipStream_t s, float4* rec, uint32_t* keys,
-                               const ObjDev* objs, bool object_keys) {
+                               const ObjDev* objs, bool object_keys, bool grouped, int64_t* obj_off) {
     if (n == 0) {
         hipLaunchKernelGGL(pairs_zero_total_kernel, dim3(1), dim3(64), 0, s, total);
         return hipGetLastError();
@@ -818,12 +961,28 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
     uint64_t* offs = reinterpret_cast<uint64_t*>(p);
     p += al256((size_t)tiles * 8);
     int32_t* first = use_mask ? nullptr : reinterpret_cast<int32_t*>(p);
-    const int64_t cap = (int64_t)num_cus * 8;  // persistent blocks
+    int64_t cap = (int64_t)num_cus * 8;  // persistent blocks
+    cap = cap < kMaxPairBlocks ? cap : kMaxPairBlocks;
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
+    if (grouped && (!use_mask || round)) return hipErrorInvalidValue;  // checked by the caller
+    // grouped: per-object block counts, their scan within each object, the
+    // object totals and bases
+    uint32_t* obj_counts = grouped ? reinterpret_cast<uint32_t*>(p) : nullptr;
+    uint32_t* obj_local = grouped ? reinterpret_cast<uint32_t*>(p + al256((size_t)64 * blocks * 4)) : nullptr;
+    uint32_t* obj_tot = grouped ? reinterpret_cast<uint32_t*>(p + 2 * al256((size_t)64 * blocks * 4)) : nullptr;
+    uint64_t* obj_base = grouped ? reinterpret_cast<uint64_t*>(p + 2 * al256((size_t)64 * blocks * 4) + 256) : nullptr;
     auto count = T.C == 1 ? (round ? pairs_count_kernel<true, true> : pairs_count_kernel<true, false>)
                           : (round ? pairs_count_kernel<false, true> : pairs_count_kernel<false, false>);
     hipLaunchKernelGGL(count, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, ray_visible, masks, counts,
-                       round ? first : nullptr, sums);
+                       round ? first : nullptr, sums, obj_counts);
+    if (grouped) {
+        hipLaunchKernelGGL(obj_scan_kernel, dim3(64), dim3(kObjScanThreads), 0, s, obj_counts, (int32_t)blocks,
+                           obj_local, obj_tot);
+        hipLaunchKernelGGL(obj_base_kernel, dim3(1), dim3(64), 0, s, obj_tot, K, obj_base, total, obj_off);
+        hipLaunchKernelGGL(pairs_emit_grouped_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, masks,
+                           obj_local, obj_base, max_pairs, rec, pair_ray);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(pairs_block_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, (int64_t)blocks, offs,
                        total);
     const PairOut out{pair_rays, pair_tmax, pair_ids, pair_ray, rec, keys, objs, K, order_fine_bits(K), object_keys};

@@ -32,7 +32,7 @@ STATUS = {0: "NIF_OK", -1: "NIF_ERR_INVALID_ARG", -2: "NIF_ERR_UNSUPPORTED", -3:
 EXPORTS = ["nif_create", "nif_destroy", "nif_param_layout", "nif_set_object", "nif_set_mlp", "nif_set_fp8_scales",
            "nif_calibrate_fp8", "nif_get_error_flags", "nif_pairs_workspace_bytes",
            "nif_expand_pairs", "nif_combine_pairs", "nif_expand_pairs_round", "nif_combine_pairs_and",
-           "nif_expand_pairs_packed", "nif_order_keys", "nif_build_image", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
+           "nif_expand_pairs_packed", "nif_order_keys", "nif_build_image", "nif_expand_pairs_by_object", "nif_init_grid", "nif_prepare", "nif_workspace_bytes", "nif_query", "nif_query_noalloc", "nif_encode", "nif_mlp",
            "nif_encode16", "nif_mlp16",
            "nif_set_option", "nif_image_bytes", "nif_set_image", "nif_order_workspace_bytes", "nif_order", "nif_query_ordered",
            "nif_order_packed", "nif_query_packed",
@@ -88,6 +88,7 @@ def lib():
             "nif_expand_pairs_packed": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp]),
             "nif_order_keys": (i32, [vp, vp, i64, vp, vp, sz, vp]),
             "nif_build_image": (i32, [vp, i32, vp]),
+            "nif_expand_pairs_by_object": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp]),
             "nif_combine_pairs_and": (i32, [vp, vp, vp, i64, i64, vp, vp]),
             "nif_calibrate_fp8": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, sz, vp]),
             "nif_init_grid": (i32, [vp, i32, C.c_uint64, C.c_float, vp]),
@@ -511,6 +512,28 @@ class Context:
             max_pairs = total
         raise RuntimeError("pair count changed between calls")
 
+    def expand_pairs_by_object(self, rays, tmax, max_pairs=None):
+        """(packed [P, 8] float32 query records grouped by object, pair_ray,
+        obj_offsets [K + 1] int64) of the rays' AABB hits
+        (nif_expand_pairs_by_object)."""
+        t = self.torch
+        n = tmax.shape[0]
+        ws = t.empty(max(1, int(lib().nif_pairs_workspace_bytes(self.h, n))), dtype=t.uint8, device=self.device)
+        cnt = t.zeros(1, dtype=t.int64, device=self.device)
+        off = t.empty(self.K + 1, dtype=t.int64, device=self.device)
+        for _ in range(2):
+            m = max(1, n if max_pairs is None else max_pairs)
+            rec = t.empty((m, 8), dtype=t.float32, device=self.device)
+            pray = t.empty(m, dtype=t.int32, device=self.device)
+            _check(lib().nif_expand_pairs_by_object(self.h, _ptr(rays), _ptr(tmax), n, m, _ptr(rec), _ptr(pray),
+                                                    _ptr(cnt), _ptr(off), _ptr(ws), ws.numel(), _stream()),
+                   "nif_expand_pairs_by_object")
+            total = int(cnt.item())
+            if total <= m:
+                return rec[:total], pray[:total], off
+            max_pairs = total
+        raise RuntimeError("pair count changed between calls")
+
     def order_keys(self, keys, perm=None, ws=None):
         """Ordering from the keys of expand_pairs_packed (nif_order_keys): perm."""
         t = self.torch
@@ -647,9 +670,10 @@ class Context:
         return perm, packed
 
     def query_packed(self, packed, perm, dtype: str = "f32", out=None, logits=None):
-        """Query on the records of order_packed, in the order perm; outputs in query order."""
+        """Query on the records of order_packed, in the order perm (None: the
+        records' own order); outputs in query order."""
         t = self.torch
-        n = perm.shape[0]
+        n = packed.shape[0] if perm is None else perm.shape[0]
         if out is None:
             out = t.empty(n, dtype=t.float32, device=self.device)
         _check(lib().nif_query_packed(self.h, DTYPES[dtype], _ptr(packed), _ptr(perm), n, _ptr(out),

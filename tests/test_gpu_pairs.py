@@ -383,3 +383,72 @@ def test_packed_pairs_order_by_object(K):
     _, _, key_ws = ctx.expand_pairs_packed(rays, tmax)
     kref = _pair_keys(model, w["rays"], w["tmax"], pr_ray.cpu().numpy().astype(np.int64), g_obj, fb)
     np.testing.assert_array_equal(key_ws.cpu().numpy().view(np.uint32).astype(np.int64), kref)
+
+
+def _check_grouped(ctx, rays, tmax, n, max_pairs=None):
+    """nif_expand_pairs_by_object against nif_expand_pairs on the same rays:
+    the same pairs, records bit for bit, grouped by object (stable: rays
+    ascending within an object), per-object offsets; returns the pair count."""
+    import torch
+    pr_rays, pr_tmax, pr_ids, pr_ray = ctx.expand_pairs(rays, tmax)
+    rec, pray, off = ctx.expand_pairs_by_object(rays, tmax, max_pairs=max_pairs)
+    g_obj = pr_ids.cpu().numpy().astype(np.int64)
+    order = np.argsort(g_obj, kind="stable")
+    P = g_obj.shape[0]
+    assert rec.shape[0] == P
+    r = rec.cpu().numpy()
+    np.testing.assert_array_equal(pray.cpu().numpy(), pr_ray.cpu().numpy()[order])
+    np.testing.assert_array_equal(r[:, 7].view(np.int32), g_obj[order])
+    np.testing.assert_array_equal(r[:, :6].view(np.uint32), pr_rays.cpu().numpy()[order].view(np.uint32))
+    np.testing.assert_array_equal(r[:, 6].view(np.uint32), pr_tmax.cpu().numpy()[order].view(np.uint32))
+    K = ctx.K
+    np.testing.assert_array_equal(off.cpu().numpy(), np.append(np.searchsorted(g_obj[order], np.arange(K)), P))
+    # queried in their own order: each pair's output as through the arrays
+    y_g = ctx.query_packed(rec, None, dtype="f32")
+    y_a = ctx.query(pr_rays, pr_ids, pr_tmax, dtype="f32")
+    np.testing.assert_array_equal(y_g.cpu().numpy().view(np.uint32), y_a.cpu().numpy()[order].view(np.uint32))
+    np.testing.assert_array_equal(ctx.combine_pairs(pray, y_g, n).cpu().numpy(),
+                                  ctx.combine_pairs(pr_ray, y_a, n).cpu().numpy())
+    return P
+
+
+@pytest.mark.parametrize("K", [1, 12, 64])
+def test_pairs_grouped_by_object(K):
+    """Pair expansion grouped by object (Sec. 4.1: the top-level stage appends
+    each object's inputs): grazing rays, tiny directions, origins inside boxes;
+    a too-small max_pairs is retried; empty inputs give empty runs."""
+    import torch
+    w = _grazing(_scene(n=16000, K=K, seed=51 + K), np.random.default_rng(K + 7))
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
+    assert _check_grouped(ctx, rays, tmax, w["tmax"].shape[0], max_pairs=100) > 1000
+    e = torch.empty(0, device="cuda")
+    rec, pray, off = ctx.expand_pairs_by_object(e.view(0, 6), e)
+    assert rec.shape[0] == 0 and pray.numel() == 0 and (off.cpu().numpy() == 0).all()
+
+
+def test_pairs_grouped_needs_at_most_64_objects():
+    import torch
+    from paper_2306_07191_amd import nif
+    w = _scene(n=1000, K=70)
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    rays, tmax = torch.from_numpy(w["rays"]).cuda(), torch.from_numpy(w["tmax"]).cuda()
+    with pytest.raises(nif.NifError) as e:
+        ctx.expand_pairs_by_object(rays, tmax)
+    assert e.value.status == nif.NIF_ERR_UNSUPPORTED
+
+
+def test_pairs_grouped_coherent_scene_rays():
+    """The large scene's 8,294,400 shadow rays against its 64 object boxes,
+    grouped by object: the same pairs as the array form, in object order."""
+    import torch
+    sc = S.scene_workload(light_seed=0, with_mesh=False)
+    K = sc["aabb"].shape[0]
+    mlps = np.stack([S.xavier_mlp(S.TINY, S.rng(70, 3, 0))])
+    w = dict(shape=S.TINY, aabb=sc["aabb"], mlps=mlps, mlp_index=np.zeros(K, np.int32))
+    ctx, _ = make_pair(w, grid_amp=0.5)
+    ctx.prepare("f32")
+    rays, tmax = torch.from_numpy(sc["rays"]).cuda(), torch.from_numpy(sc["tmax"]).cuda()
+    assert _check_grouped(ctx, rays, tmax, sc["tmax"].shape[0], max_pairs=2 * sc["tmax"].shape[0]) > 10 ** 6
