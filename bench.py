@@ -65,12 +65,12 @@ def time_launches(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def measured_traffic(name: str, shape: int):
+def measured_traffic(name: str, shape: int, pair_path: str = None):
     """HBM bytes per launch of the fused kernel in tile shape `shape`, from the
     committed counter run profiles/query_<name>_traffic.json (FETCH_SIZE and
     WRITE_SIZE scaled by the copy calibration), or None when there is none for
-    that shape or the kernel source has changed since those counters were
-    taken."""
+    that shape, the kernel source has changed since those counters were
+    taken, or they were taken with the queries in another order (pair_path)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"query_{name}_traffic.json")
     if not os.path.exists(path):
@@ -79,6 +79,8 @@ def measured_traffic(name: str, shape: int):
     src = b"".join(open(os.path.join(ROOT, "paper_2306_07191_amd", "csrc", f), "rb").read()
                    for f in ("nif_forward.hip", "nif_device.h", "nif_mlp.h"))
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    if pair_path is not None and rec.get("pair_path", pair_path) != pair_path:
         return None
     by_shape = rec.get("shapes", {}).get(str(shape))
     return None if by_shape is None else by_shape["traffic_bytes_per_launch"]
@@ -755,7 +757,8 @@ def run_scene(args):
     # on these pairs
     ctx.prepare(SCENE_DTYPE)
     sched = {}
-    for path in ("grouped", "keys", "arrays"):
+    paths = ("grouped", "keys", "arrays") if args.scene_path == "auto" else (args.scene_path,)
+    for path in paths:
         for wsort in ((0,) if path == "grouped" else (1, 0)):  # the grouped path has no ordering pass
             for obits in ((-1,) if path == "grouped" else (-1, 0)):
                 for shape in (0, 1, 2):
@@ -882,7 +885,7 @@ def run_scene(args):
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[SCENE_DTYPE], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[SCENE_DTYPE]}
     img = "y-pair image" if layout else "no image"
-    roof.update({"traffic": measured_traffic("scene_image" if layout else "scene", tile_shape),
+    roof.update({"traffic": measured_traffic("scene_image" if layout else "scene", tile_shape, pair_path),
                  "tile_shape": tile_shape,
                  "kernel": f"nif_query_kernel<{SCENE_DTYPE}, L=8, f16 grid, {img}, tile shape {tile_shape}> "
                            "(fused clip+encode+MLP)",
@@ -1178,6 +1181,8 @@ def main():
                     help="scene: skip the per-object training (initial models; for counter runs of the query step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 1 GiB device copies (scales FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--scene-path", choices=("auto", "grouped", "keys", "arrays"), default="auto",
+                    help="scene: the pair path (default: whichever the schedule search finds fastest)")
     ap.add_argument("--scene-grids", action="store_true",
                     help="scene: time the queries on the grids instead of query images built from them")
     ap.add_argument("--early-out", action="store_true",

@@ -681,23 +681,48 @@ __global__ __launch_bounds__(kPairTile) void pairs_emit_mask_kernel(
     }
 }
 
+// Object bases: exclusive scan of the 64 object totals in 64 bits (wave 0 of
+// a block, lane k for object k; the wave-wide total in every lane).
+__device__ __forceinline__ uint64_t object_base(const uint32_t* __restrict__ obj_tot, int lane, uint64_t& all) {
+    const uint64_t v = obj_tot[lane];
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    all = __shfl(x, 63);
+    return x - v;
+}
+
 // Pass 3 grouped by object (at most 64 objects): the pairs of object k go to
-// obj_base[k] + local[k * gridDim.x + block] onwards (the scan of the
-// per-object block counts), in ray order within the block, so that the whole output is grouped
+// base(k) + local[k * gridDim.x + block] onwards (base(k): the pairs of the
+// objects before k; local: the scan of the per-object block counts), in ray
+// order within the block, so that the whole output is grouped
 // by object and in ray order within each object.  Per tile, each wave counts
 // its lanes of each object present (ballots), the waves' counts give each
 // lane its place, and the block's running count per object advances.
 __global__ __launch_bounds__(kPairTile) void pairs_emit_grouped_kernel(
     const float* __restrict__ rays, const float* __restrict__ tmax, int64_t n, const uint64_t* __restrict__ masks,
-    const uint32_t* __restrict__ local, const uint64_t* __restrict__ obj_base, int64_t max_pairs,
-    float4* __restrict__ rec, uint32_t* __restrict__ pair_ray) {
+    const uint32_t* __restrict__ local, const uint32_t* __restrict__ obj_tot, int32_t K, int64_t max_pairs,
+    float4* __restrict__ rec, uint32_t* __restrict__ pair_ray, int64_t* __restrict__ total,
+    int64_t* __restrict__ obj_off) {
     __shared__ uint64_t base[64];   // where the block's pairs of each object start
     __shared__ uint32_t run[64];    // the block's pairs of each object in earlier tiles
     __shared__ uint32_t wc[4][64];  // this tile's pairs of each object per wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < 64) {
-        base[threadIdx.x] = obj_base[threadIdx.x] + local[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
-        run[threadIdx.x] = 0;
+    if (threadIdx.x < 64) {  // wave 0: where each object's pairs start, and this block's part of them
+        uint64_t all;
+        const uint64_t ob = object_base(obj_tot, lane, all);
+        base[lane] = ob + local[(int64_t)lane * gridDim.x + blockIdx.x];
+        run[lane] = 0;
+        if (blockIdx.x == 0) {  // K <= 64: lanes 0..K-1 the objects' first pairs, lane 0 also the total
+            if (obj_off && lane < K) obj_off[lane] = (int64_t)ob;
+            if (lane == 0) {
+                *total = (int64_t)all;
+                if (obj_off) obj_off[K] = (int64_t)all;
+            }
+        }
     }
     const uint64_t lt = (1ull << lane) - 1ull;  // lanes below this one
     const int64_t tiles = (n + kPairTile - 1) / kPairTile;
@@ -777,20 +802,6 @@ __global__ __launch_bounds__(kObjScanThreads) void obj_scan_kernel(const uint32_
     if (t == kObjScanThreads - 1) obj_tot[k] = part[t];
 }
 
-// Object bases (exclusive scan of the 64 totals, 64-bit), the pair total and,
-// if asked, each object's first pair and the total (obj_off, K + 1 entries).
-__global__ void obj_base_kernel(const uint32_t* __restrict__ obj_tot, int32_t K, uint64_t* __restrict__ obj_base,
-                                int64_t* __restrict__ total, int64_t* __restrict__ obj_off) {
-    if (threadIdx.x != 0) return;
-    uint64_t run = 0;
-    for (int k = 0; k < 64; ++k) {
-        obj_base[k] = run;
-        if (obj_off && k < K) obj_off[k] = (int64_t)run;
-        run += obj_tot[k];
-    }
-    *total = (int64_t)run;
-    if (obj_off) obj_off[K] = (int64_t)run;
-}
 
 // Pass 3 with more than 64 objects: the traversal again, pairs written in
 // traversal order, then the ray's written ids sorted ascending in place (the
@@ -927,13 +938,13 @@ static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 // tiles, which bounds the block count.
 // Masks (at most 64 objects) or counts, block totals and their offsets, then
 // (masks only, for the grouped form) the per-object block counts, their scan
-// within each object, the 64 object totals and bases; or (more than 64
-// objects) the first objects.
+// within each object and the 64 object totals; or (more than 64 objects) the
+// first objects.
 size_t pairs_workspace_bytes(int64_t n_rays, int32_t K) {
     const int64_t tiles = (n_rays + kPairTile - 1) / kPairTile;
     const int64_t blocks = tiles < kMaxPairBlocks ? tiles : kMaxPairBlocks;
     return al256((size_t)n_rays * (K <= 64 ? 8 : 4)) + al256((size_t)tiles * 4) + al256((size_t)tiles * 8) +
-           (K <= 64 ? 2 * al256((size_t)64 * blocks * 4) + 256 + 512 : al256((size_t)n_rays * 4));
+           (K <= 64 ? 2 * al256((size_t)64 * blocks * 4) + 256 : al256((size_t)n_rays * 4));
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -970,7 +981,6 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
     uint32_t* obj_counts = grouped ? reinterpret_cast<uint32_t*>(p) : nullptr;
     uint32_t* obj_local = grouped ? reinterpret_cast<uint32_t*>(p + al256((size_t)64 * blocks * 4)) : nullptr;
     uint32_t* obj_tot = grouped ? reinterpret_cast<uint32_t*>(p + 2 * al256((size_t)64 * blocks * 4)) : nullptr;
-    uint64_t* obj_base = grouped ? reinterpret_cast<uint64_t*>(p + 2 * al256((size_t)64 * blocks * 4) + 256) : nullptr;
     auto count = T.C == 1 ? (round ? pairs_count_kernel<true, true> : pairs_count_kernel<true, false>)
                           : (round ? pairs_count_kernel<false, true> : pairs_count_kernel<false, false>);
     hipLaunchKernelGGL(count, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, T, round, ray_visible, masks, counts,
@@ -978,9 +988,8 @@ hipError_t launch_expand_pairs(const float* rays, const float* tmax, int64_t n, 
     if (grouped) {
         hipLaunchKernelGGL(obj_scan_kernel, dim3(64), dim3(kObjScanThreads), 0, s, obj_counts, (int32_t)blocks,
                            obj_local, obj_tot);
-        hipLaunchKernelGGL(obj_base_kernel, dim3(1), dim3(64), 0, s, obj_tot, K, obj_base, total, obj_off);
         hipLaunchKernelGGL(pairs_emit_grouped_kernel, dim3(blocks), dim3(kPairTile), 0, s, rays, tmax, n, masks,
-                           obj_local, obj_base, max_pairs, rec, pair_ray);
+                           obj_local, obj_tot, K, max_pairs, rec, pair_ray, total, obj_off);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(pairs_block_scan_kernel, dim3(1), dim3(kPairScanThreads), 0, s, sums, (int64_t)blocks, offs,
