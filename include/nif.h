@@ -251,7 +251,7 @@ nif_status nif_prepare(nif_ctx* ctx, int32_t dtype, void* stream);
  * this many Morton bits per axis of the entry point in the ordering's bucket
  * key (-1, the default: as many as 4,096 buckets allow, up to 4); 0 orders
  * by object alone (many objects with many queries each gain little from the
- * finer buckets).  Plans keep the value they were created with.  Outputs are
+ * finer buckets).  Plans order by their own schedule instead.  Outputs are
  * bit-identical in every mode. */
 enum {
     NIF_OPT_ORDER = 1,
@@ -359,14 +359,15 @@ nif_status nif_query_packed(nif_ctx* ctx, int32_t dtype, const float* packed, co
  * query per (ray, object) pair).  A plan fixes ctx, dtype, the input, output
  * and workspace pointers and n; their contents may change between launches.
  * nif_plan_create: with tuning == NULL, times every candidate schedule
- *   (ordering off / bucket order / bucket order + window sort, times the
+ *   (ordering off / bucket order / bucket order + window sort / by object
+ *   alone (order 3: the bucket key's Morton bits 0, no window sort), times the
  *   persistent grid's blocks per compute unit 4..32, times the fused kernel's
  *   tile shape: shape 0 = 6 image lookups (or all 12 grid lookups) of a lane
  *   half gathered together at 3 waves per SIMD (2 for binary32), shape 1 = 12
  *   (6) at 2 waves per SIMD, shape 2 = 3 at 4 waves per SIMD; shapes 1 and 2
  *   exist for 8-level binary16 grids) on these buffers and keeps the fastest;
  *   otherwise uses the schedule of the JSON string `tuning` (as written by
- *   nif_plan_tuning: keys "order" 0..2, "blocks_per_cu" 1..32 and optionally
+ *   nif_plan_tuning: keys "order" 0..3, "blocks_per_cu" 1..32 and optionally
  *   "shape" 0..2).  When the environment variable NIF_PLAN_CACHE names a file,
  *   a schedule tuned before for the same device architecture, compute-unit
  *   count, model shape, object and MLP counts, image mode, dtype and n

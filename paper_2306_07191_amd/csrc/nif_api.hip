@@ -605,9 +605,13 @@ static nif_status run_query(nif_ctx* c, int32_t dtype, const float* rays, const 
     return ok();
 }
 
+// max_bits: the bucket key's Morton bits per axis at most (-1 automatic);
+// kOrderBitsOption: the context's NIF_OPT_ORDER_BITS.
+constexpr int32_t kOrderBitsOption = -2;
 static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, const float* tmax, int64_t n,
                             uint32_t* perm_dst, void* ws, const uint32_t** perm, hipStream_t s,
-                            bool refine = true, float4* qrec = nullptr, uint32_t* zero_words = nullptr) {
+                            bool refine = true, float4* qrec = nullptr, uint32_t* zero_words = nullptr,
+                            int32_t max_bits = kOrderBitsOption) {
     OrderArgs o{};
     o.zero_words = zero_words;
     o.qrec = qrec;
@@ -618,7 +622,7 @@ static nif_status run_order(nif_ctx* c, const float* rays, const int32_t* ids, c
     o.n = n;
     o.objs = c->d_objs;
     o.num_objects = c->K;
-    o.max_bits = c->order_bits;
+    o.max_bits = max_bits == kOrderBitsOption ? c->order_bits : max_bits;
     o.perm = perm_dst;
     HIP_TRY(launch_order(o, ws, s, perm));
     return ok();
@@ -1189,7 +1193,7 @@ extern "C" nif_status nif_backward(nif_ctx* c, int32_t mlp, const float* rays, c
 // graph that replays the ordering kernels and the fused query kernel.
 // ---------------------------------------------------------------------------
 struct Sched {
-    int32_t order;          // 0 none, 1 bucket order, 2 bucket order + window sort
+    int32_t order;          // 0 none, 1 bucket order, 2 bucket order + window sort, 3 by object alone
     int32_t blocks_per_cu;  // persistent grid: blocks per compute unit
     int32_t shape;          // tile shape of the fused kernel: gathers issued together, waves per SIMD
 };
@@ -1226,10 +1230,10 @@ static nif_status plan_run(nif_plan* p, const Sched& sc, hipStream_t s) {
     const uint32_t* perm = nullptr;
     float4* qrec = nullptr;
     uint32_t* ctr = tile_ctr_in(p->c, p->ws, p->n);
-    if (sc.order > 0) {
+    if (sc.order > 0) {  // plans order by their own schedule, not by the context's NIF_OPT_ORDER_BITS
         qrec = records_in(p->c, p->ws, p->n);
         nif_status st = run_order(p->c, p->rays, p->ids, p->tmax, p->n, nullptr, p->ws, &perm, s, sc.order == 2, qrec,
-                                  ctr);
+                                  ctr, sc.order == 3 ? 0 : -1);
         if (st != NIF_OK) return st;
     }
     return run_query(p->c, p->dtype, p->rays, p->ids, p->tmax, perm, p->n, p->vis, p->logits, s, sc.blocks_per_cu,
@@ -1267,7 +1271,7 @@ static bool cache_lookup(const std::string& key, Sched* sc) {
         if (!strstr(line, want.c_str())) continue;
         Sched s{2, 8, 0};
         if (parse_int_key(line, "\"order\"", &s.order) && parse_int_key(line, "\"blocks_per_cu\"", &s.blocks_per_cu) &&
-            parse_int_key(line, "\"shape\"", &s.shape) && s.order >= 0 && s.order <= 2 && s.blocks_per_cu >= 1 &&
+            parse_int_key(line, "\"shape\"", &s.shape) && s.order >= 0 && s.order <= 3 && s.blocks_per_cu >= 1 &&
             s.blocks_per_cu <= 32 && s.shape >= 0 && s.shape <= 2) {
             *sc = s;  // the last matching line wins
             found = true;
@@ -1333,9 +1337,9 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
         if (!parse_int_key(tuning, "\"order\"", &sc.order) || !parse_int_key(tuning, "\"blocks_per_cu\"", &sc.blocks_per_cu))
             return fail(NIF_ERR_INVALID_ARG, "tuning string lacks \"order\" or \"blocks_per_cu\"");
         (void)parse_int_key(tuning, "\"shape\"", &sc.shape);  // optional, default 0
-        if (sc.order < 0 || sc.order > 2 || sc.blocks_per_cu < 1 || sc.blocks_per_cu > 32 || sc.shape < 0 ||
+        if (sc.order < 0 || sc.order > 3 || sc.blocks_per_cu < 1 || sc.blocks_per_cu > 32 || sc.shape < 0 ||
             sc.shape > 2)
-            return fail(NIF_ERR_INVALID_ARG, "tuning out of range (order 0..2, blocks_per_cu 1..32, shape 0..2)");
+            return fail(NIF_ERR_INVALID_ARG, "tuning out of range (order 0..3, blocks_per_cu 1..32, shape 0..2)");
         p->sched = sc;
     } else if (cache_lookup(key, &cached)) {
         p->sched = cached;
@@ -1346,7 +1350,7 @@ extern "C" nif_status nif_plan_create(nif_ctx* c, int32_t dtype, const float* ra
         // kernel has them: 8-level binary16 grids)
         std::vector<Sched> cand;
         const int nshape = c->d.levels == 8 && c->d.grid_dtype == NIF_F16 ? 3 : 1;
-        for (int o = 0; o <= 2; ++o)
+        for (int o = 0; o <= 3; ++o)
             for (int b : {4, 8, 16, 32})
                 for (int sh = 0; sh < nshape; ++sh)
                     if (!(o == 0 && b == 4)) cand.push_back(Sched{o, b, sh});

@@ -32,7 +32,7 @@ def test_plan_matches_eager_and_oracle_over_replays(dtype):
     plan = nif.Plan(ctx, rays, ids, tmax, dtype=dtype, logits=z)
     tun = json.loads(plan.tuning())
     # 4-level grids: orderings x grid sizes (no tile shapes besides the default)
-    assert tun["candidates"] == 11 and tun["order"] in (0, 1, 2) and tun["tuned_us"] > 0 and tun["shape"] == 0
+    assert tun["candidates"] == 15 and tun["order"] in (0, 1, 2, 3) and tun["tuned_us"] > 0 and tun["shape"] == 0
     torch.cuda.synchronize()
     check_outputs(plan.out.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64),
                   model.forward(w["rays"], w["ids"], w["tmax"]), dtype, f"plan {dtype}")
@@ -86,11 +86,17 @@ def test_plan_tile_shapes_and_tuning_cache(tmp_path, monkeypatch):
         p.close()
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+    p = nif.Plan(ctx, rays, ids, tmax, dtype="bf16", tuning='{"order": 3, "blocks_per_cu": 8, "shape": 1}')
+    assert json.loads(p.tuning())["order"] == 3  # by object alone: the same outputs
+    p.launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(p.out.cpu().numpy(), outs[0])
+    p.close()
     cache = tmp_path / "plans.jsonl"
     monkeypatch.setenv("NIF_PLAN_CACHE", str(cache))
     p1 = nif.Plan(ctx, rays, ids, tmax, dtype="bf16")
     t1 = json.loads(p1.tuning())
-    assert t1["candidates"] == 33 and not t1["from_cache"] and t1["tuned_us"] > 0
+    assert t1["candidates"] == 45 and not t1["from_cache"] and t1["tuned_us"] > 0
     line = json.loads(cache.read_text().strip().splitlines()[-1])
     assert "gfx950" in line["key"] and line["shape"] == t1["shape"] and line["order"] == t1["order"]
     p2 = nif.Plan(ctx, rays, ids, tmax, dtype="bf16")
