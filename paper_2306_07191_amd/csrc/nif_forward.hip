@@ -349,6 +349,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
     for (int64_t it = 0;; ++it) {
         const int64_t tile = it == 0 ? first_tile : tile_at(it);
         if (tile >= lim) break;
+        const int64_t slot = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
+        const bool inb = slot < A.n;
+        const int64_t q = inb && A.perm ? (int64_t)A.perm[slot] : slot;  // the query handled here
+        float o[3] = {0, 0, 0}, d[3] = {1, 0, 0};
+        float tm = 0.0f;
+        int32_t id = -1;
+        auto load_query = [&]() {
+            if (inb && MODE != 2) {
+                if (A.qrec) {  // one 32-byte record instead of three arrays
+                    const float4 r0 = A.qrec[2 * q], r1 = A.qrec[2 * q + 1];
+                    o[0] = r0.x; o[1] = r0.y; o[2] = r0.z;
+                    d[0] = r0.w; d[1] = r1.x; d[2] = r1.y;
+                    tm = r1.z;
+                    id = __float_as_int(r1.w);
+                } else {
+                    const float* r = A.rays + q * 6;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
+                    tm = A.tmax[q];
+                    id = A.ids[q];
+                }
+            }
+        };
+        // The tile's queries are read before the MLP check below, so that their
+        // loads and the check's overlap; not for FP8, whose registers would then
+        // fall to two waves per SIMD.
+        constexpr bool kEarlyLoad = FLAV != kFP8;
+        if constexpr (kEarlyLoad) load_query();
         if (MODE == 0 && it > 0) {
             // ordered queries change MLP at object boundaries: follow the MLP of
             // the tile's first query (a block-uniform decision)
@@ -364,27 +392,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
                 blk_mlp = m;
             }
         }
-        const int64_t slot = tile * kQueriesPerBlock + wave * kQueriesPerWave + qlane;
-        const bool inb = slot < A.n;
-        const int64_t q = inb && A.perm ? (int64_t)A.perm[slot] : slot;  // the query handled here
-        float o[3] = {0, 0, 0}, d[3] = {1, 0, 0};
-        float tm = 0.0f;
-        int32_t id = -1;
-        if (inb && MODE != 2) {
-            if (A.qrec) {  // one 32-byte record instead of three arrays
-                const float4 r0 = A.qrec[2 * q], r1 = A.qrec[2 * q + 1];
-                o[0] = r0.x; o[1] = r0.y; o[2] = r0.z;
-                d[0] = r0.w; d[1] = r1.x; d[2] = r1.y;
-                tm = r1.z;
-                id = __float_as_int(r1.w);
-            } else {
-                const float* r = A.rays + q * 6;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) { o[a] = r[a]; d[a] = r[3 + a]; }
-                tm = A.tmax[q];
-                id = A.ids[q];
-            }
-        }
+        if constexpr (!kEarlyLoad) load_query();
         // status: 1 query, 0 miss (visible), -1 invalid, -2 out of range
         int status = -2;
         float xin[KH1];
