@@ -821,12 +821,14 @@ def run_scene(args):
         psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
         res[dt] = {"ms": sec * 1e3, "rays_per_s": n / sec, "pairs_per_s": P / sec, "pair_path": pair_path,
                    "outputs_identical_to_grid_path": same, "misclassification": mis,
-                   "psnr_db": psnr, "stage_ms": {"pair_expansion": t_exp * 1e3, "ordering": t_ord * 1e3,
+                   "psnr_db": psnr, "stage_ms": {"pair_expansion": t_exp * 1e3,
+                                                 # grouped: no ordering pass, only the gap of two events
+                                                 "ordering": None if pair_path == "grouped" else t_ord * 1e3,
                                                  "query_kernel": t_q * 1e3, "combination": t_comb * 1e3},
                    "step_ms_with_stage_events": sec_staged * 1e3,
                    "query_kernel_tflops": flops * P / t_q / 1e12, "wall_s": wall}
         log(f"{dt}: step {sec * 1e3:.3f} ms = {n / sec / 1e9:.3f} G rays/s ({P / sec / 1e9:.3f} G pairs/s): expansion "
-            f"{t_exp * 1e3:.3f}, ordering {t_ord * 1e3:.3f}, query kernel {t_q * 1e3:.3f} "
+            f"{t_exp * 1e3:.3f}, ordering {'none' if pair_path == 'grouped' else f'{t_ord * 1e3:.3f}'}, query kernel {t_q * 1e3:.3f} "
             f"({flops * P / t_q / 1e12:.0f} TFLOP/s), combination {t_comb * 1e3:.3f} ms; misclassification "
             f"{100 * mis:.3f} %, mask PSNR {psnr:.2f} dB; outputs identical to the grid path: {same}")
         assert same, f"{dt}: the query images must reproduce the grid path's outputs bit for bit"
