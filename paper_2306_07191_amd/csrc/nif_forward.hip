@@ -321,13 +321,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(shape_wa
     const int64_t t_end = (int64_t)(lb + 1) * A.num_tiles / A.tiles_per_block_num;
     const int64_t share_begin = (int64_t)xcd * A.num_tiles / 8;
     const int64_t lim = A.tile_ctr ? (int64_t)(xcd + 1) * A.num_tiles / 8 : t_end;
-    __shared__ int64_t next_tile;
+    // Two slots taken in turn: the slot written by call i was last read in
+    // call i - 2, before every thread passed call i - 1's barrier, so one
+    // barrier per call is enough.
+    __shared__ int64_t next_tile[2];
     auto tile_at = [&](int64_t i) -> int64_t {  // block-uniform: every thread calls it
         if (!A.tile_ctr) return t_begin + i;
+        if (threadIdx.x == 0)
+            next_tile[i & 1] = share_begin + (int64_t)atomicAdd(A.tile_ctr + xcd * kTileCtrStride, 1u);
         __syncthreads();
-        if (threadIdx.x == 0) next_tile = share_begin + (int64_t)atomicAdd(A.tile_ctr + xcd * kTileCtrStride, 1u);
-        __syncthreads();
-        return next_tile;
+        return next_tile[i & 1];
     };
     const int64_t first_tile = tile_at(0);
 
